@@ -1,0 +1,215 @@
+"""Seeded synthetic workloads: an octree box list plus a right-hand side.
+
+Each workload is a stand-in for the paper's streamer runs (section 3): the
+unit cube plays the (40 mm)^3 domain, level 4 (64^3 cells) is the 625 um base
+grid, the applied potential is 1 on the top face and 0 on the other faces, and
+refinement follows the space-charge criterion of section 2.5 (refine where
+|rho| h^2 exceeds a constant c3), here extended with a gradient term and a
+three-cell buffer, with 2:1 nesting over all 26 neighbours.  The constant c3 is
+tuned by log-bisection to hit a target leaf-cell count, and the tuned values
+are cached in ``c3_cache.json`` next to this file.
+"""
+import json
+import math
+import os
+
+import numpy as np
+
+from . import charges
+from .octree import BoxList, refine_by_score, uniform_boxes, pack
+
+DIRICHLET, NEUMANN = 0, 1
+_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_cache.json")
+
+
+class Workload:
+    """A tree (BoxList), a cubic domain with per-face boundary conditions, and
+    a function giving b = -rho/eps0 at the cells of any set of boxes."""
+
+    def __init__(self, name, boxes, rhs_fn, lo=(0.0, 0.0, 0.0), length=1.0,
+                 bc_type=(DIRICHLET,) * 6, bc_val=(0, 0, 0, 0, 0, 1.0), meta=None):
+        self.name = name
+        self.boxes = boxes
+        self._rhs_fn = rhs_fn
+        self.lo = tuple(float(v) for v in lo)
+        self.length = float(length)
+        self.bc_type = tuple(int(v) for v in bc_type)
+        self.bc_val = tuple(float(v) for v in bc_val)
+        self.meta = dict(meta or {})
+
+    def rhs(self, level, ijk, tree=None):
+        """b at the cells of the given boxes, shape [n, 8, 8, 8] ([box][k][j][i])."""
+        level = np.asarray(level).reshape(-1)
+        ijk = np.asarray(ijk).reshape(-1, 3)
+        out = np.zeros((len(level), 8, 8, 8))
+        for l in np.unique(level):
+            m = level == l
+            out[m] = self._rhs_fn(int(l), ijk[m])
+        return out
+
+    @property
+    def n_leaf(self):
+        return self.boxes.n_leaf_cells()
+
+
+# --------------------------------------------------------------------- small
+
+
+def rhs_zero(level, ijk):
+    return np.zeros((len(ijk), 8, 8, 8))
+
+
+def c1(seed=1, top_level=4, amp=400.0, sigma=0.05, noise_rel=1e-3):
+    """Uniform 64^3 grid (levels 1-4, 585 boxes): a Gaussian charge blob at the
+    centre plus seeded uniform noise of relative amplitude 1e-3."""
+    def fn(level, ijk):
+        x, y, z, I, J, K = charges.cell_centres(level, ijk, (0.0, 0.0, 0.0), 1.0)
+        rho = charges.gaussian_blob(x, y, z, amp, sigma, (0.5, 0.5, 0.5))
+        rho = rho + noise_rel * amp * charges.noise(seed, level, I, J, K)
+        return -rho
+    return Workload("uniform64_blob", uniform_boxes(top_level), fn,
+                    meta=dict(seed=seed, amp=amp, sigma=sigma, noise=noise_rel))
+
+
+# ------------------------------------------------------------- streamers
+
+
+class _Channels:
+    """Streamer channels (top point, head centre) with head amplitude A_h and
+    side amplitude A_s; sum of all channels."""
+
+    def __init__(self, chans, radius, delta, amp_head):
+        self.chans = [(np.asarray(a, float), np.asarray(b, float)) for a, b in chans]
+        self.radius, self.delta, self.amp_head = radius, delta, amp_head
+        body = sum(np.linalg.norm(b - a) for a, b in self.chans)
+        # continuum estimate of neutrality: hemisphere area vs channel side area
+        self.amp_side = amp_head * len(self.chans) * radius / body
+
+    def parts(self, x, y, z):
+        head = np.zeros_like(x)
+        side = np.zeros_like(x)
+        for p0, p1 in self.chans:
+            h, s = charges.channel_parts(x, y, z, p0, p1, self.radius, self.delta)
+            head += h
+            side += s
+        return head, side
+
+    def rho(self, x, y, z):
+        head, side = self.parts(x, y, z)
+        return self.amp_head * head - self.amp_side * side
+
+    def neutralise(self, boxes, lo, length):
+        """Set A_s so that the sum of rho*h^3 over the leaf cells vanishes."""
+        leaf = boxes.leaf_mask()
+        sh, ss = 0.0, 0.0
+        for l in np.unique(boxes.level[leaf]):
+            m = leaf & (boxes.level == l)
+            h = length / (8 * 2 ** (l - 1))
+            ijk = boxes.ijk[m]
+            for s in range(0, len(ijk), 512):
+                x, y, z, *_ = charges.cell_centres(int(l), ijk[s:s + 512], lo, length)
+                a, b = self.parts(x, y, z)
+                sh += a.sum() * h ** 3
+                ss += b.sum() * h ** 3
+        if ss > 0:
+            self.amp_side = self.amp_head * sh / ss
+
+
+def _score_fn(rho_fn, lo, length, memo):
+    """max over a box and a 3-cell buffer of max(|rho| h^2, |grad rho| h^3)."""
+    def score(level, ijk):
+        keys = pack(ijk)
+        d = memo.setdefault(level, {})
+        out = np.empty(len(ijk))
+        miss = [n for n, k in enumerate(keys.tolist()) if k not in d]
+        h = length / (8 * 2 ** (level - 1))
+        for s in range(0, len(miss), 256):
+            idx = np.array(miss[s:s + 256])
+            x, y, z, *_ = charges.cell_centres(level, ijk[idx], lo, length, pad=4)
+            r = rho_fn(x, y, z)
+            c = r[:, 1:-1, 1:-1, 1:-1]
+            gx = (r[:, 1:-1, 1:-1, 2:] - r[:, 1:-1, 1:-1, :-2]) / (2 * h)
+            gy = (r[:, 1:-1, 2:, 1:-1] - r[:, 1:-1, :-2, 1:-1]) / (2 * h)
+            gz = (r[:, 2:, 1:-1, 1:-1] - r[:, :-2, 1:-1, 1:-1]) / (2 * h)
+            crit = np.maximum(np.abs(c) * h * h, np.sqrt(gx * gx + gy * gy + gz * gz) * h ** 3)
+            mx = crit.reshape(len(idx), -1).max(axis=1)
+            for n, v in zip(idx.tolist(), mx.tolist()):
+                d[int(keys[n])] = v
+        for n, k in enumerate(keys.tolist()):
+            out[n] = d[k]
+        return out
+    return score
+
+
+def _load_cache():
+    if os.path.exists(_CACHE):
+        with open(_CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def tuned_tree(tag, rho_fn, base_level, max_level, target, lo=(0, 0, 0), length=1.0,
+               tree=0, tol=0.1, use_cache=True):
+    """Balanced tree whose leaf-cell count is within ``tol`` of ``target``.
+    c3 is found by log-bisection (and cached per ``tag``)."""
+    memo = {}
+    score = _score_fn(rho_fn, lo, length, memo)
+    cache = _load_cache() if use_cache else {}
+    if tag in cache:
+        c3 = cache[tag]
+        return refine_by_score(base_level, max_level, score, c3, tree), c3
+    lo_c, hi_c = -12.0, 6.0  # log10 bounds
+    best = None
+    for _ in range(40):
+        mid = 0.5 * (lo_c + hi_c)
+        bl = refine_by_score(base_level, max_level, score, 10 ** mid, tree)
+        n = bl.n_leaf_cells()
+        best = (bl, 10 ** mid)
+        if abs(n - target) <= tol * target:
+            break
+        if n > target:
+            lo_c = mid
+        else:
+            hi_c = mid
+    return best
+
+
+def save_c3(tag, c3):
+    cache = _load_cache()
+    cache[tag] = c3
+    with open(_CACHE, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+
+
+def c2(seed=2, refinements=4, target=5.0e6, amp_head=1e4, radius=0.02, delta=2e-3,
+       z_head=0.62, use_cache=True):
+    """Static AMR tree: base 64^3 (level 4) plus ``refinements`` levels, around
+    one streamer along the z axis from z = 1 down to a hemispherical head
+    centred at z = 0.62 (tip at 0.60), radius 0.02, head layer thickness 2e-3.
+    The seed only fixes the tag; the shape is deterministic."""
+    ch = _Channels([((0.5, 0.5, 1.0), (0.5, 0.5, z_head))], radius, delta, amp_head)
+    base = 4
+    tag = f"c2_s{seed}_r{refinements}_t{target:.3g}"
+    bl, c3 = tuned_tree(tag, ch.rho, base, base + refinements, target, use_cache=use_cache)
+    ch.neutralise(bl, (0.0, 0.0, 0.0), 1.0)
+
+    def fn(level, ijk):
+        x, y, z, *_ = charges.cell_centres(level, ijk, (0.0, 0.0, 0.0), 1.0)
+        return -ch.rho(x, y, z)
+    return Workload(f"streamer_L{base}+{refinements}", bl, fn,
+                    meta=dict(seed=seed, c3=c3, amp_head=amp_head, amp_side=ch.amp_side,
+                              radius=radius, delta=delta, target=target))
+
+
+def streamer_small(refinements=2, target=3.0e5, use_cache=True):
+    """A reduced C2-shaped tree (base 32^3 + ``refinements`` levels) small enough
+    for the CPU oracle to solve in a second or two."""
+    ch = _Channels([((0.5, 0.5, 1.0), (0.5, 0.5, 0.62))], 0.04, 8e-3, 1e3)
+    tag = f"small_r{refinements}_t{target:.3g}"
+    bl, c3 = tuned_tree(tag, ch.rho, 3, 3 + refinements, target, use_cache=use_cache)
+    ch.neutralise(bl, (0.0, 0.0, 0.0), 1.0)
+
+    def fn(level, ijk):
+        x, y, z, *_ = charges.cell_centres(level, ijk, (0.0, 0.0, 0.0), 1.0)
+        return -ch.rho(x, y, z)
+    return Workload(f"streamer_small_L3+{refinements}", bl, fn, meta=dict(c3=c3))
