@@ -1,0 +1,145 @@
+"""Benchmark: FP64 FMG solve throughput on the static streamer octree
+(base 64^3 + 4 refinement levels, ~4.8e6 leaf cells) on one MI355X.
+
+One step = one mg_fmg_solve: the FMG pass plus V(2,2) cycles until the
+relative residual is below 1e-8, residual checks included (tree creation and
+right-hand-side upload excluded).  value = leaf cells solved per second.
+
+Prints one JSON line with the solve throughput, the dominant kernel's
+roofline (red-black Gauss-Seidel half-sweep, timed with HIP events on the
+library's stream during the timed region) and the oracle's CPU throughput
+on the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+BETA_FP64 = 127.0          # bytes per stored cell per V(2,2) visit (per-sweep model)
+NORM_BYTES = 16.0          # bytes per leaf cell per residual check
+METRIC = ("cells/s per FMG solve to rel. residual 1e-8 (FP64 vs mixed vs learned); HBM GB/s")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gsrb_traffic_streamer_L4+4.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1708_08434_amd", "csrc", "kernels.hip")
+
+
+def model_bytes(level_counts, n_leaf, k):
+    """Per-sweep byte model of an FMG solve with k V-cycles after the FMG pass."""
+    cum, s = [], 0
+    for c in level_counts:
+        s += 512 * c
+        cum.append(s)
+    fmg = sum(BETA_FP64 * cum[l] for l in range(1, len(cum)))
+    return fmg + k * BETA_FP64 * cum[-1] + (k + 1) * NORM_BYTES * n_leaf
+
+
+def traffic_per_launch():
+    """HBM bytes per half-sweep launch from the committed rocprofv3 counter
+    summary, or None if the kernel source changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if rec.get("kernel_sha256") != src:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, gpu_cycles, budget_s=12.0):
+    import oracle as O
+    O.build(force=False)
+    threads = O.set_threads(0)
+    t = O.OracleTree.from_workload(w)
+    t.set_rhs_from(w)
+    times, cyc = [], None
+    t_start = time.perf_counter()
+    while len(times) < 3 or (time.perf_counter() - t_start < budget_s and len(times) < 7):
+        t0 = time.perf_counter()
+        st = t.fmg_solve(tol=1e-8)
+        times.append(time.perf_counter() - t0)
+        cyc = st["n_vcycles"]
+    med = statistics.median(times)
+    return {"value": w.n_leaf / med, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"full workload, {len(times)} FP64 FMG solves to 1e-8 "
+                      f"({cyc} V-cycles, GPU {gpu_cycles}), median {med:.3f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        sys.exit("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+                 "(see the sharding design).  Use --gpus 1.")
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    from paper_1708_08434_amd import mg as M
+    from workloads import c2
+
+    w = c2()
+    g = M.Tree.from_workload(w, device="cuda:0")
+    g.set_rhs_from(w)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        g.fmg_solve()
+    M.mg_timing_read(g.h)  # discard warm-up events
+    M.mg_timing_enable(g.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(args.steps):
+        stats = g.fmg_solve()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    M.mg_timing_enable(g.h, False)
+    kt = M.mg_timing_read(g.h)
+
+    n_leaf = int(g.info.n_leaf_cells)
+    ls = list(g.info.level_start[:g.nlev + 1])
+    counts = [ls[i + 1] - ls[i] for i in range(g.nlev)]
+    ms = 1e3 * elapsed / args.steps
+    value = n_leaf * args.steps / elapsed
+    k = stats["n_vcycles"]
+    mb = model_bytes(counts, n_leaf, k)
+    per_launch_s = kt["total_ms"] / 1e3 / max(kt["launches"], 1)
+    bytes_per_launch = kt["alg_bytes"] / max(kt["launches"], 1)
+    achieved = bytes_per_launch / per_launch_s / 1e9
+    tr = traffic_per_launch()
+    out = {
+        "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name + " static streamer octree (base 64^3 + 4 refinement levels)",
+                   "n_leaf": n_leaf, "n_boxes": g.n, "levels": g.nlev, "rel_tol": 1e-8,
+                   "vcycles_after_fmg": k, "final_rel_res": stats["rel"], "precision": "fp64",
+                   "smoothing": "V(2,2) red-black Gauss-Seidel"},
+        "roofline": {"bound": "hbm", "kernel": "k_gsrb (red-black Gauss-Seidel half-sweep)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": tr,
+                     "launches": kt["launches"], "avg_launch_us": per_launch_s * 1e6,
+                     "alg_bytes_per_launch": bytes_per_launch},
+        "model": {"bytes_per_solve": mb, "GBps": mb / (ms / 1e3) / 1e9,
+                  "roofline_cells_per_s": HBM_PEAK_GBPS * 1e9 * n_leaf / mb,
+                  "frac": value / (HBM_PEAK_GBPS * 1e9 * n_leaf / mb)},
+    }
+    if rank == 0 and not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, k)
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

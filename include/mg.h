@@ -1,0 +1,216 @@
+/*
+ * mg.h - C ABI of the MI355X octree multigrid Poisson solver.
+ *
+ * The library solves lap(phi) = b on the leaf cells of a block-structured
+ * octree of 8^3-cell boxes (paper section 2.1.1), with Dirichlet or Neumann
+ * conditions on the six faces of a cubic domain.  b is the caller's
+ * -rho/eps0 (the field equation of section 2.2); the library never applies
+ * physical constants.  The solver is geometric multigrid in
+ * full-approximation-scheme form with an FMG cycle, V-cycles and red-black
+ * Gauss-Seidel smoothing (section 2.1.2).
+ *
+ * Conventions shared by every call:
+ *   - A tree's root is one 8^3 box at level 1; a box at level l has integer
+ *     coordinates 0 <= i, j, k < 2^(l-1) and cell spacing
+ *     len / (8 * 2^(l-1)).  A refined box has all 8 children; neighbouring
+ *     boxes (over all 26 neighbours) differ by at most one level (proper
+ *     nesting, section 2.1.1).
+ *   - Boxes are renumbered into a canonical order: by level, then tree id,
+ *     then the Morton index of (i, j, k) (bit b of i, j, k goes to bit 3b,
+ *     3b+1, 3b+2).  Every per-box array the library reads or writes is in
+ *     canonical order; MG_IDX_ORDER maps canonical position -> caller index.
+ *   - Cell data crossing the ABI ("natural layout") is [box][k][j][i],
+ *     x fastest, 512 doubles per box.
+ *   - All device memory is owned by the caller.  mg_tree_info() reports the
+ *     workspace size; mg_tree_bind() attaches it.  The library does not
+ *     allocate device memory; it owns only host-side tables.
+ *   - Work is enqueued on the stream given to mg_tree_bind().  Calls that
+ *     return scalars to the host (mg_fmg_solve, mg_vcycle, mg_residual)
+ *     synchronise that stream before returning.
+ *   - Calls on one tree are not re-entrant; different trees are independent.
+ *   - Every call returns MG_OK (0) or a negative code; mg_last_error() gives
+ *     a thread-local message naming the offending box, face or argument.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MG_OK = 0,
+    MG_EINVAL = -1,   /* bad argument, duplicate box, coordinate out of range */
+    MG_ENESTING = -2, /* 2:1 proper nesting violated (26-neighbourhood)      */
+    MG_ENOMEM = -3,   /* host allocation failed or workspace too small        */
+    MG_EHIP = -4,     /* a HIP runtime call failed                            */
+    MG_ENOCONV = -5,  /* no convergence: max_cycles, non-finite or stagnating */
+    MG_ESTATE = -6,   /* call out of order (e.g. no workspace bound)          */
+    MG_ETOPO = -7     /* missing root, missing parent or incomplete siblings  */
+};
+
+enum { MG_DIRICHLET = 0, MG_NEUMANN = 1 };
+
+/* Domain [lo, lo+len]^3.  Faces are ordered -x, +x, -y, +y, -z, +z.
+ * Dirichlet ghosts are 2 g - phi_in with g = bc_val[face] (or the per-cell
+ * values of MG_FIELD_BCVAL when per_cell_bc is set); Neumann ghosts are
+ * phi_in (zero normal derivative).  At least one face must be Dirichlet. */
+typedef struct {
+    double lo[3];
+    double len;
+    int32_t bc_type[6];
+    double bc_val[6];
+    int32_t per_cell_bc; /* 1: reserve [n][6][64] per-face-cell Dirichlet data */
+} mg_domain;
+
+typedef struct mg_tree mg_tree;
+
+/* Sizes of a created tree. */
+typedef struct {
+    int64_t n_boxes;
+    int32_t n_levels;
+    int32_t n_trees;
+    int64_t n_leaf_boxes;
+    int64_t n_leaf_cells;        /* unknowns: 512 * n_leaf_boxes            */
+    int64_t n_cf_faces;          /* box faces on a refinement boundary      */
+    int64_t level_start[17];     /* boxes of level l: [level_start[l-1], level_start[l]) */
+    int64_t workspace_bytes;     /* device bytes mg_tree_bind() needs       */
+} mg_tree_info_t;
+
+/*
+ * mg_tree_create - validate a box list and build the tree's host tables.
+ *   n       number of boxes (> 0)
+ *   level   [n] host int32, 1 <= level <= 15
+ *   ijk     [n*3] host int32, box coordinates (i, j, k) per box
+ *   tree    [n] host int32 tree ids 0..T-1 (each tree needs a root), or NULL
+ *   dom     domain and boundary conditions
+ * Host-only: no device call is made.  Errors: MG_EINVAL (range, duplicates,
+ * bad boundary types, all-Neumann domain), MG_ETOPO, MG_ENESTING.  The
+ * arrays are copied; the caller keeps ownership.  *out is set on success.
+ */
+int mg_tree_create(mg_tree **out, const mg_domain *dom, int64_t n, const int32_t *level,
+                   const int32_t *ijk, const int32_t *tree);
+int mg_tree_destroy(mg_tree *t);
+int mg_tree_info(const mg_tree *t, mg_tree_info_t *info);
+
+/*
+ * mg_tree_bind - attach a caller-owned device workspace and a stream.
+ *   ws      device pointer, 256-byte aligned, >= info.workspace_bytes
+ *   stream  hipStream_t (as void*), e.g. torch.cuda.current_stream()
+ * Uploads the index tables into the workspace (asynchronously on stream) and
+ * zeroes the fields.  The workspace must stay valid until rebind or destroy.
+ */
+int mg_tree_bind(mg_tree *t, void *ws, int64_t ws_bytes, void *stream);
+
+/* Index tables (host output, canonical order), for inspection and tests. */
+enum {
+    MG_IDX_ORDER = 0,  /* [n]    caller index of each canonical box            */
+    MG_IDX_LEVEL = 1,  /* [n]                                                  */
+    MG_IDX_IJK = 2,    /* [n*3]                                                */
+    MG_IDX_TREE = 3,   /* [n]                                                  */
+    MG_IDX_PARENT = 4, /* [n]    -1 for roots                                  */
+    MG_IDX_CHILD = 5,  /* [n*8]  child (i&1)+2(j&1)+4(k&1), -1 for leaves      */
+    MG_IDX_NBR = 6,    /* [n*6]  same-level face neighbour, -1 refinement
+                                 boundary (coarser neighbour), -2 domain face  */
+    MG_IDX_CFQ = 7     /* [n*6]  coarser box across a refinement boundary, -1  */
+};
+int mg_tree_index(const mg_tree *t, int what, int32_t *host_out);
+
+/*
+ * Field transfer between caller memory in natural layout and the library's
+ * internal storage (colour-split: per box, the 256 cells with even i+j+k,
+ * then the 256 with odd i+j+k).
+ *   which   MG_FIELD_PHI (solution, all boxes), MG_FIELD_RHS (b; only leaf
+ *           boxes matter, covered boxes are overwritten by the solver),
+ *           MG_FIELD_BCVAL ([n][6][64] Dirichlet values at the face-cell
+ *           centres; per_cell_bc must be set; tangential axes in increasing
+ *           order, first fastest)
+ *   dev     device pointer to n*512 doubles (n*6*64 for BCVAL)
+ * Asynchronous on the bound stream.
+ */
+enum { MG_FIELD_PHI = 0, MG_FIELD_RHS = 1, MG_FIELD_OLD = 2, MG_FIELD_BCVAL = 3 };
+int mg_field_set(mg_tree *t, int which, const double *dev);
+int mg_field_get(const mg_tree *t, int which, double *dev);
+
+/* Solver options and statistics. */
+enum { MG_FP64 = 0 };
+typedef struct {
+    int32_t precision;   /* MG_FP64                                          */
+    int32_t n_down;      /* Gauss-Seidel sweeps before restriction (2)       */
+    int32_t n_up;        /* sweeps after prolongation (2)                    */
+    int32_t max_cycles;  /* V-cycles after the FMG pass (50)                 */
+    double rel_tol;      /* stop when |r|_2,V / |b_eff|_2,V <= rel_tol (1e-8)*/
+} mg_solve_opts;
+
+typedef struct {
+    int32_t n_vcycles;         /* V-cycles run after the FMG pass              */
+    int32_t status;
+    double rel_res;            /* final relative residual                      */
+    double l2;                 /* volume-weighted L2 norm of the leaf residual */
+    double linf;               /* max norm of the leaf residual                */
+    double beff_l2;            /* norm of the residual of phi = 0              */
+    double rel_hist[64];       /* after the FMG pass [0] and each V-cycle      */
+    double t_ms;               /* host wall time of the call                   */
+} mg_solve_stats;
+
+void mg_default_opts(mg_solve_opts *o);
+
+/*
+ * mg_fmg_solve - solve from phi = 0: one FMG pass (section 2.1.2: the
+ * initial potential), then V-cycles until the relative residual is below
+ * rel_tol.  The residual is the leaf residual after covered cells are reset
+ * to the mean of their children; its volume-weighted L2 norm is compared
+ * with that of the residual of phi = 0.  Returns MG_ENOCONV after
+ * max_cycles V-cycles, on a non-finite residual, or when it fails to
+ * decrease for 3 cycles in a row.  stats may be NULL.
+ */
+int mg_fmg_solve(mg_tree *t, const mg_solve_opts *o, mg_solve_stats *s);
+
+/*
+ * mg_vcycle - n V-cycles warm-started from the current phi (section 2.1.2:
+ * later updates of the potential reuse the previous one), then the residual
+ * check.  n <= 0 iterates until rel_tol (at most max_cycles).
+ */
+int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *s);
+
+/* Relative residual, L2 and max norms of the current phi (leaf cells). */
+int mg_residual(mg_tree *t, double *rel, double *l2, double *linf);
+
+/*
+ * mg_step - run one step of the cycle (diagnostics and step-by-step
+ * comparisons).  op: MG_OP_SMOOTH (level, arg sweeps), MG_OP_FAS_DOWN
+ * (residual, restriction, old copy and coarse right-hand side from level to
+ * level-1), MG_OP_PROLONG (add the prolonged coarse correction to level),
+ * MG_OP_COARSE (exact root solve), MG_OP_RESTRICT_ALL (covered cells <-
+ * mean of children, all levels), MG_OP_VCYCLE (V-cycle with level on top,
+ * arg sweeps each way).
+ */
+enum { MG_OP_SMOOTH = 1, MG_OP_FAS_DOWN = 2, MG_OP_PROLONG = 3, MG_OP_COARSE = 4,
+       MG_OP_RESTRICT_ALL = 5, MG_OP_VCYCLE = 6 };
+int mg_step(mg_tree *t, int op, int level, int arg);
+
+/*
+ * Kernel timing of the dominant kernel, the red-black Gauss-Seidel
+ * half-sweep.  While enabled, every half-sweep launch is bracketed by a pair
+ * of HIP events on the bound stream; mg_timing_read() synchronises the
+ * stream, returns the launch count, the summed event-pair time and the
+ * summed algorithmic bytes (per box and half-sweep: this colour's
+ * right-hand side and the other colour's solution read, this colour's
+ * solution written, 3 x 256 x 8 = 6144 bytes), and resets the counters.
+ */
+typedef struct {
+    int64_t launches;
+    double total_ms;
+    double alg_bytes;
+} mg_kernel_timing_t;
+int mg_timing_enable(mg_tree *t, int enable);
+int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out);
+
+const char *mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,73 @@
+// Internal state of an mg_tree: host tables built by tree.cpp, device views
+// carved out of the caller's workspace by solver.hip.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mg.h"
+
+namespace mg {
+
+constexpr int kMaxLevel = 15;
+constexpr int kCells = 512;      // cells per box
+constexpr int kHalf = 256;       // cells of one colour per box
+
+void set_error(const std::string &msg);
+
+// Device-side views of the workspace; all pointers are into one allocation.
+struct DevTables {
+    int32_t *nbr = nullptr;      // [n][6]  face neighbour (-1 refinement boundary, -2 domain)
+    int32_t *cfslot = nullptr;   // [n][6]  slot of a refinement-boundary face, or -1
+    int32_t *cfq = nullptr;      // [n][6]  coarser box across a refinement-boundary face
+    int32_t *ijk = nullptr;      // [n][4]  i, j, k, level
+    int32_t *parent = nullptr;   // [n]
+    int32_t *refined = nullptr;  // per-level lists of boxes with children
+    int32_t *leaf = nullptr;     // per-level lists of boxes without children
+    int32_t *slots = nullptr;    // [nslot][2] (box, face)
+    double *eig = nullptr;       // root solve: Q_x, Q_y, Q_z (8x8, column = vector), then lambda_x,y,z
+    double *phi = nullptr;       // [n][2][256] colour-split
+    double *rhs = nullptr;
+    double *old = nullptr;
+    double *chat = nullptr;      // [nslot][64] tangentially interpolated coarse values
+    double *bcval = nullptr;     // [n][6][64] or null
+    double *partial = nullptr;   // [n_leaf][2] per-box residual sums
+    double *result = nullptr;    // [8] reduced norms
+};
+
+}  // namespace mg
+
+struct mg_tree {
+    // ---- host tables (canonical order) ----
+    int64_t n = 0;
+    int nlev = 0, ntree = 0;
+    std::vector<int32_t> order, lev, ijk, tid, parent, child, nbr, cfq, cfslot;
+    int64_t lstart[mg::kMaxLevel + 2] = {0};
+    std::vector<int32_t> refined, leaf;                 // box ids grouped by level
+    int64_t rstart[mg::kMaxLevel + 2] = {0}, fstart[mg::kMaxLevel + 2] = {0};
+    std::vector<int32_t> slots;                         // (box, face) per slot
+    int64_t sstart[mg::kMaxLevel + 2] = {0};            // slots of level l: [sstart[l], sstart[l+1])
+    int64_t nslot = 0, nleaf = 0;
+    mg_domain dom{};
+    double eig[3 * 64 + 3 * 8] = {0};
+    // ---- workspace layout (byte offsets) ----
+    struct { int64_t nbr, cfslot, cfq, ijk, parent, refined, leaf, slots, eig, phi, rhs, old,
+             chat, bcval, partial, result, total; } off{};
+    // ---- bound device state ----
+    void *ws = nullptr;
+    void *stream = nullptr;
+    mg::DevTables d;
+    bool cf_valid[mg::kMaxLevel + 2] = {false};
+    double *host_result = nullptr;  // pinned host buffer for norms
+    // ---- optional event timing of the half-sweep kernel ----
+    bool timing = false;
+    std::vector<void *> ev_pool;                        // hipEvent_t, reused
+    std::vector<std::pair<void *, void *>> ev_pending;  // (start, end) per launch
+    double ev_bytes = 0.0;
+};
+
+namespace mg {
+int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level,
+               const int32_t *ijk, const int32_t *tree);
+void root_eigen(const int32_t bc_type[6], double *eig);
+}

@@ -1,0 +1,325 @@
+// Host-side octree construction: validation, canonical ordering and the
+// index tables the kernels use.
+//
+// Octree of N^3 boxes with N = 8 (paper section 2.1.1): a refined box is
+// covered by all 2^3 children, and proper nesting limits neighbouring boxes
+// (here: all 26 neighbours) to one level of difference.  Tables are built
+// level by level from parent relations, so a mesh change costs one linear
+// pass plus a sort (section 2.1.2 notes that geometric multigrid needs almost
+// no extra work when the mesh changes).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <tuple>
+
+#include "mg_internal.h"
+
+namespace mg {
+
+namespace {
+
+// Spread the low 21 bits of x so that bit b lands on bit 3b.
+uint64_t spread_bits3(uint32_t x) {
+    uint64_t v = x & 0x1fffffu;
+    v = (v | (v << 32)) & 0x1f00000000ffffULL;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+    v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+    v = (v | (v << 2)) & 0x1249249249249249ULL;
+    return v;
+}
+
+uint64_t morton(int32_t i, int32_t j, int32_t k) {
+    return spread_bits3((uint32_t)i) | (spread_bits3((uint32_t)j) << 1) |
+           (spread_bits3((uint32_t)k) << 2);
+}
+
+struct Key {
+    int32_t level, tree;
+    uint64_t m;
+    int32_t src;
+    bool operator<(const Key &o) const {
+        return std::tie(level, tree, m) < std::tie(o.level, o.tree, o.m);
+    }
+    bool same(const Key &o) const { return level == o.level && tree == o.tree && m == o.m; }
+};
+
+char g_buf[256];
+
+}  // namespace
+
+int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level,
+               const int32_t *ijk, const int32_t *tree) {
+    if (n <= 0 || n > (int64_t)1 << 30 || !level || !ijk || !dom || !(dom->len > 0)) {
+        set_error("mg_tree_create: invalid arguments");
+        return MG_EINVAL;
+    }
+    int dirichlet = 0;
+    for (int d = 0; d < 6; d++) {
+        if (dom->bc_type[d] != MG_DIRICHLET && dom->bc_type[d] != MG_NEUMANN) {
+            snprintf(g_buf, sizeof g_buf, "face %d: unknown boundary type %d", d, dom->bc_type[d]);
+            set_error(g_buf);
+            return MG_EINVAL;
+        }
+        dirichlet += dom->bc_type[d] == MG_DIRICHLET;
+    }
+    if (!dirichlet) {
+        set_error("all faces Neumann: the problem is singular");
+        return MG_EINVAL;
+    }
+    t->dom = *dom;
+
+    std::vector<Key> keys((size_t)n);
+    int ntree = 0;
+    for (int64_t b = 0; b < n; b++) {
+        int32_t l = level[b], tr = tree ? tree[b] : 0;
+        int32_t i = ijk[3 * b], j = ijk[3 * b + 1], k = ijk[3 * b + 2];
+        int32_t lim = (l >= 1 && l <= kMaxLevel) ? (1 << (l - 1)) : 0;
+        if (l < 1 || l > kMaxLevel || tr < 0 || tr > 65535 || i < 0 || j < 0 || k < 0 ||
+            i >= lim || j >= lim || k >= lim) {
+            snprintf(g_buf, sizeof g_buf, "box %lld: level %d / coordinates (%d,%d,%d) / tree %d out of range",
+                     (long long)b, l, i, j, k, tr);
+            set_error(g_buf);
+            return MG_EINVAL;
+        }
+        ntree = std::max(ntree, tr + 1);
+        keys[b] = Key{l, tr, morton(i, j, k), (int32_t)b};
+    }
+    std::sort(keys.begin(), keys.end());
+    for (int64_t b = 1; b < n; b++)
+        if (keys[b].same(keys[b - 1])) {
+            snprintf(g_buf, sizeof g_buf, "boxes %d and %d are duplicates", keys[b - 1].src, keys[b].src);
+            set_error(g_buf);
+            return MG_EINVAL;
+        }
+
+    t->n = n;
+    t->ntree = ntree;
+    t->order.resize(n);
+    t->lev.resize(n);
+    t->tid.resize(n);
+    t->ijk.resize(3 * n);
+    for (int64_t b = 0; b < n; b++) {
+        int32_t s = keys[b].src;
+        t->order[b] = s;
+        t->lev[b] = level[s];
+        t->tid[b] = tree ? tree[s] : 0;
+        for (int a = 0; a < 3; a++) t->ijk[3 * b + a] = ijk[3 * s + a];
+    }
+    t->nlev = t->lev[n - 1];
+    for (int l = 0; l <= kMaxLevel + 1; l++) t->lstart[l] = 0;
+    {
+        int64_t b = 0;
+        for (int l = 1; l <= kMaxLevel + 1; l++) {
+            t->lstart[l - 1] = b;  // level l starts at lstart[l-1]
+            while (b < n && t->lev[b] == l) b++;
+        }
+        t->lstart[kMaxLevel + 1] = n;
+    }
+    // From here on, boxes of level l occupy [lstart[l-1], lstart[l]).
+    auto lbegin = [&](int l) { return t->lstart[l - 1]; };
+    auto lend = [&](int l) { return l <= kMaxLevel ? t->lstart[l] : n; };
+
+    // roots: trees 0..T-1 each own a level-1 box
+    if (lend(1) - lbegin(1) != ntree) {
+        snprintf(g_buf, sizeof g_buf, "%d trees but %lld root boxes", ntree,
+                 (long long)(lend(1) - lbegin(1)));
+        set_error(g_buf);
+        return MG_ETOPO;
+    }
+    for (int64_t b = lbegin(1); b < lend(1); b++)
+        if (t->tid[b] != b - lbegin(1)) {
+            snprintf(g_buf, sizeof g_buf, "tree %lld has no root box", (long long)(b - lbegin(1)));
+            set_error(g_buf);
+            return MG_ETOPO;
+        }
+
+    // parents by binary search in the previous level's sorted range
+    t->parent.assign(n, -1);
+    t->child.assign(8 * n, -1);
+    for (int l = 2; l <= t->nlev; l++) {
+        const Key *pb = keys.data() + lbegin(l - 1), *pe = keys.data() + lend(l - 1);
+        for (int64_t b = lbegin(l); b < lend(l); b++) {
+            Key want{l - 1, t->tid[b], keys[b].m >> 3, 0};
+            const Key *it = std::lower_bound(pb, pe, want);
+            if (it == pe || !it->same(want)) {
+                snprintf(g_buf, sizeof g_buf, "box %d (level %d) has no parent", t->order[b], l);
+                set_error(g_buf);
+                return MG_ETOPO;
+            }
+            int32_t p = (int32_t)(it - keys.data());
+            int oct = (int)(keys[b].m & 7);  // (i&1) + 2(j&1) + 4(k&1)
+            t->parent[b] = p;
+            t->child[8 * p + oct] = (int32_t)b;
+        }
+    }
+    for (int64_t b = 0; b < n; b++) {
+        int c = 0;
+        for (int q = 0; q < 8; q++) c += t->child[8 * b + q] >= 0;
+        if (c != 0 && c != 8) {
+            snprintf(g_buf, sizeof g_buf, "box %d has %d of its 8 children", t->order[b], c);
+            set_error(g_buf);
+            return MG_ETOPO;
+        }
+    }
+
+    // 27-neighbourhood tables level by level: entry (ox,oy,oz) of box b is the
+    // same-level box at ijk + o, -1 when that position is covered only by a
+    // coarser leaf, -2 outside the domain.  A level-l box whose neighbour
+    // position is not covered down to level l-1 violates proper nesting.
+    std::vector<int32_t> n27((size_t)27 * n, -2);
+    for (int64_t b = lbegin(1); b < lend(1); b++) n27[27 * b + 13] = (int32_t)b;
+    for (int l = 2; l <= t->nlev; l++) {
+        int32_t lim = 1 << (l - 1);
+        for (int64_t b = lbegin(l); b < lend(l); b++) {
+            int32_t p = t->parent[b];
+            const int32_t *B = &t->ijk[3 * b];
+            for (int oz = -1; oz <= 1; oz++)
+                for (int oy = -1; oy <= 1; oy++)
+                    for (int ox = -1; ox <= 1; ox++) {
+                        int o[3] = {ox, oy, oz}, pos[3], up[3];
+                        bool inside = true;
+                        for (int a = 0; a < 3; a++) {
+                            pos[a] = B[a] + o[a];
+                            inside = inside && pos[a] >= 0 && pos[a] < lim;
+                            // offset of the containing level-(l-1) box from the parent
+                            up[a] = ((B[a] & 1) + o[a] + 2) / 2 - 1;
+                        }
+                        int oi = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
+                        if (!inside) { n27[27 * b + oi] = -2; continue; }
+                        int32_t cont = n27[27 * (int64_t)p + (up[0] + 1) + 3 * (up[1] + 1) + 9 * (up[2] + 1)];
+                        if (cont < 0) {
+                            snprintf(g_buf, sizeof g_buf,
+                                     "box %d (level %d) violates 2:1 nesting towards (%d,%d,%d)",
+                                     t->order[b], l, ox, oy, oz);
+                            set_error(g_buf);
+                            return MG_ENESTING;
+                        }
+                        int oct = (pos[0] & 1) + 2 * (pos[1] & 1) + 4 * (pos[2] & 1);
+                        n27[27 * b + oi] = t->child[8 * (int64_t)cont + oct];  // -1: coarser leaf
+                    }
+        }
+    }
+    // face tables
+    static const int face_oi[6] = {12, 14, 10, 16, 4, 22};
+    t->nbr.assign(6 * n, -2);
+    t->cfq.assign(6 * n, -1);
+    for (int64_t b = 0; b < n; b++) {
+        for (int d = 0; d < 6; d++) {
+            int32_t v = n27[27 * b + face_oi[d]];
+            t->nbr[6 * b + d] = v;
+            if (v == -1) {
+                int a = d >> 1, s = d & 1;
+                int32_t p = t->parent[b];
+                const int32_t *B = &t->ijk[3 * b];
+                int up[3] = {0, 0, 0};
+                up[a] = ((B[a] & 1) + (s ? 1 : -1) + 2) / 2 - 1;
+                t->cfq[6 * b + d] = n27[27 * (int64_t)p + (up[0] + 1) + 3 * (up[1] + 1) + 9 * (up[2] + 1)];
+            }
+        }
+    }
+    // refinement-boundary face slots, grouped by level
+    t->cfslot.assign(6 * n, -1);
+    t->slots.clear();
+    for (int l = 1; l <= kMaxLevel + 1; l++) {
+        t->sstart[l] = (int64_t)t->slots.size() / 2;
+        if (l > t->nlev) continue;
+        for (int64_t b = lbegin(l); b < lend(l); b++)
+            for (int d = 0; d < 6; d++)
+                if (t->nbr[6 * b + d] == -1) {
+                    t->cfslot[6 * b + d] = (int32_t)(t->slots.size() / 2);
+                    t->slots.push_back((int32_t)b);
+                    t->slots.push_back(d);
+                }
+    }
+    t->sstart[0] = 0;
+    t->nslot = (int64_t)t->slots.size() / 2;
+    // per-level lists of refined and leaf boxes
+    t->refined.clear();
+    t->leaf.clear();
+    for (int l = 1; l <= kMaxLevel + 1; l++) {
+        t->rstart[l] = (int64_t)t->refined.size();
+        t->fstart[l] = (int64_t)t->leaf.size();
+        if (l > t->nlev) continue;
+        for (int64_t b = lbegin(l); b < lend(l); b++)
+            (t->child[8 * b] >= 0 ? t->refined : t->leaf).push_back((int32_t)b);
+    }
+    t->nleaf = (int64_t)t->leaf.size();
+    root_eigen(dom->bc_type, t->eig);
+
+    // workspace layout
+    auto align = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { int64_t r = o; o = align(o + std::max<int64_t>(bytes, 8)); return r; };
+    t->off.nbr = take(24 * n);
+    t->off.cfslot = take(24 * n);
+    t->off.cfq = take(24 * n);
+    t->off.ijk = take(16 * n);
+    t->off.parent = take(4 * n);
+    t->off.refined = take(4 * (int64_t)t->refined.size());
+    t->off.leaf = take(4 * t->nleaf);
+    t->off.slots = take(8 * t->nslot);
+    t->off.eig = take(8 * (3 * 64 + 3 * 8));
+    t->off.phi = take(8 * kCells * n);
+    t->off.rhs = take(8 * kCells * n);
+    t->off.old = take(8 * kCells * n);
+    t->off.chat = take(8 * 64 * t->nslot);
+    t->off.bcval = dom->per_cell_bc ? take(8 * 6 * 64 * n) : -1;
+    t->off.partial = take(16 * t->nleaf);
+    t->off.result = take(8 * 8);
+    t->off.total = o;
+    return MG_OK;
+}
+
+// Eigen-decomposition of the 1-D second-difference matrix of the root box
+// along each axis (-2 on the diagonal, 1 off it; the end entries become -3
+// for a Dirichlet face and -1 for a Neumann face), by cyclic Jacobi rotations.
+// Used by the exact root solve (fast diagonalisation, Lynch, Rice & Thomas
+// 1964): A = (T_x (+) T_y (+) T_z) / h^2 is diagonal in the product basis.
+void root_eigen(const int32_t bc_type[6], double *eig) {
+    for (int a = 0; a < 3; a++) {
+        double A[8][8] = {{0}}, V[8][8] = {{0}};
+        for (int i = 0; i < 8; i++) {
+            A[i][i] = -2.0;
+            if (i > 0) A[i][i - 1] = 1.0;
+            if (i < 7) A[i][i + 1] = 1.0;
+            V[i][i] = 1.0;
+        }
+        A[0][0] += bc_type[2 * a] == MG_DIRICHLET ? -1.0 : 1.0;
+        A[7][7] += bc_type[2 * a + 1] == MG_DIRICHLET ? -1.0 : 1.0;
+        for (int sweep = 0; sweep < 100; sweep++) {
+            double off = 0.0;
+            for (int p = 0; p < 8; p++)
+                for (int q = p + 1; q < 8; q++) off += A[p][q] * A[p][q];
+            if (off < 1e-40) break;
+            for (int p = 0; p < 8; p++)
+                for (int q = p + 1; q < 8; q++) {
+                    if (std::fabs(A[p][q]) < 1e-300) continue;
+                    double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                    double tt = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                    double c = 1.0 / std::sqrt(tt * tt + 1.0), s = tt * c;
+                    for (int k = 0; k < 8; k++) {  // A <- A J
+                        double akp = A[k][p], akq = A[k][q];
+                        A[k][p] = c * akp - s * akq;
+                        A[k][q] = s * akp + c * akq;
+                    }
+                    for (int k = 0; k < 8; k++) {  // A <- J^T A
+                        double apk = A[p][k], aqk = A[q][k];
+                        A[p][k] = c * apk - s * aqk;
+                        A[q][k] = s * apk + c * aqk;
+                    }
+                    for (int k = 0; k < 8; k++) {  // V <- V J
+                        double vkp = V[k][p], vkq = V[k][q];
+                        V[k][p] = c * vkp - s * vkq;
+                        V[k][q] = s * vkp + c * vkq;
+                    }
+                }
+        }
+        for (int i = 0; i < 8; i++)
+            for (int m = 0; m < 8; m++) eig[a * 64 + i * 8 + m] = V[i][m];  // row i, eigenvector m
+        for (int m = 0; m < 8; m++) eig[192 + a * 8 + m] = A[m][m];
+    }
+}
+
+}  // namespace mg

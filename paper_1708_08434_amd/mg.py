@@ -1,0 +1,303 @@
+"""ctypes binding of libmg.so (declared in include/mg.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch supplies the device workspace and the stream.  There is no
+fallback: if libmg.so is missing or fails to load, this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmg.so")
+
+MG_OK, MG_EINVAL, MG_ENESTING, MG_ENOMEM, MG_EHIP, MG_ENOCONV, MG_ESTATE, MG_ETOPO = \
+    0, -1, -2, -3, -4, -5, -6, -7
+CODES = {0: "OK", -1: "EINVAL", -2: "ENESTING", -3: "ENOMEM", -4: "EHIP", -5: "ENOCONV",
+         -6: "ESTATE", -7: "ETOPO"}
+MG_DIRICHLET, MG_NEUMANN = 0, 1
+MG_IDX_ORDER, MG_IDX_LEVEL, MG_IDX_IJK, MG_IDX_TREE, MG_IDX_PARENT, MG_IDX_CHILD, MG_IDX_NBR, \
+    MG_IDX_CFQ = range(8)
+MG_FIELD_PHI, MG_FIELD_RHS, MG_FIELD_OLD, MG_FIELD_BCVAL = range(4)
+MG_FP64 = 0
+MG_OP_SMOOTH, MG_OP_FAS_DOWN, MG_OP_PROLONG, MG_OP_COARSE, MG_OP_RESTRICT_ALL, MG_OP_VCYCLE = \
+    range(1, 7)
+_WIDTH = {MG_IDX_ORDER: 1, MG_IDX_LEVEL: 1, MG_IDX_IJK: 3, MG_IDX_TREE: 1, MG_IDX_PARENT: 1,
+          MG_IDX_CHILD: 8, MG_IDX_NBR: 6, MG_IDX_CFQ: 6}
+
+EXPORTS = ["mg_tree_create", "mg_tree_destroy", "mg_tree_info", "mg_tree_bind", "mg_tree_index",
+           "mg_field_set", "mg_field_get", "mg_default_opts", "mg_fmg_solve", "mg_vcycle",
+           "mg_residual", "mg_step", "mg_timing_enable", "mg_timing_read", "mg_last_error"]
+
+
+class mg_domain(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("len", ctypes.c_double),
+                ("bc_type", ctypes.c_int32 * 6), ("bc_val", ctypes.c_double * 6),
+                ("per_cell_bc", ctypes.c_int32)]
+
+
+class mg_tree_info_t(ctypes.Structure):
+    _fields_ = [("n_boxes", ctypes.c_int64), ("n_levels", ctypes.c_int32),
+                ("n_trees", ctypes.c_int32), ("n_leaf_boxes", ctypes.c_int64),
+                ("n_leaf_cells", ctypes.c_int64), ("n_cf_faces", ctypes.c_int64),
+                ("level_start", ctypes.c_int64 * 17), ("workspace_bytes", ctypes.c_int64)]
+
+
+class mg_solve_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("n_down", ctypes.c_int32),
+                ("n_up", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
+                ("rel_tol", ctypes.c_double)]
+
+
+class mg_solve_stats(ctypes.Structure):
+    _fields_ = [("n_vcycles", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rel_res", ctypes.c_double), ("l2", ctypes.c_double), ("linf", ctypes.c_double),
+                ("beff_l2", ctypes.c_double), ("rel_hist", ctypes.c_double * 64),
+                ("t_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        n = self.n_vcycles
+        return dict(n_vcycles=n, status=self.status, rel=self.rel_res, l2=self.l2,
+                    linf=self.linf, beff=self.beff_l2, hist=np.array(self.rel_hist[:n + 1]),
+                    t_ms=self.t_ms)
+
+
+class mg_kernel_timing_t(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmg.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1708_08434_amd/build.py")
+        # torch loads its own copy of the HIP runtime (same soname); loading
+        # it first makes libmg bind to that copy, so one process holds a
+        # single HIP runtime and shares devices and streams with torch.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+        L.mg_tree_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(mg_domain), I64, P, P, P]
+        L.mg_tree_destroy.argtypes = [P]
+        L.mg_tree_info.argtypes = [P, ctypes.POINTER(mg_tree_info_t)]
+        L.mg_tree_bind.argtypes = [P, P, I64, P]
+        L.mg_tree_index.argtypes = [P, I32, P]
+        L.mg_field_set.argtypes = [P, I32, P]
+        L.mg_field_get.argtypes = [P, I32, P]
+        L.mg_default_opts.argtypes = [ctypes.POINTER(mg_solve_opts)]
+        L.mg_default_opts.restype = None
+        L.mg_fmg_solve.argtypes = [P, ctypes.POINTER(mg_solve_opts), ctypes.POINTER(mg_solve_stats)]
+        L.mg_vcycle.argtypes = [P, ctypes.POINTER(mg_solve_opts), I32,
+                                ctypes.POINTER(mg_solve_stats)]
+        L.mg_residual.argtypes = [P, P, P, P]
+        L.mg_step.argtypes = [P, I32, I32, I32]
+        L.mg_timing_enable.argtypes = [P, I32]
+        L.mg_timing_read.argtypes = [P, ctypes.POINTER(mg_kernel_timing_t)]
+        L.mg_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+class MGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{CODES.get(code, code)}: {msg}")
+        self.code = code
+        self.name = CODES.get(code, str(code))
+
+
+def check(rc):
+    if rc != MG_OK:
+        raise MGError(rc, lib().mg_last_error().decode())
+    return rc
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------- C-named calls
+
+def mg_tree_create(dom, level, ijk, tree=None):
+    level = np.ascontiguousarray(level, dtype=np.int32)
+    ijk = np.ascontiguousarray(np.asarray(ijk).reshape(-1, 3), dtype=np.int32)
+    tree = None if tree is None else np.ascontiguousarray(tree, dtype=np.int32)
+    h = ctypes.c_void_p()
+    check(lib().mg_tree_create(ctypes.byref(h), ctypes.byref(dom), len(level), _p(level), _p(ijk),
+                               None if tree is None else _p(tree)))
+    return h
+
+
+def mg_tree_destroy(h):
+    check(lib().mg_tree_destroy(h))
+
+
+def mg_tree_info(h):
+    info = mg_tree_info_t()
+    check(lib().mg_tree_info(h, ctypes.byref(info)))
+    return info
+
+
+def mg_tree_bind(h, ws_ptr, ws_bytes, stream_ptr):
+    check(lib().mg_tree_bind(h, ctypes.c_void_p(ws_ptr), int(ws_bytes), ctypes.c_void_p(stream_ptr)))
+
+
+def mg_tree_index(h, what, n):
+    out = np.zeros(n * _WIDTH[what], dtype=np.int32)
+    check(lib().mg_tree_index(h, what, _p(out)))
+    return out.reshape(n, _WIDTH[what]) if _WIDTH[what] > 1 else out
+
+
+def mg_field_set(h, which, dev_ptr):
+    check(lib().mg_field_set(h, which, ctypes.c_void_p(dev_ptr)))
+
+
+def mg_field_get(h, which, dev_ptr):
+    check(lib().mg_field_get(h, which, ctypes.c_void_p(dev_ptr)))
+
+
+def mg_default_opts():
+    o = mg_solve_opts()
+    lib().mg_default_opts(ctypes.byref(o))
+    return o
+
+
+def mg_fmg_solve(h, opts, raise_on_error=True):
+    st = mg_solve_stats()
+    rc = lib().mg_fmg_solve(h, ctypes.byref(opts), ctypes.byref(st))
+    if raise_on_error:
+        check(rc)
+    return st
+
+
+def mg_vcycle(h, opts, n_cycles, raise_on_error=True):
+    st = mg_solve_stats()
+    rc = lib().mg_vcycle(h, ctypes.byref(opts), int(n_cycles), ctypes.byref(st))
+    if raise_on_error:
+        check(rc)
+    return st
+
+
+def mg_residual(h):
+    rel, l2, linf = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    check(lib().mg_residual(h, ctypes.byref(rel), ctypes.byref(l2), ctypes.byref(linf)))
+    return dict(rel=rel.value, l2=l2.value, linf=linf.value)
+
+
+def mg_step(h, op, level=0, arg=0):
+    check(lib().mg_step(h, op, level, arg))
+
+
+def mg_timing_enable(h, enable):
+    check(lib().mg_timing_enable(h, int(bool(enable))))
+
+
+def mg_timing_read(h):
+    out = mg_kernel_timing_t()
+    check(lib().mg_timing_read(h, ctypes.byref(out)))
+    return dict(launches=out.launches, total_ms=out.total_ms, alg_bytes=out.alg_bytes)
+
+
+# --------------------------------------------------------- convenience
+
+def make_domain(lo=(0.0, 0.0, 0.0), length=1.0, bc_type=(0,) * 6, bc_val=(0.0,) * 6,
+                per_cell_bc=False):
+    d = mg_domain()
+    for a in range(3):
+        d.lo[a] = lo[a]
+    d.len = length
+    for f in range(6):
+        d.bc_type[f] = int(bc_type[f])
+        d.bc_val[f] = float(bc_val[f])
+    d.per_cell_bc = int(bool(per_cell_bc))
+    return d
+
+
+class Tree:
+    """An octree bound to a torch-allocated device workspace.
+
+    Fields cross the boundary as torch float64 tensors [n, 8, 8, 8] in
+    canonical box order (natural [k][j][i] layout)."""
+
+    def __init__(self, level, ijk, tree=None, lo=(0.0, 0.0, 0.0), length=1.0,
+                 bc_type=(0,) * 6, bc_val=(0.0,) * 6, per_cell_bc=False, device="cuda",
+                 stream=None, bind=True):
+        self.dom = make_domain(lo, length, bc_type, bc_val, per_cell_bc)
+        self.h = mg_tree_create(self.dom, level, ijk, tree)
+        self.info = mg_tree_info(self.h)
+        self.n = int(self.info.n_boxes)
+        self.nlev = int(self.info.n_levels)
+        self.length = float(length)
+        self.ws = None
+        if bind:
+            import torch
+            self.device = torch.device(device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(int(self.info.workspace_bytes), dtype=torch.uint8, device=self.device)
+            mg_tree_bind(self.h, self.ws.data_ptr(), self.ws.numel(), self.stream.cuda_stream)
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        b = w.boxes
+        return cls(b.level, b.ijk, b.tree, w.lo, w.length, w.bc_type, w.bc_val, **kw)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                mg_tree_destroy(self.h)
+            finally:
+                self.h = None
+
+    def index(self, what):
+        return mg_tree_index(self.h, what, self.n)
+
+    def leaf_mask(self):
+        return self.index(MG_IDX_CHILD)[:, 0] < 0
+
+    def set_field(self, which, x):
+        import torch
+        t = torch.as_tensor(x, dtype=torch.float64)
+        t = t.to(self.device).contiguous()
+        if which == MG_FIELD_BCVAL:
+            assert t.numel() == self.n * 6 * 64
+        else:
+            assert t.numel() == self.n * 512
+        mg_field_set(self.h, which, t.data_ptr())
+        self._keep = t  # the copy is asynchronous on the bound stream
+        return t
+
+    def get_field(self, which, to_numpy=True):
+        import torch
+        out = torch.empty((self.n, 8, 8, 8), dtype=torch.float64, device=self.device)
+        mg_field_get(self.h, which, out.data_ptr())
+        if to_numpy:
+            self.stream.synchronize()
+            return out.cpu().numpy()
+        return out
+
+    def set_rhs_from(self, w):
+        lv, ij = self.index(MG_IDX_LEVEL), self.index(MG_IDX_IJK)
+        self.set_field(MG_FIELD_RHS, w.rhs(lv, ij))
+
+    def opts(self, **kw):
+        o = mg_default_opts()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def fmg_solve(self, **kw):
+        return mg_fmg_solve(self.h, self.opts(**kw)).as_dict()
+
+    def vcycles(self, n, **kw):
+        return mg_vcycle(self.h, self.opts(**kw), n).as_dict()
+
+    def residual(self):
+        return mg_residual(self.h)
+
+    def step(self, op, level=0, arg=0):
+        mg_step(self.h, op, level, arg)

@@ -1,0 +1,195 @@
+"""GPU parity: every step of the cycle and whole solves, through the C ABI,
+against the oracle on the same seeded inputs.
+
+Tolerances: single steps 1e-12 of the field's largest magnitude (the two
+sides differ only by FMA contraction and summation order); whole solves a
+relative L2 difference of 1e-10 on the leaf potential with the same V-cycle
+count (the FP64 parity bar of the method's scope)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1708_08434_amd import mg as M
+from workloads import c1, c2, streamer_small, uniform_boxes, refine_boxes_explicit
+from tests import _geom as G
+
+pytestmark = pytest.mark.gpu
+
+STEP_TOL = 1e-12
+SOLVE_TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def pair(w, per_cell_bc=False):
+    g = M.Tree.from_workload(w, per_cell_bc=per_cell_bc)
+    o = O.OracleTree.from_workload(w)
+    assert np.array_equal(g.index(M.MG_IDX_ORDER), o.index(O.IDX_ORDER))
+    return g, o
+
+
+def relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def seed_fields(g, o, seed):
+    rng = np.random.default_rng(seed)
+    n = g.n
+    phi = rng.standard_normal((n, 8, 8, 8))
+    rhs = rng.standard_normal((n, 8, 8, 8)) * 100.0
+    old = phi + 0.1 * rng.standard_normal((n, 8, 8, 8))
+    for which_g, which_o, a in ((M.MG_FIELD_PHI, O.PHI, phi), (M.MG_FIELD_RHS, O.RHS, rhs),
+                                (M.MG_FIELD_OLD, O.OLD, old)):
+        g.set_field(which_g, a)
+        o.set_field(which_o, a)
+
+
+def compare_fields(g, o, what):
+    for which_g, which_o, name in ((M.MG_FIELD_PHI, O.PHI, "phi"), (M.MG_FIELD_RHS, O.RHS, "rhs"),
+                                   (M.MG_FIELD_OLD, O.OLD, "old")):
+        e = relmax(g.get_field(which_g), o.get_field(which_o))
+        assert e <= STEP_TOL, (what, name, e)
+
+
+STEPS = [("smooth", M.MG_OP_SMOOTH, O.OP_SMOOTH, "top", 1),
+         ("smooth2", M.MG_OP_SMOOTH, O.OP_SMOOTH, "mid", 2),
+         ("fas_down", M.MG_OP_FAS_DOWN, O.OP_FAS_DOWN, "top", 0),
+         ("fas_down_mid", M.MG_OP_FAS_DOWN, O.OP_FAS_DOWN, "mid", 0),
+         ("prolong", M.MG_OP_PROLONG, O.OP_PROLONG, "top", 0),
+         ("prolong_2", M.MG_OP_PROLONG, O.OP_PROLONG, 2, 0),
+         ("coarse", M.MG_OP_COARSE, O.OP_COARSE, 1, 0),
+         ("restrict_all", M.MG_OP_RESTRICT_ALL, O.OP_RESTRICT_ALL, 1, 0),
+         ("vcycle", M.MG_OP_VCYCLE, O.OP_VCYCLE, "top", 2)]
+
+
+@pytest.mark.parametrize("wname", ["uniform", "streamer"])
+@pytest.mark.parametrize("step", STEPS, ids=[s[0] for s in STEPS])
+def test_step_parity(wname, step):
+    name, gop, oop, lev, arg = step
+    w = c1() if wname == "uniform" else streamer_small()
+    g, o = pair(w)
+    level = {"top": o.nlev, "mid": o.nlev - 1}.get(lev, lev)
+    say("step", wname, name, "level", level, "boxes", g.n)
+    seed_fields(g, o, 17)
+    g.step(gop, level, arg)
+    o.step(oop, level, arg)
+    compare_fields(g, o, name)
+
+
+def test_step_parity_per_cell_dirichlet():
+    """Per-face-cell Dirichlet data through every ghost type and the root solve."""
+    bl = refine_boxes_explicit(2, [(2, 0, 0, 0), (3, 1, 1, 1), (3, 0, 1, 0), (4, 2, 2, 2)])
+    from workloads.configs import Workload, rhs_zero
+    w = Workload("amr_bcval", bl, rhs_zero, bc_type=(0, 0, 1, 0, 0, 0))
+    g, o = pair(w, per_cell_bc=True)
+    lv, ij = o.index(O.IDX_LEVEL), o.index(O.IDX_IJK)
+    bc = G.face_values(lv, ij, lambda x, y, z: np.sin(3 * x) + y * z)
+    g.set_field(M.MG_FIELD_BCVAL, bc)
+    o.set_bcval(bc)
+    for op_g, op_o, lev in ((M.MG_OP_VCYCLE, O.OP_VCYCLE, o.nlev), (M.MG_OP_COARSE, O.OP_COARSE, 1)):
+        seed_fields(g, o, 3)
+        g.step(op_g, lev, 2)
+        o.step(op_o, lev, 2)
+        compare_fields(g, o, "bcval")
+
+
+def solve_pair(w, tol=1e-8):
+    g, o = pair(w)
+    g.set_rhs_from(w)
+    o.set_rhs_from(w)
+    sg = g.fmg_solve(rel_tol=tol)
+    so = o.fmg_solve(tol=tol)
+    leaf = o.leaf_mask()
+    pg, po = g.get_field(M.MG_FIELD_PHI), o.get_field(O.PHI)
+    err = np.linalg.norm((pg - po)[leaf]) / np.linalg.norm(po[leaf])
+    return g, o, sg, so, err
+
+
+@pytest.mark.parametrize("wname", ["uniform64", "streamer_small"])
+def test_fmg_solve_parity(wname):
+    w = c1() if wname == "uniform64" else streamer_small()
+    say("fmg parity", wname, w.boxes.n, "boxes")
+    g, o, sg, so, err = solve_pair(w)
+    assert sg["n_vcycles"] == so["n_vcycles"], (sg["hist"], so["hist"])
+    assert err <= SOLVE_TOL, err
+    np.testing.assert_allclose(sg["hist"], so["hist"], rtol=1e-5)
+    assert sg["rel"] <= 1e-8
+
+
+def test_fmg_solve_parity_full_streamer():
+    """The benchmark workload at full size (base 64^3 + 4 refinement levels,
+    ~4.8e6 leaf cells) in the same launch sequence the benchmark times."""
+    w = c2()
+    say("fmg parity full streamer", w.boxes.n, "boxes", w.n_leaf, "leaf cells")
+    g, o, sg, so, err = solve_pair(w)
+    say("  gpu", sg["n_vcycles"], sg["rel"], "oracle", so["n_vcycles"], so["rel"], "err", err)
+    assert sg["n_vcycles"] == so["n_vcycles"]
+    assert err <= SOLVE_TOL, err
+
+
+def test_warm_vcycles_parity():
+    w = streamer_small()
+    g, o = pair(w)
+    g.set_rhs_from(w)
+    o.set_rhs_from(w)
+    g.fmg_solve(rel_tol=1e-6)
+    o.fmg_solve(tol=1e-6)
+    b = o.get_field(O.RHS)
+    leaf = o.leaf_mask()
+    b[leaf] *= 1.01
+    g.set_field(M.MG_FIELD_RHS, b)
+    o.set_field(O.RHS, b)
+    sg = g.vcycles(2)
+    so = o.vcycles(2)
+    np.testing.assert_allclose(sg["hist"], so["hist"], rtol=1e-5)
+    pg, po = g.get_field(M.MG_FIELD_PHI), o.get_field(O.PHI)
+    assert np.linalg.norm((pg - po)[leaf]) / np.linalg.norm(po[leaf]) <= SOLVE_TOL
+
+
+def test_residual_matches_oracle():
+    w = streamer_small()
+    g, o = pair(w)
+    seed_fields(g, o, 5)
+    rg, ro = g.residual(), o.residual()
+    for k in ("rel", "l2", "linf"):
+        assert abs(rg[k] - ro[k]) <= 1e-12 * abs(ro[k]), (k, rg[k], ro[k])
+
+
+def test_bitwise_repeatable():
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    g.fmg_solve()
+    a = g.get_field(M.MG_FIELD_PHI)
+    g.fmg_solve()
+    b = g.get_field(M.MG_FIELD_PHI)
+    assert np.array_equal(a, b)
+
+
+def test_linear_exact_on_gpu():
+    """Section 3.1 boundary setup on an AMR tree: the GPU solution is the
+    linear potential at every leaf cell."""
+    bl = refine_boxes_explicit(2, [(2, 0, 0, 0), (3, 1, 1, 1), (3, 0, 1, 0), (4, 2, 2, 2)])
+    g = M.Tree(bl.level, bl.ijk, None, bc_type=(1, 1, 1, 1, 0, 0), bc_val=(0, 0, 0, 0, 0, 1.0))
+    g.set_field(M.MG_FIELD_RHS, np.zeros((g.n, 8, 8, 8)))
+    g.fmg_solve(rel_tol=1e-13)
+    x, y, z, h = G.cell_centres(g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK))
+    leaf = g.leaf_mask()
+    assert np.abs(g.get_field(M.MG_FIELD_PHI)[leaf] - z[leaf]).max() < 1e-11
+
+
+def test_errors_are_reported():
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    b = w.rhs(g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK))
+    b[g.leaf_mask().nonzero()[0][0], 0, 0, 0] = np.nan
+    g.set_field(M.MG_FIELD_RHS, b)
+    st = M.mg_fmg_solve(g.h, g.opts(), raise_on_error=False)
+    assert st.status == M.MG_ENOCONV
+    g.set_rhs_from(w)
+    st = M.mg_fmg_solve(g.h, g.opts(max_cycles=1), raise_on_error=False)
+    assert st.status == M.MG_ENOCONV
+    with pytest.raises(M.MGError):
+        g.step(M.MG_OP_SMOOTH, 99, 1)
