@@ -124,28 +124,47 @@ int mg_tree_index(const mg_tree *t, int what, int32_t *host_out);
  * then the 256 with odd i+j+k).
  *   which   MG_FIELD_PHI (solution, all boxes), MG_FIELD_RHS (b; only leaf
  *           boxes matter, covered boxes are overwritten by the solver),
+ *           MG_FIELD_OLD, MG_FIELD_E32 / _R32 / _OLD32 (FP32 fields, rounded
+ *           on the way in),
  *           MG_FIELD_BCVAL ([n][6][64] Dirichlet values at the face-cell
  *           centres; per_cell_bc must be set; tangential axes in increasing
  *           order, first fastest)
  *   dev     device pointer to n*512 doubles (n*6*64 for BCVAL)
  * Asynchronous on the bound stream.
  */
-enum { MG_FIELD_PHI = 0, MG_FIELD_RHS = 1, MG_FIELD_OLD = 2, MG_FIELD_BCVAL = 3 };
+enum { MG_FIELD_PHI = 0, MG_FIELD_RHS = 1, MG_FIELD_OLD = 2, MG_FIELD_BCVAL = 3,
+       /* FP32 fields of the mixed-precision correction solve (converted to and
+          from FP64 natural-layout arrays): correction, its right-hand side,
+          and its old copy */
+       MG_FIELD_E32 = 4, MG_FIELD_R32 = 5, MG_FIELD_OLD32 = 6 };
 int mg_field_set(mg_tree *t, int which, const double *dev);
 int mg_field_get(const mg_tree *t, int which, double *dev);
 
-/* Solver options and statistics. */
-enum { MG_FP64 = 0 };
+/* Solver options and statistics.
+ * MG_FP64: the multigrid cycles run on the FP64 solution.
+ * MG_MIXED: iterative refinement.  Each step computes the FP64 leaf residual
+ *   r = b - L phi (after covered cells are reset to the mean of their
+ *   children), stores it rounded to FP32 as the right-hand side of the
+ *   correction problem L e = r with homogeneous boundary data, solves that
+ *   in FP32 from e = 0 (an FMG pass in the first step, one V-cycle after),
+ *   and updates phi += e in FP64.  The root solve stays FP64; the stopping
+ *   test is the FP64 one, so the result meets the same tolerance. */
+enum { MG_FP64 = 0, MG_MIXED = 1 };
 typedef struct {
     int32_t precision;   /* MG_FP64                                          */
     int32_t n_down;      /* Gauss-Seidel sweeps before restriction (2)       */
     int32_t n_up;        /* sweeps after prolongation (2)                    */
     int32_t max_cycles;  /* V-cycles after the FMG pass (50)                 */
     double rel_tol;      /* stop when |r|_2,V / |b_eff|_2,V <= rel_tol (1e-8)*/
+    int32_t graphs;      /* 1: record the FMG pass and the V-cycle + residual
+                            check once as HIP graphs and replay them on the
+                            bound stream; 0: launch kernel by kernel.  Both
+                            run the same kernels in the same order.  (1)     */
 } mg_solve_opts;
 
 typedef struct {
-    int32_t n_vcycles;         /* V-cycles run after the FMG pass              */
+    int32_t n_vcycles;         /* V-cycles run after the FMG pass (MG_MIXED:
+                                  refinement steps)                            */
     int32_t status;
     double rel_res;            /* final relative residual                      */
     double l2;                 /* volume-weighted L2 norm of the leaf residual */
@@ -188,22 +207,30 @@ int mg_residual(mg_tree *t, double *rel, double *l2, double *linf);
  * arg sweeps each way).
  */
 enum { MG_OP_SMOOTH = 1, MG_OP_FAS_DOWN = 2, MG_OP_PROLONG = 3, MG_OP_COARSE = 4,
-       MG_OP_RESTRICT_ALL = 5, MG_OP_VCYCLE = 6 };
+       MG_OP_RESTRICT_ALL = 5, MG_OP_VCYCLE = 6,
+       MG_OP_F32 = 0x100 /* or-ed in: apply the step to the FP32 correction
+                            fields (homogeneous boundary data)            */ };
 int mg_step(mg_tree *t, int op, int level, int arg);
 
 /*
  * Kernel timing of the dominant kernel, the red-black Gauss-Seidel
- * half-sweep.  While enabled, every half-sweep launch is bracketed by a pair
- * of HIP events on the bound stream; mg_timing_read() synchronises the
- * stream, returns the launch count, the summed event-pair time and the
- * summed algorithmic bytes (per box and half-sweep: this colour's
- * right-hand side and the other colour's solution read, this colour's
- * solution written, 3 x 256 x 8 = 6144 bytes), and resets the counters.
+ * half-sweep.  While enabled, the solver launches kernel by kernel (no graph
+ * replay) and brackets the consecutive half-sweeps of every smoothing call
+ * with a pair of HIP events on the bound stream.  mg_timing_read()
+ * synchronises the stream and returns, summed over all pairs since the last
+ * read, the half-sweep launch count, the event-pair time and the algorithmic
+ * bytes (per box and half-sweep: this colour's right-hand side and the other
+ * colour's solution read, this colour's solution written,
+ * 3 x 256 x 8 = 6144 bytes in FP64, 3072 in FP32), in total and per level;
+ * then it resets the sums.
  */
 typedef struct {
     int64_t launches;
     double total_ms;
     double alg_bytes;
+    int64_t level_launches[16]; /* the same sums per level (index level-1) */
+    double level_ms[16];
+    double level_bytes[16];
 } mg_kernel_timing_t;
 int mg_timing_enable(mg_tree *t, int enable);
 int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out);

@@ -13,32 +13,42 @@ struct Geo {
     const int32_t *cfq;     // [n][6]
     const int32_t *ijk;     // [n][4] (i, j, k, level)
     const int32_t *parent;  // [n]
-    const double *chat;     // [nslot][64]
     const double *bcval;    // [n][6][64] or null
     double bcv[6];
     int32_t bct[6];
     double len;
 };
 
-void launch_fill(double *p, int64_t count, double v, hipStream_t s);
-void launch_pack(const double *nat, double *cs, int64_t nbox, hipStream_t s);
-void launch_unpack(const double *cs, double *nat, int64_t nbox, hipStream_t s);
-void launch_gsrb(const Geo &g, double *phi, const double *rhs, int64_t b0, int64_t nb, double h2,
+// Launchers are templates over the field type T (double, or float for the
+// correction cycles of the mixed-precision solve); c_hat has the field's type.
+template <typename T> void launch_fill(T *p, int64_t count, T v, hipStream_t s);
+template <typename T> void launch_pack(const double *nat, T *cs, int64_t nbox, hipStream_t s);
+template <typename T> void launch_unpack(const T *cs, double *nat, int64_t nbox, hipStream_t s);
+template <typename T>
+void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
                  int colour, hipStream_t s);
-void launch_cf_coarse(const Geo &g, const double *phi, double *chat, const int32_t *slots,
-                      int64_t s0, int64_t ns, hipStream_t s);
-void launch_resid_restrict(const Geo &g, double *phi, double *rhs, double *old, int64_t b0,
-                           int64_t nb, const int32_t *leaf_prev, int64_t nleaf_prev,
-                           double inv_h2, hipStream_t s);
-void launch_fas_rhs(const Geo &g, const double *phi, double *rhs, const int32_t *list,
-                    int64_t nlist, double inv_h2, hipStream_t s);
-void launch_prolong(const Geo &g, double *phi, const double *old, int64_t b0, int64_t nb,
-                    hipStream_t s);
-void launch_coarse(const Geo &g, double *phi, const double *rhs, const double *eig, int64_t b0,
-                   int64_t nroot, double h, hipStream_t s);
-void launch_restrict_phi(const Geo &g, double *phi, int64_t b0, int64_t nb, hipStream_t s);
-void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const int32_t *leaf,
-                       int64_t nleaf, double *partial, hipStream_t s);
+template <typename T>
+void launch_cf_coarse(const Geo &g, const T *phi, T *chat, const int32_t *slots, int64_t s0,
+                      int64_t ns, hipStream_t s);
+template <typename T>
+void launch_resid_restrict(const Geo &g, T *phi, T *rhs, T *old, const T *chat, int64_t b0,
+                           int64_t nb, const int32_t *leaf_prev, int64_t nleaf_prev, T inv_h2,
+                           hipStream_t s);
+template <typename T>
+void launch_fas_rhs(const Geo &g, const T *phi, T *rhs, const T *chat, const int32_t *list,
+                    int64_t nlist, T inv_h2, hipStream_t s);
+template <typename T>
+void launch_prolong_cf(const Geo &g, T *phi, const T *old, int64_t b0, int64_t nb, T *chat,
+                       const int32_t *slots, int64_t s0, int64_t ns, hipStream_t s);
+template <typename T>
+void launch_coarse(const Geo &g, T *phi, const T *rhs, const double *eig, int64_t b0, int64_t nroot,
+                   double h, hipStream_t s);
+template <typename T>
+void launch_restrict_phi(const Geo &g, T *phi, int64_t b0, int64_t nb, hipStream_t s);
+void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const double *chat,
+                       const int32_t *leaf, int64_t nleaf, double *partial, float *r_out,
+                       hipStream_t s);
+void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s);
 void launch_reduce(const double *partial, int64_t n, double *result, hipStream_t s);
 
 }  // namespace mg

@@ -2,8 +2,10 @@
 //
 // The driver enqueues the kernels of kernels.hip on the caller's stream in
 // the order of the full-approximation-scheme FMG / V-cycle (paper section
-// 2.1.2).  The only device-to-host transfer per cycle is the pair of
-// reduced residual norms used by the stopping test.
+// 2.1.2).  Fixed launch sequences (the FMG pass, one V-cycle plus residual
+// check, and the steps of the mixed-precision refinement) are recorded once
+// as HIP graphs and replayed; the only device-to-host transfer per cycle is
+// the pair of reduced residual norms used by the stopping test.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -23,7 +25,7 @@ void set_error(const std::string &msg) { g_error = msg; }
 
 namespace {
 
-hipStream_t stream_of(const mg_tree *t) { return (hipStream_t)t->stream; }
+hipStream_t stream_of(const mg_tree *t) { return (hipStream_t)t->cur_stream; }
 
 double hlev(const mg_tree *t, int l) { return t->dom.len / (8.0 * (double)(1 << (l - 1))); }
 int64_t lbeg(const mg_tree *t, int l) { return t->lstart[l - 1]; }
@@ -37,36 +39,49 @@ int hip_check(hipError_t e, const char *what) {
     return MG_EHIP;
 }
 
-Geo geo(const mg_tree *t) {
+// Geometry and boundary data for the kernels.  The FP32 correction problem
+// of the mixed-precision solve has homogeneous boundary data.
+Geo geo(const mg_tree *t, bool homogeneous) {
     Geo g;
     g.nbr = t->d.nbr;
     g.cfslot = t->d.cfslot;
     g.cfq = t->d.cfq;
     g.ijk = t->d.ijk;
     g.parent = t->d.parent;
-    g.chat = t->d.chat;
-    g.bcval = t->dom.per_cell_bc ? t->d.bcval : nullptr;
+    g.bcval = (!homogeneous && t->dom.per_cell_bc) ? t->d.bcval : nullptr;
     for (int d = 0; d < 6; d++) {
-        g.bcv[d] = t->dom.bc_val[d];
+        g.bcv[d] = homogeneous ? 0.0 : t->dom.bc_val[d];
         g.bct[d] = t->dom.bc_type[d];
     }
     g.len = t->dom.len;
     return g;
 }
 
-// ---- refinement-boundary data: c_hat of level l depends on phi of level
-// l-1 only; it is recomputed lazily after level l-1 changes.
-void dirty(mg_tree *t, int l) {
-    if (l + 1 <= kMaxLevel) t->cf_valid[l + 1] = false;
+// One set of multigrid fields: the FP64 solution or the FP32 correction.
+template <typename T>
+struct Fields {
+    T *phi, *rhs, *old, *chat;
+    bool *cf_valid;  // c_hat of level l is current (it depends on level l-1 only)
+    Geo g;
+};
+Fields<double> f64(mg_tree *t) {
+    return {t->d.phi, t->d.rhs, t->d.old, t->d.chat, t->cf_valid, geo(t, false)};
 }
-void dirty_all(mg_tree *t) {
-    for (int l = 0; l <= kMaxLevel + 1; l++) t->cf_valid[l] = false;
+Fields<float> f32(mg_tree *t) {
+    return {t->d.e32, t->d.r32, t->d.old32, t->d.chat32, t->cf_valid32, geo(t, true)};
 }
-void ensure_cf(mg_tree *t, int l) {
-    if (l < 2 || l > t->nlev || t->cf_valid[l]) return;
+
+template <typename T> void dirty(const Fields<T> &F, int l) {
+    if (l + 1 <= kMaxLevel) F.cf_valid[l + 1] = false;
+}
+template <typename T> void dirty_all(const Fields<T> &F) {
+    for (int l = 0; l <= kMaxLevel + 1; l++) F.cf_valid[l] = false;
+}
+template <typename T> void ensure_cf(mg_tree *t, const Fields<T> &F, int l) {
+    if (l < 2 || l > t->nlev || F.cf_valid[l]) return;
     int64_t s0 = t->sstart[l], ns = t->sstart[l + 1] - t->sstart[l];
-    launch_cf_coarse(geo(t), t->d.phi, t->d.chat, t->d.slots, s0, ns, stream_of(t));
-    t->cf_valid[l] = true;
+    launch_cf_coarse<T>(F.g, F.phi, F.chat, t->d.slots, s0, ns, stream_of(t));
+    F.cf_valid[l] = true;
 }
 
 // ---- optional event timing of the half-sweep launches
@@ -80,79 +95,121 @@ hipEvent_t take_event(mg_tree *t) {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
+void give_event(mg_tree *t, hipEvent_t e) {
+    if (e) t->ev_pool.push_back((void *)e);
+}
 
 // ---- steps of the cycle
-void smooth(mg_tree *t, int l, int nsweep) {
+template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsweep) {
     if (nsweep <= 0) return;
-    ensure_cf(t, l);
-    double h = hlev(t, l), h2 = h * h;
-    Geo g = geo(t);
-    for (int it = 0; it < nsweep; it++)
-        for (int c = 0; c < 2; c++) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (t->timing && (e0 = take_event(t)) && (e1 = take_event(t)))
-                (void)hipEventRecord(e0, stream_of(t));
-            launch_gsrb(g, t->d.phi, t->d.rhs, lbeg(t, l), lcount(t, l), h2, c, stream_of(t));
-            if (e0 && e1) {
-                (void)hipEventRecord(e1, stream_of(t));
-                t->ev_pending.emplace_back((void *)e0, (void *)e1);
-                t->ev_bytes += 6144.0 * (double)lcount(t, l);
-            }
-        }
-    dirty(t, l);
-}
-
-void fas_down(mg_tree *t, int l) {
-    ensure_cf(t, l);
+    ensure_cf(t, F, l);
     double h = hlev(t, l);
-    launch_resid_restrict(geo(t), t->d.phi, t->d.rhs, t->d.old, lbeg(t, l), lcount(t, l),
-                          t->d.leaf + t->fstart[l - 1], t->fstart[l] - t->fstart[l - 1],
-                          1.0 / (h * h), stream_of(t));
-    dirty(t, l - 1);
-    ensure_cf(t, l - 1);
+    T h2 = (T)(h * h);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (t->timing) {
+        e0 = take_event(t);
+        e1 = take_event(t);
+        if (!e0 || !e1 || hipEventRecord(e0, stream_of(t)) != hipSuccess) {
+            give_event(t, e0);
+            give_event(t, e1);
+            e0 = e1 = nullptr;
+        }
+    }
+    for (int it = 0; it < nsweep; it++)
+        for (int c = 0; c < 2; c++)
+            launch_gsrb<T>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l), h2, c, stream_of(t));
+    if (e0) {
+        if (hipEventRecord(e1, stream_of(t)) == hipSuccess) {
+            t->probes.push_back({(void *)e0, (void *)e1, l, 2 * (int64_t)nsweep,
+                                 3.0 * 256 * sizeof(T) * (double)lcount(t, l) * 2 * nsweep});
+        } else {
+            give_event(t, e0);
+            give_event(t, e1);
+        }
+    }
+    dirty(F, l);
+}
+
+template <typename T> void fas_down(mg_tree *t, const Fields<T> &F, int l) {
+    ensure_cf(t, F, l);
+    double h = hlev(t, l);
+    launch_resid_restrict<T>(F.g, F.phi, F.rhs, F.old, F.chat, lbeg(t, l), lcount(t, l),
+                             t->d.leaf + t->fstart[l - 1], t->fstart[l] - t->fstart[l - 1],
+                             (T)(1.0 / (h * h)), stream_of(t));
+    dirty(F, l - 1);
+    ensure_cf(t, F, l - 1);
     double hc = hlev(t, l - 1);
-    launch_fas_rhs(geo(t), t->d.phi, t->d.rhs, t->d.refined + t->rstart[l - 1],
-                   t->rstart[l] - t->rstart[l - 1], 1.0 / (hc * hc), stream_of(t));
+    launch_fas_rhs<T>(F.g, F.phi, F.rhs, F.chat, t->d.refined + t->rstart[l - 1],
+                      t->rstart[l] - t->rstart[l - 1], (T)(1.0 / (hc * hc)), stream_of(t));
 }
 
-void prolong(mg_tree *t, int l) {
-    launch_prolong(geo(t), t->d.phi, t->d.old, lbeg(t, l), lcount(t, l), stream_of(t));
-    dirty(t, l);
+// Prolongation into level l, fused with the c_hat pass of level l (both read
+// only level l-1, which is final at this point of the up-leg).
+template <typename T> void prolong(mg_tree *t, const Fields<T> &F, int l) {
+    int64_t s0 = t->sstart[l], ns = t->sstart[l + 1] - t->sstart[l];
+    launch_prolong_cf<T>(F.g, F.phi, F.old, lbeg(t, l), lcount(t, l), F.chat, t->d.slots, s0, ns,
+                         stream_of(t));
+    F.cf_valid[l] = true;
+    dirty(F, l);
 }
 
-void coarse(mg_tree *t) {
-    launch_coarse(geo(t), t->d.phi, t->d.rhs, t->d.eig, lbeg(t, 1), lcount(t, 1), hlev(t, 1),
-                  stream_of(t));
-    dirty(t, 1);
+// Exact root solve (computed in FP64 for either field type).
+template <typename T> void coarse(mg_tree *t, const Fields<T> &F) {
+    launch_coarse<T>(F.g, F.phi, F.rhs, t->d.eig, lbeg(t, 1), lcount(t, 1), hlev(t, 1), stream_of(t));
+    dirty(F, 1);
 }
 
-void restrict_all(mg_tree *t) {
+template <typename T> void restrict_all(mg_tree *t, const Fields<T> &F) {
     for (int l = t->nlev; l >= 2; l--) {
-        launch_restrict_phi(geo(t), t->d.phi, lbeg(t, l), lcount(t, l), stream_of(t));
-        dirty(t, l - 1);
+        launch_restrict_phi<T>(F.g, F.phi, lbeg(t, l), lcount(t, l), stream_of(t));
+        dirty(F, l - 1);
     }
 }
 
-void vcycle(mg_tree *t, int top, int nd, int nu) {
+template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int nd, int nu) {
     for (int l = top; l >= 2; l--) {
-        smooth(t, l, nd);
-        fas_down(t, l);
+        smooth(t, F, l, nd);
+        fas_down(t, F, l);
     }
-    coarse(t);
+    coarse(t, F);
     for (int l = 2; l <= top; l++) {
-        prolong(t, l);
-        smooth(t, l, nu);
+        prolong(t, F, l);
+        smooth(t, F, l, nu);
     }
+}
+
+// FMG pass from the current (zero) field: FAS data top-down, root solve, then
+// for each finer level the prolonged correction and one V-cycle on top.
+template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int nu) {
+    for (int l = t->nlev; l >= 2; l--) fas_down(t, F, l);
+    coarse(t, F);
+    for (int l = 2; l <= t->nlev; l++) {
+        prolong(t, F, l);
+        vcycle(t, F, l, nd, nu);
+    }
+}
+
+// Leaf residual norms of the FP64 solution into result[slot], result[slot+1]
+// (sum of r^2 h^3, max |r|); r32 != null also stores the residual in FP32.
+void norms_launch(mg_tree *t, int slot, float *r32) {
+    Fields<double> F = f64(t);
+    for (int l = 2; l <= t->nlev; l++) ensure_cf(t, F, l);
+    launch_leaf_norms(F.g, F.phi, F.rhs, F.chat, t->d.leaf, t->nleaf, t->d.partial, r32,
+                      stream_of(t));
+    launch_reduce(t->d.partial, t->nleaf, t->d.result + slot, stream_of(t));
+}
+
+int read_results(mg_tree *t, int count) {
+    int rc = hip_check(hipMemcpyAsync(t->host_result, t->d.result, count * sizeof(double),
+                                      hipMemcpyDeviceToHost, (hipStream_t)t->stream), "norm readback");
+    if (rc) return rc;
+    return hip_check(hipStreamSynchronize((hipStream_t)t->stream), "stream synchronize");
 }
 
 int norms(mg_tree *t, double *l2, double *linf) {
-    for (int l = 2; l <= t->nlev; l++) ensure_cf(t, l);
-    launch_leaf_norms(geo(t), t->d.phi, t->d.rhs, t->d.leaf, t->nleaf, t->d.partial, stream_of(t));
-    launch_reduce(t->d.partial, t->nleaf, t->d.result, stream_of(t));
-    int rc = hip_check(hipMemcpyAsync(t->host_result, t->d.result, 2 * sizeof(double),
-                                      hipMemcpyDeviceToHost, stream_of(t)), "norm readback");
+    norms_launch(t, 0, nullptr);
+    int rc = read_results(t, 2);
     if (rc) return rc;
-    if ((rc = hip_check(hipStreamSynchronize(stream_of(t)), "stream synchronize"))) return rc;
     *l2 = std::sqrt(t->host_result[0]);
     *linf = t->host_result[1];
     return MG_OK;
@@ -161,32 +218,140 @@ int norms(mg_tree *t, double *l2, double *linf) {
 // Norm of the residual of phi = 0 (boundary data folded in).  The current
 // phi is parked in the old field, which holds no state between calls (every
 // down-leg rewrites it before the up-leg reads it).
-int beff_norm(mg_tree *t, bool phi_is_zero, double *beff) {
+int beff_norm(mg_tree *t, double *beff) {
+    Fields<double> F = f64(t);
     size_t bytes = (size_t)t->n * 512 * sizeof(double);
-    int rc;
     double linf;
-    if (!phi_is_zero) {
-        if ((rc = hip_check(hipMemcpyAsync(t->d.old, t->d.phi, bytes, hipMemcpyDeviceToDevice,
-                                           stream_of(t)), "park phi")))
-            return rc;
-        launch_fill(t->d.phi, 512 * t->n, 0.0, stream_of(t));
-        dirty_all(t);
-    }
+    int rc = hip_check(hipMemcpyAsync(F.old, F.phi, bytes, hipMemcpyDeviceToDevice, stream_of(t)),
+                       "park phi");
+    if (rc) return rc;
+    launch_fill<double>(F.phi, 512 * t->n, 0.0, stream_of(t));
+    dirty_all(F);
     if ((rc = norms(t, beff, &linf))) return rc;
-    if (!phi_is_zero) {
-        if ((rc = hip_check(hipMemcpyAsync(t->d.phi, t->d.old, bytes, hipMemcpyDeviceToDevice,
-                                           stream_of(t)), "restore phi")))
-            return rc;
-        dirty_all(t);
+    rc = hip_check(hipMemcpyAsync(F.phi, F.old, bytes, hipMemcpyDeviceToDevice, stream_of(t)),
+                   "restore phi");
+    dirty_all(F);
+    return rc;
+}
+
+// ---- recorded launch sequences
+//  SEQ_FMG:       phi <- 0, norm of the residual of phi = 0 into result[2..3],
+//                 FMG pass, restriction pass, leaf norms into result[0..1].
+//  SEQ_VCHECK:    V-cycle with the finest level on top, restriction pass, norms.
+//  SEQ_MIX_START: phi <- 0, leaf residual (= residual of phi = 0) in FP64 with
+//                 its FP32 copy as the correction's right-hand side, norms.
+//  SEQ_MIX_FMG / SEQ_MIX_V: e <- 0, FP32 FMG pass (first refinement step) or
+//                 one FP32 V-cycle on A e = r with homogeneous boundary data,
+//                 phi += e in FP64, restriction pass, FP64 residual, norms.
+void run_body(mg_tree *t, int seq, int nd, int nu) {
+    Fields<double> F = f64(t);
+    Fields<float> E = f32(t);
+    switch (seq) {
+    case mg_tree::SEQ_FMG:
+        launch_fill<double>(F.phi, 512 * t->n, 0.0, stream_of(t));
+        dirty_all(F);
+        norms_launch(t, 2, nullptr);
+        fmg_pass(t, F, nd, nu);
+        restrict_all(t, F);
+        norms_launch(t, 0, nullptr);
+        break;
+    case mg_tree::SEQ_VCHECK:
+        vcycle(t, F, t->nlev, nd, nu);
+        restrict_all(t, F);
+        norms_launch(t, 0, nullptr);
+        break;
+    case mg_tree::SEQ_MIX_START:
+        launch_fill<double>(F.phi, 512 * t->n, 0.0, stream_of(t));
+        dirty_all(F);
+        norms_launch(t, 0, E.rhs);
+        break;
+    case mg_tree::SEQ_MIX_FMG:
+    case mg_tree::SEQ_MIX_V:
+        launch_fill<float>(E.phi, 512 * t->n, 0.0f, stream_of(t));
+        dirty_all(E);
+        if (seq == mg_tree::SEQ_MIX_FMG) fmg_pass(t, E, nd, nu);
+        else vcycle(t, E, t->nlev, nd, nu);
+        launch_ir_update(F.phi, E.phi, 512 * t->n, stream_of(t));
+        dirty_all(F);
+        restrict_all(t, F);
+        norms_launch(t, 0, E.rhs);
+        break;
     }
+}
+
+void save_state(const mg_tree *t, bool s[2][kMaxLevel + 2]) {
+    std::memcpy(s[0], t->cf_valid, sizeof t->cf_valid);
+    std::memcpy(s[1], t->cf_valid32, sizeof t->cf_valid32);
+}
+void load_state(mg_tree *t, const bool s[2][kMaxLevel + 2]) {
+    std::memcpy(t->cf_valid, s[0], sizeof t->cf_valid);
+    std::memcpy(t->cf_valid32, s[1], sizeof t->cf_valid32);
+}
+bool same_state(const mg_tree *t, const bool s[2][kMaxLevel + 2]) {
+    return !std::memcmp(s[0], t->cf_valid, sizeof t->cf_valid) &&
+           !std::memcmp(s[1], t->cf_valid32, sizeof t->cf_valid32);
+}
+
+void drop_graph(mg_tree::Graph &g) {
+    if (g.exec) (void)hipGraphExecDestroy((hipGraphExec_t)g.exec);
+    g.exec = nullptr;
+}
+
+// Record a sequence into g on the private capture stream (nothing executes);
+// the host-side state is left as it was on entry.
+int record(mg_tree *t, mg_tree::Graph &g, int seq, int nd, int nu) {
+    drop_graph(g);
+    save_state(t, g.pre);
+    hipStream_t cs = (hipStream_t)t->cap_stream;
+    int rc = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "begin capture");
+    if (rc) return rc;
+    t->cur_stream = cs;
+    run_body(t, seq, nd, nu);
+    t->cur_stream = t->stream;
+    save_state(t, g.post);
+    load_state(t, g.pre);
+    hipGraph_t graph = nullptr;
+    if ((rc = hip_check(hipStreamEndCapture(cs, &graph), "end capture"))) return rc;
+    hipGraphExec_t exec = nullptr;
+    rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate graph");
+    (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+    g.exec = (void *)exec;
+    g.nd = nd;
+    g.nu = nu;
     return MG_OK;
 }
 
-int check_and_record(mg_tree *t, double beff, mg_solve_stats *s, int k) {
-    double l2, linf;
-    restrict_all(t);
-    int rc = norms(t, &l2, &linf);
+// Run a sequence (replaying its graph when enabled and the host-side state
+// matches the recorded one), then read back count result values.  Timing
+// probes need events on the bound stream between launches, so the timing
+// mode always launches kernel by kernel.
+int run_seq(mg_tree *t, int seq, const mg_solve_opts *o, int count) {
+    int nd = o->n_down, nu = o->n_up;
+    mg_tree::Graph &g = t->graphs[seq];
+    bool use = o->graphs && !t->timing;
+    // Every sequence but the V-cycle check starts by zeroing the fields it
+    // uses, so c_hat validity on entry is irrelevant to it; reset it so that
+    // one recorded graph serves every entry.  The V-cycle check needs the
+    // FP64 state as it is and never touches the FP32 fields.
+    dirty_all(f32(t));
+    if (seq != mg_tree::SEQ_VCHECK) dirty_all(f64(t));
+    if (use && !(g.exec && g.nd == nd && g.nu == nu && same_state(t, g.pre))) {
+        int rc = record(t, g, seq, nd, nu);
+        if (rc) return rc;
+    }
+    if (!use) {
+        run_body(t, seq, nd, nu);
+        return read_results(t, count);
+    }
+    int rc = hip_check(hipGraphLaunch((hipGraphExec_t)g.exec, (hipStream_t)t->stream), "graph launch");
     if (rc) return rc;
+    load_state(t, g.post);
+    return read_results(t, count);
+}
+
+int record_check(double beff, double l2sq, double linf, mg_solve_stats *s, int k) {
+    double l2 = std::sqrt(l2sq);
     double rel = beff > 0 ? l2 / beff : l2;
     s->rel_res = rel;
     s->l2 = l2;
@@ -200,7 +365,17 @@ int check_and_record(mg_tree *t, double beff, mg_solve_stats *s, int k) {
     return MG_OK;
 }
 
-int iterate(mg_tree *t, double beff, const mg_solve_opts *o, mg_solve_stats *s) {
+int check_and_record(mg_tree *t, double beff, mg_solve_stats *s, int k) {
+    double l2, linf;
+    restrict_all(t, f64(t));
+    int rc = norms(t, &l2, &linf);
+    if (rc) return rc;
+    return record_check(beff, l2 * l2, linf, s, k);
+}
+
+// Cycles until the stopping test holds: seq_of(k) names the sequence of step k.
+template <typename SeqOf>
+int iterate(mg_tree *t, double beff, const mg_solve_opts *o, mg_solve_stats *s, SeqOf seq_of) {
     int stall = 0;
     for (int k = 1; s->rel_res > o->rel_tol; k++) {
         if (k > o->max_cycles) {
@@ -208,10 +383,10 @@ int iterate(mg_tree *t, double beff, const mg_solve_opts *o, mg_solve_stats *s) 
             return MG_ENOCONV;
         }
         double prev = s->rel_res;
-        vcycle(t, t->nlev, o->n_down, o->n_up);
-        s->n_vcycles = k;
-        int rc = check_and_record(t, beff, s, k);
+        int rc = run_seq(t, seq_of(k), o, 2);
         if (rc) return rc;
+        s->n_vcycles = k;
+        if ((rc = record_check(beff, t->host_result[0], t->host_result[1], s, k))) return rc;
         stall = s->rel_res >= prev ? stall + 1 : 0;
         if (stall >= 3) {
             set_error("residual stagnates");
@@ -234,8 +409,8 @@ int require_bound(const mg_tree *t) {
 }
 
 int check_opts(const mg_solve_opts *o) {
-    if (!o || o->precision != MG_FP64 || o->n_down < 0 || o->n_up < 0 || o->max_cycles < 0 ||
-        o->max_cycles > 10000 || !(o->rel_tol >= 0)) {
+    if (!o || (o->precision != MG_FP64 && o->precision != MG_MIXED) || o->n_down < 0 ||
+        o->n_up < 0 || o->max_cycles < 0 || o->max_cycles > 10000 || !(o->rel_tol >= 0)) {
         set_error("invalid solver options");
         return MG_EINVAL;
     }
@@ -262,6 +437,7 @@ void mg_default_opts(mg_solve_opts *o) {
     o->n_up = 2;
     o->max_cycles = 50;
     o->rel_tol = 1e-8;
+    o->graphs = 1;
 }
 
 int mg_tree_create(mg_tree **out, const mg_domain *dom, int64_t n, const int32_t *level,
@@ -290,12 +466,14 @@ int mg_tree_create(mg_tree **out, const mg_domain *dom, int64_t n, const int32_t
 
 int mg_tree_destroy(mg_tree *t) {
     if (!t) return MG_OK;
+    for (auto &g : t->graphs) drop_graph(g);
     if (t->host_result) (void)hipHostFree(t->host_result);
-    for (auto &p : t->ev_pending) {
-        t->ev_pool.push_back(p.first);
-        t->ev_pool.push_back(p.second);
+    for (auto &p : t->probes) {
+        t->ev_pool.push_back(p.e0);
+        t->ev_pool.push_back(p.e1);
     }
     for (void *e : t->ev_pool) (void)hipEventDestroy((hipEvent_t)e);
+    if (t->cap_stream) (void)hipStreamDestroy((hipStream_t)t->cap_stream);
     delete t;
     return MG_OK;
 }
@@ -347,8 +525,16 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
         set_error("workspace too small or not 256-byte aligned");
         return MG_ENOMEM;
     }
+    for (auto &g : t->graphs) drop_graph(g);
     t->ws = ws;
     t->stream = stream;
+    t->cur_stream = stream;
+    if (!t->cap_stream) {
+        hipStream_t cs = nullptr;
+        int rc = hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+        if (rc) return rc;
+        t->cap_stream = (void *)cs;
+    }
     char *base = (char *)ws;
     DevTables &d = t->d;
     d.nbr = (int32_t *)(base + t->off.nbr);
@@ -367,6 +553,10 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.bcval = t->off.bcval >= 0 ? (double *)(base + t->off.bcval) : nullptr;
     d.partial = (double *)(base + t->off.partial);
     d.result = (double *)(base + t->off.result);
+    d.e32 = (float *)(base + t->off.e32);
+    d.r32 = (float *)(base + t->off.r32);
+    d.old32 = (float *)(base + t->off.old32);
+    d.chat32 = (float *)(base + t->off.chat32);
     if (!t->host_result) {
         int rc = hip_check(hipHostMalloc((void **)&t->host_result, 8 * sizeof(double)),
                            "pinned host buffer");
@@ -378,9 +568,9 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
         ijk4[4 * b + 3] = t->lev[b];
     }
     hipStream_t s = stream_of(t);
-    auto up = [&](void *dst, const void *src, size_t bytes) {
-        return bytes ? hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s), "table upload")
-                     : MG_OK;
+    auto up = [&](void *dst, const void *src, size_t n) {
+        return n ? hip_check(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s), "table upload")
+                 : MG_OK;
     };
     int rc = MG_OK;
     rc = rc ? rc : up(d.nbr, t->nbr.data(), t->nbr.size() * 4);
@@ -393,11 +583,15 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     rc = rc ? rc : up(d.slots, t->slots.data(), t->slots.size() * 4);
     rc = rc ? rc : up(d.eig, t->eig, sizeof t->eig);
     if (rc) return rc;
-    launch_fill(d.phi, 512 * t->n, 0.0, s);
-    launch_fill(d.rhs, 512 * t->n, 0.0, s);
-    launch_fill(d.old, 512 * t->n, 0.0, s);
-    if (d.bcval) launch_fill(d.bcval, 6 * 64 * t->n, 0.0, s);
-    dirty_all(t);
+    launch_fill<double>(d.phi, 512 * t->n, 0.0, s);
+    launch_fill<double>(d.rhs, 512 * t->n, 0.0, s);
+    launch_fill<double>(d.old, 512 * t->n, 0.0, s);
+    launch_fill<float>(d.e32, 512 * t->n, 0.0f, s);
+    launch_fill<float>(d.r32, 512 * t->n, 0.0f, s);
+    launch_fill<float>(d.old32, 512 * t->n, 0.0f, s);
+    if (d.bcval) launch_fill<double>(d.bcval, 6 * 64 * t->n, 0.0, s);
+    dirty_all(f64(t));
+    dirty_all(f32(t));
     // the host vectors used as upload sources are freed on return
     return hip_check(hipStreamSynchronize(s), "bind");
 }
@@ -407,9 +601,12 @@ int mg_field_set(mg_tree *t, int which, const double *dev) {
     if (rc) return rc;
     hipStream_t s = stream_of(t);
     switch (which) {
-    case MG_FIELD_PHI: launch_pack(dev, t->d.phi, t->n, s); dirty_all(t); break;
-    case MG_FIELD_RHS: launch_pack(dev, t->d.rhs, t->n, s); break;
-    case MG_FIELD_OLD: launch_pack(dev, t->d.old, t->n, s); break;
+    case MG_FIELD_PHI: launch_pack<double>(dev, t->d.phi, t->n, s); dirty_all(f64(t)); break;
+    case MG_FIELD_RHS: launch_pack<double>(dev, t->d.rhs, t->n, s); break;
+    case MG_FIELD_OLD: launch_pack<double>(dev, t->d.old, t->n, s); break;
+    case MG_FIELD_E32: launch_pack<float>(dev, t->d.e32, t->n, s); dirty_all(f32(t)); break;
+    case MG_FIELD_R32: launch_pack<float>(dev, t->d.r32, t->n, s); break;
+    case MG_FIELD_OLD32: launch_pack<float>(dev, t->d.old32, t->n, s); break;
     case MG_FIELD_BCVAL:
         if (!t->d.bcval) {
             set_error("per-cell boundary data not enabled for this tree");
@@ -427,9 +624,12 @@ int mg_field_get(const mg_tree *t, int which, double *dev) {
     if (rc) return rc;
     hipStream_t s = stream_of(t);
     switch (which) {
-    case MG_FIELD_PHI: launch_unpack(t->d.phi, dev, t->n, s); break;
-    case MG_FIELD_RHS: launch_unpack(t->d.rhs, dev, t->n, s); break;
-    case MG_FIELD_OLD: launch_unpack(t->d.old, dev, t->n, s); break;
+    case MG_FIELD_PHI: launch_unpack<double>(t->d.phi, dev, t->n, s); break;
+    case MG_FIELD_RHS: launch_unpack<double>(t->d.rhs, dev, t->n, s); break;
+    case MG_FIELD_OLD: launch_unpack<double>(t->d.old, dev, t->n, s); break;
+    case MG_FIELD_E32: launch_unpack<float>(t->d.e32, dev, t->n, s); break;
+    case MG_FIELD_R32: launch_unpack<float>(t->d.r32, dev, t->n, s); break;
+    case MG_FIELD_OLD32: launch_unpack<float>(t->d.old32, dev, t->n, s); break;
     default: set_error("unknown field"); return MG_EINVAL;
     }
     return hip_check(hipGetLastError(), "field get");
@@ -443,18 +643,21 @@ int mg_fmg_solve(mg_tree *t, const mg_solve_opts *o, mg_solve_stats *st) {
     mg_solve_stats *s = st ? st : &local;
     std::memset(s, 0, sizeof *s);
     double t0 = now_ms();
-    launch_fill(t->d.phi, 512 * t->n, 0.0, stream_of(t));
-    dirty_all(t);
     double beff;
-    if ((rc = beff_norm(t, true, &beff))) return s->status = rc;
-    for (int l = t->nlev; l >= 2; l--) fas_down(t, l);
-    coarse(t);
-    for (int l = 2; l <= t->nlev; l++) {
-        prolong(t, l);
-        vcycle(t, l, o->n_down, o->n_up);
+    if (o->precision == MG_FP64) {
+        if ((rc = run_seq(t, mg_tree::SEQ_FMG, o, 4))) return s->status = rc;
+        beff = std::sqrt(t->host_result[2]);
+        if ((rc = record_check(beff, t->host_result[0], t->host_result[1], s, 0))) return s->status = rc;
+        rc = iterate(t, beff, o, s, [](int) { return (int)mg_tree::SEQ_VCHECK; });
+    } else {
+        // mixed precision: FP64 residual, FP32 correction cycles, FP64 update
+        if ((rc = run_seq(t, mg_tree::SEQ_MIX_START, o, 2))) return s->status = rc;
+        beff = std::sqrt(t->host_result[0]);
+        if ((rc = record_check(beff, t->host_result[0], t->host_result[1], s, 0))) return s->status = rc;
+        rc = iterate(t, beff, o, s, [](int k) {
+            return (int)(k == 1 ? mg_tree::SEQ_MIX_FMG : mg_tree::SEQ_MIX_V);
+        });
     }
-    if ((rc = check_and_record(t, beff, s, 0))) return s->status = rc;
-    rc = iterate(t, beff, o, s);
     if (!rc) rc = hip_check(hipGetLastError(), "kernel launch");
     s->t_ms = now_ms() - t0;
     return s->status = rc;
@@ -469,15 +672,21 @@ int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *
     std::memset(s, 0, sizeof *s);
     double t0 = now_ms();
     double beff;
-    if ((rc = beff_norm(t, false, &beff))) return s->status = rc;
+    if ((rc = beff_norm(t, &beff))) return s->status = rc;
     if ((rc = check_and_record(t, beff, s, 0))) return s->status = rc;
+    int seq = o->precision == MG_FP64 ? mg_tree::SEQ_VCHECK : mg_tree::SEQ_MIX_V;
+    if (o->precision != MG_FP64) {
+        // the FP32 correction's right-hand side is the FP64 leaf residual
+        norms_launch(t, 0, t->d.r32);
+        if ((rc = read_results(t, 2))) return s->status = rc;
+    }
     if (n_cycles <= 0) {
-        rc = iterate(t, beff, o, s);
+        rc = iterate(t, beff, o, s, [seq](int) { return seq; });
     } else {
         for (int k = 1; k <= n_cycles && !rc; k++) {
-            vcycle(t, t->nlev, o->n_down, o->n_up);
+            if ((rc = run_seq(t, seq, o, 2))) break;
             s->n_vcycles = k;
-            rc = check_and_record(t, beff, s, k);
+            rc = record_check(beff, t->host_result[0], t->host_result[1], s, k);
         }
     }
     if (!rc) rc = hip_check(hipGetLastError(), "kernel launch");
@@ -489,8 +698,8 @@ int mg_residual(mg_tree *t, double *rel, double *l2, double *linf) {
     int rc = require_bound(t);
     if (rc) return rc;
     double beff, a, m;
-    if ((rc = beff_norm(t, false, &beff))) return rc;
-    restrict_all(t);
+    if ((rc = beff_norm(t, &beff))) return rc;
+    restrict_all(t, f64(t));
     if ((rc = norms(t, &a, &m))) return rc;
     if (rel) *rel = beff > 0 ? a / beff : a;
     if (l2) *l2 = a;
@@ -501,25 +710,29 @@ int mg_residual(mg_tree *t, double *rel, double *l2, double *linf) {
 int mg_step(mg_tree *t, int op, int level, int arg) {
     int rc = require_bound(t);
     if (rc) return rc;
+    bool fp32 = (op & MG_OP_F32) != 0;
+    op &= ~MG_OP_F32;
     if (op != MG_OP_COARSE && op != MG_OP_RESTRICT_ALL && (level < 1 || level > t->nlev)) {
         set_error("level out of range");
         return MG_EINVAL;
     }
-    switch (op) {
-    case MG_OP_SMOOTH: smooth(t, level, arg); break;
-    case MG_OP_FAS_DOWN:
-        if (level < 2) { set_error("level out of range"); return MG_EINVAL; }
-        fas_down(t, level);
-        break;
-    case MG_OP_PROLONG:
-        if (level < 2) { set_error("level out of range"); return MG_EINVAL; }
-        prolong(t, level);
-        break;
-    case MG_OP_COARSE: coarse(t); break;
-    case MG_OP_RESTRICT_ALL: restrict_all(t); break;
-    case MG_OP_VCYCLE: vcycle(t, level, arg, arg); break;
-    default: set_error("unknown op"); return MG_EINVAL;
+    if ((op == MG_OP_FAS_DOWN || op == MG_OP_PROLONG) && level < 2) {
+        set_error("level out of range");
+        return MG_EINVAL;
     }
+    auto apply = [&](auto F) {
+        switch (op) {
+        case MG_OP_SMOOTH: smooth(t, F, level, arg); return (int)MG_OK;
+        case MG_OP_FAS_DOWN: fas_down(t, F, level); return (int)MG_OK;
+        case MG_OP_PROLONG: prolong(t, F, level); return (int)MG_OK;
+        case MG_OP_COARSE: coarse(t, F); return (int)MG_OK;
+        case MG_OP_RESTRICT_ALL: restrict_all(t, F); return (int)MG_OK;
+        case MG_OP_VCYCLE: vcycle(t, F, level, arg, arg); return (int)MG_OK;
+        default: set_error("unknown op"); return (int)MG_EINVAL;
+        }
+    };
+    rc = fp32 ? apply(f32(t)) : apply(f64(t));
+    if (rc) return rc;
     return hip_check(hipGetLastError(), "kernel launch");
 }
 
@@ -535,23 +748,26 @@ int mg_timing_enable(mg_tree *t, int enable) {
 int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out) {
     int rc = require_bound(t);
     if (rc) return rc;
-    if ((rc = hip_check(hipStreamSynchronize(stream_of(t)), "stream synchronize"))) return rc;
-    double ms = 0.0;
-    for (auto &p : t->ev_pending) {
+    if ((rc = hip_check(hipStreamSynchronize((hipStream_t)t->stream), "stream synchronize"))) return rc;
+    mg_kernel_timing_t acc;
+    std::memset(&acc, 0, sizeof acc);
+    for (auto &p : t->probes) {
         float e = 0.0f;
-        rc = hip_check(hipEventElapsedTime(&e, (hipEvent_t)p.first, (hipEvent_t)p.second), "event time");
-        if (rc) return rc;
-        ms += e;
-        t->ev_pool.push_back(p.first);
-        t->ev_pool.push_back(p.second);
+        if ((rc = hip_check(hipEventElapsedTime(&e, (hipEvent_t)p.e0, (hipEvent_t)p.e1), "probe time")))
+            return rc;
+        acc.launches += p.launches;
+        acc.total_ms += e;
+        acc.alg_bytes += p.bytes;
+        if (p.level >= 1 && p.level <= 16) {
+            acc.level_launches[p.level - 1] += p.launches;
+            acc.level_ms[p.level - 1] += e;
+            acc.level_bytes[p.level - 1] += p.bytes;
+        }
+        give_event(t, (hipEvent_t)p.e0);
+        give_event(t, (hipEvent_t)p.e1);
     }
-    if (out) {
-        out->launches = (int64_t)t->ev_pending.size();
-        out->total_ms = ms;
-        out->alg_bytes = t->ev_bytes;
-    }
-    t->ev_pending.clear();
-    t->ev_bytes = 0.0;
+    t->probes.clear();
+    if (out) *out = acc;
     return MG_OK;
 }
 

@@ -1,5 +1,5 @@
 // Internal state of an mg_tree: host tables built by tree.cpp, device views
-// carved out of the caller's workspace by solver.hip.
+// carved out of the caller's workspace by mg_api.hip.
 #pragma once
 #include <cstdint>
 #include <string>
@@ -33,6 +33,11 @@ struct DevTables {
     double *bcval = nullptr;     // [n][6][64] or null
     double *partial = nullptr;   // [n_leaf][2] per-box residual sums
     double *result = nullptr;    // [8] reduced norms
+    // FP32 correction fields of the mixed-precision solve (same layouts)
+    float *e32 = nullptr;        // correction
+    float *r32 = nullptr;        // its right-hand side (FP64 residual rounded, FAS data)
+    float *old32 = nullptr;
+    float *chat32 = nullptr;
 };
 
 }  // namespace mg
@@ -52,18 +57,31 @@ struct mg_tree {
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
     struct { int64_t nbr, cfslot, cfq, ijk, parent, refined, leaf, slots, eig, phi, rhs, old,
-             chat, bcval, partial, result, total; } off{};
+             chat, bcval, partial, result, e32, r32, old32, chat32, total; } off{};
     // ---- bound device state ----
     void *ws = nullptr;
-    void *stream = nullptr;
+    void *stream = nullptr;      // caller's stream: every replay and direct launch goes here
+    void *cur_stream = nullptr;  // stream the launchers use (the capture stream while capturing)
+    void *cap_stream = nullptr;  // private stream used only to record graphs
     mg::DevTables d;
-    bool cf_valid[mg::kMaxLevel + 2] = {false};
+    bool cf_valid[mg::kMaxLevel + 2] = {false};    // c_hat of the FP64 field current per level
+    bool cf_valid32[mg::kMaxLevel + 2] = {false};  // same for the FP32 correction field
     double *host_result = nullptr;  // pinned host buffer for norms
     // ---- optional event timing of the half-sweep kernel ----
+    // A probe is a pair of events around the consecutive half-sweeps of one
+    // smoothing call, with its level, launch count and algorithmic bytes.
+    struct Probe { void *e0, *e1; int level; int64_t launches; double bytes; };
     bool timing = false;
-    std::vector<void *> ev_pool;                        // hipEvent_t, reused
-    std::vector<std::pair<void *, void *>> ev_pending;  // (start, end) per launch
-    double ev_bytes = 0.0;
+    std::vector<void *> ev_pool;       // hipEvent_t, reused
+    std::vector<Probe> probes;         // probes since the last mg_timing_read
+    // ---- recorded graphs (hipGraphExec_t), one per launch sequence ----
+    struct Graph {
+        void *exec = nullptr;
+        int nd = -1, nu = -1;
+        bool pre[2][mg::kMaxLevel + 2], post[2][mg::kMaxLevel + 2];  // c_hat validity
+    };
+    enum { SEQ_FMG = 0, SEQ_VCHECK, SEQ_MIX_START, SEQ_MIX_FMG, SEQ_MIX_V, SEQ_COUNT };
+    Graph graphs[SEQ_COUNT];
 };
 
 namespace mg {

@@ -268,6 +268,10 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.bcval = dom->per_cell_bc ? take(8 * 6 * 64 * n) : -1;
     t->off.partial = take(16 * t->nleaf);
     t->off.result = take(8 * 8);
+    t->off.e32 = take(4 * kCells * n);
+    t->off.r32 = take(4 * kCells * n);
+    t->off.old32 = take(4 * kCells * n);
+    t->off.chat32 = take(4 * 64 * t->nslot);
     t->off.total = o;
     return MG_OK;
 }

@@ -19,10 +19,12 @@ CODES = {0: "OK", -1: "EINVAL", -2: "ENESTING", -3: "ENOMEM", -4: "EHIP", -5: "E
 MG_DIRICHLET, MG_NEUMANN = 0, 1
 MG_IDX_ORDER, MG_IDX_LEVEL, MG_IDX_IJK, MG_IDX_TREE, MG_IDX_PARENT, MG_IDX_CHILD, MG_IDX_NBR, \
     MG_IDX_CFQ = range(8)
-MG_FIELD_PHI, MG_FIELD_RHS, MG_FIELD_OLD, MG_FIELD_BCVAL = range(4)
-MG_FP64 = 0
+MG_FIELD_PHI, MG_FIELD_RHS, MG_FIELD_OLD, MG_FIELD_BCVAL, MG_FIELD_E32, MG_FIELD_R32, \
+    MG_FIELD_OLD32 = range(7)
+MG_FP64, MG_MIXED = 0, 1
 MG_OP_SMOOTH, MG_OP_FAS_DOWN, MG_OP_PROLONG, MG_OP_COARSE, MG_OP_RESTRICT_ALL, MG_OP_VCYCLE = \
     range(1, 7)
+MG_OP_F32 = 0x100
 _WIDTH = {MG_IDX_ORDER: 1, MG_IDX_LEVEL: 1, MG_IDX_IJK: 3, MG_IDX_TREE: 1, MG_IDX_PARENT: 1,
           MG_IDX_CHILD: 8, MG_IDX_NBR: 6, MG_IDX_CFQ: 6}
 
@@ -47,7 +49,7 @@ class mg_tree_info_t(ctypes.Structure):
 class mg_solve_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("n_down", ctypes.c_int32),
                 ("n_up", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
-                ("rel_tol", ctypes.c_double)]
+                ("rel_tol", ctypes.c_double), ("graphs", ctypes.c_int32)]
 
 
 class mg_solve_stats(ctypes.Structure):
@@ -65,7 +67,8 @@ class mg_solve_stats(ctypes.Structure):
 
 class mg_kernel_timing_t(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
-                ("alg_bytes", ctypes.c_double)]
+                ("alg_bytes", ctypes.c_double), ("level_launches", ctypes.c_int64 * 16),
+                ("level_ms", ctypes.c_double * 16), ("level_bytes", ctypes.c_double * 16)]
 
 
 _lib = None
@@ -200,7 +203,9 @@ def mg_timing_enable(h, enable):
 def mg_timing_read(h):
     out = mg_kernel_timing_t()
     check(lib().mg_timing_read(h, ctypes.byref(out)))
-    return dict(launches=out.launches, total_ms=out.total_ms, alg_bytes=out.alg_bytes)
+    return dict(launches=out.launches, total_ms=out.total_ms, alg_bytes=out.alg_bytes,
+                level_launches=list(out.level_launches), level_ms=list(out.level_ms),
+                level_bytes=list(out.level_bytes))
 
 
 # --------------------------------------------------------- convenience

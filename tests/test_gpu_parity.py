@@ -193,3 +193,120 @@ def test_errors_are_reported():
     assert st.status == M.MG_ENOCONV
     with pytest.raises(M.MGError):
         g.step(M.MG_OP_SMOOTH, 99, 1)
+
+
+def test_graph_replay_matches_direct_launches():
+    """Recorded-graph replay and kernel-by-kernel launches run the same
+    kernels in the same order: identical bits."""
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    a = g.fmg_solve(graphs=0)
+    pa = g.get_field(M.MG_FIELD_PHI)
+    b = g.fmg_solve(graphs=1)
+    pb = g.get_field(M.MG_FIELD_PHI)
+    c = g.fmg_solve(graphs=1)  # replay of the recorded graphs
+    pc = g.get_field(M.MG_FIELD_PHI)
+    assert a["n_vcycles"] == b["n_vcycles"] == c["n_vcycles"]
+    assert np.array_equal(pa, pb) and np.array_equal(pb, pc)
+    np.testing.assert_array_equal(a["hist"], c["hist"])
+
+
+def test_kernel_timing_probes():
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    for graphs in (0, 1):
+        M.mg_timing_read(g.h)
+        M.mg_timing_enable(g.h, True)
+        st = g.fmg_solve(graphs=graphs)
+        M.mg_timing_enable(g.h, False)
+        kt = M.mg_timing_read(g.h)
+        say("timing", graphs, kt, st["n_vcycles"])
+        assert kt["launches"] > 0 and kt["total_ms"] > 0
+        # every half-sweep launch covers whole levels: bytes = 6144 per box
+        assert kt["alg_bytes"] % 6144.0 == 0
+
+
+# ------------------------------------------------------------- mixed precision
+
+F32_STEP_TOL = 2e-5
+
+
+def homog_pair(w):
+    """GPU tree (whose FP32 fields carry the homogeneous correction problem)
+    and an oracle tree with the same boundary types and zero boundary data."""
+    g = M.Tree.from_workload(w)
+    o = O.OracleTree(w.boxes.level, w.boxes.ijk, w.boxes.tree, w.lo, w.length, w.bc_type,
+                     (0.0,) * 6)
+    return g, o
+
+
+@pytest.mark.parametrize("step", STEPS, ids=[s[0] for s in STEPS])
+def test_fp32_step_parity(step):
+    """Every cycle step on the FP32 correction fields agrees with the FP64
+    oracle (homogeneous boundary data) to FP32 rounding."""
+    name, gop, oop, lev, arg = step
+    w = streamer_small()
+    g, o = homog_pair(w)
+    level = {"top": o.nlev, "mid": o.nlev - 1}.get(lev, lev)
+    say("fp32 step", name, "level", level)
+    rng = np.random.default_rng(23)
+    n = g.n
+    fields = [rng.standard_normal((n, 8, 8, 8)), rng.standard_normal((n, 8, 8, 8)) * 100.0]
+    fields.append(fields[0] + 0.1 * rng.standard_normal((n, 8, 8, 8)))
+    fields = [f.astype(np.float32).astype(np.float64) for f in fields]
+    for which_g, which_o, a in zip((M.MG_FIELD_E32, M.MG_FIELD_R32, M.MG_FIELD_OLD32),
+                                   (O.PHI, O.RHS, O.OLD), fields):
+        g.set_field(which_g, a)
+        o.set_field(which_o, a)
+    g.step(gop | M.MG_OP_F32, level, arg)
+    o.step(oop, level, arg)
+    for which_g, which_o, nm in ((M.MG_FIELD_E32, O.PHI, "e"), (M.MG_FIELD_R32, O.RHS, "r"),
+                                 (M.MG_FIELD_OLD32, O.OLD, "old")):
+        e = relmax(g.get_field(which_g), o.get_field(which_o))
+        assert e <= F32_STEP_TOL, (name, nm, e)
+
+
+MIXED_TOL = 1e-8
+
+
+@pytest.mark.parametrize("wname", ["uniform64", "streamer_small", "streamer_full"])
+def test_mixed_solve_accuracy(wname):
+    """FP32 cycles inside FP64 refinement.  At the 1e-8 residual tolerance the
+    potential is as close to the fully converged discrete solution (oracle,
+    1e-12) as the FP64 path's at the same tolerance (both carry an algebraic
+    error of order conditioning x residual, ~1e-7 here); with a tighter
+    tolerance the refinement keeps converging past FP32 rounding and the
+    potential matches the oracle to a relative L2 of 1e-8."""
+    w = {"uniform64": c1, "streamer_small": streamer_small, "streamer_full": c2}[wname]()
+    g, o = pair(w)
+    g.set_rhs_from(w)
+    o.set_rhs_from(w)
+    so = o.fmg_solve(tol=1e-12)
+    leaf = o.leaf_mask()
+    po = o.get_field(O.PHI)
+
+    def err():
+        pg = g.get_field(M.MG_FIELD_PHI)
+        return np.linalg.norm((pg - po)[leaf]) / np.linalg.norm(po[leaf])
+    sd = g.fmg_solve()
+    e64 = err()
+    sm = g.fmg_solve(precision=M.MG_MIXED)
+    emx = err()
+    st = g.fmg_solve(precision=M.MG_MIXED, rel_tol=1e-11)
+    etight = err()
+    say("mixed", wname, "| fp64:", sd["n_vcycles"], "cycles, err", e64, "| mixed 1e-8:",
+        sm["n_vcycles"], "steps, err", emx, "| mixed 1e-11:", st["n_vcycles"], "steps, err", etight)
+    assert sm["rel"] <= 1e-8 and st["rel"] <= 1e-11
+    assert emx <= 2.0 * e64 + 1e-12, (emx, e64)
+    assert etight <= MIXED_TOL, etight
+
+
+def test_mixed_warm_vcycles():
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    g.fmg_solve(precision=M.MG_MIXED, rel_tol=1e-6)
+    st = g.vcycles(0, precision=M.MG_MIXED)
+    assert st["rel"] <= 1e-8 and st["n_vcycles"] >= 1
