@@ -6,9 +6,12 @@ relative residual is below 1e-8, residual checks included (tree creation and
 right-hand-side upload excluded).  value = leaf cells solved per second.
 
 Prints one JSON line with the solve throughput, the dominant kernel's
-roofline (red-black Gauss-Seidel half-sweep, timed with HIP events on the
-library's stream during the timed region) and the oracle's CPU throughput
-on the same workload.
+roofline (red-black Gauss-Seidel half-sweep on the finest level, timed with
+HIP events on the library's stream), the mixed-precision solve on the same
+workload, and the oracle's CPU throughput on the same workload.
+
+--copy-probe BYTES adds one device-to-device copy of that many bytes (a plain
+copy kernel of known size, used to calibrate rocprofv3 traffic counters).
 """
 import argparse
 import hashlib
@@ -25,7 +28,7 @@ HBM_PEAK_GBPS = 8000.0
 BETA_FP64 = 127.0          # bytes per stored cell per V(2,2) visit (per-sweep model)
 NORM_BYTES = 16.0          # bytes per leaf cell per residual check
 METRIC = ("cells/s per FMG solve to rel. residual 1e-8 (FP64 vs mixed vs learned); HBM GB/s")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gsrb_traffic_streamer_L4+4.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gsrb_finest_traffic_streamer_L4+4.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1708_08434_amd", "csrc", "kernels.hip")
 
 
@@ -77,6 +80,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--copy-probe", type=int, default=0, help="bytes of a calibration copy")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
@@ -114,6 +119,26 @@ def main():
     elapsed_probe = time.perf_counter() - t1
     M.mg_timing_enable(g.h, False)
     kt = M.mg_timing_read(g.h)
+    mixed = None
+    if not args.no_mixed:
+        for _ in range(args.warmup):
+            g.fmg_solve(precision=M.MG_MIXED)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            ms_stats = g.fmg_solve(precision=M.MG_MIXED)
+        torch.cuda.synchronize()
+        el_m = time.perf_counter() - t2
+        mixed = {"value": int(g.info.n_leaf_cells) * args.steps / el_m, "unit": "cells/s",
+                 "ms_per_step": 1e3 * el_m / args.steps, "refinement_steps": ms_stats["n_vcycles"],
+                 "final_rel_res": ms_stats["rel"]}
+    if args.copy_probe > 0:
+        src = torch.empty(args.copy_probe // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     n_leaf = int(g.info.n_leaf_cells)
     ls = list(g.info.level_start[:g.nlev + 1])
@@ -122,9 +147,11 @@ def main():
     value = n_leaf * args.steps / elapsed
     k = stats["n_vcycles"]
     mb = model_bytes(counts, n_leaf, k)
-    per_launch_s = kt["total_ms"] / 1e3 / max(kt["launches"], 1)
-    bytes_per_launch = kt["alg_bytes"] / max(kt["launches"], 1)
+    fin = g.nlev - 1
+    per_launch_s = kt["level_ms"][fin] / 1e3 / max(kt["level_launches"][fin], 1)
+    bytes_per_launch = kt["level_bytes"][fin] / max(kt["level_launches"][fin], 1)
     achieved = bytes_per_launch / per_launch_s / 1e9
+    all_us = kt["total_ms"] * 1e3 / max(kt["launches"], 1)
     tr = traffic_per_launch()
     out = {
         "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1,
@@ -135,17 +162,23 @@ def main():
                    "n_leaf": n_leaf, "n_boxes": g.n, "levels": g.nlev, "rel_tol": 1e-8,
                    "vcycles_after_fmg": k, "final_rel_res": stats["rel"], "precision": "fp64",
                    "smoothing": "V(2,2) red-black Gauss-Seidel"},
-        "roofline": {"bound": "hbm", "kernel": "k_gsrb (red-black Gauss-Seidel half-sweep)",
+        "roofline": {"bound": "hbm",
+                     "kernel": f"k_gsrb<C,double> (red-black Gauss-Seidel half-sweep), finest level "
+                               f"({counts[fin]} boxes)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": tr,
-                     "launches": kt["launches"], "avg_launch_us": per_launch_s * 1e6,
+                     "launches": kt["level_launches"][fin], "avg_launch_us": per_launch_s * 1e6,
                      "alg_bytes_per_launch": bytes_per_launch,
+                     "all_levels": {"launches": kt["launches"], "avg_launch_us": all_us,
+                                    "GBps": kt["alg_bytes"] / (kt["total_ms"] / 1e3) / 1e9},
                      "probe_region_ms_per_step": 1e3 * elapsed_probe / args.steps},
         "model": {"bytes_per_solve": mb, "GBps": mb / (ms / 1e3) / 1e9,
                   "roofline_cells_per_s": HBM_PEAK_GBPS * 1e9 * n_leaf / mb,
                   "frac": value / (HBM_PEAK_GBPS * 1e9 * n_leaf / mb)},
     }
+    if mixed is not None:
+        out["mixed"] = mixed
     if rank == 0 and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, k)
     if rank == 0:
