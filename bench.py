@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--copy-probe", type=int, default=0, help="bytes of a calibration copy")
+    ap.add_argument("--workload", default="streamer", choices=["streamer", "forest"],
+                    help="streamer: base 64^3 + 4 levels (default); forest: 128 uneven trees")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
@@ -90,12 +92,16 @@ def main():
 
     import torch
     from paper_1708_08434_amd import mg as M
-    from workloads import c2
+    from workloads import c2, forest
 
-    w = c2()
+    from paper_1708_08434_amd import autotune
+
+    w = c2() if args.workload == "streamer" else forest()
     g = M.Tree.from_workload(w, device="cuda:0")
     g.set_rhs_from(w)
     torch.cuda.synchronize()
+    sched64, _ = autotune.tune(g, M.MG_FP64)
+    sched32, _ = autotune.tune(g, M.MG_MIXED)
     for _ in range(args.warmup):
         g.fmg_solve()
     # timed region 1: the solve as shipped (recorded graphs replayed)
@@ -147,7 +153,9 @@ def main():
     value = n_leaf * args.steps / elapsed
     k = stats["n_vcycles"]
     mb = model_bytes(counts, n_leaf, k)
-    fin = g.nlev - 1
+    # the level whose half-sweeps move the most bytes (the finest level of a
+    # single streamer tree; a middle level of the forest)
+    fin = max(range(g.nlev), key=lambda l: kt["level_bytes"][l])
     per_launch_s = kt["level_ms"][fin] / 1e3 / max(kt["level_launches"][fin], 1)
     bytes_per_launch = kt["level_bytes"][fin] / max(kt["level_launches"][fin], 1)
     achieved = bytes_per_launch / per_launch_s / 1e9
@@ -158,13 +166,17 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name + " static streamer octree (base 64^3 + 4 refinement levels)",
+        "config": {"workload": w.name + (" static streamer octree (base 64^3 + 4 refinement levels)"
+                                          if args.workload == "streamer" else
+                                          " forest of 128 uneven streamer trees (base 32^3 + <=5 levels)"),
+                   "n_trees": int(g.info.n_trees),
                    "n_leaf": n_leaf, "n_boxes": g.n, "levels": g.nlev, "rel_tol": 1e-8,
                    "vcycles_after_fmg": k, "final_rel_res": stats["rel"], "precision": "fp64",
-                   "smoothing": "V(2,2) red-black Gauss-Seidel"},
+                   "smoothing": "V(2,2) red-black Gauss-Seidel",
+                   "gsrb_schedule": {"fp64": sched64, "fp32": sched32}},
         "roofline": {"bound": "hbm",
-                     "kernel": f"k_gsrb<C,double> (red-black Gauss-Seidel half-sweep), finest level "
-                               f"({counts[fin]} boxes)",
+                     "kernel": f"k_gsrb<C,double> (red-black Gauss-Seidel half-sweep), level "
+                               f"{fin + 1} ({counts[fin]} boxes, the most bytes)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": tr,

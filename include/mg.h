@@ -198,6 +198,16 @@ int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *
 int mg_residual(mg_tree *t, double *rel, double *l2, double *linf);
 
 /*
+ * Forests: the trees of one mg_tree are independent problems solved together
+ * (every launch covers the boxes of one level of all trees).  The stopping
+ * test applies to every tree: rel_res is the largest relative residual over
+ * the trees, each relative to its own residual of phi = 0.
+ * mg_tree_residuals writes each tree's relative residual at the last
+ * residual check into rel[n_trees] (host memory).
+ */
+int mg_tree_residuals(const mg_tree *t, double *rel);
+
+/*
  * mg_step - run one step of the cycle (diagnostics and step-by-step
  * comparisons).  op: MG_OP_SMOOTH (level, arg sweeps), MG_OP_FAS_DOWN
  * (residual, restriction, old copy and coarse right-hand side from level to
@@ -234,6 +244,20 @@ typedef struct {
 } mg_kernel_timing_t;
 int mg_timing_enable(mg_tree *t, int enable);
 int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out);
+
+/*
+ * Autotuner of the Gauss-Seidel launch schedule.  For every level it times
+ * reps half-sweeps of each launch variant (1, 2 or 4 cells per thread, with
+ * or without the XCD-aware box mapping) with HIP events on the bound stream
+ * and keeps the fastest; precision selects the FP64 or the FP32 (MG_MIXED)
+ * kernels.  The field being swept is parked and restored, so the solver
+ * state is unchanged.  schedule (host, [n_levels], may be NULL) receives the
+ * chosen variant per level (index level-1); mg_set_schedule applies a stored
+ * schedule (e.g. from a cache keyed by the tree's level sizes).  All variants
+ * compute the same values.
+ */
+int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule);
+int mg_set_schedule(mg_tree *t, int precision, const int32_t *schedule);
 
 const char *mg_last_error(void);
 

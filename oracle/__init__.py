@@ -58,6 +58,7 @@ def lib():
         L.oracle_step.argtypes = [P, I32, I32, I32]
         L.oracle_apply.argtypes = [P, P, P, I32]
         L.oracle_set_threads.argtypes = [I32]
+        L.oracle_tree_rel.argtypes = [P, P]
         L.oracle_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -142,7 +143,7 @@ class OracleTree:
         """Evaluate the workload's right-hand side at this tree's boxes."""
         lv = self.index(IDX_LEVEL)
         ij = self.index(IDX_IJK)
-        self.set_field(RHS, w.rhs(lv, ij))
+        self.set_field(RHS, w.rhs(lv, ij, self.index(IDX_TREE)))
 
     def fmg_solve(self, tol=1e-8, max_cycles=50, n_down=2, n_up=2):
         st = np.zeros(69)
@@ -159,6 +160,11 @@ class OracleTree:
         out = np.zeros(4)
         _check(lib().oracle_residual(self.h, _ptr(out)))
         return dict(rel=out[0], l2=out[1], linf=out[2], beff=out[3])
+
+    def tree_rel(self):
+        out = np.zeros(self.ntree)
+        _check(lib().oracle_tree_rel(self.h, _ptr(out)))
+        return out
 
     def step(self, op, level=0, arg=0):
         _check(lib().oracle_step(self.h, op, level, arg))

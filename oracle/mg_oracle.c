@@ -78,6 +78,8 @@ typedef struct {
     int32_t *hval;
     int64_t hcap;
     double *chol;            /* lower Cholesky factor of the root operator */
+    double *tree_beff;       /* [ntree] norm of the residual of phi = 0 */
+    double *tree_rel;        /* [ntree] relative residual at the last check */
     double chol_h;
     int bad_lookup;          /* set when a required coarse cell is missing */
 } otree;
@@ -152,6 +154,7 @@ void oracle_destroy(otree *t) {
     free(t->bcarr);
     for (int q = 0; q < NFIELD; q++) free(t->f[q]);
     free(t->hkey); free(t->hval); free(t->chol);
+    free(t->tree_beff); free(t->tree_rel);
     free(t);
 }
 
@@ -290,6 +293,9 @@ int oracle_create(otree **out, int64_t n, const int32_t *level, const int32_t *i
         t->f[q] = (double *)calloc((size_t)n * BOX, sizeof(double));
         if (!t->f[q]) { oracle_destroy(t); return ORC_ENOMEM; }
     }
+    t->tree_beff = (double *)calloc((size_t)ntree, sizeof(double));
+    t->tree_rel = (double *)calloc((size_t)ntree, sizeof(double));
+    if (!t->tree_beff || !t->tree_rel) { oracle_destroy(t); return ORC_ENOMEM; }
     *out = t;
     return ORC_OK;
 }
@@ -679,8 +685,9 @@ static void restrict_all(otree *t) {
     for (int l = t->nlev; l >= 2; l--) restrict_field(t, l, t->f[F_PHI]);
 }
 
-/* volume-weighted L2 norm and max norm of the residual over the leaf cells */
-static void leaf_norms(otree *t, double *l2, double *linf) {
+/* volume-weighted L2 norm (squared) and max norm of the residual over the
+   leaf cells of each tree: sq[tree], mx[tree] */
+static void leaf_norms(otree *t, double *sq, double *mx) {
     double *part = (double *)calloc((size_t)t->n, sizeof(double));
     double *pmax = (double *)calloc((size_t)t->n, sizeof(double));
     for (int l = 1; l <= t->nlev; l++) {
@@ -703,46 +710,59 @@ static void leaf_norms(otree *t, double *l2, double *linf) {
             pmax[b] = m;
         }
     }
-    double s = 0.0, m = 0.0;
+    for (int tr = 0; tr < t->ntree; tr++) sq[tr] = mx[tr] = 0.0;
     for (int64_t b = 0; b < t->n; b++) {
-        s += part[b];
-        if (pmax[b] > m || pmax[b] != pmax[b]) m = pmax[b];
+        int tr = t->tid[b];
+        sq[tr] += part[b];
+        if (pmax[b] > mx[tr] || pmax[b] != pmax[b]) mx[tr] = pmax[b];
     }
     free(part); free(pmax);
-    *l2 = sqrt(s);
-    *linf = m;
 }
 
-/* norm of the residual of phi = 0 (the right-hand side with the boundary
-   data folded in) */
-static double beff_norm(otree *t) {
+/* per-tree norm of the residual of phi = 0 (the right-hand side with the
+   boundary data folded in) */
+static void beff_norm(otree *t, double *beff) {
     size_t sz = (size_t)t->n * BOX * sizeof(double);
     double *save = (double *)malloc(sz);
+    double *mx = (double *)malloc((size_t)t->ntree * sizeof(double));
     memcpy(save, t->f[F_PHI], sz);
     memset(t->f[F_PHI], 0, sz);
-    double l2, linf;
-    leaf_norms(t, &l2, &linf);
+    leaf_norms(t, beff, mx);
+    for (int tr = 0; tr < t->ntree; tr++) beff[tr] = sqrt(beff[tr]);
     memcpy(t->f[F_PHI], save, sz);
-    free(save);
-    return l2;
+    free(save); free(mx);
 }
 
 /* stats layout (doubles): 0 rel, 1 l2, 2 linf, 3 beff_l2, 4 n_vcycles,
-   5.. 5+64: relative residual after FMG (index 0) and after each V-cycle */
+   5.. 5+64: relative residual after FMG (index 0) and after each V-cycle.
+   A forest's trees are independent problems: rel is the largest relative
+   residual over the trees (each relative to its own residual of phi = 0);
+   l2, linf and beff_l2 are taken over all trees together. */
 #define ST_HIST 5
 #define ST_N (ST_HIST + 64)
 
-static int check_and_record(otree *t, double beff, double *st, int k) {
-    double l2, linf;
+static int check_and_record(otree *t, const double *beff, double *st, int k) {
+    double *sq = (double *)malloc((size_t)t->ntree * sizeof(double));
+    double *mx = (double *)malloc((size_t)t->ntree * sizeof(double));
     restrict_all(t);
-    leaf_norms(t, &l2, &linf);
-    double rel = beff > 0 ? l2 / beff : l2;
-    st[0] = rel; st[1] = l2; st[2] = linf; st[3] = beff;
+    leaf_norms(t, sq, mx);
+    double rel = 0.0, s = 0.0, m = 0.0, bsq = 0.0;
+    for (int tr = 0; tr < t->ntree; tr++) {
+        double l2 = sqrt(sq[tr]);
+        double r = beff[tr] > 0 ? l2 / beff[tr] : l2;
+        t->tree_rel[tr] = r;
+        if (r > rel || r != r) rel = r;
+        s += sq[tr];
+        bsq += beff[tr] * beff[tr];
+        if (mx[tr] > m || mx[tr] != mx[tr]) m = mx[tr];
+    }
+    free(sq); free(mx);
+    st[0] = rel; st[1] = sqrt(s); st[2] = m; st[3] = sqrt(bsq);
     if (k < 64) st[ST_HIST + k] = rel;
     return isfinite(rel) ? ORC_OK : ORC_ENOCONV;
 }
 
-static int iterate(otree *t, double beff, double tol, int max_cycles, const cycopts *o, double *st) {
+static int iterate(otree *t, const double *beff, double tol, int max_cycles, const cycopts *o, double *st) {
     int stall = 0;
     for (int k = 1; st[0] > tol; k++) {
         if (k > max_cycles) { set_err("no convergence within max_cycles"); return ORC_ENOCONV; }
@@ -762,7 +782,8 @@ int oracle_fmg_solve(otree *t, double tol, int max_cycles, int n_down, int n_up,
     for (int q = 0; q < ST_N; q++) st[q] = 0.0;
     t->bad_lookup = 0;
     memset(t->f[F_PHI], 0, (size_t)t->n * BOX * sizeof(double));
-    double beff = beff_norm(t);
+    beff_norm(t, t->tree_beff);
+    const double *beff = t->tree_beff;
     for (int l = t->nlev; l >= 2; l--) fas_down(t, l);
     int rc = coarse_solve(t);
     if (rc) return rc;
@@ -779,7 +800,8 @@ int oracle_vcycles(otree *t, int ncyc, double tol, int n_down, int n_up, double 
     cycopts o = {n_down, n_up};
     for (int q = 0; q < ST_N; q++) st[q] = 0.0;
     t->bad_lookup = 0;
-    double beff = beff_norm(t);
+    beff_norm(t, t->tree_beff);
+    const double *beff = t->tree_beff;
     int rc = check_and_record(t, beff, st, 0);
     if (rc) return rc;
     if (ncyc <= 0) return iterate(t, beff, tol, 50, &o, st);
@@ -792,12 +814,17 @@ int oracle_vcycles(otree *t, int ncyc, double tol, int n_down, int n_up, double 
 }
 
 int oracle_residual(otree *t, double *out) {
-    double l2, linf, beff = beff_norm(t);
-    restrict_all(t);
-    leaf_norms(t, &l2, &linf);
-    out[0] = beff > 0 ? l2 / beff : l2;
-    out[1] = l2; out[2] = linf; out[3] = beff;
+    double st[ST_N];
+    beff_norm(t, t->tree_beff);
+    check_and_record(t, t->tree_beff, st, 0);
+    for (int q = 0; q < 4; q++) out[q] = st[q];
     return t->bad_lookup ? ORC_ESTATE : ORC_OK;
+}
+
+/* relative residual of every tree at the last residual check */
+int oracle_tree_rel(const otree *t, double *out) {
+    memcpy(out, t->tree_rel, (size_t)t->ntree * sizeof(double));
+    return ORC_OK;
 }
 
 /* single steps of the cycle, for step-by-step comparisons:

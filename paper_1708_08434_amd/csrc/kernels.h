@@ -24,9 +24,14 @@ struct Geo {
 template <typename T> void launch_fill(T *p, int64_t count, T v, hipStream_t s);
 template <typename T> void launch_pack(const double *nat, T *cs, int64_t nbox, hipStream_t s);
 template <typename T> void launch_unpack(const T *cs, double *nat, int64_t nbox, hipStream_t s);
+// Gauss-Seidel launch variants: variant = 2 * c + x, with c = 0, 1, 2 for 1,
+// 2 or 4 cells per thread (256, 128 or 64 threads per box) and x = 1 for the
+// XCD-aware box mapping.  All variants do the same arithmetic on every cell.
+constexpr int kGsrbVariants = 6;
+constexpr int kGsrbDefault = 3;  // 2 cells per thread, XCD mapping
 template <typename T>
 void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
-                 int colour, hipStream_t s);
+                 int colour, int variant, hipStream_t s);
 template <typename T>
 void launch_cf_coarse(const Geo &g, const T *phi, T *chat, const int32_t *slots, int64_t s0,
                       int64_t ns, hipStream_t s);
@@ -49,6 +54,7 @@ void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const
                        const int32_t *leaf, int64_t nleaf, double *partial, float *r_out,
                        hipStream_t s);
 void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s);
-void launch_reduce(const double *partial, int64_t n, double *result, hipStream_t s);
+void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const int32_t *off,
+                         int ntree, double *result, hipStream_t s);
 
 }  // namespace mg

@@ -135,10 +135,13 @@ __global__ __launch_bounds__(256) void k_unpack(const T *__restrict__ cs, double
     nat[q] = (double)cs[b * 512 + cs_idx(i, j, k)];
 }
 
-// One colour C of red-black Gauss-Seidel on boxes [b0, b0+nbx): 128 threads
-// per box, two neighbouring cells of colour C each (16-byte loads, so every
-// wave keeps twice the bytes in flight).  LDS holds the other colour S[256]
-// and the 6 x 32 ghosts of this colour's face cells, H[d*32 + v*4 + (u>>1)].
+// One colour C of red-black Gauss-Seidel on boxes [b0, b0+nbx): 256/CPT
+// threads per box, CPT neighbouring cells of colour C each (vector loads of
+// CPT values, so a wave keeps CPT times the bytes in flight).  LDS holds the
+// other colour S[256] and the 6 x 32 ghosts of this colour's face cells,
+// H[d*32 + v*4 + (u>>1)].  XCD-aware box mapping when xcd != 0.  CPT and the
+// mapping are the launch variants the autotuner chooses from; every variant
+// performs the same arithmetic on every cell.
 template <typename T>
 __device__ __forceinline__ void gsrb_ghost(const Geo &g, const T *__restrict__ phi,
                                            const T *__restrict__ chat, int64_t b, int C, int e, T *H) {
@@ -149,32 +152,38 @@ __device__ __forceinline__ void gsrb_ghost(const Geo &g, const T *__restrict__ p
     H[e] = ghost_at<T>(g, phi, chat, b, d, nb, slot, u, v);
 }
 
-template <typename T> struct Vec2;
-template <> struct Vec2<double> { using type = double2; };
-template <> struct Vec2<float> { using type = float2; };
+template <typename T, int N> struct VecN;
+template <> struct VecN<double, 1> { using type = double; };
+template <> struct VecN<double, 2> { using type = double2; };
+template <> struct VecN<double, 4> { using type = double4; };
+template <> struct VecN<float, 1> { using type = float; };
+template <> struct VecN<float, 2> { using type = float2; };
+template <> struct VecN<float, 4> { using type = float4; };
 
-template <int C, typename T>
-__global__ __launch_bounds__(128) void k_gsrb(Geo g, T *__restrict__ phi, const T *__restrict__ rhs,
-                                              const T *__restrict__ chat, int64_t b0, int64_t nbx,
-                                              T h2) {
-    using V2 = typename Vec2<T>::type;
+template <int C, typename T, int CPT>
+__global__ __launch_bounds__(256 / CPT) void k_gsrb(Geo g, T *__restrict__ phi,
+                                                    const T *__restrict__ rhs,
+                                                    const T *__restrict__ chat, int64_t b0,
+                                                    int64_t nbx, T h2, int xcd) {
+    using V = typename VecN<T, CPT>::type;
+    constexpr int NT = 256 / CPT;
     __shared__ T S[256], H[192];
-    int64_t lb = xcd_map(blockIdx.x, nbx);
+    int64_t lb = xcd ? xcd_map(blockIdx.x, nbx) : (int64_t)blockIdx.x;
     if (lb >= nbx) return;
     int64_t b = b0 + lb;
     int t = threadIdx.x;
-    const V2 *opp = reinterpret_cast<const V2 *>(phi + b * 512 + (1 - C) * 256);
-    const V2 *rb = reinterpret_cast<const V2 *>(rhs + b * 512 + C * 256);
-    V2 o2 = opp[t];
-    V2 b2 = rb[t];
-    gsrb_ghost<T>(g, phi, chat, b, C, t, H);
-    if (t < 64) gsrb_ghost<T>(g, phi, chat, b, C, 128 + t, H);
-    reinterpret_cast<V2 *>(S)[t] = o2;
-    __syncthreads();
-    T out[2];
+    V o = reinterpret_cast<const V *>(phi + b * 512 + (1 - C) * 256)[t];
+    V bv = reinterpret_cast<const V *>(rhs + b * 512 + C * 256)[t];
 #pragma unroll
-    for (int w = 0; w < 2; w++) {
-        int cq = 2 * t + w;
+    for (int e = t; e < 192; e += NT) gsrb_ghost<T>(g, phi, chat, b, C, e, H);
+    reinterpret_cast<V *>(S)[t] = o;
+    __syncthreads();
+    const T *bb = reinterpret_cast<const T *>(&bv);
+    V res;
+    T *out = reinterpret_cast<T *>(&res);
+#pragma unroll
+    for (int w = 0; w < CPT; w++) {
+        int cq = CPT * t + w;
         int m = cq & 3, j = (cq >> 2) & 7, k = cq >> 5;
         int i = 2 * m + ((j + k + C) & 1);
         int row = (k * 8 + j) * 4;
@@ -185,12 +194,9 @@ __global__ __launch_bounds__(128) void k_gsrb(Geo g, T *__restrict__ phi, const 
         T zm = k > 0 ? S[row - 32 + m] : H[4 * 32 + j * 4 + m];
         T zp = k < 7 ? S[row + 32 + m] : H[5 * 32 + j * 4 + m];
         T s = xm + xp + ym + yp + zm + zp;
-        out[w] = (s - h2 * (w ? b2.y : b2.x)) * (T)kSixth;
+        out[w] = (s - h2 * bb[w]) * (T)kSixth;
     }
-    V2 res;
-    res.x = out[0];
-    res.y = out[1];
-    reinterpret_cast<V2 *>(phi + b * 512 + C * 256)[t] = res;
+    reinterpret_cast<V *>(phi + b * 512 + C * 256)[t] = res;
 }
 
 // Coarse value of cell D = C + dir * e_ax (level l-1, relative to box Q),
@@ -531,20 +537,25 @@ __global__ __launch_bounds__(256) void k_ir_update(double *__restrict__ phi, con
     if (q < count) phi[q] += (double)e[q];
 }
 
-// Deterministic reduction of the per-box partials (fixed order, one block).
-__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partial, int64_t n,
-                                                 double *__restrict__ result) {
-    __shared__ double S[1024], M[1024];
-    int t = threadIdx.x;
+// Per-tree reduction of the per-box partials in a fixed order: block t sums
+// the partials of tree t's leaf boxes (positions leaf_tree[off[t] ..
+// off[t+1])) into result[2t] (sum) and result[2t+1] (max).
+__global__ __launch_bounds__(256) void k_reduce_trees(const double *__restrict__ partial,
+                                                      const int32_t *__restrict__ leaf_tree,
+                                                      const int32_t *__restrict__ off,
+                                                      double *__restrict__ result) {
+    __shared__ double S[256], M[256];
+    int tr = blockIdx.x, t = threadIdx.x;
     double s = 0.0, m = 0.0;
-    for (int64_t q = t; q < n; q += 1024) {
-        s += partial[2 * q];
-        m = nanmax(partial[2 * q + 1], m);
+    for (int q = off[tr] + t; q < off[tr + 1]; q += 256) {
+        int64_t p = leaf_tree[q];
+        s += partial[2 * p];
+        m = nanmax(partial[2 * p + 1], m);
     }
     S[t] = s;
     M[t] = m;
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
+    for (int w = 128; w > 0; w >>= 1) {
         if (t < w) {
             S[t] += S[t + w];
             M[t] = nanmax(M[t + w], M[t]);
@@ -552,8 +563,8 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ part
         __syncthreads();
     }
     if (t == 0) {
-        result[0] = S[0];
-        result[1] = M[0];
+        result[2 * tr] = S[0];
+        result[2 * tr + 1] = M[0];
     }
 }
 
@@ -574,13 +585,26 @@ template <typename T>
 void launch_unpack(const T *cs, double *nat, int64_t nbox, hipStream_t s) {
     hipLaunchKernelGGL(k_unpack<T>, dim3((unsigned)(nbox * 2)), dim3(256), 0, s, cs, nat, nbox);
 }
+template <typename T, int CPT>
+void launch_gsrb_cpt(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb,
+                     T h2, int colour, int xcd, hipStream_t s) {
+    dim3 grid((unsigned)(xcd ? xcd_grid(nb) : nb)), block(256 / CPT);
+    if (colour == 0)
+        hipLaunchKernelGGL((k_gsrb<0, T, CPT>), grid, block, 0, s, g, phi, rhs, chat, b0, nb, h2, xcd);
+    else
+        hipLaunchKernelGGL((k_gsrb<1, T, CPT>), grid, block, 0, s, g, phi, rhs, chat, b0, nb, h2, xcd);
+}
+
 template <typename T>
 void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
-                 int colour, hipStream_t s) {
+                 int colour, int variant, hipStream_t s) {
     if (nb <= 0) return;
-    dim3 grid((unsigned)xcd_grid(nb));
-    if (colour == 0) hipLaunchKernelGGL((k_gsrb<0, T>), grid, dim3(128), 0, s, g, phi, rhs, chat, b0, nb, h2);
-    else hipLaunchKernelGGL((k_gsrb<1, T>), grid, dim3(128), 0, s, g, phi, rhs, chat, b0, nb, h2);
+    int xcd = variant & 1;
+    switch (variant >> 1) {
+    case 0: launch_gsrb_cpt<T, 1>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s); break;
+    case 2: launch_gsrb_cpt<T, 4>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s); break;
+    default: launch_gsrb_cpt<T, 2>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s); break;
+    }
 }
 template <typename T>
 void launch_cf_coarse(const Geo &g, const T *phi, T *chat, const int32_t *slots, int64_t s0,
@@ -633,8 +657,10 @@ void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s)
     if (count <= 0) return;
     hipLaunchKernelGGL(k_ir_update, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, phi, e, count);
 }
-void launch_reduce(const double *partial, int64_t n, double *result, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partial, n, result);
+void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const int32_t *off,
+                         int ntree, double *result, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_trees, dim3((unsigned)ntree), dim3(256), 0, s, partial, leaf_tree, off,
+                       result);
 }
 
 #define MG_INSTANTIATE(T)                                                                        \
@@ -642,7 +668,7 @@ void launch_reduce(const double *partial, int64_t n, double *result, hipStream_t
     template void launch_pack<T>(const double *, T *, int64_t, hipStream_t);                     \
     template void launch_unpack<T>(const T *, double *, int64_t, hipStream_t);                   \
     template void launch_gsrb<T>(const Geo &, T *, const T *, const T *, int64_t, int64_t, T, int, \
-                                 hipStream_t);                                                   \
+                                 int, hipStream_t);                                              \
     template void launch_cf_coarse<T>(const Geo &, const T *, T *, const int32_t *, int64_t,     \
                                       int64_t, hipStream_t);                                     \
     template void launch_resid_restrict<T>(const Geo &, T *, T *, T *, const T *, int64_t,       \

@@ -115,9 +115,11 @@ template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsw
             e0 = e1 = nullptr;
         }
     }
+    int variant = t->sched[sizeof(T) == 4 ? 1 : 0][l];
     for (int it = 0; it < nsweep; it++)
         for (int c = 0; c < 2; c++)
-            launch_gsrb<T>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l), h2, c, stream_of(t));
+            launch_gsrb<T>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l), h2, c, variant,
+                           stream_of(t));
     if (e0) {
         if (hipEventRecord(e1, stream_of(t)) == hipSuccess) {
             t->probes.push_back({(void *)e0, (void *)e1, l, 2 * (int64_t)nsweep,
@@ -189,14 +191,16 @@ template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int 
     }
 }
 
-// Leaf residual norms of the FP64 solution into result[slot], result[slot+1]
-// (sum of r^2 h^3, max |r|); r32 != null also stores the residual in FP32.
+// Per-tree leaf residual norms of the FP64 solution into result[slot + 2t],
+// result[slot + 2t + 1] (sum of r^2 h^3, max |r|); r32 != null also stores
+// the residual in FP32.
 void norms_launch(mg_tree *t, int slot, float *r32) {
     Fields<double> F = f64(t);
     for (int l = 2; l <= t->nlev; l++) ensure_cf(t, F, l);
     launch_leaf_norms(F.g, F.phi, F.rhs, F.chat, t->d.leaf, t->nleaf, t->d.partial, r32,
                       stream_of(t));
-    launch_reduce(t->d.partial, t->nleaf, t->d.result + slot, stream_of(t));
+    launch_reduce_trees(t->d.partial, t->d.leaf_tree, t->d.tree_off, t->ntree, t->d.result + slot,
+                        stream_of(t));
 }
 
 int read_results(mg_tree *t, int count) {
@@ -206,28 +210,24 @@ int read_results(mg_tree *t, int count) {
     return hip_check(hipStreamSynchronize((hipStream_t)t->stream), "stream synchronize");
 }
 
-int norms(mg_tree *t, double *l2, double *linf) {
+int norms(mg_tree *t) {
     norms_launch(t, 0, nullptr);
-    int rc = read_results(t, 2);
-    if (rc) return rc;
-    *l2 = std::sqrt(t->host_result[0]);
-    *linf = t->host_result[1];
-    return MG_OK;
+    return read_results(t, 2 * t->ntree);
 }
 
-// Norm of the residual of phi = 0 (boundary data folded in).  The current
-// phi is parked in the old field, which holds no state between calls (every
-// down-leg rewrites it before the up-leg reads it).
-int beff_norm(mg_tree *t, double *beff) {
+// Per-tree norm of the residual of phi = 0 (boundary data folded in), into
+// t->beff_tree.  The current phi is parked in the old field, which holds no
+// state between calls (every down-leg rewrites it before the up-leg reads it).
+int beff_norm(mg_tree *t) {
     Fields<double> F = f64(t);
     size_t bytes = (size_t)t->n * 512 * sizeof(double);
-    double linf;
     int rc = hip_check(hipMemcpyAsync(F.old, F.phi, bytes, hipMemcpyDeviceToDevice, stream_of(t)),
                        "park phi");
     if (rc) return rc;
     launch_fill<double>(F.phi, 512 * t->n, 0.0, stream_of(t));
     dirty_all(F);
-    if ((rc = norms(t, beff, &linf))) return rc;
+    if ((rc = norms(t))) return rc;
+    for (int tr = 0; tr < t->ntree; tr++) t->beff_tree[tr] = std::sqrt(t->host_result[2 * tr]);
     rc = hip_check(hipMemcpyAsync(F.phi, F.old, bytes, hipMemcpyDeviceToDevice, stream_of(t)),
                    "restore phi");
     dirty_all(F);
@@ -235,8 +235,9 @@ int beff_norm(mg_tree *t, double *beff) {
 }
 
 // ---- recorded launch sequences
-//  SEQ_FMG:       phi <- 0, norm of the residual of phi = 0 into result[2..3],
-//                 FMG pass, restriction pass, leaf norms into result[0..1].
+//  SEQ_FMG:       phi <- 0, per-tree norms of the residual of phi = 0 into
+//                 result[2T..4T), FMG pass, restriction pass, per-tree leaf
+//                 norms into result[0..2T) (T trees).
 //  SEQ_VCHECK:    V-cycle with the finest level on top, restriction pass, norms.
 //  SEQ_MIX_START: phi <- 0, leaf residual (= residual of phi = 0) in FP64 with
 //                 its FP32 copy as the correction's right-hand side, norms.
@@ -250,7 +251,7 @@ void run_body(mg_tree *t, int seq, int nd, int nu) {
     case mg_tree::SEQ_FMG:
         launch_fill<double>(F.phi, 512 * t->n, 0.0, stream_of(t));
         dirty_all(F);
-        norms_launch(t, 2, nullptr);
+        norms_launch(t, 2 * t->ntree, nullptr);
         fmg_pass(t, F, nd, nu);
         restrict_all(t, F);
         norms_launch(t, 0, nullptr);
@@ -350,13 +351,26 @@ int run_seq(mg_tree *t, int seq, const mg_solve_opts *o, int count) {
     return read_results(t, count);
 }
 
-int record_check(double beff, double l2sq, double linf, mg_solve_stats *s, int k) {
-    double l2 = std::sqrt(l2sq);
-    double rel = beff > 0 ? l2 / beff : l2;
+// Turn the per-tree norms in host_result[0..2T) into statistics.  A forest's
+// trees are independent problems: rel is the largest relative residual over
+// the trees, each relative to its own residual of phi = 0; l2, linf and
+// beff_l2 are taken over all trees together.
+int record_check(mg_tree *t, mg_solve_stats *s, int k) {
+    double rel = 0.0, sq = 0.0, mx = 0.0, bsq = 0.0;
+    for (int tr = 0; tr < t->ntree; tr++) {
+        double l2 = std::sqrt(t->host_result[2 * tr]), m = t->host_result[2 * tr + 1];
+        double b = t->beff_tree[tr];
+        double r = b > 0 ? l2 / b : l2;
+        t->rel_tree[tr] = r;
+        if (r > rel || r != r) rel = r;
+        sq += t->host_result[2 * tr];
+        bsq += b * b;
+        if (m > mx || m != m) mx = m;
+    }
     s->rel_res = rel;
-    s->l2 = l2;
-    s->linf = linf;
-    s->beff_l2 = beff;
+    s->l2 = std::sqrt(sq);
+    s->linf = mx;
+    s->beff_l2 = std::sqrt(bsq);
     if (k < 64) s->rel_hist[k] = rel;
     if (!std::isfinite(rel)) {
         set_error("non-finite residual");
@@ -365,17 +379,16 @@ int record_check(double beff, double l2sq, double linf, mg_solve_stats *s, int k
     return MG_OK;
 }
 
-int check_and_record(mg_tree *t, double beff, mg_solve_stats *s, int k) {
-    double l2, linf;
+int check_and_record(mg_tree *t, mg_solve_stats *s, int k) {
     restrict_all(t, f64(t));
-    int rc = norms(t, &l2, &linf);
+    int rc = norms(t);
     if (rc) return rc;
-    return record_check(beff, l2 * l2, linf, s, k);
+    return record_check(t, s, k);
 }
 
 // Cycles until the stopping test holds: seq_of(k) names the sequence of step k.
 template <typename SeqOf>
-int iterate(mg_tree *t, double beff, const mg_solve_opts *o, mg_solve_stats *s, SeqOf seq_of) {
+int iterate(mg_tree *t, const mg_solve_opts *o, mg_solve_stats *s, SeqOf seq_of) {
     int stall = 0;
     for (int k = 1; s->rel_res > o->rel_tol; k++) {
         if (k > o->max_cycles) {
@@ -383,10 +396,10 @@ int iterate(mg_tree *t, double beff, const mg_solve_opts *o, mg_solve_stats *s, 
             return MG_ENOCONV;
         }
         double prev = s->rel_res;
-        int rc = run_seq(t, seq_of(k), o, 2);
+        int rc = run_seq(t, seq_of(k), o, 2 * t->ntree);
         if (rc) return rc;
         s->n_vcycles = k;
-        if ((rc = record_check(beff, t->host_result[0], t->host_result[1], s, k))) return rc;
+        if ((rc = record_check(t, s, k))) return rc;
         stall = s->rel_res >= prev ? stall + 1 : 0;
         if (stall >= 3) {
             set_error("residual stagnates");
@@ -545,6 +558,8 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.refined = (int32_t *)(base + t->off.refined);
     d.leaf = (int32_t *)(base + t->off.leaf);
     d.slots = (int32_t *)(base + t->off.slots);
+    d.leaf_tree = (int32_t *)(base + t->off.leaf_tree);
+    d.tree_off = (int32_t *)(base + t->off.tree_off);
     d.eig = (double *)(base + t->off.eig);
     d.phi = (double *)(base + t->off.phi);
     d.rhs = (double *)(base + t->off.rhs);
@@ -558,7 +573,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.old32 = (float *)(base + t->off.old32);
     d.chat32 = (float *)(base + t->off.chat32);
     if (!t->host_result) {
-        int rc = hip_check(hipHostMalloc((void **)&t->host_result, 8 * sizeof(double)),
+        int rc = hip_check(hipHostMalloc((void **)&t->host_result, 4 * t->ntree * sizeof(double)),
                            "pinned host buffer");
         if (rc) return rc;
     }
@@ -581,6 +596,8 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     rc = rc ? rc : up(d.refined, t->refined.data(), t->refined.size() * 4);
     rc = rc ? rc : up(d.leaf, t->leaf.data(), t->leaf.size() * 4);
     rc = rc ? rc : up(d.slots, t->slots.data(), t->slots.size() * 4);
+    rc = rc ? rc : up(d.leaf_tree, t->leaf_tree.data(), t->leaf_tree.size() * 4);
+    rc = rc ? rc : up(d.tree_off, t->tree_off.data(), t->tree_off.size() * 4);
     rc = rc ? rc : up(d.eig, t->eig, sizeof t->eig);
     if (rc) return rc;
     launch_fill<double>(d.phi, 512 * t->n, 0.0, s);
@@ -643,18 +660,18 @@ int mg_fmg_solve(mg_tree *t, const mg_solve_opts *o, mg_solve_stats *st) {
     mg_solve_stats *s = st ? st : &local;
     std::memset(s, 0, sizeof *s);
     double t0 = now_ms();
-    double beff;
+    int T = t->ntree;
     if (o->precision == MG_FP64) {
-        if ((rc = run_seq(t, mg_tree::SEQ_FMG, o, 4))) return s->status = rc;
-        beff = std::sqrt(t->host_result[2]);
-        if ((rc = record_check(beff, t->host_result[0], t->host_result[1], s, 0))) return s->status = rc;
-        rc = iterate(t, beff, o, s, [](int) { return (int)mg_tree::SEQ_VCHECK; });
+        if ((rc = run_seq(t, mg_tree::SEQ_FMG, o, 4 * T))) return s->status = rc;
+        for (int tr = 0; tr < T; tr++) t->beff_tree[tr] = std::sqrt(t->host_result[2 * T + 2 * tr]);
+        if ((rc = record_check(t, s, 0))) return s->status = rc;
+        rc = iterate(t, o, s, [](int) { return (int)mg_tree::SEQ_VCHECK; });
     } else {
         // mixed precision: FP64 residual, FP32 correction cycles, FP64 update
-        if ((rc = run_seq(t, mg_tree::SEQ_MIX_START, o, 2))) return s->status = rc;
-        beff = std::sqrt(t->host_result[0]);
-        if ((rc = record_check(beff, t->host_result[0], t->host_result[1], s, 0))) return s->status = rc;
-        rc = iterate(t, beff, o, s, [](int k) {
+        if ((rc = run_seq(t, mg_tree::SEQ_MIX_START, o, 2 * T))) return s->status = rc;
+        for (int tr = 0; tr < T; tr++) t->beff_tree[tr] = std::sqrt(t->host_result[2 * tr]);
+        if ((rc = record_check(t, s, 0))) return s->status = rc;
+        rc = iterate(t, o, s, [](int k) {
             return (int)(k == 1 ? mg_tree::SEQ_MIX_FMG : mg_tree::SEQ_MIX_V);
         });
     }
@@ -671,22 +688,21 @@ int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *
     mg_solve_stats *s = st ? st : &local;
     std::memset(s, 0, sizeof *s);
     double t0 = now_ms();
-    double beff;
-    if ((rc = beff_norm(t, &beff))) return s->status = rc;
-    if ((rc = check_and_record(t, beff, s, 0))) return s->status = rc;
+    if ((rc = beff_norm(t))) return s->status = rc;
+    if ((rc = check_and_record(t, s, 0))) return s->status = rc;
     int seq = o->precision == MG_FP64 ? mg_tree::SEQ_VCHECK : mg_tree::SEQ_MIX_V;
     if (o->precision != MG_FP64) {
         // the FP32 correction's right-hand side is the FP64 leaf residual
         norms_launch(t, 0, t->d.r32);
-        if ((rc = read_results(t, 2))) return s->status = rc;
+        if ((rc = read_results(t, 2 * t->ntree))) return s->status = rc;
     }
     if (n_cycles <= 0) {
-        rc = iterate(t, beff, o, s, [seq](int) { return seq; });
+        rc = iterate(t, o, s, [seq](int) { return seq; });
     } else {
         for (int k = 1; k <= n_cycles && !rc; k++) {
-            if ((rc = run_seq(t, seq, o, 2))) break;
+            if ((rc = run_seq(t, seq, o, 2 * t->ntree))) break;
             s->n_vcycles = k;
-            rc = record_check(beff, t->host_result[0], t->host_result[1], s, k);
+            rc = record_check(t, s, k);
         }
     }
     if (!rc) rc = hip_check(hipGetLastError(), "kernel launch");
@@ -697,13 +713,13 @@ int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *
 int mg_residual(mg_tree *t, double *rel, double *l2, double *linf) {
     int rc = require_bound(t);
     if (rc) return rc;
-    double beff, a, m;
-    if ((rc = beff_norm(t, &beff))) return rc;
-    restrict_all(t, f64(t));
-    if ((rc = norms(t, &a, &m))) return rc;
-    if (rel) *rel = beff > 0 ? a / beff : a;
-    if (l2) *l2 = a;
-    if (linf) *linf = m;
+    if ((rc = beff_norm(t))) return rc;
+    mg_solve_stats s;
+    std::memset(&s, 0, sizeof s);
+    if ((rc = check_and_record(t, &s, 0))) return rc;
+    if (rel) *rel = s.rel_res;
+    if (l2) *l2 = s.l2;
+    if (linf) *linf = s.linf;
     return MG_OK;
 }
 
@@ -734,6 +750,93 @@ int mg_step(mg_tree *t, int op, int level, int arg) {
     rc = fp32 ? apply(f32(t)) : apply(f64(t));
     if (rc) return rc;
     return hip_check(hipGetLastError(), "kernel launch");
+}
+
+int mg_tree_residuals(const mg_tree *t, double *rel) {
+    if (!t || !rel) {
+        set_error("null argument");
+        return MG_EINVAL;
+    }
+    std::memcpy(rel, t->rel_tree.data(), t->rel_tree.size() * sizeof(double));
+    return MG_OK;
+}
+
+int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if ((precision != MG_FP64 && precision != MG_MIXED) || reps < 1 || reps > 1000) {
+        set_error("invalid autotune arguments");
+        return MG_EINVAL;
+    }
+    bool fp32 = precision == MG_MIXED;
+    hipStream_t s = (hipStream_t)t->stream;
+    hipEvent_t e0 = take_event(t), e1 = take_event(t);
+    if (!e0 || !e1) {
+        set_error("event creation failed");
+        return MG_EHIP;
+    }
+    // the sweeps change the field: park it in the old field (scratch between
+    // calls) and restore it afterwards
+    size_t bytes = (size_t)t->n * 512 * (fp32 ? sizeof(float) : sizeof(double));
+    void *fld = fp32 ? (void *)t->d.e32 : (void *)t->d.phi;
+    void *park = fp32 ? (void *)t->d.old32 : (void *)t->d.old;
+    rc = hip_check(hipMemcpyAsync(park, fld, bytes, hipMemcpyDeviceToDevice, s), "park field");
+    for (int l = 1; l <= t->nlev && !rc; l++) {
+        double h = hlev(t, l), best = 1e30;
+        int pick = kGsrbDefault;
+        for (int v = 0; v < kGsrbVariants && !rc; v++) {
+            auto sweeps = [&]() {
+                for (int q = 0; q < reps; q++) {
+                    if (fp32) {
+                        Fields<float> F = f32(t);
+                        launch_gsrb<float>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l),
+                                           (float)(h * h), q & 1, v, s);
+                    } else {
+                        Fields<double> F = f64(t);
+                        launch_gsrb<double>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l),
+                                            h * h, q & 1, v, s);
+                    }
+                }
+            };
+            sweeps();  // warm-up
+            rc = hip_check(hipEventRecord(e0, s), "event");
+            sweeps();
+            if (!rc) rc = hip_check(hipEventRecord(e1, s), "event");
+            if (!rc) rc = hip_check(hipEventSynchronize(e1), "event sync");
+            float ms = 0.0f;
+            if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+            if (!rc && ms < best) {
+                best = ms;
+                pick = v;
+            }
+        }
+        t->sched[fp32 ? 1 : 0][l] = pick;
+        if (schedule) schedule[l - 1] = pick;
+    }
+    if (!rc) rc = hip_check(hipMemcpyAsync(fld, park, bytes, hipMemcpyDeviceToDevice, s), "restore field");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "stream synchronize");
+    give_event(t, e0);
+    give_event(t, e1);
+    for (auto &g : t->graphs) drop_graph(g);  // re-record with the new schedule
+    dirty_all(f64(t));
+    dirty_all(f32(t));
+    return rc;
+}
+
+int mg_set_schedule(mg_tree *t, int precision, const int32_t *schedule) {
+    if (!t || !schedule || (precision != MG_FP64 && precision != MG_MIXED)) {
+        set_error("invalid schedule arguments");
+        return MG_EINVAL;
+    }
+    for (int l = 1; l <= t->nlev; l++) {
+        if (schedule[l - 1] < 0 || schedule[l - 1] >= kGsrbVariants) {
+            set_error("schedule entry out of range");
+            return MG_EINVAL;
+        }
+    }
+    for (int l = 1; l <= t->nlev; l++) t->sched[precision == MG_MIXED ? 1 : 0][l] = schedule[l - 1];
+    for (auto &g : t->graphs) drop_graph(g);
+    return MG_OK;
 }
 
 int mg_timing_enable(mg_tree *t, int enable) {

@@ -25,6 +25,8 @@ struct DevTables {
     int32_t *refined = nullptr;  // per-level lists of boxes with children
     int32_t *leaf = nullptr;     // per-level lists of boxes without children
     int32_t *slots = nullptr;    // [nslot][2] (box, face)
+    int32_t *leaf_tree = nullptr;  // leaf-list positions grouped by tree (ascending within a tree)
+    int32_t *tree_off = nullptr;   // [ntree+1] offsets into leaf_tree
     double *eig = nullptr;       // root solve: Q_x, Q_y, Q_z (8x8, column = vector), then lambda_x,y,z
     double *phi = nullptr;       // [n][2][256] colour-split
     double *rhs = nullptr;
@@ -32,7 +34,7 @@ struct DevTables {
     double *chat = nullptr;      // [nslot][64] tangentially interpolated coarse values
     double *bcval = nullptr;     // [n][6][64] or null
     double *partial = nullptr;   // [n_leaf][2] per-box residual sums
-    double *result = nullptr;    // [8] reduced norms
+    double *result = nullptr;    // [4*ntree] per-tree (sum r^2 h^3, max |r|), then the same for phi = 0
     // FP32 correction fields of the mixed-precision solve (same layouts)
     float *e32 = nullptr;        // correction
     float *r32 = nullptr;        // its right-hand side (FP64 residual rounded, FAS data)
@@ -51,13 +53,14 @@ struct mg_tree {
     std::vector<int32_t> refined, leaf;                 // box ids grouped by level
     int64_t rstart[mg::kMaxLevel + 2] = {0}, fstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> slots;                         // (box, face) per slot
+    std::vector<int32_t> leaf_tree, tree_off;           // leaf positions grouped by tree
     int64_t sstart[mg::kMaxLevel + 2] = {0};            // slots of level l: [sstart[l], sstart[l+1])
     int64_t nslot = 0, nleaf = 0;
     mg_domain dom{};
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
-    struct { int64_t nbr, cfslot, cfq, ijk, parent, refined, leaf, slots, eig, phi, rhs, old,
-             chat, bcval, partial, result, e32, r32, old32, chat32, total; } off{};
+    struct { int64_t nbr, cfslot, cfq, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, eig,
+             phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, total; } off{};
     // ---- bound device state ----
     void *ws = nullptr;
     void *stream = nullptr;      // caller's stream: every replay and direct launch goes here
@@ -66,7 +69,8 @@ struct mg_tree {
     mg::DevTables d;
     bool cf_valid[mg::kMaxLevel + 2] = {false};    // c_hat of the FP64 field current per level
     bool cf_valid32[mg::kMaxLevel + 2] = {false};  // same for the FP32 correction field
-    double *host_result = nullptr;  // pinned host buffer for norms
+    double *host_result = nullptr;  // pinned host buffer for norms, [4*ntree]
+    std::vector<double> beff_tree, rel_tree;  // per tree: norm of the residual of phi = 0, last rel
     // ---- optional event timing of the half-sweep kernel ----
     // A probe is a pair of events around the consecutive half-sweeps of one
     // smoothing call, with its level, launch count and algorithmic bytes.
@@ -82,6 +86,12 @@ struct mg_tree {
     };
     enum { SEQ_FMG = 0, SEQ_VCHECK, SEQ_MIX_START, SEQ_MIX_FMG, SEQ_MIX_V, SEQ_COUNT };
     Graph graphs[SEQ_COUNT];
+    // Gauss-Seidel launch variant per level, [0] FP64, [1] FP32 (autotuner)
+    int32_t sched[2][mg::kMaxLevel + 2];
+    mg_tree() {
+        for (auto &row : sched)
+            for (auto &v : row) v = 3;
+    }
 };
 
 namespace mg {

@@ -246,6 +246,18 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
             (t->child[8 * b] >= 0 ? t->refined : t->leaf).push_back((int32_t)b);
     }
     t->nleaf = (int64_t)t->leaf.size();
+    // leaf-list positions grouped by tree, ascending inside each tree (the
+    // order of the per-tree norm reduction)
+    t->tree_off.assign(ntree + 1, 0);
+    for (int64_t q = 0; q < t->nleaf; q++) t->tree_off[t->tid[t->leaf[q]] + 1]++;
+    for (int tr = 0; tr < ntree; tr++) t->tree_off[tr + 1] += t->tree_off[tr];
+    t->leaf_tree.assign(t->nleaf, 0);
+    {
+        std::vector<int32_t> fill(t->tree_off.begin(), t->tree_off.end() - 1);
+        for (int64_t q = 0; q < t->nleaf; q++) t->leaf_tree[fill[t->tid[t->leaf[q]]]++] = (int32_t)q;
+    }
+    t->beff_tree.assign(ntree, 0.0);
+    t->rel_tree.assign(ntree, 0.0);
     root_eigen(dom->bc_type, t->eig);
 
     // workspace layout
@@ -260,6 +272,8 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.refined = take(4 * (int64_t)t->refined.size());
     t->off.leaf = take(4 * t->nleaf);
     t->off.slots = take(8 * t->nslot);
+    t->off.leaf_tree = take(4 * t->nleaf);
+    t->off.tree_off = take(4 * (int64_t)(ntree + 1));
     t->off.eig = take(8 * (3 * 64 + 3 * 8));
     t->off.phi = take(8 * kCells * n);
     t->off.rhs = take(8 * kCells * n);
@@ -267,7 +281,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.chat = take(8 * 64 * t->nslot);
     t->off.bcval = dom->per_cell_bc ? take(8 * 6 * 64 * n) : -1;
     t->off.partial = take(16 * t->nleaf);
-    t->off.result = take(8 * 8);
+    t->off.result = take(8 * 4 * (int64_t)ntree);
     t->off.e32 = take(4 * kCells * n);
     t->off.r32 = take(4 * kCells * n);
     t->off.old32 = take(4 * kCells * n);

@@ -30,7 +30,8 @@ _WIDTH = {MG_IDX_ORDER: 1, MG_IDX_LEVEL: 1, MG_IDX_IJK: 3, MG_IDX_TREE: 1, MG_ID
 
 EXPORTS = ["mg_tree_create", "mg_tree_destroy", "mg_tree_info", "mg_tree_bind", "mg_tree_index",
            "mg_field_set", "mg_field_get", "mg_default_opts", "mg_fmg_solve", "mg_vcycle",
-           "mg_residual", "mg_step", "mg_timing_enable", "mg_timing_read", "mg_last_error"]
+           "mg_residual", "mg_tree_residuals", "mg_step", "mg_timing_enable", "mg_timing_read",
+           "mg_autotune", "mg_set_schedule", "mg_last_error"]
 
 
 class mg_domain(ctypes.Structure):
@@ -100,6 +101,9 @@ def lib():
                                 ctypes.POINTER(mg_solve_stats)]
         L.mg_residual.argtypes = [P, P, P, P]
         L.mg_step.argtypes = [P, I32, I32, I32]
+        L.mg_tree_residuals.argtypes = [P, P]
+        L.mg_autotune.argtypes = [P, I32, I32, P]
+        L.mg_set_schedule.argtypes = [P, I32, P]
         L.mg_timing_enable.argtypes = [P, I32]
         L.mg_timing_read.argtypes = [P, ctypes.POINTER(mg_kernel_timing_t)]
         L.mg_last_error.restype = ctypes.c_char_p
@@ -192,8 +196,25 @@ def mg_residual(h):
     return dict(rel=rel.value, l2=l2.value, linf=linf.value)
 
 
+def mg_tree_residuals(h, ntree):
+    out = np.zeros(ntree)
+    check(lib().mg_tree_residuals(h, _p(out)))
+    return out
+
+
 def mg_step(h, op, level=0, arg=0):
     check(lib().mg_step(h, op, level, arg))
+
+
+def mg_autotune(h, precision, reps, n_levels):
+    out = np.zeros(n_levels, dtype=np.int32)
+    check(lib().mg_autotune(h, precision, reps, _p(out)))
+    return out
+
+
+def mg_set_schedule(h, precision, schedule):
+    sch = np.ascontiguousarray(schedule, dtype=np.int32)
+    check(lib().mg_set_schedule(h, precision, _p(sch)))
 
 
 def mg_timing_enable(h, enable):
@@ -287,7 +308,7 @@ class Tree:
 
     def set_rhs_from(self, w):
         lv, ij = self.index(MG_IDX_LEVEL), self.index(MG_IDX_IJK)
-        self.set_field(MG_FIELD_RHS, w.rhs(lv, ij))
+        self.set_field(MG_FIELD_RHS, w.rhs(lv, ij, self.index(MG_IDX_TREE)))
 
     def opts(self, **kw):
         o = mg_default_opts()
@@ -303,6 +324,9 @@ class Tree:
 
     def residual(self):
         return mg_residual(self.h)
+
+    def tree_rel(self):
+        return mg_tree_residuals(self.h, int(self.info.n_trees))
 
     def step(self, op, level=0, arg=0):
         mg_step(self.h, op, level, arg)

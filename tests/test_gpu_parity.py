@@ -310,3 +310,99 @@ def test_mixed_warm_vcycles():
     g.fmg_solve(precision=M.MG_MIXED, rel_tol=1e-6)
     st = g.vcycles(0, precision=M.MG_MIXED)
     assert st["rel"] <= 1e-8 and st["n_vcycles"] >= 1
+
+
+# ------------------------------------------------------------------- forests
+
+def small_forest():
+    from workloads import forest
+    return forest(n_trees=6, refinements=2, base=2, lo_cells=2e4, hi_cells=1.5e5)
+
+
+def test_forest_parity():
+    """A forest of uneven trees solved together (one launch per level over all
+    trees) matches the oracle's forest solve: same refinement-step count, same
+    per-tree relative residuals, potential within 1e-10."""
+    w = small_forest()
+    say("forest", w.boxes.n, "boxes", w.n_leaf, "leaf cells", int(w.boxes.tree.max()) + 1, "trees")
+    for prec in (M.MG_FP64, M.MG_MIXED):
+        g, o, sg, so, err = None, None, None, None, None
+        g, o = pair(w)
+        g.set_rhs_from(w)
+        o.set_rhs_from(w)
+        sg = g.fmg_solve(precision=prec)
+        if prec == M.MG_FP64:
+            so = o.fmg_solve()
+            assert sg["n_vcycles"] == so["n_vcycles"]
+            np.testing.assert_allclose(g.tree_rel(), o.tree_rel(), rtol=1e-5)
+            leaf = o.leaf_mask()
+            pg, po = g.get_field(M.MG_FIELD_PHI), o.get_field(O.PHI)
+            err = np.linalg.norm((pg - po)[leaf]) / np.linalg.norm(po[leaf])
+            assert err <= SOLVE_TOL, err
+        assert sg["rel"] <= 1e-8 and np.all(g.tree_rel() <= 1e-8)
+
+
+def test_forest_trees_match_standalone_solves():
+    """Every tree of the forest solution agrees with that tree solved alone by
+    the oracle to 1e-12, to the accuracy a 1e-8 residual allows."""
+    w = small_forest()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    g.fmg_solve()
+    phi = g.get_field(M.MG_FIELD_PHI)
+    tid, leaf = g.index(M.MG_IDX_TREE), g.leaf_mask()
+    lv, ij = g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK)
+    for t in np.unique(tid):
+        m = tid == t
+        o = O.OracleTree(lv[m], ij[m], None, w.lo, w.length, w.bc_type, w.bc_val)
+        o.set_field(O.RHS, w.rhs(o.index(O.IDX_LEVEL), o.index(O.IDX_IJK),
+                                 np.full(o.n, t)))
+        o.fmg_solve(tol=1e-12)
+        po = o.get_field(O.PHI)
+        # the oracle's canonical order of a single tree equals the forest's
+        # order restricted to that tree (level, then Morton)
+        pg = phi[m]
+        lo = o.leaf_mask()
+        err = np.linalg.norm((pg - po)[lo]) / np.linalg.norm(po[lo])
+        say("tree", t, "boxes", o.n, "err vs standalone", err)
+        assert err <= 1e-6, (t, err)
+
+
+# ----------------------------------------------------------------- autotuner
+
+def test_every_gsrb_variant_gives_the_same_bits():
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    rng = np.random.default_rng(9)
+    phi0 = rng.standard_normal((g.n, 8, 8, 8))
+    g.set_rhs_from(w)
+    ref = None
+    for v in range(6):
+        M.mg_set_schedule(g.h, M.MG_FP64, [v] * g.nlev)
+        g.set_field(M.MG_FIELD_PHI, phi0)
+        g.step(M.MG_OP_VCYCLE, g.nlev, 2)
+        out = g.get_field(M.MG_FIELD_PHI)
+        if ref is None:
+            ref = out
+        assert np.array_equal(out, ref), v
+
+
+def test_autotune_keeps_the_solution(tmp_path, monkeypatch):
+    from paper_1708_08434_amd import autotune
+    monkeypatch.setenv("MG_TUNE_CACHE", str(tmp_path / "tune.json"))
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    s0 = g.fmg_solve()
+    p0 = g.get_field(M.MG_FIELD_PHI)
+    for prec in (M.MG_FP64, M.MG_MIXED):
+        sched, cached = autotune.tune(g, prec, reps=4)
+        assert not cached and len(sched) == g.nlev and all(0 <= v < 6 for v in sched)
+        say("autotuned", prec, sched)
+    # the tuner leaves the solution in place
+    assert np.array_equal(g.get_field(M.MG_FIELD_PHI), p0)
+    s1 = g.fmg_solve()
+    assert s1["n_vcycles"] == s0["n_vcycles"]
+    assert np.array_equal(g.get_field(M.MG_FIELD_PHI), p0)
+    sched2, cached = autotune.tune(g, M.MG_FP64, reps=4)
+    assert cached

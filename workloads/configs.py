@@ -41,10 +41,14 @@ class Workload:
         """b at the cells of the given boxes, shape [n, 8, 8, 8] ([box][k][j][i])."""
         level = np.asarray(level).reshape(-1)
         ijk = np.asarray(ijk).reshape(-1, 3)
+        tree = np.zeros(len(level), dtype=np.int32) if tree is None else np.asarray(tree).reshape(-1)
         out = np.zeros((len(level), 8, 8, 8))
         for l in np.unique(level):
             m = level == l
-            out[m] = self._rhs_fn(int(l), ijk[m])
+            if getattr(self, "_rhs_tree_fn", None) is not None:
+                out[m] = self._rhs_tree_fn(int(l), ijk[m], tree[m])
+            else:
+                out[m] = self._rhs_fn(int(l), ijk[m])
         return out
 
     @property
@@ -98,6 +102,25 @@ class _Channels:
         head, side = self.parts(x, y, z)
         return self.amp_head * head - self.amp_side * side
 
+    def far(self, level, ijk, lo=(0.0, 0.0, 0.0), length=1.0, pad_cells=4, tails=8.0):
+        """True for boxes whose region padded by pad_cells lies further than
+        tails*delta from every channel surface (no charge to sample)."""
+        ijk = np.asarray(ijk, dtype=np.float64).reshape(-1, 3)
+        h = length / (8 * 2 ** (level - 1))
+        c = np.asarray(lo) + (8 * ijk + 4) * h
+        reach = np.sqrt(3.0) * (4 + pad_cells) * h + tails * self.delta
+        near = np.zeros(len(c), dtype=bool)
+        for p0, p1 in self.chans:
+            ax = p1 - p0
+            L = np.linalg.norm(ax)
+            u = ax / L
+            tpar = np.clip((c - p0) @ u, 0.0, L)
+            dseg = np.linalg.norm(c - (p0 + tpar[:, None] * u), axis=1)
+            dhead = np.linalg.norm(c - p1, axis=1)
+            dsurf = np.minimum(np.abs(dseg - self.radius), np.abs(dhead - self.radius))
+            near |= dsurf <= reach
+        return ~near
+
     def neutralise(self, boxes, lo, length):
         """Set A_s so that the sum of rho*h^3 over the leaf cells vanishes."""
         leaf = boxes.leaf_mask()
@@ -115,13 +138,20 @@ class _Channels:
             self.amp_side = self.amp_head * sh / ss
 
 
-def _score_fn(rho_fn, lo, length, memo):
-    """max over a box and a 3-cell buffer of max(|rho| h^2, |grad rho| h^3)."""
+def _score_fn(rho_fn, lo, length, memo, far_fn=None):
+    """max over a box and a 3-cell buffer of max(|rho| h^2, |grad rho| h^3).
+    far_fn(level, ijk) -> bool marks boxes whose padded region holds no
+    charge at all (score 0 without sampling)."""
     def score(level, ijk):
         keys = pack(ijk)
         d = memo.setdefault(level, {})
         out = np.empty(len(ijk))
         miss = [n for n, k in enumerate(keys.tolist()) if k not in d]
+        if far_fn is not None and miss:
+            far = far_fn(level, ijk[np.array(miss)])
+            for n in np.array(miss)[far].tolist():
+                d[int(keys[n])] = 0.0
+            miss = [n for n in miss if int(keys[n]) not in d]
         h = length / (8 * 2 ** (level - 1))
         for s in range(0, len(miss), 256):
             idx = np.array(miss[s:s + 256])
@@ -149,11 +179,11 @@ def _load_cache():
 
 
 def tuned_tree(tag, rho_fn, base_level, max_level, target, lo=(0, 0, 0), length=1.0,
-               tree=0, tol=0.1, use_cache=True):
+               tree=0, tol=0.1, use_cache=True, far_fn=None):
     """Balanced tree whose leaf-cell count is within ``tol`` of ``target``.
     c3 is found by log-bisection (and cached per ``tag``)."""
     memo = {}
-    score = _score_fn(rho_fn, lo, length, memo)
+    score = _score_fn(rho_fn, lo, length, memo, far_fn)
     cache = _load_cache() if use_cache else {}
     if tag in cache:
         c3 = cache[tag]
@@ -164,8 +194,9 @@ def tuned_tree(tag, rho_fn, base_level, max_level, target, lo=(0, 0, 0), length=
         mid = 0.5 * (lo_c + hi_c)
         bl = refine_by_score(base_level, max_level, score, 10 ** mid, tree)
         n = bl.n_leaf_cells()
-        best = (bl, 10 ** mid)
-        if abs(n - target) <= tol * target:
+        if best is None or abs(np.log(n / target)) < abs(np.log(best[0].n_leaf_cells() / target)):
+            best = (bl, 10 ** mid)
+        if abs(n - target) <= tol * target or hi_c - lo_c < 1e-3:
             break
         if n > target:
             lo_c = mid
@@ -213,3 +244,60 @@ def streamer_small(refinements=2, target=3.0e5, use_cache=True):
         x, y, z, *_ = charges.cell_centres(level, ijk, (0.0, 0.0, 0.0), 1.0)
         return -ch.rho(x, y, z)
     return Workload(f"streamer_small_L3+{refinements}", bl, fn, meta=dict(c3=c3))
+
+
+def _forest_tree(t, refinements=5, base=3, lo_cells=1e5, hi_cells=2e6, use_cache=True):
+    """Tree t of the forest: a seeded streamer, and the number of refinement
+    levels (at most ``refinements``) and c3 that bring the leaf-cell count
+    closest to a log-uniform target."""
+    rng = np.random.default_rng(4000 + t)
+    target = float(np.exp(rng.uniform(np.log(lo_cells), np.log(hi_cells))))
+    tip = rng.uniform(0.55, 0.8)
+    radius = rng.uniform(0.015, 0.03)
+    delta = 0.1 * radius
+    head = tip + radius
+    ch = _Channels([((0.5, 0.5, 1.0), (0.5, 0.5, head))], radius, delta, 1e4)
+    tag = f"forest_t{t}_r{refinements}_b{base}_t{target:.4g}"
+    cache = _load_cache() if use_cache else {}
+    if tag in cache:
+        r, c3 = cache[tag]
+        memo = {}
+        bl = refine_by_score(base, base + int(r), _score_fn(ch.rho, (0, 0, 0), 1.0, memo, ch.far),
+                             c3, t)
+    else:
+        best = None
+        for r in range(1, refinements + 1):
+            bl, c3 = tuned_tree(tag, ch.rho, base, base + r, target, tree=t, use_cache=False,
+                                far_fn=ch.far)
+            err = abs(np.log(bl.n_leaf_cells() / target))
+            if best is None or err < best[0]:
+                best = (err, bl, r, c3)
+        _, bl, r, c3 = best
+        if use_cache:
+            save_c3(tag, [r, c3])
+    ch.neutralise(bl, (0.0, 0.0, 0.0), 1.0)
+    return bl, ch, (r, c3), target
+
+
+def forest(n_trees=128, refinements=5, base=3, lo_cells=1e5, hi_cells=2e6, use_cache=True):
+    """Forest of independent trees of uneven size (leaf cells log-uniform in
+    [lo_cells, hi_cells]), each with one seeded streamer (tip height in
+    [0.55, 0.8], radius in [0.015, 0.03], head layer thickness 0.1 R); tree t
+    uses seed 4000 + t.  All trees share the unit-cube domain and boundary
+    data, and differ in their charge."""
+    parts = [_forest_tree(t, refinements, base, lo_cells, hi_cells, use_cache)
+             for t in range(n_trees)]
+    boxes = BoxList.concat([p[0] for p in parts])
+    chans = [p[1] for p in parts]
+
+    def fn_tree(level, ijk, tree):
+        out = np.zeros((len(ijk), 8, 8, 8))
+        for t in np.unique(tree):
+            m = tree == t
+            x, y, z, *_ = charges.cell_centres(level, ijk[m], (0.0, 0.0, 0.0), 1.0)
+            out[m] = -chans[int(t)].rho(x, y, z)
+        return out
+    w = Workload(f"forest{n_trees}_L{base}+{refinements}", boxes, None,
+                 meta=dict(c3=[p[2] for p in parts], targets=[p[3] for p in parts]))
+    w._rhs_tree_fn = fn_tree
+    return w
