@@ -74,6 +74,79 @@ def cpu_baseline(w, gpu_cycles, budget_s=12.0):
                       f"({cyc} V-cycles, GPU {gpu_cycles}), median {med:.3f} s"}
 
 
+NN_FLOP_PER_CELL = 2 * 27 * (16 + 16 * 16 + 16)  # the three convolutions, multiply-adds x 2
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+
+
+def learned_leg(g, args, k_plain, value_plain):
+    """Train the correction network on seeded streamer trees that are not the
+    benchmark problem, then time the learned solve on the benchmark tree and
+    the network's forward kernel on all of its leaf boxes."""
+    import numpy as np
+    import torch
+    from paper_1708_08434_amd import mg as M
+    from paper_1708_08434_amd import nn as NN
+    from workloads import forest
+
+    # training problems: 8 streamer trees of the seeded forest generator
+    tw = forest(n_trees=8)
+    tt = M.Tree.from_workload(tw, device="cuda:0")
+    tt.set_rhs_from(tw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, tgt = NN.training_pairs(tt, states=(0, 1, 2))
+    rng = np.random.default_rng(1000)
+    p0 = np.concatenate([rng.standard_normal(432) * np.sqrt(2.0 / 27), np.zeros(16),
+                         rng.standard_normal(6912) * np.sqrt(2.0 / 432), np.zeros(16),
+                         rng.standard_normal(432) * np.sqrt(1.0 / 432), np.zeros(1)])
+    net = NN.Net(p0.astype(np.float32), device="cuda:0")
+    losses = NN.train(net, x, tgt, steps=args.train_steps, batch=1024, lr=1e-3, seed=1,
+                      log_every=max(1, args.train_steps - 1))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del tt
+    L = NN.Learned(g)
+    for _ in range(max(1, args.warmup)):
+        res = L.solve(net)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        res = L.solve(net)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    n_leaf = int(g.info.n_leaf_cells)
+    # forward kernel on every leaf box of the benchmark tree, HIP events on
+    # the stream it is launched on (torch's current stream)
+    xin, _ = L.inputs()
+    nbox = int(xin.shape[0])
+    y = torch.empty((nbox, 512), dtype=torch.float32, device="cuda:0")
+    for _ in range(3):
+        NN.mg_nn_forward(net.h, nbox, xin.data_ptr(), y.data_ptr())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        NN.mg_nn_forward(net.h, nbox, xin.data_ptr(), y.data_ptr())
+    e1.record()
+    torch.cuda.synchronize()
+    launch_s = e0.elapsed_time(e1) / 1e3 / reps
+    tflops = NN_FLOP_PER_CELL * 512 * nbox / launch_s / 1e12
+    return {"value": n_leaf * args.steps / el, "unit": "cells/s", "ms_per_step": 1e3 * el / args.steps,
+            "vcycles": res["n_vcycles"], "vcycles_plain_fp64": k_plain,
+            "accepted_steps": res["accepted"], "fallback_cycle": res["fallback_cycle"],
+            "learned_ms_per_step": res["t_learned_ms"], "final_rel_res": res["rel"],
+            "vs_plain_fp64": (n_leaf * args.steps / el) / value_plain,
+            "train": {"problems": "8 seeded streamer trees (base 32^3 + <=5 levels), not the "
+                                  "benchmark tree", "pairs": int(x.shape[0]),
+                      "adam_steps": args.train_steps, "batch": 1024, "lr": 1e-3,
+                      "loss_first_last": [losses[0][1], losses[-1][1]], "seconds": train_s},
+            "nn_forward": {"bound": "mfma", "kernel": "k_nn_fwd (BF16 MFMA implicit GEMM)",
+                           "boxes": nbox, "avg_launch_us": launch_s * 1e6,
+                           "flop_per_cell": NN_FLOP_PER_CELL, "achieved": tflops,
+                           "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": tflops / BF16_PEAK_TFLOPS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +154,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction leg")
+    ap.add_argument("--train-steps", type=int, default=300, help="Adam steps of the learned leg")
     ap.add_argument("--copy-probe", type=int, default=0, help="bytes of a calibration copy")
     ap.add_argument("--workload", default="streamer", choices=["streamer", "forest"],
                     help="streamer: base 64^3 + 4 levels (default); forest: 128 uneven trees")
@@ -152,6 +227,9 @@ def main():
     ms = 1e3 * elapsed / args.steps
     value = n_leaf * args.steps / elapsed
     k = stats["n_vcycles"]
+    learned = None
+    if not args.no_learned:
+        learned = learned_leg(g, args, k, value)
     mb = model_bytes(counts, n_leaf, k)
     # the level whose half-sweeps move the most bytes (the finest level of a
     # single streamer tree; a middle level of the forest)
@@ -191,6 +269,8 @@ def main():
     }
     if mixed is not None:
         out["mixed"] = mixed
+    if learned is not None:
+        out["learned"] = learned
     if rank == 0 and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, k)
     if rank == 0:

@@ -146,8 +146,8 @@ def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-
 # homogeneous boundary data) of c_l, the correction restricted to the leaf
 # boxes of level l, each tree takes the step sizes s_l that minimise the
 # volume-weighted L2 norm of r - sum_l s_l q_l over its leaf cells (a linear
-# least-squares problem; a level whose column vanishes gets 0), and
-# phi += sum_l s_l c_l.
+# least-squares problem; a level whose column vanishes or is not finite gets
+# 0), and phi += sum_l s_l c_l on the boxes whose step is not 0.
 # ---------------------------------------------------------------------------
 
 def face_ghost_layers():
@@ -226,11 +226,17 @@ def learned_step(tree, params, round_bf16=True):
     for tr in range(tree.ntree):
         m = leaf & (tid == tr)
         wm = w[m][:, None, None, None]
-        A = np.stack([(wm * q[int(l)][m]).ravel() for l in levels], axis=1)
-        sol = np.linalg.lstsq(A, (wm * r[m]).ravel(), rcond=None)[0]
-        s[tr, levels] = sol
+        cols = [(wm * q[int(l)][m]).ravel() for l in levels]
+        # a column that is not finite counts as vanishing (its level gets 0)
+        ok = [bool(np.all(np.isfinite(col))) for col in cols]
+        if any(ok):
+            A = np.stack([col for col, k in zip(cols, ok) if k], axis=1)
+            sol = np.linalg.lstsq(A, (wm * r[m]).ravel(), rcond=None)[0]
+            s[tr, [l for l, k in zip(levels, ok) if k]] = sol
     new = phi.copy()
-    new[leaf] += s[tid[leaf], level[leaf]][:, None, None, None] * c[leaf]
+    sl = s[tid[leaf], level[leaf]]
+    upd = sl != 0  # boxes whose step is 0 keep phi (also where c is not finite)
+    new[np.nonzero(leaf)[0][upd]] += sl[upd][:, None, None, None] * c[leaf][upd]
     tree.set_field(PHI, new)
     return dict(c=c, s=s, r=r, q=q, X=X, scale=scale, levels=levels)
 

@@ -53,6 +53,9 @@ void launch_restrict_phi(const Geo &g, T *phi, int64_t b0, int64_t nb, hipStream
 void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const double *chat,
                        const int32_t *leaf, int64_t nleaf, double *partial, float *r_out,
                        hipStream_t s);
+template <typename T>
+void launch_leaf_apply(const Geo &g, const T *x, const T *chat, const int32_t *leaf, int64_t nleaf,
+                       T *out, hipStream_t s);
 void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s);
 void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const int32_t *off,
                          int ntree, double *result, hipStream_t s);

@@ -529,6 +529,33 @@ __global__ __launch_bounds__(256) void k_leaf_norms(Geo g, const double *__restr
     }
 }
 
+// out[q][e] = (L x)(cell e of leaf box leaf[q]) for the composite operator
+// with the field's ghosts (same layout as the field, one 512-run per leaf
+// position); the operator applications of the learned correction step.
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_apply(Geo g, const T *__restrict__ x,
+                                                    const T *__restrict__ chat,
+                                                    const int32_t *__restrict__ leaf, int64_t nleaf,
+                                                    T *__restrict__ out) {
+    __shared__ T P[512], H[384];
+    int64_t q = xcd_map(blockIdx.x, nleaf);
+    if (q >= nleaf) return;
+    int64_t b = leaf[q];
+    int t = threadIdx.x;
+    int l = g.ijk[b * 4 + 3];
+    stage_full<T>(g, x, chat, b, P, H);
+    __syncthreads();
+    double h = g.len / (8.0 * (double)(1 << (l - 1)));
+    T inv_h2 = (T)(1.0 / (h * h));
+    int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        int i = 2 * m + ((j + k + c) & 1);
+        T own = P[c * 256 + t];
+        out[q * 512 + c * 256 + t] = (sum_full<T>(P, H, i, j, k) - (T)6 * own) * inv_h2;
+    }
+}
+
 // phi (FP64) += e (FP32) on every cell: the update of the mixed-precision
 // iterative refinement.
 __global__ __launch_bounds__(256) void k_ir_update(double *__restrict__ phi, const float *__restrict__ e,
@@ -653,6 +680,15 @@ void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const
     hipLaunchKernelGGL(k_leaf_norms, dim3((unsigned)xcd_grid(nleaf)), dim3(256), 0, s, g, phi, rhs,
                        chat, leaf, nleaf, partial, r_out);
 }
+template <typename T>
+void launch_leaf_apply(const Geo &g, const T *x, const T *chat, const int32_t *leaf, int64_t nleaf,
+                       T *out, hipStream_t s) {
+    if (nleaf <= 0) return;
+    hipLaunchKernelGGL(k_leaf_apply<T>, dim3((unsigned)xcd_grid(nleaf)), dim3(256), 0, s, g, x, chat, leaf,
+                       nleaf, out);
+}
+template void launch_leaf_apply<float>(const Geo &, const float *, const float *, const int32_t *,
+                                       int64_t, float *, hipStream_t);
 void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_ir_update, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, phi, e, count);

@@ -17,6 +17,8 @@
 
 #include "kernels.h"
 #include "mg_internal.h"
+#include "mg_nn.h"
+#include "nn.h"
 
 namespace mg {
 
@@ -435,6 +437,194 @@ double now_ms() {
         .count();
 }
 
+// ---- learned correction step
+constexpr int kStepStride = kMaxLevel + 2;  // steps[tree][level], level 0 unused
+constexpr double kLearnedKeep = 0.99;
+
+struct LearnedWs {
+    float *x, *y, *scale, *q;
+    double *partial, *steps;
+};
+
+int64_t learned_layout(const mg_tree *t, char *base, LearnedWs *L) {
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t at = o;
+        o += (bytes + 255) & ~(int64_t)255;
+        return at;
+    };
+    int64_t nl = t->nleaf;
+    int64_t ox = take(4 * 1000 * nl), oy = take(4 * 512 * nl), os = take(4 * nl);
+    int64_t oq = take(4 * 3 * 512 * nl), op = take(8 * 9 * nl);
+    int64_t ost = take(8 * (int64_t)t->ntree * kStepStride);
+    if (base && L) {
+        L->x = (float *)(base + ox);
+        L->y = (float *)(base + oy);
+        L->scale = (float *)(base + os);
+        L->q = (float *)(base + oq);
+        L->partial = (double *)(base + op);
+        L->steps = (double *)(base + ost);
+    }
+    return o;
+}
+
+int check_learned_ws(const mg_tree *t, void *ws, int64_t bytes) {
+    if (!ws || ((uintptr_t)ws & 255)) {
+        set_error("learned workspace missing or not 256-byte aligned");
+        return MG_EINVAL;
+    }
+    if (bytes < learned_layout(t, nullptr, nullptr)) {
+        set_error("learned workspace too small");
+        return MG_ENOMEM;
+    }
+    return MG_OK;
+}
+
+// Least squares per tree: minimise |r - sum_l s_l q_l| given the Gram matrix
+// G (S x S, upper triangle filled) and g = (<r, q_l>).  Levels with a zero
+// column get 0; a level whose pivot vanishes (a dependent column) is
+// dropped and the factorisation restarted.
+void solve_steps(const double *G, const double *g, double *s) {
+    const int S = kStepStride;
+    bool on[S];
+    for (int l = 0; l < S; l++) {
+        on[l] = G[l * S + l] > 0.0 && std::isfinite(G[l * S + l]);
+        s[l] = 0.0;
+    }
+    for (int attempt = 0; attempt <= S; attempt++) {
+        int idx[S], n = 0;
+        for (int l = 0; l < S; l++)
+            if (on[l]) idx[n++] = l;
+        if (n == 0) return;
+        double C[S][S] = {{0}};
+        int bad = -1;
+        for (int a = 0; a < n && bad < 0; a++) {
+            for (int c = 0; c <= a; c++) {
+                int la = idx[a], lc = idx[c];
+                double v = la <= lc ? G[la * S + lc] : G[lc * S + la];
+                for (int k = 0; k < c; k++) v -= C[a][k] * C[c][k];
+                if (c == a) {
+                    if (!(v > 1e-13 * G[la * S + la])) {
+                        bad = la;
+                        break;
+                    }
+                    C[a][a] = std::sqrt(v);
+                } else {
+                    C[a][c] = v / C[c][c];
+                }
+            }
+        }
+        if (bad >= 0) {
+            on[bad] = false;
+            continue;
+        }
+        double z[S];
+        for (int a = 0; a < n; a++) {
+            double v = g[idx[a]];
+            for (int k = 0; k < a; k++) v -= C[a][k] * z[k];
+            z[a] = v / C[a][a];
+        }
+        for (int a = n - 1; a >= 0; a--) {
+            double v = z[a];
+            for (int k = a + 1; k < n; k++) v -= C[k][a] * s[idx[k]];
+            s[idx[a]] = v / C[a][a];
+        }
+        return;
+    }
+}
+
+// One learned step on the current FP64 phi (see mg_nn.h).  The FP32
+// correction fields serve as scratch: e32 holds the correction of one level
+// class (levels = m mod 3, whose operator images do not overlap: a leaf cell
+// of level j only sees corrections of levels j-1, j, j+1), r32 the residual.
+int learned_step_impl(mg_tree *t, mg_nn *nn, const LearnedWs &L, double *steps_host) {
+    Fields<double> F = f64(t);
+    Fields<float> E = f32(t);
+    hipStream_t s = stream_of(t);
+    const int64_t nl = t->nleaf;
+    restrict_all(t, F);
+    norms_launch(t, 0, E.rhs);
+    launch_nn_gather(E.rhs, t->d.leaf, nl, t->d.nbr, t->d.ijk, t->d.isleaf, t->dom.len, L.x, L.scale, s);
+    launch_nn_forward(nn->prm, nn->pk, nl, nullptr, L.x, L.y, nullptr, nullptr, s);
+    for (int m = 0; m < 3; m++) {
+        launch_nn_scatter(L.y, L.scale, t->d.leaf, nl, t->d.ijk, m, E.phi, s);
+        dirty_all(E);
+        restrict_all(t, E);
+        for (int l = 2; l <= t->nlev; l++) ensure_cf(t, E, l);
+        launch_leaf_apply<float>(E.g, E.phi, E.chat, t->d.leaf, nl, L.q + (int64_t)m * nl * 512, s);
+    }
+    dirty_all(E);
+    launch_nn_dots(E.rhs, L.q, t->d.leaf, nl, t->d.ijk, t->dom.len, L.partial, s);
+    std::vector<double> part((size_t)9 * nl);
+    int rc = hip_check(hipMemcpyAsync(part.data(), L.partial, part.size() * sizeof(double),
+                                      hipMemcpyDeviceToHost, s), "step sums readback");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "stream synchronize");
+    if (rc) return rc;
+    const int S = kStepStride, T = t->ntree;
+    std::vector<double> G((size_t)T * S * S, 0.0), g((size_t)T * S, 0.0), st((size_t)T * S, 0.0);
+    for (int64_t q = 0; q < nl; q++) {
+        int64_t b = t->leaf[q];
+        int j = t->lev[b], tr = t->tid[b];
+        const double *p = &part[9 * q];
+        double *Gt = &G[(size_t)tr * S * S], *gt = &g[(size_t)tr * S];
+        gt[j - 1] += p[0];
+        gt[j] += p[1];
+        gt[j + 1] += p[2];
+        Gt[(j - 1) * S + j - 1] += p[3];
+        Gt[(j - 1) * S + j] += p[4];
+        Gt[(j - 1) * S + j + 1] += p[5];
+        Gt[j * S + j] += p[6];
+        Gt[j * S + j + 1] += p[7];
+        Gt[(j + 1) * S + j + 1] += p[8];
+    }
+    for (int tr = 0; tr < T; tr++) {
+        double *Gt = &G[(size_t)tr * S * S];
+        for (int l = 0; l < S; l++) Gt[l] = Gt[l * S] = 0.0;  // no level 0
+        solve_steps(Gt, &g[(size_t)tr * S], &st[(size_t)tr * S]);
+    }
+    rc = hip_check(hipMemcpyAsync(L.steps, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice, s),
+                   "step upload");
+    if (rc) return rc;
+    launch_nn_update(F.phi, L.y, L.scale, t->d.leaf, nl, t->d.ijk, t->d.tid, L.steps, S, s);
+    dirty_all(F);
+    if (steps_host)
+        for (int tr = 0; tr < T; tr++)
+            for (int l = 0; l <= t->nlev; l++) steps_host[tr * (t->nlev + 1) + l] = st[(size_t)tr * S + l];
+    rc = hip_check(hipGetLastError(), "learned step launch");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "stream synchronize");
+    return rc;
+}
+
+// Network state in the caller's device memory.
+int64_t nn_state_layout(char *base, mg_nn *nn) {
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t at = o;
+        o += (bytes + 255) & ~(int64_t)255;
+        return at;
+    };
+    int64_t op = take(4 * kNnParams), om = take(4 * kNnParams), ov = take(4 * kNnParams);
+    int64_t og = take(4 * kNnParams), ok = take(2 * kNnPacked);
+    if (base && nn) {
+        nn->prm = (float *)(base + op);
+        nn->m = (float *)(base + om);
+        nn->v = (float *)(base + ov);
+        nn->grad = (float *)(base + og);
+        nn->pk = (uint16_t *)(base + ok);
+    }
+    return o;
+}
+
+hipStream_t nn_stream(const mg_nn *nn) { return (hipStream_t)nn->stream; }
+
+int require_nn(const mg_nn *nn) {
+    if (!nn) {
+        set_error("null network");
+        return MG_EINVAL;
+    }
+    return MG_OK;
+}
+
 }  // namespace
 }  // namespace mg
 
@@ -560,6 +750,8 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.slots = (int32_t *)(base + t->off.slots);
     d.leaf_tree = (int32_t *)(base + t->off.leaf_tree);
     d.tree_off = (int32_t *)(base + t->off.tree_off);
+    d.isleaf = (int32_t *)(base + t->off.isleaf);
+    d.tid = (int32_t *)(base + t->off.tid);
     d.eig = (double *)(base + t->off.eig);
     d.phi = (double *)(base + t->off.phi);
     d.rhs = (double *)(base + t->off.rhs);
@@ -577,7 +769,8 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
                            "pinned host buffer");
         if (rc) return rc;
     }
-    std::vector<int32_t> ijk4((size_t)4 * t->n);
+    std::vector<int32_t> ijk4((size_t)4 * t->n), isleaf((size_t)t->n);
+    for (int64_t b = 0; b < t->n; b++) isleaf[b] = t->child[8 * b] < 0 ? 1 : 0;
     for (int64_t b = 0; b < t->n; b++) {
         for (int a = 0; a < 3; a++) ijk4[4 * b + a] = t->ijk[3 * b + a];
         ijk4[4 * b + 3] = t->lev[b];
@@ -598,6 +791,8 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     rc = rc ? rc : up(d.slots, t->slots.data(), t->slots.size() * 4);
     rc = rc ? rc : up(d.leaf_tree, t->leaf_tree.data(), t->leaf_tree.size() * 4);
     rc = rc ? rc : up(d.tree_off, t->tree_off.data(), t->tree_off.size() * 4);
+    rc = rc ? rc : up(d.isleaf, isleaf.data(), isleaf.size() * 4);
+    rc = rc ? rc : up(d.tid, t->tid.data(), t->tid.size() * 4);
     rc = rc ? rc : up(d.eig, t->eig, sizeof t->eig);
     if (rc) return rc;
     launch_fill<double>(d.phi, 512 * t->n, 0.0, s);
@@ -872,6 +1067,256 @@ int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out) {
     t->probes.clear();
     if (out) *out = acc;
     return MG_OK;
+}
+
+// ---------------------------------------------------------- learned step
+
+int64_t mg_nn_state_bytes(void) { return nn_state_layout(nullptr, nullptr); }
+
+int mg_nn_create(mg_nn **out, void *state, int64_t state_bytes, void *stream) {
+    if (!out || !state || ((uintptr_t)state & 255)) {
+        set_error("null output, null state or state not 256-byte aligned");
+        return MG_EINVAL;
+    }
+    *out = nullptr;
+    if (state_bytes < mg_nn_state_bytes()) {
+        set_error("network state too small");
+        return MG_ENOMEM;
+    }
+    mg_nn *nn = new (std::nothrow) mg_nn();
+    if (!nn) return MG_ENOMEM;
+    nn_state_layout((char *)state, nn);
+    nn->stream = stream;
+    int rc = hip_check(hipGetDevice(&nn->device), "current device");
+    if (!rc) rc = hip_check(hipHostMalloc((void **)&nn->host_loss, sizeof(double)), "pinned host buffer");
+    if (!rc) {
+        hipStream_t s = nn_stream(nn);
+        for (float *p : {nn->prm, nn->m, nn->v, nn->grad}) launch_fill<float>(p, kNnParams, 0.0f, s);
+        launch_nn_pack(nn->prm, nn->pk, s);
+        rc = hip_check(hipGetLastError(), "network init");
+        if (!rc) rc = hip_check(hipStreamSynchronize(s), "stream synchronize");
+    }
+    if (rc) {
+        if (nn->host_loss) (void)hipHostFree(nn->host_loss);
+        delete nn;
+        return rc;
+    }
+    *out = nn;
+    return MG_OK;
+}
+
+int mg_nn_destroy(mg_nn *nn) {
+    if (!nn) return MG_OK;
+    if (nn->host_loss) (void)hipHostFree(nn->host_loss);
+    delete nn;
+    return MG_OK;
+}
+
+int mg_nn_set_params(mg_nn *nn, const float *params) {
+    int rc = require_nn(nn);
+    if (rc) return rc;
+    if (!params) {
+        set_error("null parameters");
+        return MG_EINVAL;
+    }
+    hipStream_t s = nn_stream(nn);
+    rc = hip_check(hipMemcpyAsync(nn->prm, params, kNnParams * sizeof(float), hipMemcpyHostToDevice, s),
+                   "parameter upload");
+    if (rc) return rc;
+    launch_fill<float>(nn->m, kNnParams, 0.0f, s);
+    launch_fill<float>(nn->v, kNnParams, 0.0f, s);
+    launch_nn_pack(nn->prm, nn->pk, s);
+    nn->step = 0;
+    rc = hip_check(hipGetLastError(), "parameter pack");
+    return rc ? rc : hip_check(hipStreamSynchronize(s), "stream synchronize");
+}
+
+int mg_nn_get_params(mg_nn *nn, float *params) {
+    int rc = require_nn(nn);
+    if (rc) return rc;
+    if (!params) {
+        set_error("null parameters");
+        return MG_EINVAL;
+    }
+    hipStream_t s = nn_stream(nn);
+    rc = hip_check(hipMemcpyAsync(params, nn->prm, kNnParams * sizeof(float), hipMemcpyDeviceToHost, s),
+                   "parameter readback");
+    return rc ? rc : hip_check(hipStreamSynchronize(s), "stream synchronize");
+}
+
+int mg_nn_get_grad(mg_nn *nn, float *grad) {
+    int rc = require_nn(nn);
+    if (rc) return rc;
+    if (!grad) {
+        set_error("null gradient buffer");
+        return MG_EINVAL;
+    }
+    hipStream_t s = nn_stream(nn);
+    rc = hip_check(hipMemcpyAsync(grad, nn->grad, kNnParams * sizeof(float), hipMemcpyDeviceToHost, s),
+                   "gradient readback");
+    return rc ? rc : hip_check(hipStreamSynchronize(s), "stream synchronize");
+}
+
+int mg_nn_forward(mg_nn *nn, int64_t nbox, const float *x, float *y) {
+    int rc = require_nn(nn);
+    if (rc) return rc;
+    if (nbox < 0 || nbox > INT32_MAX || (nbox > 0 && (!x || !y))) {
+        set_error("invalid forward arguments");
+        return MG_EINVAL;
+    }
+    launch_nn_forward(nn->prm, nn->pk, nbox, nullptr, x, y, nullptr, nullptr, nn_stream(nn));
+    return hip_check(hipGetLastError(), "forward launch");
+}
+
+int64_t mg_nn_train_bytes(int64_t nbox) { return nn_train_layout(nbox < 0 ? 0 : nbox, nullptr, nullptr); }
+
+int mg_nn_gradient(mg_nn *nn, int64_t nbox, const int32_t *idx, const float *x, const float *target,
+                   void *ws, int64_t ws_bytes, double *loss) {
+    int rc = require_nn(nn);
+    if (rc) return rc;
+    if (nbox <= 0 || nbox > INT32_MAX || !x || !target || !ws || ((uintptr_t)ws & 255)) {
+        set_error("invalid gradient arguments");
+        return MG_EINVAL;
+    }
+    if (ws_bytes < mg_nn_train_bytes(nbox)) {
+        set_error("training workspace too small");
+        return MG_ENOMEM;
+    }
+    NnTrainWs w;
+    nn_train_layout(nbox, (char *)ws, &w);
+    hipStream_t s = nn_stream(nn);
+    launch_nn_forward(nn->prm, nn->pk, nbox, idx, x, w.y, w.a1, w.a2, s);
+    launch_nn_backward(nn->prm, nbox, idx, x, target, w, nn->grad, s);
+    if ((rc = hip_check(hipGetLastError(), "gradient launch"))) return rc;
+    if (!loss) return MG_OK;
+    rc = hip_check(hipMemcpyAsync(nn->host_loss, w.loss, sizeof(double), hipMemcpyDeviceToHost, s),
+                   "loss readback");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "stream synchronize");
+    if (!rc) *loss = *nn->host_loss;
+    return rc;
+}
+
+int mg_nn_adam(mg_nn *nn, const mg_adam_opts *o) {
+    int rc = require_nn(nn);
+    if (rc) return rc;
+    if (!o || !(o->lr >= 0) || !(o->beta1 >= 0 && o->beta1 < 1) || !(o->beta2 >= 0 && o->beta2 < 1) ||
+        !(o->eps > 0)) {
+        set_error("invalid Adam options");
+        return MG_EINVAL;
+    }
+    nn->step++;
+    double bc1 = 1.0 - std::pow(o->beta1, (double)nn->step), bc2 = 1.0 - std::pow(o->beta2, (double)nn->step);
+    hipStream_t s = nn_stream(nn);
+    launch_nn_adam(nn->prm, nn->m, nn->v, nn->grad, (float)o->lr, (float)o->beta1, (float)o->beta2,
+                   (float)o->eps, (float)bc1, (float)bc2, s);
+    launch_nn_pack(nn->prm, nn->pk, s);
+    return hip_check(hipGetLastError(), "Adam launch");
+}
+
+int64_t mg_learned_bytes(const mg_tree *t) { return t ? learned_layout(t, nullptr, nullptr) : 0; }
+
+int mg_nn_inputs(mg_tree *t, float *x, float *scale) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!x || !scale) {
+        set_error("null output buffers");
+        return MG_EINVAL;
+    }
+    Fields<float> E = f32(t);
+    restrict_all(t, f64(t));
+    norms_launch(t, 0, E.rhs);
+    launch_nn_gather(E.rhs, t->d.leaf, t->nleaf, t->d.nbr, t->d.ijk, t->d.isleaf, t->dom.len, x, scale,
+                     stream_of(t));
+    return hip_check(hipGetLastError(), "input gather");
+}
+
+int mg_nn_targets(mg_tree *t, const double *ref, const float *scale, float *target) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!ref || !scale || !target) {
+        set_error("null buffers");
+        return MG_EINVAL;
+    }
+    launch_nn_targets(t->d.phi, ref, scale, t->d.leaf, t->nleaf, target, stream_of(t));
+    return hip_check(hipGetLastError(), "targets");
+}
+
+int mg_learned_step(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes, double *steps) {
+    int rc = require_bound(t);
+    if (rc || (rc = require_nn(nn)) || (rc = check_learned_ws(t, ws, ws_bytes))) return rc;
+    LearnedWs L;
+    learned_layout(t, (char *)ws, &L);
+    return learned_step_impl(t, nn, L, steps);
+}
+
+int mg_learned_solve(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes, const mg_solve_opts *o,
+                     mg_solve_stats *st, mg_learned_stats *ls) {
+    int rc = require_bound(t);
+    if (rc || (rc = require_nn(nn)) || (rc = check_learned_ws(t, ws, ws_bytes)) || (rc = check_opts(o)))
+        return rc;
+    if (o->precision != MG_FP64) {
+        set_error("the learned solve runs in FP64");
+        return MG_EINVAL;
+    }
+    LearnedWs L;
+    learned_layout(t, (char *)ws, &L);
+    mg_solve_stats local;
+    mg_solve_stats *s = st ? st : &local;
+    std::memset(s, 0, sizeof *s);
+    mg_learned_stats lloc;
+    mg_learned_stats *lst = ls ? ls : &lloc;
+    std::memset(lst, 0, sizeof *lst);
+    double t0 = now_ms();
+    const int T = t->ntree;
+    Fields<double> F = f64(t);
+    const size_t bytes = (size_t)t->n * 512 * sizeof(double);
+    if ((rc = run_seq(t, mg_tree::SEQ_FMG, o, 4 * T))) return s->status = rc;
+    for (int tr = 0; tr < T; tr++) t->beff_tree[tr] = std::sqrt(t->host_result[2 * T + 2 * tr]);
+    if ((rc = record_check(t, s, 0))) return s->status = rc;
+    bool use = true;
+    int stall = 0;
+    for (int k = 1; s->rel_res > o->rel_tol; k++) {
+        if (k > o->max_cycles) {
+            set_error("no convergence within max_cycles");
+            return s->status = MG_ENOCONV;
+        }
+        double prev = s->rel_res;
+        if ((rc = run_seq(t, mg_tree::SEQ_VCHECK, o, 2 * T))) return s->status = rc;
+        s->n_vcycles = k;
+        if ((rc = record_check(t, s, k))) return s->status = rc;
+        if (s->rel_res > o->rel_tol && use) {
+            double tl = now_ms(), rel_v = s->rel_res;
+            rc = hip_check(hipMemcpyAsync(F.old, F.phi, bytes, hipMemcpyDeviceToDevice, stream_of(t)),
+                           "save phi");
+            if (!rc) rc = learned_step_impl(t, nn, L, nullptr);
+            if (rc) return s->status = rc;
+            restrict_all(t, F);
+            if ((rc = norms(t))) return s->status = rc;
+            mg_solve_stats trial = *s;
+            int rt = record_check(t, &trial, k);
+            if (rt == MG_OK && trial.rel_res <= kLearnedKeep * rel_v) {
+                *s = trial;
+                lst->accepted++;
+            } else {
+                rc = hip_check(hipMemcpyAsync(F.phi, F.old, bytes, hipMemcpyDeviceToDevice, stream_of(t)),
+                               "restore phi");
+                if (rc) return s->status = rc;
+                dirty_all(F);
+                if ((rc = check_and_record(t, s, k))) return s->status = rc;
+                use = false;
+                lst->fallback_cycle = k;
+            }
+            lst->t_learned_ms += now_ms() - tl;
+        }
+        stall = s->rel_res >= prev ? stall + 1 : 0;
+        if (stall >= 3) {
+            set_error("residual stagnates");
+            return s->status = MG_ENOCONV;
+        }
+    }
+    rc = hip_check(hipGetLastError(), "kernel launch");
+    s->t_ms = now_ms() - t0;
+    return s->status = rc;
 }
 
 }  // extern "C"

@@ -27,6 +27,8 @@ struct DevTables {
     int32_t *slots = nullptr;    // [nslot][2] (box, face)
     int32_t *leaf_tree = nullptr;  // leaf-list positions grouped by tree (ascending within a tree)
     int32_t *tree_off = nullptr;   // [ntree+1] offsets into leaf_tree
+    int32_t *isleaf = nullptr;     // [n] 1 for a box without children
+    int32_t *tid = nullptr;        // [n] tree of the box
     double *eig = nullptr;       // root solve: Q_x, Q_y, Q_z (8x8, column = vector), then lambda_x,y,z
     double *phi = nullptr;       // [n][2][256] colour-split
     double *rhs = nullptr;
@@ -59,7 +61,7 @@ struct mg_tree {
     mg_domain dom{};
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
-    struct { int64_t nbr, cfslot, cfq, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, eig,
+    struct { int64_t nbr, cfslot, cfq, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, isleaf, tid, eig,
              phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, total; } off{};
     // ---- bound device state ----
     void *ws = nullptr;

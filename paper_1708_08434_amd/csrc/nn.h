@@ -1,0 +1,57 @@
+// Learned correction network: device state and launchers (kernels in nn.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace mg {
+
+constexpr int kNnParams = 7809;   // 16*27 + 16 + 16*16*27 + 16 + 16*27 + 1
+constexpr int kNnPacked = 8192;   // BF16 MFMA operand fragments of the weights
+constexpr int kNnWgradBlocks = 512;
+
+// Per-box training buffers (the caller's workspace), see nn_train_layout.
+struct NnTrainWs {
+    float *y, *gz1, *gz2, *part;
+    uint16_t *a1, *a2;
+    double *lossp, *loss;
+};
+int64_t nn_train_layout(int64_t nbox, char *base, NnTrainWs *w);
+
+void launch_nn_pack(const float *prm, uint16_t *pk, hipStream_t s);
+void launch_nn_forward(const float *prm, const uint16_t *pk, int64_t nbox, const int32_t *idx,
+                       const float *x, float *y, uint16_t *a1, uint16_t *a2, hipStream_t s);
+void launch_nn_backward(const float *prm, int64_t nbox, const int32_t *idx, const float *x,
+                        const float *target, const NnTrainWs &w, float *grad, hipStream_t s);
+void launch_nn_adam(float *prm, float *m, float *v, const float *g, float lr, float b1, float b2,
+                    float eps, float bc1, float bc2, hipStream_t s);
+
+// Learned step on a tree (leaf boxes in leaf-list order, fields colour-split).
+void launch_nn_gather(const float *r32, const int32_t *leaf, int64_t nleaf, const int32_t *nbr,
+                      const int32_t *ijk4, const int32_t *isleaf, double len, float *x, float *scale,
+                      hipStream_t s);
+void launch_nn_scatter(const float *y, const float *scale, const int32_t *leaf, int64_t nleaf,
+                       const int32_t *ijk4, int mod3, float *e32, hipStream_t s);
+void launch_nn_dots(const float *r32, const float *q3, const int32_t *leaf, int64_t nleaf,
+                    const int32_t *ijk4, double len, double *partial, hipStream_t s);
+void launch_nn_update(double *phi, const float *y, const float *scale, const int32_t *leaf,
+                      int64_t nleaf, const int32_t *ijk4, const int32_t *tid, const double *steps,
+                      int stride, hipStream_t s);
+void launch_nn_targets(const double *phi, const double *ref, const float *scale,
+                       const int32_t *leaf, int64_t nleaf, float *target, hipStream_t s);
+
+}  // namespace mg
+
+// The network object behind the C ABI: FP32 master parameters, Adam moments,
+// packed BF16 operand fragments and a gradient buffer, in the caller's
+// device memory.
+struct mg_nn {
+    float *prm = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    uint16_t *pk = nullptr;
+    void *stream = nullptr;       // stream of the standalone calls
+    double *host_loss = nullptr;  // pinned
+    int64_t step = 0;
+    int device = 0;
+};

@@ -1,0 +1,688 @@
+// Learned correction network for the octree multigrid (gfx950).
+//
+// The network maps a leaf box's scaled residual (8^3 plus its one-cell ghost
+// layer, 10^3) to a correction on the box's 8^3 cells:
+//   conv 3^3 valid 1->16, ReLU, conv 3^3 same 16->16, ReLU, conv 3^3 same 16->1.
+// Weights, the input and both hidden activations are BF16 (round to nearest
+// even), accumulation is FP32.  Parameters are kept as FP32 masters in the
+// order W1[16][27], b1[16], W2[16 out][16 in][27], b2[16], W3[16][27], b3,
+// with tap t = (dk*3 + dj)*3 + di.
+//
+// Forward: one workgroup (4 waves) per box; everything stays in LDS.
+//  * layer 1 is an implicit GEMM [16 cells x 32 taps (27 used)] x [32 x 16
+//    channels]: one 16x16x32 BF16 MFMA per 16-cell tile;
+//  * layer 2 is an implicit GEMM with K = 27 taps x 16 channels, taken as 14
+//    16x16x32 MFMAs (two taps per instruction, the 28th tap zero) per tile;
+//    the A operand of a lane is 8 consecutive channels of one shifted cell,
+//    one 16-byte LDS read, from activations stored [padded cell][channel];
+//  * layer 3 first forms Q[tap][cell] = sum_c W3[c][tap] a2[c][cell] with
+//    16x16x16 MFMAs (N = taps), then y[cell] = b3 + sum_tap Q[tap][cell+tap-1],
+//    which turns the 16->1 convolution into a dense GEMM plus a 27-term sum.
+// The backward pass (training only) runs in FP32 on the vector units.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nn.h"
+
+namespace mg {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kW1 = 0, kB1 = 432, kW2 = 448, kB2 = 7360, kW3 = 7376, kB3 = 7808;
+constexpr int kP1 = 0, kP2 = 512, kP3 = 7680;  // offsets in the packed fragments
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float round_bf(float f) { return bf2f(f2bf(f)); }
+// max(z, 0) that propagates NaN (a non-finite weight must reach the output)
+__device__ __forceinline__ float relu(float z) { return !(z <= 0.0f) ? z : 0.0f; }
+
+// offset of tap t in a 10^3 block (x fastest)
+__host__ __device__ constexpr int tap_off(int t) { return (t / 9) * 100 + ((t / 3) % 3) * 10 + t % 3; }
+
+// colour-split index -> natural cell index (k*8 + j)*8 + i
+__device__ __forceinline__ int cs_to_nat(int e) {
+    int c = e >> 8, r = e & 255, m = r & 3, j = (r >> 2) & 7, k = r >> 5;
+    int i = 2 * m + ((j + k + c) & 1);
+    return (k * 8 + j) * 8 + i;
+}
+__device__ __forceinline__ int cs_idx(int i, int j, int k) {
+    return (((i + j + k) & 1) << 8) + ((k * 8 + j) << 2) + (i >> 1);
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum256(T v, T *S) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    int t = threadIdx.x;
+    __syncthreads();
+    if ((t & 63) == 0) S[t >> 6] = v;
+    __syncthreads();
+    return (S[0] + S[1]) + (S[2] + S[3]);
+}
+
+// ------------------------------------------------------------ weight packing
+// Fragments in the lane order of the MFMA B operand (lane l holds column
+// l % 16, K rows 8 (l / 16) .. +7 for 16x16x32, 4 (l / 16) .. +3 for 16x16x16).
+__global__ __launch_bounds__(256) void k_nn_pack(const float *__restrict__ prm, uint16_t *__restrict__ pk) {
+    for (int e = threadIdx.x; e < kNnPacked; e += 256) {
+        float v = 0.0f;
+        if (e < kP2) {
+            int lane = e >> 3, q = e & 7, o = lane & 15, g = lane >> 4, t = 8 * g + q;
+            if (t < 27) v = prm[kW1 + o * 27 + t];
+        } else if (e < kP3) {
+            int e2 = e - kP2, p = e2 >> 9, r = e2 & 511, lane = r >> 3, q = r & 7;
+            int o = lane & 15, g = lane >> 4, tap = 2 * p + (g >> 1), ch = 8 * (g & 1) + q;
+            if (tap < 27) v = prm[kW2 + (o * 16 + ch) * 27 + tap];
+        } else {
+            int e3 = e - kP3, nt = e3 >> 8, r = e3 & 255, lane = r >> 2, q = r & 3;
+            int n = lane & 15, g = lane >> 4, tap = 16 * nt + n, ch = 4 * g + q;
+            if (tap < 27) v = prm[kW3 + ch * 27 + tap];
+        }
+        pk[e] = f2bf(v);
+    }
+}
+
+// ------------------------------------------------------------------ forward
+// x [nbox][1000] FP32 (10^3, x fastest), y [nbox][512] FP32 (natural order).
+// idx (optional) maps workgroup q to input box idx[q]; outputs are written at
+// position q.  SAVE stores a1 and a2 (BF16, [nbox][16][512]) for training.
+template <bool SAVE>
+__global__ __launch_bounds__(256) void k_nn_fwd(const float *__restrict__ x, float *__restrict__ y,
+                                                const int32_t *__restrict__ idx,
+                                                const uint16_t *__restrict__ pk,
+                                                const float *__restrict__ prm,
+                                                uint16_t *__restrict__ a1o,
+                                                uint16_t *__restrict__ a2o) {
+    __shared__ __attribute__((aligned(16))) uint16_t xs[1008];
+    __shared__ __attribute__((aligned(16))) float R[27 * 512];  // A1 [1000][16] BF16, later Q [27][512]
+    __shared__ __attribute__((aligned(16))) uint16_t A2[512 * 16];
+    uint16_t *A1 = reinterpret_cast<uint16_t *>(R);
+    const int64_t q = blockIdx.x;
+    const int64_t src = idx ? (int64_t)idx[q] : q;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, row = lane & 15, g = lane >> 4;
+    const int o = lane & 15;
+
+    for (int e = t; e < 2000; e += 256) reinterpret_cast<uint4 *>(A1)[e] = make_uint4(0, 0, 0, 0);
+    const float *xb = x + src * 1000;
+    for (int e = t; e < 1000; e += 256) xs[e] = f2bf(xb[e]);
+    __syncthreads();
+
+    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    // ---- layer 1: K = 27 taps (padded to 32) of the input
+    {
+        const bf16x8 B = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(pk + kP1 + lane * 8));
+        int off[8];
+#pragma unroll
+        for (int qq = 0; qq < 8; qq++) {
+            int tp = 8 * g + qq;
+            off[qq] = tp < 27 ? tap_off(tp) : -1;
+        }
+        const float bias = prm[kB1 + o];
+        for (int m = w; m < 32; m += 4) {
+            int cell = 16 * m + row, i = cell & 7, j = (cell >> 3) & 7, k = cell >> 6;
+            int base = (k * 10 + j) * 10 + i;
+            uint32_t wv[4];
+#pragma unroll
+            for (int h = 0; h < 4; h++) {
+                uint32_t lo = off[2 * h] >= 0 ? xs[base + off[2 * h]] : 0u;
+                uint32_t hi = off[2 * h + 1] >= 0 ? xs[base + off[2 * h + 1]] : 0u;
+                wv[h] = lo | (hi << 16);
+            }
+            bf16x8 A = __builtin_bit_cast(bf16x8, make_uint4(wv[0], wv[1], wv[2], wv[3]));
+            f32x4 D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, zero, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                int c = 16 * m + 4 * g + r, ci = c & 7, cj = (c >> 3) & 7, ck = c >> 6;
+                uint16_t v = f2bf(relu(D[r] + bias));
+                A1[(((ck + 1) * 10 + cj + 1) * 10 + ci + 1) * 16 + o] = v;
+                if (SAVE) a1o[(q * 16 + o) * 512 + c] = v;
+            }
+        }
+    }
+    __syncthreads();
+    // ---- layer 2: K = 27 taps x 16 channels, two taps per MFMA
+    {
+        bf16x8 B[14];
+#pragma unroll
+        for (int p = 0; p < 14; p++)
+            B[p] = __builtin_bit_cast(bf16x8,
+                                      *reinterpret_cast<const uint4 *>(pk + kP2 + (p * 64 + lane) * 8));
+        const float bias = prm[kB2 + o];
+        const int hsel = g >> 1, cofs = 8 * (g & 1);
+        for (int m = w; m < 32; m += 4) {
+            int cell = 16 * m + row, i = cell & 7, j = (cell >> 3) & 7, k = cell >> 6;
+            int base = (k * 10 + j) * 10 + i;
+            f32x4 acc = zero;
+#pragma unroll
+            for (int p = 0; p < 14; p++) {
+                int tp = 2 * p + hsel;
+                uint4 av = make_uint4(0, 0, 0, 0);
+                if (tp < 27) {
+                    int off = hsel ? tap_off(2 * p + 1) : tap_off(2 * p);
+                    av = *reinterpret_cast<const uint4 *>(A1 + (base + off) * 16 + cofs);
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), B[p], acc,
+                                                              0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                int c = 16 * m + 4 * g + r;
+                uint16_t v = f2bf(relu(acc[r] + bias));
+                A2[c * 16 + o] = v;
+                if (SAVE) a2o[(q * 16 + o) * 512 + c] = v;
+            }
+        }
+    }
+    __syncthreads();  // A1 is dead from here on; R holds Q
+    // ---- layer 3: Q[tap][cell] = sum_c W3[c][tap] a2[c][cell]
+    {
+        float *Q = R;
+        s16x4 B3[2];
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++)
+            B3[nt] = *reinterpret_cast<const s16x4 *>(pk + kP3 + (nt * 64 + lane) * 4);
+        for (int m = w; m < 32; m += 4) {
+            int cell = 16 * m + row;
+            s16x4 A = *reinterpret_cast<const s16x4 *>(A2 + cell * 16 + 4 * g);
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++) {
+                f32x4 D = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B3[nt], zero, 0, 0, 0);
+                int tp = 16 * nt + o;
+                if (tp < 27) *reinterpret_cast<f32x4 *>(Q + tp * 512 + 16 * m + 4 * g) = D;
+            }
+        }
+    }
+    __syncthreads();
+    {
+        const float *Q = R;
+        const float b3 = prm[kB3];
+        for (int c = t; c < 512; c += 256) {
+            int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+            float s = b3;
+#pragma unroll
+            for (int tp = 0; tp < 27; tp++) {
+                int ii = i + tp % 3 - 1, jj = j + (tp / 3) % 3 - 1, kk = k + tp / 9 - 1;
+                if ((unsigned)ii < 8u && (unsigned)jj < 8u && (unsigned)kk < 8u)
+                    s += Q[tp * 512 + (kk * 8 + jj) * 8 + ii];
+            }
+            y[q * 512 + c] = s;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- backward
+// Loss = mean over boxes and cells of (y - target)^2; gy = 2 (y - target) / N.
+// Per box: gz2 = (transposed conv of gy with W3) * [a2 > 0] and
+// gz1 = (transposed conv of gz2 with W2) * [a1 > 0], with the BF16-rounded
+// weights the forward used.  Also the box's sum of squared errors.
+__global__ __launch_bounds__(256) void k_nn_bwd_act(const float *__restrict__ y,
+                                                    const float *__restrict__ tgt,
+                                                    const int32_t *__restrict__ idx,
+                                                    const uint16_t *__restrict__ a1o,
+                                                    const uint16_t *__restrict__ a2o,
+                                                    const float *__restrict__ prm, float scale2,
+                                                    float *__restrict__ gz2o, float *__restrict__ gz1o,
+                                                    double *__restrict__ lossp) {
+    __shared__ float gyp[1000];
+    __shared__ float W3s[432];
+    __shared__ __attribute__((aligned(16))) float W2s[27 * 16 * 16];  // [tap][o][i]
+    __shared__ float G2[16 * 1000];
+    __shared__ double S[4];
+    const int64_t q = blockIdx.x;
+    const int64_t src = idx ? (int64_t)idx[q] : q;
+    const int t = threadIdx.x;
+    for (int e = t; e < 1000; e += 256) gyp[e] = 0.0f;
+    for (int e = t; e < 16000; e += 256) G2[e] = 0.0f;
+    for (int e = t; e < 432; e += 256) W3s[e] = round_bf(prm[kW3 + e]);
+    for (int e = t; e < 6912; e += 256) {
+        int tp = e % 27, oi = e / 27, o = oi >> 4, i = oi & 15;  // prm index (o*16 + i)*27 + tp
+        W2s[(tp * 16 + o) * 16 + i] = round_bf(prm[kW2 + e]);
+    }
+    __syncthreads();
+    double ls = 0.0;
+    for (int c = t; c < 512; c += 256) {
+        float d = y[q * 512 + c] - tgt[src * 512 + c];
+        ls += (double)d * (double)d;
+        int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+        gyp[((k + 1) * 10 + j + 1) * 10 + i + 1] = scale2 * d;
+    }
+    double tot = block_sum256(ls, S);
+    if (t == 0) lossp[q] = tot;
+    __syncthreads();
+    for (int c = t; c < 512; c += 256) {
+        int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+        float acc[16];
+#pragma unroll
+        for (int a = 0; a < 16; a++) acc[a] = 0.0f;
+        for (int tp = 0; tp < 27; tp++) {
+            int di = tp % 3, dj = (tp / 3) % 3, dk = tp / 9;
+            float gv = gyp[((k - dk + 2) * 10 + j - dj + 2) * 10 + i - di + 2];
+#pragma unroll
+            for (int a = 0; a < 16; a++) acc[a] += W3s[a * 27 + tp] * gv;
+        }
+#pragma unroll
+        for (int a = 0; a < 16; a++) {
+            uint16_t bits = a2o[(q * 16 + a) * 512 + c];
+            float g2 = (bits & 0x7fff) ? acc[a] : 0.0f;
+            G2[a * 1000 + ((k + 1) * 10 + j + 1) * 10 + i + 1] = g2;
+            gz2o[(q * 16 + a) * 512 + c] = g2;
+        }
+    }
+    __syncthreads();
+    for (int c = t; c < 512; c += 256) {
+        int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+        float acc[16];
+#pragma unroll
+        for (int a = 0; a < 16; a++) acc[a] = 0.0f;
+        for (int tp = 0; tp < 27; tp++) {
+            int di = tp % 3, dj = (tp / 3) % 3, dk = tp / 9;
+            int sidx = ((k - dk + 2) * 10 + j - dj + 2) * 10 + i - di + 2;
+            for (int o = 0; o < 16; o++) {
+                float gv = G2[o * 1000 + sidx];
+                const float4 *wr = reinterpret_cast<const float4 *>(W2s + (tp * 16 + o) * 16);
+#pragma unroll
+                for (int v4 = 0; v4 < 4; v4++) {
+                    float4 wv = wr[v4];
+                    acc[4 * v4 + 0] += wv.x * gv;
+                    acc[4 * v4 + 1] += wv.y * gv;
+                    acc[4 * v4 + 2] += wv.z * gv;
+                    acc[4 * v4 + 3] += wv.w * gv;
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 16; a++) {
+            uint16_t bits = a1o[(q * 16 + a) * 512 + c];
+            gz1o[(q * 16 + a) * 512 + c] = (bits & 0x7fff) ? acc[a] : 0.0f;
+        }
+    }
+}
+
+// Weight gradients: block r sums over boxes r, r + gridDim.x, ... and writes
+// its partial gradient (parameter order) to part[r][kNnParams].
+__global__ __launch_bounds__(256) void k_nn_wgrad(const float *__restrict__ x,
+                                                  const float *__restrict__ y,
+                                                  const float *__restrict__ tgt,
+                                                  const int32_t *__restrict__ idx, int64_t nbox,
+                                                  float scale2, const uint16_t *__restrict__ a1o,
+                                                  const uint16_t *__restrict__ a2o,
+                                                  const float *__restrict__ gz2o,
+                                                  const float *__restrict__ gz1o,
+                                                  float *__restrict__ part) {
+    __shared__ uint16_t U[16 * 1000];  // a1 or a2, zero-padded 10^3 per channel
+    __shared__ float V[16 * 512];      // gz2 or gz1
+    __shared__ float X[1000];          // input (BF16-rounded) or gy
+    const int t = threadIdx.x;
+    const int o2 = t >> 4, c2 = t & 15;  // dW2 entry (o2, c2, all taps)
+    float acc2[27];
+#pragma unroll
+    for (int tp = 0; tp < 27; tp++) acc2[tp] = 0.0f;
+    float db2 = 0.0f, acc1[2] = {0.0f, 0.0f}, acc3[2] = {0.0f, 0.0f};
+    for (int64_t q = blockIdx.x; q < nbox; q += gridDim.x) {
+        const int64_t src = idx ? (int64_t)idx[q] : q;
+        // ---- dW2, db2
+        for (int e = t; e < 16000; e += 256) {
+            int ch = e / 1000, p = e - ch * 1000, pi = p % 10, pj = (p / 10) % 10, pk = p / 100;
+            uint16_t v = 0;
+            if (pi >= 1 && pi <= 8 && pj >= 1 && pj <= 8 && pk >= 1 && pk <= 8)
+                v = a1o[(q * 16 + ch) * 512 + ((pk - 1) * 8 + pj - 1) * 8 + pi - 1];
+            U[e] = v;
+        }
+        for (int e = t; e < 8192; e += 256) V[e] = gz2o[q * 8192 + e];
+        __syncthreads();
+        for (int c = 0; c < 512; c++) {
+            int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+            float gv = V[o2 * 512 + c];
+            int base = c2 * 1000 + (k * 10 + j) * 10 + i;
+#pragma unroll
+            for (int tp = 0; tp < 27; tp++) acc2[tp] += gv * bf2f(U[base + tap_off(tp)]);
+            db2 += gv;
+        }
+        __syncthreads();
+        // ---- dW1, db1
+        for (int e = t; e < 1000; e += 256) X[e] = round_bf(x[src * 1000 + e]);
+        for (int e = t; e < 8192; e += 256) V[e] = gz1o[q * 8192 + e];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            int p = t + 256 * s;
+            if (p < 432) {
+                int o = p / 27, tp = p % 27, off = tap_off(tp);
+                float a = 0.0f;
+                for (int c = 0; c < 512; c++) {
+                    int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+                    a += V[o * 512 + c] * X[(k * 10 + j) * 10 + i + off];
+                }
+                acc1[s] += a;
+            } else if (p < 448) {
+                float a = 0.0f;
+                for (int c = 0; c < 512; c++) a += V[(p - 432) * 512 + c];
+                acc1[s] += a;
+            }
+        }
+        __syncthreads();
+        // ---- dW3, db3
+        for (int e = t; e < 16000; e += 256) {
+            int ch = e / 1000, p = e - ch * 1000, pi = p % 10, pj = (p / 10) % 10, pk = p / 100;
+            uint16_t v = 0;
+            if (pi >= 1 && pi <= 8 && pj >= 1 && pj <= 8 && pk >= 1 && pk <= 8)
+                v = a2o[(q * 16 + ch) * 512 + ((pk - 1) * 8 + pj - 1) * 8 + pi - 1];
+            U[e] = v;
+        }
+        for (int c = t; c < 512; c += 256) X[c] = scale2 * (y[q * 512 + c] - tgt[src * 512 + c]);
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            int p = t + 256 * s;
+            if (p < 432) {
+                int ch = p / 27, tp = p % 27, off = tap_off(tp);
+                float a = 0.0f;
+                for (int c = 0; c < 512; c++) {
+                    int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+                    a += X[c] * bf2f(U[ch * 1000 + (k * 10 + j) * 10 + i + off]);
+                }
+                acc3[s] += a;
+            } else if (p == 432) {
+                float a = 0.0f;
+                for (int c = 0; c < 512; c++) a += X[c];
+                acc3[s] += a;
+            }
+        }
+        __syncthreads();
+    }
+    float *pr = part + (int64_t)blockIdx.x * kNnParams;
+#pragma unroll
+    for (int tp = 0; tp < 27; tp++) pr[kW2 + (o2 * 16 + c2) * 27 + tp] = acc2[tp];
+    if (c2 == 0) pr[kB2 + o2] = db2;
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        int p = t + 256 * s;
+        if (p < 432) {
+            pr[kW1 + p] = acc1[s];
+            pr[kW3 + p] = acc3[s];
+        } else if (p < 448) {
+            pr[kB1 + p - 432] = acc1[s];
+            if (p == 432) pr[kB3] = acc3[s];
+        }
+    }
+}
+
+// grad[p] = sum over blocks of part[block][p] (fixed order, FP64); block 0's
+// thread 0 also writes the mean squared error.
+__global__ __launch_bounds__(256) void k_nn_reduce(const float *__restrict__ part, int nblk,
+                                                   const double *__restrict__ lossp, int64_t nbox,
+                                                   float *__restrict__ grad, double *__restrict__ loss) {
+    int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < kNnParams) {
+        double s = 0.0;
+        for (int r = 0; r < nblk; r++) s += (double)part[(int64_t)r * kNnParams + p];
+        grad[p] = (float)s;
+    }
+    if (blockIdx.x == 0) {
+        __shared__ double S[4];
+        double v = 0.0;
+        for (int64_t b = threadIdx.x; b < nbox; b += 256) v += lossp[b];
+        double tot = block_sum256(v, S);
+        if (threadIdx.x == 0) *loss = tot / (512.0 * (double)nbox);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_nn_adam(float *__restrict__ p, float *__restrict__ m,
+                                                 float *__restrict__ v, const float *__restrict__ g,
+                                                 float lr, float b1, float b2, float eps, float bc1,
+                                                 float bc2) {
+    int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kNnParams) return;
+    float gg = g[e];
+    float mm = b1 * m[e] + (1.0f - b1) * gg;
+    float vv = b2 * v[e] + (1.0f - b2) * gg * gg;
+    m[e] = mm;
+    v[e] = vv;
+    p[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+}
+
+// ------------------------------------------------------- learned tree step
+// Network input of leaf position q: h^2 r on the box and on the face-ghost
+// layers taken from same-level leaf neighbours (0 elsewhere), divided by the
+// box's RMS of h^2 r (1 when that is 0).
+__global__ __launch_bounds__(256) void k_nn_gather(const float *__restrict__ r32,
+                                                   const int32_t *__restrict__ leaf,
+                                                   const int32_t *__restrict__ nbr,
+                                                   const int32_t *__restrict__ ijk4,
+                                                   const int32_t *__restrict__ isleaf, double len,
+                                                   float *__restrict__ x, float *__restrict__ scale) {
+    __shared__ float X[1000];
+    __shared__ double S[4];
+    const int64_t q = blockIdx.x;
+    const int64_t b = leaf[q];
+    const int t = threadIdx.x;
+    const int l = ijk4[b * 4 + 3];
+    const double h = len / (8.0 * (double)(1 << (l - 1)));
+    const float h2 = (float)(h * h);
+    for (int e = t; e < 1000; e += 256) X[e] = 0.0f;
+    __syncthreads();
+    double ss = 0.0;
+    for (int e = t; e < 512; e += 256) {
+        int n = cs_to_nat(e), i = n & 7, j = (n >> 3) & 7, k = n >> 6;
+        float v = h2 * r32[b * 512 + e];
+        X[((k + 1) * 10 + j + 1) * 10 + i + 1] = v;
+        ss += (double)v * (double)v;
+    }
+    for (int e = t; e < 384; e += 256) {
+        int d = e >> 6, wv = e & 63, u = wv & 7, vv = wv >> 3;
+        int nb = nbr[b * 6 + d];
+        if (nb >= 0 && isleaf[nb]) {
+            int a = d >> 1, side = d & 1, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+            int c[3], p[3];
+            c[t1] = u;
+            c[t2] = vv;
+            c[a] = side ? 0 : 7;
+            p[t1] = u + 1;
+            p[t2] = vv + 1;
+            p[a] = side ? 9 : 0;
+            X[(p[2] * 10 + p[1]) * 10 + p[0]] = h2 * r32[(int64_t)nb * 512 + cs_idx(c[0], c[1], c[2])];
+        }
+    }
+    double tot = block_sum256(ss, S);  // also orders the X writes before the reads below
+    float rms = (float)sqrt(tot / 512.0);
+    float sc = rms > 0.0f ? rms : 1.0f;
+    for (int e = t; e < 1000; e += 256) x[q * 1000 + e] = X[e] / sc;
+    if (t == 0) scale[q] = sc;
+}
+
+// e32 on leaf boxes <- scale * y (levels with level % 3 == mod3, or all when
+// mod3 < 0; zero on the other leaf boxes).
+__global__ __launch_bounds__(256) void k_nn_scatter(const float *__restrict__ y,
+                                                    const float *__restrict__ scale,
+                                                    const int32_t *__restrict__ leaf,
+                                                    const int32_t *__restrict__ ijk4, int mod3,
+                                                    float *__restrict__ e32) {
+    const int64_t q = blockIdx.x;
+    const int64_t b = leaf[q];
+    const int l = ijk4[b * 4 + 3];
+    const bool on = mod3 < 0 || l % 3 == mod3;
+    const float sc = scale[q];
+    for (int e = threadIdx.x; e < 512; e += 256)
+        e32[b * 512 + e] = on ? sc * y[q * 512 + cs_to_nat(e)] : 0.0f;
+}
+
+// Per leaf position, with j its level and Q_m the operator applied to the
+// correction of the levels = m (mod 3): the volume-weighted sums
+// <r, q_{j-1}>, <r, q_j>, <r, q_{j+1}> and the six products of the q's.
+__global__ __launch_bounds__(256) void k_nn_dots(const float *__restrict__ r32,
+                                                 const float *__restrict__ q3,
+                                                 const int32_t *__restrict__ leaf, int64_t nleaf,
+                                                 const int32_t *__restrict__ ijk4, double len,
+                                                 double *__restrict__ partial) {
+    __shared__ double S[4];
+    const int64_t q = blockIdx.x;
+    const int64_t b = leaf[q];
+    const int t = threadIdx.x;
+    const int l = ijk4[b * 4 + 3];
+    const double h = len / (8.0 * (double)(1 << (l - 1)));
+    const float *qa = q3 + (int64_t)((l + 2) % 3) * nleaf * 512 + q * 512;
+    const float *qc = q3 + (int64_t)(l % 3) * nleaf * 512 + q * 512;
+    const float *qn = q3 + (int64_t)((l + 1) % 3) * nleaf * 512 + q * 512;
+    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int e = t; e < 512; e += 256) {
+        double r = r32[b * 512 + e], a = qa[e], c = qc[e], n = qn[e];
+        s[0] += r * a;
+        s[1] += r * c;
+        s[2] += r * n;
+        s[3] += a * a;
+        s[4] += a * c;
+        s[5] += a * n;
+        s[6] += c * c;
+        s[7] += c * n;
+        s[8] += n * n;
+    }
+    const double vol = h * h * h;
+    for (int k = 0; k < 9; k++) {
+        double v = block_sum256(s[k], S);
+        if (t == 0) partial[q * 9 + k] = v * vol;
+    }
+}
+
+// phi += steps[tree][level] * (scale * y) on the leaf boxes (boxes whose
+// step is 0 are left untouched, also where the correction is not finite).
+__global__ __launch_bounds__(256) void k_nn_update(double *__restrict__ phi,
+                                                   const float *__restrict__ y,
+                                                   const float *__restrict__ scale,
+                                                   const int32_t *__restrict__ leaf,
+                                                   const int32_t *__restrict__ ijk4,
+                                                   const int32_t *__restrict__ tid,
+                                                   const double *__restrict__ steps, int stride) {
+    const int64_t q = blockIdx.x;
+    const int64_t b = leaf[q];
+    const int l = ijk4[b * 4 + 3];
+    const double st = steps[(int64_t)tid[b] * stride + l];
+    const float sc = scale[q];
+    if (st == 0.0) return;
+    for (int e = threadIdx.x; e < 512; e += 256) {
+        float c = sc * y[q * 512 + cs_to_nat(e)];
+        phi[b * 512 + e] += st * (double)c;
+    }
+}
+
+// Training target of leaf position q: (ref - phi) / scale in natural order,
+// ref in natural order [n][512].
+__global__ __launch_bounds__(256) void k_nn_targets(const double *__restrict__ phi,
+                                                    const double *__restrict__ ref,
+                                                    const float *__restrict__ scale,
+                                                    const int32_t *__restrict__ leaf,
+                                                    float *__restrict__ target) {
+    const int64_t q = blockIdx.x;
+    const int64_t b = leaf[q];
+    const double sc = scale[q];
+    for (int e = threadIdx.x; e < 512; e += 256) {
+        int n = cs_to_nat(e);
+        target[q * 512 + n] = (float)((ref[b * 512 + n] - phi[b * 512 + e]) / sc);
+    }
+}
+
+}  // namespace
+
+int64_t nn_train_layout(int64_t nbox, char *base, NnTrainWs *w) {
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t at = o;
+        o += (bytes + 255) & ~(int64_t)255;
+        return at;
+    };
+    int64_t oy = take(4 * 512 * nbox), oa1 = take(2 * 8192 * nbox), oa2 = take(2 * 8192 * nbox);
+    int64_t og2 = take(4 * 8192 * nbox), og1 = take(4 * 8192 * nbox), olp = take(8 * nbox);
+    int64_t opart = take(4 * (int64_t)kNnWgradBlocks * kNnParams), oloss = take(8);
+    if (base && w) {
+        w->y = (float *)(base + oy);
+        w->a1 = (uint16_t *)(base + oa1);
+        w->a2 = (uint16_t *)(base + oa2);
+        w->gz2 = (float *)(base + og2);
+        w->gz1 = (float *)(base + og1);
+        w->lossp = (double *)(base + olp);
+        w->part = (float *)(base + opart);
+        w->loss = (double *)(base + oloss);
+    }
+    return o;
+}
+
+void launch_nn_pack(const float *prm, uint16_t *pk, hipStream_t s) {
+    hipLaunchKernelGGL(k_nn_pack, dim3(1), dim3(256), 0, s, prm, pk);
+}
+
+void launch_nn_forward(const float *prm, const uint16_t *pk, int64_t nbox, const int32_t *idx,
+                       const float *x, float *y, uint16_t *a1, uint16_t *a2, hipStream_t s) {
+    if (nbox <= 0) return;
+    if (a1)
+        hipLaunchKernelGGL(k_nn_fwd<true>, dim3((unsigned)nbox), dim3(256), 0, s, x, y, idx, pk, prm, a1,
+                           a2);
+    else
+        hipLaunchKernelGGL(k_nn_fwd<false>, dim3((unsigned)nbox), dim3(256), 0, s, x, y, idx, pk, prm,
+                           a1, a2);
+}
+
+void launch_nn_backward(const float *prm, int64_t nbox, const int32_t *idx, const float *x,
+                        const float *target, const NnTrainWs &w, float *grad, hipStream_t s) {
+    if (nbox <= 0) return;
+    float scale2 = (float)(2.0 / (512.0 * (double)nbox));
+    hipLaunchKernelGGL(k_nn_bwd_act, dim3((unsigned)nbox), dim3(256), 0, s, w.y, target, idx, w.a1,
+                       w.a2, prm, scale2, w.gz2, w.gz1, w.lossp);
+    int nblk = (int)(nbox < kNnWgradBlocks ? nbox : kNnWgradBlocks);
+    hipLaunchKernelGGL(k_nn_wgrad, dim3((unsigned)nblk), dim3(256), 0, s, x, w.y, target, idx, nbox,
+                       scale2, w.a1, w.a2, w.gz2, w.gz1, w.part);
+    hipLaunchKernelGGL(k_nn_reduce, dim3((kNnParams + 255) / 256), dim3(256), 0, s, w.part, nblk,
+                       w.lossp, nbox, grad, w.loss);
+}
+
+void launch_nn_adam(float *prm, float *m, float *v, const float *g, float lr, float b1, float b2,
+                    float eps, float bc1, float bc2, hipStream_t s) {
+    hipLaunchKernelGGL(k_nn_adam, dim3((kNnParams + 255) / 256), dim3(256), 0, s, prm, m, v, g, lr, b1,
+                       b2, eps, bc1, bc2);
+}
+
+void launch_nn_gather(const float *r32, const int32_t *leaf, int64_t nleaf, const int32_t *nbr,
+                      const int32_t *ijk4, const int32_t *isleaf, double len, float *x, float *scale,
+                      hipStream_t s) {
+    if (nleaf <= 0) return;
+    hipLaunchKernelGGL(k_nn_gather, dim3((unsigned)nleaf), dim3(256), 0, s, r32, leaf, nbr, ijk4, isleaf,
+                       len, x, scale);
+}
+
+void launch_nn_scatter(const float *y, const float *scale, const int32_t *leaf, int64_t nleaf,
+                       const int32_t *ijk4, int mod3, float *e32, hipStream_t s) {
+    if (nleaf <= 0) return;
+    hipLaunchKernelGGL(k_nn_scatter, dim3((unsigned)nleaf), dim3(256), 0, s, y, scale, leaf, ijk4, mod3,
+                       e32);
+}
+
+void launch_nn_dots(const float *r32, const float *q3, const int32_t *leaf, int64_t nleaf,
+                    const int32_t *ijk4, double len, double *partial, hipStream_t s) {
+    if (nleaf <= 0) return;
+    hipLaunchKernelGGL(k_nn_dots, dim3((unsigned)nleaf), dim3(256), 0, s, r32, q3, leaf, nleaf, ijk4, len,
+                       partial);
+}
+
+void launch_nn_update(double *phi, const float *y, const float *scale, const int32_t *leaf,
+                      int64_t nleaf, const int32_t *ijk4, const int32_t *tid, const double *steps,
+                      int stride, hipStream_t s) {
+    if (nleaf <= 0) return;
+    hipLaunchKernelGGL(k_nn_update, dim3((unsigned)nleaf), dim3(256), 0, s, phi, y, scale, leaf, ijk4, tid,
+                       steps, stride);
+}
+
+void launch_nn_targets(const double *phi, const double *ref, const float *scale,
+                       const int32_t *leaf, int64_t nleaf, float *target, hipStream_t s) {
+    if (nleaf <= 0) return;
+    hipLaunchKernelGGL(k_nn_targets, dim3((unsigned)nleaf), dim3(256), 0, s, phi, ref, scale, leaf,
+                       target);
+}
+
+}  // namespace mg

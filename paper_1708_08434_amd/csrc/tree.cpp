@@ -274,6 +274,8 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.slots = take(8 * t->nslot);
     t->off.leaf_tree = take(4 * t->nleaf);
     t->off.tree_off = take(4 * (int64_t)(ntree + 1));
+    t->off.isleaf = take(4 * n);
+    t->off.tid = take(4 * n);
     t->off.eig = take(8 * (3 * 64 + 3 * 8));
     t->off.phi = take(8 * kCells * n);
     t->off.rhs = take(8 * kCells * n);

@@ -1,0 +1,291 @@
+"""GPU parity of the learned correction step (include/mg_nn.h) against the
+oracle (oracle/nn_oracle.py), through the C ABI.
+
+Tolerances.  Both sides round the input, weights and hidden activations to
+BF16 at the same points; the GPU accumulates in FP32 and the oracle in FP64,
+so an activation whose FP32 and FP64 values round to different BF16
+neighbours differs by one BF16 ulp (2^-8 relative).  Emulating the FP32
+accumulation on the CPU with the same rounding points gives output
+differences of at most 3e-5 relative L2 and 3e-4 of max|y| in max norm over
+three seeds; the forward bar is ten times that.  Gradients (FP32 on the GPU
+over up to 512 * nbox terms) and the step sizes (FP32 operator images, FP64
+sums) get 1e-3 relative.  Whole learned solves converge to the same discrete
+solution as the plain FP64 solve (relative residual <= 1e-8 on both)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import nn_oracle as N
+from paper_1708_08434_amd import mg as M
+from paper_1708_08434_amd import nn as NN
+from workloads import streamer_small, refine_boxes_explicit, uniform_boxes
+from workloads.octree import BoxList
+from tests import _geom as G
+
+pytestmark = pytest.mark.gpu
+
+FWD_RELL2, FWD_MAX = 5e-4, 5e-3
+GRAD_REL = 1e-3
+STEP_REL = 1e-3
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rand_params(seed, scale=1.0):
+    rng = np.random.default_rng(seed + 1)
+    W1, b1, W2, b2, W3, b3 = N.unpack(N.init_params(seed) * scale)
+    return N.pack(W1, rng.standard_normal(16) * 0.1, W2, rng.standard_normal(16) * 0.1, W3,
+                  rng.standard_normal(1) * 0.1).astype(np.float32)
+
+
+def rand_x(seed, B):
+    return np.random.default_rng(seed).standard_normal((B, 10, 10, 10)).astype(np.float32)
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("nbox", [1, 37])
+def test_forward_parity(nbox):
+    say("forward parity nbox", nbox)
+    p = rand_params(3)
+    x = rand_x(4, nbox)
+    net = NN.Net(p)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+    ref, _ = N.forward(p.astype(np.float64), x.astype(np.float64))
+    assert rel_l2(y, ref) <= FWD_RELL2
+    assert np.abs(y - ref).max() <= FWD_MAX * np.abs(ref).max()
+
+
+def test_forward_special_cases():
+    say("forward special cases")
+    # zero weights: the output is b3 everywhere, exactly
+    p = np.zeros(N.N_PARAMS, dtype=np.float32)
+    p[-1] = 0.375
+    net = NN.Net(p)
+    y = net.forward(torch.from_numpy(rand_x(5, 3)).cuda()).cpu().numpy()
+    assert np.all(y == np.float32(0.375))
+    # zero input: only the biases drive the network (exactly representable)
+    p = rand_params(6)
+    net.set_params(p)
+    y = net.forward(torch.zeros((2, 10, 10, 10)).cuda()).cpu().numpy().astype(np.float64)
+    ref, _ = N.forward(p.astype(np.float64), np.zeros((2, 10, 10, 10)))
+    assert rel_l2(y, ref) <= FWD_RELL2
+    assert np.array_equal(y[0], y[1])
+    # parameters round-trip through the device
+    assert np.array_equal(net.get_params(), p)
+
+
+def segments():
+    return [("W1", 0, N.N_W1), ("b1", N.N_W1, 16), ("W2", N.N_W1 + 16, N.N_W2),
+            ("b2", N.N_W1 + 16 + N.N_W2, 16), ("W3", N.N_W1 + 32 + N.N_W2, N.N_W3),
+            ("b3", N.N_PARAMS - 1, 1)]
+
+
+@pytest.mark.parametrize("nbox", [1, 5])
+def test_gradient_parity(nbox):
+    say("gradient parity nbox", nbox)
+    p = rand_params(7)
+    x = rand_x(8, nbox)
+    tgt = np.random.default_rng(9).standard_normal((nbox, 8, 8, 8)).astype(np.float32)
+    net = NN.Net(p)
+    loss = net.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda())
+    g = net.get_grad().astype(np.float64)
+    L, ref = N.gradients(p.astype(np.float64), x.astype(np.float64), tgt.astype(np.float64))
+    assert abs(loss - L) <= 1e-4 * L
+    for name, lo, n in segments():
+        e = rel_l2(g[lo:lo + n], ref[lo:lo + n])
+        say("  ", name, "rel", e)
+        assert e <= GRAD_REL, (name, e)
+
+
+def test_gradient_with_index_equals_gathered_batch():
+    say("gradient index")
+    p = rand_params(10)
+    x = rand_x(11, 12)
+    tgt = np.random.default_rng(12).standard_normal((12, 8, 8, 8)).astype(np.float32)
+    idx = np.array([7, 2, 11, 0, 5], dtype=np.int32)
+    net = NN.Net(p)
+    l1 = net.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda(),
+                      idx=torch.from_numpy(idx).cuda())
+    g1 = net.get_grad()
+    l2 = net.gradient(torch.from_numpy(x[idx]).cuda(), torch.from_numpy(tgt[idx]).cuda())
+    g2 = net.get_grad()
+    assert l1 == l2
+    assert np.array_equal(g1, g2)
+
+
+def test_adam_parity():
+    say("adam parity")
+    p = rand_params(13)
+    net = NN.Net(p)
+    po, m, v = p.astype(np.float64), np.zeros(N.N_PARAMS), np.zeros(N.N_PARAMS)
+    lr = 1e-3
+    for k in range(1, 3):
+        x = rand_x(20 + k, 3)
+        tgt = np.random.default_rng(30 + k).standard_normal((3, 8, 8, 8)).astype(np.float32)
+        net.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda(), want_loss=False)
+        net.adam(lr)
+        _, go = N.gradients(po, x.astype(np.float64), tgt.astype(np.float64))
+        po, m, v = N.adam_step(po, go, m, v, k, lr=lr)
+    pg = net.get_params().astype(np.float64)
+    upd_g, upd_o = pg - p, po - p
+    assert rel_l2(upd_g, upd_o) <= 1e-2
+    assert np.abs(upd_g - upd_o).max() <= 0.2 * lr
+
+
+# ---------------------------------------------------------------- tree side
+
+def amr_tree():
+    return refine_boxes_explicit(2, [(2, 0, 0, 0), (3, 1, 1, 1), (3, 0, 1, 0), (2, 1, 1, 1)])
+
+
+def blob_rhs(o):
+    x, y, z, _ = G.cell_centres(o.index(O.IDX_LEVEL), o.index(O.IDX_IJK))
+    return (np.exp(-((x - 0.3) ** 2 + (y - 0.3) ** 2 + (z - 0.35) ** 2) / 0.01) * 80
+            - np.exp(-((x - 0.65) ** 2 + (y - 0.6) ** 2 + (z - 0.6) ** 2) / 0.02) * 30)
+
+
+def tree_pair(bl, bc_type=(0, 0, 1, 1, 0, 0), bc_val=(0.0, 0.0, 0.0, 0.0, 0.0, 1.0)):
+    g = M.Tree(bl.level, bl.ijk, bl.tree, bc_type=bc_type, bc_val=bc_val)
+    o = O.OracleTree(bl.level, bl.ijk, bl.tree, (0, 0, 0), 1.0, bc_type, bc_val)
+    rhs = blob_rhs(o)
+    g.set_field(M.MG_FIELD_RHS, rhs)
+    o.set_field(O.RHS, rhs)
+    return g, o
+
+
+def test_inputs_and_targets_parity():
+    say("inputs parity")
+    g, o = tree_pair(amr_tree())
+    o.fmg_solve(tol=1e30)
+    phi = o.get_field(O.PHI)
+    g.set_field(M.MG_FIELD_PHI, phi)
+    L = NN.Learned(g)
+    x, s = L.inputs()
+    r = N.residual_leaf(o, phi)
+    X, S = N.gather_inputs(r, o.index(O.IDX_LEVEL), o.index(O.IDX_NBR), o.leaf_mask(), 1.0)
+    assert rel_l2(s.cpu().numpy().astype(np.float64), S) <= 1e-6
+    xg = x.cpu().numpy().astype(np.float64)
+    assert np.abs(xg - X).max() <= 1e-5 * np.abs(X).max()
+    # structural zeros: block edges and corners, ghosts without a same-level leaf
+    lv, nbr, leaf = o.index(O.IDX_LEVEL), o.index(O.IDX_NBR), o.leaf_mask()
+    for q, b in enumerate(np.nonzero(leaf)[0]):
+        live = np.zeros((10, 10, 10), dtype=bool)
+        live[1:9, 1:9, 1:9] = True
+        for fc, dst, _ in N.face_ghost_layers():
+            if nbr[b, fc] >= 0 and leaf[nbr[b, fc]]:
+                live[dst] = True
+        assert np.all(xg[q][~live] == 0.0)
+    ref = phi + 0.01 * np.random.default_rng(3).standard_normal(phi.shape)
+    t = L.targets(torch.from_numpy(ref).cuda(), s).cpu().numpy().astype(np.float64)
+    want = ((ref - phi)[o.leaf_mask()]) / S[:, None, None, None]
+    assert np.abs(t - want).max() <= 1e-6 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("forest", [False, True])
+def test_learned_step_parity(forest):
+    say("learned step parity forest", forest)
+    bl = amr_tree()
+    if forest:
+        bl = BoxList.concat([bl, refine_boxes_explicit(2, [(2, 1, 0, 1)], tree=1)])
+    g, o = tree_pair(bl)
+    o.fmg_solve(tol=1e30)
+    o.vcycles(1, tol=0.0)
+    phi = o.get_field(O.PHI)
+    g.set_field(M.MG_FIELD_PHI, phi)
+    p = rand_params(14, scale=0.5)
+    L = NN.Learned(g)
+    steps = L.step(NN.Net(p))
+    out = N.learned_step(o, p.astype(np.float64))
+    say("   steps gpu", steps[:, 1:], "oracle", out["s"][:, 1:])
+    lv = o.index(O.IDX_LEVEL)
+    leaf = o.leaf_mask()
+    for tr in range(o.ntree):
+        for l in np.unique(lv[leaf]):
+            a, b = steps[tr, l], out["s"][tr, l]
+            assert abs(a - b) <= STEP_REL * max(abs(b), 1e-3 * np.abs(out["s"]).max()), (tr, l, a, b)
+    dphi = g.get_field(M.MG_FIELD_PHI)[leaf] - o.get_field(O.PHI)[leaf]
+    upd = (o.get_field(O.PHI) - phi)[leaf]
+    assert np.abs(dphi).max() <= STEP_REL * np.abs(upd).max()
+    assert np.abs(upd).max() > 0
+
+
+def test_learned_solve_zero_network_falls_back_to_plain():
+    """Zero weights give a zero correction: the step is rejected at the
+    first cycle and the solve is bit-identical to the plain FP64 solve."""
+    say("zero network fallback")
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    plain = g.fmg_solve()
+    phi_plain = g.get_field(M.MG_FIELD_PHI)
+    L = NN.Learned(g)
+    res = L.solve(NN.Net(np.zeros(N.N_PARAMS, dtype=np.float32)))
+    assert res["accepted"] == 0 and res["fallback_cycle"] == 1
+    assert res["n_vcycles"] == plain["n_vcycles"]
+    assert np.array_equal(g.get_field(M.MG_FIELD_PHI), phi_plain)
+
+
+def test_learned_solve_nan_weights_fall_back():
+    say("nan network fallback")
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    plain = g.fmg_solve()
+    phi_plain = g.get_field(M.MG_FIELD_PHI)
+    p = rand_params(15)
+    p[100] = np.nan
+    res = NN.Learned(g).solve(NN.Net(p))
+    assert res["accepted"] == 0 and res["fallback_cycle"] == 1
+    assert res["n_vcycles"] == plain["n_vcycles"] and res["rel"] <= 1e-8
+    assert np.array_equal(g.get_field(M.MG_FIELD_PHI), phi_plain)
+
+
+def test_learned_solve_rejects_mixed_precision():
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    L = NN.Learned(g)
+    with pytest.raises(M.MGError) as e:
+        L.solve(NN.Net(), precision=M.MG_MIXED)
+    assert e.value.name == "EINVAL"
+
+
+def test_learned_solve_matches_oracle():
+    """Random (untrained) weights on a small AMR problem: both sides take the
+    same accept / fallback decisions and converge to the same solution."""
+    say("learned solve vs oracle")
+    g, o = tree_pair(amr_tree())
+    p = rand_params(16, scale=0.3)
+    res = NN.Learned(g).solve(NN.Net(p))
+    ref = N.learned_solve(o, p.astype(np.float64))
+    say("   gpu", res["n_vcycles"], res["accepted"], res["fallback_cycle"],
+        "oracle", ref["n_vcycles"], ref["accepted"], ref["fallback"])
+    assert res["rel"] <= 1e-8 and ref["rel"] <= 1e-8
+    assert abs(res["n_vcycles"] - ref["n_vcycles"]) <= 1
+    assert abs(res["accepted"] - ref["accepted"]) <= 1
+    leaf = o.leaf_mask()
+    a, b = g.get_field(M.MG_FIELD_PHI)[leaf], o.get_field(O.PHI)[leaf]
+    assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max()
+
+
+def test_training_lowers_the_loss_and_agrees_with_oracle():
+    say("training")
+    torch.manual_seed(0)
+    g, o = tree_pair(amr_tree())
+    x, t = NN.training_pairs(g, states=(0, 1))
+    nl = int(g.info.n_leaf_boxes)
+    assert x.shape == (2 * nl, 10, 10, 10) and t.shape == (2 * nl, 8, 8, 8)
+    net = NN.Net(N.init_params(17).astype(np.float32))
+    losses = NN.train(net, x, t, steps=60, batch=min(64, 2 * nl), lr=2e-3, seed=1, log_every=59)
+    say("   losses", losses)
+    assert losses[-1][1] < losses[0][1]
+    # the GPU loss over all pairs agrees with the oracle's for the trained weights
+    p = net.get_params().astype(np.float64)
+    lg = net.gradient(x, t)
+    lo = N.loss(p, x.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64))
+    assert abs(lg - lo) <= 1e-3 * lo

@@ -1,6 +1,7 @@
 """Host-side checks of libmg.so that need no GPU: symbol exports, the tree
 builder's tables (bit-exact against the oracle and against a brute-force
 search), and input validation."""
+import ctypes
 import os
 import re
 
@@ -9,6 +10,7 @@ import pytest
 
 import oracle as O
 from paper_1708_08434_amd import mg as M
+from paper_1708_08434_amd import nn as NN
 from workloads import uniform_boxes, refine_boxes_explicit, streamer_small
 from workloads.octree import BoxList
 from tests.test_oracle_pins import amr_tree, brute_tables
@@ -17,18 +19,43 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "mg.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mg_[a-z_]+)\s*\(", src)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in sorted(os.listdir(inc)):
+        if fn.endswith(".h"):
+            src = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, fn)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(mg_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     L = M.lib()
     names = declared_functions()
-    assert len(names) >= 13
+    assert len(names) >= 28
     for name in names:
         assert hasattr(L, name), name
-    assert set(M.EXPORTS) <= set(names)
+    assert set(M.EXPORTS) | set(NN.EXPORTS) <= set(names)
+    assert set(NN.EXPORTS) - set(M.EXPORTS) >= {"mg_learned_solve", "mg_nn_forward"}
+
+
+def test_learned_host_side_sizes_and_errors():
+    """Sizes and argument checks of the learned-step ABI that need no GPU."""
+    L = NN.lib()
+    assert NN.mg_nn_state_bytes() >= 4 * 4 * NN.MG_NN_PARAMS + 2 * 8192
+    assert NN.mg_nn_train_bytes(10) > NN.mg_nn_train_bytes(1) > 0
+    bl = uniform_boxes(2)
+    h = M.mg_tree_create(M.make_domain(), bl.level, bl.ijk)
+    try:
+        need = NN.mg_learned_bytes(h)
+        assert need >= 8 * (1000 + 512 + 3 * 512) * 4
+        # unbound tree / null network are rejected before any device work
+        rc = L.mg_learned_step(h, None, None, 0, None)
+        assert rc == M.MG_ESTATE
+    finally:
+        M.mg_tree_destroy(h)
+    out = ctypes.c_void_p()
+    assert L.mg_nn_create(ctypes.byref(out), None, 0, None) == M.MG_EINVAL
+    assert L.mg_nn_create(ctypes.byref(out), ctypes.c_void_p(256), 16, None) == M.MG_ENOMEM
 
 
 def forest():
