@@ -9,7 +9,8 @@
 namespace mg {
 
 constexpr int kNnParams = 7809;   // 16*27 + 16 + 16*16*27 + 16 + 16*27 + 1
-constexpr int kNnPacked = 8192;   // BF16 MFMA operand fragments of the weights
+constexpr int kNnPacked = 8704;   // BF16 MFMA operand fragments of the weights
+constexpr int kNnFwdBlocks = 768; // persistent forward workgroups (3 per CU)
 constexpr int kNnWgradBlocks = 512;
 
 // Per-box training buffers (the caller's workspace), see nn_train_layout.

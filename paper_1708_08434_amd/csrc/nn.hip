@@ -8,13 +8,12 @@
 // order W1[16][27], b1[16], W2[16 out][16 in][27], b2[16], W3[16][27], b3,
 // with tap t = (dk*3 + dj)*3 + di.
 //
-// Forward: one workgroup (4 waves) per box; everything stays in LDS.
+// Forward: a box's activations stay in LDS (one box at a time per workgroup).
 //  * layer 1 is an implicit GEMM [16 cells x 32 taps (27 used)] x [32 x 16
 //    channels]: one 16x16x32 BF16 MFMA per 16-cell tile;
-//  * layer 2 is an implicit GEMM with K = 27 taps x 16 channels, taken as 14
-//    16x16x32 MFMAs (two taps per instruction, the 28th tap zero) per tile;
-//    the A operand of a lane is 8 consecutive channels of one shifted cell,
-//    one 16-byte LDS read, from activations stored [padded cell][channel];
+//  * layer 2 is an implicit GEMM with K = 27 taps x 16 channels, taken as 15
+//    16x16x32 MFMAs per tile (two kernel rows of 16 channels per
+//    instruction); activations are stored [padded cell][channel];
 //  * layer 3 first forms Q[tap][cell] = sum_c W3[c][tap] a2[c][cell] with
 //    16x16x16 MFMAs (N = taps), then y[cell] = b3 + sum_tap Q[tap][cell+tap-1],
 //    which turns the 16->1 convolution into a dense GEMM plus a 27-term sum.
@@ -33,7 +32,7 @@ typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kW1 = 0, kB1 = 432, kW2 = 448, kB2 = 7360, kW3 = 7376, kB3 = 7808;
-constexpr int kP1 = 0, kP2 = 512, kP3 = 7680;  // offsets in the packed fragments
+constexpr int kP1 = 0, kP2 = 512, kP3 = 8192;  // offsets in the packed fragments
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -79,9 +78,11 @@ __global__ __launch_bounds__(256) void k_nn_pack(const float *__restrict__ prm, 
             int lane = e >> 3, q = e & 7, o = lane & 15, g = lane >> 4, t = 8 * g + q;
             if (t < 27) v = prm[kW1 + o * 27 + t];
         } else if (e < kP3) {
-            int e2 = e - kP2, p = e2 >> 9, r = e2 & 511, lane = r >> 3, q = r & 7;
-            int o = lane & 15, g = lane >> 4, tap = 2 * p + (g >> 1), ch = 8 * (g & 1) + q;
-            if (tap < 27) v = prm[kW2 + (o * 16 + ch) * 27 + tap];
+            // fragment f = 3 p + di: K groups 0-1 kernel row 2p, groups 2-3 row 2p+1
+            int e2 = e - kP2, f = e2 >> 9, r = e2 & 511, lane = r >> 3, q = r & 7;
+            int p = f / 3, di = f % 3, o = lane & 15, g = lane >> 4, ch = 8 * (g & 1) + q;
+            int krow = g < 2 ? 2 * p : 2 * p + 1;
+            if (krow < 9) v = prm[kW2 + (o * 16 + ch) * 27 + krow * 3 + di];
         } else {
             int e3 = e - kP3, nt = e3 >> 8, r = e3 & 255, lane = r >> 2, q = r & 3;
             int n = lane & 15, g = lane >> 4, tap = 16 * nt + n, ch = 4 * g + q;
@@ -93,128 +94,206 @@ __global__ __launch_bounds__(256) void k_nn_pack(const float *__restrict__ prm, 
 
 // ------------------------------------------------------------------ forward
 // x [nbox][1000] FP32 (10^3, x fastest), y [nbox][512] FP32 (natural order).
-// idx (optional) maps workgroup q to input box idx[q]; outputs are written at
-// position q.  SAVE stores a1 and a2 (BF16, [nbox][16][512]) for training.
+// idx (optional) maps output position q to input box idx[q].  SAVE stores a1
+// and a2 (BF16, [nbox][16][512]) for training.
+//
+// Persistent workgroups of 4 waves: the weight fragments stay in registers
+// while a workgroup walks over boxes q = blockIdx.x, + gridDim.x, ..., and
+// each thread prefetches its part of the next box's input during the current
+// box.  Tiles are 16 consecutive cells (two x-rows of 8), one MFMA row each.
+//
+// Layer 2 reads one 16-byte LDS fragment per lane for a pair of (dj, dk)
+// kernel rows (lanes of K groups 0-1 the first row, 2-3 the second) at the
+// centre column di = 1; the di = 0 and di = 2 operands are the same
+// fragment moved one lane down or up inside each 16-lane DPP row, zero
+// across the ends of the 8-cell x-rows (where the zero padding of the "same"
+// convolution lies).  The zeroing is applied to the moving values before
+// the move, and the moved values feed the MFMA directly: a select placed
+// after the move gave wrong values on gfx950.  5 loads and 15 MFMAs per
+// tile cover the 27 taps.
+// DPP row shifts inside rows of 16 lanes (0 where the source lane is outside
+// the row): control 0x111 (row_shr:1) hands lane l the value of lane l-1,
+// 0x101 (row_shl:1) the value of lane l+1 (checked on gfx950).
+__device__ __forceinline__ uint32_t dpp_from_prev(uint32_t v) {  // lane l gets lane l-1
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint32_t dpp_from_next(uint32_t v) {  // lane l gets lane l+1
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x101, 0xf, 0xf, true);
+}
+
+constexpr int kFwdThreads = 256;  // 4 waves; 3 workgroups per CU
+
 template <bool SAVE>
-__global__ __launch_bounds__(256) void k_nn_fwd(const float *__restrict__ x, float *__restrict__ y,
-                                                const int32_t *__restrict__ idx,
-                                                const uint16_t *__restrict__ pk,
-                                                const float *__restrict__ prm,
-                                                uint16_t *__restrict__ a1o,
-                                                uint16_t *__restrict__ a2o) {
+__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_nn_fwd(const float *__restrict__ x, float *__restrict__ y,
+                                                        const int32_t *__restrict__ idx, int64_t nbox,
+                                                        const uint16_t *__restrict__ pk,
+                                                        const float *__restrict__ prm,
+                                                        uint16_t *__restrict__ a1o,
+                                                        uint16_t *__restrict__ a2o) {
     __shared__ __attribute__((aligned(16))) uint16_t xs[1008];
-    __shared__ __attribute__((aligned(16))) float R[27 * 512];  // A1 [1000][16] BF16, later Q [27][512]
+    // A1 [1000][16] BF16 (32000 bytes), later one half of Q, [16][512] FP32 (32768 bytes)
+    __shared__ __attribute__((aligned(16))) uint4 R[2048];
     __shared__ __attribute__((aligned(16))) uint16_t A2[512 * 16];
     uint16_t *A1 = reinterpret_cast<uint16_t *>(R);
-    const int64_t q = blockIdx.x;
-    const int64_t src = idx ? (int64_t)idx[q] : q;
+    float *Q = reinterpret_cast<float *>(R);
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, row = lane & 15, g = lane >> 4;
     const int o = lane & 15;
-
-    for (int e = t; e < 2000; e += 256) reinterpret_cast<uint4 *>(A1)[e] = make_uint4(0, 0, 0, 0);
-    const float *xb = x + src * 1000;
-    for (int e = t; e < 1000; e += 256) xs[e] = f2bf(xb[e]);
-    __syncthreads();
-
     const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-    // ---- layer 1: K = 27 taps (padded to 32) of the input
-    {
-        const bf16x8 B = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(pk + kP1 + lane * 8));
-        int off[8];
+
+    // ---- weights, once per workgroup
+    const bf16x8 B1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(pk + kP1 + lane * 8));
+    bf16x8 B2[15];
 #pragma unroll
-        for (int qq = 0; qq < 8; qq++) {
-            int tp = 8 * g + qq;
-            off[qq] = tp < 27 ? tap_off(tp) : -1;
+    for (int f = 0; f < 15; f++)
+        B2[f] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(pk + kP2 + (f * 64 + lane) * 8));
+    s16x4 B3[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; nt++) B3[nt] = *reinterpret_cast<const s16x4 *>(pk + kP3 + (nt * 64 + lane) * 4);
+    const float bias1 = prm[kB1 + o], bias2 = prm[kB2 + o], b3 = prm[kB3];
+    int off1[8];  // layer-1 taps of this lane's K group (-1: padding tap 27-31)
+#pragma unroll
+    for (int qq = 0; qq < 8; qq++) {
+        int tp = 8 * g + qq;
+        off1[qq] = tp < 27 ? tap_off(tp) : -1;
+    }
+    int64_t q = blockIdx.x;
+    float xn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (q < nbox) {
+        const float *xb = x + (idx ? (int64_t)idx[q] : q) * 1000;
+#pragma unroll
+        for (int h = 0; h < 4; h++)
+            if (t + 256 * h < 1000) xn[h] = xb[t + 256 * h];
+    }
+    for (; q < nbox; q += gridDim.x) {
+        __syncthreads();  // the previous box is done with every LDS buffer
+        // zero A1 (its padding must be 0; Q of the previous box overwrote it)
+        for (int e = t; e < 2000; e += kFwdThreads) R[e] = make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < 4; h++)
+            if (t + 256 * h < 1000) xs[t + 256 * h] = f2bf(xn[h]);
+        const int64_t qn = q + gridDim.x;
+        if (qn < nbox) {
+            const float *xb = x + (idx ? (int64_t)idx[qn] : qn) * 1000;
+#pragma unroll
+            for (int h = 0; h < 4; h++)
+                if (t + 256 * h < 1000) xn[h] = xb[t + 256 * h];
         }
-        const float bias = prm[kB1 + o];
-        for (int m = w; m < 32; m += 4) {
+        __syncthreads();
+        // ---- layer 1: K = 27 taps (padded to 32) of the input
+#pragma unroll 1
+        for (int mm = 0; mm < 8; mm++) {
+            const int m = w + 4 * mm;
             int cell = 16 * m + row, i = cell & 7, j = (cell >> 3) & 7, k = cell >> 6;
             int base = (k * 10 + j) * 10 + i;
             uint32_t wv[4];
 #pragma unroll
             for (int h = 0; h < 4; h++) {
-                uint32_t lo = off[2 * h] >= 0 ? xs[base + off[2 * h]] : 0u;
-                uint32_t hi = off[2 * h + 1] >= 0 ? xs[base + off[2 * h + 1]] : 0u;
+                uint32_t lo = off1[2 * h] >= 0 ? xs[base + off1[2 * h]] : 0u;
+                uint32_t hi = off1[2 * h + 1] >= 0 ? xs[base + off1[2 * h + 1]] : 0u;
                 wv[h] = lo | (hi << 16);
             }
             bf16x8 A = __builtin_bit_cast(bf16x8, make_uint4(wv[0], wv[1], wv[2], wv[3]));
-            f32x4 D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, zero, 0, 0, 0);
+            f32x4 D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B1, zero, 0, 0, 0);
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                int c = 16 * m + 4 * g + r, ci = c & 7, cj = (c >> 3) & 7, ck = c >> 6;
-                uint16_t v = f2bf(relu(D[r] + bias));
-                A1[(((ck + 1) * 10 + cj + 1) * 10 + ci + 1) * 16 + o] = v;
+                int c = 16 * m + 4 * g + r, pi = c & 7, pj = (c >> 3) & 7, pk3 = c >> 6;
+                uint16_t v = f2bf(relu(D[r] + bias1));
+                A1[(((pk3 + 1) * 10 + pj + 1) * 10 + pi + 1) * 16 + o] = v;
                 if (SAVE) a1o[(q * 16 + o) * 512 + c] = v;
             }
         }
-    }
-    __syncthreads();
-    // ---- layer 2: K = 27 taps x 16 channels, two taps per MFMA
-    {
-        bf16x8 B[14];
+        __syncthreads();
+        // ---- layer 2: 9 kernel rows in 5 pairs, 3 x-shifts each
+        {
+            // zero the values that must not cross an x-row end before they
+            // move: di = 0 takes lane l-1 (its i = 7 lanes masked), di = 2
+            // takes lane l+1 (its i = 0 lanes masked); lanes 0 and 15 of a
+            // DPP row receive 0 from the move itself
+            const uint32_t keep_l = (row & 7) == 7 ? 0u : ~0u, keep_r = (row & 7) == 0 ? 0u : ~0u;
+#pragma unroll 1
+            for (int mm = 0; mm < 8; mm++) {
+                const int m = w + 4 * mm;
+                int cell = 16 * m + row, i = cell & 7, j = (cell >> 3) & 7, k = cell >> 6;
+                const int base = (k * 10 + j) * 10 + i + 1;  // centre column di = 1
+                f32x4 acc = zero;
 #pragma unroll
-        for (int p = 0; p < 14; p++)
-            B[p] = __builtin_bit_cast(bf16x8,
-                                      *reinterpret_cast<const uint4 *>(pk + kP2 + (p * 64 + lane) * 8));
-        const float bias = prm[kB2 + o];
-        const int hsel = g >> 1, cofs = 8 * (g & 1);
-        for (int m = w; m < 32; m += 4) {
-            int cell = 16 * m + row, i = cell & 7, j = (cell >> 3) & 7, k = cell >> 6;
-            int base = (k * 10 + j) * 10 + i;
-            f32x4 acc = zero;
-#pragma unroll
-            for (int p = 0; p < 14; p++) {
-                int tp = 2 * p + hsel;
-                uint4 av = make_uint4(0, 0, 0, 0);
-                if (tp < 27) {
-                    int off = hsel ? tap_off(2 * p + 1) : tap_off(2 * p);
-                    av = *reinterpret_cast<const uint4 *>(A1 + (base + off) * 16 + cofs);
+                for (int p = 0; p < 5; p++) {
+                    const int ra = 2 * p, rb = 2 * p + 1;  // kernel row = dk*3 + dj
+                    const int offa = (ra / 3) * 100 + (ra % 3) * 10;
+                    const int offb = rb < 9 ? (rb / 3) * 100 + (rb % 3) * 10 : 0;
+                    uint4 F = make_uint4(0, 0, 0, 0);  // the tenth kernel row does not exist
+                    if (g < 2 || rb < 9)
+                        F = *reinterpret_cast<const uint4 *>(A1 + (base + (g < 2 ? offa : offb)) * 16 +
+                                                             8 * (g & 1));
+                    uint4 L, Rr;
+                    L.x = dpp_from_prev(F.x & keep_l);
+                    L.y = dpp_from_prev(F.y & keep_l);
+                    L.z = dpp_from_prev(F.z & keep_l);
+                    L.w = dpp_from_prev(F.w & keep_l);
+                    Rr.x = dpp_from_next(F.x & keep_r);
+                    Rr.y = dpp_from_next(F.y & keep_r);
+                    Rr.z = dpp_from_next(F.z & keep_r);
+                    Rr.w = dpp_from_next(F.w & keep_r);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, L), B2[3 * p + 0],
+                                                                  acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, F), B2[3 * p + 1],
+                                                                  acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Rr), B2[3 * p + 2],
+                                                                  acc, 0, 0, 0);
                 }
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), B[p], acc,
-                                                              0, 0, 0);
-            }
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                int c = 16 * m + 4 * g + r;
-                uint16_t v = f2bf(relu(acc[r] + bias));
-                A2[c * 16 + o] = v;
-                if (SAVE) a2o[(q * 16 + o) * 512 + c] = v;
+                for (int r = 0; r < 4; r++) {
+                    int c = 16 * m + 4 * g + r;
+                    uint16_t v = f2bf(relu(acc[r] + bias2));
+                    A2[c * 16 + o] = v;
+                    if (SAVE) a2o[(q * 16 + o) * 512 + c] = v;
+                }
             }
         }
-    }
-    __syncthreads();  // A1 is dead from here on; R holds Q
-    // ---- layer 3: Q[tap][cell] = sum_c W3[c][tap] a2[c][cell]
-    {
-        float *Q = R;
-        s16x4 B3[2];
-#pragma unroll
-        for (int nt = 0; nt < 2; nt++)
-            B3[nt] = *reinterpret_cast<const s16x4 *>(pk + kP3 + (nt * 64 + lane) * 4);
-        for (int m = w; m < 32; m += 4) {
+        __syncthreads();  // A1 is dead; its space holds Q from here on
+        // ---- layer 3: Q[tap][cell] = sum_c W3[c][tap] a2[c][cell], taps
+        // 0-15 now and 16-26 after the first half of the sum
+#pragma unroll 2
+        for (int mm = 0; mm < 8; mm++) {
+            const int m = w + 4 * mm;
             int cell = 16 * m + row;
             s16x4 A = *reinterpret_cast<const s16x4 *>(A2 + cell * 16 + 4 * g);
+            f32x4 D = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B3[0], zero, 0, 0, 0);
+            *reinterpret_cast<f32x4 *>(Q + o * 512 + 16 * m + 4 * g) = D;
+        }
+        __syncthreads();
+        float s[2];
 #pragma unroll
-            for (int nt = 0; nt < 2; nt++) {
-                f32x4 D = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B3[nt], zero, 0, 0, 0);
-                int tp = 16 * nt + o;
-                if (tp < 27) *reinterpret_cast<f32x4 *>(Q + tp * 512 + 16 * m + 4 * g) = D;
+        for (int h = 0; h < 2; h++) {
+            const int c = t + 256 * h, ci = c & 7, cj = (c >> 3) & 7, ck = c >> 6;
+            s[h] = b3;
+#pragma unroll
+            for (int tp = 0; tp < 16; tp++) {
+                int ii = ci + tp % 3 - 1, jj = cj + (tp / 3) % 3 - 1, kk = ck + tp / 9 - 1;
+                if ((unsigned)ii < 8u && (unsigned)jj < 8u && (unsigned)kk < 8u)
+                    s[h] += Q[tp * 512 + (kk * 8 + jj) * 8 + ii];
             }
         }
-    }
-    __syncthreads();
-    {
-        const float *Q = R;
-        const float b3 = prm[kB3];
-        for (int c = t; c < 512; c += 256) {
-            int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
-            float s = b3;
+        __syncthreads();
+#pragma unroll 2
+        for (int mm = 0; mm < 8; mm++) {
+            const int m = w + 4 * mm;
+            int cell = 16 * m + row;
+            s16x4 A = *reinterpret_cast<const s16x4 *>(A2 + cell * 16 + 4 * g);
+            f32x4 D = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B3[1], zero, 0, 0, 0);
+            if (o < 11) *reinterpret_cast<f32x4 *>(Q + o * 512 + 16 * m + 4 * g) = D;
+        }
+        __syncthreads();
 #pragma unroll
-            for (int tp = 0; tp < 27; tp++) {
-                int ii = i + tp % 3 - 1, jj = j + (tp / 3) % 3 - 1, kk = k + tp / 9 - 1;
+        for (int h = 0; h < 2; h++) {
+            const int c = t + 256 * h, ci = c & 7, cj = (c >> 3) & 7, ck = c >> 6;
+#pragma unroll
+            for (int tp = 16; tp < 27; tp++) {
+                int ii = ci + tp % 3 - 1, jj = cj + (tp / 3) % 3 - 1, kk = ck + tp / 9 - 1;
                 if ((unsigned)ii < 8u && (unsigned)jj < 8u && (unsigned)kk < 8u)
-                    s += Q[tp * 512 + (kk * 8 + jj) * 8 + ii];
+                    s[h] += Q[(tp - 16) * 512 + (kk * 8 + jj) * 8 + ii];
             }
-            y[q * 512 + c] = s;
+            y[q * 512 + c] = s[h];
         }
     }
 }
@@ -621,11 +700,12 @@ void launch_nn_pack(const float *prm, uint16_t *pk, hipStream_t s) {
 void launch_nn_forward(const float *prm, const uint16_t *pk, int64_t nbox, const int32_t *idx,
                        const float *x, float *y, uint16_t *a1, uint16_t *a2, hipStream_t s) {
     if (nbox <= 0) return;
+    unsigned grid = (unsigned)(nbox < kNnFwdBlocks ? nbox : kNnFwdBlocks);
     if (a1)
-        hipLaunchKernelGGL(k_nn_fwd<true>, dim3((unsigned)nbox), dim3(256), 0, s, x, y, idx, pk, prm, a1,
-                           a2);
+        hipLaunchKernelGGL(k_nn_fwd<true>, dim3(grid), dim3(kFwdThreads), 0, s, x, y, idx, nbox, pk, prm,
+                           a1, a2);
     else
-        hipLaunchKernelGGL(k_nn_fwd<false>, dim3((unsigned)nbox), dim3(256), 0, s, x, y, idx, pk, prm,
+        hipLaunchKernelGGL(k_nn_fwd<false>, dim3(grid), dim3(kFwdThreads), 0, s, x, y, idx, nbox, pk, prm,
                            a1, a2);
 }
 

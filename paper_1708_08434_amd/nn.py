@@ -170,6 +170,8 @@ class Net:
         if getattr(self, "h", None):
             try:
                 mg_nn_destroy(self.h)
+            except Exception:  # interpreter shutdown: the library may be gone
+                pass
             finally:
                 self.h = None
 

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_1708_08434_amd import mg as M
-from workloads import c1, c2, streamer_small, uniform_boxes, refine_boxes_explicit
+from workloads import c1, c2, c3, streamer_small, uniform_boxes, refine_boxes_explicit
 from tests import _geom as G
 
 pytestmark = pytest.mark.gpu
@@ -118,11 +118,14 @@ def test_fmg_solve_parity(wname):
     assert sg["rel"] <= 1e-8
 
 
-def test_fmg_solve_parity_full_streamer():
-    """The benchmark workload at full size (base 64^3 + 4 refinement levels,
-    ~4.8e6 leaf cells) in the same launch sequence the benchmark times."""
-    w = c2()
-    say("fmg parity full streamer", w.boxes.n, "boxes", w.n_leaf, "leaf cells")
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("wname", ["streamer", "branched"])
+def test_fmg_solve_parity_full_size(wname):
+    """Full-size trees in the launch sequence the benchmark times: the
+    benchmark streamer (base 64^3 + 4 refinement levels, 4.8e6 leaf cells)
+    and the branched streamer (base 64^3 + 6 levels, 2.9e7 leaf cells)."""
+    w = c2() if wname == "streamer" else c3()
+    say("fmg parity full size", wname, w.boxes.n, "boxes", w.n_leaf, "leaf cells")
     g, o, sg, so, err = solve_pair(w)
     say("  gpu", sg["n_vcycles"], sg["rel"], "oracle", so["n_vcycles"], so["rel"], "err", err)
     assert sg["n_vcycles"] == so["n_vcycles"]
@@ -271,7 +274,8 @@ def test_fp32_step_parity(step):
 MIXED_TOL = 1e-8
 
 
-@pytest.mark.parametrize("wname", ["uniform64", "streamer_small", "streamer_full"])
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("wname", ["uniform64", "streamer_small", "streamer_full", "branched"])
 def test_mixed_solve_accuracy(wname):
     """FP32 cycles inside FP64 refinement.  At the 1e-8 residual tolerance the
     potential is as close to the fully converged discrete solution (oracle,
@@ -279,7 +283,8 @@ def test_mixed_solve_accuracy(wname):
     error of order conditioning x residual, ~1e-7 here); with a tighter
     tolerance the refinement keeps converging past FP32 rounding and the
     potential matches the oracle to a relative L2 of 1e-8."""
-    w = {"uniform64": c1, "streamer_small": streamer_small, "streamer_full": c2}[wname]()
+    w = {"uniform64": c1, "streamer_small": streamer_small, "streamer_full": c2,
+         "branched": c3}[wname]()
     g, o = pair(w)
     g.set_rhs_from(w)
     o.set_rhs_from(w)

@@ -140,3 +140,19 @@ def test_workspace_size_is_reported():
     n = g.n
     assert g.info.workspace_bytes >= 3 * 512 * 8 * n
     assert g.info.n_leaf_cells == w.n_leaf
+
+
+def test_workload_leaf_counts_match_the_tables():
+    """The generators' leaf count (used for neutrality and for cells/s) equals
+    the leaf count of the library's and the oracle's own tables on a deep
+    tree (coordinates beyond 2^7, where a too-narrow packed key collides)."""
+    from workloads import c2
+    w = c2()
+    h = M.mg_tree_create(M.make_domain(), w.boxes.level, w.boxes.ijk, w.boxes.tree)
+    try:
+        info = M.mg_tree_info(h)
+        assert int(info.n_leaf_cells) == w.n_leaf == 4849664
+    finally:
+        M.mg_tree_destroy(h)
+    o = O.OracleTree.from_workload(w)
+    assert int(o.leaf_mask().sum()) * 512 == w.n_leaf

@@ -22,6 +22,17 @@ DIRICHLET, NEUMANN = 0, 1
 _CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_cache.json")
 
 
+def _pmap(fn, items):
+    """fn over items on a thread pool (NumPy releases the GIL in the array
+    work), results in item order, so sums taken over them keep their order."""
+    items = list(items)
+    if len(items) <= 1:
+        return [fn(it) for it in items]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(fn, items))
+
+
 class Workload:
     """A tree (BoxList), a cubic domain with per-face boundary conditions, and
     a function giving b = -rho/eps0 at the cells of any set of boxes."""
@@ -43,12 +54,18 @@ class Workload:
         ijk = np.asarray(ijk).reshape(-1, 3)
         tree = np.zeros(len(level), dtype=np.int32) if tree is None else np.asarray(tree).reshape(-1)
         out = np.zeros((len(level), 8, 8, 8))
+        jobs = []
         for l in np.unique(level):
-            m = level == l
+            idx = np.nonzero(level == l)[0]
+            jobs += [(int(l), idx[s:s + 1024]) for s in range(0, len(idx), 1024)]
+
+        def run(job):
+            l, idx = job
             if getattr(self, "_rhs_tree_fn", None) is not None:
-                out[m] = self._rhs_tree_fn(int(l), ijk[m], tree[m])
+                out[idx] = self._rhs_tree_fn(l, ijk[idx], tree[idx])
             else:
-                out[m] = self._rhs_fn(int(l), ijk[m])
+                out[idx] = self._rhs_fn(l, ijk[idx])
+        _pmap(run, jobs)
         return out
 
     @property
@@ -82,19 +99,21 @@ class _Channels:
     """Streamer channels (top point, head centre) with head amplitude A_h and
     side amplitude A_s; sum of all channels."""
 
-    def __init__(self, chans, radius, delta, amp_head):
+    def __init__(self, chans, radius, delta, amp_head, heads=None):
         self.chans = [(np.asarray(a, float), np.asarray(b, float)) for a, b in chans]
+        self.heads = [True] * len(self.chans) if heads is None else list(heads)
         self.radius, self.delta, self.amp_head = radius, delta, amp_head
         body = sum(np.linalg.norm(b - a) for a, b in self.chans)
         # continuum estimate of neutrality: hemisphere area vs channel side area
-        self.amp_side = amp_head * len(self.chans) * radius / body
+        self.amp_side = amp_head * sum(self.heads) * radius / body
 
     def parts(self, x, y, z):
         head = np.zeros_like(x)
         side = np.zeros_like(x)
-        for p0, p1 in self.chans:
+        for (p0, p1), has_head in zip(self.chans, self.heads):
             h, s = charges.channel_parts(x, y, z, p0, p1, self.radius, self.delta)
-            head += h
+            if has_head:
+                head += h
             side += s
         return head, side
 
@@ -124,16 +143,22 @@ class _Channels:
     def neutralise(self, boxes, lo, length):
         """Set A_s so that the sum of rho*h^3 over the leaf cells vanishes."""
         leaf = boxes.leaf_mask()
-        sh, ss = 0.0, 0.0
+        jobs = []
         for l in np.unique(boxes.level[leaf]):
             m = leaf & (boxes.level == l)
-            h = length / (8 * 2 ** (l - 1))
             ijk = boxes.ijk[m]
-            for s in range(0, len(ijk), 512):
-                x, y, z, *_ = charges.cell_centres(int(l), ijk[s:s + 512], lo, length)
-                a, b = self.parts(x, y, z)
-                sh += a.sum() * h ** 3
-                ss += b.sum() * h ** 3
+            jobs += [(int(l), ijk[s:s + 512]) for s in range(0, len(ijk), 512)]
+
+        def part(job):
+            l, ijk = job
+            h = length / (8 * 2 ** (l - 1))
+            x, y, z, *_ = charges.cell_centres(l, ijk, lo, length)
+            a, b = self.parts(x, y, z)
+            return a.sum() * h ** 3, b.sum() * h ** 3
+        sh, ss = 0.0, 0.0
+        for a, b in _pmap(part, jobs):
+            sh += a
+            ss += b
         if ss > 0:
             self.amp_side = self.amp_head * sh / ss
 
@@ -153,8 +178,8 @@ def _score_fn(rho_fn, lo, length, memo, far_fn=None):
                 d[int(keys[n])] = 0.0
             miss = [n for n in miss if int(keys[n]) not in d]
         h = length / (8 * 2 ** (level - 1))
-        for s in range(0, len(miss), 256):
-            idx = np.array(miss[s:s + 256])
+
+        def chunk(idx):
             x, y, z, *_ = charges.cell_centres(level, ijk[idx], lo, length, pad=4)
             r = rho_fn(x, y, z)
             c = r[:, 1:-1, 1:-1, 1:-1]
@@ -162,7 +187,9 @@ def _score_fn(rho_fn, lo, length, memo, far_fn=None):
             gy = (r[:, 1:-1, 2:, 1:-1] - r[:, 1:-1, :-2, 1:-1]) / (2 * h)
             gz = (r[:, 2:, 1:-1, 1:-1] - r[:, :-2, 1:-1, 1:-1]) / (2 * h)
             crit = np.maximum(np.abs(c) * h * h, np.sqrt(gx * gx + gy * gy + gz * gz) * h ** 3)
-            mx = crit.reshape(len(idx), -1).max(axis=1)
+            return crit.reshape(len(idx), -1).max(axis=1)
+        parts = [np.array(miss[s:s + 256]) for s in range(0, len(miss), 256)]
+        for idx, mx in zip(parts, _pmap(chunk, parts)):
             for n, v in zip(idx.tolist(), mx.tolist()):
                 d[int(keys[n])] = v
         for n, k in enumerate(keys.tolist()):
@@ -244,6 +271,101 @@ def streamer_small(refinements=2, target=3.0e5, use_cache=True):
         x, y, z, *_ = charges.cell_centres(level, ijk, (0.0, 0.0, 0.0), 1.0)
         return -ch.rho(x, y, z)
     return Workload(f"streamer_small_L3+{refinements}", bl, fn, meta=dict(c3=c3))
+
+
+def c3(seed=3, refinements=6, target=3.0e7, amp_head=1e4, radius=0.015, delta=2e-3,
+       use_cache=True):
+    """Static AMR tree, base 64^3 plus ``refinements`` levels (effective
+    4096^3), around a branched streamer: a trunk from (1/2, 1/2, 1) down to
+    (1/2, 1/2, 0.8) and three seeded branches of length 0.25 from there, each
+    at a polar angle U(10, 40) degrees from -z and azimuth 2 pi k / 3 +
+    U(-0.3, 0.3), with a head at every branch tip (none at the fork);
+    radius 0.015, head layer thickness 2e-3, neutralised."""
+    rng = np.random.default_rng(seed)
+    fork = np.array([0.5, 0.5, 0.8])
+    chans, heads = [((0.5, 0.5, 1.0), tuple(fork))], [False]
+    for k in range(3):
+        pol = np.radians(rng.uniform(10.0, 40.0))
+        az = 2.0 * np.pi * k / 3.0 + rng.uniform(-0.3, 0.3)
+        d = np.array([np.sin(pol) * np.cos(az), np.sin(pol) * np.sin(az), -np.cos(pol)])
+        chans.append((tuple(fork), tuple(fork + 0.25 * d)))
+        heads.append(True)
+    ch = _Channels(chans, radius, delta, amp_head, heads)
+    base = 4
+    tag = f"c3_s{seed}_r{refinements}_t{target:.3g}"
+    bl, c3v = tuned_tree(tag, ch.rho, base, base + refinements, target, use_cache=use_cache,
+                         far_fn=ch.far)
+    ch.neutralise(bl, (0.0, 0.0, 0.0), 1.0)
+
+    def fn(level, ijk):
+        x, y, z, *_ = charges.cell_centres(level, ijk, (0.0, 0.0, 0.0), 1.0)
+        return -ch.rho(x, y, z)
+    return Workload(f"branched_L{base}+{refinements}", bl, fn,
+                    meta=dict(seed=seed, c3=c3v, amp_head=amp_head, amp_side=ch.amp_side,
+                              radius=radius, delta=delta, target=target,
+                              branches=[list(map(float, b)) for _, b in chans[1:]]))
+
+
+def _poisson_background(seed, base_level=4, lam=100.0):
+    """(N_i - N_e) / lam per base-level cell, N ~ Poisson(lam) drawn by the
+    inverse CDF of two counter-based uniforms per cell, [k][j][i]."""
+    from scipy.stats import poisson
+    from .rng import uniform01
+    n = 8 << (base_level - 1)
+    g = np.arange(n, dtype=np.int64)
+    K, J, I = np.meshgrid(g, g, g, indexing="ij")
+    u_i = uniform01(2 * seed, base_level, I, J, K)
+    u_e = uniform01(2 * seed + 1, base_level, I, J, K)
+    return (poisson.ppf(u_i, lam) - poisson.ppf(u_e, lam)) / lam
+
+
+def _trilinear(grid, x, y, z):
+    """Trilinear interpolation of cell-centred values on the unit cube
+    (n^3 cells, [k][j][i]), clamped to the outermost cell centres."""
+    n = grid.shape[0]
+    def split(c):
+        u = np.clip(c * n - 0.5, 0.0, n - 1.0)
+        i0 = np.minimum(np.floor(u).astype(np.int64), n - 2)
+        return i0, u - i0
+    i0, fx = split(x)
+    j0, fy = split(y)
+    k0, fz = split(z)
+    out = np.zeros_like(x)
+    for dk in (0, 1):
+        wz = fz if dk else 1.0 - fz
+        for dj in (0, 1):
+            wy = fy if dj else 1.0 - fy
+            for di in (0, 1):
+                wx = fx if di else 1.0 - fx
+                out += wx * wy * wz * grid[k0 + dk, j0 + dj, i0 + di]
+    return out
+
+
+def c5(seed=5, refinements=7, target=1.0e8, amp_head=1e4, radius=0.02, delta=2e-3,
+       use_cache=True):
+    """Static AMR tree, base 64^3 plus ``refinements`` levels (effective
+    8192^3), around two interacting streamers (axes x = 0.45 and 0.55 at
+    y = 1/2, tips at z = 0.60 and 0.50; radius 0.02, head layer 2e-3,
+    neutralised) plus a background ionisation 1e-3 A_h (N_i - N_e) / 100 with
+    N ~ Poisson(100) per base 64^3 cell, interpolated trilinearly to the cell
+    centres.  Refinement uses the channels' charge only (the background's
+    |rho| h^2 is four orders of magnitude below the threshold)."""
+    chans = [((0.45, 0.5, 1.0), (0.45, 0.5, 0.60 + radius)),
+             ((0.55, 0.5, 1.0), (0.55, 0.5, 0.50 + radius))]
+    ch = _Channels(chans, radius, delta, amp_head)
+    base = 4
+    tag = f"c5_s{seed}_r{refinements}_t{target:.3g}"
+    bl, c3v = tuned_tree(tag, ch.rho, base, base + refinements, target, use_cache=use_cache,
+                         far_fn=ch.far)
+    ch.neutralise(bl, (0.0, 0.0, 0.0), 1.0)
+    bg = 1e-3 * amp_head * _poisson_background(seed, base)
+
+    def fn(level, ijk):
+        x, y, z, *_ = charges.cell_centres(level, ijk, (0.0, 0.0, 0.0), 1.0)
+        return -(ch.rho(x, y, z) + _trilinear(bg, x, y, z))
+    return Workload(f"two_streamers_L{base}+{refinements}", bl, fn,
+                    meta=dict(seed=seed, c3=c3v, amp_head=amp_head, amp_side=ch.amp_side,
+                              radius=radius, delta=delta, target=target, background=1e-3))
 
 
 def _forest_tree(t, refinements=5, base=3, lo_cells=1e5, hi_cells=2e6, use_cache=True):

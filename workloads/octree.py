@@ -48,12 +48,15 @@ class BoxList:
 
     def leaf_mask(self):
         """True for boxes that have no children in the list."""
-        key = (self.tree.astype(np.int64) << 48) | (self.level.astype(np.int64) << 42) \
-            | pack(self.ijk)
+        def key(tree, level, ijk):
+            # 14 bits per coordinate (levels <= 15), 4 for the level, 17 for the tree
+            ijk = np.asarray(ijk, dtype=np.int64)
+            return (tree.astype(np.int64) << 46) | (level.astype(np.int64) << 42) \
+                | (ijk[:, 0] << 28) | (ijk[:, 1] << 14) | ijk[:, 2]
+        own = key(self.tree, self.level, self.ijk)
         has_parent = self.level > 1
-        pk = (self.tree.astype(np.int64) << 48) | ((self.level.astype(np.int64) - 1) << 42) \
-            | pack(self.ijk.astype(np.int64) >> 1)
-        return ~np.isin(key, pk[has_parent])
+        par = key(self.tree, self.level - 1, self.ijk.astype(np.int64) >> 1)
+        return ~np.isin(own, par[has_parent])
 
     def n_leaf_cells(self, n_cell=8):
         return int(self.leaf_mask().sum()) * n_cell ** 3
