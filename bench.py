@@ -82,6 +82,35 @@ NN_FLOP_PER_CELL = 2 * 27 * (16 + 16 * 16 + 16)  # the three convolutions, multi
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 
 
+def copy_bandwidth(nbytes=2 << 30, reps=10):
+    """Achievable streaming bandwidth: the library's 16-byte-vector copy
+    kernel (mg_stream_copy) timed with HIP events on torch's stream; bytes
+    read plus bytes written per second, best over a few grid sizes."""
+    import torch
+    from paper_1708_08434_amd import mg as M
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream().cuda_stream
+    best = None
+    for blocks in (0, 2048, 4096):
+        for _ in range(2):
+            M.mg_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, blocks, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            M.mg_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, blocks, stream)
+        e1.record()
+        torch.cuda.synchronize()
+        gbps = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+        if best is None or gbps > best[0]:
+            best = (gbps, blocks)
+    assert torch.equal(dst[:1024], src[:1024])
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBps": best[0], "bytes": nbytes, "grid": best[1] or "4 per CU",
+            "kernel": "mg_stream_copy (16-byte vector loads and stores, grid-stride)"}
+
+
 def learned_leg(g, args, k_plain, value_plain):
     """Train the correction network on seeded streamer trees that are not the
     benchmark problem, then time the learned solve on the benchmark tree and
@@ -237,6 +266,7 @@ def main():
     learned = None
     if not args.no_learned:
         learned = learned_leg(g, args, k, value)
+    copy = copy_bandwidth()
     mb = model_bytes(counts, n_leaf, k)
     # the level whose half-sweeps move the most bytes (the finest level of a
     # single streamer tree; a middle level of the forest)
@@ -267,6 +297,7 @@ def main():
                                f"{fin + 1} ({counts[fin]} boxes, the most bytes)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
+                     "copy_GBps": copy["GBps"], "frac_of_copy": achieved / copy["GBps"],
                      "traffic": tr,
                      "launches": kt["level_launches"][fin], "avg_launch_us": per_launch_s * 1e6,
                      "alg_bytes_per_launch": bytes_per_launch,
@@ -275,7 +306,9 @@ def main():
                      "probe_region_ms_per_step": 1e3 * elapsed_probe / args.steps},
         "model": {"bytes_per_solve": mb, "GBps": mb / (ms / 1e3) / 1e9,
                   "roofline_cells_per_s": HBM_PEAK_GBPS * 1e9 * n_leaf / mb,
-                  "frac": value / (HBM_PEAK_GBPS * 1e9 * n_leaf / mb)},
+                  "frac": value / (HBM_PEAK_GBPS * 1e9 * n_leaf / mb),
+                  "frac_of_copy": value / (copy["GBps"] * 1e9 * n_leaf / mb)},
+        "copy_probe": copy,
     }
     if mixed is not None:
         out["mixed"] = mixed

@@ -259,6 +259,17 @@ int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out);
 int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule);
 int mg_set_schedule(mg_tree *t, int precision, const int32_t *schedule);
 
+/*
+ * mg_stream_copy - copy `bytes` (a multiple of 16; both pointers device
+ * memory, 16-byte aligned, not overlapping) from src to dst on `stream` with
+ * 16-byte vector loads and stores in a grid-stride loop over `blocks`
+ * workgroups of 256 threads (blocks <= 0: 4 per CU).  A measurement helper:
+ * timing it gives the device's achievable streaming bandwidth, the second
+ * reference (beside the specification peak) of the solver's roofline.
+ * Asynchronous; MG_EINVAL on bad sizes or alignment.
+ */
+int mg_stream_copy(void *dst, const void *src, int64_t bytes, int blocks, void *stream);
+
 const char *mg_last_error(void);
 
 #ifdef __cplusplus

@@ -75,12 +75,32 @@ __device__ __forceinline__ T ghost_at(const Geo &g, const T *__restrict__ phi,
            (T)kCfFine2 * inward;
 }
 
+// The face tables of box b, read with block-uniform addresses (scalar loads
+// issued at kernel start), so that a ghost's value load waits on no vector
+// load of an index.
+struct FaceTab {
+    int nb[6], slot[6];
+};
+__device__ __forceinline__ FaceTab face_tab(const Geo &g, int64_t b) {
+    FaceTab f;
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        f.nb[d] = g.nbr[b * 6 + d];
+        f.slot[d] = g.cfslot[b * 6 + d];
+    }
+    return f;
+}
+__device__ __forceinline__ int pick6(const int v[6], int d) {
+    return d == 0 ? v[0] : d == 1 ? v[1] : d == 2 ? v[2] : d == 3 ? v[3] : d == 4 ? v[4] : v[5];
+}
+
 // Stage the whole box (both colours, colour-split order) into P[512] and all
 // 6 x 64 face ghosts into H[d*64 + v*8 + u]; 256 threads.  Caller syncs.
 template <typename T>
 __device__ __forceinline__ void stage_full(const Geo &g, const T *__restrict__ phi,
                                            const T *__restrict__ chat, int64_t b, T *P, T *H) {
     int t = threadIdx.x;
+    const FaceTab ft = face_tab(g, b);
     P[t] = phi[b * 512 + t];
     P[256 + t] = phi[b * 512 + 256 + t];
 #pragma unroll
@@ -88,8 +108,7 @@ __device__ __forceinline__ void stage_full(const Geo &g, const T *__restrict__ p
         int e = t + 256 * r;
         if (e < 384) {
             int d = e >> 6, w = e & 63;
-            int nb = g.nbr[b * 6 + d], slot = g.cfslot[b * 6 + d];
-            H[e] = ghost_at<T>(g, phi, chat, b, d, nb, slot, w & 7, w >> 3);
+            H[e] = ghost_at<T>(g, phi, chat, b, d, pick6(ft.nb, d), pick6(ft.slot, d), w & 7, w >> 3);
         }
     }
 }
@@ -143,13 +162,12 @@ __global__ __launch_bounds__(256) void k_unpack(const T *__restrict__ cs, double
 // mapping are the launch variants the autotuner chooses from; every variant
 // performs the same arithmetic on every cell.
 template <typename T>
-__device__ __forceinline__ void gsrb_ghost(const Geo &g, const T *__restrict__ phi,
+__device__ __forceinline__ void gsrb_ghost(const Geo &g, const FaceTab &ft, const T *__restrict__ phi,
                                            const T *__restrict__ chat, int64_t b, int C, int e, T *H) {
     int d = e >> 5, q = e & 31, v = q >> 2;
     int layer = (d & 1) ? 7 : 0;
     int u = 2 * (q & 3) + ((layer + v + C) & 1);
-    int nb = g.nbr[b * 6 + d], slot = g.cfslot[b * 6 + d];
-    H[e] = ghost_at<T>(g, phi, chat, b, d, nb, slot, u, v);
+    H[e] = ghost_at<T>(g, phi, chat, b, d, pick6(ft.nb, d), pick6(ft.slot, d), u, v);
 }
 
 template <typename T, int N> struct VecN;
@@ -172,10 +190,11 @@ __global__ __launch_bounds__(256 / CPT) void k_gsrb(Geo g, T *__restrict__ phi,
     if (lb >= nbx) return;
     int64_t b = b0 + lb;
     int t = threadIdx.x;
+    const FaceTab ft = face_tab(g, b);
     V o = reinterpret_cast<const V *>(phi + b * 512 + (1 - C) * 256)[t];
     V bv = reinterpret_cast<const V *>(rhs + b * 512 + C * 256)[t];
 #pragma unroll
-    for (int e = t; e < 192; e += NT) gsrb_ghost<T>(g, phi, chat, b, C, e, H);
+    for (int e = t; e < 192; e += NT) gsrb_ghost<T>(g, ft, phi, chat, b, C, e, H);
     reinterpret_cast<V *>(S)[t] = o;
     __syncthreads();
     const T *bb = reinterpret_cast<const T *>(&bv);
@@ -564,21 +583,14 @@ __global__ __launch_bounds__(256) void k_ir_update(double *__restrict__ phi, con
     if (q < count) phi[q] += (double)e[q];
 }
 
-// Per-tree reduction of the per-box partials in a fixed order: block t sums
-// the partials of tree t's leaf boxes (positions leaf_tree[off[t] ..
-// off[t+1])) into result[2t] (sum) and result[2t+1] (max).
-__global__ __launch_bounds__(256) void k_reduce_trees(const double *__restrict__ partial,
-                                                      const int32_t *__restrict__ leaf_tree,
-                                                      const int32_t *__restrict__ off,
-                                                      double *__restrict__ result) {
-    __shared__ double S[256], M[256];
-    int tr = blockIdx.x, t = threadIdx.x;
-    double s = 0.0, m = 0.0;
-    for (int q = off[tr] + t; q < off[tr + 1]; q += 256) {
-        int64_t p = leaf_tree[q];
-        s += partial[2 * p];
-        m = nanmax(partial[2 * p + 1], m);
-    }
+// Per-tree reduction of the per-box partials in a fixed order, in two
+// stages.  Stage 1: block c sums the partials of the leaf boxes at positions
+// leaf_tree[chunk[c].begin .. chunk[c].end) (a range of one tree, at most
+// kReduceChunk long) into part2[c].  Stage 2: block t sums the chunks
+// choff[t] .. choff[t+1] of tree t into result[2t] (sum) and result[2t+1]
+// (max).
+__device__ __forceinline__ void block_sum_max(double &s, double &m, double *S, double *M) {
+    int t = threadIdx.x;
     S[t] = s;
     M[t] = m;
     __syncthreads();
@@ -589,10 +601,53 @@ __global__ __launch_bounds__(256) void k_reduce_trees(const double *__restrict__
         }
         __syncthreads();
     }
-    if (t == 0) {
-        result[2 * tr] = S[0];
-        result[2 * tr + 1] = M[0];
+    s = S[0];
+    m = M[0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_chunks(const double *__restrict__ partial,
+                                                       const int32_t *__restrict__ leaf_tree,
+                                                       const int32_t *__restrict__ chunk,
+                                                       double *__restrict__ part2) {
+    __shared__ double S[256], M[256];
+    int c = blockIdx.x, t = threadIdx.x;
+    int beg = chunk[3 * c + 1], end = chunk[3 * c + 2];
+    double s = 0.0, m = 0.0;
+    for (int q = beg + t; q < end; q += 256) {
+        int64_t p = leaf_tree[q];
+        s += partial[2 * p];
+        m = nanmax(partial[2 * p + 1], m);
     }
+    block_sum_max(s, m, S, M);
+    if (t == 0) {
+        part2[2 * c] = s;
+        part2[2 * c + 1] = m;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_trees(const double *__restrict__ part2,
+                                                      const int32_t *__restrict__ choff,
+                                                      double *__restrict__ result) {
+    __shared__ double S[256], M[256];
+    int tr = blockIdx.x, t = threadIdx.x;
+    double s = 0.0, m = 0.0;
+    for (int c = choff[tr] + t; c < choff[tr + 1]; c += 256) {
+        s += part2[2 * c];
+        m = nanmax(part2[2 * c + 1], m);
+    }
+    block_sum_max(s, m, S, M);
+    if (t == 0) {
+        result[2 * tr] = s;
+        result[2 * tr + 1] = m;
+    }
+}
+
+// Streaming copy with 16-byte vector accesses, grid-stride: the achievable
+// device bandwidth reference of the roofline.
+__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                int64_t n16) {
+    int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n16; q += stride) dst[q] = src[q];
 }
 
 }  // namespace
@@ -693,10 +748,18 @@ void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s)
     if (count <= 0) return;
     hipLaunchKernelGGL(k_ir_update, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, phi, e, count);
 }
-void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const int32_t *off,
-                         int ntree, double *result, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_trees, dim3((unsigned)ntree), dim3(256), 0, s, partial, leaf_tree, off,
-                       result);
+void launch_copy16(const void *src, void *dst, int64_t n16, int blocks, hipStream_t s) {
+    if (n16 <= 0) return;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst,
+                       n16);
+}
+void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const int32_t *chunk,
+                         int64_t nchunk, const int32_t *choff, int ntree, double *part2,
+                         double *result, hipStream_t s) {
+    if (nchunk > 0)
+        hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)nchunk), dim3(256), 0, s, partial, leaf_tree,
+                           chunk, part2);
+    hipLaunchKernelGGL(k_reduce_trees, dim3((unsigned)ntree), dim3(256), 0, s, part2, choff, result);
 }
 
 #define MG_INSTANTIATE(T)                                                                        \

@@ -201,8 +201,8 @@ void norms_launch(mg_tree *t, int slot, float *r32) {
     for (int l = 2; l <= t->nlev; l++) ensure_cf(t, F, l);
     launch_leaf_norms(F.g, F.phi, F.rhs, F.chat, t->d.leaf, t->nleaf, t->d.partial, r32,
                       stream_of(t));
-    launch_reduce_trees(t->d.partial, t->d.leaf_tree, t->d.tree_off, t->ntree, t->d.result + slot,
-                        stream_of(t));
+    launch_reduce_trees(t->d.partial, t->d.leaf_tree, t->d.chunk, (int64_t)t->chunk.size() / 3, t->d.choff,
+                        t->ntree, t->d.part2, t->d.result + slot, stream_of(t));
 }
 
 int read_results(mg_tree *t, int count) {
@@ -750,6 +750,9 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.slots = (int32_t *)(base + t->off.slots);
     d.leaf_tree = (int32_t *)(base + t->off.leaf_tree);
     d.tree_off = (int32_t *)(base + t->off.tree_off);
+    d.chunk = (int32_t *)(base + t->off.chunk);
+    d.choff = (int32_t *)(base + t->off.choff);
+    d.part2 = (double *)(base + t->off.part2);
     d.isleaf = (int32_t *)(base + t->off.isleaf);
     d.tid = (int32_t *)(base + t->off.tid);
     d.eig = (double *)(base + t->off.eig);
@@ -791,6 +794,8 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     rc = rc ? rc : up(d.slots, t->slots.data(), t->slots.size() * 4);
     rc = rc ? rc : up(d.leaf_tree, t->leaf_tree.data(), t->leaf_tree.size() * 4);
     rc = rc ? rc : up(d.tree_off, t->tree_off.data(), t->tree_off.size() * 4);
+    rc = rc ? rc : up(d.chunk, t->chunk.data(), t->chunk.size() * 4);
+    rc = rc ? rc : up(d.choff, t->choff.data(), t->choff.size() * 4);
     rc = rc ? rc : up(d.isleaf, isleaf.data(), isleaf.size() * 4);
     rc = rc ? rc : up(d.tid, t->tid.data(), t->tid.size() * 4);
     rc = rc ? rc : up(d.eig, t->eig, sizeof t->eig);
@@ -1067,6 +1072,23 @@ int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out) {
     t->probes.clear();
     if (out) *out = acc;
     return MG_OK;
+}
+
+int mg_stream_copy(void *dst, const void *src, int64_t bytes, int blocks, void *stream) {
+    if (!dst || !src || bytes < 0 || (bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15)) {
+        set_error("stream copy: null pointer, or size or alignment not a multiple of 16");
+        return MG_EINVAL;
+    }
+    if (blocks <= 0) {
+        int dev = 0, cus = 0;
+        int rc = hip_check(hipGetDevice(&dev), "current device");
+        if (!rc) rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
+                                "CU count");
+        if (rc) return rc;
+        blocks = 4 * cus;
+    }
+    launch_copy16(src, dst, bytes / 16, blocks, (hipStream_t)stream);
+    return hip_check(hipGetLastError(), "stream copy launch");
 }
 
 // ---------------------------------------------------------- learned step

@@ -27,6 +27,9 @@ struct DevTables {
     int32_t *slots = nullptr;    // [nslot][2] (box, face)
     int32_t *leaf_tree = nullptr;  // leaf-list positions grouped by tree (ascending within a tree)
     int32_t *tree_off = nullptr;   // [ntree+1] offsets into leaf_tree
+    int32_t *chunk = nullptr;      // [nchunk][3] tree, begin, end of a norm-reduction chunk
+    int32_t *choff = nullptr;      // [ntree+1] offsets into the chunks
+    double *part2 = nullptr;       // [nchunk][2] first-stage sums
     int32_t *isleaf = nullptr;     // [n] 1 for a box without children
     int32_t *tid = nullptr;        // [n] tree of the box
     double *eig = nullptr;       // root solve: Q_x, Q_y, Q_z (8x8, column = vector), then lambda_x,y,z
@@ -56,12 +59,13 @@ struct mg_tree {
     int64_t rstart[mg::kMaxLevel + 2] = {0}, fstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> slots;                         // (box, face) per slot
     std::vector<int32_t> leaf_tree, tree_off;           // leaf positions grouped by tree
+    std::vector<int32_t> chunk, choff;                  // norm-reduction chunks (tree, begin, end)
     int64_t sstart[mg::kMaxLevel + 2] = {0};            // slots of level l: [sstart[l], sstart[l+1])
     int64_t nslot = 0, nleaf = 0;
     mg_domain dom{};
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
-    struct { int64_t nbr, cfslot, cfq, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, isleaf, tid, eig,
+    struct { int64_t nbr, cfslot, cfq, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, eig,
              phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, total; } off{};
     // ---- bound device state ----
     void *ws = nullptr;

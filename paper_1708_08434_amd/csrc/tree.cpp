@@ -13,6 +13,7 @@
 #include <cstring>
 #include <tuple>
 
+#include "kernels.h"
 #include "mg_internal.h"
 
 namespace mg {
@@ -256,6 +257,18 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
         std::vector<int32_t> fill(t->tree_off.begin(), t->tree_off.end() - 1);
         for (int64_t q = 0; q < t->nleaf; q++) t->leaf_tree[fill[t->tid[t->leaf[q]]]++] = (int32_t)q;
     }
+    // chunks of at most kReduceChunk leaf positions inside one tree, for the
+    // first stage of the per-tree norm reduction
+    t->chunk.clear();
+    t->choff.assign(ntree + 1, 0);
+    for (int tr = 0; tr < ntree; tr++) {
+        for (int32_t b = t->tree_off[tr]; b < t->tree_off[tr + 1]; b += kReduceChunk) {
+            t->chunk.push_back(tr);
+            t->chunk.push_back(b);
+            t->chunk.push_back(std::min<int32_t>(b + kReduceChunk, t->tree_off[tr + 1]));
+        }
+        t->choff[tr + 1] = (int32_t)(t->chunk.size() / 3);
+    }
     t->beff_tree.assign(ntree, 0.0);
     t->rel_tree.assign(ntree, 0.0);
     root_eigen(dom->bc_type, t->eig);
@@ -274,6 +287,9 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.slots = take(8 * t->nslot);
     t->off.leaf_tree = take(4 * t->nleaf);
     t->off.tree_off = take(4 * (int64_t)(ntree + 1));
+    t->off.chunk = take(4 * (int64_t)t->chunk.size());
+    t->off.choff = take(4 * (int64_t)(ntree + 1));
+    t->off.part2 = take(16 * (int64_t)(t->chunk.size() / 3));
     t->off.isleaf = take(4 * n);
     t->off.tid = take(4 * n);
     t->off.eig = take(8 * (3 * 64 + 3 * 8));

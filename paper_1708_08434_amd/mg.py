@@ -31,7 +31,7 @@ _WIDTH = {MG_IDX_ORDER: 1, MG_IDX_LEVEL: 1, MG_IDX_IJK: 3, MG_IDX_TREE: 1, MG_ID
 EXPORTS = ["mg_tree_create", "mg_tree_destroy", "mg_tree_info", "mg_tree_bind", "mg_tree_index",
            "mg_field_set", "mg_field_get", "mg_default_opts", "mg_fmg_solve", "mg_vcycle",
            "mg_residual", "mg_tree_residuals", "mg_step", "mg_timing_enable", "mg_timing_read",
-           "mg_autotune", "mg_set_schedule", "mg_last_error"]
+           "mg_autotune", "mg_set_schedule", "mg_stream_copy", "mg_last_error"]
 
 
 class mg_domain(ctypes.Structure):
@@ -106,6 +106,7 @@ def lib():
         L.mg_set_schedule.argtypes = [P, I32, P]
         L.mg_timing_enable.argtypes = [P, I32]
         L.mg_timing_read.argtypes = [P, ctypes.POINTER(mg_kernel_timing_t)]
+        L.mg_stream_copy.argtypes = [P, P, I64, I32, P]
         L.mg_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -227,6 +228,11 @@ def mg_timing_read(h):
     return dict(launches=out.launches, total_ms=out.total_ms, alg_bytes=out.alg_bytes,
                 level_launches=list(out.level_launches), level_ms=list(out.level_ms),
                 level_bytes=list(out.level_bytes))
+
+
+def mg_stream_copy(dst_ptr, src_ptr, nbytes, blocks=0, stream_ptr=0):
+    check(lib().mg_stream_copy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), int(nbytes),
+                               int(blocks), ctypes.c_void_p(stream_ptr)))
 
 
 # --------------------------------------------------------- convenience

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_1708_08434_amd import mg as M
-from workloads import c1, c2, c3, streamer_small, uniform_boxes, refine_boxes_explicit
+from workloads import c1, c2, c3, c5, streamer_small, uniform_boxes, refine_boxes_explicit
 from tests import _geom as G
 
 pytestmark = pytest.mark.gpu
@@ -118,13 +118,15 @@ def test_fmg_solve_parity(wname):
     assert sg["rel"] <= 1e-8
 
 
-@pytest.mark.timeout(400)
-@pytest.mark.parametrize("wname", ["streamer", "branched"])
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("wname", ["streamer", "branched", "two_streamers"])
 def test_fmg_solve_parity_full_size(wname):
     """Full-size trees in the launch sequence the benchmark times: the
-    benchmark streamer (base 64^3 + 4 refinement levels, 4.8e6 leaf cells)
-    and the branched streamer (base 64^3 + 6 levels, 2.9e7 leaf cells)."""
-    w = c2() if wname == "streamer" else c3()
+    benchmark streamer (base 64^3 + 4 refinement levels, 4.8e6 leaf cells),
+    the branched streamer (base 64^3 + 6 levels, 2.9e7 leaf cells) and the
+    two streamers with background ionisation (base 64^3 + 7 levels, 1.2e8
+    leaf cells)."""
+    w = {"streamer": c2, "branched": c3, "two_streamers": c5}[wname]()
     say("fmg parity full size", wname, w.boxes.n, "boxes", w.n_leaf, "leaf cells")
     g, o, sg, so, err = solve_pair(w)
     say("  gpu", sg["n_vcycles"], sg["rel"], "oracle", so["n_vcycles"], so["rel"], "err", err)
