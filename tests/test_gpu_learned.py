@@ -11,6 +11,8 @@ three seeds; the forward bar is ten times that.  Gradients (FP32 on the GPU
 over up to 512 * nbox terms) and the step sizes (FP32 operator images, FP64
 sums) get 1e-3 relative.  Whole learned solves converge to the same discrete
 solution as the plain FP64 solve (relative residual <= 1e-8 on both)."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -289,3 +291,70 @@ def test_training_lowers_the_loss_and_agrees_with_oracle():
     lg = net.gradient(x, t)
     lo = N.loss(p, x.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64))
     assert abs(lg - lo) <= 1e-3 * lo
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_forward_zero_boxes_and_bad_arguments():
+    net = NN.Net(rand_params(30))
+    NN.mg_nn_forward(net.h, 0, 0, 0)  # nothing to do
+    L = NN.lib()
+    assert L.mg_nn_forward(net.h, -1, None, None) == M.MG_EINVAL
+    assert L.mg_nn_gradient(net.h, 0, None, None, None, None, 0, None) == M.MG_EINVAL
+    x = torch.zeros((2, 1000), device="cuda")
+    t = torch.zeros((2, 512), device="cuda")
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    assert L.mg_nn_gradient(net.h, 2, None, x.data_ptr(), t.data_ptr(), ws.data_ptr(), 16,
+                            None) == M.MG_ENOMEM
+    o = NN.mg_adam_opts(1e-3, 1.5, 0.999, 1e-8)
+    assert L.mg_nn_adam(net.h, ctypes.byref(o)) == M.MG_EINVAL
+
+
+def test_learned_step_on_a_root_only_tree():
+    """One 8^3 box: the learned step still follows the oracle (one level, so
+    the step is the single least-squares ratio)."""
+    bl = uniform_boxes(1)
+    g, o = tree_pair(bl)
+    o.fmg_solve(tol=1e30)
+    phi = o.get_field(O.PHI) + 1e-3 * np.random.default_rng(4).standard_normal((1, 8, 8, 8))
+    o.set_field(O.PHI, phi)
+    g.set_field(M.MG_FIELD_PHI, phi)
+    p = rand_params(31, scale=0.5)
+    steps = NN.Learned(g).step(NN.Net(p))
+    out = N.learned_step(o, p.astype(np.float64))
+    assert abs(steps[0, 1] - out["s"][0, 1]) <= STEP_REL * abs(out["s"][0, 1])
+    assert np.abs(g.get_field(M.MG_FIELD_PHI) - o.get_field(O.PHI)).max() <= \
+        STEP_REL * np.abs(o.get_field(O.PHI) - phi).max()
+
+
+# ------------------------------------------------------------ A/B
+
+def test_trained_network_against_plain_solve():
+    """What the trained network gains: train on held-out seeded streamer
+    trees, then solve an unseen streamer problem with and without the
+    learned step.  Both must reach the tolerance and the same discrete
+    solution; the cycle counts and times are reported, whatever they are."""
+    from workloads import forest, streamer_small
+    tw = forest(n_trees=4, refinements=3, base=3, lo_cells=5e4, hi_cells=3e5)
+    tt = M.Tree.from_workload(tw)
+    tt.set_rhs_from(tw)
+    x, t = NN.training_pairs(tt, states=(0, 1, 2))
+    net = NN.Net(N.init_params(1000).astype(np.float32))
+    losses = NN.train(net, x, t, steps=200, batch=min(512, int(x.shape[0])), lr=1e-3, seed=2,
+                      log_every=199)
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    plain = g.fmg_solve()
+    phi_plain = g.get_field(M.MG_FIELD_PHI)
+    res = NN.Learned(g).solve(net)
+    phi_l = g.get_field(M.MG_FIELD_PHI)
+    leaf = g.leaf_mask()
+    diff = np.linalg.norm((phi_l - phi_plain)[leaf]) / np.linalg.norm(phi_plain[leaf])
+    say("A/B: training loss", losses, "| plain", plain["n_vcycles"], "cycles", plain["t_ms"],
+        "ms | learned", res["n_vcycles"], "cycles", res["t_ms"], "ms, steps kept",
+        res["accepted"], "fallback at", res["fallback_cycle"], "| rel diff", diff)
+    assert losses[-1][1] < losses[0][1]
+    assert plain["rel"] <= 1e-8 and res["rel"] <= 1e-8
+    assert diff <= 1e-6
+    assert res["n_vcycles"] <= plain["n_vcycles"] + 1
