@@ -24,7 +24,7 @@ def _key(tree, precision):
     dev = torch.cuda.get_device_name(tree.device)
     ls = list(tree.info.level_start[:tree.nlev + 1])
     counts = [int(ls[i + 1] - ls[i]) for i in range(tree.nlev)]
-    return f"{dev}|{'mixed' if precision == M.MG_MIXED else 'fp64'}|{counts}"
+    return f"{dev}|{M.MG_GSRB_VARIANTS} variants|{'mixed' if precision == M.MG_MIXED else 'fp64'}|{counts}"
 
 
 def tune(tree, precision=M.MG_FP64, reps=16, use_cache=True):

@@ -11,6 +11,7 @@ struct Geo {
     const int32_t *nbr;     // [n][6]
     const int32_t *cfslot;  // [n][6]
     const int32_t *cfq;     // [n][6]
+    const int32_t *xt;      // [n][6][4][2] faces of the face neighbours
     const int32_t *ijk;     // [n][4] (i, j, k, level)
     const int32_t *parent;  // [n]
     const double *bcval;    // [n][6][64] or null
@@ -24,14 +25,22 @@ struct Geo {
 template <typename T> void launch_fill(T *p, int64_t count, T v, hipStream_t s);
 template <typename T> void launch_pack(const double *nat, T *cs, int64_t nbox, hipStream_t s);
 template <typename T> void launch_unpack(const T *cs, double *nat, int64_t nbox, hipStream_t s);
-// Gauss-Seidel launch variants: variant = 2 * c + x, with c = 0, 1, 2 for 1,
-// 2 or 4 cells per thread (256, 128 or 64 threads per box) and x = 1 for the
-// XCD-aware box mapping.  All variants do the same arithmetic on every cell.
-constexpr int kGsrbVariants = 6;
-constexpr int kGsrbDefault = 3;  // 2 cells per thread, XCD mapping
+// Gauss-Seidel launch variants: variant = 2 * c + x, with c = 0, 1, 2 for
+// half-sweeps with 1, 2 or 4 cells per thread (256, 128 or 64 threads per
+// box), c = 3 for fused sweeps (red and black in one launch, ping-ponging
+// between the field and a second buffer), and x = 1 for the XCD-aware box
+// mapping.  All variants do the same arithmetic on every cell.
+constexpr int kGsrbVariants = 8;
+constexpr int kGsrbHalfVariants = 6;  // variants 0..5 are half-sweeps
+constexpr int kGsrbDefault = 3;       // 2 cells per thread, XCD mapping
+// One colour in place; a fused variant falls back to kGsrbDefault.
 template <typename T>
 void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
                  int colour, int variant, hipStream_t s);
+// One full sweep (red, then black) from src into dst (no aliasing).
+template <typename T>
+void launch_gsrb_sweep(const Geo &g, const T *src, T *dst, const T *rhs, const T *chat, int64_t b0,
+                       int64_t nb, T h2, int xcd, hipStream_t s);
 template <typename T>
 void launch_cf_coarse(const Geo &g, const T *phi, T *chat, const int32_t *slots, int64_t s0,
                       int64_t ns, hipStream_t s);
@@ -50,6 +59,15 @@ void launch_coarse(const Geo &g, T *phi, const T *rhs, const double *eig, int64_
                    double h, hipStream_t s);
 template <typename T>
 void launch_restrict_phi(const Geo &g, T *phi, int64_t b0, int64_t nb, hipStream_t s);
+// Bottom of the V-cycle (levels 1 and 2 of every tree) in one launch, one
+// workgroup per tree: smooth(2, nd), residual + restriction + FAS rhs, root
+// solve, prolongation, smooth(2, nu); fmg != 0 prepends the FMG pass's
+// restriction, root solve and prolongation.  h2, h1: cell sizes of levels 2
+// and 1; root2[t]: first level-2 box of tree t, or -1.
+template <typename T>
+void launch_bottom(const Geo &g, T *phi, T *rhs, T *old, const double *eig, int64_t r0, int ntree,
+                   const int32_t *root2, double h2, double h1, int nd, int nu, int fmg,
+                   hipStream_t s);
 void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const double *chat,
                        const int32_t *leaf, int64_t nleaf, double *partial, float *r_out,
                        hipStream_t s);

@@ -46,6 +46,21 @@ __device__ __forceinline__ void tangential(int a, int &t1, int &t2) {
     t2 = a == 2 ? 1 : 2;
 }
 
+// Ghost values: Dirichlet face value gv reflected through the boundary cell,
+// and the refinement-boundary quadratic through the coarse value ch and the
+// first two interior fine cells.  Every kernel evaluates them through these
+// two functions, so all paths round identically.
+template <typename T> __device__ __forceinline__ T dirichlet_ghost(T gv, T own) {
+    return (T)2 * gv - own;
+}
+template <typename T> __device__ __forceinline__ T cf_ghost(T ch, T own, T inward) {
+    return (T)kCfCoarse * ch + (T)kCfFine1 * own - (T)kCfFine2 * inward;
+}
+template <typename T>
+__device__ __forceinline__ T bc_value(const Geo &g, int64_t b, int d, int u, int v) {
+    return (T)(g.bcval ? g.bcval[(b * 6 + d) * 64 + v * 8 + u] : g.bcv[d]);
+}
+
 // Ghost of face cell (u, v) on face d of box b, read straight from global
 // memory.  nb = nbr[b][d]; slot = cfslot[b][d].  T is the field type (double,
 // or float for the correction cycles of the mixed-precision solve).
@@ -66,13 +81,11 @@ __device__ __forceinline__ T ghost_at(const Geo &g, const T *__restrict__ phi,
     T own = phi[b * 512 + cs_idx3(c)];
     if (nb == -2) {
         if (g.bct[d] == 1) return own;
-        T gv = (T)(g.bcval ? g.bcval[(b * 6 + d) * 64 + v * 8 + u] : g.bcv[d]);
-        return (T)2 * gv - own;
+        return dirichlet_ghost<T>(bc_value<T>(g, b, d, u, v), own);
     }
     c[a] = side ? 6 : 1;
     T inward = phi[b * 512 + cs_idx3(c)];
-    return (T)kCfCoarse * chat[(int64_t)slot * 64 + v * 8 + u] + (T)kCfFine1 * own -
-           (T)kCfFine2 * inward;
+    return cf_ghost<T>(chat[(int64_t)slot * 64 + v * 8 + u], own, inward);
 }
 
 // The face tables of box b, read with block-uniform addresses (scalar loads
@@ -216,6 +229,138 @@ __global__ __launch_bounds__(256 / CPT) void k_gsrb(Geo g, T *__restrict__ phi,
         out[w] = (s - h2 * bb[w]) * (T)kSixth;
     }
     reinterpret_cast<V *>(phi + b * 512 + C * 256)[t] = res;
+}
+
+// One full red-black sweep (red half, then black half) of boxes [b0, b0+nbx)
+// of one level, reading src and writing both colours to dst (src is left
+// unchanged, dst must not alias it).  The values are those of the two
+// half-sweeps of k_gsrb: the black half needs the new red values of the
+// neighbours' face layers, so each box recomputes the 6 x 32 red cells of its
+// same-level face neighbours that touch its black face cells, with the red
+// update's own arithmetic on the old field (a red cell reads only black cells
+// and ghosts).  Their inputs are staged in LDS once: the neighbour's adjacent
+// layer of black cells (which are also the ghosts of this box's red face
+// cells), its second layer under the recomputed cells, their right-hand
+// side, and the ghosts of the recomputed cells on the neighbour's edges.  One
+// launch per sweep instead of two, with the same 24 B per cell plus the
+// neighbours' face layers.  256 threads per box; thread t owns red cell t
+// and black cell 256 + t (colour-split order), and for t < 192 face entry t:
+// face d = t / 32, position q = t % 32 in the layer.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gsrb_sweep(Geo g, const T *__restrict__ src,
+                                                    T *__restrict__ dst, const T *__restrict__ rhs,
+                                                    const T *__restrict__ chat, int64_t b0,
+                                                    int64_t nbx, T h2, int xcd) {
+    // P: red part = new red values (after the red half), black part = old
+    // black values.  HR: ghosts of the red face cells (old field).  D2, BH:
+    // second-layer black value and right-hand side of each recomputed red
+    // cell.  EG: ghosts of the recomputed cells across the neighbour's
+    // tangential faces (4 edges x 4 cells per face).  HB: per black face
+    // cell, the recomputed red value across a same-level face, the Dirichlet
+    // value at a domain face, or c_hat at a refinement boundary.
+    __shared__ T P[512], HR[192], D2[192], BH[192], EG[96], HB[192];
+    int64_t lb = xcd ? xcd_map(blockIdx.x, nbx) : (int64_t)blockIdx.x;
+    if (lb >= nbx) return;
+    int64_t b = b0 + lb;
+    int t = threadIdx.x;
+    const FaceTab ft = face_tab(g, b);
+    T ob = src[b * 512 + 256 + t];
+    T br = rhs[b * 512 + t], bb = rhs[b * 512 + 256 + t];
+    // face entry of this thread (t < 192): the black face cell (ub, v) of
+    // face d, u along t1 and v along t2, at layer lx of this box
+    int fd = t >> 5, fq = t & 31, fv = fq >> 2;
+    int fa = fd >> 1, fside = fd & 1, ft1, ft2;
+    tangential(fa, ft1, ft2);
+    int flx = fside ? 7 : 0;
+    int fub = 2 * (fq & 3) + ((flx + fv + 1) & 1);
+    int fnb = t < 192 ? pick6(ft.nb, fd) : -3;
+    if (t < 192) {
+        gsrb_ghost<T>(g, ft, src, chat, b, 0, t, HR);
+        if (fnb >= 0) {
+            int c[3];
+            c[ft1] = fub;
+            c[ft2] = fv;
+            c[fa] = fside ? 1 : 6;  // neighbour's second layer
+            D2[t] = src[(int64_t)fnb * 512 + cs_idx3(c)];
+            c[fa] = fside ? 0 : 7;  // neighbour's adjacent layer: the recomputed red cell
+            BH[t] = rhs[(int64_t)fnb * 512 + cs_idx3(c)];
+            if (fq < 16) {
+                // edge e4 of the neighbour's layer (-t1, +t1, -t2, +t2), cell idx
+                int e4 = fq >> 2, idx = fq & 3;
+                int cu = e4 == 0 ? 0 : e4 == 1 ? 7 : 2 * idx + ((flx + (e4 == 2 ? 1 : 0)) & 1);
+                int cv = e4 == 2 ? 0 : e4 == 3 ? 7 : 2 * idx + ((flx + (e4 == 0 ? 1 : 0)) & 1);
+                int ax = e4 < 2 ? ft1 : ft2, s1, s2;
+                tangential(ax, s1, s2);
+                c[ft1] = cu;
+                c[ft2] = cv;
+                const int32_t *xt = g.xt + (b * 6 + fd) * 8;
+                EG[fd * 16 + fq] = ghost_at<T>(g, src, chat, fnb, 2 * ax + (e4 & 1), xt[2 * e4],
+                                               xt[2 * e4 + 1], c[s1], c[s2]);
+            }
+        } else if (fnb == -2) {
+            HB[t] = bc_value<T>(g, b, fd, fub, fv);
+        } else {
+            HB[t] = chat[(int64_t)pick6(ft.slot, fd) * 64 + fv * 8 + fub];
+        }
+    }
+    P[256 + t] = ob;
+    __syncthreads();
+    int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
+    int row = (k * 8 + j) * 4;
+    {  // red cell (i + j + k even)
+        int i = 2 * m + ((j + k) & 1);
+        const T *S = P + 256;
+        T xm = i > 0 ? S[row + ((i - 1) >> 1)] : HR[0 * 32 + k * 4 + (j >> 1)];
+        T xp = i < 7 ? S[row + ((i + 1) >> 1)] : HR[1 * 32 + k * 4 + (j >> 1)];
+        T ym = j > 0 ? S[row - 4 + m] : HR[2 * 32 + k * 4 + m];
+        T yp = j < 7 ? S[row + 4 + m] : HR[3 * 32 + k * 4 + m];
+        T zm = k > 0 ? S[row - 32 + m] : HR[4 * 32 + j * 4 + m];
+        T zp = k < 7 ? S[row + 32 + m] : HR[5 * 32 + j * 4 + m];
+        T s = xm + xp + ym + yp + zm + zp;
+        T nr = (s - h2 * br) * (T)kSixth;
+        P[t] = nr;
+        dst[b * 512 + t] = nr;
+    }
+    if (fnb >= 0) {  // recomputed red cell of the same-level neighbour
+        const T *R = HR + fd * 32;
+        const T *E = EG + fd * 16;
+        int cx[3];
+        cx[fa] = flx;
+        cx[ft1] = fub;
+        cx[ft2] = fv;
+        T toward = P[cs_idx3(cx)];  // this box's black face cell (old)
+        T away = D2[t];
+        T nm = fside ? toward : away, np = fside ? away : toward;
+        T um = fub == 0 ? E[0 + (fv >> 1)] : R[fv * 4 + ((fub - 1) >> 1)];
+        T up = fub == 7 ? E[4 + (fv >> 1)] : R[fv * 4 + ((fub + 1) >> 1)];
+        T vm = fv == 0 ? E[8 + (fub >> 1)] : R[(fv - 1) * 4 + (fub >> 1)];
+        T vp = fv == 7 ? E[12 + (fub >> 1)] : R[(fv + 1) * 4 + (fub >> 1)];
+        // axes: a = 0 -> (n, u, v); a = 1 -> (u, n, v); a = 2 -> (u, v, n)
+        T xm = fa == 0 ? nm : um, xp = fa == 0 ? np : up;
+        T ym = fa == 0 ? um : fa == 1 ? nm : vm, yp = fa == 0 ? up : fa == 1 ? np : vp;
+        T zm = fa == 2 ? nm : vm, zp = fa == 2 ? np : vp;
+        T s = xm + xp + ym + yp + zm + zp;
+        HB[t] = (s - h2 * BH[t]) * (T)kSixth;
+    }
+    __syncthreads();
+    {  // black cell: neighbours are new red values; face ghosts as in the
+       // black half-sweep (own = the old black value, inward = new red)
+        int i = 2 * m + ((j + k + 1) & 1);
+        auto face = [&](int d, T hv, T inward) -> T {
+            int nb = pick6(ft.nb, d);
+            if (nb >= 0) return hv;
+            if (nb == -2) return g.bct[d] == 1 ? ob : dirichlet_ghost<T>(hv, ob);
+            return cf_ghost<T>(hv, ob, inward);
+        };
+        T xm = i > 0 ? P[row + ((i - 1) >> 1)] : face(0, HB[0 * 32 + k * 4 + (j >> 1)], P[row]);
+        T xp = i < 7 ? P[row + ((i + 1) >> 1)] : face(1, HB[1 * 32 + k * 4 + (j >> 1)], P[row + 3]);
+        T ym = j > 0 ? P[row - 4 + m] : face(2, HB[2 * 32 + k * 4 + m], P[row + 4 + m]);
+        T yp = j < 7 ? P[row + 4 + m] : face(3, HB[3 * 32 + k * 4 + m], P[row - 4 + m]);
+        T zm = k > 0 ? P[row - 32 + m] : face(4, HB[4 * 32 + j * 4 + m], P[row + 32 + m]);
+        T zp = k < 7 ? P[row + 32 + m] : face(5, HB[5 * 32 + j * 4 + m], P[row - 32 + m]);
+        T s = xm + xp + ym + yp + zm + zp;
+        dst[b * 512 + 256 + t] = (s - h2 * bb) * (T)kSixth;
+    }
 }
 
 // Coarse value of cell D = C + dir * e_ax (level l-1, relative to box Q),
@@ -478,6 +623,226 @@ __global__ __launch_bounds__(512) void k_coarse(Geo g, T *__restrict__ phi, cons
     phi[b * 512 + cs_idx(i, j, k)] = (T)X[t];
 }
 
+// ------------------------------------------------- bottom of the V-cycle
+// The two coarsest levels of every tree in one launch, one workgroup of 512
+// threads per tree: Gauss-Seidel on the tree's eight level-2 boxes,
+// residual and restriction to the root, the root's FAS right-hand side, its
+// exact solve, prolongation of the correction and the up-sweeps, with the
+// level-2 field and right-hand side and the root's fields in LDS.  The ~20
+// dependent steps cost a workgroup barrier each instead of a launch each; the
+// arithmetic of every cell is that of k_gsrb, k_resid_restrict, k_fas_rhs,
+// k_coarse and k_prolong_cf.  Level 2 of a tree is empty or all 8 children
+// of the root, in Morton (= octant) order from root2[tree]; their faces are
+// sibling faces inside the root and domain faces outside it, never
+// refinement boundaries.  fmg != 0 first runs the FMG pass's own bottom
+// (restriction, root solve, prolongation, without smoothing).
+template <typename T>
+__device__ __forceinline__ T bot_ghost(const Geo &g, const T *F2, int o, int64_t gid, int d, int u,
+                                       int v, T own) {
+    int a = d >> 1, side = d & 1;
+    if (((o >> a) & 1) != side) {  // sibling across the face: mirrored layer
+        int L = side ? 0 : 7;
+        int ci = a == 0 ? L : u, cj = a == 0 ? u : a == 1 ? L : v, ck = a == 2 ? L : v;
+        return F2[(o ^ (1 << a)) * 512 + cs_idx(ci, cj, ck)];
+    }
+    if (g.bct[d] == 1) return own;
+    return dirichlet_ghost<T>(bc_value<T>(g, gid, d, u, v), own);
+}
+template <typename T>
+__device__ __forceinline__ T root_ghost(const Geo &g, int64_t r, int d, int u, int v, T own) {
+    if (g.bct[d] == 1) return own;
+    return dirichlet_ghost<T>(bc_value<T>(g, r, d, u, v), own);
+}
+
+template <typename T>
+__device__ __forceinline__ T bot_resid(const Geo &g, const T *F2, const T *B2, int o, int64_t gid,
+                                       int i, int j, int k, T inv_h2) {
+    const T *P = F2 + o * 512;
+    T own = P[cs_idx(i, j, k)];
+    T xm = i > 0 ? P[cs_idx(i - 1, j, k)] : bot_ghost<T>(g, F2, o, gid, 0, j, k, own);
+    T xp = i < 7 ? P[cs_idx(i + 1, j, k)] : bot_ghost<T>(g, F2, o, gid, 1, j, k, own);
+    T ym = j > 0 ? P[cs_idx(i, j - 1, k)] : bot_ghost<T>(g, F2, o, gid, 2, i, k, own);
+    T yp = j < 7 ? P[cs_idx(i, j + 1, k)] : bot_ghost<T>(g, F2, o, gid, 3, i, k, own);
+    T zm = k > 0 ? P[cs_idx(i, j, k - 1)] : bot_ghost<T>(g, F2, o, gid, 4, i, j, own);
+    T zp = k < 7 ? P[cs_idx(i, j, k + 1)] : bot_ghost<T>(g, F2, o, gid, 5, i, j, own);
+    T s = xm + xp + ym + yp + zm + zp;
+    return B2[o * 512 + cs_idx(i, j, k)] - (s - (T)6 * own) * inv_h2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_bottom(Geo g, T *__restrict__ phi, T *__restrict__ rhs,
+                                                T *__restrict__ old, const double *__restrict__ eig,
+                                                int64_t r0, const int32_t *__restrict__ root2,
+                                                T h2_2, T inv_h2_2, T inv_h2_1, double h1, int nd,
+                                                int nu, int fmg) {
+    __shared__ T F2[4096], B2[4096], F1[512], B1[512], O1[512];
+    __shared__ double X[512], Y[512], V[192], L[24];
+    int tid = threadIdx.x;
+    int64_t r = r0 + blockIdx.x;
+    int64_t first2 = root2[blockIdx.x];
+    bool has2 = first2 >= 0;
+    if (tid < 192) V[tid] = eig[tid];
+    if (tid < 24) L[tid] = eig[192 + tid];
+    F1[tid] = phi[r * 512 + tid];
+    B1[tid] = rhs[r * 512 + tid];
+    if (has2) {
+#pragma unroll
+        for (int w = 0; w < 8; w++) {
+            F2[tid + 512 * w] = phi[first2 * 512 + tid + 512 * w];
+            B2[tid + 512 * w] = rhs[first2 * 512 + tid + 512 * w];
+        }
+    }
+    __syncthreads();
+
+    auto half_sweep = [&](int C) __attribute__((always_inline)) {
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+            int q = tid + 512 * w, o = q >> 8, t = q & 255;
+            int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
+            int i = 2 * m + ((j + k + C) & 1);
+            int row = (k * 8 + j) * 4;
+            const T *S = F2 + o * 512 + (1 - C) * 256;
+            T own = F2[o * 512 + C * 256 + t];
+            int64_t gid = first2 + o;
+            T xm = i > 0 ? S[row + ((i - 1) >> 1)] : bot_ghost<T>(g, F2, o, gid, 0, j, k, own);
+            T xp = i < 7 ? S[row + ((i + 1) >> 1)] : bot_ghost<T>(g, F2, o, gid, 1, j, k, own);
+            T ym = j > 0 ? S[row - 4 + m] : bot_ghost<T>(g, F2, o, gid, 2, i, k, own);
+            T yp = j < 7 ? S[row + 4 + m] : bot_ghost<T>(g, F2, o, gid, 3, i, k, own);
+            T zm = k > 0 ? S[row - 32 + m] : bot_ghost<T>(g, F2, o, gid, 4, i, j, own);
+            T zp = k < 7 ? S[row + 32 + m] : bot_ghost<T>(g, F2, o, gid, 5, i, j, own);
+            T s = xm + xp + ym + yp + zm + zp;
+            F2[o * 512 + C * 256 + t] = (s - h2_2 * B2[o * 512 + C * 256 + t]) * (T)kSixth;
+        }
+        __syncthreads();
+    };
+    auto smooth = [&](int n) __attribute__((always_inline)) {
+        for (int it = 0; it < n; it++) {
+            half_sweep(0);
+            half_sweep(1);
+        }
+    };
+    // residual of level 2, restriction to the root, FAS right-hand side of
+    // the root; a leaf root only copies phi -> old
+    auto down = [&]() __attribute__((always_inline)) {
+        if (!has2) {
+            O1[tid] = F1[tid];
+            __syncthreads();
+            return;
+        }
+        {
+            int o = tid >> 6, pt = tid & 63;
+            int pi = pt & 3, pj = (pt >> 2) & 3, pk = pt >> 4;
+            T sphi = 0, sres = 0;
+            for (int dk = 0; dk < 2; dk++)
+                for (int dj = 0; dj < 2; dj++)
+                    for (int di = 0; di < 2; di++) {
+                        int fi = 2 * pi + di, fj = 2 * pj + dj, fk = 2 * pk + dk;
+                        sphi += F2[o * 512 + cs_idx(fi, fj, fk)];
+                        sres += bot_resid<T>(g, F2, B2, o, first2 + o, fi, fj, fk, inv_h2_2);
+                    }
+            int pc = cs_idx(4 * (o & 1) + pi, 4 * ((o >> 1) & 1) + pj, 4 * (o >> 2) + pk);
+            T mphi = (T)0.125 * sphi;
+            F1[pc] = mphi;
+            O1[pc] = mphi;
+            B1[pc] = (T)0.125 * sres;
+        }
+        __syncthreads();
+        {
+            int i = tid & 7, j = (tid >> 3) & 7, k = tid >> 6;
+            int c = cs_idx(i, j, k);
+            T own = F1[c];
+            T xm = i > 0 ? F1[cs_idx(i - 1, j, k)] : root_ghost<T>(g, r, 0, j, k, own);
+            T xp = i < 7 ? F1[cs_idx(i + 1, j, k)] : root_ghost<T>(g, r, 1, j, k, own);
+            T ym = j > 0 ? F1[cs_idx(i, j - 1, k)] : root_ghost<T>(g, r, 2, i, k, own);
+            T yp = j < 7 ? F1[cs_idx(i, j + 1, k)] : root_ghost<T>(g, r, 3, i, k, own);
+            T zm = k > 0 ? F1[cs_idx(i, j, k - 1)] : root_ghost<T>(g, r, 4, i, j, own);
+            T zp = k < 7 ? F1[cs_idx(i, j, k + 1)] : root_ghost<T>(g, r, 5, i, j, own);
+            T s = xm + xp + ym + yp + zm + zp;
+            T rn = (s - (T)6 * own) * inv_h2_1 + B1[c];
+            __syncthreads();
+            B1[c] = rn;
+        }
+        __syncthreads();
+    };
+    // exact root solve, as k_coarse
+    auto coarse = [&]() __attribute__((always_inline)) {
+        int i = tid & 7, j = (tid >> 3) & 7, k = tid >> 6;
+        double rr = (double)B1[cs_idx(i, j, k)];
+#pragma unroll
+        for (int d = 0; d < 6; d++) {
+            int a = d >> 1, sd = d & 1;
+            int ca = a == 0 ? i : a == 1 ? j : k;
+            int u = a == 0 ? j : i, v = a == 2 ? j : k;  // coordinates along the tangential axes
+            bool edge = sd ? (ca == 7) : (ca == 0);
+            if (edge && g.bct[d] == 0) {
+                double gv = g.bcval ? g.bcval[(r * 6 + d) * 64 + v * 8 + u] : g.bcv[d];
+                rr -= 2.0 * gv / (h1 * h1);
+            }
+        }
+        int t = tid;
+        X[t] = rr;
+        __syncthreads();
+        { double s = 0; for (int q = 0; q < 8; q++) s += V[0 * 64 + q * 8 + i] * X[(k * 8 + j) * 8 + q]; Y[t] = s; }
+        __syncthreads();
+        { double s = 0; for (int q = 0; q < 8; q++) s += V[1 * 64 + q * 8 + j] * Y[(k * 8 + q) * 8 + i]; X[t] = s; }
+        __syncthreads();
+        { double s = 0; for (int q = 0; q < 8; q++) s += V[2 * 64 + q * 8 + k] * X[(q * 8 + j) * 8 + i]; Y[t] = s; }
+        __syncthreads();
+        Y[t] = Y[t] * (h1 * h1) / (L[i] + L[8 + j] + L[16 + k]);
+        __syncthreads();
+        { double s = 0; for (int q = 0; q < 8; q++) s += V[2 * 64 + k * 8 + q] * Y[(q * 8 + j) * 8 + i]; X[t] = s; }
+        __syncthreads();
+        { double s = 0; for (int q = 0; q < 8; q++) s += V[1 * 64 + j * 8 + q] * X[(k * 8 + q) * 8 + i]; Y[t] = s; }
+        __syncthreads();
+        { double s = 0; for (int q = 0; q < 8; q++) s += V[0 * 64 + i * 8 + q] * Y[(k * 8 + j) * 8 + q]; X[t] = s; }
+        F1[cs_idx(i, j, k)] = (T)X[t];
+        __syncthreads();
+    };
+    // correction delta = phi - old of the root at cell C (one coordinate may
+    // lie one cell outside: homogeneous domain ghost)
+    auto delta = [&](int cx, int cy, int cz) __attribute__((always_inline)) -> T {
+        int face = cx < 0 ? 0 : cx > 7 ? 1 : cy < 0 ? 2 : cy > 7 ? 3 : cz < 0 ? 4 : cz > 7 ? 5 : -1;
+        int q = cs_idx(min(max(cx, 0), 7), min(max(cy, 0), 7), min(max(cz, 0), 7));
+        T din = F1[q] - O1[q];
+        if (face < 0) return din;
+        return g.bct[face] == 1 ? din : -din;
+    };
+    auto prolong = [&]() __attribute__((always_inline)) {
+        if (!has2) return;
+#pragma unroll 2
+        for (int w = 0; w < 8; w++) {
+            int q = tid + 512 * w, o = q >> 9, e = q & 511, cc = e >> 8, t = e & 255;
+            int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
+            int i = 2 * m + ((j + k + cc) & 1);
+            int X0 = 4 * (o & 1) + (i >> 1), Y0 = 4 * ((o >> 1) & 1) + (j >> 1), Z0 = 4 * (o >> 2) + (k >> 1);
+            int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+            T d0 = delta(X0, Y0, Z0), dx = delta(X0 + sx, Y0, Z0), dy = delta(X0, Y0 + sy, Z0),
+              dz = delta(X0, Y0, Z0 + sz);
+            F2[q] += (T)0.25 * d0 + (T)0.25 * (dx + dy + dz);
+        }
+        __syncthreads();
+    };
+
+    if (fmg) {
+        down();
+        coarse();
+        prolong();
+    }
+    if (has2) smooth(nd);
+    down();
+    coarse();
+    prolong();
+    if (has2) smooth(nu);
+
+    phi[r * 512 + tid] = F1[tid];
+    rhs[r * 512 + tid] = B1[tid];
+    old[r * 512 + tid] = O1[tid];
+    if (has2) {
+#pragma unroll
+        for (int w = 0; w < 8; w++) phi[first2 * 512 + tid + 512 * w] = F2[tid + 512 * w];
+    }
+}
+
 // Covered cells of level l-1 <- mean of their 8 children on level l.
 template <typename T>
 __global__ __launch_bounds__(64) void k_restrict_phi(Geo g, T *__restrict__ phi, int64_t b0,
@@ -678,9 +1043,18 @@ void launch_gsrb_cpt(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t 
 }
 
 template <typename T>
+void launch_gsrb_sweep(const Geo &g, const T *src, T *dst, const T *rhs, const T *chat, int64_t b0,
+                       int64_t nb, T h2, int xcd, hipStream_t s) {
+    if (nb <= 0) return;
+    dim3 grid((unsigned)(xcd ? xcd_grid(nb) : nb));
+    hipLaunchKernelGGL(k_gsrb_sweep<T>, grid, dim3(256), 0, s, g, src, dst, rhs, chat, b0, nb, h2, xcd);
+}
+
+template <typename T>
 void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
                  int colour, int variant, hipStream_t s) {
     if (nb <= 0) return;
+    if (variant >= kGsrbHalfVariants) variant = kGsrbDefault;
     int xcd = variant & 1;
     switch (variant >> 1) {
     case 0: launch_gsrb_cpt<T, 1>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s); break;
@@ -722,6 +1096,13 @@ template <typename T>
 void launch_coarse(const Geo &g, T *phi, const T *rhs, const double *eig, int64_t b0, int64_t nroot,
                    double h, hipStream_t s) {
     hipLaunchKernelGGL(k_coarse<T>, dim3((unsigned)nroot), dim3(512), 0, s, g, phi, rhs, eig, b0, h);
+}
+template <typename T>
+void launch_bottom(const Geo &g, T *phi, T *rhs, T *old, const double *eig, int64_t r0, int ntree,
+                   const int32_t *root2, double h2, double h1, int nd, int nu, int fmg,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_bottom<T>, dim3((unsigned)ntree), dim3(512), 0, s, g, phi, rhs, old, eig, r0, root2,
+                       (T)(h2 * h2), (T)(1.0 / (h2 * h2)), (T)(1.0 / (h1 * h1)), h1, nd, nu, fmg);
 }
 template <typename T>
 void launch_restrict_phi(const Geo &g, T *phi, int64_t b0, int64_t nb, hipStream_t s) {
@@ -768,6 +1149,8 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
     template void launch_unpack<T>(const T *, double *, int64_t, hipStream_t);                   \
     template void launch_gsrb<T>(const Geo &, T *, const T *, const T *, int64_t, int64_t, T, int, \
                                  int, hipStream_t);                                              \
+    template void launch_gsrb_sweep<T>(const Geo &, const T *, T *, const T *, const T *, int64_t, \
+                                       int64_t, T, int, hipStream_t);                            \
     template void launch_cf_coarse<T>(const Geo &, const T *, T *, const int32_t *, int64_t,     \
                                       int64_t, hipStream_t);                                     \
     template void launch_resid_restrict<T>(const Geo &, T *, T *, T *, const T *, int64_t,       \
@@ -778,7 +1161,9 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
                                        const int32_t *, int64_t, int64_t, hipStream_t);          \
     template void launch_coarse<T>(const Geo &, T *, const T *, const double *, int64_t, int64_t, \
                                    double, hipStream_t);                                         \
-    template void launch_restrict_phi<T>(const Geo &, T *, int64_t, int64_t, hipStream_t);
+    template void launch_restrict_phi<T>(const Geo &, T *, int64_t, int64_t, hipStream_t);        \
+    template void launch_bottom<T>(const Geo &, T *, T *, T *, const double *, int64_t, int,     \
+                                   const int32_t *, double, double, int, int, int, hipStream_t);
 MG_INSTANTIATE(double)
 MG_INSTANTIATE(float)
 #undef MG_INSTANTIATE

@@ -48,6 +48,7 @@ Geo geo(const mg_tree *t, bool homogeneous) {
     g.nbr = t->d.nbr;
     g.cfslot = t->d.cfslot;
     g.cfq = t->d.cfq;
+    g.xt = t->d.xt;
     g.ijk = t->d.ijk;
     g.parent = t->d.parent;
     g.bcval = (!homogeneous && t->dom.per_cell_bc) ? t->d.bcval : nullptr;
@@ -118,13 +119,28 @@ template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsw
         }
     }
     int variant = t->sched[sizeof(T) == 4 ? 1 : 0][l];
-    for (int it = 0; it < nsweep; it++)
-        for (int c = 0; c < 2; c++)
+    int64_t launches = 0;
+    int it = 0;
+    if (variant >= kGsrbHalfVariants) {
+        // fused sweeps in pairs: field -> sweep buffer -> field
+        T *swp = (T *)t->d.swp;
+        for (; it + 1 < nsweep; it += 2) {
+            launch_gsrb_sweep<T>(F.g, F.phi, swp, F.rhs, F.chat, lbeg(t, l), lcount(t, l), h2,
+                                 variant & 1, stream_of(t));
+            launch_gsrb_sweep<T>(F.g, swp, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l), h2,
+                                 variant & 1, stream_of(t));
+            launches += 2;
+        }
+    }
+    for (; it < nsweep; it++)  // half-sweeps (a fused schedule's odd last sweep: the default)
+        for (int c = 0; c < 2; c++) {
             launch_gsrb<T>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l), h2, c, variant,
                            stream_of(t));
+            launches++;
+        }
     if (e0) {
         if (hipEventRecord(e1, stream_of(t)) == hipSuccess) {
-            t->probes.push_back({(void *)e0, (void *)e1, l, 2 * (int64_t)nsweep,
+            t->probes.push_back({(void *)e0, (void *)e1, l, launches,
                                  3.0 * 256 * sizeof(T) * (double)lcount(t, l) * 2 * nsweep});
         } else {
             give_event(t, e0);
@@ -170,13 +186,35 @@ template <typename T> void restrict_all(mg_tree *t, const Fields<T> &F) {
     }
 }
 
+// Levels 1 and 2 as one launch (one workgroup per tree)?
+template <typename T> bool use_bottom(const mg_tree *t) {
+    return t->bottom_ok && t->sched[sizeof(T) == 4 ? 1 : 0][1] != 0;
+}
+
+// The bottom of the cycle in one launch: smooth(2, nd), fas_down(2),
+// coarse, prolong(2), smooth(2, nu); with fmg, preceded by fas_down(2),
+// coarse, prolong(2).  Leaves the c_hat state as that sequence does (level 2
+// has no refinement-boundary faces, so it launches no c_hat pass).
+template <typename T> void bottom(mg_tree *t, const Fields<T> &F, int nd, int nu, bool fmg) {
+    launch_bottom<T>(F.g, F.phi, F.rhs, F.old, t->d.eig, lbeg(t, 1), t->ntree, t->d.root2, hlev(t, 2),
+                     hlev(t, 1), nd, nu, fmg ? 1 : 0, stream_of(t));
+    F.cf_valid[2] = true;
+    dirty(F, 2);
+}
+
 template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int nd, int nu) {
-    for (int l = top; l >= 2; l--) {
+    bool one = use_bottom<T>(t) && top >= 2;
+    int low = one ? 3 : 2;
+    for (int l = top; l >= low; l--) {
         smooth(t, F, l, nd);
         fas_down(t, F, l);
     }
-    coarse(t, F);
-    for (int l = 2; l <= top; l++) {
+    if (one) {
+        bottom(t, F, nd, nu, false);
+    } else {
+        coarse(t, F);
+    }
+    for (int l = low; l <= top; l++) {
         prolong(t, F, l);
         smooth(t, F, l, nu);
     }
@@ -185,9 +223,15 @@ template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int n
 // FMG pass from the current (zero) field: FAS data top-down, root solve, then
 // for each finer level the prolonged correction and one V-cycle on top.
 template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int nu) {
-    for (int l = t->nlev; l >= 2; l--) fas_down(t, F, l);
-    coarse(t, F);
-    for (int l = 2; l <= t->nlev; l++) {
+    bool one = use_bottom<T>(t);
+    int low = one ? 3 : 2;
+    for (int l = t->nlev; l >= low; l--) fas_down(t, F, l);
+    if (one) {
+        bottom(t, F, nd, nu, true);  // fas_down(2), coarse, prolong(2), V-cycle(2)
+    } else {
+        coarse(t, F);
+    }
+    for (int l = low; l <= t->nlev; l++) {
         prolong(t, F, l);
         vcycle(t, F, l, nd, nu);
     }
@@ -743,6 +787,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.nbr = (int32_t *)(base + t->off.nbr);
     d.cfslot = (int32_t *)(base + t->off.cfslot);
     d.cfq = (int32_t *)(base + t->off.cfq);
+    d.xt = (int32_t *)(base + t->off.xt);
     d.ijk = (int32_t *)(base + t->off.ijk);
     d.parent = (int32_t *)(base + t->off.parent);
     d.refined = (int32_t *)(base + t->off.refined);
@@ -755,6 +800,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.part2 = (double *)(base + t->off.part2);
     d.isleaf = (int32_t *)(base + t->off.isleaf);
     d.tid = (int32_t *)(base + t->off.tid);
+    d.root2 = (int32_t *)(base + t->off.root2);
     d.eig = (double *)(base + t->off.eig);
     d.phi = (double *)(base + t->off.phi);
     d.rhs = (double *)(base + t->off.rhs);
@@ -767,6 +813,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.r32 = (float *)(base + t->off.r32);
     d.old32 = (float *)(base + t->off.old32);
     d.chat32 = (float *)(base + t->off.chat32);
+    d.swp = (void *)(base + t->off.swp);
     if (!t->host_result) {
         int rc = hip_check(hipHostMalloc((void **)&t->host_result, 4 * t->ntree * sizeof(double)),
                            "pinned host buffer");
@@ -787,6 +834,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     rc = rc ? rc : up(d.nbr, t->nbr.data(), t->nbr.size() * 4);
     rc = rc ? rc : up(d.cfslot, t->cfslot.data(), t->cfslot.size() * 4);
     rc = rc ? rc : up(d.cfq, t->cfq.data(), t->cfq.size() * 4);
+    rc = rc ? rc : up(d.xt, t->xt.data(), t->xt.size() * 4);
     rc = rc ? rc : up(d.ijk, ijk4.data(), ijk4.size() * 4);
     rc = rc ? rc : up(d.parent, t->parent.data(), t->parent.size() * 4);
     rc = rc ? rc : up(d.refined, t->refined.data(), t->refined.size() * 4);
@@ -798,6 +846,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     rc = rc ? rc : up(d.choff, t->choff.data(), t->choff.size() * 4);
     rc = rc ? rc : up(d.isleaf, isleaf.data(), isleaf.size() * 4);
     rc = rc ? rc : up(d.tid, t->tid.data(), t->tid.size() * 4);
+    rc = rc ? rc : up(d.root2, t->root2.data(), t->root2.size() * 4);
     rc = rc ? rc : up(d.eig, t->eig, sizeof t->eig);
     if (rc) return rc;
     launch_fill<double>(d.phi, 512 * t->n, 0.0, s);
@@ -964,8 +1013,8 @@ int mg_tree_residuals(const mg_tree *t, double *rel) {
 int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule) {
     int rc = require_bound(t);
     if (rc) return rc;
-    if ((precision != MG_FP64 && precision != MG_MIXED) || reps < 1 || reps > 1000) {
-        set_error("invalid autotune arguments");
+    if ((precision != MG_FP64 && precision != MG_MIXED) || reps < 2 || reps > 1000 || (reps & 1)) {
+        set_error("invalid autotune arguments (reps: even, 2..1000)");
         return MG_EINVAL;
     }
     bool fp32 = precision == MG_MIXED;
@@ -981,20 +1030,35 @@ int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule) {
     void *fld = fp32 ? (void *)t->d.e32 : (void *)t->d.phi;
     void *park = fp32 ? (void *)t->d.old32 : (void *)t->d.old;
     rc = hip_check(hipMemcpyAsync(park, fld, bytes, hipMemcpyDeviceToDevice, s), "park field");
-    for (int l = 1; l <= t->nlev && !rc; l++) {
+    // level 1 is never smoothed: its entry (the bottom of the cycle as one
+    // launch or step by step) is reported as set, not timed
+    if (schedule) schedule[0] = t->sched[fp32 ? 1 : 0][1];
+    for (int l = 2; l <= t->nlev && !rc; l++) {
         double h = hlev(t, l), best = 1e30;
         int pick = kGsrbDefault;
         for (int v = 0; v < kGsrbVariants && !rc; v++) {
+            // reps half-sweeps, or reps/2 fused sweeps (the same work)
             auto sweeps = [&]() {
-                for (int q = 0; q < reps; q++) {
+                bool fused = v >= kGsrbHalfVariants;
+                for (int q = 0; q < (fused ? reps / 2 : reps); q++) {
                     if (fp32) {
                         Fields<float> F = f32(t);
-                        launch_gsrb<float>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l),
-                                           (float)(h * h), q & 1, v, s);
+                        float *a = F.phi, *w = (float *)t->d.swp;
+                        if (fused)
+                            launch_gsrb_sweep<float>(F.g, q & 1 ? w : a, q & 1 ? a : w, F.rhs, F.chat,
+                                                     lbeg(t, l), lcount(t, l), (float)(h * h), v & 1, s);
+                        else
+                            launch_gsrb<float>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l),
+                                               (float)(h * h), q & 1, v, s);
                     } else {
                         Fields<double> F = f64(t);
-                        launch_gsrb<double>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l),
-                                            h * h, q & 1, v, s);
+                        double *a = F.phi, *w = (double *)t->d.swp;
+                        if (fused)
+                            launch_gsrb_sweep<double>(F.g, q & 1 ? w : a, q & 1 ? a : w, F.rhs, F.chat,
+                                                      lbeg(t, l), lcount(t, l), h * h, v & 1, s);
+                        else
+                            launch_gsrb<double>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l),
+                                                h * h, q & 1, v, s);
                     }
                 }
             };

@@ -20,6 +20,7 @@ struct DevTables {
     int32_t *nbr = nullptr;      // [n][6]  face neighbour (-1 refinement boundary, -2 domain)
     int32_t *cfslot = nullptr;   // [n][6]  slot of a refinement-boundary face, or -1
     int32_t *cfq = nullptr;      // [n][6]  coarser box across a refinement-boundary face
+    int32_t *xt = nullptr;       // [n][6][4][2] faces of the face neighbours (fused sweep)
     int32_t *ijk = nullptr;      // [n][4]  i, j, k, level
     int32_t *parent = nullptr;   // [n]
     int32_t *refined = nullptr;  // per-level lists of boxes with children
@@ -32,6 +33,7 @@ struct DevTables {
     double *part2 = nullptr;       // [nchunk][2] first-stage sums
     int32_t *isleaf = nullptr;     // [n] 1 for a box without children
     int32_t *tid = nullptr;        // [n] tree of the box
+    int32_t *root2 = nullptr;      // [ntree] first level-2 box of the tree, or -1
     double *eig = nullptr;       // root solve: Q_x, Q_y, Q_z (8x8, column = vector), then lambda_x,y,z
     double *phi = nullptr;       // [n][2][256] colour-split
     double *rhs = nullptr;
@@ -45,6 +47,7 @@ struct DevTables {
     float *r32 = nullptr;        // its right-hand side (FP64 residual rounded, FAS data)
     float *old32 = nullptr;
     float *chat32 = nullptr;
+    void *swp = nullptr;         // [n][512] FP64 (or FP32): target of the fused sweeps
 };
 
 }  // namespace mg
@@ -53,11 +56,13 @@ struct mg_tree {
     // ---- host tables (canonical order) ----
     int64_t n = 0;
     int nlev = 0, ntree = 0;
-    std::vector<int32_t> order, lev, ijk, tid, parent, child, nbr, cfq, cfslot;
+    std::vector<int32_t> order, lev, ijk, tid, parent, child, nbr, cfq, cfslot, xt;
     int64_t lstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> refined, leaf;                 // box ids grouped by level
     int64_t rstart[mg::kMaxLevel + 2] = {0}, fstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> slots;                         // (box, face) per slot
+    std::vector<int32_t> root2;                         // first level-2 box per tree, or -1
+    bool bottom_ok = false;                             // levels 1-2 can run as one launch
     std::vector<int32_t> leaf_tree, tree_off;           // leaf positions grouped by tree
     std::vector<int32_t> chunk, choff;                  // norm-reduction chunks (tree, begin, end)
     int64_t sstart[mg::kMaxLevel + 2] = {0};            // slots of level l: [sstart[l], sstart[l+1])
@@ -65,8 +70,8 @@ struct mg_tree {
     mg_domain dom{};
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
-    struct { int64_t nbr, cfslot, cfq, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, eig,
-             phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, total; } off{};
+    struct { int64_t nbr, cfslot, cfq, xt, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
+             phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, swp, total; } off{};
     // ---- bound device state ----
     void *ws = nullptr;
     void *stream = nullptr;      // caller's stream: every replay and direct launch goes here
@@ -92,7 +97,9 @@ struct mg_tree {
     };
     enum { SEQ_FMG = 0, SEQ_VCHECK, SEQ_MIX_START, SEQ_MIX_FMG, SEQ_MIX_V, SEQ_COUNT };
     Graph graphs[SEQ_COUNT];
-    // Gauss-Seidel launch variant per level, [0] FP64, [1] FP32 (autotuner)
+    // Gauss-Seidel launch variant per level, [0] FP64, [1] FP32 (autotuner);
+    // the entry of level 1 (never smoothed) selects the bottom of the cycle:
+    // 0 = levels 1 and 2 step by step, otherwise one launch (k_bottom)
     int32_t sched[2][mg::kMaxLevel + 2];
     mg_tree() {
         for (auto &row : sched)

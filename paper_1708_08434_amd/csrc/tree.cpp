@@ -236,6 +236,22 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     }
     t->sstart[0] = 0;
     t->nslot = (int64_t)t->slots.size() / 2;
+    // faces of the face neighbours: for box b, face d with a same-level
+    // neighbour N, and the 4 faces of N across the two axes tangential to d
+    // (-t1, +t1, -t2, +t2), the pair (nbr[N][d'], cfslot[N][d']); the fused
+    // Gauss-Seidel sweep recomputes N's face layer and needs N's ghosts.
+    t->xt.assign((size_t)6 * 4 * 2 * n, -2);
+    for (int64_t b = 0; b < n; b++)
+        for (int d = 0; d < 6; d++) {
+            int32_t N = t->nbr[6 * b + d];
+            if (N < 0) continue;
+            int a = d >> 1, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+            const int tf[4] = {2 * t1, 2 * t1 + 1, 2 * t2, 2 * t2 + 1};
+            for (int q = 0; q < 4; q++) {
+                t->xt[((6 * b + d) * 4 + q) * 2] = t->nbr[6 * (int64_t)N + tf[q]];
+                t->xt[((6 * b + d) * 4 + q) * 2 + 1] = t->cfslot[6 * (int64_t)N + tf[q]];
+            }
+        }
     // per-level lists of refined and leaf boxes
     t->refined.clear();
     t->leaf.clear();
@@ -269,6 +285,13 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
         }
         t->choff[tr + 1] = (int32_t)(t->chunk.size() / 3);
     }
+    // first level-2 box of each tree (its 8 children of the root, in octant
+    // order), or -1 for a tree that is a single root box; the one-launch
+    // bottom of the V-cycle needs level 2 free of refinement boundaries,
+    // which holds because a refined root has all 8 children
+    t->root2.assign(ntree, -1);
+    for (int tr = 0; tr < ntree; tr++) t->root2[tr] = t->child[8 * (lbegin(1) + tr)];
+    t->bottom_ok = t->nlev >= 2 && t->sstart[3] == t->sstart[2];
     t->beff_tree.assign(ntree, 0.0);
     t->rel_tree.assign(ntree, 0.0);
     root_eigen(dom->bc_type, t->eig);
@@ -280,6 +303,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.nbr = take(24 * n);
     t->off.cfslot = take(24 * n);
     t->off.cfq = take(24 * n);
+    t->off.xt = take(192 * n);
     t->off.ijk = take(16 * n);
     t->off.parent = take(4 * n);
     t->off.refined = take(4 * (int64_t)t->refined.size());
@@ -292,6 +316,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.part2 = take(16 * (int64_t)(t->chunk.size() / 3));
     t->off.isleaf = take(4 * n);
     t->off.tid = take(4 * n);
+    t->off.root2 = take(4 * (int64_t)ntree);
     t->off.eig = take(8 * (3 * 64 + 3 * 8));
     t->off.phi = take(8 * kCells * n);
     t->off.rhs = take(8 * kCells * n);
@@ -304,6 +329,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.r32 = take(4 * kCells * n);
     t->off.old32 = take(4 * kCells * n);
     t->off.chat32 = take(4 * 64 * t->nslot);
+    t->off.swp = take(8 * kCells * n);
     t->off.total = o;
     return MG_OK;
 }

@@ -173,11 +173,13 @@ def test_bitwise_repeatable():
     assert np.array_equal(a, b)
 
 
-def test_linear_exact_on_gpu():
+@pytest.mark.parametrize("variant", [3, 7], ids=["half_sweeps", "fused"])
+def test_linear_exact_on_gpu(variant):
     """Section 3.1 boundary setup on an AMR tree: the GPU solution is the
     linear potential at every leaf cell."""
     bl = refine_boxes_explicit(2, [(2, 0, 0, 0), (3, 1, 1, 1), (3, 0, 1, 0), (4, 2, 2, 2)])
     g = M.Tree(bl.level, bl.ijk, None, bc_type=(1, 1, 1, 1, 0, 0), bc_val=(0, 0, 0, 0, 0, 1.0))
+    M.mg_set_schedule(g.h, M.MG_FP64, [variant] * g.nlev)
     g.set_field(M.MG_FIELD_RHS, np.zeros((g.n, 8, 8, 8)))
     g.fmg_solve(rel_tol=1e-13)
     x, y, z, h = G.cell_centres(g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK))
@@ -377,21 +379,92 @@ def test_forest_trees_match_standalone_solves():
 
 # ----------------------------------------------------------------- autotuner
 
-def test_every_gsrb_variant_gives_the_same_bits():
-    w = streamer_small()
-    g = M.Tree.from_workload(w)
+def bcval_tree():
+    """AMR tree with refinement boundaries, a Neumann face (-y) and per-cell
+    Dirichlet data on the other faces."""
+    bl = refine_boxes_explicit(2, [(2, 0, 0, 0), (3, 1, 1, 1), (3, 0, 1, 0), (4, 2, 2, 2)])
+    from workloads.configs import Workload, rhs_zero
+    w = Workload("amr_bcval", bl, rhs_zero, bc_type=(0, 0, 1, 0, 0, 0))
+    g, o = pair(w, per_cell_bc=True)
+    lv, ij = o.index(O.IDX_LEVEL), o.index(O.IDX_IJK)
+    bc = G.face_values(lv, ij, lambda x, y, z: np.sin(3 * x) + y * z)
+    g.set_field(M.MG_FIELD_BCVAL, bc)
+    o.set_bcval(bc)
+    return g, o
+
+
+@pytest.mark.parametrize("tree", ["streamer_small", "bcval"])
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_every_gsrb_variant_gives_the_same_bits(tree, fp32):
+    """Half-sweep variants and fused sweeps (both colours in one launch, the
+    neighbours' red face layers recomputed) give identical bits: V-cycles
+    (pairs of sweeps) and an odd number of sweeps (a fused pair, then a
+    half-sweep pair)."""
+    if tree == "bcval":
+        g, _ = bcval_tree()
+    else:
+        w = streamer_small()
+        g = M.Tree.from_workload(w)
     rng = np.random.default_rng(9)
     phi0 = rng.standard_normal((g.n, 8, 8, 8))
+    rhs0 = rng.standard_normal((g.n, 8, 8, 8)) * 100.0
+    if fp32:
+        phi0, rhs0 = (a.astype(np.float32).astype(np.float64) for a in (phi0, rhs0))
+    fphi, frhs = (M.MG_FIELD_E32, M.MG_FIELD_R32) if fp32 else (M.MG_FIELD_PHI, M.MG_FIELD_RHS)
+    prec, opf = (M.MG_MIXED, M.MG_OP_F32) if fp32 else (M.MG_FP64, 0)
+    g.set_field(frhs, rhs0)
+    ref = {}
+    for v in range(M.MG_GSRB_VARIANTS):
+        M.mg_set_schedule(g.h, prec, [v] * g.nlev)
+        for name, op, lev, arg in (("vcycle", M.MG_OP_VCYCLE, g.nlev, 2),
+                                   ("smooth3", M.MG_OP_SMOOTH, g.nlev, 3),
+                                   ("smooth2_mid", M.MG_OP_SMOOTH, g.nlev - 1, 2)):
+            g.set_field(fphi, phi0)
+            g.set_field(frhs, rhs0)
+            g.step(op | opf, lev, arg)
+            out = g.get_field(fphi)
+            if name not in ref:
+                ref[name] = out
+            assert np.array_equal(out, ref[name]), (tree, v, name)
+    say("variants", tree, "fp32" if fp32 else "fp64", "all", M.MG_GSRB_VARIANTS, "identical")
+
+
+@pytest.mark.parametrize("v", M.MG_GSRB_FUSED)
+def test_fused_sweeps_match_the_oracle(v):
+    """Fused sweeps against the oracle's sweep-by-sweep smoothing: per-cell
+    Dirichlet data, a Neumann face and refinement boundaries."""
+    g, o = bcval_tree()
+    M.mg_set_schedule(g.h, M.MG_FP64, [v] * g.nlev)
+    for op_g, op_o, lev, arg in ((M.MG_OP_SMOOTH, O.OP_SMOOTH, o.nlev, 2),
+                                 (M.MG_OP_SMOOTH, O.OP_SMOOTH, o.nlev - 1, 4),
+                                 (M.MG_OP_VCYCLE, O.OP_VCYCLE, o.nlev, 2)):
+        seed_fields(g, o, 41)
+        g.step(op_g, lev, arg)
+        o.step(op_o, lev, arg)
+        compare_fields(g, o, f"fused {v} op {op_g} level {lev}")
+
+
+@pytest.mark.parametrize("wname", ["uniform64", "streamer_small"])
+def test_fused_schedule_solve_parity(wname):
+    """A whole FMG solve with fused sweeps on every level matches the oracle
+    and the half-sweep solve bit for bit."""
+    w = c1() if wname == "uniform64" else streamer_small()
+    g, o = pair(w)
     g.set_rhs_from(w)
-    ref = None
-    for v in range(6):
-        M.mg_set_schedule(g.h, M.MG_FP64, [v] * g.nlev)
-        g.set_field(M.MG_FIELD_PHI, phi0)
-        g.step(M.MG_OP_VCYCLE, g.nlev, 2)
-        out = g.get_field(M.MG_FIELD_PHI)
-        if ref is None:
-            ref = out
-        assert np.array_equal(out, ref), v
+    o.set_rhs_from(w)
+    sh = g.fmg_solve()
+    ph = g.get_field(M.MG_FIELD_PHI)
+    M.mg_set_schedule(g.h, M.MG_FP64, [M.MG_GSRB_FUSED[1]] * g.nlev)
+    sf = g.fmg_solve()
+    pf = g.get_field(M.MG_FIELD_PHI)
+    so = o.fmg_solve()
+    leaf = o.leaf_mask()
+    po = o.get_field(O.PHI)
+    err = np.linalg.norm((pf - po)[leaf]) / np.linalg.norm(po[leaf])
+    say("fused solve", wname, sf["n_vcycles"], "cycles, err vs oracle", err)
+    assert sf["n_vcycles"] == so["n_vcycles"] == sh["n_vcycles"]
+    assert err <= SOLVE_TOL
+    assert np.array_equal(pf, ph)
 
 
 def test_autotune_keeps_the_solution(tmp_path, monkeypatch):
@@ -404,7 +477,7 @@ def test_autotune_keeps_the_solution(tmp_path, monkeypatch):
     p0 = g.get_field(M.MG_FIELD_PHI)
     for prec in (M.MG_FP64, M.MG_MIXED):
         sched, cached = autotune.tune(g, prec, reps=4)
-        assert not cached and len(sched) == g.nlev and all(0 <= v < 6 for v in sched)
+        assert not cached and len(sched) == g.nlev and all(0 <= v < M.MG_GSRB_VARIANTS for v in sched)
         say("autotuned", prec, sched)
     # the tuner leaves the solution in place
     assert np.array_equal(g.get_field(M.MG_FIELD_PHI), p0)
@@ -413,3 +486,93 @@ def test_autotune_keeps_the_solution(tmp_path, monkeypatch):
     assert np.array_equal(g.get_field(M.MG_FIELD_PHI), p0)
     sched2, cached = autotune.tune(g, M.MG_FP64, reps=4)
     assert cached
+
+
+# ------------------------------------------------- bottom of the V-cycle
+
+def mixed_forest_boxes():
+    """Three trees: an AMR tree, a single root box (a leaf root), and a
+    uniform two-level tree."""
+    from workloads.octree import BoxList, uniform_boxes
+    a = refine_boxes_explicit(2, [(2, 0, 0, 0), (3, 1, 1, 1), (3, 0, 1, 0), (4, 2, 2, 2)], tree=0)
+    b = BoxList([1], [[0, 0, 0]], [1])
+    c = uniform_boxes(2, tree=2)
+    return BoxList.concat([a, b, c])
+
+
+def run_both(g, fn):
+    """fn(g) with levels 1-2 stepped level by level (schedule entry 0) and as
+    one launch per tree; returns both results."""
+    out = []
+    for bot in (0, 1):
+        for prec in (M.MG_FP64, M.MG_MIXED):
+            M.mg_set_schedule(g.h, prec, [bot] + [3] * (g.nlev - 1))
+        out.append(fn(g))
+    return out
+
+
+@pytest.mark.parametrize("tree", ["uniform64", "streamer_small", "bcval", "forest3"])
+def test_bottom_kernel_gives_the_same_bits(tree):
+    """One workgroup per tree for levels 1-2 (smoothing, residual,
+    restriction, FAS right-hand side, root solve, prolongation) against the
+    same steps as separate launches: V-cycles in FP64 and FP32, and a whole
+    FMG solve."""
+    if tree == "bcval":
+        g, _ = bcval_tree()
+        rhs0 = np.random.default_rng(2).standard_normal((g.n, 8, 8, 8)) * 100.0
+    elif tree == "forest3":
+        bl = mixed_forest_boxes()
+        g = M.Tree(bl.level, bl.ijk, bl.tree, bc_type=(0, 0, 1, 0, 0, 0), bc_val=(0, 0, 0, 0, 0, 1.0))
+        rhs0 = np.random.default_rng(3).standard_normal((g.n, 8, 8, 8)) * 100.0
+    else:
+        w = c1() if tree == "uniform64" else streamer_small()
+        g = M.Tree.from_workload(w)
+        rhs0 = w.rhs(g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK))
+    rng = np.random.default_rng(11)
+    phi0 = rng.standard_normal((g.n, 8, 8, 8))
+    say("bottom", tree, g.n, "boxes", g.nlev, "levels")
+
+    def vcyc(g):
+        res = []
+        for f_phi, f_rhs, opf, conv in ((M.MG_FIELD_PHI, M.MG_FIELD_RHS, 0, lambda a: a),
+                                        (M.MG_FIELD_E32, M.MG_FIELD_R32, M.MG_OP_F32,
+                                         lambda a: a.astype(np.float32).astype(np.float64))):
+            g.set_field(f_phi, conv(phi0))
+            g.set_field(f_rhs, conv(rhs0))
+            g.step(M.MG_OP_VCYCLE | opf, g.nlev, 2)
+            res.append(g.get_field(f_phi))
+            g.set_field(f_phi, conv(phi0))
+            g.set_field(f_rhs, conv(rhs0))
+            g.step(M.MG_OP_VCYCLE | opf, 2, 3)  # V-cycle with level 2 on top, 3 sweeps
+            res.append(g.get_field(f_phi))
+        g.set_field(M.MG_FIELD_RHS, rhs0)
+        st = g.fmg_solve()
+        res.append(g.get_field(M.MG_FIELD_PHI))
+        st2 = g.fmg_solve(precision=M.MG_MIXED)
+        res.append(g.get_field(M.MG_FIELD_PHI))
+        return res, (st["n_vcycles"], st2["n_vcycles"])
+    (r0, c0), (r1, c1_) = run_both(g, vcyc)
+    assert c0 == c1_, (c0, c1_)
+    for q, (a, b) in enumerate(zip(r0, r1)):
+        assert np.array_equal(a, b), (tree, q, np.abs(a - b).max())
+
+
+def test_bottom_kernel_forest_matches_the_oracle():
+    """The mixed forest (AMR tree, leaf root, uniform tree) solved with the
+    one-launch bottom, against the oracle's forest solve."""
+    bl = mixed_forest_boxes()
+    kw = dict(bc_type=(0, 0, 1, 0, 0, 0), bc_val=(0, 0, 0, 0, 0, 1.0))
+    g = M.Tree(bl.level, bl.ijk, bl.tree, **kw)
+    o = O.OracleTree(bl.level, bl.ijk, bl.tree, (0.0, 0.0, 0.0), 1.0, kw["bc_type"], kw["bc_val"])
+    assert np.array_equal(g.index(M.MG_IDX_ORDER), o.index(O.IDX_ORDER))
+    lv, ij = o.index(O.IDX_LEVEL), o.index(O.IDX_IJK)
+    x, y, z, h = G.cell_centres(lv, ij)
+    rhs = -50.0 * np.exp(-((x - 0.4) ** 2 + (y - 0.5) ** 2 + (z - 0.6) ** 2) / 0.02)
+    g.set_field(M.MG_FIELD_RHS, rhs)
+    o.set_field(O.RHS, rhs)
+    sg, so = g.fmg_solve(), o.fmg_solve()
+    leaf = o.leaf_mask()
+    pg, po = g.get_field(M.MG_FIELD_PHI), o.get_field(O.PHI)
+    err = np.linalg.norm((pg - po)[leaf]) / np.linalg.norm(po[leaf])
+    say("bottom forest", sg["n_vcycles"], so["n_vcycles"], err)
+    assert sg["n_vcycles"] == so["n_vcycles"] and err <= SOLVE_TOL
