@@ -624,94 +624,121 @@ __global__ __launch_bounds__(512) void k_coarse(Geo g, T *__restrict__ phi, cons
 }
 
 // ------------------------------------------------- bottom of the V-cycle
-// The two coarsest levels of every tree in one launch, one workgroup of 512
+// The two coarsest levels of every tree in one launch, one workgroup of 1024
 // threads per tree: Gauss-Seidel on the tree's eight level-2 boxes,
 // residual and restriction to the root, the root's FAS right-hand side, its
-// exact solve, prolongation of the correction and the up-sweeps, with the
-// level-2 field and right-hand side and the root's fields in LDS.  The ~20
-// dependent steps cost a workgroup barrier each instead of a launch each; the
-// arithmetic of every cell is that of k_gsrb, k_resid_restrict, k_fas_rhs,
-// k_coarse and k_prolong_cf.  Level 2 of a tree is empty or all 8 children
-// of the root, in Morton (= octant) order from root2[tree]; their faces are
-// sibling faces inside the root and domain faces outside it, never
-// refinement boundaries.  fmg != 0 first runs the FMG pass's own bottom
-// (restriction, root solve, prolongation, without smoothing).
-template <typename T>
-__device__ __forceinline__ T bot_ghost(const Geo &g, const T *F2, int o, int64_t gid, int d, int u,
-                                       int v, T own) {
-    int a = d >> 1, side = d & 1;
-    if (((o >> a) & 1) != side) {  // sibling across the face: mirrored layer
-        int L = side ? 0 : 7;
-        int ci = a == 0 ? L : u, cj = a == 0 ? u : a == 1 ? L : v, ck = a == 2 ? L : v;
-        return F2[(o ^ (1 << a)) * 512 + cs_idx(ci, cj, ck)];
-    }
-    if (g.bct[d] == 1) return own;
-    return dirichlet_ghost<T>(bc_value<T>(g, gid, d, u, v), own);
-}
+// exact solve, prolongation of the correction and the up-sweeps.  Level 2 of
+// a tree is empty or all 8 children of the root (Morton = octant order from
+// root2[tree]), i.e. one uniform 16^3 grid whose only ghosts are domain
+// ghosts; it is held in LDS (colour-split, rows x fastest) with its
+// right-hand side, the doubled Dirichlet values of its six faces and the
+// root's fields (natural order), so the ~20 dependent steps cost a
+// workgroup barrier each instead of a launch each.  The arithmetic of every
+// cell, and the order of every sum, are those of k_gsrb, k_resid_restrict,
+// k_fas_rhs, k_coarse and k_prolong_cf.  fmg != 0 first runs the FMG pass's
+// own bottom (restriction, root solve, prolongation, without smoothing).
+
 template <typename T>
 __device__ __forceinline__ T root_ghost(const Geo &g, int64_t r, int d, int u, int v, T own) {
     if (g.bct[d] == 1) return own;
     return dirichlet_ghost<T>(bc_value<T>(g, r, d, u, v), own);
 }
-
+// The 16^3 grid in LDS is colour-split like a box: colour (I+J+K)&1, then
+// row K*16 + J, then I/2, so a wave of a half-sweep reads consecutive words.
+__device__ __forceinline__ int cs16(int I, int J, int K) {
+    return (((I + J + K) & 1) << 11) + ((K * 16 + J) << 3) + (I >> 1);
+}
+// (I, J, K) of colour-split index p of the 16^3 grid
+__device__ __forceinline__ void cs16_cell(int p, int &I, int &J, int &K) {
+    J = (p >> 3) & 15;
+    K = (p >> 7) & 15;
+    I = 2 * (p & 7) + ((J + K + (p >> 11)) & 1);
+}
+// six-neighbour sum of fine cell (I, J, K), order -x, +x, -y, +y, -z, +z.
+// Domain ghosts: own (Neumann) or GB - own with GB = 2 g (Dirichlet), GB
+// indexed by the face cell (v * 16 + u, u and v along the tangential axes in
+// increasing order).
 template <typename T>
-__device__ __forceinline__ T bot_resid(const Geo &g, const T *F2, const T *B2, int o, int64_t gid,
-                                       int i, int j, int k, T inv_h2) {
-    const T *P = F2 + o * 512;
-    T own = P[cs_idx(i, j, k)];
-    T xm = i > 0 ? P[cs_idx(i - 1, j, k)] : bot_ghost<T>(g, F2, o, gid, 0, j, k, own);
-    T xp = i < 7 ? P[cs_idx(i + 1, j, k)] : bot_ghost<T>(g, F2, o, gid, 1, j, k, own);
-    T ym = j > 0 ? P[cs_idx(i, j - 1, k)] : bot_ghost<T>(g, F2, o, gid, 2, i, k, own);
-    T yp = j < 7 ? P[cs_idx(i, j + 1, k)] : bot_ghost<T>(g, F2, o, gid, 3, i, k, own);
-    T zm = k > 0 ? P[cs_idx(i, j, k - 1)] : bot_ghost<T>(g, F2, o, gid, 4, i, j, own);
-    T zp = k < 7 ? P[cs_idx(i, j, k + 1)] : bot_ghost<T>(g, F2, o, gid, 5, i, j, own);
-    T s = xm + xp + ym + yp + zm + zp;
-    return B2[o * 512 + cs_idx(i, j, k)] - (s - (T)6 * own) * inv_h2;
+__device__ __forceinline__ T bot_sum(const T *F2, const T *GB, const int nm[6], int I, int J, int K,
+                                     T own) {
+    const T *S = F2 + ((((I + J + K) & 1) ^ 1) << 11);  // the other colour
+    int row = (K * 16 + J) << 3;
+    T xm = I > 0 ? S[row + ((I - 1) >> 1)] : nm[0] ? own : GB[0 * 256 + K * 16 + J] - own;
+    T xp = I < 15 ? S[row + ((I + 1) >> 1)] : nm[1] ? own : GB[1 * 256 + K * 16 + J] - own;
+    T ym = J > 0 ? S[row - 8 + (I >> 1)] : nm[2] ? own : GB[2 * 256 + K * 16 + I] - own;
+    T yp = J < 15 ? S[row + 8 + (I >> 1)] : nm[3] ? own : GB[3 * 256 + K * 16 + I] - own;
+    T zm = K > 0 ? S[row - 128 + (I >> 1)] : nm[4] ? own : GB[4 * 256 + J * 16 + I] - own;
+    T zp = K < 15 ? S[row + 128 + (I >> 1)] : nm[5] ? own : GB[5 * 256 + J * 16 + I] - own;
+    return xm + xp + ym + yp + zm + zp;
+}
+// colour-split index c of a box -> (i, j, k)
+__device__ __forceinline__ void cs_cell(int c, int &i, int &j, int &k) {
+    int q = c & 255;
+    j = (q >> 2) & 7;
+    k = q >> 5;
+    i = 2 * (q & 3) + ((j + k + (c >> 8)) & 1);
 }
 
 template <typename T>
-__global__ __launch_bounds__(512) void k_bottom(Geo g, T *__restrict__ phi, T *__restrict__ rhs,
-                                                T *__restrict__ old, const double *__restrict__ eig,
-                                                int64_t r0, const int32_t *__restrict__ root2,
-                                                T h2_2, T inv_h2_2, T inv_h2_1, double h1, int nd,
-                                                int nu, int fmg) {
-    __shared__ T F2[4096], B2[4096], F1[512], B1[512], O1[512];
-    __shared__ double X[512], Y[512], V[192], L[24];
-    int tid = threadIdx.x;
-    int64_t r = r0 + blockIdx.x;
-    int64_t first2 = root2[blockIdx.x];
-    bool has2 = first2 >= 0;
+__global__ __launch_bounds__(1024) void k_bottom(Geo g, T *__restrict__ phi, T *__restrict__ rhs,
+                                                 T *__restrict__ old, const double *__restrict__ eig,
+                                                 int64_t r0, const int32_t *__restrict__ root2,
+                                                 T h2_2, T inv_h2_2, T inv_h2_1, double h1, int nd,
+                                                 int nu, int fmg) {
+    // F2, B2: level-2 field and right-hand side; GB: 2 g on the six faces of
+    // the 16^3 grid; F1, B1, O1: the root's phi, rhs, old; W: the level-2
+    // residual, then the root solve's X and Y, then the root correction
+    // padded by its domain ghosts (10^3).
+    __shared__ T F2[4096], B2[4096], GB[6 * 256], F1[512], B1[512], O1[512];
+    __shared__ double W[4096], V[192], L[24];
+    T *R2 = reinterpret_cast<T *>(W);
+    double *X = W, *Y = W + 512;
+    T *D1 = reinterpret_cast<T *>(W + 1024);
+    const int tid = threadIdx.x;
+    const int64_t r = r0 + blockIdx.x;
+    const int64_t first2 = root2[blockIdx.x];
+    const bool has2 = first2 >= 0;
+    int nm[6];
+#pragma unroll
+    for (int d = 0; d < 6; d++) nm[d] = g.bct[d] == 1;
+    // root cell of this thread (tid < 512), natural order
+    const int ri = tid & 7, rj = (tid >> 3) & 7, rk = (tid >> 6) & 7;
     if (tid < 192) V[tid] = eig[tid];
     if (tid < 24) L[tid] = eig[192 + tid];
-    F1[tid] = phi[r * 512 + tid];
-    B1[tid] = rhs[r * 512 + tid];
+    if (tid < 512) {
+        int i, j, k;
+        cs_cell(tid, i, j, k);
+        F1[i + 8 * j + 64 * k] = phi[r * 512 + tid];
+        B1[i + 8 * j + 64 * k] = rhs[r * 512 + tid];
+    }
     if (has2) {
 #pragma unroll
-        for (int w = 0; w < 8; w++) {
-            F2[tid + 512 * w] = phi[first2 * 512 + tid + 512 * w];
-            B2[tid + 512 * w] = rhs[first2 * 512 + tid + 512 * w];
+        for (int w = 0; w < 4; w++) {
+            int e = tid + 1024 * w, o = e >> 9, i, j, k;
+            cs_cell(e & 511, i, j, k);
+            int p = cs16(8 * (o & 1) + i, 8 * ((o >> 1) & 1) + j, 8 * (o >> 2) + k);
+            F2[p] = phi[first2 * 512 + e];
+            B2[p] = rhs[first2 * 512 + e];
+        }
+        for (int e = tid; e < 6 * 256; e += 1024) {
+            int d = e >> 8, u = e & 15, v = (e >> 4) & 15, a = d >> 1, side = d & 1;
+            int c[3];  // the face cell's box: octant side along a, u and v across it
+            c[a] = side;
+            c[a == 0 ? 1 : 0] = u >> 3;
+            c[a == 2 ? 1 : 2] = v >> 3;
+            int o = c[0] | (c[1] << 1) | (c[2] << 2);
+            GB[e] = (T)2 * bc_value<T>(g, first2 + o, d, u & 7, v & 7);
         }
     }
     __syncthreads();
 
     auto half_sweep = [&](int C) __attribute__((always_inline)) {
 #pragma unroll
-        for (int w = 0; w < 4; w++) {
-            int q = tid + 512 * w, o = q >> 8, t = q & 255;
-            int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
-            int i = 2 * m + ((j + k + C) & 1);
-            int row = (k * 8 + j) * 4;
-            const T *S = F2 + o * 512 + (1 - C) * 256;
-            T own = F2[o * 512 + C * 256 + t];
-            int64_t gid = first2 + o;
-            T xm = i > 0 ? S[row + ((i - 1) >> 1)] : bot_ghost<T>(g, F2, o, gid, 0, j, k, own);
-            T xp = i < 7 ? S[row + ((i + 1) >> 1)] : bot_ghost<T>(g, F2, o, gid, 1, j, k, own);
-            T ym = j > 0 ? S[row - 4 + m] : bot_ghost<T>(g, F2, o, gid, 2, i, k, own);
-            T yp = j < 7 ? S[row + 4 + m] : bot_ghost<T>(g, F2, o, gid, 3, i, k, own);
-            T zm = k > 0 ? S[row - 32 + m] : bot_ghost<T>(g, F2, o, gid, 4, i, j, own);
-            T zp = k < 7 ? S[row + 32 + m] : bot_ghost<T>(g, F2, o, gid, 5, i, j, own);
-            T s = xm + xp + ym + yp + zm + zp;
-            F2[o * 512 + C * 256 + t] = (s - h2_2 * B2[o * 512 + C * 256 + t]) * (T)kSixth;
+        for (int w = 0; w < 2; w++) {
+            int p = (C << 11) + tid + 1024 * w, I, J, K;
+            cs16_cell(p, I, J, K);
+            T s = bot_sum<T>(F2, GB, nm, I, J, K, F2[p]);
+            F2[p] = (s - h2_2 * B2[p]) * (T)kSixth;
         }
         __syncthreads();
     };
@@ -725,100 +752,112 @@ __global__ __launch_bounds__(512) void k_bottom(Geo g, T *__restrict__ phi, T *_
     // the root; a leaf root only copies phi -> old
     auto down = [&]() __attribute__((always_inline)) {
         if (!has2) {
-            O1[tid] = F1[tid];
+            if (tid < 512) O1[tid] = F1[tid];
             __syncthreads();
             return;
         }
-        {
-            int o = tid >> 6, pt = tid & 63;
-            int pi = pt & 3, pj = (pt >> 2) & 3, pk = pt >> 4;
-            T sphi = 0, sres = 0;
-            for (int dk = 0; dk < 2; dk++)
-                for (int dj = 0; dj < 2; dj++)
-                    for (int di = 0; di < 2; di++) {
-                        int fi = 2 * pi + di, fj = 2 * pj + dj, fk = 2 * pk + dk;
-                        sphi += F2[o * 512 + cs_idx(fi, fj, fk)];
-                        sres += bot_resid<T>(g, F2, B2, o, first2 + o, fi, fj, fk, inv_h2_2);
-                    }
-            int pc = cs_idx(4 * (o & 1) + pi, 4 * ((o >> 1) & 1) + pj, 4 * (o >> 2) + pk);
-            T mphi = (T)0.125 * sphi;
-            F1[pc] = mphi;
-            O1[pc] = mphi;
-            B1[pc] = (T)0.125 * sres;
-        }
-        __syncthreads();
-        {
-            int i = tid & 7, j = (tid >> 3) & 7, k = tid >> 6;
-            int c = cs_idx(i, j, k);
-            T own = F1[c];
-            T xm = i > 0 ? F1[cs_idx(i - 1, j, k)] : root_ghost<T>(g, r, 0, j, k, own);
-            T xp = i < 7 ? F1[cs_idx(i + 1, j, k)] : root_ghost<T>(g, r, 1, j, k, own);
-            T ym = j > 0 ? F1[cs_idx(i, j - 1, k)] : root_ghost<T>(g, r, 2, i, k, own);
-            T yp = j < 7 ? F1[cs_idx(i, j + 1, k)] : root_ghost<T>(g, r, 3, i, k, own);
-            T zm = k > 0 ? F1[cs_idx(i, j, k - 1)] : root_ghost<T>(g, r, 4, i, j, own);
-            T zp = k < 7 ? F1[cs_idx(i, j, k + 1)] : root_ghost<T>(g, r, 5, i, j, own);
-            T s = xm + xp + ym + yp + zm + zp;
-            T rn = (s - (T)6 * own) * inv_h2_1 + B1[c];
-            __syncthreads();
-            B1[c] = rn;
-        }
-        __syncthreads();
-    };
-    // exact root solve, as k_coarse
-    auto coarse = [&]() __attribute__((always_inline)) {
-        int i = tid & 7, j = (tid >> 3) & 7, k = tid >> 6;
-        double rr = (double)B1[cs_idx(i, j, k)];
 #pragma unroll
-        for (int d = 0; d < 6; d++) {
-            int a = d >> 1, sd = d & 1;
-            int ca = a == 0 ? i : a == 1 ? j : k;
-            int u = a == 0 ? j : i, v = a == 2 ? j : k;  // coordinates along the tangential axes
-            bool edge = sd ? (ca == 7) : (ca == 0);
-            if (edge && g.bct[d] == 0) {
-                double gv = g.bcval ? g.bcval[(r * 6 + d) * 64 + v * 8 + u] : g.bcv[d];
-                rr -= 2.0 * gv / (h1 * h1);
-            }
+        for (int w = 0; w < 4; w++) {
+            int p = tid + 1024 * w, I, J, K;
+            cs16_cell(p, I, J, K);
+            T own = F2[p];
+            T sum = bot_sum<T>(F2, GB, nm, I, J, K, own);
+            R2[p] = B2[p] - (sum - (T)6 * own) * inv_h2_2;
         }
-        int t = tid;
-        X[t] = rr;
         __syncthreads();
-        { double s = 0; for (int q = 0; q < 8; q++) s += V[0 * 64 + q * 8 + i] * X[(k * 8 + j) * 8 + q]; Y[t] = s; }
+        if (tid < 512) {
+            T sphi = 0, sres = 0;
+#pragma unroll
+            for (int dk = 0; dk < 2; dk++)
+#pragma unroll
+                for (int dj = 0; dj < 2; dj++)
+#pragma unroll
+                    for (int di = 0; di < 2; di++) {
+                        int p = cs16(2 * ri + di, 2 * rj + dj, 2 * rk + dk);
+                        sphi += F2[p];
+                        sres += R2[p];
+                    }
+            T mphi = (T)0.125 * sphi;
+            F1[tid] = mphi;
+            O1[tid] = mphi;
+            B1[tid] = (T)0.125 * sres;
+        }
         __syncthreads();
-        { double s = 0; for (int q = 0; q < 8; q++) s += V[1 * 64 + q * 8 + j] * Y[(k * 8 + q) * 8 + i]; X[t] = s; }
-        __syncthreads();
-        { double s = 0; for (int q = 0; q < 8; q++) s += V[2 * 64 + q * 8 + k] * X[(q * 8 + j) * 8 + i]; Y[t] = s; }
-        __syncthreads();
-        Y[t] = Y[t] * (h1 * h1) / (L[i] + L[8 + j] + L[16 + k]);
-        __syncthreads();
-        { double s = 0; for (int q = 0; q < 8; q++) s += V[2 * 64 + k * 8 + q] * Y[(q * 8 + j) * 8 + i]; X[t] = s; }
-        __syncthreads();
-        { double s = 0; for (int q = 0; q < 8; q++) s += V[1 * 64 + j * 8 + q] * X[(k * 8 + q) * 8 + i]; Y[t] = s; }
-        __syncthreads();
-        { double s = 0; for (int q = 0; q < 8; q++) s += V[0 * 64 + i * 8 + q] * Y[(k * 8 + j) * 8 + q]; X[t] = s; }
-        F1[cs_idx(i, j, k)] = (T)X[t];
+        if (tid < 512) {
+            T own = F1[tid];
+            T xm = ri > 0 ? F1[tid - 1] : root_ghost<T>(g, r, 0, rj, rk, own);
+            T xp = ri < 7 ? F1[tid + 1] : root_ghost<T>(g, r, 1, rj, rk, own);
+            T ym = rj > 0 ? F1[tid - 8] : root_ghost<T>(g, r, 2, ri, rk, own);
+            T yp = rj < 7 ? F1[tid + 8] : root_ghost<T>(g, r, 3, ri, rk, own);
+            T zm = rk > 0 ? F1[tid - 64] : root_ghost<T>(g, r, 4, ri, rj, own);
+            T zp = rk < 7 ? F1[tid + 64] : root_ghost<T>(g, r, 5, ri, rj, own);
+            T s = xm + xp + ym + yp + zm + zp;
+            B1[tid] = (s - (T)6 * own) * inv_h2_1 + B1[tid];
+        }
         __syncthreads();
     };
-    // correction delta = phi - old of the root at cell C (one coordinate may
-    // lie one cell outside: homogeneous domain ghost)
-    auto delta = [&](int cx, int cy, int cz) __attribute__((always_inline)) -> T {
-        int face = cx < 0 ? 0 : cx > 7 ? 1 : cy < 0 ? 2 : cy > 7 ? 3 : cz < 0 ? 4 : cz > 7 ? 5 : -1;
-        int q = cs_idx(min(max(cx, 0), 7), min(max(cy, 0), 7), min(max(cz, 0), 7));
-        T din = F1[q] - O1[q];
-        if (face < 0) return din;
-        return g.bct[face] == 1 ? din : -din;
+    // exact root solve, as k_coarse (threads < 512, root cell tid)
+    auto coarse = [&]() __attribute__((always_inline)) {
+        const int t = tid & 511, i = ri, j = rj, k = rk;
+        if (tid < 512) {
+            double rr = (double)B1[t];
+#pragma unroll
+            for (int d = 0; d < 6; d++) {
+                int a = d >> 1, sd = d & 1;
+                int ca = a == 0 ? i : a == 1 ? j : k;
+                int u = a == 0 ? j : i, v = a == 2 ? j : k;  // coordinates along the tangential axes
+                bool edge = sd ? (ca == 7) : (ca == 0);
+                if (edge && g.bct[d] == 0) {
+                    double gv = g.bcval ? g.bcval[(r * 6 + d) * 64 + v * 8 + u] : g.bcv[d];
+                    rr -= 2.0 * gv / (h1 * h1);
+                }
+            }
+            X[t] = rr;
+        }
+        __syncthreads();
+        if (tid < 512) { double s = 0; for (int q = 0; q < 8; q++) s += V[0 * 64 + q * 8 + i] * X[(k * 8 + j) * 8 + q]; Y[t] = s; }
+        __syncthreads();
+        if (tid < 512) { double s = 0; for (int q = 0; q < 8; q++) s += V[1 * 64 + q * 8 + j] * Y[(k * 8 + q) * 8 + i]; X[t] = s; }
+        __syncthreads();
+        if (tid < 512) {
+            double s = 0;
+            for (int q = 0; q < 8; q++) s += V[2 * 64 + q * 8 + k] * X[(q * 8 + j) * 8 + i];
+            Y[t] = s * (h1 * h1) / (L[i] + L[8 + j] + L[16 + k]);
+        }
+        __syncthreads();
+        if (tid < 512) { double s = 0; for (int q = 0; q < 8; q++) s += V[2 * 64 + k * 8 + q] * Y[(q * 8 + j) * 8 + i]; X[t] = s; }
+        __syncthreads();
+        if (tid < 512) { double s = 0; for (int q = 0; q < 8; q++) s += V[1 * 64 + j * 8 + q] * X[(k * 8 + q) * 8 + i]; Y[t] = s; }
+        __syncthreads();
+        if (tid < 512) {
+            double s = 0;
+            for (int q = 0; q < 8; q++) s += V[0 * 64 + i * 8 + q] * Y[(k * 8 + j) * 8 + q];
+            F1[t] = (T)s;
+        }
+        __syncthreads();
     };
+    // prolongation: the root correction delta = phi - old padded by its
+    // homogeneous domain ghosts (faces only) into D1[10^3], then
+    // phi_f += 1/4 d0 + 1/4 (dx + dy + dz) on every level-2 cell
     auto prolong = [&]() __attribute__((always_inline)) {
         if (!has2) return;
-#pragma unroll 2
-        for (int w = 0; w < 8; w++) {
-            int q = tid + 512 * w, o = q >> 9, e = q & 511, cc = e >> 8, t = e & 255;
-            int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
-            int i = 2 * m + ((j + k + cc) & 1);
-            int X0 = 4 * (o & 1) + (i >> 1), Y0 = 4 * ((o >> 1) & 1) + (j >> 1), Z0 = 4 * (o >> 2) + (k >> 1);
-            int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
-            T d0 = delta(X0, Y0, Z0), dx = delta(X0 + sx, Y0, Z0), dy = delta(X0, Y0 + sy, Z0),
-              dz = delta(X0, Y0, Z0 + sz);
-            F2[q] += (T)0.25 * d0 + (T)0.25 * (dx + dy + dz);
+        if (tid < 1000) {
+            int x = tid % 10 - 1, y = (tid / 10) % 10 - 1, z = tid / 100 - 1;
+            int face = x < 0 ? 0 : x > 7 ? 1 : y < 0 ? 2 : y > 7 ? 3 : z < 0 ? 4 : z > 7 ? 5 : -1;
+            int out = (x < 0 || x > 7) + (y < 0 || y > 7) + (z < 0 || z > 7);
+            int q = min(max(x, 0), 7) + 8 * min(max(y, 0), 7) + 64 * min(max(z, 0), 7);
+            T din = F1[q] - O1[q];
+            D1[tid] = out > 1 ? (T)0 : face < 0 ? din : nm[face] ? din : -din;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+            int p = tid + 1024 * w, I, J, K;
+            cs16_cell(p, I, J, K);
+            int c = ((K >> 1) + 1) * 100 + ((J >> 1) + 1) * 10 + (I >> 1) + 1;
+            int sx = (I & 1) ? 1 : -1, sy = (J & 1) ? 10 : -10, sz = (K & 1) ? 100 : -100;
+            T d0 = D1[c], dx = D1[c + sx], dy = D1[c + sy], dz = D1[c + sz];
+            F2[p] += (T)0.25 * d0 + (T)0.25 * (dx + dy + dz);
         }
         __syncthreads();
     };
@@ -834,12 +873,22 @@ __global__ __launch_bounds__(512) void k_bottom(Geo g, T *__restrict__ phi, T *_
     prolong();
     if (has2) smooth(nu);
 
-    phi[r * 512 + tid] = F1[tid];
-    rhs[r * 512 + tid] = B1[tid];
-    old[r * 512 + tid] = O1[tid];
+    if (tid < 512) {
+        int i, j, k;
+        cs_cell(tid, i, j, k);
+        int n = i + 8 * j + 64 * k;
+        phi[r * 512 + tid] = F1[n];
+        rhs[r * 512 + tid] = B1[n];
+        old[r * 512 + tid] = O1[n];
+    }
     if (has2) {
 #pragma unroll
-        for (int w = 0; w < 8; w++) phi[first2 * 512 + tid + 512 * w] = F2[tid + 512 * w];
+        for (int w = 0; w < 4; w++) {
+            int e = tid + 1024 * w, o = e >> 9, i, j, k;
+            cs_cell(e & 511, i, j, k);
+            int p = cs16(8 * (o & 1) + i, 8 * ((o >> 1) & 1) + j, 8 * (o >> 2) + k);
+            phi[first2 * 512 + e] = F2[p];
+        }
     }
 }
 
@@ -1101,7 +1150,7 @@ template <typename T>
 void launch_bottom(const Geo &g, T *phi, T *rhs, T *old, const double *eig, int64_t r0, int ntree,
                    const int32_t *root2, double h2, double h1, int nd, int nu, int fmg,
                    hipStream_t s) {
-    hipLaunchKernelGGL(k_bottom<T>, dim3((unsigned)ntree), dim3(512), 0, s, g, phi, rhs, old, eig, r0, root2,
+    hipLaunchKernelGGL(k_bottom<T>, dim3((unsigned)ntree), dim3(1024), 0, s, g, phi, rhs, old, eig, r0, root2,
                        (T)(h2 * h2), (T)(1.0 / (h2 * h2)), (T)(1.0 / (h1 * h1)), h1, nd, nu, fmg);
 }
 template <typename T>
