@@ -42,15 +42,16 @@ def model_bytes(level_counts, n_leaf, k):
     return fmg + k * BETA_FP64 * cum[-1] + (k + 1) * NORM_BYTES * n_leaf
 
 
-def traffic_per_launch():
-    """HBM bytes per half-sweep launch from the committed rocprofv3 counter
-    summary, or None if the kernel source changed since it was taken."""
+def traffic_per_launch(variant):
+    """HBM bytes per launch of the finest-level Gauss-Seidel kernel from the
+    committed rocprofv3 counter summary, or None if the kernel source changed
+    since it was taken or the counters were taken on another launch variant."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         rec = json.load(f)
     src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if rec.get("kernel_sha256") != src:
+    if rec.get("kernel_sha256") != src or rec.get("variant") != variant:
         return None
     return rec.get("bytes_per_launch")
 
@@ -275,7 +276,7 @@ def main():
     bytes_per_launch = kt["level_bytes"][fin] / max(kt["level_launches"][fin], 1)
     achieved = bytes_per_launch / per_launch_s / 1e9
     all_us = kt["total_ms"] * 1e3 / max(kt["launches"], 1)
-    tr = traffic_per_launch()
+    tr = traffic_per_launch(sched64[fin])
     out = {
         "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -293,8 +294,12 @@ def main():
                    "smoothing": "V(2,2) red-black Gauss-Seidel",
                    "gsrb_schedule": {"fp64": sched64, "fp32": sched32}},
         "roofline": {"bound": "hbm",
-                     "kernel": f"k_gsrb<C,double> (red-black Gauss-Seidel half-sweep), level "
-                               f"{fin + 1} ({counts[fin]} boxes, the most bytes)",
+                     "kernel": (f"k_gsrb_sweep<double> (fused red-black Gauss-Seidel sweep)"
+                                if sched64[fin] >= 6 else
+                                f"k_gsrb<C,double,{(1, 2, 4)[sched64[fin] >> 1]}> (red-black "
+                                f"Gauss-Seidel half-sweep)")
+                               + f", level {fin + 1} ({counts[fin]} boxes, the most bytes), "
+                                 f"schedule variant {sched64[fin]}",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "copy_GBps": copy["GBps"], "frac_of_copy": achieved / copy["GBps"],
