@@ -247,23 +247,30 @@ int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out);
 
 /*
  * Autotuner of the Gauss-Seidel launch schedule.  Variant v = 2c + x:
- * c = 0, 1, 2 are half-sweeps (one colour per launch) with 1, 2 or 4 cells
- * per thread; c = 3 is the fused sweep (both colours in one launch: each box
- * recomputes the red face layers of its same-level neighbours from the old
- * field, and sweeps ping-pong between the field and a buffer in the
- * workspace, so a level is smoothed in pairs of sweeps; an odd last sweep
- * runs as half-sweeps of variant 3); x = 1 selects the XCD-aware box
- * mapping.  For every level the tuner times reps half-sweeps of each variant
- * (reps / 2 fused sweeps) with HIP events on the bound stream and keeps the
- * fastest; reps must be even, 2..1000.  precision selects the FP64 or the
- * FP32 (MG_MIXED) kernels.  The field being swept is parked and restored, so
- * the solver state is unchanged.  schedule (host, [n_levels], may be NULL)
+ *   c = 0, 1, 2: half-sweeps (one colour per launch) with 1, 2 or 4 cells per
+ *         thread;
+ *   c = 3: fused sweeps (both colours in one launch: each box recomputes the
+ *         red face layers of its same-level neighbours from the old field;
+ *         sweeps ping-pong between the field and a buffer in the workspace,
+ *         so a level is smoothed in pairs of sweeps and an odd last sweep
+ *         runs as half-sweeps of variant 3);
+ *   c = 4: half-sweeps over octets of sibling boxes (one workgroup per 16^3
+ *         octet; faces between siblings come from LDS);
+ *   x = 1 selects the XCD-aware mapping of workgroups to boxes.
+ * The entry of level 1 (never smoothed) selects how the two coarsest levels
+ * run: 0 = step by step, any other value = one launch per V-cycle with one
+ * workgroup per tree (the default); the tuner reports it as set.  For every
+ * level >= 2 the tuner times reps half-sweeps of each variant (reps / 2
+ * fused sweeps) with HIP events on the bound stream and keeps the fastest;
+ * reps must be even, 2..1000.  precision selects the FP64 or the FP32
+ * (MG_MIXED) kernels.  The field being swept is parked and restored, so the
+ * solver state is unchanged.  schedule (host, [n_levels], may be NULL)
  * receives the chosen variant per level (index level-1); mg_set_schedule
  * applies a stored schedule (e.g. from a cache keyed by the tree's level
  * sizes) and rejects entries outside 0..MG_GSRB_VARIANTS-1.  All variants
  * compute the same values.
  */
-#define MG_GSRB_VARIANTS 8
+#define MG_GSRB_VARIANTS 10
 int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule);
 int mg_set_schedule(mg_tree *t, int precision, const int32_t *schedule);
 

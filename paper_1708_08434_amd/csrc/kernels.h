@@ -28,12 +28,17 @@ template <typename T> void launch_unpack(const T *cs, double *nat, int64_t nbox,
 // Gauss-Seidel launch variants: variant = 2 * c + x, with c = 0, 1, 2 for
 // half-sweeps with 1, 2 or 4 cells per thread (256, 128 or 64 threads per
 // box), c = 3 for fused sweeps (red and black in one launch, ping-ponging
-// between the field and a second buffer), and x = 1 for the XCD-aware box
-// mapping.  All variants do the same arithmetic on every cell.
-constexpr int kGsrbVariants = 8;
-constexpr int kGsrbHalfVariants = 6;  // variants 0..5 are half-sweeps
+// between the field and a second buffer), c = 4 for half-sweeps over octets
+// of sibling boxes (one 512-thread workgroup per 16^3 octet; levels >= 2,
+// whose boxes come in complete consecutive octets), and x = 1 for the
+// XCD-aware mapping.  All variants do the same arithmetic on every cell.
+constexpr int kGsrbVariants = 10;
+constexpr int kGsrbHalfVariants = 6;  // variants 0..5 are one-box half-sweeps
+constexpr int kGsrbFusedVariant = 6;  // 6, 7: fused sweeps
+constexpr int kGsrbOctVariant = 8;    // 8, 9: octet half-sweeps
 constexpr int kGsrbDefault = 3;       // 2 cells per thread, XCD mapping
-// One colour in place; a fused variant falls back to kGsrbDefault.
+// One colour in place; a fused variant, or an octet variant on a box count
+// that is not a multiple of 8, falls back to kGsrbDefault.
 template <typename T>
 void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
                  int colour, int variant, hipStream_t s);

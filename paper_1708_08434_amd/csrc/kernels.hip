@@ -231,6 +231,70 @@ __global__ __launch_bounds__(256 / CPT) void k_gsrb(Geo g, T *__restrict__ phi,
     reinterpret_cast<V *>(phi + b * 512 + C * 256)[t] = res;
 }
 
+// One colour C of red-black Gauss-Seidel on the octets (complete sets of 8
+// sibling boxes, consecutive in canonical order) of boxes [b0, b0+8*noct):
+// one 512-thread workgroup per octet, which is a 16^3 grid.  Faces between
+// siblings are read from LDS, so only the octet's outer surface (6 x 128
+// cells of this colour) needs ghosts: half the ghost traffic per cell of the
+// one-box launches.  S holds the other colour of the 16^3 grid (colour-split
+// rows: (K*16 + J)*8 + I/2); thread t owns one box row (4 cells) of colour C,
+// read and written as one vector.  Same arithmetic per cell as k_gsrb.
+template <int C, typename T>
+__global__ __launch_bounds__(512) void k_gsrb_oct(Geo g, T *__restrict__ phi, const T *__restrict__ rhs,
+                                                  const T *__restrict__ chat, int64_t b0, int64_t noct,
+                                                  T h2, int xcd) {
+    using V4 = typename VecN<T, 4>::type;
+    __shared__ T S[2048], H[6 * 128];
+    int64_t lo = xcd ? xcd_map(blockIdx.x, noct) : (int64_t)blockIdx.x;
+    if (lo >= noct) return;
+    int64_t ob = b0 + 8 * lo;
+    int t = threadIdx.x;
+    int o = t >> 6, rw = t & 63, j = rw & 7, k = rw >> 3;  // box of the octet, row (j, k) in it
+    int64_t bx = ob + o;
+    int ox = 8 * (o & 1), oy = 8 * ((o >> 1) & 1), oz = 8 * (o >> 2);
+    // other colour of row (j, k) of box o: 4 values, I/2 = ox/2 + m
+    V4 so = reinterpret_cast<const V4 *>(phi + bx * 512 + (1 - C) * 256)[rw];
+    V4 bv = reinterpret_cast<const V4 *>(rhs + bx * 512 + C * 256)[rw];
+    // ghosts of the outer surface: entry e = d*128 + v*8 + u/2 over the
+    // 16 x 16 face (u along t1, v along t2), cells of colour C
+    for (int e = t; e < 768; e += 512) {
+        int d = e >> 7, q = e & 127, v = q >> 3;
+        int a = d >> 1, side = d & 1;
+        int L = side ? 15 : 0;
+        int u = 2 * (q & 7) + ((L + v + C) & 1);
+        int c[3];  // octant of the box holding face cell (u, v)
+        c[a] = side;
+        c[a == 0 ? 1 : 0] = u >> 3;
+        c[a == 2 ? 1 : 2] = v >> 3;
+        int64_t gb = ob + (c[0] | (c[1] << 1) | (c[2] << 2));
+        H[e] = ghost_at<T>(g, phi, chat, gb, d, g.nbr[gb * 6 + d], g.cfslot[gb * 6 + d], u & 7, v & 7);
+    }
+    {
+        const T *sv = reinterpret_cast<const T *>(&so);
+        int row = ((oz + k) * 16 + oy + j) * 8 + (ox >> 1);
+#pragma unroll
+        for (int m = 0; m < 4; m++) S[row + m] = sv[m];
+    }
+    __syncthreads();
+    const T *bb = reinterpret_cast<const T *>(&bv);
+    V4 res;
+    T *out = reinterpret_cast<T *>(&res);
+    int J = oy + j, K = oz + k, row = (K * 16 + J) * 8;
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        int I = ox + 2 * m + ((j + k + C) & 1);
+        T xm = I > 0 ? S[row + ((I - 1) >> 1)] : H[0 * 128 + K * 8 + (J >> 1)];
+        T xp = I < 15 ? S[row + ((I + 1) >> 1)] : H[1 * 128 + K * 8 + (J >> 1)];
+        T ym = J > 0 ? S[row - 8 + (I >> 1)] : H[2 * 128 + K * 8 + (I >> 1)];
+        T yp = J < 15 ? S[row + 8 + (I >> 1)] : H[3 * 128 + K * 8 + (I >> 1)];
+        T zm = K > 0 ? S[row - 128 + (I >> 1)] : H[4 * 128 + J * 8 + (I >> 1)];
+        T zp = K < 15 ? S[row + 128 + (I >> 1)] : H[5 * 128 + J * 8 + (I >> 1)];
+        T s = xm + xp + ym + yp + zm + zp;
+        out[m] = (s - h2 * bb[m]) * (T)kSixth;
+    }
+    reinterpret_cast<V4 *>(phi + bx * 512 + C * 256)[rw] = res;
+}
+
 // One full red-black sweep (red half, then black half) of boxes [b0, b0+nbx)
 // of one level, reading src and writing both colours to dst (src is left
 // unchanged, dst must not alias it).  The values are those of the two
@@ -1103,6 +1167,16 @@ template <typename T>
 void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
                  int colour, int variant, hipStream_t s) {
     if (nb <= 0) return;
+    if (variant >= kGsrbOctVariant && (nb & 7) == 0) {
+        int64_t noct = nb >> 3;
+        int xcd = variant & 1;
+        dim3 grid((unsigned)(xcd ? xcd_grid(noct) : noct));
+        if (colour == 0)
+            hipLaunchKernelGGL((k_gsrb_oct<0, T>), grid, dim3(512), 0, s, g, phi, rhs, chat, b0, noct, h2, xcd);
+        else
+            hipLaunchKernelGGL((k_gsrb_oct<1, T>), grid, dim3(512), 0, s, g, phi, rhs, chat, b0, noct, h2, xcd);
+        return;
+    }
     if (variant >= kGsrbHalfVariants) variant = kGsrbDefault;
     int xcd = variant & 1;
     switch (variant >> 1) {

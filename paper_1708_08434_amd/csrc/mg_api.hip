@@ -86,6 +86,18 @@ template <typename T> void ensure_cf(mg_tree *t, const Fields<T> &F, int l) {
     launch_cf_coarse<T>(F.g, F.phi, F.chat, t->d.slots, s0, ns, stream_of(t));
     F.cf_valid[l] = true;
 }
+// c_hat of every level in one launch (slots are grouped by level, and each
+// level's c_hat reads only the level below it).  Valid only where no level
+// changes between this call and the use of a c_hat computed here: after the
+// restriction pass, and at the start of an FMG pass from a zero field.
+template <typename T> void ensure_cf_all(mg_tree *t, const Fields<T> &F) {
+    bool any = false;
+    for (int l = 2; l <= t->nlev; l++) any = any || !F.cf_valid[l];
+    if (!any) return;
+    int64_t s0 = t->sstart[2], ns = t->sstart[t->nlev + 1] - t->sstart[2];
+    launch_cf_coarse<T>(F.g, F.phi, F.chat, t->d.slots, s0, ns, stream_of(t));
+    for (int l = 2; l <= t->nlev; l++) F.cf_valid[l] = true;
+}
 
 // ---- optional event timing of the half-sweep launches
 hipEvent_t take_event(mg_tree *t) {
@@ -119,9 +131,10 @@ template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsw
         }
     }
     int variant = t->sched[sizeof(T) == 4 ? 1 : 0][l];
+    if (l < 2 && variant >= kGsrbOctVariant) variant = kGsrbDefault;  // roots are not octets
     int64_t launches = 0;
     int it = 0;
-    if (variant >= kGsrbHalfVariants) {
+    if (variant >= kGsrbFusedVariant && variant < kGsrbOctVariant) {
         // fused sweeps in pairs: field -> sweep buffer -> field
         T *swp = (T *)t->d.swp;
         for (; it + 1 < nsweep; it += 2) {
@@ -223,6 +236,10 @@ template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int n
 // FMG pass from the current (zero) field: FAS data top-down, root solve, then
 // for each finer level the prolonged correction and one V-cycle on top.
 template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int nu) {
+    // the top-down FAS pass changes level l-1 only after the last use of
+    // c_hat(l), and c_hat(l-1) reads level l-2, still untouched: every c_hat
+    // it needs can be computed up front from the initial field
+    ensure_cf_all(t, F);
     bool one = use_bottom<T>(t);
     int low = one ? 3 : 2;
     for (int l = t->nlev; l >= low; l--) fas_down(t, F, l);
@@ -242,7 +259,7 @@ template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int 
 // the residual in FP32.
 void norms_launch(mg_tree *t, int slot, float *r32) {
     Fields<double> F = f64(t);
-    for (int l = 2; l <= t->nlev; l++) ensure_cf(t, F, l);
+    ensure_cf_all(t, F);
     launch_leaf_norms(F.g, F.phi, F.rhs, F.chat, t->d.leaf, t->nleaf, t->d.partial, r32,
                       stream_of(t));
     launch_reduce_trees(t->d.partial, t->d.leaf_tree, t->d.chunk, (int64_t)t->chunk.size() / 3, t->d.choff,
@@ -1039,7 +1056,7 @@ int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule) {
         for (int v = 0; v < kGsrbVariants && !rc; v++) {
             // reps half-sweeps, or reps/2 fused sweeps (the same work)
             auto sweeps = [&]() {
-                bool fused = v >= kGsrbHalfVariants;
+                bool fused = v >= kGsrbFusedVariant && v < kGsrbOctVariant;
                 for (int q = 0; q < (fused ? reps / 2 : reps); q++) {
                     if (fp32) {
                         Fields<float> F = f32(t);

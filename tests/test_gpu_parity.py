@@ -429,10 +429,11 @@ def test_every_gsrb_variant_gives_the_same_bits(tree, fp32):
     say("variants", tree, "fp32" if fp32 else "fp64", "all", M.MG_GSRB_VARIANTS, "identical")
 
 
-@pytest.mark.parametrize("v", M.MG_GSRB_FUSED)
-def test_fused_sweeps_match_the_oracle(v):
-    """Fused sweeps against the oracle's sweep-by-sweep smoothing: per-cell
-    Dirichlet data, a Neumann face and refinement boundaries."""
+@pytest.mark.parametrize("v", M.MG_GSRB_FUSED + M.MG_GSRB_OCTET)
+def test_fused_and_octet_sweeps_match_the_oracle(v):
+    """Fused sweeps and octet half-sweeps against the oracle's sweep-by-sweep
+    smoothing: per-cell Dirichlet data, a Neumann face and refinement
+    boundaries."""
     g, o = bcval_tree()
     M.mg_set_schedule(g.h, M.MG_FP64, [v] * g.nlev)
     for op_g, op_o, lev, arg in ((M.MG_OP_SMOOTH, O.OP_SMOOTH, o.nlev, 2),
