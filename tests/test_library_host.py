@@ -138,8 +138,31 @@ def test_workspace_size_is_reported():
     w = streamer_small()
     g = M.Tree.from_workload(w, bind=False)
     n = g.n
-    assert g.info.workspace_bytes >= 3 * 512 * 8 * n
+    # phi, rhs, old and the fused sweeps' second buffer (FP64), plus the FP32 fields
+    assert g.info.workspace_bytes >= 4 * 512 * 8 * n + 3 * 512 * 4 * n
     assert g.info.n_leaf_cells == w.n_leaf
+
+
+def test_schedule_entries_are_validated():
+    """mg_set_schedule takes one entry per level in 0..MG_GSRB_VARIANTS-1
+    (host state only, no GPU); mg_autotune needs a bound workspace."""
+    hdr = open(os.path.join(ROOT, "include", "mg.h")).read()
+    assert int(re.search(r"#define MG_GSRB_VARIANTS (\d+)", hdr).group(1)) == M.MG_GSRB_VARIANTS
+    bl = uniform_boxes(3)
+    h = M.mg_tree_create(M.make_domain(), bl.level, bl.ijk)
+    try:
+        L = M.lib()
+        for prec in (M.MG_FP64, M.MG_MIXED):
+            for v in range(M.MG_GSRB_VARIANTS):
+                M.mg_set_schedule(h, prec, [v, v, v])
+            for bad in (-1, M.MG_GSRB_VARIANTS):
+                sch = np.array([3, bad, 3], dtype=np.int32)
+                assert L.mg_set_schedule(h, prec, sch.ctypes.data) == M.MG_EINVAL
+        sch = np.zeros(3, dtype=np.int32)
+        assert L.mg_set_schedule(h, 7, sch.ctypes.data) == M.MG_EINVAL
+        assert L.mg_autotune(h, M.MG_FP64, 4, sch.ctypes.data) == M.MG_ESTATE
+    finally:
+        M.mg_tree_destroy(h)
 
 
 def test_workload_leaf_counts_match_the_tables():
