@@ -12,6 +12,8 @@ struct Geo {
     const int32_t *cfslot;  // [n][6]
     const int32_t *cfq;     // [n][6]
     const int32_t *xt;      // [n][6][4][2] faces of the face neighbours
+    const int32_t *pnb;     // [n][6] the parent's face neighbours
+    const int32_t *slotx;   // [nslot][8] Q, base t1, base t2, Q's neighbours -t1 +t1 -t2 +t2
     const int32_t *ijk;     // [n][4] (i, j, k, level)
     const int32_t *parent;  // [n]
     const double *bcval;    // [n][6][64] or null

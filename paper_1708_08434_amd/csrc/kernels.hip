@@ -428,15 +428,15 @@ __global__ __launch_bounds__(256) void k_gsrb_sweep(Geo g, const T *__restrict__
 }
 
 // Coarse value of cell D = C + dir * e_ax (level l-1, relative to box Q),
-// with the coarse physical ghost outside the domain.
+// with the coarse physical ghost outside the domain; N is Q's neighbour
+// across the face D leaves Q through.
 template <typename T>
 __device__ __forceinline__ T coarse_at(const Geo &g, const T *__restrict__ phi, int64_t Q,
-                                       const int C[3], int ax, int dir) {
+                                       const int C[3], int ax, int dir, int N) {
     int D[3] = {C[0], C[1], C[2]};
     D[ax] += dir;
     if (D[ax] >= 0 && D[ax] < 8) return phi[Q * 512 + cs_idx3(D)];
     int face = 2 * ax + (dir > 0 ? 1 : 0);
-    int N = g.nbr[Q * 6 + face];
     if (N >= 0) {
         D[ax] = dir > 0 ? 0 : 7;
         return phi[(int64_t)N * 512 + cs_idx3(D)];
@@ -456,23 +456,23 @@ __device__ __forceinline__ T coarse_at(const Geo &g, const T *__restrict__ phi, 
 template <typename T>
 __device__ __forceinline__ void cf_face(const Geo &g, const T *__restrict__ phi, T *__restrict__ chat,
                                         const int32_t *__restrict__ slots, int64_t s, int lane) {
-    int64_t b = slots[2 * s];
     int d = slots[2 * s + 1];
+    const int32_t *x = g.slotx + 8 * s;  // Q, base t1, base t2, Q's neighbours
     int a = d >> 1, side = d & 1, t1, t2;
     tangential(a, t1, t2);
     int u = lane & 7, v = lane >> 3;
-    int64_t Q = g.cfq[b * 6 + d];
+    int64_t Q = x[0];
     int C[3];
     C[a] = side ? 0 : 7;
-    C[t1] = 4 * (g.ijk[b * 4 + t1] & 1) + (u >> 1);
-    C[t2] = 4 * (g.ijk[b * 4 + t2] & 1) + (v >> 1);
+    C[t1] = x[1] + (u >> 1);
+    C[t2] = x[2] + (v >> 1);
     T acc = (T)0.875 * phi[Q * 512 + cs_idx3(C)];
 #pragma unroll
     for (int q = 0; q < 2; q++) {
         int ax = q ? t2 : t1;
         T st = (((q ? v : u) & 1) ? (T)1 : (T)-1);
-        T cp = coarse_at<T>(g, phi, Q, C, ax, 1);
-        T cm = coarse_at<T>(g, phi, Q, C, ax, -1);
+        T cp = coarse_at<T>(g, phi, Q, C, ax, 1, x[4 + 2 * q]);
+        T cm = coarse_at<T>(g, phi, Q, C, ax, -1, x[3 + 2 * q]);
         acc += ((T)(1.0 / 32.0) + st / (T)8) * cp + ((T)(1.0 / 32.0) - st / (T)8) * cm;
     }
     chat[s * 64 + lane] = acc;
@@ -515,6 +515,9 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Geo g, T *__restrict__ p
     int64_t lb = xcd_map(blk, nbx);
     if (lb >= nbx) return;
     int64_t b = b0 + lb;
+    // indices of the parent cells, loaded with the data (not after the barriers)
+    const int64_t p = g.parent[b];
+    const int bi = g.ijk[b * 4] & 1, bj = g.ijk[b * 4 + 1] & 1, bk = g.ijk[b * 4 + 2] & 1;
     T r0 = rhs[b * 512 + t], r1 = rhs[b * 512 + 256 + t];
     stage_full<T>(g, phi, chat, b, P, H);
     __syncthreads();
@@ -540,9 +543,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Geo g, T *__restrict__ p
                     sphi += P[c];
                     sres += R[c];
                 }
-        int64_t p = g.parent[b];
-        int ci = 4 * (g.ijk[b * 4] & 1) + pi, cj = 4 * (g.ijk[b * 4 + 1] & 1) + pj,
-            ck = 4 * (g.ijk[b * 4 + 2] & 1) + pk;
+        int ci = 4 * bi + pi, cj = 4 * bj + pj, ck = 4 * bk + pk;
         int64_t pc = p * 512 + cs_idx(ci, cj, ck);
         T mphi = (T)0.125 * sphi;
         phi[pc] = mphi;
@@ -602,6 +603,8 @@ __global__ __launch_bounds__(256) void k_prolong_cf(Geo g, T *__restrict__ phi, 
     int64_t b = b0 + lb;
     int64_t p = g.parent[b];
     int o[3] = {g.ijk[b * 4] & 1, g.ijk[b * 4 + 1] & 1, g.ijk[b * 4 + 2] & 1};
+    // this box's values, loaded with the correction (not after the barrier)
+    T f0 = phi[b * 512 + t], f1 = phi[b * 512 + 256 + t];
     if (t < 216) {
         int c[3] = {t % 6 - 1, (t / 6) % 6 - 1, t / 36 - 1}, out = 0, oax = 0;
         for (int a = 0; a < 3; a++)
@@ -614,7 +617,7 @@ __global__ __launch_bounds__(256) void k_prolong_cf(Geo g, T *__restrict__ phi, 
                 del = phi[q] - old[q];
             } else {
                 int face = 2 * oax + (C[oax] > 7 ? 1 : 0);
-                int N = g.nbr[p * 6 + face];
+                int N = g.pnb[b * 6 + face];  // = nbr[p][face]
                 if (N >= 0) {
                     C[oax] = C[oax] > 7 ? 0 : 7;
                     int64_t q = (int64_t)N * 512 + cs_idx3(C);
@@ -639,7 +642,7 @@ __global__ __launch_bounds__(256) void k_prolong_cf(Geo g, T *__restrict__ phi, 
         int at = (z * 6 + y) * 6 + x;
         T d0 = D[at], dx = D[at + sx], dy = D[at + 6 * sy], dz = D[at + 36 * sz];
         int64_t idx = b * 512 + c * 256 + t;
-        phi[idx] += (T)0.25 * d0 + (T)0.25 * (dx + dy + dz);
+        phi[idx] = (c ? f1 : f0) + ((T)0.25 * d0 + (T)0.25 * (dx + dy + dz));
     }
 }
 

@@ -49,6 +49,8 @@ Geo geo(const mg_tree *t, bool homogeneous) {
     g.cfslot = t->d.cfslot;
     g.cfq = t->d.cfq;
     g.xt = t->d.xt;
+    g.pnb = t->d.pnb;
+    g.slotx = t->d.slotx;
     g.ijk = t->d.ijk;
     g.parent = t->d.parent;
     g.bcval = (!homogeneous && t->dom.per_cell_bc) ? t->d.bcval : nullptr;
@@ -805,6 +807,8 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.cfslot = (int32_t *)(base + t->off.cfslot);
     d.cfq = (int32_t *)(base + t->off.cfq);
     d.xt = (int32_t *)(base + t->off.xt);
+    d.pnb = (int32_t *)(base + t->off.pnb);
+    d.slotx = (int32_t *)(base + t->off.slotx);
     d.ijk = (int32_t *)(base + t->off.ijk);
     d.parent = (int32_t *)(base + t->off.parent);
     d.refined = (int32_t *)(base + t->off.refined);
@@ -852,6 +856,8 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     rc = rc ? rc : up(d.cfslot, t->cfslot.data(), t->cfslot.size() * 4);
     rc = rc ? rc : up(d.cfq, t->cfq.data(), t->cfq.size() * 4);
     rc = rc ? rc : up(d.xt, t->xt.data(), t->xt.size() * 4);
+    rc = rc ? rc : up(d.pnb, t->pnb.data(), t->pnb.size() * 4);
+    rc = rc ? rc : up(d.slotx, t->slotx.data(), t->slotx.size() * 4);
     rc = rc ? rc : up(d.ijk, ijk4.data(), ijk4.size() * 4);
     rc = rc ? rc : up(d.parent, t->parent.data(), t->parent.size() * 4);
     rc = rc ? rc : up(d.refined, t->refined.data(), t->refined.size() * 4);

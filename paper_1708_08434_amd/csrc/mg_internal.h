@@ -21,6 +21,8 @@ struct DevTables {
     int32_t *cfslot = nullptr;   // [n][6]  slot of a refinement-boundary face, or -1
     int32_t *cfq = nullptr;      // [n][6]  coarser box across a refinement-boundary face
     int32_t *xt = nullptr;       // [n][6][4][2] faces of the face neighbours (fused sweep)
+    int32_t *pnb = nullptr;      // [n][6] the parent's face neighbours
+    int32_t *slotx = nullptr;    // [nslot][8] coarse-side indices of a slot's c_hat
     int32_t *ijk = nullptr;      // [n][4]  i, j, k, level
     int32_t *parent = nullptr;   // [n]
     int32_t *refined = nullptr;  // per-level lists of boxes with children
@@ -56,7 +58,7 @@ struct mg_tree {
     // ---- host tables (canonical order) ----
     int64_t n = 0;
     int nlev = 0, ntree = 0;
-    std::vector<int32_t> order, lev, ijk, tid, parent, child, nbr, cfq, cfslot, xt;
+    std::vector<int32_t> order, lev, ijk, tid, parent, child, nbr, cfq, cfslot, xt, pnb, slotx;
     int64_t lstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> refined, leaf;                 // box ids grouped by level
     int64_t rstart[mg::kMaxLevel + 2] = {0}, fstart[mg::kMaxLevel + 2] = {0};
@@ -70,7 +72,7 @@ struct mg_tree {
     mg_domain dom{};
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
-    struct { int64_t nbr, cfslot, cfq, xt, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
+    struct { int64_t nbr, cfslot, cfq, xt, pnb, slotx, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
              phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, swp, total; } off{};
     // ---- bound device state ----
     void *ws = nullptr;

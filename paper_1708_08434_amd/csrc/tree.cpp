@@ -236,6 +236,29 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     }
     t->sstart[0] = 0;
     t->nslot = (int64_t)t->slots.size() / 2;
+    // per slot, the coarse-side indices of its c_hat: the coarser box Q, the
+    // base coordinates of the face's quarter of Q along the two tangential
+    // axes, and Q's face neighbours across them (-t1, +t1, -t2, +t2)
+    t->slotx.assign((size_t)8 * t->nslot, 0);
+    for (int64_t q = 0; q < t->nslot; q++) {
+        int64_t b = t->slots[2 * q];
+        int d = t->slots[2 * q + 1], a = d >> 1, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+        int32_t Q = t->cfq[6 * b + d];
+        int32_t *x = &t->slotx[8 * q];
+        x[0] = Q;
+        x[1] = 4 * (t->ijk[3 * b + t1] & 1);
+        x[2] = 4 * (t->ijk[3 * b + t2] & 1);
+        x[3] = t->nbr[6 * (int64_t)Q + 2 * t1];
+        x[4] = t->nbr[6 * (int64_t)Q + 2 * t1 + 1];
+        x[5] = t->nbr[6 * (int64_t)Q + 2 * t2];
+        x[6] = t->nbr[6 * (int64_t)Q + 2 * t2 + 1];
+    }
+    // the parent's face neighbours of every box (prolongation stages the
+    // parent's correction one cell beyond its octant)
+    t->pnb.assign((size_t)6 * n, -2);
+    for (int64_t b = 0; b < n; b++)
+        if (t->parent[b] >= 0)
+            for (int f = 0; f < 6; f++) t->pnb[6 * b + f] = t->nbr[6 * (int64_t)t->parent[b] + f];
     // faces of the face neighbours: for box b, face d with a same-level
     // neighbour N, and the 4 faces of N across the two axes tangential to d
     // (-t1, +t1, -t2, +t2), the pair (nbr[N][d'], cfslot[N][d']); the fused
@@ -304,11 +327,13 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.cfslot = take(24 * n);
     t->off.cfq = take(24 * n);
     t->off.xt = take(192 * n);
+    t->off.pnb = take(24 * n);
     t->off.ijk = take(16 * n);
     t->off.parent = take(4 * n);
     t->off.refined = take(4 * (int64_t)t->refined.size());
     t->off.leaf = take(4 * t->nleaf);
     t->off.slots = take(8 * t->nslot);
+    t->off.slotx = take(32 * t->nslot);
     t->off.leaf_tree = take(4 * t->nleaf);
     t->off.tree_off = take(4 * (int64_t)(ntree + 1));
     t->off.chunk = take(4 * (int64_t)t->chunk.size());
