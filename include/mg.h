@@ -256,6 +256,8 @@ int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out);
  *         runs as half-sweeps of variant 3);
  *   c = 4: half-sweeps over octets of sibling boxes (one workgroup per 16^3
  *         octet; faces between siblings come from LDS);
+ *   c = 5, 6: half-sweeps by at most 2048 or 4096 persistent workgroups,
+ *         each walking a run of boxes with the next box's data in flight;
  *   x = 1 selects the XCD-aware mapping of workgroups to boxes.
  * The entry of level 1 (never smoothed) selects how the two coarsest levels
  * run: 0 = step by step, any other value = one launch per V-cycle with one
@@ -270,7 +272,7 @@ int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out);
  * sizes) and rejects entries outside 0..MG_GSRB_VARIANTS-1.  All variants
  * compute the same values.
  */
-#define MG_GSRB_VARIANTS 10
+#define MG_GSRB_VARIANTS 14
 int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule);
 int mg_set_schedule(mg_tree *t, int precision, const int32_t *schedule);
 

@@ -32,12 +32,15 @@ template <typename T> void launch_unpack(const T *cs, double *nat, int64_t nbox,
 // box), c = 3 for fused sweeps (red and black in one launch, ping-ponging
 // between the field and a second buffer), c = 4 for half-sweeps over octets
 // of sibling boxes (one 512-thread workgroup per 16^3 octet; levels >= 2,
-// whose boxes come in complete consecutive octets), and x = 1 for the
-// XCD-aware mapping.  All variants do the same arithmetic on every cell.
-constexpr int kGsrbVariants = 10;
+// whose boxes come in complete consecutive octets), c = 5, 6 for half-sweeps
+// by at most 2048 or 4096 persistent workgroups that prefetch their next
+// box, and x = 1 for the XCD-aware mapping.  All variants do the same
+// arithmetic on every cell.
+constexpr int kGsrbVariants = 14;
 constexpr int kGsrbHalfVariants = 6;  // variants 0..5 are one-box half-sweeps
 constexpr int kGsrbFusedVariant = 6;  // 6, 7: fused sweeps
 constexpr int kGsrbOctVariant = 8;    // 8, 9: octet half-sweeps
+constexpr int kGsrbPipeVariant = 10;  // 10..13: persistent prefetching half-sweeps
 constexpr int kGsrbDefault = 3;       // 2 cells per thread, XCD mapping
 // One colour in place; a fused variant, or an octet variant on a box count
 // that is not a multiple of 8, falls back to kGsrbDefault.

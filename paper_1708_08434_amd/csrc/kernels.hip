@@ -175,12 +175,17 @@ __global__ __launch_bounds__(256) void k_unpack(const T *__restrict__ cs, double
 // mapping are the launch variants the autotuner chooses from; every variant
 // performs the same arithmetic on every cell.
 template <typename T>
-__device__ __forceinline__ void gsrb_ghost(const Geo &g, const FaceTab &ft, const T *__restrict__ phi,
-                                           const T *__restrict__ chat, int64_t b, int C, int e, T *H) {
+__device__ __forceinline__ T gsrb_ghost_val(const Geo &g, const FaceTab &ft, const T *__restrict__ phi,
+                                            const T *__restrict__ chat, int64_t b, int C, int e) {
     int d = e >> 5, q = e & 31, v = q >> 2;
     int layer = (d & 1) ? 7 : 0;
     int u = 2 * (q & 3) + ((layer + v + C) & 1);
-    H[e] = ghost_at<T>(g, phi, chat, b, d, pick6(ft.nb, d), pick6(ft.slot, d), u, v);
+    return ghost_at<T>(g, phi, chat, b, d, pick6(ft.nb, d), pick6(ft.slot, d), u, v);
+}
+template <typename T>
+__device__ __forceinline__ void gsrb_ghost(const Geo &g, const FaceTab &ft, const T *__restrict__ phi,
+                                           const T *__restrict__ chat, int64_t b, int C, int e, T *H) {
+    H[e] = gsrb_ghost_val<T>(g, ft, phi, chat, b, C, e);
 }
 
 template <typename T, int N> struct VecN;
@@ -229,6 +234,99 @@ __global__ __launch_bounds__(256 / CPT) void k_gsrb(Geo g, T *__restrict__ phi,
         out[w] = (s - h2 * bb[w]) * (T)kSixth;
     }
     reinterpret_cast<V *>(phi + b * 512 + C * 256)[t] = res;
+}
+
+// Workgroup barrier that orders LDS only: global loads issued before it stay
+// in flight (the prefetch of the next box), unlike __syncthreads().
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One colour C of red-black Gauss-Seidel with persistent workgroups of 128
+// threads (2 cells each): workgroup w takes boxes base, base + step, ...
+// (with the XCD mapping: the boxes of its XCD's contiguous range, in turn
+// with the XCD's other workgroups), and while it updates one box it has the
+// next box's cells, right-hand side and ghosts in flight and the face table
+// of the one after.  The ghosts of a box read only the other colour and the
+// box's own cells, which no workgroup writes during this half-sweep before
+// the box itself is updated, so loading them early changes nothing.  Same
+// arithmetic per cell as k_gsrb.
+template <int C, typename T>
+__global__ __launch_bounds__(128) void k_gsrb_pipe(Geo g, T *__restrict__ phi, const T *__restrict__ rhs,
+                                                   const T *__restrict__ chat, int64_t b0, int64_t nbx,
+                                                   T h2, int xcd) {
+    using V = typename VecN<T, 2>::type;
+    __shared__ T S[256], H[192];
+    const int t = threadIdx.x;
+    int64_t base, step, end;
+    if (xcd) {
+        int64_t per = (nbx + 7) >> 3, x = blockIdx.x & 7;
+        base = x * per + (blockIdx.x >> 3);
+        step = gridDim.x >> 3;
+        end = min((x + 1) * per, nbx);
+    } else {
+        base = blockIdx.x;
+        step = gridDim.x;
+        end = nbx;
+    }
+    if (base >= end) return;
+    int64_t b = b0 + base;
+    FaceTab ft = face_tab(g, b);
+    V o = reinterpret_cast<const V *>(phi + b * 512 + (1 - C) * 256)[t];
+    V bv = reinterpret_cast<const V *>(rhs + b * 512 + C * 256)[t];
+    T g0 = gsrb_ghost_val<T>(g, ft, phi, chat, b, C, t);
+    T g1 = t < 64 ? gsrb_ghost_val<T>(g, ft, phi, chat, b, C, t + 128) : (T)0;
+    int64_t nxt = base + step;
+    FaceTab ftn = ft;
+    if (nxt < end) ftn = face_tab(g, b0 + nxt);
+    for (;;) {
+        const bool more = nxt < end;
+        const int64_t bn = b0 + nxt;
+        V on = o, bvn = bv;
+        T g0n = 0, g1n = 0;
+        FaceTab ftnn = ftn;
+        if (more) {
+            on = reinterpret_cast<const V *>(phi + bn * 512 + (1 - C) * 256)[t];
+            bvn = reinterpret_cast<const V *>(rhs + bn * 512 + C * 256)[t];
+            g0n = gsrb_ghost_val<T>(g, ftn, phi, chat, bn, C, t);
+            if (t < 64) g1n = gsrb_ghost_val<T>(g, ftn, phi, chat, bn, C, t + 128);
+            if (nxt + step < end) ftnn = face_tab(g, bn + step);
+        }
+        reinterpret_cast<V *>(S)[t] = o;
+        H[t] = g0;
+        if (t < 64) H[t + 128] = g1;
+        lds_sync();
+        const T *bb = reinterpret_cast<const T *>(&bv);
+        V res;
+        T *out = reinterpret_cast<T *>(&res);
+#pragma unroll
+        for (int w = 0; w < 2; w++) {
+            int cq = 2 * t + w;
+            int m = cq & 3, j = (cq >> 2) & 7, k = cq >> 5;
+            int i = 2 * m + ((j + k + C) & 1);
+            int row = (k * 8 + j) * 4;
+            T xm = i > 0 ? S[row + ((i - 1) >> 1)] : H[0 * 32 + k * 4 + (j >> 1)];
+            T xp = i < 7 ? S[row + ((i + 1) >> 1)] : H[1 * 32 + k * 4 + (j >> 1)];
+            T ym = j > 0 ? S[row - 4 + m] : H[2 * 32 + k * 4 + m];
+            T yp = j < 7 ? S[row + 4 + m] : H[3 * 32 + k * 4 + m];
+            T zm = k > 0 ? S[row - 32 + m] : H[4 * 32 + j * 4 + m];
+            T zp = k < 7 ? S[row + 32 + m] : H[5 * 32 + j * 4 + m];
+            T s = xm + xp + ym + yp + zm + zp;
+            out[w] = (s - h2 * bb[w]) * (T)kSixth;
+        }
+        reinterpret_cast<V *>(phi + b * 512 + C * 256)[t] = res;
+        lds_sync();
+        if (!more) break;
+        b = bn;
+        o = on;
+        bv = bvn;
+        g0 = g0n;
+        g1 = g1n;
+        ftn = ftnn;
+        nxt += step;
+    }
 }
 
 // One colour C of red-black Gauss-Seidel on the octets (complete sets of 8
@@ -1170,6 +1268,18 @@ template <typename T>
 void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
                  int colour, int variant, hipStream_t s) {
     if (nb <= 0) return;
+    if (variant >= kGsrbPipeVariant) {
+        // persistent workgroups: at most 2048 (c = 5) or 4096 (c = 6)
+        int64_t cap = variant >= kGsrbPipeVariant + 2 ? 4096 : 2048;
+        int xcd = variant & 1;
+        int64_t nw = nb < cap ? nb : cap;
+        dim3 grid((unsigned)(xcd ? xcd_grid(nw) : nw));
+        if (colour == 0)
+            hipLaunchKernelGGL((k_gsrb_pipe<0, T>), grid, dim3(128), 0, s, g, phi, rhs, chat, b0, nb, h2, xcd);
+        else
+            hipLaunchKernelGGL((k_gsrb_pipe<1, T>), grid, dim3(128), 0, s, g, phi, rhs, chat, b0, nb, h2, xcd);
+        return;
+    }
     if (variant >= kGsrbOctVariant && (nb & 7) == 0) {
         int64_t noct = nb >> 3;
         int xcd = variant & 1;

@@ -133,7 +133,8 @@ template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsw
         }
     }
     int variant = t->sched[sizeof(T) == 4 ? 1 : 0][l];
-    if (l < 2 && variant >= kGsrbOctVariant) variant = kGsrbDefault;  // roots are not octets
+    if (l < 2 && variant >= kGsrbOctVariant && variant < kGsrbPipeVariant)
+        variant = kGsrbDefault;  // roots are not octets
     int64_t launches = 0;
     int it = 0;
     if (variant >= kGsrbFusedVariant && variant < kGsrbOctVariant) {

@@ -25,9 +25,10 @@ MG_FP64, MG_MIXED = 0, 1
 MG_OP_SMOOTH, MG_OP_FAS_DOWN, MG_OP_PROLONG, MG_OP_COARSE, MG_OP_RESTRICT_ALL, MG_OP_VCYCLE = \
     range(1, 7)
 MG_OP_F32 = 0x100
-MG_GSRB_VARIANTS = 10  # Gauss-Seidel launch variants: 6, 7 fused sweeps, 8, 9 octet half-sweeps
+MG_GSRB_VARIANTS = 14  # launch variants: 6, 7 fused sweeps, 8, 9 octets, 10-13 persistent
 MG_GSRB_FUSED = (6, 7)
 MG_GSRB_OCTET = (8, 9)
+MG_GSRB_PERSISTENT = (10, 11, 12, 13)
 _WIDTH = {MG_IDX_ORDER: 1, MG_IDX_LEVEL: 1, MG_IDX_IJK: 3, MG_IDX_TREE: 1, MG_IDX_PARENT: 1,
           MG_IDX_CHILD: 8, MG_IDX_NBR: 6, MG_IDX_CFQ: 6}
 
