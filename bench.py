@@ -181,6 +181,70 @@ def learned_leg(g, args, k_plain, value_plain):
                            "frac": tflops / BF16_PEAK_TFLOPS}}
 
 
+EFIELD_BYTES_PER_BOX = 8 * (512 + 3 * 9 * 64 + 512)  # read phi; write face components and |E|
+
+
+def time_step_leg(g, args):
+    """The solver as a time-stepped streamer run uses it (paper sections
+    2.1.2 and 2.4): after the initial FMG solve, every field solve sets the
+    new right-hand side, runs two V-cycles warm-started from the previous
+    potential (mg_vcycle) and forms the electric field on every box
+    (mg_efield); a time step holds two field solves.  The right-hand sides are
+    the benchmark streamer with its head moved down by dz per field solve, on
+    the same tree, generated beforehand and resident in HBM."""
+    import torch
+    from paper_1708_08434_amd import mg as M
+    from workloads import c2_head_sequence
+    nsolve = 2 * args.ts_steps
+    dz = 2.5e-5  # 1 um of the paper's 40 mm domain per field solve
+    lv, ij = g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK)
+    seq = c2_head_sequence(lv, ij, nsolve + 3, dz)
+    rhs = [torch.from_numpy(seq[s]).to("cuda:0") for s in range(nsolve + 3)]
+    del seq
+    face = torch.empty((g.n, 3, 9, 8, 8), dtype=torch.float64, device="cuda:0")
+    norm = torch.empty((g.n, 8, 8, 8), dtype=torch.float64, device="cuda:0")
+    opts = g.opts()
+    M.mg_field_set(g.h, M.MG_FIELD_RHS, rhs[0].data_ptr())
+    g.fmg_solve()
+
+    def field_solve(s):
+        M.mg_field_set(g.h, M.MG_FIELD_RHS, rhs[s].data_ptr())
+        st = M.mg_vcycle(g.h, opts, 2)
+        M.mg_efield(g.h, face.data_ptr(), norm.data_ptr())
+        return st
+    for s in (1, 2):  # warm-up (records the V-cycle graph)
+        field_solve(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rel0, rel2 = [], []
+    for s in range(3, nsolve + 3):
+        st = field_solve(s)
+        rel0.append(st.rel_hist[0])
+        rel2.append(st.rel_res)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # the field kernel alone, HIP events on the tree's stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(g.stream):
+        e0.record()
+        for _ in range(10):
+            M.mg_efield(g.h, face.data_ptr(), norm.data_ptr())
+        e1.record()
+    torch.cuda.synchronize()
+    ef_s = e0.elapsed_time(e1) / 1e3 / 10
+    n_leaf = int(g.info.n_leaf_cells)
+    gbps = EFIELD_BYTES_PER_BOX * g.n / ef_s / 1e9
+    return {"field_solves_per_s": nsolve / el, "ms_per_field_solve": 1e3 * el / nsolve,
+            "ms_per_time_step": 2e3 * el / nsolve, "vcycles_per_s": 2 * nsolve / el,
+            "leaf_cells_per_s": n_leaf * nsolve / el, "field_solves": nsolve,
+            "head_shift_per_solve": dz,
+            "rel_res_before_max": max(rel0), "rel_res_after_2_vcycles_max": max(rel2),
+            "efield": {"kernel": "k_efield (face components + cell strength, all boxes)",
+                       "boxes": g.n, "avg_launch_us": ef_s * 1e6,
+                       "bytes_per_box": EFIELD_BYTES_PER_BOX, "achieved": gbps,
+                       "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +254,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction leg")
     ap.add_argument("--train-steps", type=int, default=300, help="Adam steps of the learned leg")
+    ap.add_argument("--ts-steps", type=int, default=8,
+                    help="time steps (2 warm-started field solves each) of the time-stepping leg; "
+                         "0 skips it (benchmark streamer only)")
     ap.add_argument("--copy-probe", type=int, default=0, help="bytes of a calibration copy")
     ap.add_argument("--workload", default="streamer",
                     choices=["streamer", "forest", "branched", "two_streamers"],
@@ -267,6 +334,9 @@ def main():
     learned = None
     if not args.no_learned:
         learned = learned_leg(g, args, k, value)
+    time_step = None
+    if args.ts_steps > 0 and args.workload == "streamer":
+        time_step = time_step_leg(g, args)
     copy = copy_bandwidth()
     mb = model_bytes(counts, n_leaf, k)
     # the level whose half-sweeps move the most bytes (the finest level of a
@@ -319,6 +389,8 @@ def main():
         out["mixed"] = mixed
     if learned is not None:
         out["learned"] = learned
+    if time_step is not None:
+        out["time_step"] = time_step
     if rank == 0 and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, k)
     if rank == 0:

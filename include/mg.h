@@ -194,6 +194,26 @@ int mg_fmg_solve(mg_tree *t, const mg_solve_opts *o, mg_solve_stats *s);
  */
 int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *s);
 
+/*
+ * mg_efield - electric field of the current phi (section 2.3: E = -grad phi,
+ * components on the cell faces, strength at the cell centres).  Covered
+ * cells of phi are first reset to the mean of their children (as before a
+ * residual check); each box then uses its own ghosts (same-level neighbour,
+ * boundary condition, refinement-boundary interpolation), as the solver does.
+ *   e_face  device, n*3*9*64 doubles, or NULL: for box b (canonical order),
+ *           axis a (x, y, z) and face f = 0..8 across the box (face f lies
+ *           between cells f-1 and f; faces 0 and 8 on the box boundary),
+ *           E_a = (phi(f-1) - phi(f)) / h at index ((b*3 + a)*9 + f)*64 +
+ *           v*8 + u, with u and v the cell indices along the other two axes
+ *           in increasing order.
+ *   e_norm  device, n*512 doubles, or NULL: sqrt(Ex^2 + Ey^2 + Ez^2) at each
+ *           cell centre (natural order, x fastest), each component the mean
+ *           of the cell's two face values.
+ * Every box is written, covered ones included.  Asynchronous on the bound
+ * stream; MG_EINVAL if both outputs are NULL.
+ */
+int mg_efield(mg_tree *t, double *e_face, double *e_norm);
+
 /* Relative residual, L2 and max norms of the current phi (leaf cells). */
 int mg_residual(mg_tree *t, double *rel, double *l2, double *linf);
 

@@ -59,6 +59,7 @@ def lib():
         L.oracle_apply.argtypes = [P, P, P, I32]
         L.oracle_set_threads.argtypes = [I32]
         L.oracle_tree_rel.argtypes = [P, P]
+        L.oracle_efield.argtypes = [P, P, P]
         L.oracle_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -174,6 +175,16 @@ class OracleTree:
         y = np.zeros_like(x)
         _check(lib().oracle_apply(self.h, _ptr(x), _ptr(y), int(homog)))
         return y
+
+    def efield(self):
+        """Electric field of the current phi (covered cells reset to the mean
+        of their children first): face components [n][3][9][8][8] (axis,
+        face index, second then first tangential axis) and the cell-centre
+        strength [n][8][8][8] (natural order)."""
+        face = np.zeros((self.n, 3, 9, 8, 8))
+        norm = np.zeros((self.n, 8, 8, 8))
+        _check(lib().oracle_efield(self.h, _ptr(face), _ptr(norm)))
+        return face, norm
 
     def leaf_mask(self):
         return self.index(IDX_CHILD)[:, 0] < 0

@@ -719,6 +719,57 @@ static void leaf_norms(otree *t, double *sq, double *mx) {
     free(part); free(pmax);
 }
 
+/* ---------------------------------------------------------- electric field */
+
+/* Electric field of the current phi (paper section 2.3, E = -grad phi).  On
+   the cell faces by central differences: the x-component at the face between
+   cells i and i+1 is (phi_i - phi_{i+1}) / h, and likewise in y and z.  The
+   field strength at a cell centre is sqrt(Ex^2 + Ey^2 + Ez^2), each component
+   the mean of the cell's two face values.  Covered cells are first reset to
+   the mean of their children and every box's ghosts are filled as for the
+   residual, so a box-boundary face uses the box's own ghost.
+   e_face (or NULL): [n][3][9][64], axis a, face f = 0..8 between cells f-1
+   and f along a, tangential cell v*8 + u (u along the first other axis).
+   e_norm (or NULL): [n][512], natural order (x fastest). */
+int oracle_efield(otree *t, double *e_face, double *e_norm) {
+    t->bad_lookup = 0;
+    restrict_all(t);
+    for (int l = 1; l <= t->nlev; l++) fill_ghosts(t, l, t->f[F_PHI], 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < t->n; b++) {
+        const double *fb = t->f[F_PHI] + b * BOX;
+        double h = hlev(t, t->lev[b]);
+        double E[3][9][64];
+        for (int a = 0; a < 3; a++) {
+            int t1, t2;
+            tang_axes(a, &t1, &t2);
+            for (int f = 0; f <= 8; f++)
+                for (int v = 0; v < 8; v++)
+                    for (int u = 0; u < 8; u++) {
+                        int lo[3], hi[3];
+                        lo[t1] = hi[t1] = u;
+                        lo[t2] = hi[t2] = v;
+                        lo[a] = f - 1;
+                        hi[a] = f;
+                        E[a][f][v * 8 + u] =
+                            (fb[AT(lo[0], lo[1], lo[2])] - fb[AT(hi[0], hi[1], hi[2])]) / h;
+                    }
+        }
+        if (e_face) memcpy(e_face + b * 3 * 9 * 64, E, sizeof E);
+        if (e_norm)
+            for (int k = 0; k < 8; k++)
+                for (int j = 0; j < 8; j++)
+                    for (int i = 0; i < 8; i++) {
+                        /* tangential index of the cell on each axis' faces */
+                        double ex = (E[0][i][k * 8 + j] + E[0][i + 1][k * 8 + j]) / 2.0;
+                        double ey = (E[1][j][k * 8 + i] + E[1][j + 1][k * 8 + i]) / 2.0;
+                        double ez = (E[2][k][j * 8 + i] + E[2][k + 1][j * 8 + i]) / 2.0;
+                        e_norm[b * 512 + (k * 8 + j) * 8 + i] = sqrt(ex * ex + ey * ey + ez * ez);
+                    }
+    }
+    return t->bad_lookup ? ORC_ESTATE : ORC_OK;
+}
+
 /* per-tree norm of the residual of phi = 0 (the right-hand side with the
    boundary data folded in) */
 static void beff_norm(otree *t, double *beff) {

@@ -85,6 +85,9 @@ template <typename T>
 void launch_leaf_apply(const Geo &g, const T *x, const T *chat, const int32_t *leaf, int64_t nleaf,
                        T *out, hipStream_t s);
 void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s);
+// Electric field of phi on all n boxes (face components and cell strength).
+void launch_efield(const Geo &g, const double *phi, const double *chat, int64_t n, double *e_face,
+                   double *e_norm, hipStream_t s);
 void launch_copy16(const void *src, void *dst, int64_t n16, int blocks, hipStream_t s);
 constexpr int kReduceChunk = 2048;  // leaf positions per first-stage block of the norm reduction
 void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const int32_t *chunk,

@@ -1154,6 +1154,50 @@ __global__ __launch_bounds__(256) void k_leaf_apply(Geo g, const T *__restrict__
     }
 }
 
+// Electric field of phi (section 2.3, E = -grad phi), one box per block:
+// face components by central differences, (phi(f-1) - phi(f)) / h across face
+// f = 0..8 of each axis (faces 0 and 8 with the box's ghosts), into
+// e_face[((b*3 + a)*9 + f)*64 + v*8 + u]; and the strength at the cell
+// centres, sqrt(Ex^2 + Ey^2 + Ez^2) with each component the mean of the
+// cell's two faces, into e_norm[b*512 + natural index].  Either output may
+// be null.  The 1728 face values are formed once (times 1/h) in LDS.
+__global__ __launch_bounds__(256) void k_efield(Geo g, const double *__restrict__ phi,
+                                                const double *__restrict__ chat, int64_t n,
+                                                double *__restrict__ e_face, double *__restrict__ e_norm) {
+    __shared__ double P[512], H[384], EF[1728];
+    int64_t b = xcd_map(blockIdx.x, n);
+    if (b >= n) return;
+    int t = threadIdx.x;
+    int l = g.ijk[b * 4 + 3];
+    stage_full<double>(g, phi, chat, b, P, H);
+    __syncthreads();
+    const double inv_h = (8.0 * (double)(1 << (l - 1))) / g.len;
+    // value of cell c along axis a (c = -1 or 8: the ghost on that face) at
+    // tangential (u, v)
+    auto val = [&](int a, int c, int u, int v) __attribute__((always_inline)) -> double {
+        if (c < 0) return H[(2 * a) * 64 + v * 8 + u];
+        if (c > 7) return H[(2 * a + 1) * 64 + v * 8 + u];
+        int i = a == 0 ? c : u, j = a == 0 ? u : a == 1 ? c : v, k = a == 2 ? c : v;
+        return P[cs_idx(i, j, k)];
+    };
+    for (int e = t; e < 3 * 9 * 64; e += 256) {
+        int a = e / 576, r = e - 576 * a, f = r >> 6, v = (r >> 3) & 7, u = r & 7;
+        double ef = (val(a, f - 1, u, v) - val(a, f, u, v)) * inv_h;
+        EF[e] = ef;
+        if (e_face) e_face[b * 1728 + e] = ef;
+    }
+    if (!e_norm) return;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 2; w++) {
+        int c = t + 256 * w, i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+        double ex = (EF[0 * 576 + i * 64 + k * 8 + j] + EF[0 * 576 + (i + 1) * 64 + k * 8 + j]) / 2.0;
+        double ey = (EF[1 * 576 + j * 64 + k * 8 + i] + EF[1 * 576 + (j + 1) * 64 + k * 8 + i]) / 2.0;
+        double ez = (EF[2 * 576 + k * 64 + j * 8 + i] + EF[2 * 576 + (k + 1) * 64 + j * 8 + i]) / 2.0;
+        e_norm[b * 512 + c] = sqrt(ex * ex + ey * ey + ez * ez);
+    }
+}
+
 // phi (FP64) += e (FP32) on every cell: the update of the mixed-precision
 // iterative refinement.
 __global__ __launch_bounds__(256) void k_ir_update(double *__restrict__ phi, const float *__restrict__ e,
@@ -1361,6 +1405,11 @@ void launch_leaf_apply(const Geo &g, const T *x, const T *chat, const int32_t *l
 }
 template void launch_leaf_apply<float>(const Geo &, const float *, const float *, const int32_t *,
                                        int64_t, float *, hipStream_t);
+void launch_efield(const Geo &g, const double *phi, const double *chat, int64_t n, double *e_face,
+                   double *e_norm, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_efield, dim3((unsigned)xcd_grid(n)), dim3(256), 0, s, g, phi, chat, n, e_face, e_norm);
+}
 void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_ir_update, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, phi, e, count);

@@ -983,6 +983,20 @@ int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *
     return s->status = rc;
 }
 
+int mg_efield(mg_tree *t, double *e_face, double *e_norm) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!e_face && !e_norm) {
+        set_error("mg_efield: no output");
+        return MG_EINVAL;
+    }
+    Fields<double> F = f64(t);
+    restrict_all(t, F);
+    ensure_cf_all(t, F);
+    launch_efield(F.g, F.phi, F.chat, t->n, e_face, e_norm, stream_of(t));
+    return hip_check(hipGetLastError(), "efield launch");
+}
+
 int mg_residual(mg_tree *t, double *rel, double *l2, double *linf) {
     int rc = require_bound(t);
     if (rc) return rc;

@@ -35,7 +35,7 @@ _WIDTH = {MG_IDX_ORDER: 1, MG_IDX_LEVEL: 1, MG_IDX_IJK: 3, MG_IDX_TREE: 1, MG_ID
 EXPORTS = ["mg_tree_create", "mg_tree_destroy", "mg_tree_info", "mg_tree_bind", "mg_tree_index",
            "mg_field_set", "mg_field_get", "mg_default_opts", "mg_fmg_solve", "mg_vcycle",
            "mg_residual", "mg_tree_residuals", "mg_step", "mg_timing_enable", "mg_timing_read",
-           "mg_autotune", "mg_set_schedule", "mg_stream_copy", "mg_last_error"]
+           "mg_autotune", "mg_set_schedule", "mg_stream_copy", "mg_efield", "mg_last_error"]
 
 
 class mg_domain(ctypes.Structure):
@@ -104,6 +104,7 @@ def lib():
         L.mg_vcycle.argtypes = [P, ctypes.POINTER(mg_solve_opts), I32,
                                 ctypes.POINTER(mg_solve_stats)]
         L.mg_residual.argtypes = [P, P, P, P]
+        L.mg_efield.argtypes = [P, P, P]
         L.mg_step.argtypes = [P, I32, I32, I32]
         L.mg_tree_residuals.argtypes = [P, P]
         L.mg_autotune.argtypes = [P, I32, I32, P]
@@ -199,6 +200,11 @@ def mg_residual(h):
     rel, l2, linf = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     check(lib().mg_residual(h, ctypes.byref(rel), ctypes.byref(l2), ctypes.byref(linf)))
     return dict(rel=rel.value, l2=l2.value, linf=linf.value)
+
+
+def mg_efield(h, face_ptr, norm_ptr):
+    """Electric field of the current phi into device buffers (either 0)."""
+    check(lib().mg_efield(h, ctypes.c_void_p(face_ptr or None), ctypes.c_void_p(norm_ptr or None)))
 
 
 def mg_tree_residuals(h, ntree):
@@ -334,6 +340,18 @@ class Tree:
 
     def residual(self):
         return mg_residual(self.h)
+
+    def efield(self, to_numpy=True):
+        """Face components [n][3][9][8][8] and cell-centre strength [n][8][8][8]
+        of E = -grad phi (mg_efield)."""
+        import torch
+        face = torch.empty((self.n, 3, 9, 8, 8), dtype=torch.float64, device=self.device)
+        norm = torch.empty((self.n, 8, 8, 8), dtype=torch.float64, device=self.device)
+        mg_efield(self.h, face.data_ptr(), norm.data_ptr())
+        if to_numpy:
+            self.stream.synchronize()
+            return face.cpu().numpy(), norm.cpu().numpy()
+        return face, norm
 
     def tree_rel(self):
         return mg_tree_residuals(self.h, int(self.info.n_trees))

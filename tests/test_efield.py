@@ -1,0 +1,181 @@
+"""Electric field on the octree (paper section 2.3: E = -grad phi on cell
+faces by central differences, the strength at cell centres from the mean of
+each component's two faces).
+
+CPU pins of the oracle (no GPU): a linear potential with matching Dirichlet
+data gives the exact constant field on an AMR tree (the refinement-boundary
+interpolation and the Dirichlet ghost are exact for linear functions); a
+quadratic potential gives E = -grad phi exactly at every face away from the
+domain boundary (central differences are exact for quadratics); and on a
+uniform tree the oracle's per-box face array equals differences of the
+assembled global grid (the box layout, its ghosts and the (u, v) face
+indexing, checked against numpy.diff).
+
+GPU parity: the library's mg_efield against the oracle on the same phi,
+within 1e-12 of the largest |E| (the two differ in FMA contraction of the
+refinement-boundary ghosts and in multiplying by 1/h where the oracle
+divides by h)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import streamer_small, uniform_boxes, refine_boxes_explicit
+from workloads.configs import Workload, rhs_zero
+from tests import _geom as G
+
+AMR = [(2, 0, 0, 0), (3, 1, 1, 1), (3, 0, 1, 0), (4, 2, 2, 2)]
+
+
+def oracle_with(bl, fn=None, bc_type=(0,) * 6):
+    o = O.OracleTree(bl.level, bl.ijk, bl.tree, (0.0, 0.0, 0.0), 1.0, bc_type, (0.0,) * 6)
+    lv, ij = o.index(O.IDX_LEVEL), o.index(O.IDX_IJK)
+    if fn is not None:
+        o.set_bcval(G.face_values(lv, ij, fn))
+    return o, lv, ij
+
+
+def test_linear_potential_gives_the_exact_field_on_an_amr_tree():
+    a, b, c, d = 0.7, -1.3, 2.1, 0.4
+    fn = lambda x, y, z: a * x + b * y + c * z + d
+    bl = refine_boxes_explicit(2, AMR)
+    o, lv, ij = oracle_with(bl, fn)
+    x, y, z, h = G.cell_centres(lv, ij)
+    o.set_field(O.PHI, fn(x, y, z))
+    face, norm = o.efield()
+    for ax, want in enumerate((-a, -b, -c)):
+        err = np.abs(face[:, ax] - want).max()
+        assert err < 1e-11, (ax, err)
+    assert np.abs(norm - np.sqrt(a * a + b * b + c * c)).max() < 1e-11
+
+
+def test_quadratic_potential_exact_away_from_the_domain_boundary():
+    fn = lambda x, y, z: x * x + 2 * y * y - z * z + x * y
+    bl = uniform_boxes(3)
+    o, lv, ij = oracle_with(bl, fn)
+    x, y, z, h = G.cell_centres(lv, ij)
+    o.set_field(O.PHI, fn(x, y, z))
+    face, _ = o.efield()
+    n = len(lv)
+    hh = h[:, None, None, None]
+    f = np.arange(9)[None, :, None, None]
+    u = np.arange(8)[None, None, None, :]
+    v = np.arange(8)[None, None, :, None]
+    B = ij.astype(float)
+    checked = 0
+    for ax in range(3):
+        t1, t2 = (1, 2) if ax == 0 else (0, 2) if ax == 1 else (0, 1)
+        pos = [None, None, None]
+        pos[ax] = (8 * B[:, ax, None, None, None] + f) * hh                    # face coordinate
+        pos[t1] = (8 * B[:, t1, None, None, None] + u + 0.5) * hh
+        pos[t2] = (8 * B[:, t2, None, None, None] + v + 0.5) * hh
+        px, py, pz = (np.broadcast_to(p, (n, 9, 8, 8)) for p in pos)
+        grad = [2 * px + py, 4 * py + px, -2 * pz][ax]
+        inside = (pos[ax] > 1e-12) & (pos[ax] < 1 - 1e-12)
+        inside = np.broadcast_to(inside, (n, 9, 8, 8))
+        err = np.abs(face[:, ax] + grad)[inside].max()
+        assert err < 1e-11, (ax, err)
+        checked += int(inside.sum())
+    assert checked > 3 * 60 * 64 * 6
+
+
+def test_faces_equal_differences_of_the_global_grid():
+    """Uniform level 3 (32^3 cells): assemble phi into one global array and
+    difference it with numpy; every face the boxes share, and every cell
+    strength away from the domain boundary, must agree with the oracle's
+    per-box arrays (this pins the face layout and the (u, v) indexing)."""
+    rng = np.random.default_rng(4)
+    bl = uniform_boxes(3)
+    o, lv, ij = oracle_with(bl, None)
+    phi = rng.standard_normal((len(lv), 8, 8, 8))
+    top = lv == 3
+    o.set_field(O.PHI, phi)
+    face, norm = o.efield()
+    N, h = 32, 1.0 / 32
+    glob = np.zeros((N, N, N))          # [z][y][x]
+    for b in np.nonzero(top)[0]:
+        i, j, k = ij[b]
+        glob[8 * k:8 * k + 8, 8 * j:8 * j + 8, 8 * i:8 * i + 8] = phi[b]
+    ex = -(np.diff(glob, axis=2)) / h   # face between x-cells X and X+1: [z][y][X]
+    ey = -(np.diff(glob, axis=1)) / h
+    ez = -(np.diff(glob, axis=0)) / h
+    for b in np.nonzero(top)[0]:
+        i, j, k = ij[b]
+        for f in range(9):
+            X = 8 * i + f - 1           # face between global cells X and X+1
+            if 0 <= X < N - 1:
+                np.testing.assert_allclose(face[b, 0, f], ex[8 * k:8 * k + 8, 8 * j:8 * j + 8, X],
+                                           rtol=0, atol=1e-12)
+            Y = 8 * j + f - 1
+            if 0 <= Y < N - 1:          # y-faces: u along x, v along z
+                np.testing.assert_allclose(face[b, 1, f], ey[8 * k:8 * k + 8, Y, 8 * i:8 * i + 8],
+                                           rtol=0, atol=1e-12)
+            Z = 8 * k + f - 1
+            if 0 <= Z < N - 1:          # z-faces: u along x, v along y
+                np.testing.assert_allclose(face[b, 2, f], ez[Z, 8 * j:8 * j + 8, 8 * i:8 * i + 8],
+                                           rtol=0, atol=1e-12)
+    cx = (ex[1:-1, 1:-1, :-1] + ex[1:-1, 1:-1, 1:]) / 2.0
+    cy = (ey[1:-1, :-1, 1:-1] + ey[1:-1, 1:, 1:-1]) / 2.0
+    cz = (ez[:-1, 1:-1, 1:-1] + ez[1:, 1:-1, 1:-1]) / 2.0
+    want = np.sqrt(cx * cx + cy * cy + cz * cz)   # interior cells [1, N-2]^3
+    got = np.zeros((N, N, N))
+    for b in np.nonzero(top)[0]:
+        i, j, k = ij[b]
+        got[8 * k:8 * k + 8, 8 * j:8 * j + 8, 8 * i:8 * i + 8] = norm[b]
+    np.testing.assert_allclose(got[1:-1, 1:-1, 1:-1], want, rtol=1e-13, atol=1e-13)
+
+
+def test_efield_resets_covered_cells_first():
+    """Covered cells take the mean of their children before the field is
+    formed, so a covered box's field is that of the restricted potential."""
+    bl = uniform_boxes(2)
+    o, lv, ij = oracle_with(bl, None)
+    rng = np.random.default_rng(8)
+    phi = rng.standard_normal((len(lv), 8, 8, 8))
+    o.set_field(O.PHI, phi)
+    o.efield()
+    got = o.get_field(O.PHI)
+    root = np.nonzero(lv == 1)[0][0]
+    kids = np.nonzero(lv == 2)[0]
+    mean = np.zeros((8, 8, 8))
+    for b in kids:
+        i, j, k = ij[b]
+        c = phi[b].reshape(4, 2, 4, 2, 4, 2).mean(axis=(1, 3, 5))
+        mean[4 * k:4 * k + 4, 4 * j:4 * j + 4, 4 * i:4 * i + 4] = c
+    np.testing.assert_allclose(got[root], mean, rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------------- GPU
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("tree", ["streamer_small", "bcval"])
+def test_gpu_efield_matches_the_oracle(tree):
+    from paper_1708_08434_amd import mg as M
+    rng = np.random.default_rng(12)
+    if tree == "bcval":
+        bl = refine_boxes_explicit(2, AMR)
+        w = Workload("amr_bcval", bl, rhs_zero, bc_type=(0, 0, 1, 0, 0, 0))
+        g = M.Tree.from_workload(w, per_cell_bc=True)
+        o = O.OracleTree.from_workload(w)
+        lv, ij = o.index(O.IDX_LEVEL), o.index(O.IDX_IJK)
+        bc = G.face_values(lv, ij, lambda x, y, z: np.sin(3 * x) + y * z)
+        g.set_field(M.MG_FIELD_BCVAL, bc)
+        o.set_bcval(bc)
+        phi = rng.standard_normal((g.n, 8, 8, 8))
+    else:
+        w = streamer_small()
+        g = M.Tree.from_workload(w)
+        o = O.OracleTree.from_workload(w)
+        g.set_rhs_from(w)
+        g.fmg_solve()
+        phi = g.get_field(M.MG_FIELD_PHI)
+    assert np.array_equal(g.index(M.MG_IDX_ORDER), o.index(O.IDX_ORDER))
+    g.set_field(M.MG_FIELD_PHI, phi)
+    o.set_field(O.PHI, phi)
+    fg, ng = g.efield()
+    fo, no = o.efield()
+    print("efield", tree, g.n, "boxes, max |E|", np.abs(fo).max(), flush=True)
+    scale = np.abs(fo).max()
+    assert np.abs(fg - fo).max() <= 1e-12 * scale
+    assert np.abs(ng - no).max() <= 1e-12 * scale
+    # the covered cells were reset on both sides
+    assert np.abs(g.get_field(M.MG_FIELD_PHI) - o.get_field(O.PHI)).max() <= 1e-13 * np.abs(phi).max()

@@ -259,6 +259,27 @@ def c2(seed=2, refinements=4, target=5.0e6, amp_head=1e4, radius=0.02, delta=2e-
                               radius=radius, delta=delta, target=target))
 
 
+def c2_head_sequence(level, ijk, steps, dz, amp_head=1e4, radius=0.02, delta=2e-3, z_head=0.62):
+    """Right-hand sides b = -rho of the C2 streamer on the unchanged C2 tree
+    with its head centre moved down by s * dz, s = 0 .. steps-1 (the slow
+    change of the charge between field solves of a time-stepped run), each
+    neutralised on the C2 tree's leaf cells.  Returns [steps, n, 8, 8, 8] for
+    the given boxes."""
+    bl = c2().boxes
+    level = np.asarray(level).reshape(-1)
+    ijk = np.asarray(ijk).reshape(-1, 3)
+    out = np.zeros((steps, len(level), 8, 8, 8))
+    for s in range(steps):
+        ch = _Channels([((0.5, 0.5, 1.0), (0.5, 0.5, z_head - s * dz))], radius, delta, amp_head)
+        ch.neutralise(bl, (0.0, 0.0, 0.0), 1.0)
+
+        def fn(lv, ij, ch=ch):
+            x, y, z, *_ = charges.cell_centres(lv, ij, (0.0, 0.0, 0.0), 1.0)
+            return -ch.rho(x, y, z)
+        out[s] = Workload("c2_head_step", bl, fn).rhs(level, ijk)
+    return out
+
+
 def streamer_small(refinements=2, target=3.0e5, use_cache=True):
     """A reduced C2-shaped tree (base 32^3 + ``refinements`` levels) small enough
     for the CPU oracle to solve in a second or two."""
