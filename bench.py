@@ -259,10 +259,11 @@ def main():
                          "0 skips it (benchmark streamer only)")
     ap.add_argument("--copy-probe", type=int, default=0, help="bytes of a calibration copy")
     ap.add_argument("--workload", default="streamer",
-                    choices=["streamer", "forest", "branched", "two_streamers"],
+                    choices=["streamer", "forest", "branched", "two_streamers", "paper_setup"],
                     help="streamer: base 64^3 + 4 levels, 4.8e6 cells (default); forest: 128 "
                          "uneven trees, 7.1e7 cells; branched: base 64^3 + 6 levels, 2.9e7 "
-                         "cells; two_streamers: base 64^3 + 7 levels, ~1e8 cells")
+                         "cells; two_streamers: base 64^3 + 7 levels, ~1e8 cells; paper_setup: "
+                         "the streamer tree in the paper's SI setup (40 mm, 80 kV, Neumann sides)")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
@@ -271,11 +272,12 @@ def main():
 
     import torch
     from paper_1708_08434_amd import mg as M
-    from workloads import c2, c3, c5, forest
+    from workloads import c2, c3, c5, forest, paper_setup
 
     from paper_1708_08434_amd import autotune
 
-    w = {"streamer": c2, "forest": forest, "branched": c3, "two_streamers": c5}[args.workload]()
+    w = {"streamer": c2, "forest": forest, "branched": c3, "two_streamers": c5,
+         "paper_setup": paper_setup}[args.workload]()
     g = M.Tree.from_workload(w, device="cuda:0")
     g.set_rhs_from(w)
     torch.cuda.synchronize()
@@ -357,7 +359,9 @@ def main():
                        "forest": " forest of 128 uneven streamer trees (base 32^3 + <=5 levels)",
                        "branched": " branched streamer octree (base 64^3 + 6 refinement levels)",
                        "two_streamers": " two streamers + Poisson background (base 64^3 + 7 "
-                                        "refinement levels)"}[args.workload],
+                                        "refinement levels)",
+                       "paper_setup": " streamer octree in SI units: (40 mm)^3, 80 kV top, "
+                                      "grounded bottom, Neumann sides"}[args.workload],
                    "n_trees": int(g.info.n_trees),
                    "n_leaf": n_leaf, "n_boxes": g.n, "levels": g.nlev, "rel_tol": 1e-8,
                    "vcycles_after_fmg": k, "final_rel_res": stats["rel"], "precision": "fp64",
@@ -391,6 +395,13 @@ def main():
         out["learned"] = learned
     if time_step is not None:
         out["time_step"] = time_step
+    if args.workload == "paper_setup":
+        g.fmg_solve()
+        _, en = g.efield()
+        leaf = g.leaf_mask()
+        out["field"] = {"background_V_per_m": w.meta["e0"], "max_E_V_per_m": float(en[leaf].max()),
+                        "max_E_over_background": float(en[leaf].max() / w.meta["e0"]),
+                        "n_head_per_m3": w.meta["n_head"]}
     if rank == 0 and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, k)
     if rank == 0:

@@ -280,6 +280,32 @@ def c2_head_sequence(level, ijk, steps, dz, amp_head=1e4, radius=0.02, delta=2e-
     return out
 
 
+E_CHARGE = 1.602176634e-19   # C
+EPS0 = 8.8541878128e-12      # F/m
+
+
+def paper_setup(n_head=1e19, length=0.04, volts=80e3):
+    """The paper's field configuration in SI units (section 3.1): a (40 mm)^3
+    domain with the base grid at 625 um (level 4 = 64^3), the bottom face
+    grounded, 80 kV on the top face (a 2 MV/m background field along -z) and
+    Neumann-zero sides.  The tree and the streamer are the C2 ones scaled to
+    the domain; the charge density is e times a net ion-minus-electron density
+    whose head layer peaks at n_head per m^3 (the channel sides neutralise
+    it; 1e19 puts the head field near 10x the background, about what positive
+    streamers reach in nitrogen at 1 bar), and the right-hand side is
+    b = -rho / eps0 in V/m^2."""
+    w = c2()
+    scale = E_CHARGE * n_head / w.meta["amp_head"] / EPS0
+    base_fn = w._rhs_fn
+
+    def fn(level, ijk):
+        return scale * base_fn(level, ijk)
+    meta = dict(w.meta, n_head=n_head, length=length, volts=volts, e0=volts / length)
+    return Workload("paper_setup_40mm", w.boxes, fn, length=length,
+                    bc_type=(NEUMANN, NEUMANN, NEUMANN, NEUMANN, DIRICHLET, DIRICHLET),
+                    bc_val=(0.0, 0.0, 0.0, 0.0, 0.0, volts), meta=meta)
+
+
 def streamer_small(refinements=2, target=3.0e5, use_cache=True):
     """A reduced C2-shaped tree (base 32^3 + ``refinements`` levels) small enough
     for the CPU oracle to solve in a second or two."""
