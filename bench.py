@@ -42,6 +42,18 @@ def model_bytes(level_counts, n_leaf, k):
     return fmg + k * BETA_FP64 * cum[-1] + (k + 1) * NORM_BYTES * n_leaf
 
 
+def gsrb_kernel_name(v):
+    """The Gauss-Seidel kernel of launch variant v (include/mg.h)."""
+    if v < 6:
+        return f"k_gsrb<C,double,{(1, 2, 4)[v >> 1]}> (red-black Gauss-Seidel half-sweep)"
+    if v < 8:
+        return "k_gsrb_sweep<double> (fused red-black Gauss-Seidel sweep)"
+    if v < 10:
+        return "k_gsrb_oct<C,double> (red-black Gauss-Seidel half-sweep over sibling octets)"
+    return (f"k_gsrb_pipe<C,double> (red-black Gauss-Seidel half-sweep, at most "
+            f"{2048 if v < 12 else 4096} persistent workgroups)")
+
+
 def traffic_per_launch(variant):
     """HBM bytes per launch of the finest-level Gauss-Seidel kernel from the
     committed rocprofv3 counter summary, or None if the kernel source changed
@@ -368,10 +380,7 @@ def main():
                    "smoothing": "V(2,2) red-black Gauss-Seidel",
                    "gsrb_schedule": {"fp64": sched64, "fp32": sched32}},
         "roofline": {"bound": "hbm",
-                     "kernel": (f"k_gsrb_sweep<double> (fused red-black Gauss-Seidel sweep)"
-                                if sched64[fin] >= 6 else
-                                f"k_gsrb<C,double,{(1, 2, 4)[sched64[fin] >> 1]}> (red-black "
-                                f"Gauss-Seidel half-sweep)")
+                     "kernel": gsrb_kernel_name(sched64[fin])
                                + f", level {fin + 1} ({counts[fin]} boxes, the most bytes), "
                                  f"schedule variant {sched64[fin]}",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
