@@ -257,6 +257,84 @@ def time_step_leg(g, args):
                        "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS}}
 
 
+def regrid_leg(w, args, sched64):
+    """Mesh adaptation as the streamer moves (paper section 2.5).  The
+    benchmark tree is refined geometrically around the channel, more finely
+    than its charge asks for, so it is first adapted to the charge (an
+    untimed regrid step with c3 = 1e-3 of the largest refinement score: every
+    cell whose |b| h^2 exceeds 0.1% of the peak is refined).  Then the head
+    moves down 2.5e-4 (10 um of the paper's 40 mm domain, a quarter of a
+    finest cell) per field solve, each field solve runs two warm-started
+    V-cycles, and every 4th solve is preceded by a timed regrid step: GPU
+    refinement scores, the host plan, the new tree (create + bind, with the
+    benchmark tree's autotuned schedule) and the transfer of phi
+    (mg_transfer).  The charge of each mesh is generated on the host and is
+    not timed."""
+    import torch
+    from paper_1708_08434_amd import mg as M
+    from workloads import c2_head_sequence
+    dz, every, z0, deref = 2.5e-4, 4, 0.62, 0.125
+
+    def tree(lv, ij, tr):
+        t = M.Tree(lv, ij, tr, w.lo, w.length, w.bc_type, w.bc_val, device="cuda:0")
+        if int(t.nlev) == len(sched64):
+            M.mg_set_schedule(t.h, M.MG_FP64, sched64)
+        return t
+
+    def charge(t, s):
+        lv, ij = t.index(M.MG_IDX_LEVEL), t.index(M.MG_IDX_IJK)
+        t.set_field(M.MG_FIELD_RHS, c2_head_sequence(lv, ij, 1, dz, z_head=z0 - s * dz)[0])
+
+    g0 = M.Tree.from_workload(w, device="cuda:0")
+    charge(g0, 0)
+    sc = g0.refine_scores()
+    c3, max_level = 1e-3 * float(sc.max()), g0.nlev
+    g = tree(*M.mg_regrid_plan(g0.h, sc, c3, deref, max_level))
+    bench_boxes, adapted_boxes = g0.n, g.n
+    del g0
+    charge(g, 0)
+    g.fmg_solve()
+    opts = g.opts()
+    regrids, vtimes, rel_after = [], [], []
+    for s in range(1, args.regrid_steps + 1):
+        fresh = s % every == 0
+        if fresh:
+            charge(g, s)  # the current charge on the current mesh
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sc = g.refine_scores()
+            t1 = time.perf_counter()
+            plan = M.mg_regrid_plan(g.h, sc, c3, deref, max_level)
+            t2 = time.perf_counter()
+            g2 = tree(*plan)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            M.mg_transfer(g.h, g2.h)
+            t4 = time.perf_counter()
+            regrids.append({"solve": s, "boxes_before": g.n, "boxes_after": g2.n,
+                            "leaf_cells_after": int(g2.info.n_leaf_cells),
+                            "ms": {"scores": 1e3 * (t1 - t0), "plan": 1e3 * (t2 - t1),
+                                   "create_bind": 1e3 * (t3 - t2), "transfer": 1e3 * (t4 - t3),
+                                   "total": 1e3 * (t4 - t0)}})
+            del g
+            g = g2
+        charge(g, s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = M.mg_vcycle(g.h, opts, 2)
+        torch.cuda.synchronize()
+        vtimes.append((1e3 * (time.perf_counter() - t0), fresh))
+        rel_after.append(st.rel_res)
+    steady = [t for t, fresh in vtimes if not fresh]
+    return {"c3": c3, "deref_factor": deref, "boxes_benchmark_tree": bench_boxes,
+            "boxes_adapted": adapted_boxes, "head_shift_per_solve": dz, "regrid_every": every,
+            "field_solves": len(vtimes), "regrids": regrids,
+            "ms_regrid_median": statistics.median(r["ms"]["total"] for r in regrids) if regrids else None,
+            "ms_2_vcycles_median": statistics.median(steady) if steady else None,
+            "ms_2_vcycles_first_on_new_tree": [t for t, fresh in vtimes if fresh],
+            "rel_res_after_2_vcycles_max": max(rel_after)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +344,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction leg")
     ap.add_argument("--train-steps", type=int, default=300, help="Adam steps of the learned leg")
+    ap.add_argument("--regrid-steps", type=int, default=8,
+                    help="field solves of the regrid leg (a regrid every 4th); 0 skips it "
+                         "(benchmark streamer only)")
     ap.add_argument("--ts-steps", type=int, default=8,
                     help="time steps (2 warm-started field solves each) of the time-stepping leg; "
                          "0 skips it (benchmark streamer only)")
@@ -351,6 +432,9 @@ def main():
     time_step = None
     if args.ts_steps > 0 and args.workload == "streamer":
         time_step = time_step_leg(g, args)
+    regrid = None
+    if args.regrid_steps > 0 and args.workload == "streamer":
+        regrid = regrid_leg(w, args, sched64)
     copy = copy_bandwidth()
     mb = model_bytes(counts, n_leaf, k)
     # the level whose half-sweeps move the most bytes (the finest level of a
@@ -404,6 +488,8 @@ def main():
         out["learned"] = learned
     if time_step is not None:
         out["time_step"] = time_step
+    if regrid is not None:
+        out["regrid"] = regrid
     if args.workload == "paper_setup":
         g.fmg_solve()
         _, en = g.efield()

@@ -214,6 +214,41 @@ int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *
  */
 int mg_efield(mg_tree *t, double *e_face, double *e_norm);
 
+/*
+ * Mesh adaptation (section 2.5), one step at a time, as the charge moves:
+ *   1. mg_refine_scores: per box, 27 refinement scores of the right-hand
+ *      side on the GPU: scores[b*27 + r] = max |b| h^2 over the box's cells in
+ *      region r = (sx+1) + 3(sy+1) + 9(sz+1), where along each axis s = -1
+ *      takes cells 0..2, s = +1 cells 5..7 and s = 0 all cells (r = 13: the
+ *      whole box; the others: the cells within 3 of a face, edge or corner).
+ *      Only leaf boxes' scores are meaningful (the solver overwrites b on
+ *      covered boxes).  scores: device, n*27 doubles.  Asynchronous.
+ *   2. mg_regrid_plan (host): the new box list.  A leaf box below max_level
+ *      is refined when |b| h^2 > c3 at one of its cells or at a cell of a
+ *      same-level leaf neighbour within 3 cells (the paper's space-charge
+ *      criterion h > sqrt(c3 eps0 / |rho|) with its 3-cell buffer).  The 8
+ *      children of a box are removed when they are leaves, none is refined,
+ *      no cell of theirs or of a same-level leaf neighbour within 3 cells
+ *      exceeds deref*c3, and no box two levels finer would touch the parent.
+ *      Then 2:1 nesting over 26 neighbours is restored by refining coarse
+ *      leaves.  scores: host copy of step 1.  Writes n_out boxes (level,
+ *      ijk[3], tree; any order) if n_out <= cap, else MG_ENOMEM with n_out set.
+ *   3. mg_tree_create + mg_tree_bind on the list, then mg_transfer.
+ * mg_transfer: phi of `to` from `from` (same domain and trees): covered cells
+ * of `from` are first reset to the mean of their children; boxes present in
+ * both (same tree, level, position) are copied; the others, level by level,
+ * are interpolated from their parent in `to` by the prolongation stencil
+ * 1/4 p(C) + 1/4 (p(C+s_x) + p(C+s_y) + p(C+s_z)) on phi (exact for linear
+ * potentials), with the parent's ghosts outside it.  Runs on to's stream and
+ * synchronises it; `from` must not be in use meanwhile.  to's right-hand side
+ * is the caller's (set it from the new boxes).  MG_EINVAL if a tree of `to`
+ * has no root in `from` or the domains differ.
+ */
+int mg_refine_scores(mg_tree *t, double *scores);
+int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, int max_level,
+                   int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree, int64_t *n_out);
+int mg_transfer(mg_tree *from, mg_tree *to);
+
 /* Relative residual, L2 and max norms of the current phi (leaf cells). */
 int mg_residual(mg_tree *t, double *rel, double *l2, double *linf);
 

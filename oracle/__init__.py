@@ -60,6 +60,7 @@ def lib():
         L.oracle_set_threads.argtypes = [I32]
         L.oracle_tree_rel.argtypes = [P, P]
         L.oracle_efield.argtypes = [P, P, P]
+        L.oracle_transfer.argtypes = [P, P]
         L.oracle_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -175,6 +176,11 @@ class OracleTree:
         y = np.zeros_like(x)
         _check(lib().oracle_apply(self.h, _ptr(x), _ptr(y), int(homog)))
         return y
+
+    def transfer_from(self, other):
+        """phi of this tree from another over the same domain (regrid step):
+        common boxes copied, new boxes interpolated from their parents."""
+        _check(lib().oracle_transfer(other.h, self.h))
 
     def efield(self):
         """Electric field of the current phi (covered cells reset to the mean

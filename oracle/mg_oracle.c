@@ -770,6 +770,56 @@ int oracle_efield(otree *t, double *e_face, double *e_norm) {
     return t->bad_lookup ? ORC_ESTATE : ORC_OK;
 }
 
+/* ------------------------------------------------------- mesh adaptation */
+
+/* Potential of tree `to` from tree `from` over the same domain (a regrid
+   step, paper section 2.5).  Covered cells of `from` are first reset to the
+   mean of their children.  A box of `to` that `from` also has (same tree,
+   level and position) takes its values.  The others, from the coarsest level
+   up, are interpolated from their parent in `to`, filled before them: a fine
+   cell gets 1/4 of its parent cell plus 1/4 of each of the parent cell's three
+   neighbours on the fine cell's side (the stencil of the correction
+   prolongation, applied to phi; exact for linear functions), with the
+   parent's ghost layer standing in for cells outside the parent. */
+int oracle_transfer(otree *from, otree *to) {
+    from->bad_lookup = to->bad_lookup = 0;
+    restrict_all(from);
+    char *have = (char *)calloc((size_t)to->n, 1);
+    if (!have) return ORC_ENOMEM;
+    for (int64_t b = 0; b < to->n; b++) {
+        int32_t o = find(from, to->tid[b], to->lev[b], to->bx[b], to->by[b], to->bz[b]);
+        if (o < 0) {
+            if (to->lev[b] == 1) { free(have); set_err("transfer: a tree has no counterpart"); return ORC_EINVAL; }
+            continue;
+        }
+        have[b] = 1;
+        for (int k = 0; k < 8; k++)
+            for (int j = 0; j < 8; j++)
+                for (int i = 0; i < 8; i++)
+                    to->f[F_PHI][b * BOX + AT(i, j, k)] = from->f[F_PHI][(int64_t)o * BOX + AT(i, j, k)];
+    }
+    for (int l = 2; l <= to->nlev; l++) {
+        fill_ghosts(to, l - 1, to->f[F_PHI], 0);
+        for (int64_t b = to->lstart[l]; b < to->lstart[l + 1]; b++) {
+            if (have[b]) continue;
+            const double *pb = to->f[F_PHI] + (int64_t)to->parent[b] * BOX;
+            int ox = to->bx[b] & 1, oy = to->by[b] & 1, oz = to->bz[b] & 1;
+            for (int k = 0; k < 8; k++)
+                for (int j = 0; j < 8; j++)
+                    for (int i = 0; i < 8; i++) {
+                        int cx = 4 * ox + i / 2, cy = 4 * oy + j / 2, cz = 4 * oz + k / 2;
+                        int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+                        double c = pb[AT(cx, cy, cz)];
+                        double nx = pb[AT(cx + sx, cy, cz)], ny = pb[AT(cx, cy + sy, cz)],
+                               nz = pb[AT(cx, cy, cz + sz)];
+                        to->f[F_PHI][b * BOX + AT(i, j, k)] = 0.25 * c + 0.25 * (nx + ny + nz);
+                    }
+        }
+    }
+    free(have);
+    return to->bad_lookup ? ORC_ESTATE : ORC_OK;
+}
+
 /* per-tree norm of the residual of phi = 0 (the right-hand side with the
    boundary data folded in) */
 static void beff_norm(otree *t, double *beff) {

@@ -85,6 +85,13 @@ template <typename T>
 void launch_leaf_apply(const Geo &g, const T *x, const T *chat, const int32_t *leaf, int64_t nleaf,
                        T *out, hipStream_t s);
 void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s);
+// Mesh adaptation: per-box refinement scores (27 region maxima of |b| h^2),
+// and the transfer of phi to a new tree (copy of boxes present in both, then
+// level by level the interpolation of new boxes from their parents).
+void launch_refine_scores(const Geo &g, const double *rhs, int64_t n, double *scores, hipStream_t s);
+void launch_transfer_copy(const double *from, double *to, const int32_t *src, int64_t n, hipStream_t s);
+void launch_transfer_interp(const Geo &g, double *phi, const double *chat, const int32_t *list, int64_t nlist,
+                            hipStream_t s);
 // Electric field of phi on all n boxes (face components and cell strength).
 void launch_efield(const Geo &g, const double *phi, const double *chat, int64_t n, double *e_face,
                    double *e_norm, hipStream_t s);

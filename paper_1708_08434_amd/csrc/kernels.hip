@@ -1198,6 +1198,100 @@ __global__ __launch_bounds__(256) void k_efield(Geo g, const double *__restrict_
     }
 }
 
+// Refinement scores (section 2.5, the space-charge criterion |b| h^2 > c3):
+// for box b, scores[b*27 + r] = the largest |b| h^2 over its cells in region
+// r = (sx+1) + 3 (sy+1) + 9 (sz+1), where along each axis s = -1 takes cells
+// 0..2, s = +1 cells 5..7 and s = 0 all cells (so r = 13 is the whole box
+// and the 26 others the cells within 3 of each face, edge and corner).
+__global__ __launch_bounds__(256) void k_refine_scores(Geo g, const double *__restrict__ rhs, int64_t n,
+                                                       double *__restrict__ scores) {
+    __shared__ double W[4][27];
+    int64_t b = xcd_map(blockIdx.x, n);
+    if (b >= n) return;
+    int t = threadIdx.x;
+    int l = g.ijk[b * 4 + 3];
+    double h = g.len / (8.0 * (double)(1 << (l - 1)));
+    double m[27];
+#pragma unroll
+    for (int r = 0; r < 27; r++) m[r] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        int q = c * 256 + t, mm = q & 3, j = (q >> 2) & 7, k = (q >> 5) & 7;
+        int i = 2 * mm + ((j + k + c) & 1);
+        double v = fabs(rhs[b * 512 + q]) * (h * h);
+        bool lo[3] = {i <= 2, j <= 2, k <= 2}, hi[3] = {i >= 5, j >= 5, k >= 5};
+#pragma unroll
+        for (int r = 0; r < 27; r++) {
+            int sx = r % 3 - 1, sy = (r / 3) % 3 - 1, sz = r / 9 - 1;
+            bool in = (sx == 0 || (sx < 0 ? lo[0] : hi[0])) && (sy == 0 || (sy < 0 ? lo[1] : hi[1])) &&
+                      (sz == 0 || (sz < 0 ? lo[2] : hi[2]));
+            if (in) m[r] = fmax(m[r], v);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 27; r++) {
+        double v = m[r];
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+        if ((t & 63) == 0) W[t >> 6][r] = v;
+    }
+    __syncthreads();
+    if (t < 27) scores[b * 27 + t] = fmax(fmax(W[0][t], W[1][t]), fmax(W[2][t], W[3][t]));
+}
+
+// Transfer of phi to a new tree.  Copy: new box b takes the old box src[b]
+// (same level and position) when src[b] >= 0.
+__global__ __launch_bounds__(256) void k_transfer_copy(const double *__restrict__ from, double *__restrict__ to,
+                                                       const int32_t *__restrict__ src, int64_t n) {
+    int64_t b = xcd_map(blockIdx.x, n);
+    if (b >= n) return;
+    int64_t o = src[b];
+    if (o < 0) return;
+    int t = threadIdx.x;
+    to[b * 512 + t] = from[o * 512 + t];
+    to[b * 512 + 256 + t] = from[o * 512 + 256 + t];
+}
+
+// Interpolation: new box list[q] (level l, no counterpart in the old tree)
+// from its parent in the new tree (already filled), with the stencil of the
+// correction prolongation applied to phi itself, 1/4 p(C) + 1/4 (p(C + s_x) +
+// p(C + s_y) + p(C + s_z)), C the parent cell and s the side of the fine cell
+// in it; a neighbour outside the parent is the parent's ghost on that face
+// (same-level neighbour, boundary condition or refinement-boundary value).
+// Exact for linear functions.
+__global__ __launch_bounds__(256) void k_transfer_interp(Geo g, double *__restrict__ phi,
+                                                         const double *__restrict__ chat,
+                                                         const int32_t *__restrict__ list, int64_t nlist) {
+    __shared__ double P[512], H[384];
+    int64_t q = xcd_map(blockIdx.x, nlist);
+    if (q >= nlist) return;
+    int64_t b = list[q];
+    int64_t p = g.parent[b];
+    int o[3] = {g.ijk[b * 4] & 1, g.ijk[b * 4 + 1] & 1, g.ijk[b * 4 + 2] & 1};
+    int t = threadIdx.x;
+    stage_full<double>(g, phi, chat, p, P, H);
+    __syncthreads();
+    // parent value at (x, y, z); at most one coordinate is -1 or 8 (a face ghost)
+    auto pv = [&](int x, int y, int z) __attribute__((always_inline)) -> double {
+        if (x < 0) return H[0 * 64 + z * 8 + y];
+        if (x > 7) return H[1 * 64 + z * 8 + y];
+        if (y < 0) return H[2 * 64 + z * 8 + x];
+        if (y > 7) return H[3 * 64 + z * 8 + x];
+        if (z < 0) return H[4 * 64 + y * 8 + x];
+        if (z > 7) return H[5 * 64 + y * 8 + x];
+        return P[cs_idx(x, y, z)];
+    };
+    int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        int i = 2 * m + ((j + k + c) & 1);
+        int cx = 4 * o[0] + (i >> 1), cy = 4 * o[1] + (j >> 1), cz = 4 * o[2] + (k >> 1);
+        int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+        double d0 = pv(cx, cy, cz), dx = pv(cx + sx, cy, cz), dy = pv(cx, cy + sy, cz),
+               dz = pv(cx, cy, cz + sz);
+        phi[b * 512 + c * 256 + t] = 0.25 * d0 + 0.25 * (dx + dy + dz);
+    }
+}
+
 // phi (FP64) += e (FP32) on every cell: the update of the mixed-precision
 // iterative refinement.
 __global__ __launch_bounds__(256) void k_ir_update(double *__restrict__ phi, const float *__restrict__ e,
@@ -1409,6 +1503,20 @@ void launch_efield(const Geo &g, const double *phi, const double *chat, int64_t 
                    double *e_norm, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_efield, dim3((unsigned)xcd_grid(n)), dim3(256), 0, s, g, phi, chat, n, e_face, e_norm);
+}
+void launch_refine_scores(const Geo &g, const double *rhs, int64_t n, double *scores, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_refine_scores, dim3((unsigned)xcd_grid(n)), dim3(256), 0, s, g, rhs, n, scores);
+}
+void launch_transfer_copy(const double *from, double *to, const int32_t *src, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_transfer_copy, dim3((unsigned)xcd_grid(n)), dim3(256), 0, s, from, to, src, n);
+}
+void launch_transfer_interp(const Geo &g, double *phi, const double *chat, const int32_t *list, int64_t nlist,
+                            hipStream_t s) {
+    if (nlist <= 0) return;
+    hipLaunchKernelGGL(k_transfer_interp, dim3((unsigned)xcd_grid(nlist)), dim3(256), 0, s, g, phi, chat, list,
+                       nlist);
 }
 void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s) {
     if (count <= 0) return;

@@ -8,10 +8,12 @@
 // the pair of reduced residual norms used by the stopping test.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <unordered_map>
 #include <new>
 #include <string>
 
@@ -995,6 +997,114 @@ int mg_efield(mg_tree *t, double *e_face, double *e_norm) {
     ensure_cf_all(t, F);
     launch_efield(F.g, F.phi, F.chat, t->n, e_face, e_norm, stream_of(t));
     return hip_check(hipGetLastError(), "efield launch");
+}
+
+int mg_refine_scores(mg_tree *t, double *scores) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!scores) {
+        set_error("mg_refine_scores: null output");
+        return MG_EINVAL;
+    }
+    launch_refine_scores(geo(t, false), t->d.rhs, t->n, scores, stream_of(t));
+    return hip_check(hipGetLastError(), "refine scores launch");
+}
+
+int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, int max_level,
+                   int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree, int64_t *n_out) {
+    if (!t || !scores || !n_out || !(c3 > 0) || !(deref >= 0) || max_level < 1 || max_level > kMaxLevel ||
+        cap < 0 || (cap > 0 && (!level || !ijk || !tree))) {
+        set_error("mg_regrid_plan: invalid arguments");
+        return MG_EINVAL;
+    }
+    std::vector<int32_t> lv, ij, tr;
+    try {
+        regrid_plan(t, scores, c3, deref, max_level, lv, ij, tr);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return MG_ENOMEM;
+    }
+    *n_out = (int64_t)lv.size();
+    if ((int64_t)lv.size() > cap) {
+        set_error("mg_regrid_plan: output capacity too small (n_out holds the size needed)");
+        return MG_ENOMEM;
+    }
+    std::copy(lv.begin(), lv.end(), level);
+    std::copy(ij.begin(), ij.end(), ijk);
+    std::copy(tr.begin(), tr.end(), tree);
+    return MG_OK;
+}
+
+int mg_transfer(mg_tree *from, mg_tree *to) {
+    int rc = require_bound(from);
+    if (!rc) rc = require_bound(to);
+    if (rc) return rc;
+    if (from == to) {
+        set_error("mg_transfer: the two trees must differ");
+        return MG_EINVAL;
+    }
+    for (int a = 0; a < 3; a++)
+        if (from->dom.lo[a] != to->dom.lo[a]) rc = MG_EINVAL;
+    if (rc || from->dom.len != to->dom.len) {
+        set_error("mg_transfer: the trees cover different domains");
+        return MG_EINVAL;
+    }
+    auto key = [](const mg_tree *t, int64_t b) {
+        return ((uint64_t)t->tid[b] << 48) | ((uint64_t)t->lev[b] << 42) | ((uint64_t)t->ijk[3 * b] << 28) |
+               ((uint64_t)t->ijk[3 * b + 1] << 14) | (uint64_t)t->ijk[3 * b + 2];
+    };
+    // new box -> old box with the same level and position (or -1); the boxes
+    // without one, grouped by level, are interpolated from their parents
+    std::vector<int32_t> src((size_t)to->n), list;
+    std::vector<int64_t> lstart(to->nlev + 2, 0);
+    try {
+        std::unordered_map<uint64_t, int32_t> old;
+        old.reserve((size_t)from->n * 2);
+        for (int64_t b = 0; b < from->n; b++) old.emplace(key(from, b), (int32_t)b);
+        for (int64_t b = 0; b < to->n; b++) {
+            auto it = old.find(key(to, b));
+            src[b] = it == old.end() ? -1 : it->second;
+            if (src[b] < 0 && to->lev[b] == 1) {
+                set_error("mg_transfer: a tree of the new forest has no counterpart in the old one");
+                return MG_EINVAL;
+            }
+        }
+        for (int l = 2; l <= to->nlev; l++) {
+            lstart[l] = (int64_t)list.size();
+            for (int64_t b = lbeg(to, l); b < lbeg(to, l) + lcount(to, l); b++)
+                if (src[b] < 0) list.push_back((int32_t)b);
+        }
+        lstart[to->nlev + 1] = (int64_t)list.size();
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return MG_ENOMEM;
+    }
+    hipStream_t s = (hipStream_t)to->stream;
+    // the maps go to the new tree's sweep buffer (scratch between calls)
+    int32_t *d_src = (int32_t *)to->d.swp, *d_list = d_src + to->n;
+    rc = hip_check(hipMemcpyAsync(d_src, src.data(), src.size() * 4, hipMemcpyHostToDevice, s), "map upload");
+    if (!rc && !list.empty())
+        rc = hip_check(hipMemcpyAsync(d_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, s),
+                       "list upload");
+    if (rc) return rc;
+    // the old tree's covered cells <- mean of their children (on the new
+    // tree's stream: the old tree must not be in use elsewhere)
+    Fields<double> Fo = f64(from), Fn = f64(to);
+    for (int l = from->nlev; l >= 2; l--) launch_restrict_phi<double>(Fo.g, Fo.phi, lbeg(from, l), lcount(from, l), s);
+    dirty_all(Fo);
+    launch_transfer_copy(Fo.phi, Fn.phi, d_src, to->n, s);
+    for (int l = 2; l <= to->nlev; l++) {
+        int64_t nl = lstart[l + 1] - lstart[l];
+        if (nl <= 0) continue;
+        // c_hat of the parents' level (reads level l-2, filled)
+        launch_cf_coarse<double>(Fn.g, Fn.phi, Fn.chat, to->d.slots, to->sstart[l - 1],
+                                 to->sstart[l] - to->sstart[l - 1], s);
+        launch_transfer_interp(Fn.g, Fn.phi, Fn.chat, d_list + lstart[l], nl, s);
+    }
+    dirty_all(Fn);
+    rc = hip_check(hipGetLastError(), "transfer launch");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "stream synchronize");  // host maps freed on return
+    return rc;
 }
 
 int mg_residual(mg_tree *t, double *rel, double *l2, double *linf) {

@@ -63,6 +63,7 @@ struct mg_tree {
     std::vector<int32_t> refined, leaf;                 // box ids grouped by level
     int64_t rstart[mg::kMaxLevel + 2] = {0}, fstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> slots;                         // (box, face) per slot
+    std::vector<int32_t> n27;                           // [n][27] same-level box at ijk + o, -1, -2
     std::vector<int32_t> root2;                         // first level-2 box per tree, or -1
     bool bottom_ok = false;                             // levels 1-2 can run as one launch
     std::vector<int32_t> leaf_tree, tree_off;           // leaf positions grouped by tree
@@ -112,5 +113,9 @@ struct mg_tree {
 namespace mg {
 int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level,
                const int32_t *ijk, const int32_t *tree);
+// One regrid step (regrid.cpp): the new box list from per-box refinement
+// scores; see mg_regrid_plan in mg.h.
+int regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, int max_level,
+                std::vector<int32_t> &level, std::vector<int32_t> &ijk, std::vector<int32_t> &tree);
 void root_eigen(const int32_t bc_type[6], double *eig);
 }

@@ -202,7 +202,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
                     }
         }
     }
-    // face tables
+    // face tables (the 27-neighbourhood is kept for the regrid planner)
     static const int face_oi[6] = {12, 14, 10, 16, 4, 22};
     t->nbr.assign(6 * n, -2);
     t->cfq.assign(6 * n, -1);
@@ -315,6 +315,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->root2.assign(ntree, -1);
     for (int tr = 0; tr < ntree; tr++) t->root2[tr] = t->child[8 * (lbegin(1) + tr)];
     t->bottom_ok = t->nlev >= 2 && t->sstart[3] == t->sstart[2];
+    t->n27 = std::move(n27);
     t->beff_tree.assign(ntree, 0.0);
     t->rel_tree.assign(ntree, 0.0);
     root_eigen(dom->bc_type, t->eig);

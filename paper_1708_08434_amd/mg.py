@@ -35,7 +35,8 @@ _WIDTH = {MG_IDX_ORDER: 1, MG_IDX_LEVEL: 1, MG_IDX_IJK: 3, MG_IDX_TREE: 1, MG_ID
 EXPORTS = ["mg_tree_create", "mg_tree_destroy", "mg_tree_info", "mg_tree_bind", "mg_tree_index",
            "mg_field_set", "mg_field_get", "mg_default_opts", "mg_fmg_solve", "mg_vcycle",
            "mg_residual", "mg_tree_residuals", "mg_step", "mg_timing_enable", "mg_timing_read",
-           "mg_autotune", "mg_set_schedule", "mg_stream_copy", "mg_efield", "mg_last_error"]
+           "mg_autotune", "mg_set_schedule", "mg_stream_copy", "mg_efield", "mg_refine_scores",
+           "mg_regrid_plan", "mg_transfer", "mg_last_error"]
 
 
 class mg_domain(ctypes.Structure):
@@ -105,6 +106,9 @@ def lib():
                                 ctypes.POINTER(mg_solve_stats)]
         L.mg_residual.argtypes = [P, P, P, P]
         L.mg_efield.argtypes = [P, P, P]
+        L.mg_refine_scores.argtypes = [P, P]
+        L.mg_regrid_plan.argtypes = [P, P, ctypes.c_double, ctypes.c_double, I32, I64, P, P, P, P]
+        L.mg_transfer.argtypes = [P, P]
         L.mg_step.argtypes = [P, I32, I32, I32]
         L.mg_tree_residuals.argtypes = [P, P]
         L.mg_autotune.argtypes = [P, I32, I32, P]
@@ -205,6 +209,32 @@ def mg_residual(h):
 def mg_efield(h, face_ptr, norm_ptr):
     """Electric field of the current phi into device buffers (either 0)."""
     check(lib().mg_efield(h, ctypes.c_void_p(face_ptr or None), ctypes.c_void_p(norm_ptr or None)))
+
+
+def mg_refine_scores(h, scores_ptr):
+    check(lib().mg_refine_scores(h, ctypes.c_void_p(scores_ptr)))
+
+
+def mg_regrid_plan(h, scores, c3, deref, max_level):
+    """New box list (level, ijk, tree) from host scores [n][27]."""
+    sc = np.ascontiguousarray(scores, dtype=np.float64)
+    need = ctypes.c_int64()
+    L = lib()
+    rc = L.mg_regrid_plan(h, _p(sc), float(c3), float(deref), int(max_level), 0, None, None, None,
+                          ctypes.byref(need))
+    if rc not in (MG_OK, MG_ENOMEM):
+        check(rc)
+    n = need.value
+    lv = np.zeros(n, dtype=np.int32)
+    ij = np.zeros((n, 3), dtype=np.int32)
+    tr = np.zeros(n, dtype=np.int32)
+    check(L.mg_regrid_plan(h, _p(sc), float(c3), float(deref), int(max_level), n, _p(lv), _p(ij), _p(tr),
+                           ctypes.byref(need)))
+    return lv, ij, tr
+
+
+def mg_transfer(h_from, h_to):
+    check(lib().mg_transfer(h_from, h_to))
 
 
 def mg_tree_residuals(h, ntree):
@@ -340,6 +370,14 @@ class Tree:
 
     def residual(self):
         return mg_residual(self.h)
+
+    def refine_scores(self):
+        """[n][27] refinement scores (mg_refine_scores), as a numpy array."""
+        import torch
+        out = torch.empty((self.n, 27), dtype=torch.float64, device=self.device)
+        mg_refine_scores(self.h, out.data_ptr())
+        self.stream.synchronize()
+        return out.cpu().numpy()
 
     def efield(self, to_numpy=True):
         """Face components [n][3][9][8][8] and cell-centre strength [n][8][8][8]
