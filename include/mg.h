@@ -229,7 +229,9 @@ int mg_efield(mg_tree *t, double *e_face, double *e_norm);
  *      criterion h > sqrt(c3 eps0 / |rho|) with its 3-cell buffer).  The 8
  *      children of a box are removed when they are leaves, none is refined,
  *      no cell of theirs or of a same-level leaf neighbour within 3 cells
- *      exceeds deref*c3, and no box two levels finer would touch the parent.
+ *      exceeds deref*c3 (the paper: 1/8), their cell size is below h_deref
+ *      (the paper's Delta x_deref; +inf: no floor), and no box two levels
+ *      finer would touch the parent.
  *      Then 2:1 nesting over 26 neighbours is restored by refining coarse
  *      leaves.  scores: host copy of step 1.  Writes n_out boxes (level,
  *      ijk[3], tree; any order) if n_out <= cap, else MG_ENOMEM with n_out set.
@@ -245,8 +247,8 @@ int mg_efield(mg_tree *t, double *e_face, double *e_norm);
  * has no root in `from` or the domains differ.
  */
 int mg_refine_scores(mg_tree *t, double *scores);
-int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, int max_level,
-                   int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree, int64_t *n_out);
+int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, double h_deref,
+                   int max_level, int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree, int64_t *n_out);
 int mg_transfer(mg_tree *from, mg_tree *to);
 
 /* Relative residual, L2 and max norms of the current phi (leaf cells). */

@@ -1010,16 +1010,17 @@ int mg_refine_scores(mg_tree *t, double *scores) {
     return hip_check(hipGetLastError(), "refine scores launch");
 }
 
-int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, int max_level,
-                   int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree, int64_t *n_out) {
-    if (!t || !scores || !n_out || !(c3 > 0) || !(deref >= 0) || max_level < 1 || max_level > kMaxLevel ||
+int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, double h_deref,
+                   int max_level, int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree, int64_t *n_out) {
+    if (!t || !scores || !n_out || !(c3 > 0) || !(deref >= 0) || !(h_deref > 0) || max_level < 1 ||
+        max_level > kMaxLevel ||
         cap < 0 || (cap > 0 && (!level || !ijk || !tree))) {
         set_error("mg_regrid_plan: invalid arguments");
         return MG_EINVAL;
     }
     std::vector<int32_t> lv, ij, tr;
     try {
-        regrid_plan(t, scores, c3, deref, max_level, lv, ij, tr);
+        regrid_plan(t, scores, c3, deref, h_deref, max_level, lv, ij, tr);
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed");
         return MG_ENOMEM;

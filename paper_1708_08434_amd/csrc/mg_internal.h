@@ -113,9 +113,14 @@ struct mg_tree {
 namespace mg {
 int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level,
                const int32_t *ijk, const int32_t *tree);
+// Morton code of a box position (bit b of i, j, k on bits 3b, 3b+1, 3b+2);
+// within a level and tree, the canonical box order is increasing Morton code.
+uint64_t morton(int32_t i, int32_t j, int32_t k);
+
 // One regrid step (regrid.cpp): the new box list from per-box refinement
 // scores; see mg_regrid_plan in mg.h.
-int regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, int max_level,
+int regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, double h_deref,
+                int max_level,
                 std::vector<int32_t> &level, std::vector<int32_t> &ijk, std::vector<int32_t> &tree);
 void root_eigen(const int32_t bc_type[6], double *eig);
 }

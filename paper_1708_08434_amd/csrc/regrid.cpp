@@ -10,10 +10,13 @@
 // is below max_level.  The 8 children of a box are removed when all of them
 // are leaves, none is refined in this step, and neither their cells nor the
 // cells of same-level leaf neighbours within 3 cells exceed deref * c3
-// (section 2.5 derefines with a smaller constant), unless a box two levels
-// finer than the parent would then touch it.  Finally 2:1 proper nesting over
-// all 26 neighbours is restored by refining coarse leaves.  A step changes a
-// leaf by at most one level, apart from the refinement the nesting forces.
+// (section 2.5 derefines with a smaller constant, 1/8 there) and their cell
+// size is below h_deref (the paper's Delta x_deref, which keeps a floor on
+// the resolution where the discharge has stopped growing), unless a box two
+// levels finer than the parent would then touch it.  Finally 2:1 proper
+// nesting over all 26 neighbours is restored by refining coarse leaves.  A
+// step changes a leaf by at most one level, apart from the refinement the
+// nesting forces.
 #include <algorithm>
 #include <unordered_set>
 
@@ -23,41 +26,53 @@ namespace mg {
 
 namespace {
 
-// (tree, level, i, j, k): 16 + 4 + 3 x 14 bits (levels <= 15)
+// Box keys sort like the canonical box order: level (bits 58..61), tree
+// (42..57), Morton code of (i, j, k) (0..41; 14 bits per coordinate).
 uint64_t key(int64_t tree, int l, int64_t i, int64_t j, int64_t k) {
-    return ((uint64_t)tree << 48) | ((uint64_t)l << 42) | ((uint64_t)i << 28) | ((uint64_t)j << 14) |
-           (uint64_t)k;
+    return ((uint64_t)l << 58) | ((uint64_t)tree << 42) | morton((int32_t)i, (int32_t)j, (int32_t)k);
+}
+
+// every third bit of m, from bit s, packed
+int32_t compact3(uint64_t m, int s) {
+    int32_t v = 0;
+    for (int b = 0; b < 14; b++) v |= (int32_t)((m >> (3 * b + s)) & 1) << b;
+    return v;
 }
 
 }  // namespace
 
-int regrid_plan(const mg_tree *t, const double *sc, double c3, double deref, int max_level,
+int regrid_plan(const mg_tree *t, const double *sc, double c3, double deref, double h_deref, int max_level,
                 std::vector<int32_t> &level, std::vector<int32_t> &ijk, std::vector<int32_t> &tree) {
     const int64_t n = t->n;
     std::vector<char> leaf(n), refine(n, 0), drop(n, 0);
     for (int64_t b = 0; b < n; b++) leaf[b] = t->child[8 * b] < 0;
-    // a cell of box b, or of a same-level leaf neighbour within 3 cells of
-    // b, above thr; scores[b][r] is the largest |b| h^2 over the cells of b
-    // in region r = (sx+1) + 3 (sy+1) + 9 (sz+1) (s_a = -1: cells 0..2 along
-    // a, +1: cells 5..7, 0: all), and the cells of neighbour b + o within 3
-    // cells of b form its region -o, i.e. 26 - o
-    auto hot = [&](int64_t b, double thr) {
-        if (sc[27 * b + 13] > thr) return true;
+    // near[b] (leaves): the largest score over the cells of b and the cells
+    // of same-level leaf neighbours within 3 cells of b; scores[b][r] is the
+    // largest |b| h^2 over the cells of b in region r = (sx+1) + 3 (sy+1) +
+    // 9 (sz+1) (s_a = -1: cells 0..2 along a, +1: cells 5..7, 0: all), and
+    // the cells of neighbour b + o within 3 cells of b form its region -o,
+    // i.e. 26 - o.  Scores are >= 0, so a missing neighbour reads b's own.
+    std::vector<double> near(n, 0.0);
+    for (int64_t b = 0; b < n; b++) {
+        if (!leaf[b]) continue;
+        const int32_t *nb = &t->n27[27 * b];
+        double m = sc[27 * b + 13];
         for (int o = 0; o < 27; o++) {
-            if (o == 13) continue;
-            int32_t N = t->n27[27 * b + o];
-            if (N >= 0 && leaf[N] && sc[27 * (int64_t)N + (26 - o)] > thr) return true;
+            int64_t N = nb[o];
+            bool use = N >= 0 && leaf[N >= 0 ? N : b];
+            m = std::max(m, sc[use ? 27 * N + (26 - o) : 27 * b + 13]);
         }
-        return false;
-    };
+        near[b] = m;
+    }
     for (int64_t b = 0; b < n; b++)
-        if (leaf[b] && t->lev[b] < max_level && hot(b, c3)) refine[b] = 1;
+        if (leaf[b] && t->lev[b] < max_level && near[b] > c3) refine[b] = 1;
+    const double thr_d = deref * c3;
     for (int64_t p = 0; p < n; p++) {
-        if (leaf[p]) continue;
+        if (leaf[p] || !(t->dom.len / (8.0 * (double)(1 << t->lev[p])) < h_deref)) continue;
         bool ok = true;
         for (int q = 0; q < 8 && ok; q++) {
             int64_t c = t->child[8 * p + q];
-            ok = leaf[c] && !refine[c] && !hot(c, deref * c3);
+            ok = leaf[c] && !refine[c] && !(near[c] > thr_d);
         }
         // after the removal p is a leaf of level l: no box of level l+2 may
         // touch it, i.e. no same-level neighbour may have (or get) grandchildren
@@ -71,20 +86,27 @@ int regrid_plan(const mg_tree *t, const double *sc, double c3, double deref, int
         }
         drop[p] = ok;
     }
-    std::unordered_set<uint64_t> set;
+    // the kept boxes, in canonical order (so their keys are sorted); they
+    // satisfy 2:1 nesting among themselves: the tree did, and a removal is
+    // only allowed where no box two levels finer touches the new leaf, so
+    // only added boxes (and what they force) need the nesting check
+    std::vector<uint64_t> kept;
+    kept.reserve(n);
+    for (int64_t b = 0; b < n; b++)
+        if (!(t->lev[b] >= 2 && drop[t->parent[b]]))
+            kept.push_back(key(t->tid[b], t->lev[b], t->ijk[3 * b], t->ijk[3 * b + 1], t->ijk[3 * b + 2]));
+    if (!std::is_sorted(kept.begin(), kept.end())) std::sort(kept.begin(), kept.end());
+    std::unordered_set<uint64_t> added;
     std::vector<uint64_t> work;
-    set.reserve((size_t)(n * 1.3) + 64);
-    auto add = [&](int64_t tr, int l, int64_t i, int64_t j, int64_t k) {
-        if (set.insert(key(tr, l, i, j, k)).second) work.push_back(key(tr, l, i, j, k));
+    auto has = [&](uint64_t kb) { return std::binary_search(kept.begin(), kept.end(), kb) || added.count(kb); };
+    auto add = [&](uint64_t kb) {
+        if (!std::binary_search(kept.begin(), kept.end(), kb) && added.insert(kb).second) work.push_back(kb);
     };
-    for (int64_t b = 0; b < n; b++) {
-        if (t->lev[b] >= 2 && drop[t->parent[b]]) continue;
-        int64_t tr = t->tid[b], i = t->ijk[3 * b], j = t->ijk[3 * b + 1], k = t->ijk[3 * b + 2];
-        add(tr, t->lev[b], i, j, k);
-        if (refine[b])
-            for (int q = 0; q < 8; q++)
-                add(tr, t->lev[b] + 1, 2 * i + (q & 1), 2 * j + ((q >> 1) & 1), 2 * k + (q >> 2));
-    }
+    auto add_children = [&](int64_t tr, int l, int64_t i, int64_t j, int64_t k) {
+        for (int q = 0; q < 8; q++) add(key(tr, l + 1, 2 * i + (q & 1), 2 * j + ((q >> 1) & 1), 2 * k + (q >> 2)));
+    };
+    for (int64_t b = 0; b < n; b++)
+        if (refine[b]) add_children(t->tid[b], t->lev[b], t->ijk[3 * b], t->ijk[3 * b + 1], t->ijk[3 * b + 2]);
     // 2:1 nesting: every position next to a box of level l (26 directions,
     // inside the domain) must be covered down to level l-1; otherwise the
     // deepest box that covers it is refined (and its children checked in turn)
@@ -92,10 +114,9 @@ int regrid_plan(const mg_tree *t, const double *sc, double c3, double deref, int
         std::vector<uint64_t> cur;
         cur.swap(work);
         for (uint64_t kb : cur) {
-            int64_t tr = (int64_t)(kb >> 48);
-            int l = (int)((kb >> 42) & 63);
-            int64_t i = (int64_t)((kb >> 28) & 16383), j = (int64_t)((kb >> 14) & 16383),
-                    k = (int64_t)(kb & 16383);
+            int l = (int)(kb >> 58);
+            int64_t tr = (int64_t)((kb >> 42) & 0xffff);
+            int64_t i = compact3(kb, 0), j = compact3(kb, 1), k = compact3(kb, 2);
             if (l < 3) continue;
             int64_t lim = (int64_t)1 << (l - 1);
             for (int oz = -1; oz <= 1; oz++)
@@ -105,32 +126,30 @@ int regrid_plan(const mg_tree *t, const double *sc, double c3, double deref, int
                         if ((ox | oy | oz) == 0 || pi < 0 || pj < 0 || pk < 0 || pi >= lim ||
                             pj >= lim || pk >= lim)
                             continue;
-                        if (set.count(key(tr, l - 1, pi >> 1, pj >> 1, pk >> 1))) continue;
+                        if (has(key(tr, l - 1, pi >> 1, pj >> 1, pk >> 1))) continue;
                         for (int m = l - 2; m >= 1; m--) {
                             int sh = l - m;
-                            if (set.count(key(tr, m, pi >> sh, pj >> sh, pk >> sh))) {
-                                int64_t ai = pi >> sh, aj = pj >> sh, ak = pk >> sh;
-                                for (int q = 0; q < 8; q++)
-                                    add(tr, m + 1, 2 * ai + (q & 1), 2 * aj + ((q >> 1) & 1),
-                                        2 * ak + (q >> 2));
+                            if (has(key(tr, m, pi >> sh, pj >> sh, pk >> sh))) {
+                                add_children(tr, m, pi >> sh, pj >> sh, pk >> sh);
                                 break;
                             }
                         }
                     }
         }
     }
-    std::vector<uint64_t> keys(set.begin(), set.end());
-    std::sort(keys.begin(), keys.end());
+    std::vector<uint64_t> extra(added.begin(), added.end()), keys(kept.size() + added.size());
+    std::sort(extra.begin(), extra.end());
+    std::merge(kept.begin(), kept.end(), extra.begin(), extra.end(), keys.begin());
     level.resize(keys.size());
     tree.resize(keys.size());
     ijk.resize(3 * keys.size());
     for (size_t q = 0; q < keys.size(); q++) {
         uint64_t kb = keys[q];
-        tree[q] = (int32_t)(kb >> 48);
-        level[q] = (int32_t)((kb >> 42) & 63);
-        ijk[3 * q] = (int32_t)((kb >> 28) & 16383);
-        ijk[3 * q + 1] = (int32_t)((kb >> 14) & 16383);
-        ijk[3 * q + 2] = (int32_t)(kb & 16383);
+        level[q] = (int32_t)(kb >> 58);
+        tree[q] = (int32_t)((kb >> 42) & 0xffff);
+        ijk[3 * q] = compact3(kb, 0);
+        ijk[3 * q + 1] = compact3(kb, 1);
+        ijk[3 * q + 2] = compact3(kb, 2);
     }
     return MG_OK;
 }

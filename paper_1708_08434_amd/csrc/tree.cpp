@@ -18,10 +18,8 @@
 
 namespace mg {
 
-namespace {
-
 // Spread the low 21 bits of x so that bit b lands on bit 3b.
-uint64_t spread_bits3(uint32_t x) {
+static uint64_t spread_bits3(uint32_t x) {
     uint64_t v = x & 0x1fffffu;
     v = (v | (v << 32)) & 0x1f00000000ffffULL;
     v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
@@ -35,6 +33,8 @@ uint64_t morton(int32_t i, int32_t j, int32_t k) {
     return spread_bits3((uint32_t)i) | (spread_bits3((uint32_t)j) << 1) |
            (spread_bits3((uint32_t)k) << 2);
 }
+
+namespace {
 
 struct Key {
     int32_t level, tree;

@@ -107,7 +107,8 @@ def lib():
         L.mg_residual.argtypes = [P, P, P, P]
         L.mg_efield.argtypes = [P, P, P]
         L.mg_refine_scores.argtypes = [P, P]
-        L.mg_regrid_plan.argtypes = [P, P, ctypes.c_double, ctypes.c_double, I32, I64, P, P, P, P]
+        L.mg_regrid_plan.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I32, I64,
+                                      P, P, P, P]
         L.mg_transfer.argtypes = [P, P]
         L.mg_step.argtypes = [P, I32, I32, I32]
         L.mg_tree_residuals.argtypes = [P, P]
@@ -215,22 +216,23 @@ def mg_refine_scores(h, scores_ptr):
     check(lib().mg_refine_scores(h, ctypes.c_void_p(scores_ptr)))
 
 
-def mg_regrid_plan(h, scores, c3, deref, max_level):
+def mg_regrid_plan(h, scores, c3, deref, max_level, h_deref=float("inf")):
     """New box list (level, ijk, tree) from host scores [n][27]."""
     sc = np.ascontiguousarray(scores, dtype=np.float64)
     need = ctypes.c_int64()
-    L = lib()
-    rc = L.mg_regrid_plan(h, _p(sc), float(c3), float(deref), int(max_level), 0, None, None, None,
-                          ctypes.byref(need))
-    if rc not in (MG_OK, MG_ENOMEM):
+    args = (float(c3), float(deref), float(h_deref), int(max_level))
+    n = 2 * len(sc) + 4096                   # enough unless the step refines most boxes
+    while True:
+        lv = np.zeros(n, dtype=np.int32)
+        ij = np.zeros((n, 3), dtype=np.int32)
+        tr = np.zeros(n, dtype=np.int32)
+        rc = lib().mg_regrid_plan(h, _p(sc), *args, n, _p(lv), _p(ij), _p(tr), ctypes.byref(need))
+        if rc == MG_ENOMEM and need.value > n:
+            n = need.value
+            continue
         check(rc)
-    n = need.value
-    lv = np.zeros(n, dtype=np.int32)
-    ij = np.zeros((n, 3), dtype=np.int32)
-    tr = np.zeros(n, dtype=np.int32)
-    check(L.mg_regrid_plan(h, _p(sc), float(c3), float(deref), int(max_level), n, _p(lv), _p(ij), _p(tr),
-                           ctypes.byref(need)))
-    return lv, ij, tr
+        m = need.value
+        return lv[:m], ij[:m], tr[:m]
 
 
 def mg_transfer(h_from, h_to):

@@ -48,7 +48,7 @@ def children(k):
     return [(t, l + 1, 2 * i + a, 2 * j + b, 2 * kk + c) for c in (0, 1) for b in (0, 1) for a in (0, 1)]
 
 
-def ref_plan(level, ijk, tree, scores, c3, deref, max_level):
+def ref_plan(level, ijk, tree, scores, c3, deref, max_level, h_deref=np.inf, length=1.0):
     keys = [(int(t), int(l), int(c[0]), int(c[1]), int(c[2])) for l, c, t in zip(level, ijk, tree)]
     idx = {k: q for q, k in enumerate(keys)}
     leaf = {k: children(k)[0] not in idx for k in keys}
@@ -69,7 +69,7 @@ def ref_plan(level, ijk, tree, scores, c3, deref, max_level):
     refine = {k for k in keys if leaf[k] and k[1] < max_level and hot(k, c3)}
     drop = set()
     for k in keys:
-        if leaf[k]:
+        if leaf[k] or not length / (8 * 2 ** k[1]) < h_deref:   # children's cell size
             continue
         ok = all(leaf[c] and c not in refine and not hot(c, deref * c3) for c in children(k))
         if ok:
@@ -115,25 +115,33 @@ def forest_boxes():
     return BoxList.concat([a, b])
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2, 3])
-def test_plan_matches_the_rules_on_random_scores(seed):
+@pytest.mark.parametrize("seed,h_deref", [(0, np.inf), (1, np.inf), (2, np.inf), (3, np.inf),
+                                          (0, 1 / 40), (2, 1 / 40)])
+def test_plan_matches_the_rules_on_random_scores(seed, h_deref):
     bl = forest_boxes()
     rng = np.random.default_rng(seed)
-    sc = rng.lognormal(0.0, 1.5, (bl.n, 27))
+    # per-box magnitudes over four decades, so that quiet octets exist
+    sc = rng.lognormal(0.0, 1.5, (bl.n, 27)) * 10.0 ** rng.uniform(-4, 0, (bl.n, 1))
     sc[:, 13] = np.maximum(sc[:, 13], sc.max(axis=1))  # the whole box bounds its regions
-    c3 = float(np.quantile(sc[:, 13], 0.8))
+    c3 = float(np.quantile(sc[:, 13], 0.98))
     h = M.mg_tree_create(M.make_domain(), bl.level, bl.ijk, bl.tree)
     try:
         order = M.mg_tree_index(h, M.MG_IDX_ORDER, bl.n).reshape(-1)
         canon = sc[order]                       # scores of canonical box q = caller box order[q]
-        lv, ij, tr = M.mg_regrid_plan(h, canon, c3, 0.3, 6)
+        lv, ij, tr = M.mg_regrid_plan(h, canon, c3, 0.3, 6, h_deref)
     finally:
         M.mg_tree_destroy(h)
     got = {(int(t), int(l), *map(int, c)) for l, c, t in zip(lv, ij, tr)}
-    want = ref_plan(bl.level, bl.ijk, bl.tree, sc, c3, 0.3, 6)
+    want = ref_plan(bl.level, bl.ijk, bl.tree, sc, c3, 0.3, 6, h_deref)
     old = {(int(t), int(l), *map(int, c)) for l, c, t in zip(bl.level, bl.ijk, bl.tree)}
     assert got == want, (len(got ^ want), sorted(got ^ want)[:5])
-    assert got != old                            # the step changed the mesh
+    assert got - old                             # refined somewhere
+    if seed < 3 and h_deref == np.inf:
+        assert old - got                         # and derefined somewhere
+    # removed boxes are finer than h_deref (cell size 1 / (8 * 2^(level-1)))
+    assert all(1.0 / (8 * 2 ** (k[1] - 1)) < h_deref for k in old - got)
+    if h_deref < np.inf:
+        assert got != ref_plan(bl.level, bl.ijk, bl.tree, sc, c3, 0.3, 6) or seed >= 3
     # valid trees for the library and the oracle
     h2 = M.mg_tree_create(M.make_domain(), lv, ij, tr)
     M.mg_tree_destroy(h2)
