@@ -28,7 +28,7 @@ HBM_PEAK_GBPS = 8000.0
 BETA_FP64 = 127.0          # bytes per stored cell per V(2,2) visit (per-sweep model)
 NORM_BYTES = 16.0          # bytes per leaf cell per residual check
 METRIC = ("cells/s per FMG solve to rel. residual 1e-8 (FP64 vs mixed vs learned); HBM GB/s")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gsrb_finest_traffic_streamer_L4+4.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gsrb_finest_traffic_{}.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1708_08434_amd", "csrc", "kernels.hip")
 
 
@@ -54,18 +54,63 @@ def gsrb_kernel_name(v):
             f"{2048 if v < 12 else 4096} persistent workgroups)")
 
 
-def traffic_per_launch(variant):
-    """HBM bytes per launch of the finest-level Gauss-Seidel kernel from the
-    committed rocprofv3 counter summary, or None if the kernel source changed
-    since it was taken or the counters were taken on another launch variant."""
-    if not os.path.exists(TRAFFIC_FILE):
+def traffic_per_launch(workload, level, variant):
+    """HBM bytes per launch of the Gauss-Seidel kernel on the given level of
+    this workload in this launch variant, from the committed rocprofv3 counter
+    summary, or None if there is none or the kernel source has changed since
+    the counters were taken."""
+    path = TRAFFIC_FILE.format(workload)
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         rec = json.load(f)
     src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if rec.get("kernel_sha256") != src or rec.get("variant") != variant:
+    if rec.get("kernel_sha256") != src or rec.get("level") != level:
         return None
-    return rec.get("bytes_per_launch")
+    v = rec.get("variants", {}).get(str(variant))
+    return v["bytes_per_launch"] if v else None
+
+
+def traffic_probe(w, reps=8):
+    """Launches to count HBM traffic under rocprofv3 --pmc: on the level of
+    the tree with the most boxes (the finest level of a single streamer),
+    `reps` smoothing calls of 2 sweeps with each Gauss-Seidel launch variant
+    in turn (that level's schedule entry), each variant's launches preceded by a 1 KiB copy-kernel launch of variant + 1
+    blocks that marks where they start; then the 2 GiB copy kernel whose
+    counters calibrate FETCH_SIZE and WRITE_SIZE.  No autotuning (the other
+    levels keep the default variant, and only the finest level runs)."""
+    import numpy as np
+    import torch
+    from paper_1708_08434_amd import mg as M
+    g = M.Tree.from_workload(w, device="cuda:0")
+    g.set_rhs_from(w)
+    g.fmg_solve()
+    levels = np.bincount(g.index(M.MG_IDX_LEVEL).reshape(-1))
+    fin = int(np.argmax(levels))
+    sched = [3] * g.nlev
+    mark = torch.zeros(2, 1024 // 8, dtype=torch.float64, device="cuda:0")
+    out = {}
+    for v in range(M.MG_GSRB_VARIANTS):
+        sched[fin - 1] = v
+        M.mg_set_schedule(g.h, M.MG_FP64, sched)
+        torch.cuda.synchronize()
+        M.mg_stream_copy(mark[1].data_ptr(), mark[0].data_ptr(), 1024, v + 1, g.stream.cuda_stream)
+        for _ in range(reps):
+            M.mg_step(g.h, M.MG_OP_SMOOTH, fin, 2)
+        torch.cuda.synchronize()
+        out[v] = {"smooth_calls": reps, "sweeps_per_call": 2}
+        print(f"traffic probe: variant {v} done", flush=True)
+    nbytes = 2 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        M.mg_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, 0, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    print(json.dumps({"traffic_probe": {"workload": w.name, "level": fin,
+                                        "boxes": int(levels[fin]), "variants": out,
+                                        "copy_bytes": nbytes,
+                                        "kernel_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()}}),
+          flush=True)
 
 
 def cpu_baseline(w, gpu_cycles, budget_s=12.0):
@@ -351,6 +396,8 @@ def main():
                     help="time steps (2 warm-started field solves each) of the time-stepping leg; "
                          "0 skips it (benchmark streamer only)")
     ap.add_argument("--copy-probe", type=int, default=0, help="bytes of a calibration copy")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only the launches that rocprofv3 --pmc counts for the traffic summary")
     ap.add_argument("--workload", default="streamer",
                     choices=["streamer", "forest", "branched", "two_streamers", "paper_setup"],
                     help="streamer: base 64^3 + 4 levels, 4.8e6 cells (default); forest: 128 "
@@ -371,6 +418,9 @@ def main():
 
     w = {"streamer": c2, "forest": forest, "branched": c3, "two_streamers": c5,
          "paper_setup": paper_setup}[args.workload]()
+    if args.traffic_probe:
+        traffic_probe(w)
+        return
     g = M.Tree.from_workload(w, device="cuda:0")
     g.set_rhs_from(w)
     torch.cuda.synchronize()
@@ -444,7 +494,7 @@ def main():
     bytes_per_launch = kt["level_bytes"][fin] / max(kt["level_launches"][fin], 1)
     achieved = bytes_per_launch / per_launch_s / 1e9
     all_us = kt["total_ms"] * 1e3 / max(kt["launches"], 1)
-    tr = traffic_per_launch(sched64[fin])
+    tr = traffic_per_launch(w.name, fin + 1, sched64[fin])
     out = {
         "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
