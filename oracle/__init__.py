@@ -61,6 +61,11 @@ def lib():
         L.oracle_tree_rel.argtypes = [P, P]
         L.oracle_efield.argtypes = [P, P, P]
         L.oracle_transfer.argtypes = [P, P]
+        L.oracle_koren_psi.argtypes = [D]
+        L.oracle_koren_psi.restype = D
+        L.oracle_fluid_coeffs.argtypes = [P, I32, D, D, P]
+        L.oracle_fluid_coeffs.restype = None
+        L.oracle_fluid_stage.argtypes = [P, P, P, P, P, P, P, P, I32, D, D, D, D, P, P, P]
         L.oracle_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -191,6 +196,38 @@ class OracleTree:
         norm = np.zeros((self.n, 8, 8, 8))
         _check(lib().oracle_efield(self.h, _ptr(face), _ptr(norm)))
         return face, norm
+
+    def fluid_stage(self, ne, ni, n0e, n0i, e_face, e_norm, table, emax, dt, wa=0.0, wb=1.0):
+        """One explicit stage of the fluid model (paper section 2.4) on the
+        leaf cells: out = wa * n0 + wb * (n + dt * rate(n)); densities
+        [n][8][8][8] in SI units, table [ntab][3] = (mu, D, alpha) at
+        E = k * emax / (ntab - 1).  Also sets this tree's right-hand side on
+        the leaf cells to -e (n_i - n_e) / eps0 of the output.  Returns
+        (out_e, out_i, dt limit); non-leaf boxes of the outputs keep the
+        input values."""
+        arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (ne, ni, n0e, n0i, e_face, e_norm)]
+        tab = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 3)
+        oe, oi = arr[0].copy(), arr[1].copy()
+        lim = np.zeros(1)
+        _check(lib().oracle_fluid_stage(self.h, *[_ptr(x) for x in arr], _ptr(tab), len(tab),
+                                        float(emax), float(dt), float(wa), float(wb), _ptr(oe),
+                                        _ptr(oi), _ptr(lim)))
+        return oe, oi, float(lim[0])
+
+    def fluid_step(self, ne, ni, dt, table, emax, n_vcycles=2, safety=0.9):
+        """One time step of the paper's explicit trapezoidal scheme (section
+        2.4): keep n, a forward Euler stage over dt, a new field (n_vcycles
+        warm-started V-cycles), a second Euler stage, the average of its
+        result with the kept densities, a new field.  phi must be the
+        potential of (ne, ni) on entry.  Returns (ne, ni, next dt = safety x
+        the limit evaluated in the second stage)."""
+        ef, en = self.efield()
+        n1e, n1i, _ = self.fluid_stage(ne, ni, ne, ni, ef, en, table, emax, dt, 0.0, 1.0)
+        self.vcycles(n_vcycles, tol=0.0)
+        ef, en = self.efield()
+        oe, oi, lim = self.fluid_stage(n1e, n1i, ne, ni, ef, en, table, emax, dt, 0.5, 0.5)
+        self.vcycles(n_vcycles, tol=0.0)
+        return oe, oi, safety * lim
 
     def leaf_mask(self):
         return self.index(IDX_CHILD)[:, 0] < 0

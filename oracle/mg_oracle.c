@@ -988,3 +988,230 @@ int oracle_set_threads(int n) {
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------ fluid model */
+/* One explicit stage of the drift-diffusion-reaction model of paper section
+   2.4 (equations for n_e and n_i, the spatial discretisation of the fluxes,
+   the time-step limits), on the leaf cells of the tree:
+     out_e = wa * n0_e + wb * (n_e + dt * R_e),  R_e = -div(flux) + S,
+     out_i = wa * n0_i + wb * (n_i + dt * S),    S = alpha(E) mu(E) E n_e,
+   with E = |E| at the cell centre.  The flux of electrons across a face in
+   the +a direction is v n_face - D(E*) (n_R - n_L) / h, where v = -mu(E*) E_a
+   (E_a the face component, E* the mean of the two cells' |E|), and n_face the
+   Koren-limited upwind value of the paper (psi(x) = max(0, min(1, (2+x)/6,
+   x)) applied to the ratio of consecutive differences; a zero denominator
+   gives no correction).  Densities outside a box: the same-level box's cell
+   (its mean over children if it is refined), the mirrored interior cell at
+   the domain boundary (zero gradient), and across a refinement boundary a
+   fine ghost = 1/4 of the coarse cell containing it plus 1/4 of the coarse
+   cell's three neighbours on the ghost's side (linear interpolation), capped
+   at twice the coarse value.  |E| outside a box: the same-level cell, the
+   mirrored cell, or the containing coarse cell.  On a face with a refined
+   neighbour the flux is the mean of the four fine fluxes on it (the coarse
+   flux is their sum per area).  Coefficients: linear interpolation in a
+   table of (mu, D, alpha) at E = k * emax / (ntab - 1), the last entry
+   beyond emax.  dt limit: the minimum over leaf cells of 0.5 / V,
+   1 / (V + 6 D / h^2) and eps0 / (e mu n_e), V = sum over axes of the larger
+   |v| of the cell's two faces divided by h. */
+
+#define Q_ELEM 1.602176634e-19   /* C (CODATA 2018, exact) */
+#define EPS_VAC 8.8541878128e-12 /* F/m (CODATA 2018) */
+
+double oracle_koren_psi(double x) {
+    double m = 1.0;
+    if ((2.0 + x) / 6.0 < m) m = (2.0 + x) / 6.0;
+    if (x < m) m = x;
+    return m > 0.0 ? m : 0.0;
+}
+
+void oracle_fluid_coeffs(const double *tab, int ntab, double emax, double E, double *out3) {
+    double x = E / emax * (double)(ntab - 1);
+    int k = (int)floor(x);
+    if (k >= ntab - 1 || !(x >= 0.0)) {
+        int q = k >= ntab - 1 ? ntab - 1 : 0;
+        for (int c = 0; c < 3; c++) out3[c] = tab[3 * q + c];
+        return;
+    }
+    double w = x - (double)k;
+    for (int c = 0; c < 3; c++) out3[c] = (1.0 - w) * tab[3 * k + c] + w * tab[3 * (k + 1) + c];
+}
+
+typedef struct {
+    otree *t;
+    const double *n;      /* electron density, natural [n][512], covered boxes = mean of children */
+    const double *ef, *en;
+    const double *tab;
+    int ntab;
+    double emax;
+} fctx;
+
+static int mirror(int I, int N) { return I < 0 ? -1 - I : (I >= N ? 2 * N - 1 - I : I); }
+
+/* field value (natural layout) at level-l global cell G of a tree, mirrored
+   into the domain; -1 box if no level-l box holds it */
+static double nat_at(const otree *t, const double *f, int tree, int l, const int G[3], int *found) {
+    int N = 8 << (l - 1), M[3];
+    for (int a = 0; a < 3; a++) M[a] = mirror(G[a], N);
+    int32_t b = find(t, tree, l, M[0] >> 3, M[1] >> 3, M[2] >> 3);
+    *found = b >= 0;
+    if (b < 0) return 0.0;
+    return f[(int64_t)b * 512 + ((M[2] & 7) * 8 + (M[1] & 7)) * 8 + (M[0] & 7)];
+}
+
+/* electron density at level-l global cell G of the tree of box b */
+static double dens(fctx *c, int tree, int l, const int G[3]) {
+    int found;
+    double v = nat_at(c->t, c->n, tree, l, G, &found);
+    if (found) return v;
+    int C[3] = {G[0] >> 1, G[1] >> 1, G[2] >> 1};
+    double cc = nat_at(c->t, c->n, tree, l - 1, C, &found);
+    if (!found) { c->t->bad_lookup = 1; return 0.0; }
+    double s = 0.0;
+    for (int a = 0; a < 3; a++) {
+        int D[3] = {C[0], C[1], C[2]};
+        D[a] += (G[a] & 1) ? 1 : -1;
+        s += nat_at(c->t, c->n, tree, l - 1, D, &found);
+        if (!found) c->t->bad_lookup = 1;
+    }
+    double g = 0.25 * cc + 0.25 * s;
+    return g < 2.0 * cc ? g : 2.0 * cc;
+}
+
+/* |E| at level-l global cell G: same level, mirrored, or the coarse cell */
+static double enorm(fctx *c, int tree, int l, const int G[3]) {
+    int found;
+    double v = nat_at(c->t, c->en, tree, l, G, &found);
+    if (found) return v;
+    int C[3] = {G[0] >> 1, G[1] >> 1, G[2] >> 1};
+    v = nat_at(c->t, c->en, tree, l - 1, C, &found);
+    if (!found) c->t->bad_lookup = 1;
+    return v;
+}
+
+/* flux in the +a direction across face f (between local cells f-1 and f)
+   of box b at tangential cell (u, v); *vel receives the face velocity */
+static double face_flux(fctx *c, int64_t b, int a, int f, int u, int v, double *vel) {
+    otree *t = c->t;
+    int l = t->lev[b], tree = t->tid[b];
+    int B[3] = {t->bx[b], t->by[b], t->bz[b]}, t1, t2;
+    tang_axes(a, &t1, &t2);
+    double h = hlev(t, l);
+    /* velocity from this box's face field */
+    int G[3];
+    G[t1] = 8 * B[t1] + u;
+    G[t2] = 8 * B[t2] + v;
+    G[a] = 8 * B[a] + f - 1;
+    double eL = enorm(c, tree, l, G);
+    G[a] = 8 * B[a] + f;
+    double eR = enorm(c, tree, l, G);
+    double co[3];
+    oracle_fluid_coeffs(c->tab, c->ntab, c->emax, 0.5 * (eL + eR), co);
+    double vx = -co[0] * c->ef[((b * 3 + a) * 9 + f) * 64 + v * 8 + u];
+    *vel = vx;
+    if (f == 0 || f == 8) {
+        int32_t N = t->nbr[6 * b + 2 * a + (f == 8)];
+        if (N >= 0 && t->child[8 * (int64_t)N] >= 0) {
+            /* refined neighbour: mean of the four fine fluxes on this face */
+            double s = 0.0, dummy;
+            for (int dv = 0; dv < 2; dv++)
+                for (int du = 0; du < 2; du++) {
+                    int F[3];
+                    F[t1] = 2 * G[t1] + du;
+                    F[t2] = 2 * G[t2] + dv;
+                    F[a] = f == 8 ? 16 * (B[a] + 1) : 16 * B[a] - 1;  /* fine cell beyond the face */
+                    int32_t fb = find(t, tree, l + 1, F[0] >> 3, F[1] >> 3, F[2] >> 3);
+                    if (fb < 0) { t->bad_lookup = 1; continue; }
+                    s += face_flux(c, fb, a, f == 8 ? 0 : 8, F[t1] & 7, F[t2] & 7, &dummy);
+                }
+            return 0.25 * s;
+        }
+    }
+    double n[4];
+    for (int q = 0; q < 4; q++) {
+        G[a] = 8 * B[a] + f - 2 + q;
+        n[q] = dens(c, tree, l, G);
+    }
+    double nf;
+    if (vx < 0.0) {
+        double den = n[2] - n[1];
+        nf = n[2] - (den == 0.0 ? 0.0 : oracle_koren_psi((n[3] - n[2]) / den) * den);
+    } else {
+        double den = n[2] - n[1];
+        nf = n[1] + (den == 0.0 ? 0.0 : oracle_koren_psi((n[1] - n[0]) / den) * den);
+    }
+    return vx * nf - co[1] * (n[2] - n[1]) / h;
+}
+
+int oracle_fluid_stage(otree *t, const double *ne, const double *ni, const double *n0e,
+                       const double *n0i, const double *e_face, const double *e_norm,
+                       const double *tab, int ntab, double emax, double dt, double wa, double wb,
+                       double *oute, double *outi, double *dtlim) {
+    if (ntab < 2 || !(emax > 0.0)) return ORC_EINVAL;
+    t->bad_lookup = 0;
+    size_t sz = (size_t)t->n * 512;
+    double *nr = (double *)malloc(sz * sizeof(double));
+    if (!nr) return ORC_ENOMEM;
+    memcpy(nr, ne, sz * sizeof(double));
+    /* covered cells: mean of their children, finest levels first */
+    for (int l = t->nlev; l >= 2; l--)
+        for (int64_t p = t->lstart[l - 1]; p < t->lstart[l]; p++) {
+            if (t->child[8 * p] < 0) continue;
+            for (int k = 0; k < 8; k++)
+                for (int j = 0; j < 8; j++)
+                    for (int i = 0; i < 8; i++) {
+                        const double *fc = nr + (int64_t)t->child[8 * p + (i >> 2) + 2 * (j >> 2) + 4 * (k >> 2)] * 512;
+                        double s = 0.0;
+                        for (int dk = 0; dk < 2; dk++)
+                            for (int dj = 0; dj < 2; dj++)
+                                for (int di = 0; di < 2; di++)
+                                    s += fc[((2 * (k & 3) + dk) * 8 + 2 * (j & 3) + dj) * 8 + 2 * (i & 3) + di];
+                        nr[p * 512 + (k * 8 + j) * 8 + i] = 0.125 * s;
+                    }
+        }
+    fctx c = {t, nr, e_face, e_norm, tab, ntab, emax};
+    double lim = INFINITY;
+#pragma omp parallel for schedule(dynamic, 4) reduction(min : lim)
+    for (int64_t b = 0; b < t->n; b++) {
+        if (t->child[8 * b] >= 0) continue;
+        double h = hlev(t, t->lev[b]);
+        /* flux and velocity on every face of the box */
+        double F[3][9][64], V[3][9][64];
+        for (int a = 0; a < 3; a++)
+            for (int f = 0; f <= 8; f++)
+                for (int q = 0; q < 64; q++) F[a][f][q] = face_flux(&c, b, a, f, q & 7, q >> 3, &V[a][f][q]);
+        for (int k = 0; k < 8; k++)
+            for (int j = 0; j < 8; j++)
+                for (int i = 0; i < 8; i++) {
+                    int64_t x = b * 512 + (k * 8 + j) * 8 + i;
+                    int idx[3] = {i, j, k};
+                    double div = 0.0, vs = 0.0;
+                    for (int a = 0; a < 3; a++) {
+                        int t1, t2;
+                        tang_axes(a, &t1, &t2);
+                        int q = idx[t2] * 8 + idx[t1];
+                        div += (F[a][idx[a] + 1][q] - F[a][idx[a]][q]) / h;
+                        double v0 = fabs(V[a][idx[a]][q]), v1 = fabs(V[a][idx[a] + 1][q]);
+                        vs += (v0 > v1 ? v0 : v1) / h;
+                    }
+                    double E = e_norm[x], co[3];
+                    oracle_fluid_coeffs(tab, ntab, emax, E, co);
+                    double S = co[2] * co[0] * E * ne[x];
+                    oute[x] = wa * n0e[x] + wb * (ne[x] + dt * (S - div));
+                    outi[x] = wa * n0i[x] + wb * (ni[x] + dt * S);
+                    double cand = INFINITY;
+                    if (vs > 0.0) cand = 0.5 / vs;
+                    double ad = 1.0 / (vs + 6.0 * co[1] / (h * h));
+                    if (ad < cand) cand = ad;
+                    if (ne[x] > 0.0 && co[0] > 0.0) {
+                        double dr = EPS_VAC / (Q_ELEM * co[0] * ne[x]);
+                        if (dr < cand) cand = dr;
+                    }
+                    if (cand < lim) lim = cand;
+                    /* Poisson right-hand side lap(phi) = -e (n_i - n_e) / eps0 */
+                    t->f[F_RHS][b * BOX + AT(i, j, k)] = -Q_ELEM * (outi[x] - oute[x]) / EPS_VAC;
+                }
+    }
+    free(nr);
+    if (dtlim) *dtlim = lim;
+    return t->bad_lookup ? ORC_ESTATE : ORC_OK;
+}
