@@ -251,6 +251,54 @@ int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double der
                    int max_level, int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree, int64_t *n_out);
 int mg_transfer(mg_tree *from, mg_tree *to);
 
+/*
+ * Fluid model (section 2.4): the drift-diffusion-reaction equations for the
+ * electron and ion densities (SI units, m^-3), advanced with the explicit
+ * trapezoidal rule.  Densities are device arrays in natural layout
+ * [box][k][j][i] over all boxes; only leaf boxes carry data (covered boxes
+ * are overwritten with the mean of their children).  Per stage, on every
+ * leaf cell:
+ *   out_e = wa n0_e + wb (n_e + dt (S - div F)),  out_i = wa n0_i + wb (n_i + dt S),
+ *   S = alpha(|E|) mu(|E|) |E| n_e,
+ *   F (+a direction) = v n_face - D(E*) (n_R - n_L) / h,  v = -mu(E*) E_a,
+ * E_a the face component of the field and E* the mean |E| of the two cells;
+ * n_face is the upwind value corrected with the Koren limiter
+ * psi(x) = max(0, min(1, (2 + x)/6, x)) of the ratio of consecutive
+ * differences (a zero denominator gives no correction).  Ghosts: the
+ * same-level cell, the mirrored cell at the domain boundary (zero
+ * gradient), or across a refinement boundary 1/4 of the coarse cell holding
+ * the ghost plus 1/4 of its three neighbours on the ghost's side, capped at
+ * twice the coarse value.  The flux on the coarse side of a refinement
+ * boundary is the mean of the four fine fluxes on it.  The stage also sets
+ * the solver's right-hand side on leaf cells to -e (n_i - n_e) / eps0 of the
+ * output, and gives the time-step bound min over leaf cells of 0.5 / V,
+ * 1 / (V + 6 D / h^2) and eps0 / (e mu n_e), V = sum over axes of the larger
+ * |v| of the cell's two faces, divided by h.
+ *
+ * mg_fluid_workspace_bytes: size of the fluid workspace for n_table table
+ *   entries (-1 on bad arguments).
+ * mg_fluid_bind: attaches it (device, 256-byte aligned, caller-owned) and
+ *   uploads the transport table (host, [n_table][3] = (mu, D, alpha) at
+ *   E = k e_max / (n_table - 1); linear interpolation, the last entry beyond
+ *   e_max).  The tree must be bound.  Synchronises the tree's stream.
+ * mg_fluid_stage: one stage; e_face [n][3][9][64] and e_norm [n][512] as
+ *   mg_efield writes them; ne is read and its covered boxes are overwritten;
+ *   out_e, out_i (leaf boxes written) must not alias the inputs.  dt_limit
+ *   (host, may be NULL): the time-step bound, which synchronises the stream.
+ * mg_fluid_step: one time step in place: keep (ne, ni), a stage with
+ *   (wa, wb) = (0, 1) into the workspace, n_vcycles warm-started V-cycles and
+ *   the field, a stage with (1/2, 1/2) from that result back into (ne, ni),
+ *   n_vcycles V-cycles.  phi must be the potential of (ne, ni) on entry.
+ *   dt_next (host, may be NULL) = 0.9 x the bound of the second stage.
+ * MG_ESTATE without a bound fluid workspace; MG_EINVAL on bad arguments.
+ */
+int64_t mg_fluid_workspace_bytes(const mg_tree *t, int32_t n_table);
+int mg_fluid_bind(mg_tree *t, void *ws, int64_t bytes, const double *table, int32_t n_table, double e_max);
+int mg_fluid_stage(mg_tree *t, const double *e_face, const double *e_norm, double *ne, const double *ni,
+                   const double *n0e, const double *n0i, double dt, double wa, double wb, double *out_e,
+                   double *out_i, double *dt_limit);
+int mg_fluid_step(mg_tree *t, double *ne, double *ni, double dt, int32_t n_vcycles, double *dt_next);
+
 /* Relative residual, L2 and max norms of the current phi (leaf cells). */
 int mg_residual(mg_tree *t, double *rel, double *l2, double *linf);
 

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmg.so")
-SOURCES = ["tree.cpp", "regrid.cpp", "kernels.hip", "nn.hip", "mg_api.hip"]
+SOURCES = ["tree.cpp", "regrid.cpp", "kernels.hip", "fluid.hip", "nn.hip", "mg_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code.

@@ -101,4 +101,26 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
                          int64_t nchunk, const int32_t *choff, int ntree, double *part2,
                          double *result, hipStream_t s);
 
+// Fluid model (fluid.hip).  Transport table: v[3 k + c] = (mu, D, alpha)
+// at E = k emax / (n - 1).
+struct FluidTable {
+    const double *v;
+    int n;
+    double emax;
+};
+struct FluidArgs {
+    FluidTable tab;
+    const int32_t *isleaf, *cfrev, *leaf, *slots;  // cfrev: [n][6][4] fine slots of a coarse face
+    int64_t nleaf, nslot;
+    double *ne;                                    // covered cells overwritten (mean of children)
+    const double *ni, *n0e, *n0i, *ef, *en;
+    double dt, wa, wb;
+    double *oute, *outi, *rhs;                     // rhs: the solver's colour-split field
+    double *cf;                                    // [nslot][4][64] scratch
+    double *partial, *result;                      // [nleaf] scratch, [1] the time-step bound
+};
+// One stage: restriction of ne into covered cells, the refinement-boundary
+// faces, the update of every leaf box and the minimum time-step bound.
+void launch_fluid_stage(const Geo &g, const FluidArgs &a, hipStream_t s);
+
 }  // namespace mg

@@ -1036,6 +1036,196 @@ int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double der
     return MG_OK;
 }
 
+// ------------------------------------------------------------ fluid model
+
+namespace {
+
+void fluid_layout(const mg_tree *t, int32_t ntab, decltype(mg_tree::foff) &o) {
+    int64_t at = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t r = at;
+        at += (bytes + 255) / 256 * 256;
+        return r;
+    };
+    int64_t cells = t->n * 512 * (int64_t)sizeof(double);
+    o.tab = take((int64_t)ntab * 3 * sizeof(double));
+    o.cfrev = take(t->n * 24 * (int64_t)sizeof(int32_t));
+    o.cf = take(t->nslot * 256 * (int64_t)sizeof(double));
+    o.part = take(t->nleaf * (int64_t)sizeof(double));
+    o.res = take(sizeof(double));
+    o.n0e = take(cells);
+    o.n0i = take(cells);
+    o.n1e = take(cells);
+    o.n1i = take(cells);
+    o.ef = take(t->n * 1728 * (int64_t)sizeof(double));
+    o.en = take(cells);
+    o.total = at;
+}
+
+double *fdp(const mg_tree *t, int64_t off) { return (double *)((char *)t->fws + off); }
+int32_t *fip(const mg_tree *t, int64_t off) { return (int32_t *)((char *)t->fws + off); }
+
+int require_fluid(const mg_tree *t) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!t->fws) {
+        set_error("no fluid workspace bound (call mg_fluid_bind first)");
+        return MG_ESTATE;
+    }
+    return MG_OK;
+}
+
+int fluid_stage(mg_tree *t, const double *ef, const double *en, double *ne, const double *ni,
+                const double *n0e, const double *n0i, double dt, double wa, double wb, double *oute,
+                double *outi, double *lim) {
+    hipStream_t s = stream_of(t);
+    FluidArgs A;
+    A.tab = {fdp(t, t->foff.tab), t->ntab, t->emax};
+    A.isleaf = t->d.isleaf;
+    A.cfrev = fip(t, t->foff.cfrev);
+    A.leaf = t->d.leaf;
+    A.slots = t->d.slots;
+    A.nleaf = t->nleaf;
+    A.nslot = t->nslot;
+    A.ne = ne;
+    A.ni = ni;
+    A.n0e = n0e;
+    A.n0i = n0i;
+    A.ef = ef;
+    A.en = en;
+    A.dt = dt;
+    A.wa = wa;
+    A.wb = wb;
+    A.oute = oute;
+    A.outi = outi;
+    A.rhs = t->d.rhs;
+    A.cf = fdp(t, t->foff.cf);
+    A.partial = fdp(t, t->foff.part);
+    A.result = fdp(t, t->foff.res);
+    launch_fluid_stage(geo(t, false), A, s);
+    int rc = hip_check(hipGetLastError(), "fluid stage launch");
+    if (rc || !lim) return rc;
+    rc = hip_check(hipMemcpyAsync(t->host_result, A.result, sizeof(double), hipMemcpyDeviceToHost, s),
+                   "fluid time-step bound copy");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "fluid stage");
+    if (!rc) *lim = t->host_result[0];
+    return rc;
+}
+
+}  // namespace
+
+int64_t mg_fluid_workspace_bytes(const mg_tree *t, int32_t n_table) {
+    if (!t || n_table < 2) {
+        set_error("mg_fluid_workspace_bytes: null tree or fewer than 2 table entries");
+        return -1;
+    }
+    decltype(mg_tree::foff) o;
+    fluid_layout(t, n_table, o);
+    return o.total;
+}
+
+int mg_fluid_bind(mg_tree *t, void *ws, int64_t bytes, const double *table, int32_t n_table, double e_max) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!ws || !table || n_table < 2 || !(e_max > 0.0) || !std::isfinite(e_max) || ((uintptr_t)ws & 255)) {
+        set_error("mg_fluid_bind: null workspace or table, fewer than 2 entries, e_max <= 0, or a "
+                  "workspace not aligned to 256 bytes");
+        return MG_EINVAL;
+    }
+    for (int64_t q = 0; q < 3 * (int64_t)n_table; q++)
+        if (!std::isfinite(table[q])) {
+            set_error("mg_fluid_bind: non-finite table entry");
+            return MG_EINVAL;
+        }
+    decltype(mg_tree::foff) o;
+    fluid_layout(t, n_table, o);
+    if (bytes < o.total) {
+        set_error("mg_fluid_bind: workspace smaller than mg_fluid_workspace_bytes()");
+        return MG_EINVAL;
+    }
+    // for a face of a leaf box whose same-level neighbour is refined: the
+    // slots of the four children on it, ordered (t2 bit, t1 bit)
+    std::vector<int32_t> rev((size_t)t->n * 24, -1);
+    for (int64_t b = 0; b < t->n; b++)
+        for (int d = 0; d < 6 && t->child[8 * b] < 0; d++) {
+            int32_t N = t->nbr[6 * b + d];
+            if (N < 0 || t->child[8 * (int64_t)N] < 0) continue;
+            int a = d >> 1, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+            for (int tb2 = 0; tb2 < 2; tb2++)
+                for (int tb1 = 0; tb1 < 2; tb1++) {
+                    int bits[3];
+                    bits[a] = (d & 1) ? 0 : 1;
+                    bits[t1] = tb1;
+                    bits[t2] = tb2;
+                    int32_t c = t->child[8 * (int64_t)N + (bits[0] | (bits[1] << 1) | (bits[2] << 2))];
+                    int32_t sl = c >= 0 ? t->cfslot[6 * (int64_t)c + (d ^ 1)] : -1;
+                    if (sl < 0) {
+                        set_error("mg_fluid_bind: a refined neighbour's child has no refinement-boundary slot");
+                        return MG_ETOPO;
+                    }
+                    rev[(size_t)(b * 6 + d) * 4 + tb2 * 2 + tb1] = sl;
+                }
+        }
+    hipStream_t s = stream_of(t);
+    t->fws = ws;
+    t->foff = o;
+    t->ntab = n_table;
+    t->emax = e_max;
+    rc = hip_check(hipMemcpyAsync(fdp(t, o.tab), table, (size_t)n_table * 3 * sizeof(double),
+                                  hipMemcpyHostToDevice, s), "fluid table upload");
+    if (!rc) rc = hip_check(hipMemcpyAsync(fip(t, o.cfrev), rev.data(), rev.size() * sizeof(int32_t),
+                                           hipMemcpyHostToDevice, s), "fluid table upload");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "fluid bind");
+    if (rc) t->fws = nullptr;
+    return rc;
+}
+
+int mg_fluid_stage(mg_tree *t, const double *e_face, const double *e_norm, double *ne, const double *ni,
+                   const double *n0e, const double *n0i, double dt, double wa, double wb, double *out_e,
+                   double *out_i, double *dt_limit) {
+    int rc = require_fluid(t);
+    if (rc) return rc;
+    if (!e_face || !e_norm || !ne || !ni || !n0e || !n0i || !out_e || !out_i || !std::isfinite(dt) ||
+        dt < 0.0 || !std::isfinite(wa) || !std::isfinite(wb)) {
+        set_error("mg_fluid_stage: null pointer or non-finite argument");
+        return MG_EINVAL;
+    }
+    if (out_e == ne || out_e == ni || out_i == ne || out_i == ni || out_e == out_i) {
+        set_error("mg_fluid_stage: outputs must not alias the inputs or each other");
+        return MG_EINVAL;
+    }
+    return fluid_stage(t, e_face, e_norm, ne, ni, n0e, n0i, dt, wa, wb, out_e, out_i, dt_limit);
+}
+
+int mg_fluid_step(mg_tree *t, double *ne, double *ni, double dt, int32_t n_vcycles, double *dt_next) {
+    int rc = require_fluid(t);
+    if (rc) return rc;
+    if (!ne || !ni || ne == ni || !std::isfinite(dt) || dt < 0.0 || n_vcycles < 1) {
+        set_error("mg_fluid_step: null or aliased densities, bad dt, or n_vcycles < 1");
+        return MG_EINVAL;
+    }
+    hipStream_t s = stream_of(t);
+    size_t bytes = (size_t)t->n * 512 * sizeof(double);
+    double *n0e = fdp(t, t->foff.n0e), *n0i = fdp(t, t->foff.n0i);
+    double *n1e = fdp(t, t->foff.n1e), *n1i = fdp(t, t->foff.n1i);
+    double *ef = fdp(t, t->foff.ef), *en = fdp(t, t->foff.en);
+    rc = hip_check(hipMemcpyAsync(n0e, ne, bytes, hipMemcpyDeviceToDevice, s), "fluid step copy");
+    if (!rc) rc = hip_check(hipMemcpyAsync(n0i, ni, bytes, hipMemcpyDeviceToDevice, s), "fluid step copy");
+    mg_solve_opts o;
+    mg_default_opts(&o);
+    double lim = 0.0;
+    // forward Euler stage, new field, second stage averaged with the kept
+    // densities, new field (the explicit trapezoidal rule)
+    if (!rc) rc = mg_efield(t, ef, en);
+    if (!rc) rc = fluid_stage(t, ef, en, ne, ni, ne, ni, dt, 0.0, 1.0, n1e, n1i, nullptr);
+    if (!rc) rc = mg_vcycle(t, &o, n_vcycles, nullptr);
+    if (!rc) rc = mg_efield(t, ef, en);
+    if (!rc) rc = fluid_stage(t, ef, en, n1e, n1i, n0e, n0i, dt, 0.5, 0.5, ne, ni, &lim);
+    if (!rc) rc = mg_vcycle(t, &o, n_vcycles, nullptr);
+    if (!rc && dt_next) *dt_next = 0.9 * lim;
+    return rc;
+}
+
 int mg_transfer(mg_tree *from, mg_tree *to) {
     int rc = require_bound(from);
     if (!rc) rc = require_bound(to);

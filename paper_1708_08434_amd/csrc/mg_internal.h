@@ -75,6 +75,11 @@ struct mg_tree {
     // ---- workspace layout (byte offsets) ----
     struct { int64_t nbr, cfslot, cfq, xt, pnb, slotx, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
              phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, swp, total; } off{};
+    // ---- fluid model (mg_fluid_bind): caller's second workspace ----
+    void *fws = nullptr;
+    int32_t ntab = 0;
+    double emax = 0.0;
+    struct { int64_t tab, cfrev, cf, part, res, n0e, n0i, n1e, n1i, ef, en, total; } foff{};
     // ---- bound device state ----
     void *ws = nullptr;
     void *stream = nullptr;      // caller's stream: every replay and direct launch goes here

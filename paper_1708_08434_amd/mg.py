@@ -36,7 +36,8 @@ EXPORTS = ["mg_tree_create", "mg_tree_destroy", "mg_tree_info", "mg_tree_bind", 
            "mg_field_set", "mg_field_get", "mg_default_opts", "mg_fmg_solve", "mg_vcycle",
            "mg_residual", "mg_tree_residuals", "mg_step", "mg_timing_enable", "mg_timing_read",
            "mg_autotune", "mg_set_schedule", "mg_stream_copy", "mg_efield", "mg_refine_scores",
-           "mg_regrid_plan", "mg_transfer", "mg_last_error"]
+           "mg_regrid_plan", "mg_transfer", "mg_fluid_workspace_bytes", "mg_fluid_bind",
+           "mg_fluid_stage", "mg_fluid_step", "mg_last_error"]
 
 
 class mg_domain(ctypes.Structure):
@@ -110,6 +111,12 @@ def lib():
         L.mg_regrid_plan.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I32, I64,
                                       P, P, P, P]
         L.mg_transfer.argtypes = [P, P]
+        L.mg_fluid_workspace_bytes.argtypes = [P, I32]
+        L.mg_fluid_workspace_bytes.restype = I64
+        L.mg_fluid_bind.argtypes = [P, P, I64, P, I32, ctypes.c_double]
+        L.mg_fluid_stage.argtypes = [P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, P, P, P]
+        L.mg_fluid_step.argtypes = [P, P, P, ctypes.c_double, I32, P]
         L.mg_step.argtypes = [P, I32, I32, I32]
         L.mg_tree_residuals.argtypes = [P, P]
         L.mg_autotune.argtypes = [P, I32, I32, P]
@@ -233,6 +240,35 @@ def mg_regrid_plan(h, scores, c3, deref, max_level, h_deref=float("inf")):
         check(rc)
         m = need.value
         return lv[:m], ij[:m], tr[:m]
+
+
+def mg_fluid_workspace_bytes(h, n_table):
+    n = lib().mg_fluid_workspace_bytes(h, int(n_table))
+    if n < 0:
+        check(MG_EINVAL)
+    return n
+
+
+def mg_fluid_bind(h, ws_ptr, ws_bytes, table, e_max):
+    tab = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 3)
+    check(lib().mg_fluid_bind(h, ctypes.c_void_p(ws_ptr), int(ws_bytes), _p(tab), len(tab), float(e_max)))
+
+
+def mg_fluid_stage(h, ef_ptr, en_ptr, ne_ptr, ni_ptr, n0e_ptr, n0i_ptr, dt, wa, wb, oute_ptr, outi_ptr,
+                   want_limit=True):
+    lim = ctypes.c_double()
+    V = ctypes.c_void_p
+    check(lib().mg_fluid_stage(h, V(ef_ptr), V(en_ptr), V(ne_ptr), V(ni_ptr), V(n0e_ptr), V(n0i_ptr),
+                               float(dt), float(wa), float(wb), V(oute_ptr), V(outi_ptr),
+                               ctypes.byref(lim) if want_limit else None))
+    return lim.value if want_limit else None
+
+
+def mg_fluid_step(h, ne_ptr, ni_ptr, dt, n_vcycles=2):
+    nxt = ctypes.c_double()
+    check(lib().mg_fluid_step(h, ctypes.c_void_p(ne_ptr), ctypes.c_void_p(ni_ptr), float(dt),
+                              int(n_vcycles), ctypes.byref(nxt)))
+    return nxt.value
 
 
 def mg_transfer(h_from, h_to):
@@ -392,6 +428,14 @@ class Tree:
             self.stream.synchronize()
             return face.cpu().numpy(), norm.cpu().numpy()
         return face, norm
+
+    def fluid_bind(self, table, e_max):
+        """Allocate and attach the fluid workspace with this transport table."""
+        import torch
+        nb = mg_fluid_workspace_bytes(self.h, len(np.asarray(table).reshape(-1, 3)))
+        self.fws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.fws.data_ptr() + 255) // 256 * 256
+        mg_fluid_bind(self.h, ptr, nb, table, e_max)
 
     def tree_rel(self):
         return mg_tree_residuals(self.h, int(self.info.n_trees))

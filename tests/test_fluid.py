@@ -187,3 +187,147 @@ def test_stage_along_x_equals_the_one_dimensional_scheme(volts):
     for c in range(32):
         vals = got[gx == c]
         np.testing.assert_allclose(vals, want[c], rtol=1e-12, err_msg=f"cell {c}")
+
+
+# --------------------------------------------------------------------- GPU
+
+def small_si_tree():
+    """The small streamer tree (649 boxes, refined around the channel) in a
+    (1 cm)^3 domain: 20 kV on top, grounded bottom, Neumann sides."""
+    w = streamer_small()
+    b = w.boxes
+    return b, 0.01, (1, 1, 1, 1, 0, 0), (0.0, 0.0, 0.0, 0.0, 0.0, 2e4)
+
+
+def densities(lv, ij, L, seed, head=(0.5, 0.5, 0.62), width=0.05):
+    """Background 1e15 m^-3 plus a seeded, perturbed 1e19 m^-3 blob at the
+    streamer head (it crosses the refinement boundaries); ions 0.8 of it."""
+    x, y, z, _ = G.cell_centres(lv, ij, L)
+    rng = np.random.default_rng(seed)
+    r2 = ((x - head[0] * L) ** 2 + (y - head[1] * L) ** 2 + (z - head[2] * L) ** 2) / (width * L) ** 2
+    blob = 1e19 * np.exp(-r2)
+    ne = 1e15 + blob * (1.0 + 0.3 * rng.random(x.shape))
+    ni = 1e15 + 0.8 * blob
+    return ne, ni
+
+
+def pair(bl, L, bct, bcv):
+    from paper_1708_08434_amd import mg as M
+    g = M.Tree(bl.level, bl.ijk, bl.tree, (0.0, 0.0, 0.0), L, bct, bcv)
+    o = O.OracleTree(bl.level, bl.ijk, bl.tree, length=L, bc_type=bct, bc_val=bcv)
+    assert np.array_equal(g.index(M.MG_IDX_ORDER), o.index(O.IDX_ORDER))
+    return g, o
+
+
+def dev(g, a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(g.device)
+
+
+def leaf_close(got, want, leaf, rtol, what):
+    err = np.abs(got - want)[leaf].max() / np.abs(want[leaf]).max()
+    print(f"{what}: max difference {err:.2e} of the largest value", flush=True)
+    assert err <= rtol, (what, err)
+
+
+@pytest.mark.gpu
+def test_gpu_stage_matches_the_oracle():
+    """Same densities and the same field (the oracle's) on both sides: the
+    outputs of a stage, the solver's right-hand side and the time-step bound."""
+    import torch
+    from paper_1708_08434_amd import mg as M
+    bl, L, bct, bcv = small_si_tree()
+    g, o = pair(bl, L, bct, bcv)
+    lv, ij = o.index(O.IDX_LEVEL), o.index(O.IDX_IJK)
+    ne, ni = densities(lv, ij, L, 11)
+    o.set_field(O.RHS, -E_CHARGE * (ni - ne) / EPS0)
+    o.fmg_solve(tol=1e-10)
+    ef, en = o.efield()
+    tab = synthetic_n2_table()
+    g.fluid_bind(tab, EMAX)
+    Ef, En, Ne, Ni, N0e, N0i = (dev(g, a) for a in (ef, en, ne, ni, 0.9 * ne, 1.1 * ni))
+    Oe, Oi = torch.zeros_like(Ne), torch.zeros_like(Ni)
+    dt = 5e-12
+    lim_g = M.mg_fluid_stage(g.h, Ef.data_ptr(), En.data_ptr(), Ne.data_ptr(), Ni.data_ptr(),
+                             N0e.data_ptr(), N0i.data_ptr(), dt, 0.5, 0.5, Oe.data_ptr(), Oi.data_ptr())
+    oe, oi, lim_o = o.fluid_stage(ne, ni, 0.9 * ne, 1.1 * ni, ef, en, tab, EMAX, dt, 0.5, 0.5)
+    leaf = o.leaf_mask()
+    torch.cuda.synchronize()
+    leaf_close(Oe.cpu().numpy(), oe, leaf, 1e-12, "n_e")
+    leaf_close(Oi.cpu().numpy(), oi, leaf, 1e-12, "n_i")
+    leaf_close(g.get_field(M.MG_FIELD_RHS), o.get_field(O.RHS), leaf, 1e-12, "right-hand side")
+    assert abs(lim_g - lim_o) <= 1e-12 * lim_o, (lim_g, lim_o)
+    assert np.abs(Oe.cpu().numpy() - ne)[leaf].max() > 1e-3 * ne.max()   # the stage did something
+
+
+@pytest.mark.gpu
+def test_gpu_stage_conserves_mass_at_refinement_boundaries():
+    import torch
+    from paper_1708_08434_amd import mg as M
+    bl, L, bct, bcv = small_si_tree()
+    g, o = pair(bl, L, bct, bcv)
+    lv, ij = o.index(O.IDX_LEVEL), o.index(O.IDX_IJK)
+    # a blob around the streamer head, which crosses refinement boundaries;
+    # at the domain faces (>= 6.7 widths away) it is ~1e-19 of its peak, so
+    # no mass flows out there
+    ne, ni = densities(lv, ij, L, 12, head=(0.5, 0.5, 0.6), width=0.06)
+    ne -= 1e15
+    g.set_field(M.MG_FIELD_RHS, -E_CHARGE * (ni - ne) / EPS0)
+    g.fmg_solve()
+    tab = synthetic_n2_table()
+    tab[:, 2] = 0.0                                  # no ionisation
+    g.fluid_bind(tab, EMAX)
+    face, norm = g.efield(to_numpy=False)
+    Ne, Ni = dev(g, ne), dev(g, ni)
+    Oe, Oi = torch.zeros_like(Ne), torch.zeros_like(Ni)
+    M.mg_fluid_stage(g.h, face.data_ptr(), norm.data_ptr(), Ne.data_ptr(), Ni.data_ptr(), Ne.data_ptr(),
+                     Ni.data_ptr(), 2e-11, 0.0, 1.0, Oe.data_ptr(), Oi.data_ptr())
+    leaf = o.leaf_mask()
+    vol = (L / (8.0 * 2.0 ** (lv - 1))) ** 3
+    out = Oe.cpu().numpy()
+    m0 = np.sum(ne[leaf].sum(axis=(1, 2, 3)) * vol[leaf])
+    m1 = np.sum(out[leaf].sum(axis=(1, 2, 3)) * vol[leaf])
+    assert np.abs(out - ne)[leaf].max() > 1e-3 * ne.max()
+    assert abs(m1 - m0) <= 1e-13 * m0, (m1 - m0) / m0
+
+
+def step_parity(bl, L, bct, bcv, ne, ni, dt, rtol):
+    from paper_1708_08434_amd import mg as M
+    g, o = pair(bl, L, bct, bcv)
+    b = -E_CHARGE * (ni - ne) / EPS0
+    g.set_field(M.MG_FIELD_RHS, b)
+    o.set_field(O.RHS, b)
+    g.fmg_solve(rel_tol=1e-10)
+    o.fmg_solve(tol=1e-10)
+    tab = synthetic_n2_table()
+    g.fluid_bind(tab, EMAX)
+    Ne, Ni = dev(g, ne), dev(g, ni)
+    nxt_g = M.mg_fluid_step(g.h, Ne.data_ptr(), Ni.data_ptr(), dt, 2)
+    oe, oi, nxt_o = o.fluid_step(ne, ni, dt, tab, EMAX, 2)
+    leaf = o.leaf_mask()
+    leaf_close(Ne.cpu().numpy(), oe, leaf, rtol, "n_e after the step")
+    leaf_close(Ni.cpu().numpy(), oi, leaf, rtol, "n_i after the step")
+    leaf_close(g.get_field(M.MG_FIELD_PHI), o.get_field(O.PHI), leaf, rtol, "phi after the step")
+    assert abs(nxt_g - nxt_o) <= rtol * nxt_o, (nxt_g, nxt_o)
+    return nxt_g
+
+
+@pytest.mark.gpu
+def test_gpu_time_step_matches_the_oracle():
+    bl, L, bct, bcv = small_si_tree()
+    o = O.OracleTree(bl.level, bl.ijk, bl.tree, length=L)
+    ne, ni = densities(o.index(O.IDX_LEVEL), o.index(O.IDX_IJK), L, 13)
+    step_parity(bl, L, bct, bcv, ne, ni, 5e-12, 1e-10)
+
+
+@pytest.mark.gpu
+def test_gpu_time_step_full_size_matches_the_oracle():
+    """The paper's setup ((40 mm)^3, 80 kV, the benchmark tree) with a
+    perturbed electron blob at the streamer head, one whole step."""
+    from workloads import paper_setup
+    w = paper_setup()
+    bl = w.boxes
+    o = O.OracleTree(bl.level, bl.ijk, bl.tree, length=w.length)
+    ne, ni = densities(o.index(O.IDX_LEVEL), o.index(O.IDX_IJK), w.length, 14, width=0.03)
+    nxt = step_parity(bl, w.length, w.bc_type, w.bc_val, ne, ni, 2e-12, 1e-9)
+    print("next dt", nxt, flush=True)
