@@ -380,6 +380,82 @@ def regrid_leg(w, args, sched64):
             "rel_res_after_2_vcycles_max": max(rel_after)}
 
 
+FLUID_BYTES_PER_LEAF_BOX = 8 * (4 * 512 + 1728 + 512 + 3 * 512)
+
+
+def fluid_leg(args, sched64):
+    """The fluid model's time step (paper section 2.4) on the benchmark tree in
+    the paper's SI setup ((40 mm)^3, 80 kV): electron and ion densities of a
+    perturbed 1e19 m^-3 blob at the streamer head over a 1e15 m^-3
+    background, synthetic transport table (1000 entries up to 35 MV/m).
+    Each step is the explicit trapezoidal rule with two warm-started
+    V-cycles per field solve (mg_fluid_step); the step size follows the
+    limits of the previous step.  The stage alone (restriction, refinement
+    boundaries, update, bound) is timed with HIP events."""
+    import numpy as np
+    import torch
+    from paper_1708_08434_amd import mg as M
+    from workloads import paper_setup, synthetic_n2_table, EMAX
+    w = paper_setup()
+    g = M.Tree.from_workload(w, device="cuda:0")
+    if int(g.nlev) == len(sched64):
+        M.mg_set_schedule(g.h, M.MG_FP64, sched64)
+    lv = g.index(M.MG_IDX_LEVEL).astype(np.float64)
+    ij = g.index(M.MG_IDX_IJK).astype(np.float64)
+    L = w.length
+    h = L / (8.0 * 2.0 ** (lv - 1))
+    c = (np.arange(8) + 0.5)
+    x = (8 * ij[:, 0, None, None, None] + c[None, None, None, :]) * h[:, None, None, None]
+    y = (8 * ij[:, 1, None, None, None] + c[None, None, :, None]) * h[:, None, None, None]
+    z = (8 * ij[:, 2, None, None, None] + c[None, :, None, None]) * h[:, None, None, None]
+    rng = np.random.default_rng(21)
+    blob = 1e19 * np.exp(-((x - 0.5 * L) ** 2 + (y - 0.5 * L) ** 2 + (z - 0.62 * L) ** 2) / (0.03 * L) ** 2)
+    ne = 1e15 + blob * (1.0 + 0.3 * rng.random(blob.shape))
+    ni = 1e15 + 0.8 * blob
+    g.set_field(M.MG_FIELD_RHS, -1.602176634e-19 * (ni - ne) / 8.8541878128e-12)
+    g.fmg_solve()
+    g.fluid_bind(synthetic_n2_table(), EMAX)
+    Ne = torch.from_numpy(ne).to("cuda:0")
+    Ni = torch.from_numpy(ni).to("cuda:0")
+    del x, y, z, blob, ne, ni
+    dt = 1e-12
+    for _ in range(2):
+        dt = M.mg_fluid_step(g.h, Ne.data_ptr(), Ni.data_ptr(), dt, 2)
+    torch.cuda.synchronize()
+    dts = []
+    t0 = time.perf_counter()
+    for _ in range(args.fluid_steps):
+        dts.append(dt)
+        dt = M.mg_fluid_step(g.h, Ne.data_ptr(), Ni.data_ptr(), dt, 2)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # one stage alone, on the tree's stream
+    face, norm = g.efield(to_numpy=False)
+    Oe, Oi = torch.empty_like(Ne), torch.empty_like(Ni)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    with torch.cuda.stream(g.stream):
+        e0.record()
+        for _ in range(reps):
+            M.mg_fluid_stage(g.h, face.data_ptr(), norm.data_ptr(), Ne.data_ptr(), Ni.data_ptr(),
+                             Ne.data_ptr(), Ni.data_ptr(), dt, 0.0, 1.0, Oe.data_ptr(), Oi.data_ptr(),
+                             want_limit=False)
+        e1.record()
+    torch.cuda.synchronize()
+    st_s = e0.elapsed_time(e1) / 1e3 / reps
+    nleaf_box = int(g.info.n_leaf_cells) // 512
+    gbps = FLUID_BYTES_PER_LEAF_BOX * nleaf_box / st_s / 1e9
+    n_leaf = int(g.info.n_leaf_cells)
+    return {"workload": "paper_setup_40mm (benchmark tree, SI units), perturbed head blob",
+            "steps": args.fluid_steps, "ms_per_step": 1e3 * el / args.fluid_steps,
+            "leaf_cells_per_s": n_leaf * args.fluid_steps / el,
+            "dt_first": dts[0], "dt_last": dt, "n_e_max": float(Ne.max()),
+            "stage": {"kernels": "k_fluid_restrict, k_fluid_cf, k_fluid_update, k_fluid_min",
+                      "avg_us": st_s * 1e6, "leaf_boxes": nleaf_box,
+                      "bytes_per_leaf_box": FLUID_BYTES_PER_LEAF_BOX, "achieved": gbps,
+                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -396,6 +472,8 @@ def main():
                     help="time steps (2 warm-started field solves each) of the time-stepping leg; "
                          "0 skips it (benchmark streamer only)")
     ap.add_argument("--copy-probe", type=int, default=0, help="bytes of a calibration copy")
+    ap.add_argument("--fluid-steps", type=int, default=10,
+                    help="time steps of the fluid leg (paper setup, SI units); 0 skips it")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only the launches that rocprofv3 --pmc counts for the traffic summary")
     ap.add_argument("--workload", default="streamer",
@@ -485,6 +563,9 @@ def main():
     regrid = None
     if args.regrid_steps > 0 and args.workload == "streamer":
         regrid = regrid_leg(w, args, sched64)
+    fluid = None
+    if args.fluid_steps > 0 and args.workload == "streamer":
+        fluid = fluid_leg(args, sched64)
     copy = copy_bandwidth()
     mb = model_bytes(counts, n_leaf, k)
     # the level whose half-sweeps move the most bytes (the finest level of a
@@ -540,6 +621,8 @@ def main():
         out["time_step"] = time_step
     if regrid is not None:
         out["regrid"] = regrid
+    if fluid is not None:
+        out["fluid"] = fluid
     if args.workload == "paper_setup":
         g.fmg_solve()
         _, en = g.efield()
