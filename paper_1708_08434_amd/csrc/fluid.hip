@@ -53,41 +53,54 @@ __device__ __forceinline__ int64_t xcd_pos(int64_t blk, int64_t n) {
     return (blk & 7) * per + (blk >> 3);
 }
 
-// (mu, D, alpha) at field strength E: linear interpolation between the two
-// entries around E, the last entry beyond emax
-__device__ __forceinline__ void coef(const FluidTable &T, double E, double &mu, double &D, double &al) {
-    double x = E / T.emax * (double)(T.n - 1);
+// Position of field strength E in the table: interval row k and weight w
+// (linear interpolation between entries k and k+1; beyond emax the last
+// row, which repeats entry n-1, with w = 0)
+__device__ __forceinline__ const double2 *tab_row(const FluidTable &T, double E, double &w) {
+    double x = E * T.scale;
     int k = (int)floor(x);
     if (k >= T.n - 1 || !(x >= 0.0)) {
-        int q = k >= T.n - 1 ? T.n - 1 : 0;
-        mu = T.v[3 * q];
-        D = T.v[3 * q + 1];
-        al = T.v[3 * q + 2];
-        return;
+        k = k >= T.n - 1 ? T.n - 1 : 0;
+        w = 0.0;
+    } else {
+        w = x - (double)k;
     }
-    double w = x - (double)k;
-    const double *p = T.v + 3 * k;
-    mu = (1.0 - w) * p[0] + w * p[3];
-    D = (1.0 - w) * p[1] + w * p[4];
-    al = (1.0 - w) * p[2] + w * p[5];
+    return reinterpret_cast<const double2 *>(T.v + 6 * (int64_t)k);
+}
+__device__ __forceinline__ double lerp(double2 p, double w) { return (1.0 - w) * p.x + w * p.y; }
+// mu and D at E (two 16-byte loads)
+__device__ __forceinline__ void coef2(const FluidTable &T, double E, double &mu, double &D) {
+    double w;
+    const double2 *r = tab_row(T, E, w);
+    mu = lerp(r[0], w);
+    D = lerp(r[1], w);
+}
+// mu, D and alpha at E (three 16-byte loads)
+__device__ __forceinline__ void coef(const FluidTable &T, double E, double &mu, double &D, double &al) {
+    double w;
+    const double2 *r = tab_row(T, E, w);
+    mu = lerp(r[0], w);
+    D = lerp(r[1], w);
+    al = lerp(r[2], w);
 }
 
 // psi(a / b) * b for the Koren limiter psi(x) = max(0, min(1, (2 + x) / 6, x)),
 // without the division: for b > 0 it is max(0, min(b, (2b + a) / 6, a)), for
 // b < 0 the same with min and max exchanged, and 0 for b = 0
 __device__ __forceinline__ double koren(double a, double b) {
-    if (b > 0.0) return fmax(0.0, fmin(b, fmin((2.0 * b + a) / 6.0, a)));
-    if (b < 0.0) return fmin(0.0, fmax(b, fmax((2.0 * b + a) / 6.0, a)));
+    const double sixth = 1.0 / 6.0;
+    if (b > 0.0) return fmax(0.0, fmin(b, fmin((2.0 * b + a) * sixth, a)));
+    if (b < 0.0) return fmin(0.0, fmax(b, fmax((2.0 * b + a) * sixth, a)));
     return 0.0;
 }
 
 // flux across the face between cells L = f-1 and R = f, from the densities
 // of cells f-2, f-1, f, f+1
 __device__ __forceinline__ double flux(double m2, double m1, double p0, double p1, double vel, double D,
-                                       double h) {
+                                       double inv_h) {
     double b = p0 - m1;
     double nf = vel < 0.0 ? p0 - koren(p1 - p0, b) : m1 + koren(m1 - m2, b);
-    return vel * nf - D * b / h;
+    return vel * nf - D * b * inv_h;
 }
 
 __device__ __forceinline__ double cell_h(const Geo &g, int l) { return g.len / (8.0 * (double)(1 << (l - 1))); }
@@ -130,7 +143,7 @@ __global__ __launch_bounds__(64) void k_fluid_cf(Geo g, const double *__restrict
     const int32_t *x = g.slotx + 8 * s;  // Q, base t1, base t2, Q's neighbours -t1 +t1 -t2 +t2
     int64_t Q = x[0];
     int64_t P = g.parent[B];
-    double h = cell_h(g, g.ijk[B * 4 + 3]);
+    double inv_h = 1.0 / cell_h(g, g.ijk[B * 4 + 3]);
     int C[3];
     C[a] = side ? 0 : 7;
     C[t1] = x[1] + (u >> 1);
@@ -203,13 +216,13 @@ __global__ __launch_bounds__(64) void k_fluid_cf(Geo g, const double *__restrict
         p1 = gh[1];
         eR = eg;
     }
-    double mu, D, al;
-    coef(T, 0.5 * (eL + eR), mu, D, al);
+    double mu, D;
+    coef2(T, 0.5 * (eL + eR), mu, D);
     double vel = -mu * ef[((B * 3 + a) * 9 + f) * 64 + q];
     double* o = cf + s * 256;
     o[q] = gh[0];
     o[64 + q] = gh[1];
-    o[128 + q] = flux(m2, m1, p0, p1, vel, D, h);
+    o[128 + q] = flux(m2, m1, p0, p1, vel, D, inv_h);
     o[192 + q] = vel;
 }
 
@@ -237,7 +250,7 @@ __global__ __launch_bounds__(512) void k_fluid_update(
         nb[d] = g.nbr[b * 6 + d];
         sl[d] = g.cfslot[b * 6 + d];
     }
-    double h = cell_h(g, g.ijk[b * 4 + 3]);
+    double h = cell_h(g, g.ijk[b * 4 + 3]), inv_h = 1.0 / h;
     double nec = ne[b * 512 + t], nic = ni[b * 512 + t], n0ec = n0e[b * 512 + t], n0ic = n0i[b * 512 + t];
     double enc = en[b * 512 + t];
     N[p2(i, j, k)] = nec;
@@ -285,8 +298,8 @@ __global__ __launch_bounds__(512) void k_fluid_update(
         int u = qq & 7, v = qq >> 3;
         Cell cl = place(a, f - 1, u, v), cr = place(a, f, u, v);
         double eL = EN[p1(cl.x, cl.y, cl.z)], eR = EN[p1(cr.x, cr.y, cr.z)];
-        double mu, D, al;
-        coef(T, 0.5 * (eL + eR), mu, D, al);
+        double mu, D;
+        coef2(T, 0.5 * (eL + eR), mu, D);
         double V = -mu * ef[((b * 3 + a) * 9 + f) * 64 + qq], F;
         int d = 2 * a + (f == 8 ? 1 : 0);
         int nbd = d == 0 ? nb[0] : d == 1 ? nb[1] : d == 2 ? nb[2] : d == 3 ? nb[3] : d == 4 ? nb[4] : nb[5];
@@ -305,7 +318,7 @@ __global__ __launch_bounds__(512) void k_fluid_update(
         } else {
             Cell c0 = place(a, f - 2, u, v), c3 = place(a, f + 1, u, v);
             F = flux(N[p2(c0.x, c0.y, c0.z)], N[p2(cl.x, cl.y, cl.z)], N[p2(cr.x, cr.y, cr.z)],
-                     N[p2(c3.x, c3.y, c3.z)], V, D, h);
+                     N[p2(c3.x, c3.y, c3.z)], V, D, inv_h);
         }
         FX[e] = F;
         VX[e] = V;
@@ -317,9 +330,9 @@ __global__ __launch_bounds__(512) void k_fluid_update(
         // the cell's faces along a: position f0, tangential (t1, t2) cell qa
         int f0 = a == 0 ? i : (a == 1 ? j : k);
         int qa = a == 0 ? k * 8 + j : (a == 1 ? k * 8 + i : j * 8 + i);
-        div += (FX[a * 576 + (f0 + 1) * 64 + qa] - FX[a * 576 + f0 * 64 + qa]) / h;
+        div += (FX[a * 576 + (f0 + 1) * 64 + qa] - FX[a * 576 + f0 * 64 + qa]) * inv_h;
         double v0 = fabs(VX[a * 576 + f0 * 64 + qa]), v1 = fabs(VX[a * 576 + (f0 + 1) * 64 + qa]);
-        vs += (v0 > v1 ? v0 : v1) / h;
+        vs += (v0 > v1 ? v0 : v1) * inv_h;
     }
     double mu, D, al;
     coef(T, enc, mu, D, al);

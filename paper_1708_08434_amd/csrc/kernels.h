@@ -101,12 +101,14 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
                          int64_t nchunk, const int32_t *choff, int ntree, double *part2,
                          double *result, hipStream_t s);
 
-// Fluid model (fluid.hip).  Transport table: v[3 k + c] = (mu, D, alpha)
-// at E = k emax / (n - 1).
+// Fluid model (fluid.hip).  Transport table of n entries (mu, D, alpha) at
+// E = k emax / (n - 1), stored as interval rows of 6 doubles
+// v[6 k ..] = (mu_k, mu_k+1, D_k, D_k+1, alpha_k, alpha_k+1), the last row
+// repeating entry n-1; scale = (n - 1) / emax.
 struct FluidTable {
     const double *v;
     int n;
-    double emax;
+    double scale;
 };
 struct FluidArgs {
     FluidTable tab;

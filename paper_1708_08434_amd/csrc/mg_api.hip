@@ -1048,7 +1048,7 @@ void fluid_layout(const mg_tree *t, int32_t ntab, decltype(mg_tree::foff) &o) {
         return r;
     };
     int64_t cells = t->n * 512 * (int64_t)sizeof(double);
-    o.tab = take((int64_t)ntab * 3 * sizeof(double));
+    o.tab = take((int64_t)ntab * 6 * sizeof(double));
     o.cfrev = take(t->n * 24 * (int64_t)sizeof(int32_t));
     o.cf = take(t->nslot * 256 * (int64_t)sizeof(double));
     o.part = take(t->nleaf * (int64_t)sizeof(double));
@@ -1080,7 +1080,7 @@ int fluid_stage(mg_tree *t, const double *ef, const double *en, double *ne, cons
                 double *outi, double *lim) {
     hipStream_t s = stream_of(t);
     FluidArgs A;
-    A.tab = {fdp(t, t->foff.tab), t->ntab, t->emax};
+    A.tab = {fdp(t, t->foff.tab), t->ntab, (double)(t->ntab - 1) / t->emax};
     A.isleaf = t->d.isleaf;
     A.cfrev = fip(t, t->foff.cfrev);
     A.leaf = t->d.leaf;
@@ -1166,12 +1166,22 @@ int mg_fluid_bind(mg_tree *t, void *ws, int64_t bytes, const double *table, int3
                     rev[(size_t)(b * 6 + d) * 4 + tb2 * 2 + tb1] = sl;
                 }
         }
+    // interval rows (entry k, entry k+1) per coefficient; the last row
+    // repeats the last entry
+    std::vector<double> rows((size_t)n_table * 6);
+    for (int32_t k = 0; k < n_table; k++) {
+        int32_t k1 = k + 1 < n_table ? k + 1 : k;
+        for (int c = 0; c < 3; c++) {
+            rows[6 * (size_t)k + 2 * c] = table[3 * (size_t)k + c];
+            rows[6 * (size_t)k + 2 * c + 1] = table[3 * (size_t)k1 + c];
+        }
+    }
     hipStream_t s = stream_of(t);
     t->fws = ws;
     t->foff = o;
     t->ntab = n_table;
     t->emax = e_max;
-    rc = hip_check(hipMemcpyAsync(fdp(t, o.tab), table, (size_t)n_table * 3 * sizeof(double),
+    rc = hip_check(hipMemcpyAsync(fdp(t, o.tab), rows.data(), rows.size() * sizeof(double),
                                   hipMemcpyHostToDevice, s), "fluid table upload");
     if (!rc) rc = hip_check(hipMemcpyAsync(fip(t, o.cfrev), rev.data(), rev.size() * sizeof(int32_t),
                                            hipMemcpyHostToDevice, s), "fluid table upload");
