@@ -179,3 +179,49 @@ def test_workload_leaf_counts_match_the_tables():
         M.mg_tree_destroy(h)
     o = O.OracleTree.from_workload(w)
     assert int(o.leaf_mask().sum()) * 512 == w.n_leaf
+
+
+def test_mesh_adaptation_and_fluid_argument_checks():
+    """Argument and state checks of the mesh-adaptation and fluid entry
+    points that need no GPU: the plan rejects bad thresholds and levels and
+    reports the size it needs; the fluid workspace size grows with the table
+    and the tree; an unbound tree is refused before any device work."""
+    bl = refine_boxes_explicit(2, [(2, 0, 0, 0)])
+    h = M.mg_tree_create(M.make_domain(), bl.level, bl.ijk)
+    try:
+        L = M.lib()
+        n = len(bl.level)
+        sc = np.ones((n, 27))
+        lv = np.zeros(4 * n, dtype=np.int32)
+        ij = np.zeros((4 * n, 3), dtype=np.int32)
+        tr = np.zeros(4 * n, dtype=np.int32)
+        need = ctypes.c_int64()
+        P = lambda a: a.ctypes.data
+
+        def plan(c3, deref, h_deref, max_level, cap):
+            return L.mg_regrid_plan(h, P(sc), c3, deref, h_deref, max_level, cap, P(lv), P(ij), P(tr),
+                                    ctypes.byref(need))
+        for bad in [(0.0, 0.1, 1.0, 5), (-1.0, 0.1, 1.0, 5), (1.0, -0.1, 1.0, 5), (1.0, 0.1, 0.0, 5),
+                    (1.0, 0.1, 1.0, 0), (1.0, 0.1, 1.0, 16)]:
+            assert plan(*bad, 4 * n) == M.MG_EINVAL, bad
+        # scores of 1 everywhere, c3 = 0.5: every leaf below level 4 is refined
+        assert plan(0.5, 0.1, float("inf"), 4, 0) == M.MG_ENOMEM
+        assert need.value > n
+        m = need.value                              # room for the whole plan
+        lv, ij, tr = (np.zeros(m, dtype=np.int32), np.zeros((m, 3), dtype=np.int32),
+                      np.zeros(m, dtype=np.int32))
+        assert plan(0.5, 0.1, float("inf"), 4, m) == M.MG_OK
+        assert plan(0.5, 0.1, float("inf"), 4, m - 1) == M.MG_ENOMEM and need.value == m
+        a = M.mg_fluid_workspace_bytes(h, 2)
+        b = M.mg_fluid_workspace_bytes(h, 1000)
+        assert b > a >= n * 8 * (4 * 512 + 1728 + 512)
+        assert L.mg_fluid_workspace_bytes(h, 1) == -1
+        tab = np.ones((4, 3))
+        assert L.mg_fluid_bind(h, ctypes.c_void_p(256), 1 << 30, P(tab), 4, 1.0) == M.MG_ESTATE
+        x = ctypes.c_void_p(256)
+        assert L.mg_fluid_step(h, x, x, ctypes.c_double(1e-12), 2, None) == M.MG_ESTATE
+        assert L.mg_fluid_stage(h, x, x, x, x, x, x, ctypes.c_double(0.0), ctypes.c_double(0.0),
+                                ctypes.c_double(1.0), x, x, None) == M.MG_ESTATE
+        assert L.mg_refine_scores(h, x) == M.MG_ESTATE
+    finally:
+        M.mg_tree_destroy(h)
