@@ -429,6 +429,34 @@ def test_every_gsrb_variant_gives_the_same_bits(tree, fp32):
     say("variants", tree, "fp32" if fp32 else "fp64", "all", M.MG_GSRB_VARIANTS, "identical")
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_persistent_sweeps_walk_several_boxes_on_the_benchmark_tree(fp32):
+    """The persistent half-sweeps give a workgroup several boxes only on
+    levels with more boxes than workgroups (2048 or 4096): on the benchmark
+    tree's finest level (6784 boxes) they give the same bits as the one-box
+    half-sweeps."""
+    w = c2()
+    g = M.Tree.from_workload(w)
+    rng = np.random.default_rng(17)
+    phi0 = rng.standard_normal((g.n, 8, 8, 8))
+    rhs0 = rng.standard_normal((g.n, 8, 8, 8)) * 100.0
+    if fp32:
+        phi0, rhs0 = (a.astype(np.float32).astype(np.float64) for a in (phi0, rhs0))
+    fphi, frhs = (M.MG_FIELD_E32, M.MG_FIELD_R32) if fp32 else (M.MG_FIELD_PHI, M.MG_FIELD_RHS)
+    prec, opf = (M.MG_MIXED, M.MG_OP_F32) if fp32 else (M.MG_FP64, 0)
+    ref = None
+    for v in (3,) + M.MG_GSRB_PERSISTENT:
+        M.mg_set_schedule(g.h, prec, [v] * g.nlev)
+        g.set_field(fphi, phi0)
+        g.set_field(frhs, rhs0)
+        g.step(M.MG_OP_SMOOTH | opf, g.nlev, 3)
+        out = g.get_field(fphi)
+        if ref is None:
+            ref = out
+        assert np.array_equal(out, ref), v
+    say("persistent variants on", g.n, "boxes:", "identical")
+
+
 @pytest.mark.parametrize("v", M.MG_GSRB_FUSED + M.MG_GSRB_OCTET)
 def test_fused_and_octet_sweeps_match_the_oracle(v):
     """Fused sweeps and octet half-sweeps against the oracle's sweep-by-sweep
