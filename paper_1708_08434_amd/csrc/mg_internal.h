@@ -2,6 +2,7 @@
 // carved out of the caller's workspace by mg_api.hip.
 #pragma once
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -14,6 +15,26 @@ constexpr int kCells = 512;      // cells per box
 constexpr int kHalf = 256;       // cells of one colour per box
 
 void set_error(const std::string &msg);
+
+// Host array of a trivially copyable type that is not value-initialised:
+// the large index tables are filled by parallel loops that write every
+// entry, so no serial prefill (and first touch) precedes them.
+template <typename T> class RawArray {
+  public:
+    void reset(size_t n) {
+        p_.reset(n ? new T[n] : nullptr);
+        n_ = n;
+    }
+    T *data() { return p_.get(); }
+    const T *data() const { return p_.get(); }
+    size_t size() const { return n_; }
+    T &operator[](size_t i) { return p_[i]; }
+    const T &operator[](size_t i) const { return p_[i]; }
+
+  private:
+    std::unique_ptr<T[]> p_;
+    size_t n_ = 0;
+};
 
 // Device-side views of the workspace; all pointers are into one allocation.
 struct DevTables {
@@ -58,12 +79,13 @@ struct mg_tree {
     // ---- host tables (canonical order) ----
     int64_t n = 0;
     int nlev = 0, ntree = 0;
-    std::vector<int32_t> order, lev, ijk, tid, parent, child, nbr, cfq, cfslot, xt, pnb, slotx;
+    std::vector<int32_t> order, lev, ijk, tid, parent, child, nbr, cfq, cfslot, pnb, slotx;
+    mg::RawArray<int32_t> xt;                           // [n][6][4][2] (see tree.cpp)
     int64_t lstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> refined, leaf;                 // box ids grouped by level
     int64_t rstart[mg::kMaxLevel + 2] = {0}, fstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> slots;                         // (box, face) per slot
-    std::vector<int32_t> n27;                           // [n][27] same-level box at ijk + o, -1, -2
+    mg::RawArray<int32_t> n27;                          // [n][27] same-level box at ijk + o, -1, -2
     std::vector<int32_t> root2;                         // first level-2 box per tree, or -1
     bool bottom_ok = false;                             // levels 1-2 can run as one launch
     std::vector<int32_t> leaf_tree, tree_off;           // leaf positions grouped by tree

@@ -10,7 +10,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <atomic>
 #include <cstring>
+#include <thread>
 #include <tuple>
 
 #include "kernels.h"
@@ -35,6 +37,35 @@ uint64_t morton(int32_t i, int32_t j, int32_t k) {
 }
 
 namespace {
+
+// f(lo, hi) over [0, n) in contiguous pieces on up to 16 host threads; one
+// piece (the calling thread) below 16384 items per thread
+template <typename F> void parallel_for(int64_t n, F f) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t nt = std::min<int64_t>({(int64_t)(hw ? hw : 1), (int64_t)16, std::max<int64_t>(1, n / 16384)});
+    if (nt <= 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    int64_t per = (n + nt - 1) / nt;
+    std::vector<std::thread> th;
+    for (int64_t q = 1; q < nt; q++) {
+        int64_t lo = q * per, hi = std::min(n, lo + per);
+        if (lo < hi) th.emplace_back(f, lo, hi);
+    }
+    f((int64_t)0, std::min(n, per));
+    for (auto &x : th) x.join();
+}
+
+// smallest box index reported by any thread (-1: none)
+struct FirstBad {
+    std::atomic<int64_t> v{-1};
+    void add(int64_t b) {
+        int64_t cur = v.load();
+        while ((cur < 0 || b < cur) && !v.compare_exchange_weak(cur, b)) {
+        }
+    }
+};
 
 struct Key {
     int32_t level, tree;
@@ -87,7 +118,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
         ntree = std::max(ntree, tr + 1);
         keys[b] = Key{l, tr, morton(i, j, k), (int32_t)b};
     }
-    std::sort(keys.begin(), keys.end());
+    if (!std::is_sorted(keys.begin(), keys.end())) std::sort(keys.begin(), keys.end());
     for (int64_t b = 1; b < n; b++)
         if (keys[b].same(keys[b - 1])) {
             snprintf(g_buf, sizeof g_buf, "boxes %d and %d are duplicates", keys[b - 1].src, keys[b].src);
@@ -139,26 +170,37 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     // parents by binary search in the previous level's sorted range
     t->parent.assign(n, -1);
     t->child.assign(8 * n, -1);
+    // (the parents of a level's boxes, in order, are non-decreasing in the
+    // previous level's order: one forward walk)
     for (int l = 2; l <= t->nlev; l++) {
-        const Key *pb = keys.data() + lbegin(l - 1), *pe = keys.data() + lend(l - 1);
+        int64_t pq = lbegin(l - 1), pe = lend(l - 1);
         for (int64_t b = lbegin(l); b < lend(l); b++) {
             Key want{l - 1, t->tid[b], keys[b].m >> 3, 0};
-            const Key *it = std::lower_bound(pb, pe, want);
-            if (it == pe || !it->same(want)) {
+            while (pq < pe && keys[pq] < want) pq++;
+            if (pq == pe || !keys[pq].same(want)) {
                 snprintf(g_buf, sizeof g_buf, "box %d (level %d) has no parent", t->order[b], l);
                 set_error(g_buf);
                 return MG_ETOPO;
             }
-            int32_t p = (int32_t)(it - keys.data());
+            int32_t p = (int32_t)pq;
             int oct = (int)(keys[b].m & 7);  // (i&1) + 2(j&1) + 4(k&1)
             t->parent[b] = p;
             t->child[8 * p + oct] = (int32_t)b;
         }
     }
-    for (int64_t b = 0; b < n; b++) {
-        int c = 0;
-        for (int q = 0; q < 8; q++) c += t->child[8 * b + q] >= 0;
-        if (c != 0 && c != 8) {
+    {
+        FirstBad bad;
+        parallel_for(n, [&](int64_t lo, int64_t hi) {
+            for (int64_t b = lo; b < hi; b++) {
+                int c = 0;
+                for (int q = 0; q < 8; q++) c += t->child[8 * b + q] >= 0;
+                if (c != 0 && c != 8) bad.add(b);
+            }
+        });
+        if (bad.v >= 0) {
+            int64_t b = bad.v;
+            int c = 0;
+            for (int q = 0; q < 8; q++) c += t->child[8 * b + q] >= 0;
             snprintf(g_buf, sizeof g_buf, "box %d has %d of its 8 children", t->order[b], c);
             set_error(g_buf);
             return MG_ETOPO;
@@ -169,11 +211,15 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     // same-level box at ijk + o, -1 when that position is covered only by a
     // coarser leaf, -2 outside the domain.  A level-l box whose neighbour
     // position is not covered down to level l-1 violates proper nesting.
-    std::vector<int32_t> n27((size_t)27 * n, -2);
-    for (int64_t b = lbegin(1); b < lend(1); b++) n27[27 * b + 13] = (int32_t)b;
+    RawArray<int32_t> n27;
+    n27.reset((size_t)27 * n);
+    for (int64_t b = lbegin(1); b < lend(1); b++)
+        for (int o = 0; o < 27; o++) n27[27 * b + o] = o == 13 ? (int32_t)b : -2;
     for (int l = 2; l <= t->nlev; l++) {
         int32_t lim = 1 << (l - 1);
-        for (int64_t b = lbegin(l); b < lend(l); b++) {
+        // fills the 27 entries of box b; returns the first direction that
+        // violates nesting, or -1
+        auto fill27 = [&](int64_t b) {
             int32_t p = t->parent[b];
             const int32_t *B = &t->ijk[3 * b];
             for (int oz = -1; oz <= 1; oz++)
@@ -188,25 +234,38 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
                             up[a] = ((B[a] & 1) + o[a] + 2) / 2 - 1;
                         }
                         int oi = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
-                        if (!inside) { n27[27 * b + oi] = -2; continue; }
-                        int32_t cont = n27[27 * (int64_t)p + (up[0] + 1) + 3 * (up[1] + 1) + 9 * (up[2] + 1)];
-                        if (cont < 0) {
-                            snprintf(g_buf, sizeof g_buf,
-                                     "box %d (level %d) violates 2:1 nesting towards (%d,%d,%d)",
-                                     t->order[b], l, ox, oy, oz);
-                            set_error(g_buf);
-                            return MG_ENESTING;
+                        if (!inside) {
+                            n27[27 * b + oi] = -2;
+                            continue;
                         }
+                        int32_t cont = n27[27 * (int64_t)p + (up[0] + 1) + 3 * (up[1] + 1) + 9 * (up[2] + 1)];
+                        if (cont < 0) return oi;
                         int oct = (pos[0] & 1) + 2 * (pos[1] & 1) + 4 * (pos[2] & 1);
                         n27[27 * b + oi] = t->child[8 * (int64_t)cont + oct];  // -1: coarser leaf
                     }
+            return -1;
+        };
+        FirstBad bad;
+        int64_t l0 = lbegin(l);
+        parallel_for(lend(l) - l0, [&](int64_t lo, int64_t hi) {
+            for (int64_t b = l0 + lo; b < l0 + hi; b++)
+                if (fill27(b) >= 0) bad.add(b);
+        });
+        if (bad.v >= 0) {
+            int64_t bb = bad.v;
+            int oi = fill27(bb);
+            snprintf(g_buf, sizeof g_buf, "box %d (level %d) violates 2:1 nesting towards (%d,%d,%d)",
+                     t->order[bb], l, oi % 3 - 1, (oi / 3) % 3 - 1, oi / 9 - 1);
+            set_error(g_buf);
+            return MG_ENESTING;
         }
     }
     // face tables (the 27-neighbourhood is kept for the regrid planner)
     static const int face_oi[6] = {12, 14, 10, 16, 4, 22};
     t->nbr.assign(6 * n, -2);
     t->cfq.assign(6 * n, -1);
-    for (int64_t b = 0; b < n; b++) {
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t b = lo; b < hi; b++) {
         for (int d = 0; d < 6; d++) {
             int32_t v = n27[27 * b + face_oi[d]];
             t->nbr[6 * b + d] = v;
@@ -220,6 +279,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
             }
         }
     }
+    });
     // refinement-boundary face slots, grouped by level
     t->cfslot.assign(6 * n, -1);
     t->slots.clear();
@@ -240,7 +300,8 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     // base coordinates of the face's quarter of Q along the two tangential
     // axes, and Q's face neighbours across them (-t1, +t1, -t2, +t2)
     t->slotx.assign((size_t)8 * t->nslot, 0);
-    for (int64_t q = 0; q < t->nslot; q++) {
+    parallel_for(t->nslot, [&](int64_t lo, int64_t hi) {
+    for (int64_t q = lo; q < hi; q++) {
         int64_t b = t->slots[2 * q];
         int d = t->slots[2 * q + 1], a = d >> 1, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
         int32_t Q = t->cfq[6 * b + d];
@@ -253,21 +314,28 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
         x[5] = t->nbr[6 * (int64_t)Q + 2 * t2];
         x[6] = t->nbr[6 * (int64_t)Q + 2 * t2 + 1];
     }
+    });
     // the parent's face neighbours of every box (prolongation stages the
     // parent's correction one cell beyond its octant)
     t->pnb.assign((size_t)6 * n, -2);
-    for (int64_t b = 0; b < n; b++)
-        if (t->parent[b] >= 0)
-            for (int f = 0; f < 6; f++) t->pnb[6 * b + f] = t->nbr[6 * (int64_t)t->parent[b] + f];
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t b = lo; b < hi; b++)
+            if (t->parent[b] >= 0)
+                for (int f = 0; f < 6; f++) t->pnb[6 * b + f] = t->nbr[6 * (int64_t)t->parent[b] + f];
+    });
     // faces of the face neighbours: for box b, face d with a same-level
     // neighbour N, and the 4 faces of N across the two axes tangential to d
     // (-t1, +t1, -t2, +t2), the pair (nbr[N][d'], cfslot[N][d']); the fused
     // Gauss-Seidel sweep recomputes N's face layer and needs N's ghosts.
-    t->xt.assign((size_t)6 * 4 * 2 * n, -2);
-    for (int64_t b = 0; b < n; b++)
+    t->xt.reset((size_t)6 * 4 * 2 * n);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t b = lo; b < hi; b++)
         for (int d = 0; d < 6; d++) {
             int32_t N = t->nbr[6 * b + d];
-            if (N < 0) continue;
+            if (N < 0) {
+                for (int q = 0; q < 8; q++) t->xt[(6 * b + d) * 8 + q] = -2;
+                continue;
+            }
             int a = d >> 1, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
             const int tf[4] = {2 * t1, 2 * t1 + 1, 2 * t2, 2 * t2 + 1};
             for (int q = 0; q < 4; q++) {
@@ -275,6 +343,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
                 t->xt[((6 * b + d) * 4 + q) * 2 + 1] = t->cfslot[6 * (int64_t)N + tf[q]];
             }
         }
+    });
     // per-level lists of refined and leaf boxes
     t->refined.clear();
     t->leaf.clear();

@@ -78,6 +78,31 @@ def test_tables_match_oracle(name):
     assert np.array_equal(ls, o.level_start)
 
 
+@pytest.mark.parametrize("order", ["shuffled", "canonical"])
+def test_tables_match_oracle_on_a_large_tree(order):
+    """41,545 boxes (uniform level 6 plus a refined 8^3 block of it): the
+    table loops run on several host threads at this size, and canonical
+    input skips the sort."""
+    bl = refine_boxes_explicit(6, [(6, i, j, k) for i in range(12, 20) for j in range(20, 28)
+                                   for k in range(8, 16)])
+    if order == "shuffled":
+        bl = bl.shuffled(5)
+    else:
+        h = M.mg_tree_create(M.make_domain(), bl.level, bl.ijk, bl.tree)
+        try:
+            perm = M.mg_tree_index(h, M.MG_IDX_ORDER, len(bl.level)).reshape(-1)
+        finally:
+            M.mg_tree_destroy(h)
+        bl = BoxList(bl.level[perm], bl.ijk[perm], bl.tree[perm])
+    g = M.Tree(bl.level, bl.ijk, bl.tree, bind=False)
+    assert g.n == 41545
+    o = O.OracleTree(bl.level, bl.ijk, bl.tree)
+    for what in range(8):
+        assert np.array_equal(g.index(what), o.index(what)), what
+    if order == "canonical":
+        assert np.array_equal(g.index(M.MG_IDX_ORDER).reshape(-1), np.arange(g.n))
+
+
 def test_tables_match_brute_force():
     bl = forest().shuffled(5)
     g = M.Tree(bl.level, bl.ijk, bl.tree, bind=False)
