@@ -1,9 +1,11 @@
 // Internal state of an mg_tree: host tables built by tree.cpp, device views
 // carved out of the caller's workspace by mg_api.hip.
 #pragma once
+#include <algorithm>
 #include <cstdint>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mg.h"
@@ -15,6 +17,25 @@ constexpr int kCells = 512;      // cells per box
 constexpr int kHalf = 256;       // cells of one colour per box
 
 void set_error(const std::string &msg);
+
+// f(lo, hi) over [0, n) in contiguous pieces on up to 16 host threads; one
+// piece (the calling thread) below 16384 items per thread
+template <typename F> void parallel_for(int64_t n, F f) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t nt = std::min<int64_t>({(int64_t)(hw ? hw : 1), (int64_t)16, std::max<int64_t>(1, n / 16384)});
+    if (nt <= 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    int64_t per = (n + nt - 1) / nt;
+    std::vector<std::thread> th;
+    for (int64_t q = 1; q < nt; q++) {
+        int64_t lo = q * per, hi = std::min(n, lo + per);
+        if (lo < hi) th.emplace_back(f, lo, hi);
+    }
+    f((int64_t)0, std::min(n, per));
+    for (auto &x : th) x.join();
+}
 
 // Host array of a trivially copyable type that is not value-initialised:
 // the large index tables are filled by parallel loops that write every

@@ -45,7 +45,9 @@ int regrid_plan(const mg_tree *t, const double *sc, double c3, double deref, dou
                 std::vector<int32_t> &level, std::vector<int32_t> &ijk, std::vector<int32_t> &tree) {
     const int64_t n = t->n;
     std::vector<char> leaf(n), refine(n, 0), drop(n, 0);
-    for (int64_t b = 0; b < n; b++) leaf[b] = t->child[8 * b] < 0;
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t b = lo; b < hi; b++) leaf[b] = t->child[8 * b] < 0;
+    });
     // near[b] (leaves): the largest score over the cells of b and the cells
     // of same-level leaf neighbours within 3 cells of b; scores[b][r] is the
     // largest |b| h^2 over the cells of b in region r = (sx+1) + 3 (sy+1) +
@@ -53,21 +55,26 @@ int regrid_plan(const mg_tree *t, const double *sc, double c3, double deref, dou
     // the cells of neighbour b + o within 3 cells of b form its region -o,
     // i.e. 26 - o.  Scores are >= 0, so a missing neighbour reads b's own.
     std::vector<double> near(n, 0.0);
-    for (int64_t b = 0; b < n; b++) {
-        if (!leaf[b]) continue;
-        const int32_t *nb = &t->n27[27 * b];
-        double m = sc[27 * b + 13];
-        for (int o = 0; o < 27; o++) {
-            int64_t N = nb[o];
-            bool use = N >= 0 && leaf[N >= 0 ? N : b];
-            m = std::max(m, sc[use ? 27 * N + (26 - o) : 27 * b + 13]);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t b = lo; b < hi; b++) {
+            if (!leaf[b]) continue;
+            const int32_t *nb = &t->n27[27 * b];
+            double m = sc[27 * b + 13];
+            for (int o = 0; o < 27; o++) {
+                int64_t N = nb[o];
+                bool use = N >= 0 && leaf[N >= 0 ? N : b];
+                m = std::max(m, sc[use ? 27 * N + (26 - o) : 27 * b + 13]);
+            }
+            near[b] = m;
         }
-        near[b] = m;
-    }
-    for (int64_t b = 0; b < n; b++)
-        if (leaf[b] && t->lev[b] < max_level && near[b] > c3) refine[b] = 1;
+    });
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t b = lo; b < hi; b++)
+            if (leaf[b] && t->lev[b] < max_level && near[b] > c3) refine[b] = 1;
+    });
     const double thr_d = deref * c3;
-    for (int64_t p = 0; p < n; p++) {
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t p = lo; p < hi; p++) {
         if (leaf[p] || !(t->dom.len / (8.0 * (double)(1 << t->lev[p])) < h_deref)) continue;
         bool ok = true;
         for (int q = 0; q < 8 && ok; q++) {
@@ -86,15 +93,22 @@ int regrid_plan(const mg_tree *t, const double *sc, double c3, double deref, dou
         }
         drop[p] = ok;
     }
+    });
     // the kept boxes, in canonical order (so their keys are sorted); they
     // satisfy 2:1 nesting among themselves: the tree did, and a removal is
     // only allowed where no box two levels finer touches the new leaf, so
     // only added boxes (and what they force) need the nesting check
+    std::vector<uint64_t> all(n);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t b = lo; b < hi; b++)
+            all[b] = (t->lev[b] >= 2 && drop[t->parent[b]])
+                         ? ~(uint64_t)0
+                         : key(t->tid[b], t->lev[b], t->ijk[3 * b], t->ijk[3 * b + 1], t->ijk[3 * b + 2]);
+    });
     std::vector<uint64_t> kept;
     kept.reserve(n);
     for (int64_t b = 0; b < n; b++)
-        if (!(t->lev[b] >= 2 && drop[t->parent[b]]))
-            kept.push_back(key(t->tid[b], t->lev[b], t->ijk[3 * b], t->ijk[3 * b + 1], t->ijk[3 * b + 2]));
+        if (all[b] != ~(uint64_t)0) kept.push_back(all[b]);
     if (!std::is_sorted(kept.begin(), kept.end())) std::sort(kept.begin(), kept.end());
     std::unordered_set<uint64_t> added;
     std::vector<uint64_t> work;
@@ -143,14 +157,16 @@ int regrid_plan(const mg_tree *t, const double *sc, double c3, double deref, dou
     level.resize(keys.size());
     tree.resize(keys.size());
     ijk.resize(3 * keys.size());
-    for (size_t q = 0; q < keys.size(); q++) {
-        uint64_t kb = keys[q];
-        level[q] = (int32_t)(kb >> 58);
-        tree[q] = (int32_t)((kb >> 42) & 0xffff);
-        ijk[3 * q] = compact3(kb, 0);
-        ijk[3 * q + 1] = compact3(kb, 1);
-        ijk[3 * q + 2] = compact3(kb, 2);
-    }
+    parallel_for((int64_t)keys.size(), [&](int64_t lo, int64_t hi) {
+        for (int64_t q = lo; q < hi; q++) {
+            uint64_t kb = keys[q];
+            level[q] = (int32_t)(kb >> 58);
+            tree[q] = (int32_t)((kb >> 42) & 0xffff);
+            ijk[3 * q] = compact3(kb, 0);
+            ijk[3 * q + 1] = compact3(kb, 1);
+            ijk[3 * q + 2] = compact3(kb, 2);
+        }
+    });
     return MG_OK;
 }
 

@@ -38,25 +38,6 @@ uint64_t morton(int32_t i, int32_t j, int32_t k) {
 
 namespace {
 
-// f(lo, hi) over [0, n) in contiguous pieces on up to 16 host threads; one
-// piece (the calling thread) below 16384 items per thread
-template <typename F> void parallel_for(int64_t n, F f) {
-    unsigned hw = std::thread::hardware_concurrency();
-    int64_t nt = std::min<int64_t>({(int64_t)(hw ? hw : 1), (int64_t)16, std::max<int64_t>(1, n / 16384)});
-    if (nt <= 1) {
-        f((int64_t)0, n);
-        return;
-    }
-    int64_t per = (n + nt - 1) / nt;
-    std::vector<std::thread> th;
-    for (int64_t q = 1; q < nt; q++) {
-        int64_t lo = q * per, hi = std::min(n, lo + per);
-        if (lo < hi) th.emplace_back(f, lo, hi);
-    }
-    f((int64_t)0, std::min(n, per));
-    for (auto &x : th) x.join();
-}
-
 // smallest box index reported by any thread (-1: none)
 struct FirstBad {
     std::atomic<int64_t> v{-1};
