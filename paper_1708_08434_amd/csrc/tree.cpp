@@ -38,6 +38,36 @@ uint64_t morton(int32_t i, int32_t j, int32_t k) {
 
 namespace {
 
+// Sorts keys in (level, tree, Morton) order: an LSD radix sort of the packed
+// 62-bit key level << 58 | tree << 42 | Morton (four 16-bit digits).
+template <typename K> void sort_keys(std::vector<K> &keys) {
+    const size_t n = keys.size();
+    std::vector<uint64_t> a(n), b(n);
+    std::vector<int32_t> ia(n), ib(n);
+    for (size_t q = 0; q < n; q++) {
+        a[q] = ((uint64_t)keys[q].level << 58) | ((uint64_t)keys[q].tree << 42) | keys[q].m;
+        ia[q] = (int32_t)q;
+    }
+    std::vector<uint32_t> cnt(65537);
+    for (int pass = 0; pass < 4; pass++) {
+        int sh = 16 * pass;
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        for (size_t q = 0; q < n; q++) cnt[((a[q] >> sh) & 0xffff) + 1]++;
+        if (cnt[1] == n) continue;  // every key has this digit 0
+        for (int d = 0; d < 65536; d++) cnt[d + 1] += cnt[d];
+        for (size_t q = 0; q < n; q++) {
+            uint32_t at = cnt[(a[q] >> sh) & 0xffff]++;
+            b[at] = a[q];
+            ib[at] = ia[q];
+        }
+        a.swap(b);
+        ia.swap(ib);
+    }
+    std::vector<K> out(n);
+    for (size_t q = 0; q < n; q++) out[q] = keys[ia[q]];
+    keys.swap(out);
+}
+
 // smallest box index reported by any thread (-1: none)
 struct FirstBad {
     std::atomic<int64_t> v{-1};
@@ -99,7 +129,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
         ntree = std::max(ntree, tr + 1);
         keys[b] = Key{l, tr, morton(i, j, k), (int32_t)b};
     }
-    if (!std::is_sorted(keys.begin(), keys.end())) std::sort(keys.begin(), keys.end());
+    if (!std::is_sorted(keys.begin(), keys.end())) sort_keys(keys);
     for (int64_t b = 1; b < n; b++)
         if (keys[b].same(keys[b - 1])) {
             snprintf(g_buf, sizeof g_buf, "boxes %d and %d are duplicates", keys[b - 1].src, keys[b].src);
