@@ -306,8 +306,9 @@ def regrid_leg(w, args, sched64):
     """Mesh adaptation as the streamer moves (paper section 2.5).  The
     benchmark tree is refined geometrically around the channel, more finely
     than its charge asks for, so it is first adapted to the charge (an
-    untimed regrid step with c3 = 1e-3 of the largest refinement score: every
-    cell whose |b| h^2 exceeds 0.1% of the peak is refined).  Then the head
+    untimed regrid step with c3 = 0.1 of the largest leaf-box score: leaf
+    cells whose |b| h^2 exceeds 10% of the leaf peak keep or get the finest
+    level).  Then the head
     moves down 2.5e-4 (10 um of the paper's 40 mm domain, a quarter of a
     finest cell) per field solve, each field solve runs two warm-started
     V-cycles, and every 4th solve is preceded by a timed regrid step: GPU
@@ -333,7 +334,8 @@ def regrid_leg(w, args, sched64):
     g0 = M.Tree.from_workload(w, device="cuda:0")
     charge(g0, 0)
     sc = g0.refine_scores()
-    c3, max_level = 1e-3 * float(sc.max()), g0.nlev
+    leaf = g0.leaf_mask()
+    c3, max_level = 0.1 * float(sc[leaf, 13].max()), g0.nlev
     g = tree(*M.mg_regrid_plan(g0.h, sc, c3, deref, max_level))
     bench_boxes, adapted_boxes = g0.n, g.n
     del g0

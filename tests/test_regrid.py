@@ -278,3 +278,50 @@ def test_gpu_regrid_step_matches_the_oracle():
     print("after 2 V-cycles: rel", sg["rel"], so["rel"], "phi err", err, flush=True)
     np.testing.assert_allclose(sg["hist"], so["hist"], rtol=1e-5)
     assert err <= 1e-10
+
+
+@pytest.mark.gpu
+def test_gpu_regrid_full_size_matches_the_oracle():
+    """The benchmark tree (10,825 boxes) with its streamer head moved down by
+    0.01: GPU scores equal numpy's, the plan (c3 = 0.3 of the largest leaf
+    score, one level deeper allowed) both refines and derefines, the GPU
+    transfer equals the oracle's, and two warm-started V-cycles on the new
+    tree agree with the oracle's."""
+    from workloads import c2, c2_head_sequence
+    w = c2()
+    g = M.Tree.from_workload(w)
+    o = O.OracleTree.from_workload(w)
+    g.set_rhs_from(w)
+    o.set_rhs_from(w)
+    g.fmg_solve()
+    o.fmg_solve()
+    lv, ij = g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK)
+    b = c2_head_sequence(lv, ij, 1, 0.0, z_head=0.61)[0]
+    g.set_field(M.MG_FIELD_RHS, b)
+    sc = g.refine_scores()
+    assert np.array_equal(sc, numpy_scores(lv, ij, b))
+    leaf = g.leaf_mask()
+    nl, nij, ntr = M.mg_regrid_plan(g.h, sc, 0.3 * float(sc[leaf, 13].max()), 0.125, g.nlev + 1)
+    old = {(int(l), *map(int, c)) for l, c in zip(lv, ij)}
+    new = {(int(l), *map(int, c)) for l, c in zip(nl, nij)}
+    assert new - old and old - new
+    g2 = M.Tree(nl, nij, ntr, w.lo, w.length, w.bc_type, w.bc_val)
+    o2 = O.OracleTree(nl, nij, ntr, w.lo, w.length, w.bc_type, w.bc_val)
+    assert np.array_equal(g2.index(M.MG_IDX_ORDER), o2.index(O.IDX_ORDER))
+    M.mg_transfer(g.h, g2.h)
+    o.set_field(O.PHI, g.get_field(M.MG_FIELD_PHI))
+    o2.transfer_from(o)
+    pg, po = g2.get_field(M.MG_FIELD_PHI), o2.get_field(O.PHI)
+    print("regrid:", g.n, "->", g2.n, "boxes; transfer max diff", np.abs(pg - po).max(), flush=True)
+    assert np.abs(pg - po).max() <= 1e-13 * np.abs(po).max()
+    lv2, ij2 = g2.index(M.MG_IDX_LEVEL), g2.index(M.MG_IDX_IJK)
+    b2 = c2_head_sequence(lv2, ij2, 1, 0.0, z_head=0.61)[0]
+    g2.set_field(M.MG_FIELD_RHS, b2)
+    o2.set_field(O.RHS, b2)
+    sg, so = g2.vcycles(2), o2.vcycles(2)
+    leaf = o2.leaf_mask()
+    pg, po = g2.get_field(M.MG_FIELD_PHI), o2.get_field(O.PHI)
+    err = np.linalg.norm((pg - po)[leaf]) / np.linalg.norm(po[leaf])
+    print("after 2 V-cycles: rel", sg["rel"], so["rel"], "phi err", err, flush=True)
+    np.testing.assert_allclose(sg["hist"], so["hist"], rtol=1e-5)
+    assert err <= 1e-10
