@@ -49,8 +49,13 @@ void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, 
                  int colour, int variant, hipStream_t s);
 // One full sweep (red, then black) from src into dst (no aliasing).
 template <typename T>
-void launch_gsrb_sweep(const Geo &g, const T *src, T *dst, const T *rhs, const T *chat, int64_t b0,
-                       int64_t nb, T h2, int xcd, hipStream_t s);
+// fas = 1: also complete the FAS right-hand side L src + restricted
+// residual on the boxes with children (isleaf == 0), smooth with it and
+// store it in fasbuf; fas = 2: take those boxes' values from fasbuf and copy
+// them into rhs (the sweep after a fas = 1 sweep).  inv_h2 = 1 / h^2.
+void launch_gsrb_sweep(const Geo &g, const T *src, T *dst, T *rhs, const T *chat, int64_t b0,
+                       int64_t nb, T h2, int xcd, hipStream_t s, int fas = 0,
+                       const int32_t *isleaf = nullptr, T inv_h2 = (T)0, T *fasbuf = nullptr);
 template <typename T>
 void launch_cf_coarse(const Geo &g, const T *phi, T *chat, const int32_t *slots, int64_t s0,
                       int64_t ns, hipStream_t s);

@@ -408,26 +408,55 @@ __global__ __launch_bounds__(512) void k_gsrb_oct(Geo g, T *__restrict__ phi, co
 // neighbours' face layers.  256 threads per box; thread t owns red cell t
 // and black cell 256 + t (colour-split order), and for t < 192 face entry t:
 // face d = t / 32, position q = t % 32 in the layer.
-template <typename T>
+//
+// The first sweep after a restriction can also complete the coarse
+// right-hand side of the full approximation scheme (the values k_fas_rhs
+// writes: L src + the restricted residual, on the boxes with children):
+// fas = 1 computes it from src, which no workgroup writes, smooths with it
+// and stores it in fasbuf; the right-hand side of a refined face neighbour
+// under a recomputed red cell is formed the same way from the same inputs
+// plus that cell's old value.  fas = 2 (the next sweep) reads those values
+// from fasbuf and copies a box's own back into rhs; nothing reads rhs of a
+// box with children meanwhile, so the copy races with no read.
+template <typename T, bool FAS>
 __global__ __launch_bounds__(256) void k_gsrb_sweep(Geo g, const T *__restrict__ src,
-                                                    T *__restrict__ dst, const T *__restrict__ rhs,
+                                                    T *__restrict__ dst, T *__restrict__ rhs,
                                                     const T *__restrict__ chat, int64_t b0,
-                                                    int64_t nbx, T h2, int xcd) {
+                                                    int64_t nbx, T h2, int xcd, int fas,
+                                                    const int32_t *__restrict__ isleaf, T inv_h2,
+                                                    T *__restrict__ fasbuf) {
     // P: red part = new red values (after the red half), black part = old
     // black values.  HR: ghosts of the red face cells (old field).  D2, BH:
     // second-layer black value and right-hand side of each recomputed red
     // cell.  EG: ghosts of the recomputed cells across the neighbour's
     // tangential faces (4 edges x 4 cells per face).  HB: per black face
     // cell, the recomputed red value across a same-level face, the Dirichlet
-    // value at a domain face, or c_hat at a refinement boundary.
+    // value at a domain face, or c_hat at a refinement boundary.  With
+    // fas = 1 on a box with children: PR, the old red values, and GB, the
+    // ghosts of the black face cells; NR, the old value of each recomputed
+    // red cell of a neighbour with children.
     __shared__ T P[512], HR[192], D2[192], BH[192], EG[96], HB[192];
+    __shared__ T PR[FAS ? 256 : 1], GB[FAS ? 192 : 1], NR[FAS ? 192 : 1];
     int64_t lb = xcd ? xcd_map(blockIdx.x, nbx) : (int64_t)blockIdx.x;
     if (lb >= nbx) return;
     int64_t b = b0 + lb;
     int t = threadIdx.x;
     const FaceTab ft = face_tab(g, b);
+    if (!FAS) fas = 0;
+    const bool own_fas = fas != 0 && isleaf[b] == 0;
     T ob = src[b * 512 + 256 + t];
-    T br = rhs[b * 512 + t], bb = rhs[b * 512 + 256 + t];
+    T br, bb;
+    if (own_fas && fas == 2) {
+        br = fasbuf[b * 512 + t];
+        bb = fasbuf[b * 512 + 256 + t];
+        rhs[b * 512 + t] = br;
+        rhs[b * 512 + 256 + t] = bb;
+    } else {
+        br = rhs[b * 512 + t];
+        bb = rhs[b * 512 + 256 + t];
+    }
+    T orr = (T)0;
+    if (own_fas && fas == 1) orr = src[b * 512 + t];
     // face entry of this thread (t < 192): the black face cell (ub, v) of
     // face d, u along t1 and v along t2, at layer lx of this box
     int fd = t >> 5, fq = t & 31, fv = fq >> 2;
@@ -436,8 +465,10 @@ __global__ __launch_bounds__(256) void k_gsrb_sweep(Geo g, const T *__restrict__
     int flx = fside ? 7 : 0;
     int fub = 2 * (fq & 3) + ((flx + fv + 1) & 1);
     int fnb = t < 192 ? pick6(ft.nb, fd) : -3;
+    bool nb_fas = fas != 0 && fnb >= 0 && isleaf[fnb] == 0;
     if (t < 192) {
         gsrb_ghost<T>(g, ft, src, chat, b, 0, t, HR);
+        if (own_fas && fas == 1) gsrb_ghost<T>(g, ft, src, chat, b, 1, t, GB);
         if (fnb >= 0) {
             int c[3];
             c[ft1] = fub;
@@ -445,7 +476,12 @@ __global__ __launch_bounds__(256) void k_gsrb_sweep(Geo g, const T *__restrict__
             c[fa] = fside ? 1 : 6;  // neighbour's second layer
             D2[t] = src[(int64_t)fnb * 512 + cs_idx3(c)];
             c[fa] = fside ? 0 : 7;  // neighbour's adjacent layer: the recomputed red cell
-            BH[t] = rhs[(int64_t)fnb * 512 + cs_idx3(c)];
+            if (nb_fas && fas == 2) {
+                BH[t] = fasbuf[(int64_t)fnb * 512 + cs_idx3(c)];
+            } else {
+                BH[t] = rhs[(int64_t)fnb * 512 + cs_idx3(c)];
+                if (nb_fas) NR[t] = src[(int64_t)fnb * 512 + cs_idx3(c)];
+            }
             if (fq < 16) {
                 // edge e4 of the neighbour's layer (-t1, +t1, -t2, +t2), cell idx
                 int e4 = fq >> 2, idx = fq & 3;
@@ -466,9 +502,22 @@ __global__ __launch_bounds__(256) void k_gsrb_sweep(Geo g, const T *__restrict__
         }
     }
     P[256 + t] = ob;
+    if (own_fas && fas == 1) PR[t] = orr;
     __syncthreads();
     int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
     int row = (k * 8 + j) * 4;
+    if (own_fas && fas == 1) {  // black cell's right-hand side from the old field
+        int i = 2 * m + ((j + k + 1) & 1);
+        T xm = i > 0 ? PR[row + ((i - 1) >> 1)] : GB[0 * 32 + k * 4 + (j >> 1)];
+        T xp = i < 7 ? PR[row + ((i + 1) >> 1)] : GB[1 * 32 + k * 4 + (j >> 1)];
+        T ym = j > 0 ? PR[row - 4 + m] : GB[2 * 32 + k * 4 + m];
+        T yp = j < 7 ? PR[row + 4 + m] : GB[3 * 32 + k * 4 + m];
+        T zm = k > 0 ? PR[row - 32 + m] : GB[4 * 32 + j * 4 + m];
+        T zp = k < 7 ? PR[row + 32 + m] : GB[5 * 32 + j * 4 + m];
+        T s = xm + xp + ym + yp + zm + zp;
+        bb = (s - (T)6 * ob) * inv_h2 + bb;
+        fasbuf[b * 512 + 256 + t] = bb;
+    }
     {  // red cell (i + j + k even)
         int i = 2 * m + ((j + k) & 1);
         const T *S = P + 256;
@@ -479,6 +528,10 @@ __global__ __launch_bounds__(256) void k_gsrb_sweep(Geo g, const T *__restrict__
         T zm = k > 0 ? S[row - 32 + m] : HR[4 * 32 + j * 4 + m];
         T zp = k < 7 ? S[row + 32 + m] : HR[5 * 32 + j * 4 + m];
         T s = xm + xp + ym + yp + zm + zp;
+        if (own_fas && fas == 1) {
+            br = (s - (T)6 * orr) * inv_h2 + br;
+            fasbuf[b * 512 + t] = br;
+        }
         T nr = (s - h2 * br) * (T)kSixth;
         P[t] = nr;
         dst[b * 512 + t] = nr;
@@ -502,7 +555,9 @@ __global__ __launch_bounds__(256) void k_gsrb_sweep(Geo g, const T *__restrict__
         T ym = fa == 0 ? um : fa == 1 ? nm : vm, yp = fa == 0 ? up : fa == 1 ? np : vp;
         T zm = fa == 2 ? nm : vm, zp = fa == 2 ? np : vp;
         T s = xm + xp + ym + yp + zm + zp;
-        HB[t] = (s - h2 * BH[t]) * (T)kSixth;
+        T bh = BH[t];
+        if (nb_fas && fas == 1) bh = (s - (T)6 * NR[t]) * inv_h2 + bh;
+        HB[t] = (s - h2 * bh) * (T)kSixth;
     }
     __syncthreads();
     {  // black cell: neighbours are new red values; face ghosts as in the
@@ -1395,11 +1450,17 @@ void launch_gsrb_cpt(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t 
 }
 
 template <typename T>
-void launch_gsrb_sweep(const Geo &g, const T *src, T *dst, const T *rhs, const T *chat, int64_t b0,
-                       int64_t nb, T h2, int xcd, hipStream_t s) {
+void launch_gsrb_sweep(const Geo &g, const T *src, T *dst, T *rhs, const T *chat, int64_t b0,
+                       int64_t nb, T h2, int xcd, hipStream_t s, int fas, const int32_t *isleaf,
+                       T inv_h2, T *fasbuf) {
     if (nb <= 0) return;
     dim3 grid((unsigned)(xcd ? xcd_grid(nb) : nb));
-    hipLaunchKernelGGL(k_gsrb_sweep<T>, grid, dim3(256), 0, s, g, src, dst, rhs, chat, b0, nb, h2, xcd);
+    if (fas)
+        hipLaunchKernelGGL((k_gsrb_sweep<T, true>), grid, dim3(256), 0, s, g, src, dst, rhs, chat, b0, nb, h2,
+                           xcd, fas, isleaf, inv_h2, fasbuf);
+    else
+        hipLaunchKernelGGL((k_gsrb_sweep<T, false>), grid, dim3(256), 0, s, g, src, dst, rhs, chat, b0, nb,
+                           h2, xcd, 0, isleaf, inv_h2, fasbuf);
 }
 
 template <typename T>
@@ -1542,8 +1603,8 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
     template void launch_unpack<T>(const T *, double *, int64_t, hipStream_t);                   \
     template void launch_gsrb<T>(const Geo &, T *, const T *, const T *, int64_t, int64_t, T, int, \
                                  int, hipStream_t);                                              \
-    template void launch_gsrb_sweep<T>(const Geo &, const T *, T *, const T *, const T *, int64_t, \
-                                       int64_t, T, int, hipStream_t);                            \
+    template void launch_gsrb_sweep<T>(const Geo &, const T *, T *, T *, const T *, int64_t,       \
+                                       int64_t, T, int, hipStream_t, int, const int32_t *, T, T *); \
     template void launch_cf_coarse<T>(const Geo &, const T *, T *, const int32_t *, int64_t,     \
                                       int64_t, hipStream_t);                                     \
     template void launch_resid_restrict<T>(const Geo &, T *, T *, T *, const T *, int64_t,       \

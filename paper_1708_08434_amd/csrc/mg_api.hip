@@ -119,7 +119,13 @@ void give_event(mg_tree *t, hipEvent_t e) {
 }
 
 // ---- steps of the cycle
-template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsweep) {
+// fas_first: the level's coarse FAS right-hand side is still to be formed
+// (fas_down deferred it); the first pair of fused sweeps forms it.
+template <typename T> bool smooth_fuses_fas(const mg_tree *t, int l, int nsweep) {
+    int variant = t->sched[sizeof(T) == 4 ? 1 : 0][l];
+    return nsweep >= 2 && l >= 2 && variant >= kGsrbFusedVariant && variant < kGsrbOctVariant;
+}
+template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsweep, bool fas_first = false) {
     if (nsweep <= 0) return;
     ensure_cf(t, F, l);
     double h = hlev(t, l);
@@ -141,12 +147,14 @@ template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsw
     int it = 0;
     if (variant >= kGsrbFusedVariant && variant < kGsrbOctVariant) {
         // fused sweeps in pairs: field -> sweep buffer -> field
-        T *swp = (T *)t->d.swp;
+        T *swp = (T *)t->d.swp, *fbuf = (T *)t->d.fas;
+        T inv_h2 = (T)(1.0 / (h * h));
         for (; it + 1 < nsweep; it += 2) {
+            int f1 = fas_first && it == 0 ? 1 : 0, f2 = f1 ? 2 : 0;
             launch_gsrb_sweep<T>(F.g, F.phi, swp, F.rhs, F.chat, lbeg(t, l), lcount(t, l), h2,
-                                 variant & 1, stream_of(t));
+                                 variant & 1, stream_of(t), f1, t->d.isleaf, inv_h2, fbuf);
             launch_gsrb_sweep<T>(F.g, swp, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l), h2,
-                                 variant & 1, stream_of(t));
+                                 variant & 1, stream_of(t), f2, t->d.isleaf, inv_h2, fbuf);
             launches += 2;
         }
     }
@@ -168,7 +176,10 @@ template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsw
     dirty(F, l);
 }
 
-template <typename T> void fas_down(mg_tree *t, const Fields<T> &F, int l) {
+// defer_rhs: leave the coarse right-hand side L phi_c + r_c of the refined
+// level-(l-1) boxes to the first fused sweep of level l-1 (smooth with
+// fas_first), which forms it from the same values.
+template <typename T> void fas_down(mg_tree *t, const Fields<T> &F, int l, bool defer_rhs = false) {
     ensure_cf(t, F, l);
     double h = hlev(t, l);
     launch_resid_restrict<T>(F.g, F.phi, F.rhs, F.old, F.chat, lbeg(t, l), lcount(t, l),
@@ -176,6 +187,7 @@ template <typename T> void fas_down(mg_tree *t, const Fields<T> &F, int l) {
                              (T)(1.0 / (h * h)), stream_of(t));
     dirty(F, l - 1);
     ensure_cf(t, F, l - 1);
+    if (defer_rhs) return;
     double hc = hlev(t, l - 1);
     launch_fas_rhs<T>(F.g, F.phi, F.rhs, F.chat, t->d.refined + t->rstart[l - 1],
                       t->rstart[l] - t->rstart[l - 1], (T)(1.0 / (hc * hc)), stream_of(t));
@@ -223,9 +235,11 @@ template <typename T> void bottom(mg_tree *t, const Fields<T> &F, int nd, int nu
 template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int nd, int nu) {
     bool one = use_bottom<T>(t) && top >= 2;
     int low = one ? 3 : 2;
+    bool deferred = false;
     for (int l = top; l >= low; l--) {
-        smooth(t, F, l, nd);
-        fas_down(t, F, l);
+        smooth(t, F, l, nd, deferred);
+        deferred = l - 1 >= low && smooth_fuses_fas<T>(t, l - 1, nd);
+        fas_down(t, F, l, deferred);
     }
     if (one) {
         bottom(t, F, nd, nu, false);
@@ -838,6 +852,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.old32 = (float *)(base + t->off.old32);
     d.chat32 = (float *)(base + t->off.chat32);
     d.swp = (void *)(base + t->off.swp);
+    d.fas = (void *)(base + t->off.fas);
     if (!t->host_result) {
         int rc = hip_check(hipHostMalloc((void **)&t->host_result, 4 * t->ntree * sizeof(double)),
                            "pinned host buffer");

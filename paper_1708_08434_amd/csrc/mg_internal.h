@@ -92,6 +92,7 @@ struct DevTables {
     float *old32 = nullptr;
     float *chat32 = nullptr;
     void *swp = nullptr;         // [n][512] FP64 (or FP32): target of the fused sweeps
+    void *fas = nullptr;         // [n][512] FP64 (or FP32): FAS right-hand sides formed by a fused sweep
 };
 
 }  // namespace mg
@@ -117,7 +118,7 @@ struct mg_tree {
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
     struct { int64_t nbr, cfslot, cfq, xt, pnb, slotx, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
-             phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, swp, total; } off{};
+             phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, swp, fas, total; } off{};
     // ---- fluid model (mg_fluid_bind): caller's second workspace ----
     void *fws = nullptr;
     int32_t ntab = 0;

@@ -436,6 +436,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.old32 = take(4 * kCells * n);
     t->off.chat32 = take(4 * 64 * t->nslot);
     t->off.swp = take(8 * kCells * n);
+    t->off.fas = take(8 * kCells * n);
     t->off.total = o;
     return MG_OK;
 }
