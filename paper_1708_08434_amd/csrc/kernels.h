@@ -56,6 +56,10 @@ template <typename T>
 void launch_gsrb_sweep(const Geo &g, const T *src, T *dst, T *rhs, const T *chat, int64_t b0,
                        int64_t nb, T h2, int xcd, hipStream_t s, int fas = 0,
                        const int32_t *isleaf = nullptr, T inv_h2 = (T)0, T *fasbuf = nullptr);
+// The parent cells of every listed leaf box (level >= 2) <- mean of its
+// cells under them, in one launch (the restriction a stopping test needs).
+template <typename T>
+void launch_restrict_leaves(const Geo &g, T *phi, const int32_t *leaf, int64_t nleaf, hipStream_t s);
 template <typename T>
 void launch_cf_coarse(const Geo &g, const T *phi, T *chat, const int32_t *slots, int64_t s0,
                       int64_t ns, hipStream_t s);

@@ -1133,6 +1133,32 @@ __global__ __launch_bounds__(64) void k_restrict_phi(Geo g, T *__restrict__ phi,
     phi[p * 512 + cs_idx(ci, cj, ck)] = (T)0.125 * s;
 }
 
+// The parent cells of every leaf box of level >= 2 <- the mean of the box's
+// 8 cells under each (the arithmetic of k_restrict_phi), all levels in one
+// launch.  Under 2:1 nesting every covered cell that a residual or a c_hat
+// reads has only leaf children, so this is the restriction a stopping test
+// needs; covered cells whose children have children are left as they are.
+template <typename T>
+__global__ __launch_bounds__(64) void k_restrict_leaves(Geo g, T *__restrict__ phi,
+                                                        const int32_t *__restrict__ leaf, int64_t nleaf) {
+    int64_t q = xcd_map(blockIdx.x, nleaf);
+    if (q >= nleaf) return;
+    int64_t b = leaf[q];
+    if (g.ijk[b * 4 + 3] < 2) return;
+    int t = threadIdx.x, pi = t & 3, pj = (t >> 2) & 3, pk = t >> 4;
+    T s = 0;
+#pragma unroll
+    for (int dk = 0; dk < 2; dk++)
+#pragma unroll
+        for (int dj = 0; dj < 2; dj++)
+#pragma unroll
+            for (int di = 0; di < 2; di++) s += phi[b * 512 + cs_idx(2 * pi + di, 2 * pj + dj, 2 * pk + dk)];
+    int64_t p = g.parent[b];
+    int ci = 4 * (g.ijk[b * 4] & 1) + pi, cj = 4 * (g.ijk[b * 4 + 1] & 1) + pj,
+        ck = 4 * (g.ijk[b * 4 + 2] & 1) + pk;
+    phi[p * 512 + cs_idx(ci, cj, ck)] = (T)0.125 * s;
+}
+
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
 // Leaf residual norms: per listed box, sum of r^2 h^3 and max |r|.  When
@@ -1544,6 +1570,12 @@ void launch_restrict_phi(const Geo &g, T *phi, int64_t b0, int64_t nb, hipStream
     if (nb <= 0) return;
     hipLaunchKernelGGL(k_restrict_phi<T>, dim3((unsigned)xcd_grid(nb)), dim3(64), 0, s, g, phi, b0, nb);
 }
+template <typename T>
+void launch_restrict_leaves(const Geo &g, T *phi, const int32_t *leaf, int64_t nleaf, hipStream_t s) {
+    if (nleaf <= 0) return;
+    hipLaunchKernelGGL(k_restrict_leaves<T>, dim3((unsigned)xcd_grid(nleaf)), dim3(64), 0, s, g, phi, leaf,
+                       nleaf);
+}
 void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const double *chat,
                        const int32_t *leaf, int64_t nleaf, double *partial, float *r_out,
                        hipStream_t s) {
@@ -1605,6 +1637,7 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
                                  int, hipStream_t);                                              \
     template void launch_gsrb_sweep<T>(const Geo &, const T *, T *, T *, const T *, int64_t,       \
                                        int64_t, T, int, hipStream_t, int, const int32_t *, T, T *); \
+    template void launch_restrict_leaves<T>(const Geo &, T *, const int32_t *, int64_t, hipStream_t); \
     template void launch_cf_coarse<T>(const Geo &, const T *, T *, const int32_t *, int64_t,     \
                                       int64_t, hipStream_t);                                     \
     template void launch_resid_restrict<T>(const Geo &, T *, T *, T *, const T *, int64_t,       \

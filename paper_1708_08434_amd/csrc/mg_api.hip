@@ -216,6 +216,16 @@ template <typename T> void restrict_all(mg_tree *t, const Fields<T> &F) {
     }
 }
 
+// Before a stopping test: every leaf box's parent cells <- the mean of their
+// children, in one launch.  A residual or c_hat reads covered cells only next
+// to leaf cells of their own level, and under 2:1 nesting those have only
+// leaf children, so the test sees exactly the values of restrict_all; the
+// next cycle's down-leg restricts every level before it reads it.
+template <typename T> void restrict_for_check(mg_tree *t, const Fields<T> &F) {
+    launch_restrict_leaves<T>(F.g, F.phi, t->d.leaf, t->nleaf, stream_of(t));
+    for (int l = t->nlev; l >= 2; l--) dirty(F, l - 1);
+}
+
 // Levels 1 and 2 as one launch (one workgroup per tree)?
 template <typename T> bool use_bottom(const mg_tree *t) {
     return t->bottom_ok && t->sched[sizeof(T) == 4 ? 1 : 0][1] != 0;
@@ -335,12 +345,12 @@ void run_body(mg_tree *t, int seq, int nd, int nu) {
         dirty_all(F);
         norms_launch(t, 2 * t->ntree, nullptr);
         fmg_pass(t, F, nd, nu);
-        restrict_all(t, F);
+        restrict_for_check(t, F);
         norms_launch(t, 0, nullptr);
         break;
     case mg_tree::SEQ_VCHECK:
         vcycle(t, F, t->nlev, nd, nu);
-        restrict_all(t, F);
+        restrict_for_check(t, F);
         norms_launch(t, 0, nullptr);
         break;
     case mg_tree::SEQ_MIX_START:
@@ -356,7 +366,7 @@ void run_body(mg_tree *t, int seq, int nd, int nu) {
         else vcycle(t, E, t->nlev, nd, nu);
         launch_ir_update(F.phi, E.phi, 512 * t->n, stream_of(t));
         dirty_all(F);
-        restrict_all(t, F);
+        restrict_for_check(t, F);
         norms_launch(t, 0, E.rhs);
         break;
     }
@@ -462,7 +472,7 @@ int record_check(mg_tree *t, mg_solve_stats *s, int k) {
 }
 
 int check_and_record(mg_tree *t, mg_solve_stats *s, int k) {
-    restrict_all(t, f64(t));
+    restrict_for_check(t, f64(t));
     int rc = norms(t);
     if (rc) return rc;
     return record_check(t, s, k);
@@ -965,6 +975,7 @@ int mg_fmg_solve(mg_tree *t, const mg_solve_opts *o, mg_solve_stats *st) {
             return (int)(k == 1 ? mg_tree::SEQ_MIX_FMG : mg_tree::SEQ_MIX_V);
         });
     }
+    if (!rc) restrict_all(t, f64(t));  // every covered cell: the mean of its children
     if (!rc) rc = hip_check(hipGetLastError(), "kernel launch");
     s->t_ms = now_ms() - t0;
     return s->status = rc;
@@ -995,6 +1006,7 @@ int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *
             rc = record_check(t, s, k);
         }
     }
+    if (!rc) restrict_all(t, f64(t));  // every covered cell: the mean of its children
     if (!rc) rc = hip_check(hipGetLastError(), "kernel launch");
     s->t_ms = now_ms() - t0;
     return s->status = rc;
@@ -1764,6 +1776,7 @@ int mg_learned_solve(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes, const mg
             return s->status = MG_ENOCONV;
         }
     }
+    restrict_all(t, F);  // every covered cell: the mean of its children
     rc = hip_check(hipGetLastError(), "kernel launch");
     s->t_ms = now_ms() - t0;
     return s->status = rc;
