@@ -473,11 +473,13 @@ def test_fused_and_octet_sweeps_match_the_oracle(v):
         compare_fields(g, o, f"fused {v} op {op_g} level {lev}")
 
 
-@pytest.mark.parametrize("wname", ["uniform64", "streamer_small"])
+@pytest.mark.parametrize("wname", ["uniform64", "streamer_small", "forest"])
 def test_fused_schedule_solve_parity(wname):
     """A whole FMG solve with fused sweeps on every level matches the oracle
-    and the half-sweep solve bit for bit."""
-    w = c1() if wname == "uniform64" else streamer_small()
+    and the half-sweep solve bit for bit (on a forest too, where the fused
+    down-sweep forms the coarse right-hand side of every tree's refined
+    boxes in one launch)."""
+    w = {"uniform64": c1, "streamer_small": streamer_small, "forest": small_forest}[wname]()
     g, o = pair(w)
     g.set_rhs_from(w)
     o.set_rhs_from(w)
@@ -493,6 +495,26 @@ def test_fused_schedule_solve_parity(wname):
     say("fused solve", wname, sf["n_vcycles"], "cycles, err vs oracle", err)
     assert sf["n_vcycles"] == so["n_vcycles"] == sh["n_vcycles"]
     assert err <= SOLVE_TOL
+    assert np.array_equal(pf, ph)
+
+
+@pytest.mark.parametrize("wname", ["streamer_small", "forest"])
+def test_fused_schedule_mixed_solve_bits(wname):
+    """Mixed precision: the FP32 correction cycles with fused sweeps on every
+    level give the same refinement steps and the same FP64 potential, bit for
+    bit, as with half-sweeps."""
+    w = streamer_small() if wname == "streamer_small" else small_forest()
+    g = M.Tree.from_workload(w, device="cuda:0")
+    g.set_rhs_from(w)
+    M.mg_set_schedule(g.h, M.MG_MIXED, [1] * g.nlev)  # one-box half-sweeps
+    sh = g.fmg_solve(precision=M.MG_MIXED)
+    ph = g.get_field(M.MG_FIELD_PHI)
+    M.mg_set_schedule(g.h, M.MG_MIXED, [M.MG_GSRB_FUSED[1]] * g.nlev)
+    sf = g.fmg_solve(precision=M.MG_MIXED)
+    pf = g.get_field(M.MG_FIELD_PHI)
+    say("mixed fused", wname, sh["n_vcycles"], sf["n_vcycles"], sf["rel"])
+    assert sf["n_vcycles"] == sh["n_vcycles"]
+    assert sf["rel"] <= 1e-8
     assert np.array_equal(pf, ph)
 
 
