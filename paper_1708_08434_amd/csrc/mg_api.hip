@@ -216,13 +216,15 @@ template <typename T> void restrict_all(mg_tree *t, const Fields<T> &F) {
     }
 }
 
-// Before a stopping test: every leaf box's parent cells <- the mean of their
-// children, in one launch.  A residual or c_hat reads covered cells only next
-// to leaf cells of their own level, and under 2:1 nesting those have only
-// leaf children, so the test sees exactly the values of restrict_all; the
-// next cycle's down-leg restricts every level before it reads it.
+// Before a stopping test: parent cells <- the mean of their children, in one
+// launch over the leaf boxes of the list cleaf.  A residual or c_hat reads a
+// covered cell only next to a leaf cell of its own level, that is across the
+// parent's outer face on the child's side where the parent's neighbour is a
+// leaf box, and under 2:1 nesting such a cell has only leaf children; so the
+// test sees exactly the values of restrict_all.  The next cycle's down-leg
+// restricts every level before it reads it.
 template <typename T> void restrict_for_check(mg_tree *t, const Fields<T> &F) {
-    launch_restrict_leaves<T>(F.g, F.phi, t->d.leaf, t->nleaf, stream_of(t));
+    launch_restrict_leaves<T>(F.g, F.phi, t->d.cleaf, (int64_t)t->cleaf.size(), stream_of(t));
     for (int l = t->nlev; l >= 2; l--) dirty(F, l - 1);
 }
 
@@ -840,6 +842,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.parent = (int32_t *)(base + t->off.parent);
     d.refined = (int32_t *)(base + t->off.refined);
     d.leaf = (int32_t *)(base + t->off.leaf);
+    d.cleaf = (int32_t *)(base + t->off.cleaf);
     d.slots = (int32_t *)(base + t->off.slots);
     d.leaf_tree = (int32_t *)(base + t->off.leaf_tree);
     d.tree_off = (int32_t *)(base + t->off.tree_off);
@@ -890,6 +893,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     rc = rc ? rc : up(d.parent, t->parent.data(), t->parent.size() * 4);
     rc = rc ? rc : up(d.refined, t->refined.data(), t->refined.size() * 4);
     rc = rc ? rc : up(d.leaf, t->leaf.data(), t->leaf.size() * 4);
+    rc = rc ? rc : up(d.cleaf, t->cleaf.data(), t->cleaf.size() * 4);
     rc = rc ? rc : up(d.slots, t->slots.data(), t->slots.size() * 4);
     rc = rc ? rc : up(d.leaf_tree, t->leaf_tree.data(), t->leaf_tree.size() * 4);
     rc = rc ? rc : up(d.tree_off, t->tree_off.data(), t->tree_off.size() * 4);

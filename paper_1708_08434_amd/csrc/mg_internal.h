@@ -69,6 +69,7 @@ struct DevTables {
     int32_t *parent = nullptr;   // [n]
     int32_t *refined = nullptr;  // per-level lists of boxes with children
     int32_t *leaf = nullptr;     // per-level lists of boxes without children
+    int32_t *cleaf = nullptr;    // leaf boxes whose parent cells a stopping test reads
     int32_t *slots = nullptr;    // [nslot][2] (box, face)
     int32_t *leaf_tree = nullptr;  // leaf-list positions grouped by tree (ascending within a tree)
     int32_t *tree_off = nullptr;   // [ntree+1] offsets into leaf_tree
@@ -105,6 +106,7 @@ struct mg_tree {
     mg::RawArray<int32_t> xt;                           // [n][6][4][2] (see tree.cpp)
     int64_t lstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> refined, leaf;                 // box ids grouped by level
+    std::vector<int32_t> cleaf;                         // leaf boxes restricted before a stopping test
     int64_t rstart[mg::kMaxLevel + 2] = {0}, fstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> slots;                         // (box, face) per slot
     mg::RawArray<int32_t> n27;                          // [n][27] same-level box at ijk + o, -1, -2
@@ -117,7 +119,7 @@ struct mg_tree {
     mg_domain dom{};
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
-    struct { int64_t nbr, cfslot, cfq, xt, pnb, slotx, ijk, parent, refined, leaf, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
+    struct { int64_t nbr, cfslot, cfq, xt, pnb, slotx, ijk, parent, refined, leaf, cleaf, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
              phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, swp, fas, total; } off{};
     // ---- fluid model (mg_fluid_bind): caller's second workspace ----
     void *fws = nullptr;

@@ -366,6 +366,24 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
             (t->child[8 * b] >= 0 ? t->refined : t->leaf).push_back((int32_t)b);
     }
     t->nleaf = (int64_t)t->leaf.size();
+    // leaf boxes whose parent cells a stopping test can read: a residual or a
+    // c_hat reads a covered cell only next to a leaf cell of its own level,
+    // so only across the parent's outer faces on the child's side, and only
+    // where the parent's neighbour there is a leaf box (a refined box has
+    // all 8 children and no refinement-boundary face)
+    t->cleaf.clear();
+    for (int64_t q = 0; q < t->nleaf; q++) {
+        int64_t b = t->leaf[q];
+        if (t->lev[b] < 2) continue;
+        int64_t p = t->parent[b];
+        for (int a = 0; a < 3; a++) {
+            int32_t nb = t->nbr[6 * p + 2 * a + (t->ijk[3 * b + a] & 1)];
+            if (nb >= 0 && t->child[8 * (int64_t)nb] < 0) {
+                t->cleaf.push_back((int32_t)b);
+                break;
+            }
+        }
+    }
     // leaf-list positions grouped by tree, ascending inside each tree (the
     // order of the per-tree norm reduction)
     t->tree_off.assign(ntree + 1, 0);
@@ -413,6 +431,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.parent = take(4 * n);
     t->off.refined = take(4 * (int64_t)t->refined.size());
     t->off.leaf = take(4 * t->nleaf);
+    t->off.cleaf = take(4 * (int64_t)t->cleaf.size());
     t->off.slots = take(8 * t->nslot);
     t->off.slotx = take(32 * t->nslot);
     t->off.leaf_tree = take(4 * t->nleaf);

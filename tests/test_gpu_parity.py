@@ -153,8 +153,14 @@ def test_warm_vcycles_parity():
     assert np.linalg.norm((pg - po)[leaf]) / np.linalg.norm(po[leaf]) <= SOLVE_TOL
 
 
-def test_residual_matches_oracle():
-    w = streamer_small()
+@pytest.mark.parametrize("wname", ["streamer_small", "forest", "streamer"])
+def test_residual_matches_oracle(wname):
+    """Norms of the residual of a random field whose covered cells are not the
+    means of their children: the library restricts, before a stopping test,
+    only the covered cells next to leaf cells of their own level; the oracle
+    restricts every level.  On a forest and on the full-size benchmark tree
+    too."""
+    w = {"streamer_small": streamer_small, "forest": small_forest, "streamer": c2}[wname]()
     g, o = pair(w)
     seed_fields(g, o, 5)
     rg, ro = g.residual(), o.residual()
