@@ -478,6 +478,10 @@ def main():
                     help="time steps of the fluid leg (paper setup, SI units); 0 skips it")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only the launches that rocprofv3 --pmc counts for the traffic summary")
+    ap.add_argument("--schedule", default=None,
+                    help="fixed Gauss-Seidel launch variant per level instead of the autotuner: "
+                         "FP64 list, optionally '/' and the FP32 list, e.g. 3,7,7,1,7,7,1,11/3,1,7,1,7,7,1,9 "
+                         "(reproduces a tuned run's launches, e.g. under a profiler)")
     ap.add_argument("--workload", default="streamer",
                     choices=["streamer", "forest", "branched", "two_streamers", "paper_setup"],
                     help="streamer: base 64^3 + 4 levels, 4.8e6 cells (default); forest: 128 "
@@ -504,8 +508,20 @@ def main():
     g = M.Tree.from_workload(w, device="cuda:0")
     g.set_rhs_from(w)
     torch.cuda.synchronize()
-    sched64, _ = autotune.tune(g, M.MG_FP64)
-    sched32, _ = autotune.tune(g, M.MG_MIXED)
+    if args.schedule:
+        parts = [[int(v) for v in p.split(",")] for p in args.schedule.split("/")]
+        if any(len(p) != g.nlev or not all(0 <= v < M.MG_GSRB_VARIANTS for v in p) for p in parts):
+            raise SystemExit(f"--schedule: {g.nlev} variants in 0..{M.MG_GSRB_VARIANTS - 1} per list")
+        sched64 = parts[0]
+        M.mg_set_schedule(g.h, M.MG_FP64, sched64)
+        if len(parts) > 1:
+            sched32 = parts[1]
+            M.mg_set_schedule(g.h, M.MG_MIXED, sched32)
+        else:
+            sched32, _ = autotune.tune(g, M.MG_MIXED)
+    else:
+        sched64, _ = autotune.tune(g, M.MG_FP64)
+        sched32, _ = autotune.tune(g, M.MG_MIXED)
     for _ in range(args.warmup):
         g.fmg_solve()
     # timed region 1: the solve as shipped (recorded graphs replayed)

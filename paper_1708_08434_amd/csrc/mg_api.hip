@@ -1391,6 +1391,13 @@ int mg_tree_residuals(const mg_tree *t, double *rel) {
 }
 
 int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule) {
+    // Near-ties go to the simpler launch: among the variants within kTuneTie
+    // of the fastest, the lowest kernel family (v >> 1) wins, and within a
+    // family the XCD-aware mapping (fewer HBM bytes).  Without it the choice
+    // between variants a few tenths of a microsecond apart flips from run to
+    // run on timing noise.
+    constexpr double kTuneTie = 0.015;
+    auto tune_rank = [](int v) { return 2 * (v >> 1) + ((v & 1) ? 0 : 1); };
     int rc = require_bound(t);
     if (rc) return rc;
     if ((precision != MG_FP64 && precision != MG_MIXED) || reps < 2 || reps > 1000 || (reps & 1)) {
@@ -1415,7 +1422,7 @@ int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule) {
     if (schedule) schedule[0] = t->sched[fp32 ? 1 : 0][1];
     for (int l = 2; l <= t->nlev && !rc; l++) {
         double h = hlev(t, l), best = 1e30;
-        int pick = kGsrbDefault;
+        double tv[kGsrbVariants];
         for (int v = 0; v < kGsrbVariants && !rc; v++) {
             // reps half-sweeps, or reps/2 fused sweeps (the same work)
             auto sweeps = [&]() {
@@ -1449,11 +1456,13 @@ int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule) {
             if (!rc) rc = hip_check(hipEventSynchronize(e1), "event sync");
             float ms = 0.0f;
             if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
-            if (!rc && ms < best) {
-                best = ms;
-                pick = v;
-            }
+            tv[v] = ms;
+            if (!rc && ms < best) best = ms;
         }
+        int pick = -1;
+        for (int v = 0; v < kGsrbVariants && !rc; v++)
+            if (tv[v] <= best * (1.0 + kTuneTie) && (pick < 0 || tune_rank(v) < tune_rank(pick))) pick = v;
+        if (pick < 0) pick = kGsrbDefault;
         t->sched[fp32 ? 1 : 0][l] = pick;
         if (schedule) schedule[l - 1] = pick;
     }
