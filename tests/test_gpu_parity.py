@@ -557,6 +557,32 @@ def mixed_forest_boxes():
     return BoxList.concat([a, b, c])
 
 
+@pytest.mark.parametrize("top", [1, 2])
+@pytest.mark.parametrize("prec", [M.MG_FP64, M.MG_MIXED], ids=["fp64", "mixed"])
+def test_degenerate_trees_solve_like_the_oracle(top, prec):
+    """The smallest trees: a single root box (the FMG pass is the exact root
+    solve) and a uniform two-level tree (levels 1-2 only, one launch per
+    cycle), with Dirichlet data on five faces and a Neumann face."""
+    from workloads.octree import uniform_boxes
+    bl = uniform_boxes(top)
+    bct, bcv = (0, 0, 1, 0, 0, 0), (0.3, -0.2, 0.0, 0.1, 0.0, 1.0)
+    g = M.Tree(bl.level, bl.ijk, bl.tree, bc_type=bct, bc_val=bcv)
+    o = O.OracleTree(bl.level, bl.ijk, bl.tree, bc_type=bct, bc_val=bcv)
+    rhs = np.random.default_rng(17 + top).standard_normal((g.n, 8, 8, 8)) * 50.0
+    g.set_field(M.MG_FIELD_RHS, rhs)
+    o.set_field(O.RHS, rhs)
+    sg = g.fmg_solve(precision=prec)
+    so = o.fmg_solve()
+    leaf = o.leaf_mask()
+    pg, po = g.get_field(M.MG_FIELD_PHI), o.get_field(O.PHI)
+    err = np.linalg.norm((pg - po)[leaf]) / np.linalg.norm(po[leaf])
+    say("degenerate", top, "levels", g.n, "boxes", sg["n_vcycles"], so["n_vcycles"], sg["rel"], "err", err)
+    assert sg["rel"] <= 1e-8
+    if prec == M.MG_FP64:
+        assert sg["n_vcycles"] == so["n_vcycles"]
+    assert err <= SOLVE_TOL, err
+
+
 def run_both(g, fn):
     """fn(g) with levels 1-2 stepped level by level (schedule entry 0) and as
     one launch per tree; returns both results."""
