@@ -81,12 +81,15 @@ void launch_restrict_phi(const Geo &g, T *phi, int64_t b0, int64_t nb, hipStream
 // Bottom of the V-cycle (levels 1 and 2 of every tree) in one launch, one
 // workgroup per tree: smooth(2, nd), residual + restriction + FAS rhs, root
 // solve, prolongation, smooth(2, nu); fmg != 0 prepends the FMG pass's
-// restriction, root solve and prolongation.  h2, h1: cell sizes of levels 2
-// and 1; root2[t]: first level-2 box of tree t, or -1.
+// restriction, root solve and prolongation.  fas2 != 0 first completes the
+// FAS right-hand side of the level-2 boxes with children (isleaf[b] == 0),
+// rhs <- L phi + rhs, and stores it (the k_fas_rhs step after the
+// restriction from level 3).  h2, h1: cell sizes of levels 2 and 1;
+// root2[t]: first level-2 box of tree t, or -1.
 template <typename T>
 void launch_bottom(const Geo &g, T *phi, T *rhs, T *old, const double *eig, int64_t r0, int ntree,
-                   const int32_t *root2, double h2, double h1, int nd, int nu, int fmg,
-                   hipStream_t s);
+                   const int32_t *root2, double h2, double h1, int nd, int nu, int fmg, int fas2,
+                   const int32_t *isleaf, hipStream_t s);
 void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const double *chat,
                        const int32_t *leaf, int64_t nleaf, double *partial, float *r_out,
                        hipStream_t s);

@@ -904,7 +904,8 @@ __global__ __launch_bounds__(1024) void k_bottom(Geo g, T *__restrict__ phi, T *
                                                  T *__restrict__ old, const double *__restrict__ eig,
                                                  int64_t r0, const int32_t *__restrict__ root2,
                                                  T h2_2, T inv_h2_2, T inv_h2_1, double h1, int nd,
-                                                 int nu, int fmg) {
+                                                 int nu, int fmg, int fas2,
+                                                 const int32_t *__restrict__ isleaf) {
     // F2, B2: level-2 field and right-hand side; GB: 2 g on the six faces of
     // the 16^3 grid; F1, B1, O1: the root's phi, rhs, old; W: the level-2
     // residual, then the root solve's X and Y, then the root correction
@@ -951,6 +952,26 @@ __global__ __launch_bounds__(1024) void k_bottom(Geo g, T *__restrict__ phi, T *
         }
     }
     __syncthreads();
+    // FAS right-hand side of the level-2 boxes with children, L phi + rhs
+    // (the level-3 restriction has just written both), as k_fas_rhs forms
+    // it: same neighbour order, same domain ghosts; stored for the rest of
+    // the cycle
+    if (fas2 && has2) {
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+            int e = tid + 1024 * w, o = e >> 9, i, j, k;
+            if (isleaf[first2 + o]) continue;
+            cs_cell(e & 511, i, j, k);
+            int I = 8 * (o & 1) + i, J = 8 * ((o >> 1) & 1) + j, K = 8 * (o >> 2) + k;
+            int p = cs16(I, J, K);
+            T own = F2[p];
+            T s = bot_sum<T>(F2, GB, nm, I, J, K, own);
+            T bn = (s - (T)6 * own) * inv_h2_2 + B2[p];
+            B2[p] = bn;
+            rhs[first2 * 512 + e] = bn;
+        }
+        __syncthreads();
+    }
 
     auto half_sweep = [&](int C) __attribute__((always_inline)) {
 #pragma unroll
@@ -1560,10 +1581,11 @@ void launch_coarse(const Geo &g, T *phi, const T *rhs, const double *eig, int64_
 }
 template <typename T>
 void launch_bottom(const Geo &g, T *phi, T *rhs, T *old, const double *eig, int64_t r0, int ntree,
-                   const int32_t *root2, double h2, double h1, int nd, int nu, int fmg,
-                   hipStream_t s) {
+                   const int32_t *root2, double h2, double h1, int nd, int nu, int fmg, int fas2,
+                   const int32_t *isleaf, hipStream_t s) {
     hipLaunchKernelGGL(k_bottom<T>, dim3((unsigned)ntree), dim3(1024), 0, s, g, phi, rhs, old, eig, r0, root2,
-                       (T)(h2 * h2), (T)(1.0 / (h2 * h2)), (T)(1.0 / (h1 * h1)), h1, nd, nu, fmg);
+                       (T)(h2 * h2), (T)(1.0 / (h2 * h2)), (T)(1.0 / (h1 * h1)), h1, nd, nu, fmg, fas2,
+                       isleaf);
 }
 template <typename T>
 void launch_restrict_phi(const Geo &g, T *phi, int64_t b0, int64_t nb, hipStream_t s) {
@@ -1650,7 +1672,8 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
                                    double, hipStream_t);                                         \
     template void launch_restrict_phi<T>(const Geo &, T *, int64_t, int64_t, hipStream_t);        \
     template void launch_bottom<T>(const Geo &, T *, T *, T *, const double *, int64_t, int,     \
-                                   const int32_t *, double, double, int, int, int, hipStream_t);
+                                   const int32_t *, double, double, int, int, int, int,          \
+                                   const int32_t *, hipStream_t);
 MG_INSTANTIATE(double)
 MG_INSTANTIATE(float)
 #undef MG_INSTANTIATE

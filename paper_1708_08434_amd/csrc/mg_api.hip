@@ -237,9 +237,11 @@ template <typename T> bool use_bottom(const mg_tree *t) {
 // coarse, prolong(2), smooth(2, nu); with fmg, preceded by fas_down(2),
 // coarse, prolong(2).  Leaves the c_hat state as that sequence does (level 2
 // has no refinement-boundary faces, so it launches no c_hat pass).
-template <typename T> void bottom(mg_tree *t, const Fields<T> &F, int nd, int nu, bool fmg) {
+// fas2: the restriction from level 3 deferred level 2's FAS right-hand side
+// to this launch.
+template <typename T> void bottom(mg_tree *t, const Fields<T> &F, int nd, int nu, bool fmg, bool fas2) {
     launch_bottom<T>(F.g, F.phi, F.rhs, F.old, t->d.eig, lbeg(t, 1), t->ntree, t->d.root2, hlev(t, 2),
-                     hlev(t, 1), nd, nu, fmg ? 1 : 0, stream_of(t));
+                     hlev(t, 1), nd, nu, fmg ? 1 : 0, fas2 ? 1 : 0, t->d.isleaf, stream_of(t));
     F.cf_valid[2] = true;
     dirty(F, 2);
 }
@@ -251,10 +253,10 @@ template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int n
     for (int l = top; l >= low; l--) {
         smooth(t, F, l, nd, deferred);
         deferred = l - 1 >= low && smooth_fuses_fas<T>(t, l - 1, nd);
-        fas_down(t, F, l, deferred);
+        fas_down(t, F, l, deferred || (one && l == low));
     }
     if (one) {
-        bottom(t, F, nd, nu, false);
+        bottom(t, F, nd, nu, false, top >= low);
     } else {
         coarse(t, F);
     }
@@ -273,9 +275,9 @@ template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int 
     ensure_cf_all(t, F);
     bool one = use_bottom<T>(t);
     int low = one ? 3 : 2;
-    for (int l = t->nlev; l >= low; l--) fas_down(t, F, l);
+    for (int l = t->nlev; l >= low; l--) fas_down(t, F, l, one && l == low);
     if (one) {
-        bottom(t, F, nd, nu, true);  // fas_down(2), coarse, prolong(2), V-cycle(2)
+        bottom(t, F, nd, nu, true, t->nlev >= low);  // fas_down(2), coarse, prolong(2), V-cycle(2)
     } else {
         coarse(t, F);
     }
