@@ -458,6 +458,20 @@ def fluid_leg(args, sched64):
                       "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS}}
 
 
+def parse_schedule(text, nlev, nvariants):
+    """--schedule text: the FP64 list of launch variants per level, optionally
+    '/' and the FP32 list; each list has nlev entries in 0..nvariants-1."""
+    try:
+        parts = [[int(v) for v in p.split(",")] for p in text.split("/")]
+    except ValueError:
+        parts = None
+    if (not parts or len(parts) > 2
+            or any(len(p) != nlev or not all(0 <= v < nvariants for v in p) for p in parts)):
+        raise SystemExit(f"--schedule: one or two lists of {nlev} variants in 0..{nvariants - 1}, "
+                         f"separated by '/', got {text!r}")
+    return parts
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -509,9 +523,7 @@ def main():
     g.set_rhs_from(w)
     torch.cuda.synchronize()
     if args.schedule:
-        parts = [[int(v) for v in p.split(",")] for p in args.schedule.split("/")]
-        if any(len(p) != g.nlev or not all(0 <= v < M.MG_GSRB_VARIANTS for v in p) for p in parts):
-            raise SystemExit(f"--schedule: {g.nlev} variants in 0..{M.MG_GSRB_VARIANTS - 1} per list")
+        parts = parse_schedule(args.schedule, g.nlev, M.MG_GSRB_VARIANTS)
         sched64 = parts[0]
         M.mg_set_schedule(g.h, M.MG_FP64, sched64)
         if len(parts) > 1:

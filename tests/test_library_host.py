@@ -250,3 +250,22 @@ def test_mesh_adaptation_and_fluid_argument_checks():
         assert L.mg_refine_scores(h, x) == M.MG_ESTATE
     finally:
         M.mg_tree_destroy(h)
+
+
+def test_bench_schedule_option_and_gpu_count():
+    """bench.py --schedule: one or two lists (FP64, then FP32) of one launch
+    variant per level; anything else is refused.  --gpus above 1 is refused
+    with a message, before any GPU work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    assert bench.parse_schedule("3,7,7,11", 4, 14) == [[3, 7, 7, 11]]
+    assert bench.parse_schedule("3,7,7,11/3,7,7,9", 4, 14) == [[3, 7, 7, 11], [3, 7, 7, 9]]
+    for bad in ("3,7,7", "3,7,7,14", "3,7,7,-1", "3,7,x,1", "1,1,1,1/1,1,1,1/1,1,1,1", ""):
+        with pytest.raises(SystemExit):
+            bench.parse_schedule(bad, 4, 14)
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr), (r.returncode, r.stdout, r.stderr)
