@@ -504,8 +504,8 @@ def main():
                          "the streamer tree in the paper's SI setup (40 mm, 80 kV, Neumann sides)")
     args = ap.parse_args()
     if args.gpus != 1:
-        sys.exit("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
-                 "(see the sharding design).  Use --gpus 1.")
+        sys.exit("bench.py: measures one GPU only; the solver has no multi-GPU path "
+                 "(sharding across GPUs is a design, not code).  Use --gpus 1.")
     rank = int(os.environ.get("RANK", "0"))
 
     import torch
