@@ -160,6 +160,14 @@ typedef struct {
                             check once as HIP graphs and replay them on the
                             bound stream; 0: launch kernel by kernel.  Both
                             run the same kernels in the same order.  (1)     */
+    int32_t final_check_only; /* mg_vcycle with n_cycles > 0 in MG_FP64: 1
+                            runs the n cycles back to back and the residual
+                            check only after the last (the time step of
+                            section 2.1.2 needs no test in between); phi is
+                            the same bits as with 0, rel_hist[0 .. n-1] are
+                            NaN.  0 (default): a check before and after every
+                            cycle.  Ignored elsewhere (mixed precision needs
+                            each step's residual).                          */
 } mg_solve_opts;
 
 typedef struct {

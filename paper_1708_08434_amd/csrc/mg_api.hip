@@ -357,6 +357,14 @@ void run_body(mg_tree *t, int seq, int nd, int nu) {
         restrict_for_check(t, F);
         norms_launch(t, 0, nullptr);
         break;
+    case mg_tree::SEQ_V:
+        // a check without its norms: the next cycle starts from the state a
+        // check leaves (covered cells read by c_hat restricted, every
+        // level's c_hat computed from them), so phi is the same bits
+        vcycle(t, F, t->nlev, nd, nu);
+        restrict_for_check(t, F);
+        ensure_cf_all(t, F);
+        break;
     case mg_tree::SEQ_MIX_START:
         launch_fill<double>(F.phi, 512 * t->n, 0.0, stream_of(t));
         dirty_all(F);
@@ -427,24 +435,24 @@ int run_seq(mg_tree *t, int seq, const mg_solve_opts *o, int count) {
     int nd = o->n_down, nu = o->n_up;
     mg_tree::Graph &g = t->graphs[seq];
     bool use = o->graphs && !t->timing;
-    // Every sequence but the V-cycle check starts by zeroing the fields it
-    // uses, so c_hat validity on entry is irrelevant to it; reset it so that
-    // one recorded graph serves every entry.  The V-cycle check needs the
-    // FP64 state as it is and never touches the FP32 fields.
+    // Every sequence but the V-cycles starts by zeroing the fields it uses,
+    // so c_hat validity on entry is irrelevant to it; reset it so that one
+    // recorded graph serves every entry.  The V-cycles need the FP64 state
+    // as it is and never touch the FP32 fields.
     dirty_all(f32(t));
-    if (seq != mg_tree::SEQ_VCHECK) dirty_all(f64(t));
+    if (seq != mg_tree::SEQ_VCHECK && seq != mg_tree::SEQ_V) dirty_all(f64(t));
     if (use && !(g.exec && g.nd == nd && g.nu == nu && same_state(t, g.pre))) {
         int rc = record(t, g, seq, nd, nu);
         if (rc) return rc;
     }
     if (!use) {
         run_body(t, seq, nd, nu);
-        return read_results(t, count);
+        return count ? read_results(t, count) : MG_OK;
     }
     int rc = hip_check(hipGraphLaunch((hipGraphExec_t)g.exec, (hipStream_t)t->stream), "graph launch");
     if (rc) return rc;
     load_state(t, g.post);
-    return read_results(t, count);
+    return count ? read_results(t, count) : MG_OK;
 }
 
 // Turn the per-tree norms in host_result[0..2T) into statistics.  A forest's
@@ -519,7 +527,8 @@ int require_bound(const mg_tree *t) {
 
 int check_opts(const mg_solve_opts *o) {
     if (!o || (o->precision != MG_FP64 && o->precision != MG_MIXED) || o->n_down < 0 ||
-        o->n_up < 0 || o->max_cycles < 0 || o->max_cycles > 10000 || !(o->rel_tol >= 0)) {
+        o->n_up < 0 || o->max_cycles < 0 || o->max_cycles > 10000 || !(o->rel_tol >= 0) ||
+        (o->final_check_only != 0 && o->final_check_only != 1)) {
         set_error("invalid solver options");
         return MG_EINVAL;
     }
@@ -735,6 +744,7 @@ void mg_default_opts(mg_solve_opts *o) {
     o->max_cycles = 50;
     o->rel_tol = 1e-8;
     o->graphs = 1;
+    o->final_check_only = 0;
 }
 
 int mg_tree_create(mg_tree **out, const mg_domain *dom, int64_t n, const int32_t *level,
@@ -996,6 +1006,25 @@ int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *
     std::memset(s, 0, sizeof *s);
     double t0 = now_ms();
     if ((rc = beff_norm(t))) return s->status = rc;
+    if (o->precision == MG_FP64 && n_cycles > 0 && o->final_check_only) {
+        // n - 1 cycles with no host round trip, then the last with its check.
+        // Each cycle starts from the state the skipped check would leave
+        // (restricted covered cells, c_hat of every level), so phi is the
+        // same bits as with a check around every cycle.
+        for (int k = 0; k < n_cycles && k < 64; k++) s->rel_hist[k] = std::nan("");
+        restrict_for_check(t, f64(t));
+        ensure_cf_all(t, f64(t));
+        for (int k = 1; k < n_cycles && !rc; k++) rc = run_seq(t, mg_tree::SEQ_V, o, 0);
+        if (!rc) rc = run_seq(t, mg_tree::SEQ_VCHECK, o, 2 * t->ntree);
+        if (!rc) {
+            s->n_vcycles = n_cycles;
+            rc = record_check(t, s, n_cycles);
+        }
+        if (!rc) restrict_all(t, f64(t));  // every covered cell: the mean of its children
+        if (!rc) rc = hip_check(hipGetLastError(), "kernel launch");
+        s->t_ms = now_ms() - t0;
+        return s->status = rc;
+    }
     if ((rc = check_and_record(t, s, 0))) return s->status = rc;
     int seq = o->precision == MG_FP64 ? mg_tree::SEQ_VCHECK : mg_tree::SEQ_MIX_V;
     if (o->precision != MG_FP64) {
@@ -1256,6 +1285,7 @@ int mg_fluid_step(mg_tree *t, double *ne, double *ni, double dt, int32_t n_vcycl
     if (!rc) rc = hip_check(hipMemcpyAsync(n0i, ni, bytes, hipMemcpyDeviceToDevice, s), "fluid step copy");
     mg_solve_opts o;
     mg_default_opts(&o);
+    o.final_check_only = 1;  // the step needs the field, not the residual history
     double lim = 0.0;
     // forward Euler stage, new field, second stage averaged with the kept
     // densities, new field (the explicit trapezoidal rule)

@@ -149,7 +149,7 @@ struct mg_tree {
         int nd = -1, nu = -1;
         bool pre[2][mg::kMaxLevel + 2], post[2][mg::kMaxLevel + 2];  // c_hat validity
     };
-    enum { SEQ_FMG = 0, SEQ_VCHECK, SEQ_MIX_START, SEQ_MIX_FMG, SEQ_MIX_V, SEQ_COUNT };
+    enum { SEQ_FMG = 0, SEQ_VCHECK, SEQ_MIX_START, SEQ_MIX_FMG, SEQ_MIX_V, SEQ_V, SEQ_COUNT };
     Graph graphs[SEQ_COUNT];
     // Gauss-Seidel launch variant per level, [0] FP64, [1] FP32 (autotuner);
     // the entry of level 1 (never smoothed) selects the bottom of the cycle:

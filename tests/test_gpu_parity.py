@@ -153,6 +153,35 @@ def test_warm_vcycles_parity():
     assert np.linalg.norm((pg - po)[leaf]) / np.linalg.norm(po[leaf]) <= SOLVE_TOL
 
 
+@pytest.mark.parametrize("wname", ["streamer_small", "forest"])
+def test_final_check_only_gives_the_same_bits(wname):
+    """mg_vcycle with the residual check only after the last cycle: the same
+    phi bits, final residual and cycle count as with a check around every
+    cycle (the checks change no value a cycle reads); the skipped entries of
+    the history are NaN.  Twice in a row, so the recorded graphs are replayed."""
+    w = streamer_small() if wname == "streamer_small" else small_forest()
+    g = M.Tree.from_workload(w)
+    lv, ij = g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK)
+    rhs0 = w.rhs(lv, ij, g.index(M.MG_IDX_TREE))
+    g.set_field(M.MG_FIELD_RHS, rhs0)
+    g.fmg_solve()
+    phi0 = g.get_field(M.MG_FIELD_PHI)
+    rhs1 = rhs0 * 1.05 + np.random.default_rng(5).standard_normal(rhs0.shape) * np.abs(rhs0).max() * 1e-3
+    for rep in range(2):
+        out = []
+        for fco in (0, 1):
+            g.set_field(M.MG_FIELD_PHI, phi0)
+            g.set_field(M.MG_FIELD_RHS, rhs1)
+            st = g.vcycles(2, final_check_only=fco)
+            out.append((st, g.get_field(M.MG_FIELD_PHI)))
+        (sa, pa), (sb, pb) = out
+        say("final check only", wname, rep, sa["hist"], sb["hist"])
+        assert sa["n_vcycles"] == sb["n_vcycles"] == 2
+        assert np.array_equal(pa, pb)
+        assert sa["rel"] == sb["rel"] and sb["hist"][2] == sa["hist"][2]
+        assert np.isnan(sb["hist"][0]) and np.isnan(sb["hist"][1]) and not np.isnan(sa["hist"][1])
+
+
 @pytest.mark.parametrize("wname", ["streamer_small", "forest", "streamer"])
 def test_residual_matches_oracle(wname):
     """Norms of the residual of a random field whose covered cells are not the
