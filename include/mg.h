@@ -296,7 +296,9 @@ int mg_transfer(mg_tree *from, mg_tree *to);
  * mg_fluid_step: one time step in place: keep (ne, ni), a stage with
  *   (wa, wb) = (0, 1) into the workspace, n_vcycles warm-started V-cycles and
  *   the field, a stage with (1/2, 1/2) from that result back into (ne, ni),
- *   n_vcycles V-cycles.  phi must be the potential of (ne, ni) on entry.
+ *   n_vcycles V-cycles (no residual norms and no host round trip: phi is
+ *   the same bits as after mg_vcycle).  phi must be the potential of
+ *   (ne, ni) on entry.
  *   dt_next (host, may be NULL) = 0.9 x the bound of the second stage.
  * MG_ESTATE without a bound fluid workspace; MG_EINVAL on bad arguments.
  */

@@ -513,6 +513,21 @@ int iterate(mg_tree *t, const mg_solve_opts *o, mg_solve_stats *s, SeqOf seq_of)
     return MG_OK;
 }
 
+// n warm-started V-cycles for callers that need only the field: no residual
+// norms and no host round trip.  The first cycle starts, and every cycle
+// ends, in the state a stopping test leaves (covered cells that c_hat reads
+// restricted, every level's c_hat computed from them), and the last is
+// followed by the full restriction, so phi is the same bits as mg_vcycle's.
+int vcycles_no_stats(mg_tree *t, const mg_solve_opts *o, int n) {
+    restrict_for_check(t, f64(t));
+    ensure_cf_all(t, f64(t));
+    int rc = MG_OK;
+    for (int k = 0; k < n && !rc; k++) rc = run_seq(t, mg_tree::SEQ_V, o, 0);
+    if (!rc) restrict_all(t, f64(t));  // every covered cell: the mean of its children
+    if (!rc) rc = hip_check(hipGetLastError(), "kernel launch");
+    return rc;
+}
+
 int require_bound(const mg_tree *t) {
     if (!t) {
         set_error("null tree");
@@ -1285,16 +1300,15 @@ int mg_fluid_step(mg_tree *t, double *ne, double *ni, double dt, int32_t n_vcycl
     if (!rc) rc = hip_check(hipMemcpyAsync(n0i, ni, bytes, hipMemcpyDeviceToDevice, s), "fluid step copy");
     mg_solve_opts o;
     mg_default_opts(&o);
-    o.final_check_only = 1;  // the step needs the field, not the residual history
     double lim = 0.0;
     // forward Euler stage, new field, second stage averaged with the kept
     // densities, new field (the explicit trapezoidal rule)
     if (!rc) rc = mg_efield(t, ef, en);
     if (!rc) rc = fluid_stage(t, ef, en, ne, ni, ne, ni, dt, 0.0, 1.0, n1e, n1i, nullptr);
-    if (!rc) rc = mg_vcycle(t, &o, n_vcycles, nullptr);
+    if (!rc) rc = vcycles_no_stats(t, &o, n_vcycles);
     if (!rc) rc = mg_efield(t, ef, en);
     if (!rc) rc = fluid_stage(t, ef, en, n1e, n1i, n0e, n0i, dt, 0.5, 0.5, ne, ni, &lim);
-    if (!rc) rc = mg_vcycle(t, &o, n_vcycles, nullptr);
+    if (!rc) rc = vcycles_no_stats(t, &o, n_vcycles);
     if (!rc && dt_next) *dt_next = 0.9 * lim;
     return rc;
 }
