@@ -249,6 +249,7 @@ def time_step_leg(g, args):
     (mg_efield); a time step holds two field solves.  The right-hand sides are
     the benchmark streamer with its head moved down by dz per field solve, on
     the same tree, generated beforehand and resident in HBM."""
+    import numpy as np
     import torch
     from paper_1708_08434_amd import mg as M
     from workloads import c2_head_sequence
@@ -260,35 +261,36 @@ def time_step_leg(g, args):
     del seq
     face = torch.empty((g.n, 3, 9, 8, 8), dtype=torch.float64, device="cuda:0")
     norm = torch.empty((g.n, 8, 8, 8), dtype=torch.float64, device="cuda:0")
-    # the time step's field solves: two V-cycles, the residual check after
-    # the second only (final_check_only); the residual before each solve
-    # comes from an untimed replay with a check around every cycle
-    opts, opts_check = g.opts(final_check_only=1), g.opts()
+    # the time step's field solves: two V-cycles with no statistics (no
+    # residual norm, no host wait: mg_vcycle with stats NULL); the residuals
+    # before and after each solve come from an untimed replay with a check
+    # around every cycle, which must end on the same phi bits
+    opts = g.opts()
     M.mg_field_set(g.h, M.MG_FIELD_RHS, rhs[0].data_ptr())
     g.fmg_solve()
 
-    def field_solve(s, o):
+    def field_solve(s, stats):
         M.mg_field_set(g.h, M.MG_FIELD_RHS, rhs[s].data_ptr())
-        st = M.mg_vcycle(g.h, o, 2)
+        st = M.mg_vcycle(g.h, opts, 2, stats=stats)
         M.mg_efield(g.h, face.data_ptr(), norm.data_ptr())
         return st
     for s in (1, 2):  # warm-up (records the V-cycle graphs)
-        field_solve(s, opts)
+        field_solve(s, False)
     phi_start = g.get_field(M.MG_FIELD_PHI)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rel2 = []
     for s in range(3, nsolve + 3):
-        st = field_solve(s, opts)
-        rel2.append(st.rel_res)
+        field_solve(s, False)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    phi_end = g.get_field(M.MG_FIELD_PHI)
     g.set_field(M.MG_FIELD_PHI, phi_start)
-    rel0, rel2_check = [], []
+    rel0, rel2 = [], []
     for s in range(3, nsolve + 3):
-        st = field_solve(s, opts_check)
+        st = field_solve(s, True)
         rel0.append(st.rel_hist[0])
-        rel2_check.append(st.rel_res)
+        rel2.append(st.rel_res)
+    replay_same = bool(np.array_equal(phi_end, g.get_field(M.MG_FIELD_PHI)))
     # the field kernel alone, HIP events on the tree's stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(g.stream):
@@ -305,9 +307,9 @@ def time_step_leg(g, args):
             "leaf_cells_per_s": n_leaf * nsolve / el, "field_solves": nsolve,
             "head_shift_per_solve": dz,
             "rel_res_before_max": max(rel0), "rel_res_after_2_vcycles_max": max(rel2),
-            "checks": "after the second V-cycle only (final_check_only); the residual before "
-                      "each solve from an untimed replay with a check around every cycle",
-            "replay_same_residuals": rel2_check == rel2,
+            "checks": "none in the timed solves (no statistics requested); the residuals from "
+                      "an untimed replay with a check around every cycle",
+            "replay_same_phi": replay_same,
             "efield": {"kernel": "k_efield (face components + cell strength, all boxes)",
                        "boxes": g.n, "avg_launch_us": ef_s * 1e6,
                        "bytes_per_box": EFIELD_BYTES_PER_BOX, "achieved": gbps,

@@ -198,7 +198,9 @@ int mg_fmg_solve(mg_tree *t, const mg_solve_opts *o, mg_solve_stats *s);
 /*
  * mg_vcycle - n V-cycles warm-started from the current phi (section 2.1.2:
  * later updates of the potential reuse the previous one), then the residual
- * check.  n <= 0 iterates until rel_tol (at most max_cycles).
+ * check.  n <= 0 iterates until rel_tol (at most max_cycles).  With stats
+ * NULL, n > 0 and MG_FP64 no residual norm is computed and the host does not
+ * wait for the GPU (the time step's field solves); phi is the same bits.
  */
 int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *s);
 

@@ -1016,6 +1016,7 @@ int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *
     int rc = require_bound(t);
     if (rc) return rc;
     if ((rc = check_opts(o))) return rc;
+    if (!st && o->precision == MG_FP64 && n_cycles > 0) return vcycles_no_stats(t, o, n_cycles);
     mg_solve_stats local;
     mg_solve_stats *s = st ? st : &local;
     std::memset(s, 0, sizeof *s);

@@ -201,9 +201,11 @@ def mg_fmg_solve(h, opts, raise_on_error=True):
     return st
 
 
-def mg_vcycle(h, opts, n_cycles, raise_on_error=True):
-    st = mg_solve_stats()
-    rc = lib().mg_vcycle(h, ctypes.byref(opts), int(n_cycles), ctypes.byref(st))
+def mg_vcycle(h, opts, n_cycles, raise_on_error=True, stats=True):
+    """stats=False passes no statistics record (mg_vcycle then computes no
+    residual norm for n_cycles > 0 in FP64) and returns None."""
+    st = mg_solve_stats() if stats else None
+    rc = lib().mg_vcycle(h, ctypes.byref(opts), int(n_cycles), ctypes.byref(st) if stats else None)
     if raise_on_error:
         check(rc)
     return st

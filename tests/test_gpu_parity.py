@@ -155,10 +155,11 @@ def test_warm_vcycles_parity():
 
 @pytest.mark.parametrize("wname", ["streamer_small", "forest"])
 def test_final_check_only_gives_the_same_bits(wname):
-    """mg_vcycle with the residual check only after the last cycle: the same
-    phi bits, final residual and cycle count as with a check around every
-    cycle (the checks change no value a cycle reads); the skipped entries of
-    the history are NaN.  Twice in a row, so the recorded graphs are replayed."""
+    """mg_vcycle with the residual check only after the last cycle, and with
+    no statistics at all (no residual norm): the same phi bits, final
+    residual and cycle count as with a check around every cycle; the skipped
+    entries of the history are NaN.  Twice in a row, so the recorded graphs
+    are replayed."""
     w = streamer_small() if wname == "streamer_small" else small_forest()
     g = M.Tree.from_workload(w)
     lv, ij = g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK)
@@ -175,6 +176,10 @@ def test_final_check_only_gives_the_same_bits(wname):
             st = g.vcycles(2, final_check_only=fco)
             out.append((st, g.get_field(M.MG_FIELD_PHI)))
         (sa, pa), (sb, pb) = out
+        g.set_field(M.MG_FIELD_PHI, phi0)
+        g.set_field(M.MG_FIELD_RHS, rhs1)
+        assert M.mg_vcycle(g.h, g.opts(), 2, stats=False) is None   # no statistics: no norms
+        assert np.array_equal(g.get_field(M.MG_FIELD_PHI), pa)
         say("final check only", wname, rep, sa["hist"], sb["hist"])
         assert sa["n_vcycles"] == sb["n_vcycles"] == 2
         assert np.array_equal(pa, pb)
