@@ -1,14 +1,24 @@
-"""Benchmark: FP64 FMG solve throughput on the static streamer octree
-(base 64^3 + 4 refinement levels, ~4.8e6 leaf cells) on one MI355X.
+"""Benchmark: FP64 FMG solve throughput on one MI355X.
+
+Default workload: two interacting streamers plus Poisson background
+ionisation on an octree of base 64^3 + 7 refinement levels (effective
+8192^3, ~1.2e8 leaf cells, 11 levels), the largest single-GPU configuration.
 
 One step = one mg_fmg_solve: the FMG pass plus V(2,2) cycles until the
 relative residual is below 1e-8, residual checks included (tree creation and
-right-hand-side upload excluded).  value = leaf cells solved per second.
+right-hand-side upload excluded).  value = leaf cells solved per second over
+the K timed steps; each step is also timed on its own (the solve returns
+after its last residual check has been read back), and the median and the
+minimum are reported.
 
-Prints one JSON line with the solve throughput, the dominant kernel's
-roofline (red-black Gauss-Seidel half-sweep on the finest level, timed with
-HIP events on the library's stream), the mixed-precision solve on the same
-workload, and the oracle's CPU throughput on the same workload.
+Prints one JSON line with the solve throughput, the solve-level roofline
+(the byte model of the FMG solve against the 8 TB/s HBM peak) with the
+dominant kernel beside it (red-black Gauss-Seidel half-sweep on the level
+that moves the most bytes, timed with HIP events on the library's stream),
+the mixed-precision and learned solves on the same workload, the oracle's
+CPU throughput, and each GPU result's distance from the oracle's solution.
+The time-step, mesh-adaptation and fluid legs run on the smaller static
+streamer tree (base 64^3 + 4 levels) as secondary keys.
 
 --copy-probe BYTES adds one device-to-device copy of that many bytes (a plain
 copy kernel of known size, used to calibrate rocprofv3 traffic counters).
@@ -30,6 +40,11 @@ NORM_BYTES = 16.0          # bytes per leaf cell per residual check
 METRIC = ("cells/s per FMG solve to rel. residual 1e-8 (FP64 vs mixed vs learned); HBM GB/s")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gsrb_finest_traffic_{}.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1708_08434_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    """Progress line on stderr (the JSON result goes to stdout)."""
+    print("bench:", *a, file=sys.stderr, flush=True)
 
 
 def model_bytes(level_counts, n_leaf, k):
@@ -113,12 +128,43 @@ def traffic_probe(w, reps=8):
           flush=True)
 
 
-def cpu_baseline(w, gpu_cycles, budget_s=12.0):
+def cpu_model():
+    """The host CPU's model name from /proc/cpuinfo (None if unreadable)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def leaf_rel_l2(x, ref, leaf):
+    """Relative L2 distance of x from ref over the leaf cells."""
+    import numpy as np
+    return float(np.linalg.norm((x - ref)[leaf]) / np.linalg.norm(ref[leaf]))
+
+
+def cpu_baseline(w, rhs, order, gpu_cycles, results, small=None, budget_s=20.0):
+    """The oracle (the plain FP64 CPU multigrid of the same algorithm) on the
+    host cores, on the same tree and right-hand side.
+
+    Timed: FP64 FMG solves to a relative residual of 1e-8 on all host threads
+    (at least one; up to five while under budget_s), and one FMG solve of the
+    smaller workload `small` on one thread and on all
+    threads.  Untimed: V-cycles from the oracle's 1e-8 solution until 1e-12,
+    the converged reference against which every GPU result in `results`
+    (name -> potential in natural layout, canonical order) is stated as a
+    relative L2 distance over the leaf cells, beside its distance from the
+    oracle's own 1e-8 solution."""
+    import numpy as np
     import oracle as O
     O.build(force=False)
     threads = O.set_threads(0)
     t = O.OracleTree.from_workload(w)
-    t.set_rhs_from(w)
+    assert np.array_equal(t.index(O.IDX_ORDER), order), "oracle and library orders differ"
+    t.set_field(O.RHS, rhs)
     times, cyc = [], None
     t_start = time.perf_counter()
     while True:
@@ -127,13 +173,47 @@ def cpu_baseline(w, gpu_cycles, budget_s=12.0):
         times.append(time.perf_counter() - t0)
         cyc = st["n_vcycles"]
         el = time.perf_counter() - t_start
-        # at least 3 solves unless one solve alone takes a third of the budget
-        if len(times) >= 7 or (el >= budget_s and (len(times) >= 3 or times[-1] > budget_s / 3)):
+        if len(times) >= 5 or el + times[-1] > budget_s:
             break
     med = statistics.median(times)
-    return {"value": w.n_leaf / med, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"full workload, {len(times)} FP64 FMG solves to 1e-8 "
-                      f"({cyc} V-cycles, GPU {gpu_cycles}), median {med:.3f} s"}
+    log(f"oracle: {len(times)} solve(s), median {med:.2f} s")
+    leaf = t.leaf_mask()
+    phi8 = t.get_field(O.PHI)
+    st12 = t.vcycles(0, tol=1e-12)
+    ref = t.get_field(O.PHI)
+    log(f"oracle reference: {st12['n_vcycles']} more V-cycles, rel {st12['rel']:.2e}")
+    del t
+    acc = {"reference": f"oracle FP64 solve continued to rel. residual {st12['rel']:.2e} "
+                        f"({cyc} + {st12['n_vcycles']} V-cycles)",
+           "oracle_1e-8_vs_reference": leaf_rel_l2(phi8, ref, leaf)}
+    for name, phi in results.items():
+        acc[name] = {"rel_l2_vs_reference": leaf_rel_l2(phi, ref, leaf),
+                     "rel_l2_vs_oracle_1e-8": leaf_rel_l2(phi, phi8, leaf)}
+    del phi8, ref
+    out = {"value": w.n_leaf / med, "unit": "cells/s", "cores": threads, "kind": "oracle",
+           "sample": f"full workload, {len(times)} FP64 FMG solve(s) to 1e-8 on {threads} threads "
+                     f"({cyc} V-cycles, GPU {gpu_cycles}), median {med:.3f} s",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    if small is not None:
+        ws = small
+        ts = O.OracleTree.from_workload(ws)
+        ts.set_rhs_from(ws)
+        t0 = time.perf_counter()
+        ts.fmg_solve(tol=1e-8)
+        t_all = time.perf_counter() - t0
+        O.set_threads(1)
+        try:
+            t0 = time.perf_counter()
+            ts.fmg_solve(tol=1e-8)
+            t_one = time.perf_counter() - t0
+        finally:
+            O.set_threads(threads)
+        out["one_thread"] = {"workload": ws.name, "n_leaf": ws.n_leaf,
+                             "value": ws.n_leaf / t_one, "unit": "cells/s",
+                             "all_threads_value": ws.n_leaf / t_all,
+                             "sample": f"one FP64 FMG solve to 1e-8 of {ws.name}: "
+                                       f"{t_one:.2f} s on 1 thread, {t_all:.3f} s on {threads}"}
+    return out, acc
 
 
 NN_FLOP_PER_CELL = 2 * 27 * (16 + 16 * 16 + 16)  # the three convolutions, multiply-adds x 2
@@ -201,10 +281,14 @@ def learned_leg(g, args, k_plain, value_plain):
         res = L.solve(net)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    run_s = []
     for _ in range(args.steps):
-        res = L.solve(net)
+        t_run = time.perf_counter()
+        res = L.solve(net)  # returns after its last residual check is read back
+        run_s.append(time.perf_counter() - t_run)
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
+    phi = g.get_field(M.MG_FIELD_PHI)
     n_leaf = int(g.info.n_leaf_cells)
     # forward kernel on every leaf box of the benchmark tree, HIP events on
     # the stream it is launched on (torch's current stream)
@@ -222,7 +306,8 @@ def learned_leg(g, args, k_plain, value_plain):
     torch.cuda.synchronize()
     launch_s = e0.elapsed_time(e1) / 1e3 / reps
     tflops = NN_FLOP_PER_CELL * 512 * nbox / launch_s / 1e12
-    return {"value": n_leaf * args.steps / el, "unit": "cells/s", "ms_per_step": 1e3 * el / args.steps,
+    return phi, {"value": n_leaf * args.steps / el, "unit": "cells/s", "ms_per_step": 1e3 * el / args.steps,
+            "runs": run_stats(run_s, n_leaf),
             "vcycles": res["n_vcycles"], "vcycles_plain_fp64": k_plain,
             "accepted_steps": res["accepted"], "fallback_cycle": res["fallback_cycle"],
             "learned_ms_per_step": res["t_learned_ms"], "final_rel_res": res["rel"],
@@ -400,7 +485,7 @@ FLUID_BYTES_PER_LEAF_BOX = 8 * (4 * 512 + 1728 + 512 + 3 * 512)
 
 
 def fluid_leg(args, sched64):
-    """The fluid model's time step (paper section 2.4) on the benchmark tree in
+    """The fluid model's time step (paper sections 2.2-2.4) on the benchmark tree in
     the paper's SI setup ((40 mm)^3, 80 kV): electron and ion densities of a
     perturbed 1e19 m^-3 blob at the streamer head over a 1e15 m^-3
     background, synthetic transport table (1000 entries up to 35 MV/m).
@@ -486,21 +571,58 @@ def parse_schedule(text, nlev, nvariants):
     return parts
 
 
+def run_stats(run_s, n_leaf):
+    """Median, minimum and maximum of individually timed solves."""
+    med = statistics.median(run_s)
+    return {"n": len(run_s), "median_ms": 1e3 * med, "min_ms": 1e3 * min(run_s),
+            "max_ms": 1e3 * max(run_s), "median_cells_per_s": n_leaf / med,
+            "best_cells_per_s": n_leaf / min(run_s)}
+
+
+SOLVE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_traffic_{}.json")
+DRIVER_SRC = os.path.join(ROOT, "paper_1708_08434_amd", "csrc", "mg_api.hip")
+
+
+def solve_traffic(workload):
+    """HBM bytes per FP64 FMG solve of this workload from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE summed over one
+    solve's dispatches, scaled by the copy kernel's reading), or None if
+    there is none or the kernels or the driver changed since."""
+    path = SOLVE_TRAFFIC_FILE.format(workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read() + open(DRIVER_SRC, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_solve")
+
+
+WORKLOAD_TEXT = {
+    "streamer": " static streamer octree (base 64^3 + 4 refinement levels)",
+    "forest": " forest of 128 uneven streamer trees (base 32^3 + <=5 levels)",
+    "branched": " branched streamer octree (base 64^3 + 6 refinement levels)",
+    "two_streamers": " two streamers + Poisson background (base 64^3 + 7 refinement levels)",
+    "paper_setup": " streamer octree in SI units: (40 mm)^3, 80 kV top, grounded bottom, "
+                   "Neumann sides"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10,
+                    help="timed FMG solves (each also timed on its own: median and minimum)")
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction leg")
     ap.add_argument("--train-steps", type=int, default=300, help="Adam steps of the learned leg")
     ap.add_argument("--regrid-steps", type=int, default=8,
-                    help="field solves of the regrid leg (a regrid every 4th); 0 skips it "
-                         "(benchmark streamer only)")
+                    help="field solves of the regrid leg (a regrid every 4th); 0 skips it")
     ap.add_argument("--ts-steps", type=int, default=8,
                     help="time steps (2 warm-started field solves each) of the time-stepping leg; "
-                         "0 skips it (benchmark streamer only)")
+                         "0 skips it")
     ap.add_argument("--copy-probe", type=int, default=0, help="bytes of a calibration copy")
     ap.add_argument("--fluid-steps", type=int, default=10,
                     help="time steps of the fluid leg (paper setup, SI units); 0 skips it")
@@ -510,32 +632,37 @@ def main():
                     help="fixed Gauss-Seidel launch variant per level instead of the autotuner: "
                          "FP64 list, optionally '/' and the FP32 list, e.g. 3,7,7,1,7,7,1,11/3,1,7,1,7,7,1,9 "
                          "(reproduces a tuned run's launches, e.g. under a profiler)")
-    ap.add_argument("--workload", default="streamer",
+    ap.add_argument("--workload", default="two_streamers",
                     choices=["streamer", "forest", "branched", "two_streamers", "paper_setup"],
-                    help="streamer: base 64^3 + 4 levels, 4.8e6 cells (default); forest: 128 "
-                         "uneven trees, 7.1e7 cells; branched: base 64^3 + 6 levels, 2.9e7 "
-                         "cells; two_streamers: base 64^3 + 7 levels, ~1e8 cells; paper_setup: "
-                         "the streamer tree in the paper's SI setup (40 mm, 80 kV, Neumann sides)")
+                    help="two_streamers: base 64^3 + 7 levels, 1.2e8 cells (default); streamer: "
+                         "base 64^3 + 4 levels, 4.8e6 cells; forest: 128 uneven trees, 7.1e7 "
+                         "cells; branched: base 64^3 + 6 levels, 2.9e7 cells; paper_setup: the "
+                         "streamer tree in the paper's SI setup (40 mm, 80 kV, Neumann sides)")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py: measures one GPU only; the solver has no multi-GPU path "
                  "(sharding across GPUs is a design, not code).  Use --gpus 1.")
     rank = int(os.environ.get("RANK", "0"))
 
+    import numpy as np
     import torch
     from paper_1708_08434_amd import mg as M
     from workloads import c2, c3, c5, forest, paper_setup
 
     from paper_1708_08434_amd import autotune
 
-    w = {"streamer": c2, "forest": forest, "branched": c3, "two_streamers": c5,
-         "paper_setup": paper_setup}[args.workload]()
+    gen = {"streamer": c2, "forest": forest, "branched": c3, "two_streamers": c5,
+           "paper_setup": paper_setup}
+    w = gen[args.workload]()
     if args.traffic_probe:
         traffic_probe(w)
         return
     g = M.Tree.from_workload(w, device="cuda:0")
-    g.set_rhs_from(w)
+    order = g.index(M.MG_IDX_ORDER)
+    rhs = w.rhs(g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK), g.index(M.MG_IDX_TREE))
+    g.set_field(M.MG_FIELD_RHS, rhs)
     torch.cuda.synchronize()
+    log(f"{w.name}, {g.n} boxes, {int(g.info.n_leaf_cells)} leaf cells")
     if args.schedule:
         parts = parse_schedule(args.schedule, g.nlev, M.MG_GSRB_VARIANTS)
         sched64 = parts[0]
@@ -548,16 +675,22 @@ def main():
     else:
         sched64, _ = autotune.tune(g, M.MG_FP64)
         sched32, _ = autotune.tune(g, M.MG_MIXED)
+    log("schedules", sched64, sched32)
     for _ in range(args.warmup):
         g.fmg_solve()
-    # timed region 1: the solve as shipped (recorded graphs replayed)
+    # timed region 1: the solve as shipped (recorded graphs replayed); every
+    # solve returns after its last residual check has been read back, so it
+    # is also timed on its own
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = None
+    stats, run_s = None, []
     for _ in range(args.steps):
+        t_run = time.perf_counter()
         stats = g.fmg_solve()
+        run_s.append(time.perf_counter() - t_run)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    results = {"fp64": g.get_field(M.MG_FIELD_PHI)}
     # timed region 2: the same solves with HIP-event probes around the
     # Gauss-Seidel half-sweeps on the library's stream (kernel-by-kernel
     # launches, since events inside replayed graphs carry no usable times)
@@ -571,19 +704,25 @@ def main():
     elapsed_probe = time.perf_counter() - t1
     M.mg_timing_enable(g.h, False)
     kt = M.mg_timing_read(g.h)
+    n_leaf = int(g.info.n_leaf_cells)
+    log("fp64 solves done")
     mixed = None
     if not args.no_mixed:
         for _ in range(args.warmup):
             g.fmg_solve(precision=M.MG_MIXED)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        mrun = []
         for _ in range(args.steps):
+            t_run = time.perf_counter()
             ms_stats = g.fmg_solve(precision=M.MG_MIXED)
+            mrun.append(time.perf_counter() - t_run)
         torch.cuda.synchronize()
         el_m = time.perf_counter() - t2
-        mixed = {"value": int(g.info.n_leaf_cells) * args.steps / el_m, "unit": "cells/s",
-                 "ms_per_step": 1e3 * el_m / args.steps, "refinement_steps": ms_stats["n_vcycles"],
-                 "final_rel_res": ms_stats["rel"]}
+        results["mixed"] = g.get_field(M.MG_FIELD_PHI)
+        mixed = {"value": n_leaf * args.steps / el_m, "unit": "cells/s",
+                 "ms_per_step": 1e3 * el_m / args.steps, "runs": run_stats(mrun, n_leaf),
+                 "refinement_steps": ms_stats["n_vcycles"], "final_rel_res": ms_stats["rel"]}
     if args.copy_probe > 0:
         src = torch.empty(args.copy_probe // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
         dst = torch.empty_like(src)
@@ -592,7 +731,6 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    n_leaf = int(g.info.n_leaf_cells)
     ls = list(g.info.level_start[:g.nlev + 1])
     counts = [ls[i + 1] - ls[i] for i in range(g.nlev)]
     ms = 1e3 * elapsed / args.steps
@@ -600,16 +738,8 @@ def main():
     k = stats["n_vcycles"]
     learned = None
     if not args.no_learned:
-        learned = learned_leg(g, args, k, value)
-    time_step = None
-    if args.ts_steps > 0 and args.workload == "streamer":
-        time_step = time_step_leg(g, args)
-    regrid = None
-    if args.regrid_steps > 0 and args.workload == "streamer":
-        regrid = regrid_leg(w, args, sched64)
-    fluid = None
-    if args.fluid_steps > 0 and args.workload == "streamer":
-        fluid = fluid_leg(args, sched64)
+        log("learned leg")
+        results["learned"], learned = learned_leg(g, args, k, value)
     copy = copy_bandwidth()
     mb = model_bytes(counts, n_leaf, k)
     # the level whose half-sweeps move the most bytes (the finest level of a
@@ -620,53 +750,52 @@ def main():
     achieved = bytes_per_launch / per_launch_s / 1e9
     all_us = kt["total_ms"] * 1e3 / max(kt["launches"], 1)
     tr = traffic_per_launch(w.name, fin + 1, sched64[fin])
+    model_gbps = mb / (ms / 1e3) / 1e9
     out = {
         "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name + {
-                       "streamer": " static streamer octree (base 64^3 + 4 refinement levels)",
-                       "forest": " forest of 128 uneven streamer trees (base 32^3 + <=5 levels)",
-                       "branched": " branched streamer octree (base 64^3 + 6 refinement levels)",
-                       "two_streamers": " two streamers + Poisson background (base 64^3 + 7 "
-                                        "refinement levels)",
-                       "paper_setup": " streamer octree in SI units: (40 mm)^3, 80 kV top, "
-                                      "grounded bottom, Neumann sides"}[args.workload],
+        "config": {"workload": w.name + WORKLOAD_TEXT[args.workload],
                    "n_trees": int(g.info.n_trees),
                    "n_leaf": n_leaf, "n_boxes": g.n, "levels": g.nlev, "rel_tol": 1e-8,
                    "vcycles_after_fmg": k, "final_rel_res": stats["rel"], "precision": "fp64",
                    "smoothing": "V(2,2) red-black Gauss-Seidel",
                    "gsrb_schedule": {"fp64": sched64, "fp32": sched32}},
-        "roofline": {"bound": "hbm",
-                     "kernel": gsrb_kernel_name(sched64[fin])
-                               + f", level {fin + 1} ({counts[fin]} boxes, the most bytes), "
-                                 f"schedule variant {sched64[fin]}",
-                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS,
-                     "copy_GBps": copy["GBps"], "frac_of_copy": achieved / copy["GBps"],
-                     "traffic": tr,
-                     "launches": kt["level_launches"][fin], "avg_launch_us": per_launch_s * 1e6,
-                     "alg_bytes_per_launch": bytes_per_launch,
-                     "all_levels": {"launches": kt["launches"], "avg_launch_us": all_us,
-                                    "GBps": kt["alg_bytes"] / (kt["total_ms"] / 1e3) / 1e9},
-                     "probe_region_ms_per_step": 1e3 * elapsed_probe / args.steps},
-        "model": {"bytes_per_solve": mb, "GBps": mb / (ms / 1e3) / 1e9,
+        "runs": run_stats(run_s, n_leaf),
+        # solve level: the per-sweep byte model of the FMG solve (127 B per
+        # stored cell per V(2,2) visit, FMG summed over the top levels, 16 B
+        # per leaf cell per residual check) over the solve time
+        "roofline": {"bound": "hbm", "scope": "FP64 FMG solve (all kernels), per-sweep byte model",
+                     "achieved": model_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": model_gbps / HBM_PEAK_GBPS, "traffic": solve_traffic(w.name),
+                     "alg_bytes_per_solve": mb,
+                     "copy_GBps": copy["GBps"], "frac_of_copy": model_gbps / copy["GBps"]},
+        "dominant_kernel": {
+            "bound": "hbm",
+            "kernel": gsrb_kernel_name(sched64[fin])
+                      + f", level {fin + 1} ({counts[fin]} boxes, the most bytes), "
+                        f"schedule variant {sched64[fin]}",
+            "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "copy_GBps": copy["GBps"], "frac_of_copy": achieved / copy["GBps"],
+            "traffic": tr,
+            "launches": kt["level_launches"][fin], "avg_launch_us": per_launch_s * 1e6,
+            "alg_bytes_per_launch": bytes_per_launch,
+            "all_levels": {"launches": kt["launches"], "avg_launch_us": all_us,
+                           "GBps": kt["alg_bytes"] / (kt["total_ms"] / 1e3) / 1e9},
+            "probe_region_ms_per_step": 1e3 * elapsed_probe / args.steps},
+        "model": {"bytes_per_solve": mb, "GBps": model_gbps,
                   "roofline_cells_per_s": HBM_PEAK_GBPS * 1e9 * n_leaf / mb,
                   "frac": value / (HBM_PEAK_GBPS * 1e9 * n_leaf / mb),
                   "frac_of_copy": value / (copy["GBps"] * 1e9 * n_leaf / mb)},
         "copy_probe": copy,
     }
     if mixed is not None:
+        mixed["vs_fp64"] = mixed["value"] / value
         out["mixed"] = mixed
     if learned is not None:
         out["learned"] = learned
-    if time_step is not None:
-        out["time_step"] = time_step
-    if regrid is not None:
-        out["regrid"] = regrid
-    if fluid is not None:
-        out["fluid"] = fluid
     if args.workload == "paper_setup":
         g.fmg_solve()
         _, en = g.efield()
@@ -674,8 +803,40 @@ def main():
         out["field"] = {"background_V_per_m": w.meta["e0"], "max_E_V_per_m": float(en[leaf].max()),
                         "max_E_over_background": float(en[leaf].max() / w.meta["e0"]),
                         "n_head_per_m3": w.meta["n_head"]}
+    del g
+    torch.cuda.empty_cache()
+    # secondary legs on the static streamer tree (base 64^3 + 4 levels)
+    w2 = g2 = None
+    if args.ts_steps > 0 or args.regrid_steps > 0 or args.fluid_steps > 0 or not args.no_cpu:
+        w2 = w if args.workload == "streamer" else c2()
+    if args.ts_steps > 0 or args.regrid_steps > 0 or args.fluid_steps > 0:
+        g2 = M.Tree.from_workload(w2, device="cuda:0")
+        g2.set_rhs_from(w2)
+        if args.workload == "streamer":
+            s2 = sched64
+            M.mg_set_schedule(g2.h, M.MG_FP64, s2)
+        else:
+            s2, _ = autotune.tune(g2, M.MG_FP64)
+        g2.fmg_solve()
+        sec = {"workload": w2.name + WORKLOAD_TEXT["streamer"], "n_leaf": w2.n_leaf}
+        log("secondary legs on", w2.name)
+        if args.ts_steps > 0:
+            out["time_step"] = dict(sec, **time_step_leg(g2, args))
+        if args.regrid_steps > 0:
+            out["regrid"] = dict(sec, **regrid_leg(w2, args, s2))
+        if args.fluid_steps > 0:
+            out["fluid"] = fluid_leg(args, s2)
+        del g2
+        torch.cuda.empty_cache()
     if rank == 0 and not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, k)
+        small = w2 if (w2 is not None and w2 is not w) else None
+        log("cpu baseline")
+        base, acc = cpu_baseline(w, rhs, order, k, results, small=small)
+        out["cpu_baseline"] = base
+        out["accuracy"] = acc
+        for name, key in (("mixed", "mixed"), ("learned", "learned")):
+            if key in out and name in acc:
+                out[key]["rel_l2_vs_oracle_reference"] = acc[name]["rel_l2_vs_reference"]
     if rank == 0:
         print(json.dumps(out), flush=True)
 

@@ -92,6 +92,8 @@ typedef struct {
  */
 int mg_tree_create(mg_tree **out, const mg_domain *dom, int64_t n, const int32_t *level,
                    const int32_t *ijk, const int32_t *tree);
+/* mg_tree_destroy synchronises the bound stream (work enqueued without a
+ * host wait may still be running), then frees the host state. */
 int mg_tree_destroy(mg_tree *t);
 int mg_tree_info(const mg_tree *t, mg_tree_info_t *info);
 
@@ -262,9 +264,11 @@ int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double der
 int mg_transfer(mg_tree *from, mg_tree *to);
 
 /*
- * Fluid model (section 2.4): the drift-diffusion-reaction equations for the
+ * Fluid model: the drift-diffusion-reaction equations (section 2.2) for the
  * electron and ion densities (SI units, m^-3), advanced with the explicit
- * trapezoidal rule.  Densities are device arrays in natural layout
+ * trapezoidal rule and its time-step limits (section 2.4).  The fluxes, the
+ * limiter, the refinement-boundary treatment and the coefficient table are
+ * the spatial discretisation of section 2.3.  Densities are device arrays in natural layout
  * [box][k][j][i] over all boxes; only leaf boxes carry data (covered boxes
  * are overwritten with the mean of their children).  Per stage, on every
  * leaf cell:
@@ -283,7 +287,8 @@ int mg_transfer(mg_tree *from, mg_tree *to);
  * the solver's right-hand side on leaf cells to -e (n_i - n_e) / eps0 of the
  * output, and gives the time-step bound min over leaf cells of 0.5 / V,
  * 1 / (V + 6 D / h^2) and eps0 / (e mu n_e), V = sum over axes of the larger
- * |v| of the cell's two faces, divided by h.
+ * |v| of the cell's two faces, divided by h.  A stage with a non-finite
+ * output density gives a NaN bound.
  *
  * mg_fluid_workspace_bytes: size of the fluid workspace for n_table table
  *   entries (-1 on bad arguments).
@@ -302,6 +307,8 @@ int mg_transfer(mg_tree *from, mg_tree *to);
  *   the same bits as after mg_vcycle).  phi must be the potential of
  *   (ne, ni) on entry.
  *   dt_next (host, may be NULL) = 0.9 x the bound of the second stage.
+ *   MG_ENOCONV when a density of the step is not finite (a diverging step,
+ *   e.g. dt far above the bound); the densities and phi are then not usable.
  * MG_ESTATE without a bound fluid workspace; MG_EINVAL on bad arguments.
  */
 int64_t mg_fluid_workspace_bytes(const mg_tree *t, int32_t n_table);
@@ -392,6 +399,7 @@ int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out);
 #define MG_GSRB_VARIANTS 14
 int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule);
 int mg_set_schedule(mg_tree *t, int precision, const int32_t *schedule);
+
 
 /*
  * mg_stream_copy - copy `bytes` (a multiple of 16; both pointers device

@@ -5,6 +5,7 @@ benchmark's CPU-baseline leg, never by the GPU library.  It shares no code
 with the GPU path.
 """
 import ctypes
+import sys
 import os
 import subprocess
 
@@ -120,10 +121,14 @@ class OracleTree:
         b = w.boxes
         return cls(b.level, b.ijk, b.tree, w.lo, w.length, w.bc_type, w.bc_val)
 
-    def __del__(self):
-        if getattr(self, "h", None):
-            lib().oracle_destroy(self.h)
-            self.h = None
+    def __del__(self, _finalizing=sys.is_finalizing):
+        h = getattr(self, "h", None)
+        if not h:
+            return
+        self.h = None
+        if _finalizing():
+            return  # process exit releases the memory; module globals may already be gone
+        lib().oracle_destroy(h)
 
     def index(self, what):
         out = np.zeros((self.n, _WIDTH[what]), dtype=np.int32)
@@ -198,7 +203,7 @@ class OracleTree:
         return face, norm
 
     def fluid_stage(self, ne, ni, n0e, n0i, e_face, e_norm, table, emax, dt, wa=0.0, wb=1.0):
-        """One explicit stage of the fluid model (paper section 2.4) on the
+        """One explicit stage of the fluid model (paper sections 2.2-2.4) on the
         leaf cells: out = wa * n0 + wb * (n + dt * rate(n)); densities
         [n][8][8][8] in SI units, table [ntab][3] = (mu, D, alpha) at
         E = k * emax / (ntab - 1).  Also sets this tree's right-hand side on

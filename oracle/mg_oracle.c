@@ -990,9 +990,10 @@ int oracle_set_threads(int n) {
 }
 
 /* ------------------------------------------------------------ fluid model */
-/* One explicit stage of the drift-diffusion-reaction model of paper section
-   2.4 (equations for n_e and n_i, the spatial discretisation of the fluxes,
-   the time-step limits), on the leaf cells of the tree:
+/* One explicit stage of the drift-diffusion-reaction model (paper section
+   2.2 for the equations for n_e and n_i, section 2.3 for the spatial
+   discretisation of the fluxes and the coefficient table, section 2.4 for
+   the stages and the time-step limits), on the leaf cells of the tree:
      out_e = wa * n0_e + wb * (n_e + dt * R_e),  R_e = -div(flux) + S,
      out_i = wa * n0_i + wb * (n_i + dt * S),    S = alpha(E) mu(E) E n_e,
    with E = |E| at the cell centre.  The flux of electrons across a face in

@@ -1,5 +1,7 @@
-// Fluid model on the octree (paper section 2.4): one explicit stage of the
-// drift-diffusion-reaction equations for the electron and ion densities,
+// Fluid model on the octree: one explicit stage of the drift-diffusion-
+// reaction equations for the electron and ion densities (paper section 2.2;
+// fluxes, limiter, refinement-boundary treatment and the coefficient table:
+// section 2.3; the trapezoidal stages and the time-step limits: section 2.4),
 //   out_e = wa n0_e + wb (n_e + dt (S - div F)),  out_i = wa n0_i + wb (n_i + dt S),
 // with S = alpha(E) mu(E) E n_e at the cell centre (E = |E|) and F the
 // electron flux across each face: v n_face - D(E*) (n_R - n_L) / h, where
@@ -82,6 +84,12 @@ __device__ __forceinline__ void coef(const FluidTable &T, double E, double &mu, 
     mu = lerp(r[0], w);
     D = lerp(r[1], w);
     al = lerp(r[2], w);
+}
+
+// Minimum that carries NaN through (fmin drops it): the time-step bound of a
+// stage with a non-finite output is NaN.
+__device__ __forceinline__ double nanmin(double a, double b) {
+    return (a != a || a < b) ? a : b;
 }
 
 // psi(a / b) * b for the Koren limiter psi(x) = max(0, min(1, (2 + x) / 6, x)),
@@ -352,12 +360,14 @@ __global__ __launch_bounds__(512) void k_fluid_update(
         double dr = kEps0 / (kCharge * mu * nec);
         if (dr < cand) cand = dr;
     }
-    for (int off = 32; off > 0; off >>= 1) cand = fmin(cand, __shfl_xor(cand, off));
+    // a non-finite output poisons the bound, so a diverging step is seen
+    if (!isfinite(oe) || !isfinite(oi)) cand = NAN;
+    for (int off = 32; off > 0; off >>= 1) cand = nanmin(cand, __shfl_xor(cand, off));
     if ((t & 63) == 0) red[t >> 6] = cand;
     __syncthreads();
     if (t == 0) {
         double m = red[0];
-        for (int w = 1; w < 8; w++) m = fmin(m, red[w]);
+        for (int w = 1; w < 8; w++) m = nanmin(m, red[w]);
         partial[q] = m;
     }
 }
@@ -368,13 +378,13 @@ __global__ __launch_bounds__(1024) void k_fluid_min(const double *__restrict__ p
     __shared__ double red[16];
     int t = threadIdx.x;
     double m = INFINITY;
-    for (int64_t q = t; q < n; q += 1024) m = fmin(m, partial[q]);
-    for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off));
+    for (int64_t q = t; q < n; q += 1024) m = nanmin(m, partial[q]);
+    for (int off = 32; off > 0; off >>= 1) m = nanmin(m, __shfl_xor(m, off));
     if ((t & 63) == 0) red[t >> 6] = m;
     __syncthreads();
     if (t == 0) {
         double r = red[0];
-        for (int w = 1; w < 16; w++) r = fmin(r, red[w]);
+        for (int w = 1; w < 16; w++) r = nanmin(r, red[w]);
         out[0] = r;
     }
 }

@@ -788,6 +788,10 @@ int mg_tree_create(mg_tree **out, const mg_domain *dom, int64_t n, const int32_t
 
 int mg_tree_destroy(mg_tree *t) {
     if (!t) return MG_OK;
+    // work enqueued without a host wait (mg_vcycle without statistics,
+    // mg_fluid_step, mg_field_set) may still run on the bound stream and use
+    // the graphs and the pinned buffer released below
+    if (t->stream) (void)hipStreamSynchronize((hipStream_t)t->stream);
     for (auto &g : t->graphs) drop_graph(g);
     if (t->host_result) (void)hipHostFree(t->host_result);
     for (auto &p : t->probes) {
@@ -1310,6 +1314,10 @@ int mg_fluid_step(mg_tree *t, double *ne, double *ni, double dt, int32_t n_vcycl
     if (!rc) rc = mg_efield(t, ef, en);
     if (!rc) rc = fluid_stage(t, ef, en, n1e, n1i, n0e, n0i, dt, 0.5, 0.5, ne, ni, &lim);
     if (!rc) rc = vcycles_no_stats(t, &o, n_vcycles);
+    if (!rc && std::isnan(lim)) {
+        set_error("mg_fluid_step: non-finite density after the step (time-step bound is NaN)");
+        rc = MG_ENOCONV;
+    }
     if (!rc && dt_next) *dt_next = 0.9 * lim;
     return rc;
 }

@@ -88,7 +88,7 @@ struct Key {
     bool same(const Key &o) const { return level == o.level && tree == o.tree && m == o.m; }
 };
 
-char g_buf[256];
+thread_local char g_buf[256];  // error text, per thread like mg_last_error()
 
 }  // namespace
 

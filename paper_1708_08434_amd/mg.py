@@ -6,6 +6,7 @@ fallback: if libmg.so is missing or fails to load, this module raises.
 """
 import ctypes
 import os
+import sys
 
 import numpy as np
 
@@ -359,12 +360,14 @@ class Tree:
         b = w.boxes
         return cls(b.level, b.ijk, b.tree, w.lo, w.length, w.bc_type, w.bc_val, **kw)
 
-    def __del__(self):
-        if getattr(self, "h", None):
-            try:
-                mg_tree_destroy(self.h)
-            finally:
-                self.h = None
+    def __del__(self, _finalizing=sys.is_finalizing):
+        h = getattr(self, "h", None)
+        if not h:
+            return
+        self.h = None
+        if _finalizing():
+            return  # process exit releases everything; module globals may already be gone
+        mg_tree_destroy(h)
 
     def index(self, what):
         return mg_tree_index(self.h, what, self.n)

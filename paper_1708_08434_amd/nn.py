@@ -5,6 +5,7 @@ optimiser, the input gathering and the learned step all run in libmg's HIP
 kernels.  Device buffers are torch tensors (plumbing for memory and streams).
 """
 import ctypes
+import sys
 
 import numpy as np
 
@@ -166,14 +167,14 @@ class Net:
         if params is not None:
             self.set_params(params)
 
-    def __del__(self):
-        if getattr(self, "h", None):
-            try:
-                mg_nn_destroy(self.h)
-            except Exception:  # interpreter shutdown: the library may be gone
-                pass
-            finally:
-                self.h = None
+    def __del__(self, _finalizing=sys.is_finalizing):
+        h = getattr(self, "h", None)
+        if not h:
+            return
+        self.h = None
+        if _finalizing():
+            return  # process exit releases everything; module globals may already be gone
+        mg_nn_destroy(h)
 
     def set_params(self, p):
         mg_nn_set_params(self.h, p)

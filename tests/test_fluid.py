@@ -1,4 +1,4 @@
-"""The fluid step (paper section 2.4): drift-diffusion-reaction update of the
+"""The fluid step (paper sections 2.2-2.4): drift-diffusion-reaction update of the
 electron and ion densities with Koren-limited advective fluxes, central
 diffusive fluxes, the ionisation source, refinement-boundary ghosts and flux
 fix-up, the explicit trapezoidal time step and its time-step limits.

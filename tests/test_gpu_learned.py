@@ -51,8 +51,13 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.mark.parametrize("nbox", [1, 37])
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("nbox", [1, 37, 1601])
 def test_forward_parity(nbox):
+    """1601 boxes: more than twice the persistent forward grid (768
+    workgroups), so workgroups walk three boxes each with the next box's
+    input in flight; every box has its own random input, so a box computed
+    from another's input or written to another's slot fails."""
     say("forward parity nbox", nbox)
     p = rand_params(3)
     x = rand_x(4, nbox)
@@ -88,14 +93,27 @@ def segments():
             ("b3", N.N_PARAMS - 1, 1)]
 
 
-@pytest.mark.parametrize("nbox", [1, 5])
-def test_gradient_parity(nbox):
-    say("gradient parity nbox", nbox)
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("nbox,indexed", [(1, False), (5, False), (1030, False), (1030, True)],
+                         ids=["1", "5", "1030", "1030_idx"])
+def test_gradient_parity(nbox, indexed):
+    """1030 boxes: more than twice the weight-gradient grid (512
+    workgroups), so every workgroup accumulates several boxes before the
+    fixed-order reduction; with an index, the boxes are a permutation of a
+    larger batch (the training mini-batch path)."""
+    say("gradient parity nbox", nbox, "indexed", indexed)
     p = rand_params(7)
-    x = rand_x(8, nbox)
-    tgt = np.random.default_rng(9).standard_normal((nbox, 8, 8, 8)).astype(np.float32)
+    nall = nbox + 70 if indexed else nbox
+    x = rand_x(8, nall)
+    tgt = np.random.default_rng(9).standard_normal((nall, 8, 8, 8)).astype(np.float32)
     net = NN.Net(p)
-    loss = net.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda())
+    if indexed:
+        idx = np.random.default_rng(10).permutation(nall)[:nbox].astype(np.int32)
+        loss = net.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda(),
+                            idx=torch.from_numpy(idx).cuda())
+        x, tgt = x[idx], tgt[idx]
+    else:
+        loss = net.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda())
     g = net.get_grad().astype(np.float64)
     L, ref = N.gradients(p.astype(np.float64), x.astype(np.float64), tgt.astype(np.float64))
     assert abs(loss - L) <= 1e-4 * L

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_1708_08434_amd import mg as M
-from workloads import c1, c2, c3, c5, streamer_small, uniform_boxes, refine_boxes_explicit
+from workloads import c1, c2, c3, c5, forest, streamer_small, uniform_boxes, refine_boxes_explicit
 from tests import _geom as G
 
 pytestmark = pytest.mark.gpu
@@ -119,19 +119,25 @@ def test_fmg_solve_parity(wname):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("wname", ["streamer", "branched", "two_streamers"])
+@pytest.mark.parametrize("wname", ["streamer", "branched", "forest", "two_streamers"])
 def test_fmg_solve_parity_full_size(wname):
     """Full-size trees in the launch sequence the benchmark times: the
     benchmark streamer (base 64^3 + 4 refinement levels, 4.8e6 leaf cells),
-    the branched streamer (base 64^3 + 6 levels, 2.9e7 leaf cells) and the
-    two streamers with background ionisation (base 64^3 + 7 levels, 1.2e8
-    leaf cells)."""
-    w = {"streamer": c2, "branched": c3, "two_streamers": c5}[wname]()
+    the branched streamer (base 64^3 + 6 levels, 2.9e7 leaf cells), the
+    forest of 128 uneven trees (7.1e7 leaf cells; its largest trees span
+    several chunks of the per-tree norm reduction) and the two streamers
+    with background ionisation (base 64^3 + 7 levels, 1.2e8 leaf cells)."""
+    w = {"streamer": c2, "branched": c3, "forest": forest, "two_streamers": c5}[wname]()
     say("fmg parity full size", wname, w.boxes.n, "boxes", w.n_leaf, "leaf cells")
     g, o, sg, so, err = solve_pair(w)
     say("  gpu", sg["n_vcycles"], sg["rel"], "oracle", so["n_vcycles"], so["rel"], "err", err)
     assert sg["n_vcycles"] == so["n_vcycles"]
     assert err <= SOLVE_TOL, err
+    if wname == "forest":
+        nleaf_tree = np.bincount(g.index(M.MG_IDX_TREE)[g.leaf_mask()])
+        say("  leaf boxes per tree: max", nleaf_tree.max(), "min", nleaf_tree.min())
+        assert nleaf_tree.max() > 2048  # a tree spans more than one reduction chunk
+        np.testing.assert_allclose(g.tree_rel(), o.tree_rel(), rtol=1e-5)
 
 
 def test_warm_vcycles_parity():
@@ -318,8 +324,9 @@ def test_fp32_step_parity(step):
 MIXED_TOL = 1e-8
 
 
-@pytest.mark.timeout(400)
-@pytest.mark.parametrize("wname", ["uniform64", "streamer_small", "streamer_full", "branched"])
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("wname", ["uniform64", "streamer_small", "streamer_full", "branched",
+                                   "forest"])
 def test_mixed_solve_accuracy(wname):
     """FP32 cycles inside FP64 refinement.  At the 1e-8 residual tolerance the
     potential is as close to the fully converged discrete solution (oracle,
@@ -328,7 +335,7 @@ def test_mixed_solve_accuracy(wname):
     tolerance the refinement keeps converging past FP32 rounding and the
     potential matches the oracle to a relative L2 of 1e-8."""
     w = {"uniform64": c1, "streamer_small": streamer_small, "streamer_full": c2,
-         "branched": c3}[wname]()
+         "branched": c3, "forest": forest}[wname]()
     g, o = pair(w)
     g.set_rhs_from(w)
     o.set_rhs_from(w)

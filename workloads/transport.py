@@ -1,4 +1,4 @@
-"""Synthetic transport coefficients for the fluid model (paper section 2.4).
+"""Synthetic transport coefficients for the fluid model (paper section 2.3).
 
 The paper builds its lookup table from BOLSIG+ output for nitrogen at 1 bar;
 those data are not available here, so the table is filled from smooth closed
