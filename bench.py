@@ -632,6 +632,8 @@ def main():
                     help="fixed Gauss-Seidel launch variant per level instead of the autotuner: "
                          "FP64 list, optionally '/' and the FP32 list, e.g. 3,7,7,1,7,7,1,11/3,1,7,1,7,7,1,9 "
                          "(reproduces a tuned run's launches, e.g. under a profiler)")
+    ap.add_argument("--fusion", type=int, default=None,
+                    help="mg_set_fusion flags for the solves (default: all fused sequences)")
     ap.add_argument("--workload", default="two_streamers",
                     choices=["streamer", "forest", "branched", "two_streamers", "paper_setup"],
                     help="two_streamers: base 64^3 + 7 levels, 1.2e8 cells (default); streamer: "
@@ -658,6 +660,8 @@ def main():
         traffic_probe(w)
         return
     g = M.Tree.from_workload(w, device="cuda:0")
+    if args.fusion is not None:
+        M.mg_set_fusion(g.h, args.fusion)
     order = g.index(M.MG_IDX_ORDER)
     rhs = w.rhs(g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK), g.index(M.MG_IDX_TREE))
     g.set_field(M.MG_FIELD_RHS, rhs)
@@ -761,6 +765,7 @@ def main():
                    "n_leaf": n_leaf, "n_boxes": g.n, "levels": g.nlev, "rel_tol": 1e-8,
                    "vcycles_after_fmg": k, "final_rel_res": stats["rel"], "precision": "fp64",
                    "smoothing": "V(2,2) red-black Gauss-Seidel",
+                   "fusion": M.MG_FUSE_ALL if args.fusion is None else args.fusion,
                    "gsrb_schedule": {"fp64": sched64, "fp32": sched32}},
         "runs": run_stats(run_s, n_leaf),
         # solve level: the per-sweep byte model of the FMG solve (127 B per

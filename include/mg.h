@@ -126,8 +126,11 @@ int mg_tree_index(const mg_tree *t, int what, int32_t *host_out);
  * then the 256 with odd i+j+k).
  *   which   MG_FIELD_PHI (solution, all boxes), MG_FIELD_RHS (b; only leaf
  *           boxes matter, covered boxes are overwritten by the solver),
- *           MG_FIELD_OLD, MG_FIELD_E32 / _R32 / _OLD32 (FP32 fields, rounded
- *           on the way in),
+ *           MG_FIELD_OLD (the coarse values a down-leg keeps for the
+ *           correction; scratch: a down-leg writes it only where a
+ *           prolongation reads it, i.e. on boxes with children and on leaf
+ *           boxes with a same-level face or edge neighbour that has children),
+ *           MG_FIELD_E32 / _R32 / _OLD32 (FP32 fields, rounded on the way in),
  *           MG_FIELD_BCVAL ([n][6][64] Dirichlet values at the face-cell
  *           centres; per_cell_bc must be set; tangential axes in increasing
  *           order, first fastest)
@@ -400,6 +403,19 @@ int mg_timing_read(mg_tree *t, mg_kernel_timing_t *out);
 int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule);
 int mg_set_schedule(mg_tree *t, int precision, const int32_t *schedule);
 
+/*
+ * mg_set_fusion - which fused launch sequences the cycle uses (all by
+ * default).  Every combination computes the same bits; the flags exist to
+ * compare and time the sequences.
+ *   MG_FUSE_PROLONG: on a level smoothed by half-sweeps, the prolongation of
+ *     the coarse correction (section 2.1.2's interpolation between levels) is
+ *     not a pass of its own: the first red and black half-sweeps after it form
+ *     each prolonged value they read from the unprolonged field and the
+ *     parent's correction, which saves reading and writing the level once.
+ * MG_EINVAL on unknown flags.  Changing the flags drops recorded graphs.
+ */
+enum { MG_FUSE_PROLONG = 1, MG_FUSE_ALL = 1 };
+int mg_set_fusion(mg_tree *t, int flags);
 
 /*
  * mg_stream_copy - copy `bytes` (a multiple of 16; both pointers device

@@ -13,6 +13,8 @@ struct Geo {
     const int32_t *cfq;     // [n][6]
     const int32_t *xt;      // [n][6][4][2] faces of the face neighbours
     const int32_t *pnb;     // [n][6] the parent's face neighbours
+    const int32_t *n27;     // [n][27] same-level box at ijk + o, o in {-1,0,1}^3 (x fastest);
+                            // -1 covered only by a coarser leaf, -2 outside the domain
     const int32_t *slotx;   // [nslot][8] Q, base t1, base t2, Q's neighbours -t1 +t1 -t2 +t2
     const int32_t *ijk;     // [n][4] (i, j, k, level)
     const int32_t *parent;  // [n]
@@ -73,6 +75,15 @@ void launch_fas_rhs(const Geo &g, const T *phi, T *rhs, const T *chat, const int
 template <typename T>
 void launch_prolong_cf(const Geo &g, T *phi, const T *old, int64_t b0, int64_t nb, T *chat,
                        const int32_t *slots, int64_t s0, int64_t ns, hipStream_t s);
+// First red-black sweep after the prolongation into level l (l >= 2): the
+// prolonged value of every cell a half-sweep reads is formed on the fly from
+// the unprolonged field and the parent's correction phi - old, so the
+// prolongation pass is not launched; colour 0 then colour 1.  The level
+// ends with the values of prolongation + one sweep.  c_hat of the level
+// must be current.
+template <typename T>
+void launch_gsrb_pro(const Geo &g, T *phi, const T *rhs, const T *old, const T *chat, int64_t b0, int64_t nb,
+                     T h2, int colour, hipStream_t s);
 template <typename T>
 void launch_coarse(const Geo &g, T *phi, const T *rhs, const double *eig, int64_t b0, int64_t nroot,
                    double h, hipStream_t s);

@@ -53,8 +53,12 @@ __device__ __forceinline__ void tangential(int a, int &t1, int &t2) {
 template <typename T> __device__ __forceinline__ T dirichlet_ghost(T gv, T own) {
     return (T)2 * gv - own;
 }
+// Fused multiply-adds written out, so that every kernel rounds the
+// refinement-boundary ghost the same way whatever the compiler would contract.
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <typename T> __device__ __forceinline__ T cf_ghost(T ch, T own, T inward) {
-    return (T)kCfCoarse * ch + (T)kCfFine1 * own - (T)kCfFine2 * inward;
+    return fmadd((T)kCfCoarse, ch, fmadd((T)kCfFine1, own, -((T)kCfFine2 * inward)));
 }
 template <typename T>
 __device__ __forceinline__ T bc_value(const Geo &g, int64_t b, int d, int u, int v) {
@@ -646,7 +650,9 @@ __global__ __launch_bounds__(256) void k_cf_coarse(Geo g, const T *__restrict__ 
 // scheme): the residual of all 512 cells goes to LDS, then each of 64 threads
 // owns one parent cell and writes phi_c = mean(phi), old_c = phi_c and
 // rhs_c = mean(residual) (the coarse right-hand side is completed by
-// k_fas_rhs).  Extra blocks copy phi -> old on the leaf boxes of level l-1.
+// k_fas_rhs).  Extra blocks copy phi -> old on the listed leaf boxes of level
+// l-1 (those with a refined face or edge neighbour: the only leaf boxes whose
+// old values a prolongation reads).
 template <typename T>
 __global__ __launch_bounds__(256) void k_resid_restrict(Geo g, T *__restrict__ phi, T *__restrict__ rhs,
                                                         T *__restrict__ old, const T *__restrict__ chat,
@@ -797,6 +803,284 @@ __global__ __launch_bounds__(256) void k_prolong_cf(Geo g, T *__restrict__ phi, 
         int64_t idx = b * 512 + c * 256 + t;
         phi[idx] = (c ? f1 : f0) + ((T)0.25 * d0 + (T)0.25 * (dx + dy + dz));
     }
+}
+
+// ------------------------------------- prolongation fused into the up-sweep
+// The first red-black sweep after the prolongation of a level reads the
+// prolonged field only where the red and the black half-sweeps read it: the
+// red half reads every black cell (its own, and the neighbours' face layers
+// as ghosts) and, for the boundary ghosts of its face cells, the red face
+// cells on domain and refinement-boundary faces; the black half reads the
+// new red cells and, for the same boundary ghosts, its own black face cells
+// on those faces.  Every other prolonged value is overwritten unread.  So the
+// two half-sweeps below take the prolonged value f + p(delta) of each cell
+// they read on the fly, from the unprolonged field and the parent's
+// correction delta = phi - old, and nothing writes the prolongation itself:
+// the level ends the sweep with the values of the prolongation followed by
+// the two half-sweeps (same arithmetic in the same order, so the same bits).
+//
+// Correction region of a box: the parent's delta over the box's octant and
+// one layer around it, D[z][y][x] with x, y, z in 0..5 at coarse index
+// 4 o_a + x_a - 1 (o = the octant).  Cells outside the parent lie in the
+// parent's face or edge neighbours (corners are never read): the face layers
+// serve the box's own cells, the edges the prolongation of a same-level face
+// neighbour's face layer.  Outside the domain, delta is mirrored with the
+// sign of the homogeneous boundary condition (Dirichlet -, Neumann +).
+template <typename T>
+__device__ __forceinline__ T delta_region(const Geo &g, const T *__restrict__ phi, const T *__restrict__ old,
+                                          const int32_t *__restrict__ np, const int o[3], int e) {
+    int c[3] = {4 * o[0] + e % 6 - 1, 4 * o[1] + (e / 6) % 6 - 1, 4 * o[2] + e / 36 - 1};
+    int s[3], nout = 0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        s[a] = c[a] < 0 ? -1 : c[a] > 7 ? 1 : 0;
+        nout += s[a] != 0;
+    }
+    if (nout == 3) return (T)0;
+    bool neg = false;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (s[a] == 0) continue;
+        int fo = 13 + (a == 0 ? s[a] : a == 1 ? 3 * s[a] : 9 * s[a]);
+        if (np[fo] == -2) {  // the parent's face on this side is a domain face: mirror
+            int face = 2 * a + (s[a] > 0 ? 1 : 0);
+            c[a] = s[a] < 0 ? 0 : 7;
+            s[a] = 0;
+            if (g.bct[face] != 1) neg = !neg;
+        }
+    }
+    int32_t q = np[(s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1)];
+    if (q < 0) return (T)0;  // never read under proper nesting
+    int cc[3] = {c[0] & 7, c[1] & 7, c[2] & 7};
+    int64_t at = (int64_t)q * 512 + cs_idx3(cc);
+    T d = phi[at] - old[at];
+    return neg ? -d : d;
+}
+// Prolonged correction at fine cell (i, j, k) of the box, i, j, k in -1..8
+// (at most one outside 0..7: a face ghost), as k_prolong_cf adds it.
+template <typename T>
+__device__ __forceinline__ T prolonged(const T *D, int i, int j, int k) {
+    int x = (i + 2) >> 1, y = (j + 2) >> 1, z = (k + 2) >> 1;
+    int sx = ((i + 2) & 1) ? 1 : -1, sy = ((j + 2) & 1) ? 6 : -6, sz = ((k + 2) & 1) ? 36 : -36;
+    int at = (z * 6 + y) * 6 + x;
+    T d0 = D[at], dx = D[at + sx], dy = D[at + sy], dz = D[at + sz];
+    return (T)0.25 * d0 + (T)0.25 * (dx + dy + dz);
+}
+// The face cell of face d at tangential (u, v) and layer `layer` (0..7, or
+// -1 / 8 outside the box), as (i, j, k)
+__device__ __forceinline__ void face_cell(int d, int layer, int u, int v, int &i, int &j, int &k) {
+    int a = d >> 1, t1, t2;
+    tangential(a, t1, t2);
+    int c[3];
+    c[a] = layer;
+    c[t1] = u;
+    c[t2] = v;
+    i = c[0];
+    j = c[1];
+    k = c[2];
+}
+
+// Red half of the first sweep after the prolongation into boxes [b0,
+// b0+nbx) of level l >= 2 (128 threads, 2 cells each, XCD-aware mapping).
+// LDS: S the prolonged black cells, H the ghosts of the red face cells, D
+// the correction region.  Same-level ghost: the neighbour's black cell +
+// its prolonged correction; domain and refinement-boundary ghosts from the
+// prolonged red face cell (and, at a refinement boundary, the prolonged
+// black cell behind it).  Writes the red cells only.
+template <typename T>
+__global__ __launch_bounds__(128) void k_gsrb_pro_red(Geo g, T *__restrict__ phi, const T *__restrict__ rhs,
+                                                      const T *__restrict__ old, const T *__restrict__ chat,
+                                                      int64_t b0, int64_t nbx, T h2) {
+    using V = typename VecN<T, 2>::type;
+    __shared__ T S[256], H[192], D[216];
+    int64_t lb = xcd_map(blockIdx.x, nbx);
+    if (lb >= nbx) return;
+    int64_t b = b0 + lb;
+    const int t = threadIdx.x;
+    const FaceTab ft = face_tab(g, b);
+    const int64_t p = g.parent[b];
+    const int o[3] = {g.ijk[b * 4] & 1, g.ijk[b * 4 + 1] & 1, g.ijk[b * 4 + 2] & 1};
+    const int32_t *np = g.n27 + p * 27;
+    V blk = reinterpret_cast<const V *>(phi + b * 512 + 256)[t];
+    V bv = reinterpret_cast<const V *>(rhs + b * 512)[t];
+    T dv0 = delta_region<T>(g, phi, old, np, o, t);
+    T dv1 = t + 128 < 216 ? delta_region<T>(g, phi, old, np, o, t + 128) : (T)0;
+    // ghost entries e = t, t + 128 (< 192): face d, red face cell (u, v) at layer L
+    T raw[2], in_raw[2], ch[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        int e = t + 128 * r;
+        raw[r] = in_raw[r] = ch[r] = (T)0;
+        if (e >= 192) continue;
+        int d = e >> 5, q = e & 31, v = q >> 2, L = (d & 1) ? 7 : 0;
+        int u = 2 * (q & 3) + ((L + v) & 1);
+        int nb = pick6(ft.nb, d), i, j, k;
+        if (nb >= 0) {
+            face_cell(d, (d & 1) ? 0 : 7, u, v, i, j, k);  // mirrored cell in the neighbour
+            raw[r] = phi[(int64_t)nb * 512 + cs_idx(i, j, k)];
+        } else {
+            face_cell(d, L, u, v, i, j, k);
+            raw[r] = phi[b * 512 + cs_idx(i, j, k)];
+            if (nb == -1) {
+                face_cell(d, (d & 1) ? 6 : 1, u, v, i, j, k);
+                in_raw[r] = phi[b * 512 + cs_idx(i, j, k)];
+                ch[r] = chat[(int64_t)pick6(ft.slot, d) * 64 + v * 8 + u];
+            }
+        }
+    }
+    D[t] = dv0;
+    if (t + 128 < 216) D[t + 128] = dv1;
+    __syncthreads();
+    {
+        const T *bl = reinterpret_cast<const T *>(&blk);
+        V sv;
+        T *so = reinterpret_cast<T *>(&sv);
+#pragma unroll
+        for (int w = 0; w < 2; w++) {
+            int cq = 2 * t + w;
+            int m = cq & 3, j = (cq >> 2) & 7, k = cq >> 5;
+            int i = 2 * m + ((j + k + 1) & 1);
+            so[w] = bl[w] + prolonged<T>(D, i, j, k);
+        }
+        reinterpret_cast<V *>(S)[t] = sv;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        int e = t + 128 * r;
+        if (e >= 192) continue;
+        int d = e >> 5, q = e & 31, v = q >> 2, L = (d & 1) ? 7 : 0;
+        int u = 2 * (q & 3) + ((L + v) & 1);
+        int nb = pick6(ft.nb, d), i, j, k;
+        T gv;
+        if (nb >= 0) {
+            face_cell(d, (d & 1) ? 8 : -1, u, v, i, j, k);
+            gv = raw[r] + prolonged<T>(D, i, j, k);
+        } else {
+            face_cell(d, L, u, v, i, j, k);
+            T own = raw[r] + prolonged<T>(D, i, j, k);
+            if (nb == -2) {
+                gv = g.bct[d] == 1 ? own : dirichlet_ghost<T>(bc_value<T>(g, b, d, u, v), own);
+            } else {
+                face_cell(d, (d & 1) ? 6 : 1, u, v, i, j, k);
+                gv = cf_ghost<T>(ch[r], own, in_raw[r] + prolonged<T>(D, i, j, k));
+            }
+        }
+        H[e] = gv;
+    }
+    __syncthreads();
+    const T *bb = reinterpret_cast<const T *>(&bv);
+    V res;
+    T *out = reinterpret_cast<T *>(&res);
+#pragma unroll
+    for (int w = 0; w < 2; w++) {
+        int cq = 2 * t + w;
+        int m = cq & 3, j = (cq >> 2) & 7, k = cq >> 5;
+        int i = 2 * m + ((j + k) & 1);
+        int row = (k * 8 + j) * 4;
+        T xm = i > 0 ? S[row + ((i - 1) >> 1)] : H[0 * 32 + k * 4 + (j >> 1)];
+        T xp = i < 7 ? S[row + ((i + 1) >> 1)] : H[1 * 32 + k * 4 + (j >> 1)];
+        T ym = j > 0 ? S[row - 4 + m] : H[2 * 32 + k * 4 + m];
+        T yp = j < 7 ? S[row + 4 + m] : H[3 * 32 + k * 4 + m];
+        T zm = k > 0 ? S[row - 32 + m] : H[4 * 32 + j * 4 + m];
+        T zp = k < 7 ? S[row + 32 + m] : H[5 * 32 + j * 4 + m];
+        T sm = xm + xp + ym + yp + zm + zp;
+        out[w] = (sm - h2 * bb[w]) * (T)kSixth;
+    }
+    reinterpret_cast<V *>(phi + b * 512)[t] = res;
+}
+
+// Black half of the first sweep after the prolongation: as k_gsrb<1, T, 2>,
+// except that the ghosts of black face cells on domain and
+// refinement-boundary faces take the prolonged black face cell (its
+// unprolonged value + the correction, from the correction region, staged
+// only by boxes with such faces).
+template <typename T>
+__global__ __launch_bounds__(128) void k_gsrb_pro_black(Geo g, T *__restrict__ phi, const T *__restrict__ rhs,
+                                                        const T *__restrict__ old, const T *__restrict__ chat,
+                                                        int64_t b0, int64_t nbx, T h2) {
+    using V = typename VecN<T, 2>::type;
+    __shared__ T S[256], H[192], D[216];
+    int64_t lb = xcd_map(blockIdx.x, nbx);
+    if (lb >= nbx) return;
+    int64_t b = b0 + lb;
+    const int t = threadIdx.x;
+    const FaceTab ft = face_tab(g, b);
+    bool bnd = false;
+#pragma unroll
+    for (int d = 0; d < 6; d++) bnd = bnd || ft.nb[d] < 0;
+    V o = reinterpret_cast<const V *>(phi + b * 512)[t];
+    V bv = reinterpret_cast<const V *>(rhs + b * 512 + 256)[t];
+    T raw[2], in_new[2], ch[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        int e = t + 128 * r;
+        raw[r] = in_new[r] = ch[r] = (T)0;
+        if (e >= 192) continue;
+        int d = e >> 5, q = e & 31, v = q >> 2, L = (d & 1) ? 7 : 0;
+        int u = 2 * (q & 3) + ((L + v + 1) & 1);
+        int nb = pick6(ft.nb, d), i, j, k;
+        if (nb >= 0) {
+            face_cell(d, (d & 1) ? 0 : 7, u, v, i, j, k);
+            raw[r] = phi[(int64_t)nb * 512 + cs_idx(i, j, k)];  // the neighbour's new red cell
+        } else {
+            face_cell(d, L, u, v, i, j, k);
+            raw[r] = phi[b * 512 + cs_idx(i, j, k)];  // own black face cell, unprolonged
+            if (nb == -1) {
+                face_cell(d, (d & 1) ? 6 : 1, u, v, i, j, k);
+                in_new[r] = phi[b * 512 + cs_idx(i, j, k)];  // new red cell behind it
+                ch[r] = chat[(int64_t)pick6(ft.slot, d) * 64 + v * 8 + u];
+            }
+        }
+    }
+    if (bnd) {
+        const int64_t p = g.parent[b];
+        const int oc[3] = {g.ijk[b * 4] & 1, g.ijk[b * 4 + 1] & 1, g.ijk[b * 4 + 2] & 1};
+        const int32_t *np = g.n27 + p * 27;
+        T dv0 = delta_region<T>(g, phi, old, np, oc, t);
+        T dv1 = t + 128 < 216 ? delta_region<T>(g, phi, old, np, oc, t + 128) : (T)0;
+        D[t] = dv0;
+        if (t + 128 < 216) D[t + 128] = dv1;
+    }
+    reinterpret_cast<V *>(S)[t] = o;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        int e = t + 128 * r;
+        if (e >= 192) continue;
+        int d = e >> 5, q = e & 31, v = q >> 2, L = (d & 1) ? 7 : 0;
+        int u = 2 * (q & 3) + ((L + v + 1) & 1);
+        int nb = pick6(ft.nb, d), i, j, k;
+        T gv = raw[r];
+        if (nb < 0) {
+            face_cell(d, L, u, v, i, j, k);
+            T own = raw[r] + prolonged<T>(D, i, j, k);
+            if (nb == -2)
+                gv = g.bct[d] == 1 ? own : dirichlet_ghost<T>(bc_value<T>(g, b, d, u, v), own);
+            else
+                gv = cf_ghost<T>(ch[r], own, in_new[r]);
+        }
+        H[e] = gv;
+    }
+    __syncthreads();
+    const T *bb = reinterpret_cast<const T *>(&bv);
+    V res;
+    T *out = reinterpret_cast<T *>(&res);
+#pragma unroll
+    for (int w = 0; w < 2; w++) {
+        int cq = 2 * t + w;
+        int m = cq & 3, j = (cq >> 2) & 7, k = cq >> 5;
+        int i = 2 * m + ((j + k + 1) & 1);
+        int row = (k * 8 + j) * 4;
+        T xm = i > 0 ? S[row + ((i - 1) >> 1)] : H[0 * 32 + k * 4 + (j >> 1)];
+        T xp = i < 7 ? S[row + ((i + 1) >> 1)] : H[1 * 32 + k * 4 + (j >> 1)];
+        T ym = j > 0 ? S[row - 4 + m] : H[2 * 32 + k * 4 + m];
+        T yp = j < 7 ? S[row + 4 + m] : H[3 * 32 + k * 4 + m];
+        T zm = k > 0 ? S[row - 32 + m] : H[4 * 32 + j * 4 + m];
+        T zp = k < 7 ? S[row + 32 + m] : H[5 * 32 + j * 4 + m];
+        T sm = xm + xp + ym + yp + zm + zp;
+        out[w] = (sm - h2 * bb[w]) * (T)kSixth;
+    }
+    reinterpret_cast<V *>(phi + b * 512 + 256)[t] = res;
 }
 
 // Exact solve on each root box by fast diagonalisation: with the 1-D
@@ -1575,6 +1859,16 @@ void launch_prolong_cf(const Geo &g, T *phi, const T *old, int64_t b0, int64_t n
     hipLaunchKernelGGL(k_prolong_cf<T>, grid, dim3(256), 0, s, g, phi, old, b0, nb, chat, slots, s0, ns);
 }
 template <typename T>
+void launch_gsrb_pro(const Geo &g, T *phi, const T *rhs, const T *old, const T *chat, int64_t b0, int64_t nb,
+                     T h2, int colour, hipStream_t s) {
+    if (nb <= 0) return;
+    dim3 grid((unsigned)xcd_grid(nb));
+    if (colour == 0)
+        hipLaunchKernelGGL(k_gsrb_pro_red<T>, grid, dim3(128), 0, s, g, phi, rhs, old, chat, b0, nb, h2);
+    else
+        hipLaunchKernelGGL(k_gsrb_pro_black<T>, grid, dim3(128), 0, s, g, phi, rhs, old, chat, b0, nb, h2);
+}
+template <typename T>
 void launch_coarse(const Geo &g, T *phi, const T *rhs, const double *eig, int64_t b0, int64_t nroot,
                    double h, hipStream_t s) {
     hipLaunchKernelGGL(k_coarse<T>, dim3((unsigned)nroot), dim3(512), 0, s, g, phi, rhs, eig, b0, h);
@@ -1668,6 +1962,8 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
                                     int64_t, T, hipStream_t);                                    \
     template void launch_prolong_cf<T>(const Geo &, T *, const T *, int64_t, int64_t, T *,       \
                                        const int32_t *, int64_t, int64_t, hipStream_t);          \
+    template void launch_gsrb_pro<T>(const Geo &, T *, const T *, const T *, const T *, int64_t,   \
+                                     int64_t, T, int, hipStream_t);                              \
     template void launch_coarse<T>(const Geo &, T *, const T *, const double *, int64_t, int64_t, \
                                    double, hipStream_t);                                         \
     template void launch_restrict_phi<T>(const Geo &, T *, int64_t, int64_t, hipStream_t);        \

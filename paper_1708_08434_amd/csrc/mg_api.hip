@@ -52,6 +52,7 @@ Geo geo(const mg_tree *t, bool homogeneous) {
     g.cfq = t->d.cfq;
     g.xt = t->d.xt;
     g.pnb = t->d.pnb;
+    g.n27 = t->d.n27;
     g.slotx = t->d.slotx;
     g.ijk = t->d.ijk;
     g.parent = t->d.parent;
@@ -183,7 +184,7 @@ template <typename T> void fas_down(mg_tree *t, const Fields<T> &F, int l, bool 
     ensure_cf(t, F, l);
     double h = hlev(t, l);
     launch_resid_restrict<T>(F.g, F.phi, F.rhs, F.old, F.chat, lbeg(t, l), lcount(t, l),
-                             t->d.leaf + t->fstart[l - 1], t->fstart[l] - t->fstart[l - 1],
+                             t->d.oldcp + t->ostart[l - 1], t->ostart[l] - t->ostart[l - 1],
                              (T)(1.0 / (h * h)), stream_of(t));
     dirty(F, l - 1);
     ensure_cf(t, F, l - 1);
@@ -246,12 +247,39 @@ template <typename T> void bottom(mg_tree *t, const Fields<T> &F, int nd, int nu
     dirty(F, 2);
 }
 
-template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int nd, int nu) {
+// Prolongation into level l followed by nsweep sweeps.  With the fusion on
+// (and a half-sweep schedule on the level) the first sweep forms the
+// prolonged values it reads on the fly and no prolongation pass runs; the
+// result is the same bits.
+template <typename T> void prolong_smooth(mg_tree *t, const Fields<T> &F, int l, int nsweep) {
+    int variant = t->sched[sizeof(T) == 4 ? 1 : 0][l];
+    bool fused_sweeps = variant >= kGsrbFusedVariant && variant < kGsrbOctVariant;
+    if (!(t->fusion & MG_FUSE_PROLONG) || nsweep < 1 || l < 2 || fused_sweeps) {
+        prolong(t, F, l);
+        smooth(t, F, l, nsweep);
+        return;
+    }
+    ensure_cf(t, F, l);  // c_hat of level l reads level l-1 only, final here
+    double h = hlev(t, l);
+    for (int c = 0; c < 2; c++)
+        launch_gsrb_pro<T>(F.g, F.phi, F.rhs, F.old, F.chat, lbeg(t, l), lcount(t, l), (T)(h * h), c,
+                           stream_of(t));
+    dirty(F, l);
+    smooth(t, F, l, nsweep - 1);
+}
+
+// pro_top: the top level still needs the prolonged correction before its
+// first smoothing (the FMG pass's interpolation to a new finest level).
+template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int nd, int nu,
+                                  bool pro_top = false) {
     bool one = use_bottom<T>(t) && top >= 2;
     int low = one ? 3 : 2;
     bool deferred = false;
     for (int l = top; l >= low; l--) {
-        smooth(t, F, l, nd, deferred);
+        if (l == top && pro_top)
+            prolong_smooth(t, F, l, nd);
+        else
+            smooth(t, F, l, nd, deferred);
         deferred = l - 1 >= low && smooth_fuses_fas<T>(t, l - 1, nd);
         fas_down(t, F, l, deferred || (one && l == low));
     }
@@ -260,10 +288,7 @@ template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int n
     } else {
         coarse(t, F);
     }
-    for (int l = low; l <= top; l++) {
-        prolong(t, F, l);
-        smooth(t, F, l, nu);
-    }
+    for (int l = low; l <= top; l++) prolong_smooth(t, F, l, nu);
 }
 
 // FMG pass from the current (zero) field: FAS data top-down, root solve, then
@@ -281,10 +306,7 @@ template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int 
     } else {
         coarse(t, F);
     }
-    for (int l = low; l <= t->nlev; l++) {
-        prolong(t, F, l);
-        vcycle(t, F, l, nd, nu);
-    }
+    for (int l = low; l <= t->nlev; l++) vcycle(t, F, l, nd, nu, true);
 }
 
 // Per-tree leaf residual norms of the FP64 solution into result[slot + 2t],
@@ -735,6 +757,7 @@ int64_t nn_state_layout(char *base, mg_nn *nn) {
 
 hipStream_t nn_stream(const mg_nn *nn) { return (hipStream_t)nn->stream; }
 
+
 int require_nn(const mg_nn *nn) {
     if (!nn) {
         set_error("null network");
@@ -868,12 +891,14 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.cfq = (int32_t *)(base + t->off.cfq);
     d.xt = (int32_t *)(base + t->off.xt);
     d.pnb = (int32_t *)(base + t->off.pnb);
+    d.n27 = (int32_t *)(base + t->off.n27);
     d.slotx = (int32_t *)(base + t->off.slotx);
     d.ijk = (int32_t *)(base + t->off.ijk);
     d.parent = (int32_t *)(base + t->off.parent);
     d.refined = (int32_t *)(base + t->off.refined);
     d.leaf = (int32_t *)(base + t->off.leaf);
     d.cleaf = (int32_t *)(base + t->off.cleaf);
+    d.oldcp = (int32_t *)(base + t->off.oldcp);
     d.slots = (int32_t *)(base + t->off.slots);
     d.leaf_tree = (int32_t *)(base + t->off.leaf_tree);
     d.tree_off = (int32_t *)(base + t->off.tree_off);
@@ -919,12 +944,14 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     rc = rc ? rc : up(d.cfq, t->cfq.data(), t->cfq.size() * 4);
     rc = rc ? rc : up(d.xt, t->xt.data(), t->xt.size() * 4);
     rc = rc ? rc : up(d.pnb, t->pnb.data(), t->pnb.size() * 4);
+    rc = rc ? rc : up(d.n27, t->n27.data(), t->n27.size() * 4);
     rc = rc ? rc : up(d.slotx, t->slotx.data(), t->slotx.size() * 4);
     rc = rc ? rc : up(d.ijk, ijk4.data(), ijk4.size() * 4);
     rc = rc ? rc : up(d.parent, t->parent.data(), t->parent.size() * 4);
     rc = rc ? rc : up(d.refined, t->refined.data(), t->refined.size() * 4);
     rc = rc ? rc : up(d.leaf, t->leaf.data(), t->leaf.size() * 4);
     rc = rc ? rc : up(d.cleaf, t->cleaf.data(), t->cleaf.size() * 4);
+    rc = rc ? rc : up(d.oldcp, t->oldcp.data(), t->oldcp.size() * 4);
     rc = rc ? rc : up(d.slots, t->slots.data(), t->slots.size() * 4);
     rc = rc ? rc : up(d.leaf_tree, t->leaf_tree.data(), t->leaf_tree.size() * 4);
     rc = rc ? rc : up(d.tree_off, t->tree_off.data(), t->tree_off.size() * 4);
@@ -1568,6 +1595,18 @@ int mg_autotune(mg_tree *t, int precision, int reps, int32_t *schedule) {
     return rc;
 }
 
+int mg_set_fusion(mg_tree *t, int flags) {
+    if (!t || (flags & ~MG_FUSE_ALL)) {
+        set_error("mg_set_fusion: null tree or unknown flags");
+        return MG_EINVAL;
+    }
+    if (flags != t->fusion) {
+        for (auto &g : t->graphs) drop_graph(g);  // recorded sequences change
+        t->fusion = flags;
+    }
+    return MG_OK;
+}
+
 int mg_set_schedule(mg_tree *t, int precision, const int32_t *schedule) {
     if (!t || !schedule || (precision != MG_FP64 && precision != MG_MIXED)) {
         set_error("invalid schedule arguments");
@@ -1762,6 +1801,7 @@ int mg_nn_gradient(mg_nn *nn, int64_t nbox, const int32_t *idx, const float *x, 
     if (!rc) *loss = *nn->host_loss;
     return rc;
 }
+
 
 int mg_nn_adam(mg_nn *nn, const mg_adam_opts *o) {
     int rc = require_nn(nn);

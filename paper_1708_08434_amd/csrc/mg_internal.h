@@ -64,12 +64,14 @@ struct DevTables {
     int32_t *cfq = nullptr;      // [n][6]  coarser box across a refinement-boundary face
     int32_t *xt = nullptr;       // [n][6][4][2] faces of the face neighbours (fused sweep)
     int32_t *pnb = nullptr;      // [n][6] the parent's face neighbours
+    int32_t *n27 = nullptr;      // [n][27] same-level box at ijk + o (-1 coarser, -2 outside)
     int32_t *slotx = nullptr;    // [nslot][8] coarse-side indices of a slot's c_hat
     int32_t *ijk = nullptr;      // [n][4]  i, j, k, level
     int32_t *parent = nullptr;   // [n]
     int32_t *refined = nullptr;  // per-level lists of boxes with children
     int32_t *leaf = nullptr;     // per-level lists of boxes without children
     int32_t *cleaf = nullptr;    // leaf boxes whose parent cells a stopping test reads
+    int32_t *oldcp = nullptr;    // per level: leaf boxes whose phi_old a prolongation reads
     int32_t *slots = nullptr;    // [nslot][2] (box, face)
     int32_t *leaf_tree = nullptr;  // leaf-list positions grouped by tree (ascending within a tree)
     int32_t *tree_off = nullptr;   // [ntree+1] offsets into leaf_tree
@@ -107,6 +109,8 @@ struct mg_tree {
     int64_t lstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> refined, leaf;                 // box ids grouped by level
     std::vector<int32_t> cleaf;                         // leaf boxes restricted before a stopping test
+    std::vector<int32_t> oldcp;                         // per level: leaf boxes copied into phi_old
+    int64_t ostart[mg::kMaxLevel + 2] = {0};            // oldcp of level l: [ostart[l], ostart[l+1])
     int64_t rstart[mg::kMaxLevel + 2] = {0}, fstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> slots;                         // (box, face) per slot
     mg::RawArray<int32_t> n27;                          // [n][27] same-level box at ijk + o, -1, -2
@@ -119,7 +123,7 @@ struct mg_tree {
     mg_domain dom{};
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
-    struct { int64_t nbr, cfslot, cfq, xt, pnb, slotx, ijk, parent, refined, leaf, cleaf, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
+    struct { int64_t nbr, cfslot, cfq, xt, pnb, n27, slotx, ijk, parent, refined, leaf, cleaf, oldcp, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
              phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, swp, fas, total; } off{};
     // ---- fluid model (mg_fluid_bind): caller's second workspace ----
     void *fws = nullptr;
@@ -155,6 +159,7 @@ struct mg_tree {
     // the entry of level 1 (never smoothed) selects the bottom of the cycle:
     // 0 = levels 1 and 2 step by step, otherwise one launch (k_bottom)
     int32_t sched[2][mg::kMaxLevel + 2];
+    int32_t fusion = MG_FUSE_ALL;  // mg_set_fusion flags
     mg_tree() {
         for (auto &row : sched)
             for (auto &v : row) v = 3;

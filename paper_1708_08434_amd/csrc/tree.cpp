@@ -366,6 +366,30 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
             (t->child[8 * b] >= 0 ? t->refined : t->leaf).push_back((int32_t)b);
     }
     t->nleaf = (int64_t)t->leaf.size();
+    // per-level lists of the leaf boxes whose phi a down-leg copies into
+    // phi_old.  The prolongation into level l+1 reads phi - phi_old of level l
+    // only on the parents of level-(l+1) boxes and one cell layer around them,
+    // which lies in those parents' face and edge neighbours; the parents' own
+    // cells (all covered) get phi_old from the restriction.  So a leaf box
+    // needs the copy only when a same-level face or edge neighbour has children.
+    t->oldcp.clear();
+    for (int l = 1; l <= kMaxLevel + 1; l++) {
+        t->ostart[l] = (int64_t)t->oldcp.size();
+        if (l > t->nlev) continue;
+        for (int64_t q = t->fstart[l]; q < (int64_t)t->leaf.size() && t->lev[t->leaf[q]] == l; q++) {
+            int64_t b = t->leaf[q];
+            for (int o = 0; o < 27; o++) {
+                int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+                int m = (ox != 0) + (oy != 0) + (oz != 0);
+                if (m == 0 || m == 3) continue;
+                int32_t nb = n27[27 * b + o];
+                if (nb >= 0 && t->child[8 * (int64_t)nb] >= 0) {
+                    t->oldcp.push_back((int32_t)b);
+                    break;
+                }
+            }
+        }
+    }
     // leaf boxes whose parent cells a stopping test can read: a residual or a
     // c_hat reads a covered cell only next to a leaf cell of its own level,
     // so only across the parent's outer faces on the child's side, and only
@@ -427,11 +451,13 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.cfq = take(24 * n);
     t->off.xt = take(192 * n);
     t->off.pnb = take(24 * n);
+    t->off.n27 = take(108 * n);
     t->off.ijk = take(16 * n);
     t->off.parent = take(4 * n);
     t->off.refined = take(4 * (int64_t)t->refined.size());
     t->off.leaf = take(4 * t->nleaf);
     t->off.cleaf = take(4 * (int64_t)t->cleaf.size());
+    t->off.oldcp = take(4 * (int64_t)t->oldcp.size());
     t->off.slots = take(8 * t->nslot);
     t->off.slotx = take(32 * t->nslot);
     t->off.leaf_tree = take(4 * t->nleaf);

@@ -26,6 +26,8 @@ MG_FP64, MG_MIXED = 0, 1
 MG_OP_SMOOTH, MG_OP_FAS_DOWN, MG_OP_PROLONG, MG_OP_COARSE, MG_OP_RESTRICT_ALL, MG_OP_VCYCLE = \
     range(1, 7)
 MG_OP_F32 = 0x100
+MG_FUSE_PROLONG = 1
+MG_FUSE_ALL = 1
 MG_GSRB_VARIANTS = 14  # launch variants: 6, 7 fused sweeps, 8, 9 octets, 10-13 persistent
 MG_GSRB_FUSED = (6, 7)
 MG_GSRB_OCTET = (8, 9)
@@ -38,7 +40,7 @@ EXPORTS = ["mg_tree_create", "mg_tree_destroy", "mg_tree_info", "mg_tree_bind", 
            "mg_residual", "mg_tree_residuals", "mg_step", "mg_timing_enable", "mg_timing_read",
            "mg_autotune", "mg_set_schedule", "mg_stream_copy", "mg_efield", "mg_refine_scores",
            "mg_regrid_plan", "mg_transfer", "mg_fluid_workspace_bytes", "mg_fluid_bind",
-           "mg_fluid_stage", "mg_fluid_step", "mg_last_error"]
+           "mg_fluid_stage", "mg_fluid_step", "mg_set_fusion", "mg_last_error"]
 
 
 class mg_domain(ctypes.Structure):
@@ -123,6 +125,7 @@ def lib():
         L.mg_tree_residuals.argtypes = [P, P]
         L.mg_autotune.argtypes = [P, I32, I32, P]
         L.mg_set_schedule.argtypes = [P, I32, P]
+        L.mg_set_fusion.argtypes = [P, I32]
         L.mg_timing_enable.argtypes = [P, I32]
         L.mg_timing_read.argtypes = [P, ctypes.POINTER(mg_kernel_timing_t)]
         L.mg_stream_copy.argtypes = [P, P, I64, I32, P]
@@ -293,6 +296,10 @@ def mg_autotune(h, precision, reps, n_levels):
     out = np.zeros(n_levels, dtype=np.int32)
     check(lib().mg_autotune(h, precision, reps, _p(out)))
     return out
+
+
+def mg_set_fusion(h, flags):
+    check(lib().mg_set_fusion(h, int(flags)))
 
 
 def mg_set_schedule(h, precision, schedule):

@@ -63,3 +63,23 @@ def leaf_errors(phi, exact, leaf, h):
     vol = (h[leaf] ** 3)[:, None, None, None]
     l2 = np.sqrt((e * e * vol).sum())
     return l2, np.abs(e).max()
+
+
+def old_read_mask(level, ijk, tree, child):
+    """Per box: True where the multigrid's old copy of a coarse level is read
+    by the prolongation of the correction into the next finer level, i.e. the
+    box has children (its cells are covered and get the restricted value) or
+    a same-level face or edge neighbour (same tree) has children.  Elsewhere
+    the old field is scratch that the solver need not write."""
+    lv = np.asarray(level).reshape(-1)
+    ij = np.asarray(ijk).reshape(-1, 3)
+    tr = np.zeros(len(lv), dtype=np.int64) if tree is None else np.asarray(tree).reshape(-1)
+    refined = np.asarray(child).reshape(len(lv), -1)[:, 0] >= 0
+    keys = {(int(tr[q]), int(lv[q]), int(ij[q, 0]), int(ij[q, 1]), int(ij[q, 2])) for q in np.nonzero(refined)[0]}
+    offs = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)
+            if 0 < abs(a) + abs(b) + abs(c) <= 2]
+    out = refined.copy()
+    for q in np.nonzero(~refined)[0]:
+        t, l, i, j, k = int(tr[q]), int(lv[q]), int(ij[q, 0]), int(ij[q, 1]), int(ij[q, 2])
+        out[q] = any((t, l, i + a, j + b, k + c) in keys for a, b, c in offs)
+    return out

@@ -331,3 +331,37 @@ def test_gpu_time_step_full_size_matches_the_oracle():
     ne, ni = densities(o.index(O.IDX_LEVEL), o.index(O.IDX_IJK), w.length, 14, width=0.03)
     nxt = step_parity(bl, w.length, w.bc_type, w.bc_val, ne, ni, 2e-12, 1e-9)
     print("next dt", nxt, flush=True)
+
+
+@pytest.mark.gpu
+def test_gpu_step_reports_a_non_finite_density():
+    """A NaN density (a diverged step) is not silently carried on: the stage's
+    time-step bound is NaN and the step returns MG_ENOCONV."""
+    import torch
+    from paper_1708_08434_amd import mg as M
+    bl, L, bct, bcv = small_si_tree()
+    g, o = pair(bl, L, bct, bcv)
+    lv, ij = o.index(O.IDX_LEVEL), o.index(O.IDX_IJK)
+    ne, ni = densities(lv, ij, L, 15)
+    g.set_field(M.MG_FIELD_RHS, -E_CHARGE * (ni - ne) / EPS0)
+    g.fmg_solve()
+    g.fluid_bind(synthetic_n2_table(), EMAX)
+    leaf = o.leaf_mask()
+    q = int(np.nonzero(leaf)[0][len(np.nonzero(leaf)[0]) // 2])
+    bad = ne.copy()
+    bad[q, 3, 4, 5] = np.nan
+    face, norm = g.efield(to_numpy=False)
+    Ne, Ni = dev(g, bad), dev(g, ni)
+    Oe, Oi = torch.zeros_like(Ne), torch.zeros_like(Ni)
+    lim = M.mg_fluid_stage(g.h, face.data_ptr(), norm.data_ptr(), Ne.data_ptr(), Ni.data_ptr(),
+                           Ne.data_ptr(), Ni.data_ptr(), 1e-12, 0.0, 1.0, Oe.data_ptr(), Oi.data_ptr())
+    assert np.isnan(lim), lim
+    with pytest.raises(M.MGError) as e:
+        M.mg_fluid_step(g.h, Ne.data_ptr(), Ni.data_ptr(), 1e-12, 2)
+    assert e.value.code == M.MG_ENOCONV
+    # finite densities still step normally afterwards
+    g.set_field(M.MG_FIELD_RHS, -E_CHARGE * (ni - ne) / EPS0)
+    g.fmg_solve()
+    Ne, Ni = dev(g, ne), dev(g, ni)  # the failed step left NaN in both (updated in place)
+    dt = M.mg_fluid_step(g.h, Ne.data_ptr(), Ni.data_ptr(), 1e-12, 2)
+    assert np.isfinite(dt) and dt > 0
