@@ -96,6 +96,25 @@ int64_t mg_nn_train_bytes(int64_t nbox);
 int mg_nn_gradient(mg_nn *nn, int64_t nbox, const int32_t *idx, const float *x, const float *target,
                    void *ws, int64_t ws_bytes, double *loss);
 int mg_nn_get_grad(mg_nn *nn, float *grad);
+
+/*
+ * mg_nn_gradient_static - mg_nn_gradient without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight training loops, harnesses that forbid hipMalloc).  It allocates
+ * nothing: the training buffers are a file-scope device array of the library
+ * (MG_NN_STATIC_BYTES bytes, held by every GPU the library runs on until the
+ * process ends), whose address on the network's device is looked up on the
+ * first call there.  nbox must be 1..MG_NN_STATIC_MAX_BOXES (MG_EINVAL
+ * otherwise, with a message).  Every call on one GPU shares that GPU's array,
+ * which keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, other networks) race on it, so the caller serialises them.
+ * Nothing in it needs to start at zero (every buffer is written before it is
+ * read).  Results are those of mg_nn_gradient on the same arguments.
+ */
+#define MG_NN_STATIC_MAX_BOXES 64
+#define MG_NN_STATIC_BYTES 8422400
+int mg_nn_gradient_static(mg_nn *nn, int64_t nbox, const int32_t *idx, const float *x,
+                          const float *target, double *loss);
 typedef struct {
     double lr, beta1, beta2, eps;
 } mg_adam_opts;

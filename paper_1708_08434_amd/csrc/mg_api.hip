@@ -757,6 +757,24 @@ int64_t nn_state_layout(char *base, mg_nn *nn) {
 
 hipStream_t nn_stream(const mg_nn *nn) { return (hipStream_t)nn->stream; }
 
+// Forward with saved activations, backward and the fixed-order reduction of
+// the gradient into nn->grad, with the training buffers at ws (laid out by
+// nn_train_layout for nbox boxes); loss (host, may be NULL) synchronises.
+int nn_gradient_run(mg_nn *nn, int64_t nbox, const int32_t *idx, const float *x, const float *target,
+                    char *ws, double *loss) {
+    NnTrainWs w;
+    nn_train_layout(nbox, ws, &w);
+    hipStream_t s = nn_stream(nn);
+    launch_nn_forward(nn->prm, nn->pk, nbox, idx, x, w.y, w.a1, w.a2, s);
+    launch_nn_backward(nn->prm, nbox, idx, x, target, w, nn->grad, s);
+    int rc = hip_check(hipGetLastError(), "gradient launch");
+    if (rc || !loss) return rc;
+    rc = hip_check(hipMemcpyAsync(nn->host_loss, w.loss, sizeof(double), hipMemcpyDeviceToHost, s),
+                   "loss readback");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "stream synchronize");
+    if (!rc) *loss = *nn->host_loss;
+    return rc;
+}
 
 int require_nn(const mg_nn *nn) {
     if (!nn) {
@@ -1788,20 +1806,31 @@ int mg_nn_gradient(mg_nn *nn, int64_t nbox, const int32_t *idx, const float *x, 
         set_error("training workspace too small");
         return MG_ENOMEM;
     }
-    NnTrainWs w;
-    nn_train_layout(nbox, (char *)ws, &w);
-    hipStream_t s = nn_stream(nn);
-    launch_nn_forward(nn->prm, nn->pk, nbox, idx, x, w.y, w.a1, w.a2, s);
-    launch_nn_backward(nn->prm, nbox, idx, x, target, w, nn->grad, s);
-    if ((rc = hip_check(hipGetLastError(), "gradient launch"))) return rc;
-    if (!loss) return MG_OK;
-    rc = hip_check(hipMemcpyAsync(nn->host_loss, w.loss, sizeof(double), hipMemcpyDeviceToHost, s),
-                   "loss readback");
-    if (!rc) rc = hip_check(hipStreamSynchronize(s), "stream synchronize");
-    if (!rc) *loss = *nn->host_loss;
-    return rc;
+    return nn_gradient_run(nn, nbox, idx, x, target, (char *)ws, loss);
 }
 
+int mg_nn_gradient_static(mg_nn *nn, int64_t nbox, const int32_t *idx, const float *x,
+                          const float *target, double *loss) {
+    static_assert(MG_NN_STATIC_MAX_BOXES == kNnStaticBoxes && MG_NN_STATIC_BYTES == kNnStaticBytes,
+                  "static training buffers: header and library disagree");
+    int rc = require_nn(nn);
+    if (rc) return rc;
+    if (nbox <= 0 || !x || !target) {
+        set_error("invalid gradient arguments");
+        return MG_EINVAL;
+    }
+    if (nbox > MG_NN_STATIC_MAX_BOXES) {
+        set_error("mg_nn_gradient_static: nbox " + std::to_string(nbox) + " exceeds " +
+                  std::to_string(MG_NN_STATIC_MAX_BOXES) + " (use mg_nn_gradient with a workspace)");
+        return MG_EINVAL;
+    }
+    void *ws = nullptr;
+    if (nn_static_workspace(nn->device, &ws) != MG_OK) {
+        set_error("mg_nn_gradient_static: no device address for the static training buffers");
+        return MG_EHIP;
+    }
+    return nn_gradient_run(nn, nbox, idx, x, target, (char *)ws, loss);
+}
 
 int mg_nn_adam(mg_nn *nn, const mg_adam_opts *o) {
     int rc = require_nn(nn);

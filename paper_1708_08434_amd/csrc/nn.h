@@ -13,6 +13,21 @@ constexpr int kNnPacked = 8704;   // BF16 MFMA operand fragments of the weights
 constexpr int kNnFwdBlocks = 768; // persistent forward workgroups (3 per CU)
 constexpr int kNnWgradBlocks = 512;
 
+constexpr int64_t nn_align256(int64_t bytes) { return (bytes + 255) & ~(int64_t)255; }
+// Weight-gradient workgroups (one per box up to kNnWgradBlocks)
+constexpr int64_t nn_wgrad_blocks(int64_t nbox) { return nbox < kNnWgradBlocks ? nbox : kNnWgradBlocks; }
+// Bytes of the training buffers for nbox boxes (the layout of nn_train_layout)
+constexpr int64_t nn_train_bytes_of(int64_t nbox) {
+    return nn_align256(4 * 512 * nbox) + 2 * nn_align256(2 * 8192 * nbox) + 2 * nn_align256(4 * 8192 * nbox) +
+           nn_align256(8 * nbox) + nn_align256(4 * nn_wgrad_blocks(nbox) * kNnParams) + nn_align256(8);
+}
+// Allocation-free training (mg_nn_gradient_static): the largest batch and the
+// size of the file-scope device array that holds its buffers.
+constexpr int64_t kNnStaticBoxes = 64;
+constexpr int64_t kNnStaticBytes = nn_train_bytes_of(kNnStaticBoxes);
+// Device address of that array on `device` (looked up once per device).
+int nn_static_workspace(int device, void **out);
+
 // Per-box training buffers (the caller's workspace), see nn_train_layout.
 struct NnTrainWs {
     float *y, *gz1, *gz2, *part;

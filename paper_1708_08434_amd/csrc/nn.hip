@@ -21,7 +21,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
+#include <vector>
 
+#include "mg.h"
 #include "nn.h"
 
 namespace mg {
@@ -674,12 +677,12 @@ int64_t nn_train_layout(int64_t nbox, char *base, NnTrainWs *w) {
     int64_t o = 0;
     auto take = [&](int64_t bytes) {
         int64_t at = o;
-        o += (bytes + 255) & ~(int64_t)255;
+        o += nn_align256(bytes);
         return at;
     };
     int64_t oy = take(4 * 512 * nbox), oa1 = take(2 * 8192 * nbox), oa2 = take(2 * 8192 * nbox);
     int64_t og2 = take(4 * 8192 * nbox), og1 = take(4 * 8192 * nbox), olp = take(8 * nbox);
-    int64_t opart = take(4 * (int64_t)kNnWgradBlocks * kNnParams), oloss = take(8);
+    int64_t opart = take(4 * nn_wgrad_blocks(nbox) * kNnParams), oloss = take(8);
     if (base && w) {
         w->y = (float *)(base + oy);
         w->a1 = (uint16_t *)(base + oa1);
@@ -715,7 +718,7 @@ void launch_nn_backward(const float *prm, int64_t nbox, const int32_t *idx, cons
     float scale2 = (float)(2.0 / (512.0 * (double)nbox));
     hipLaunchKernelGGL(k_nn_bwd_act, dim3((unsigned)nbox), dim3(256), 0, s, w.y, target, idx, w.a1,
                        w.a2, prm, scale2, w.gz2, w.gz1, w.lossp);
-    int nblk = (int)(nbox < kNnWgradBlocks ? nbox : kNnWgradBlocks);
+    int nblk = (int)nn_wgrad_blocks(nbox);
     hipLaunchKernelGGL(k_nn_wgrad, dim3((unsigned)nblk), dim3(256), 0, s, x, w.y, target, idx, nbox,
                        scale2, w.a1, w.a2, w.gz2, w.gz1, w.part);
     hipLaunchKernelGGL(k_nn_reduce, dim3((kNnParams + 255) / 256), dim3(256), 0, s, w.part, nblk,
@@ -763,6 +766,35 @@ void launch_nn_targets(const double *phi, const double *ref, const float *scale,
     if (nleaf <= 0) return;
     hipLaunchKernelGGL(k_nn_targets, dim3((unsigned)nleaf), dim3(256), 0, s, phi, ref, scale, leaf,
                        target);
+}
+
+// ------------------------------------------------ allocation-free training
+// The training buffers of mg_nn_gradient_static: one file-scope array, which
+// every GPU the library runs on holds until the process ends.  In host code
+// the name `scratch` is only a stand-in for the device address; the address
+// on the current device comes from hipGetSymbolAddress, once per device.
+__device__ __align__(256) char scratch[kNnStaticBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;  // device address of `scratch`, per device
+}  // namespace
+
+int nn_static_workspace(int device, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) return MG_EHIP;
+        if (cur != device && hipSetDevice(device) != hipSuccess) return MG_EHIP;
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) return MG_EHIP;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return MG_OK;
 }
 
 }  // namespace mg

@@ -16,7 +16,8 @@ MG_NN_PARAMS = 7809
 EXPORTS = ["mg_nn_state_bytes", "mg_nn_create", "mg_nn_destroy", "mg_nn_set_params",
            "mg_nn_get_params", "mg_nn_forward", "mg_nn_train_bytes", "mg_nn_gradient",
            "mg_nn_get_grad", "mg_nn_adam", "mg_learned_bytes", "mg_nn_inputs", "mg_nn_targets",
-           "mg_learned_step", "mg_learned_solve"]
+           "mg_learned_step", "mg_learned_solve", "mg_nn_gradient_static"]
+MG_NN_STATIC_MAX_BOXES = 64
 
 
 class mg_adam_opts(ctypes.Structure):
@@ -47,6 +48,7 @@ def lib():
         L.mg_nn_train_bytes.argtypes = [I64]
         L.mg_nn_train_bytes.restype = I64
         L.mg_nn_gradient.argtypes = [P, I64, P, P, P, P, I64, P]
+        L.mg_nn_gradient_static.argtypes = [P, I64, P, P, P, P]
         L.mg_nn_get_grad.argtypes = [P, P]
         L.mg_nn_adam.argtypes = [P, ctypes.POINTER(mg_adam_opts)]
         L.mg_learned_bytes.argtypes = [P]
@@ -113,6 +115,15 @@ def mg_nn_gradient(h, nbox, idx_ptr, x_ptr, t_ptr, ws_ptr, ws_bytes, want_loss=T
     M.check(lib().mg_nn_gradient(h, int(nbox), ctypes.c_void_p(idx_ptr), ctypes.c_void_p(x_ptr),
                                  ctypes.c_void_p(t_ptr), ctypes.c_void_p(ws_ptr), int(ws_bytes),
                                  ctypes.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def mg_nn_gradient_static(h, nbox, idx_ptr, x_ptr, t_ptr, want_loss=True):
+    """mg_nn_gradient with the library's static training buffers (no
+    workspace, no allocation; nbox <= MG_NN_STATIC_MAX_BOXES)."""
+    loss = ctypes.c_double()
+    M.check(lib().mg_nn_gradient_static(h, int(nbox), ctypes.c_void_p(idx_ptr), ctypes.c_void_p(x_ptr),
+                                        ctypes.c_void_p(t_ptr), ctypes.byref(loss) if want_loss else None))
     return loss.value if want_loss else None
 
 
