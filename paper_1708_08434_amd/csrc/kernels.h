@@ -82,8 +82,14 @@ void launch_prolong_cf(const Geo &g, T *phi, const T *old, int64_t b0, int64_t n
 // ends with the values of prolongation + one sweep.  c_hat of the level
 // must be current.
 template <typename T>
-void launch_gsrb_pro(const Geo &g, T *phi, const T *rhs, const T *old, const T *chat, int64_t b0, int64_t nb,
+void launch_gsrb_pro(const Geo &g, T *phi, const T *rhs, const T *pad, const T *chat, int64_t b0, int64_t nb,
                      T h2, int colour, hipStream_t s);
+// The correction phi - old of the refined boxes refined[0..nref) of level l-1
+// as padded 10^3 blocks (pad[k * 1000 ..]) for launch_gsrb_pro on level l,
+// plus c_hat of the refinement-boundary slots [s0, s0+ns) of level l.
+template <typename T>
+void launch_delta_pad(const Geo &g, const T *phi, const T *old, const int32_t *refined, int64_t nref, T *pad,
+                      T *chat, const int32_t *slots, int64_t s0, int64_t ns, hipStream_t s);
 template <typename T>
 void launch_coarse(const Geo &g, T *phi, const T *rhs, const double *eig, int64_t b0, int64_t nroot,
                    double h, hipStream_t s);

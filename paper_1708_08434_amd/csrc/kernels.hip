@@ -819,43 +819,79 @@ __global__ __launch_bounds__(256) void k_prolong_cf(Geo g, T *__restrict__ phi, 
 // the level ends the sweep with the values of the prolongation followed by
 // the two half-sweeps (same arithmetic in the same order, so the same bits).
 //
-// Correction region of a box: the parent's delta over the box's octant and
-// one layer around it, D[z][y][x] with x, y, z in 0..5 at coarse index
-// 4 o_a + x_a - 1 (o = the octant).  Cells outside the parent lie in the
-// parent's face or edge neighbours (corners are never read): the face layers
-// serve the box's own cells, the edges the prolongation of a same-level face
-// neighbour's face layer.  Outside the domain, delta is mirrored with the
-// sign of the homogeneous boundary condition (Dirichlet -, Neumann +).
+// The correction is staged once per refined box P of level l-1 (k_delta_pad)
+// as a padded block of 10^3 values, x fastest: delta over P's cells and one
+// cell layer around them.  The layer comes from P's same-level face and edge
+// neighbours (corners are never read: a fine cell's stencil steps at most
+// one coarse cell along each of two axes from P's face layers), or outside
+// the domain from P's own cell mirrored, with the sign of the homogeneous
+// boundary condition (Dirichlet -, Neumann +), as k_prolong_cf takes it.  The
+// children of the k-th refined box of level l-1 are the boxes 8k .. 8k+7 of
+// level l (canonical order), octant = position & 7, and read the 6^3
+// sub-block 4 o + 0..5 of block k.
 template <typename T>
-__device__ __forceinline__ T delta_region(const Geo &g, const T *__restrict__ phi, const T *__restrict__ old,
-                                          const int32_t *__restrict__ np, const int o[3], int e) {
-    int c[3] = {4 * o[0] + e % 6 - 1, 4 * o[1] + (e / 6) % 6 - 1, 4 * o[2] + e / 36 - 1};
-    int s[3], nout = 0;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        s[a] = c[a] < 0 ? -1 : c[a] > 7 ? 1 : 0;
-        nout += s[a] != 0;
+__global__ __launch_bounds__(256) void k_delta_pad(Geo g, const T *__restrict__ phi, const T *__restrict__ old,
+                                                   const int32_t *__restrict__ refined, int64_t nref,
+                                                   T *__restrict__ pad, T *__restrict__ chat,
+                                                   const int32_t *__restrict__ slots, int64_t s0, int64_t ns) {
+    __shared__ int32_t NP[27];
+    int64_t blk = blockIdx.x;
+    int t = threadIdx.x;
+    int64_t nmain = xcd_grid(nref);
+    if (blk >= nmain) {  // c_hat of the refinement-boundary faces of level l (reads level l-1 only)
+        int64_t sl = 4 * (blk - nmain) + (t >> 6);
+        if (sl < ns) cf_face<T>(g, phi, chat, slots, s0 + sl, t & 63);
+        return;
     }
-    if (nout == 3) return (T)0;
-    bool neg = false;
+    int64_t k = xcd_map(blk, nref);
+    if (k >= nref) return;
+    int64_t P = refined[k];
+    if (t < 27) NP[t] = g.n27[P * 27 + t];
+    __syncthreads();
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        if (s[a] == 0) continue;
-        int fo = 13 + (a == 0 ? s[a] : a == 1 ? 3 * s[a] : 9 * s[a]);
-        if (np[fo] == -2) {  // the parent's face on this side is a domain face: mirror
-            int face = 2 * a + (s[a] > 0 ? 1 : 0);
-            c[a] = s[a] < 0 ? 0 : 7;
-            s[a] = 0;
-            if (g.bct[face] != 1) neg = !neg;
+    for (int r = 0; r < 4; r++) {
+        int e = t + 256 * r;
+        if (e >= 1000) break;
+        int c[3] = {e % 10 - 1, (e / 10) % 10 - 1, e / 100 - 1};
+        int sd[3], nout = 0;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            sd[a] = c[a] < 0 ? -1 : c[a] > 7 ? 1 : 0;
+            nout += sd[a] != 0;
         }
+        T v = (T)0;
+        if (nout < 3) {
+            bool neg = false;
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                if (sd[a] == 0) continue;
+                int fo = 13 + (a == 0 ? sd[a] : a == 1 ? 3 * sd[a] : 9 * sd[a]);
+                if (NP[fo] == -2) {  // P's face on this side is a domain face: mirror
+                    int face = 2 * a + (sd[a] > 0 ? 1 : 0);
+                    c[a] = sd[a] < 0 ? 0 : 7;
+                    sd[a] = 0;
+                    if (g.bct[face] != 1) neg = !neg;
+                }
+            }
+            int32_t q = NP[(sd[0] + 1) + 3 * (sd[1] + 1) + 9 * (sd[2] + 1)];
+            if (q >= 0) {  // always, for every value a prolongation reads (proper nesting)
+                int cc[3] = {c[0] & 7, c[1] & 7, c[2] & 7};
+                int64_t at = (int64_t)q * 512 + cs_idx3(cc);
+                T d = phi[at] - old[at];
+                v = neg ? -d : d;
+            }
+        }
+        pad[k * 1000 + e] = v;
     }
-    int32_t q = np[(s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1)];
-    if (q < 0) return (T)0;  // never read under proper nesting
-    int cc[3] = {c[0] & 7, c[1] & 7, c[2] & 7};
-    int64_t at = (int64_t)q * 512 + cs_idx3(cc);
-    T d = phi[at] - old[at];
-    return neg ? -d : d;
 }
+// Offset of the 6^3 correction region of the box at position lb of its level
+// (octant lb & 7) in its parent's padded block, and of region cell e
+// (x fastest) from there.
+__device__ __forceinline__ int pad_corner(int64_t lb) {
+    int o = (int)(lb & 7);
+    return 4 * ((o & 1) + 10 * ((o >> 1) & 1) + 100 * (o >> 2));
+}
+__device__ __forceinline__ int pad_off(int e) { return e % 6 + 10 * ((e / 6) % 6) + 100 * (e / 36); }
 // Prolonged correction at fine cell (i, j, k) of the box, i, j, k in -1..8
 // (at most one outside 0..7: a face ghost), as k_prolong_cf adds it.
 template <typename T>
@@ -889,7 +925,7 @@ __device__ __forceinline__ void face_cell(int d, int layer, int u, int v, int &i
 // black cell behind it).  Writes the red cells only.
 template <typename T>
 __global__ __launch_bounds__(128) void k_gsrb_pro_red(Geo g, T *__restrict__ phi, const T *__restrict__ rhs,
-                                                      const T *__restrict__ old, const T *__restrict__ chat,
+                                                      const T *__restrict__ pad, const T *__restrict__ chat,
                                                       int64_t b0, int64_t nbx, T h2) {
     using V = typename VecN<T, 2>::type;
     __shared__ T S[256], H[192], D[216];
@@ -898,13 +934,11 @@ __global__ __launch_bounds__(128) void k_gsrb_pro_red(Geo g, T *__restrict__ phi
     int64_t b = b0 + lb;
     const int t = threadIdx.x;
     const FaceTab ft = face_tab(g, b);
-    const int64_t p = g.parent[b];
-    const int o[3] = {g.ijk[b * 4] & 1, g.ijk[b * 4 + 1] & 1, g.ijk[b * 4 + 2] & 1};
-    const int32_t *np = g.n27 + p * 27;
     V blk = reinterpret_cast<const V *>(phi + b * 512 + 256)[t];
     V bv = reinterpret_cast<const V *>(rhs + b * 512)[t];
-    T dv0 = delta_region<T>(g, phi, old, np, o, t);
-    T dv1 = t + 128 < 216 ? delta_region<T>(g, phi, old, np, o, t + 128) : (T)0;
+    const T *pk = pad + (lb >> 3) * 1000 + pad_corner(lb);
+    T dv0 = pk[pad_off(t)];
+    T dv1 = t + 128 < 216 ? pk[pad_off(t + 128)] : (T)0;
     // ghost entries e = t, t + 128 (< 192): face d, red face cell (u, v) at layer L
     T raw[2], in_raw[2], ch[2];
 #pragma unroll
@@ -996,7 +1030,7 @@ __global__ __launch_bounds__(128) void k_gsrb_pro_red(Geo g, T *__restrict__ phi
 // only by boxes with such faces).
 template <typename T>
 __global__ __launch_bounds__(128) void k_gsrb_pro_black(Geo g, T *__restrict__ phi, const T *__restrict__ rhs,
-                                                        const T *__restrict__ old, const T *__restrict__ chat,
+                                                        const T *__restrict__ pad, const T *__restrict__ chat,
                                                         int64_t b0, int64_t nbx, T h2) {
     using V = typename VecN<T, 2>::type;
     __shared__ T S[256], H[192], D[216];
@@ -1033,11 +1067,9 @@ __global__ __launch_bounds__(128) void k_gsrb_pro_black(Geo g, T *__restrict__ p
         }
     }
     if (bnd) {
-        const int64_t p = g.parent[b];
-        const int oc[3] = {g.ijk[b * 4] & 1, g.ijk[b * 4 + 1] & 1, g.ijk[b * 4 + 2] & 1};
-        const int32_t *np = g.n27 + p * 27;
-        T dv0 = delta_region<T>(g, phi, old, np, oc, t);
-        T dv1 = t + 128 < 216 ? delta_region<T>(g, phi, old, np, oc, t + 128) : (T)0;
+        const T *pk = pad + (lb >> 3) * 1000 + pad_corner(lb);
+        T dv0 = pk[pad_off(t)];
+        T dv1 = t + 128 < 216 ? pk[pad_off(t + 128)] : (T)0;
         D[t] = dv0;
         if (t + 128 < 216) D[t + 128] = dv1;
     }
@@ -1859,14 +1891,21 @@ void launch_prolong_cf(const Geo &g, T *phi, const T *old, int64_t b0, int64_t n
     hipLaunchKernelGGL(k_prolong_cf<T>, grid, dim3(256), 0, s, g, phi, old, b0, nb, chat, slots, s0, ns);
 }
 template <typename T>
-void launch_gsrb_pro(const Geo &g, T *phi, const T *rhs, const T *old, const T *chat, int64_t b0, int64_t nb,
+void launch_delta_pad(const Geo &g, const T *phi, const T *old, const int32_t *refined, int64_t nref, T *pad,
+                      T *chat, const int32_t *slots, int64_t s0, int64_t ns, hipStream_t s) {
+    if (nref <= 0 && ns <= 0) return;
+    dim3 grid((unsigned)(xcd_grid(nref) + (ns + 3) / 4));
+    hipLaunchKernelGGL(k_delta_pad<T>, grid, dim3(256), 0, s, g, phi, old, refined, nref, pad, chat, slots, s0, ns);
+}
+template <typename T>
+void launch_gsrb_pro(const Geo &g, T *phi, const T *rhs, const T *pad, const T *chat, int64_t b0, int64_t nb,
                      T h2, int colour, hipStream_t s) {
     if (nb <= 0) return;
     dim3 grid((unsigned)xcd_grid(nb));
     if (colour == 0)
-        hipLaunchKernelGGL(k_gsrb_pro_red<T>, grid, dim3(128), 0, s, g, phi, rhs, old, chat, b0, nb, h2);
+        hipLaunchKernelGGL(k_gsrb_pro_red<T>, grid, dim3(128), 0, s, g, phi, rhs, pad, chat, b0, nb, h2);
     else
-        hipLaunchKernelGGL(k_gsrb_pro_black<T>, grid, dim3(128), 0, s, g, phi, rhs, old, chat, b0, nb, h2);
+        hipLaunchKernelGGL(k_gsrb_pro_black<T>, grid, dim3(128), 0, s, g, phi, rhs, pad, chat, b0, nb, h2);
 }
 template <typename T>
 void launch_coarse(const Geo &g, T *phi, const T *rhs, const double *eig, int64_t b0, int64_t nroot,
@@ -1964,6 +2003,8 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
                                        const int32_t *, int64_t, int64_t, hipStream_t);          \
     template void launch_gsrb_pro<T>(const Geo &, T *, const T *, const T *, const T *, int64_t,   \
                                      int64_t, T, int, hipStream_t);                              \
+    template void launch_delta_pad<T>(const Geo &, const T *, const T *, const int32_t *, int64_t, \
+                                      T *, T *, const int32_t *, int64_t, int64_t, hipStream_t);   \
     template void launch_coarse<T>(const Geo &, T *, const T *, const double *, int64_t, int64_t, \
                                    double, hipStream_t);                                         \
     template void launch_restrict_phi<T>(const Geo &, T *, int64_t, int64_t, hipStream_t);        \

@@ -259,10 +259,16 @@ template <typename T> void prolong_smooth(mg_tree *t, const Fields<T> &F, int l,
         smooth(t, F, l, nsweep);
         return;
     }
-    ensure_cf(t, F, l);  // c_hat of level l reads level l-1 only, final here
+    // the parents' corrections as padded blocks, with c_hat of level l (both
+    // read level l-1 only, final here)
+    T *pad = (T *)t->d.dpad;
+    int64_t s0 = t->sstart[l], ns = t->sstart[l + 1] - t->sstart[l];
+    launch_delta_pad<T>(F.g, F.phi, F.old, t->d.refined + t->rstart[l - 1], t->rstart[l] - t->rstart[l - 1], pad,
+                        F.chat, t->d.slots, s0, ns, stream_of(t));
+    F.cf_valid[l] = true;
     double h = hlev(t, l);
     for (int c = 0; c < 2; c++)
-        launch_gsrb_pro<T>(F.g, F.phi, F.rhs, F.old, F.chat, lbeg(t, l), lcount(t, l), (T)(h * h), c,
+        launch_gsrb_pro<T>(F.g, F.phi, F.rhs, pad, F.chat, lbeg(t, l), lcount(t, l), (T)(h * h), c,
                            stream_of(t));
     dirty(F, l);
     smooth(t, F, l, nsweep - 1);
@@ -940,6 +946,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.chat32 = (float *)(base + t->off.chat32);
     d.swp = (void *)(base + t->off.swp);
     d.fas = (void *)(base + t->off.fas);
+    d.dpad = (void *)(base + t->off.dpad);
     if (!t->host_result) {
         int rc = hip_check(hipHostMalloc((void **)&t->host_result, 4 * t->ntree * sizeof(double)),
                            "pinned host buffer");

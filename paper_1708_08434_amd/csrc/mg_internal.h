@@ -96,6 +96,7 @@ struct DevTables {
     float *chat32 = nullptr;
     void *swp = nullptr;         // [n][512] FP64 (or FP32): target of the fused sweeps
     void *fas = nullptr;         // [n][512] FP64 (or FP32): FAS right-hand sides formed by a fused sweep
+    void *dpad = nullptr;        // [refined boxes of a level][1000] FP64 (or FP32): padded corrections
 };
 
 }  // namespace mg
@@ -124,7 +125,7 @@ struct mg_tree {
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
     struct { int64_t nbr, cfslot, cfq, xt, pnb, n27, slotx, ijk, parent, refined, leaf, cleaf, oldcp, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
-             phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, swp, fas, total; } off{};
+             phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, swp, fas, dpad, total; } off{};
     // ---- fluid model (mg_fluid_bind): caller's second workspace ----
     void *fws = nullptr;
     int32_t ntab = 0;

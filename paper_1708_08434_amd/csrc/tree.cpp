@@ -482,6 +482,11 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.chat32 = take(4 * 64 * t->nslot);
     t->off.swp = take(8 * kCells * n);
     t->off.fas = take(8 * kCells * n);
+    {  // padded correction blocks of the refined boxes of one level
+        int64_t mref = 0;
+        for (int l = 1; l <= t->nlev; l++) mref = std::max(mref, t->rstart[l + 1] - t->rstart[l]);
+        t->off.dpad = take(8 * 1000 * mref);
+    }
     t->off.total = o;
     return MG_OK;
 }
