@@ -145,6 +145,29 @@ enum { MG_FIELD_PHI = 0, MG_FIELD_RHS = 1, MG_FIELD_OLD = 2, MG_FIELD_BCVAL = 3,
 int mg_field_set(mg_tree *t, int which, const double *dev);
 int mg_field_get(const mg_tree *t, int which, double *dev);
 
+/*
+ * mg_field - borrowed device pointer to a field's own storage in the bound
+ * workspace (no copy), for callers that read or write the fields in place.
+ *   which          MG_FIELD_PHI, _RHS, _OLD (dtype MG_DTYPE_F64), MG_FIELD_E32,
+ *                  _R32, _OLD32 (MG_DTYPE_F32), MG_FIELD_BCVAL (F64, only with
+ *                  per_cell_bc)
+ *   dtype          must be the field's storage type (MG_EINVAL otherwise)
+ *   dev_ptr        out: device pointer; valid until rebind or destroy
+ *   n_elems        out (may be NULL): number of elements
+ *   level_offsets  out (may be NULL): [n_levels + 1], first box of each level
+ *                  in canonical order (level l: [lo[l-1], lo[l]))
+ * Cell fields hold box b (canonical order) at elements [512 b, 512 b + 512),
+ * and cell (i, j, k) of a box at ((i + j + k) & 1) * 256 + (k * 8 + j) * 4 +
+ * (i >> 1): the colour-split order the red-black sweeps stream (the 256
+ * cells with even i + j + k first), not the natural order of mg_field_set.
+ * BCVAL is [n][6][64] as in mg_field_set.  The solver keeps values derived
+ * from PHI (the refinement-boundary interpolation); a call to mg_field marks
+ * them stale, so a caller that writes through the pointer calls mg_field
+ * again after writing and before the next solve call.
+ */
+enum { MG_DTYPE_F64 = 0, MG_DTYPE_F32 = 1 };
+int mg_field(mg_tree *t, int which, int dtype, void **dev_ptr, int64_t *n_elems, int64_t *level_offsets);
+
 /* Solver options and statistics.
  * MG_FP64: the multigrid cycles run on the FP64 solution.
  * MG_MIXED: iterative refinement.  Each step computes the FP64 leaf residual
@@ -153,8 +176,11 @@ int mg_field_get(const mg_tree *t, int which, double *dev);
  *   correction problem L e = r with homogeneous boundary data, solves that
  *   in FP32 from e = 0 (an FMG pass in the first step, one V-cycle after),
  *   and updates phi += e in FP64.  The root solve stays FP64; the stopping
- *   test is the FP64 one, so the result meets the same tolerance. */
-enum { MG_FP64 = 0, MG_MIXED = 1 };
+ *   test is the FP64 one, so the result meets the same tolerance.
+ * MG_LEARNED: the FP64 solve with a learned correction step after every
+ *   V-cycle that does not meet the tolerance (include/mg_nn.h: the network
+ *   and its workspace are attached with mg_nn_bind; mg_fmg_solve only). */
+enum { MG_FP64 = 0, MG_MIXED = 1, MG_LEARNED = 2 };
 typedef struct {
     int32_t precision;   /* MG_FP64                                          */
     int32_t n_down;      /* Gauss-Seidel sweeps before restriction (2)       */
@@ -185,6 +211,9 @@ typedef struct {
     double beff_l2;            /* norm of the residual of phi = 0              */
     double rel_hist[64];       /* after the FMG pass [0] and each V-cycle      */
     double t_ms;               /* host wall time of the call                   */
+    int32_t nn_accepted;       /* MG_LEARNED: learned steps kept               */
+    int32_t nn_fell_back;      /* MG_LEARNED: cycle at which the learned step
+                                  was dropped for plain V-cycles, 0 if never   */
 } mg_solve_stats;
 
 void mg_default_opts(mg_solve_opts *o);
@@ -321,7 +350,13 @@ int mg_fluid_stage(mg_tree *t, const double *e_face, const double *e_norm, doubl
                    double *out_i, double *dt_limit);
 int mg_fluid_step(mg_tree *t, double *ne, double *ni, double dt, int32_t n_vcycles, double *dt_next);
 
-/* Relative residual, L2 and max norms of the current phi (leaf cells). */
+/* Relative residual, L2 and max norms of the current phi on the leaf cells,
+ * as the stopping test of mg_fmg_solve takes them (the survey's reading of
+ * the residual norm, which the paper does not give): covered cells first
+ * reset to the mean of their children; r = b - L phi with the ghosts of the
+ * solver; l2 = sqrt(sum r^2 h^3) over leaf cells (volume-weighted); linf =
+ * max |r|; rel = l2 divided by the l2 of the residual of phi = 0 (boundary
+ * data included), for a forest the largest over the trees.  Synchronises. */
 int mg_residual(mg_tree *t, double *rel, double *l2, double *linf);
 
 /*

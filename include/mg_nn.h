@@ -156,6 +156,15 @@ typedef struct {
 int mg_learned_solve(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes, const mg_solve_opts *o,
                      mg_solve_stats *s, mg_learned_stats *ls);
 
+/*
+ * mg_nn_bind - attach a network and its learned-step workspace (as for
+ * mg_learned_solve) to a tree, so that mg_fmg_solve with precision
+ * MG_LEARNED runs that solve (its stats carry nn_accepted and nn_fell_back).
+ * nn = NULL detaches.  Both stay owned by the caller and must outlive the
+ * binding.  MG_EINVAL/MG_ENOMEM as mg_learned_solve checks them.
+ */
+int mg_nn_bind(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes);
+
 #ifdef __cplusplus
 }
 #endif

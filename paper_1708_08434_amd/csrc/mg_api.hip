@@ -321,8 +321,7 @@ template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int 
 void norms_launch(mg_tree *t, int slot, float *r32) {
     Fields<double> F = f64(t);
     ensure_cf_all(t, F);
-    launch_leaf_norms(F.g, F.phi, F.rhs, F.chat, t->d.leaf, t->nleaf, t->d.partial, r32,
-                      stream_of(t));
+    launch_leaf_norms(F.g, F.phi, F.rhs, F.chat, t->d.leaf, t->nleaf, t->d.partial, r32, stream_of(t));
     launch_reduce_trees(t->d.partial, t->d.leaf_tree, t->d.chunk, (int64_t)t->chunk.size() / 3, t->d.choff,
                         t->ntree, t->d.part2, t->d.result + slot, stream_of(t));
 }
@@ -569,7 +568,8 @@ int require_bound(const mg_tree *t) {
 }
 
 int check_opts(const mg_solve_opts *o) {
-    if (!o || (o->precision != MG_FP64 && o->precision != MG_MIXED) || o->n_down < 0 ||
+    if (!o || (o->precision != MG_FP64 && o->precision != MG_MIXED && o->precision != MG_LEARNED) ||
+        o->n_down < 0 ||
         o->n_up < 0 || o->max_cycles < 0 || o->max_cycles > 10000 || !(o->rel_tol >= 0) ||
         (o->final_check_only != 0 && o->final_check_only != 1)) {
         set_error("invalid solver options");
@@ -1039,10 +1039,60 @@ int mg_field_get(const mg_tree *t, int which, double *dev) {
     return hip_check(hipGetLastError(), "field get");
 }
 
+int mg_field(mg_tree *t, int which, int dtype, void **dev_ptr, int64_t *n_elems, int64_t *level_offsets) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!dev_ptr) {
+        set_error("mg_field: null dev_ptr");
+        return MG_EINVAL;
+    }
+    void *p = nullptr;
+    int want = MG_DTYPE_F64;
+    int64_t n = (int64_t)512 * t->n;
+    switch (which) {
+    case MG_FIELD_PHI: p = t->d.phi; break;
+    case MG_FIELD_RHS: p = t->d.rhs; break;
+    case MG_FIELD_OLD: p = t->d.old; break;
+    case MG_FIELD_E32: p = t->d.e32; want = MG_DTYPE_F32; break;
+    case MG_FIELD_R32: p = t->d.r32; want = MG_DTYPE_F32; break;
+    case MG_FIELD_OLD32: p = t->d.old32; want = MG_DTYPE_F32; break;
+    case MG_FIELD_BCVAL:
+        if (!t->d.bcval) {
+            set_error("mg_field: no per-cell boundary data (per_cell_bc not set)");
+            return MG_EINVAL;
+        }
+        p = t->d.bcval;
+        n = (int64_t)6 * 64 * t->n;
+        break;
+    default: set_error("mg_field: unknown field"); return MG_EINVAL;
+    }
+    if (dtype != want) {
+        set_error("mg_field: dtype does not match the field's storage type");
+        return MG_EINVAL;
+    }
+    // the caller may write through the pointer: cached derived values are stale
+    dirty_all(f64(t));
+    dirty_all(f32(t));
+    *dev_ptr = p;
+    if (n_elems) *n_elems = n;
+    if (level_offsets)
+        for (int l = 0; l <= t->nlev; l++) level_offsets[l] = t->lstart[l];
+    return MG_OK;
+}
+
 int mg_fmg_solve(mg_tree *t, const mg_solve_opts *o, mg_solve_stats *st) {
     int rc = require_bound(t);
     if (rc) return rc;
     if ((rc = check_opts(o))) return rc;
+    if (o->precision == MG_LEARNED) {
+        if (!t->nn) {
+            set_error("MG_LEARNED: no network bound to the tree (mg_nn_bind)");
+            return MG_ESTATE;
+        }
+        mg_solve_opts f = *o;
+        f.precision = MG_FP64;
+        return mg_learned_solve(t, t->nn, t->nn_ws, t->nn_ws_bytes, &f, st, nullptr);
+    }
     mg_solve_stats local;
     mg_solve_stats *s = st ? st : &local;
     std::memset(s, 0, sizeof *s);
@@ -1071,6 +1121,10 @@ int mg_fmg_solve(mg_tree *t, const mg_solve_opts *o, mg_solve_stats *st) {
 int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *st) {
     int rc = require_bound(t);
     if (rc) return rc;
+    if (o && o->precision == MG_LEARNED) {
+        set_error("mg_vcycle: learned steps run inside mg_fmg_solve (MG_LEARNED)");
+        return MG_EINVAL;
+    }
     if ((rc = check_opts(o))) return rc;
     if (!st && o->precision == MG_FP64 && n_cycles > 0) return vcycles_no_stats(t, o, n_cycles);
     mg_solve_stats local;
@@ -1960,7 +2014,25 @@ int mg_learned_solve(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes, const mg
     restrict_all(t, F);  // every covered cell: the mean of its children
     rc = hip_check(hipGetLastError(), "kernel launch");
     s->t_ms = now_ms() - t0;
+    s->nn_accepted = lst->accepted;
+    s->nn_fell_back = lst->fallback_cycle;
     return s->status = rc;
+}
+
+int mg_nn_bind(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!nn) {
+        t->nn = nullptr;
+        t->nn_ws = nullptr;
+        t->nn_ws_bytes = 0;
+        return MG_OK;
+    }
+    if ((rc = require_nn(nn)) || (rc = check_learned_ws(t, ws, ws_bytes))) return rc;
+    t->nn = nn;
+    t->nn_ws = ws;
+    t->nn_ws_bytes = ws_bytes;
+    return MG_OK;
 }
 
 }  // extern "C"

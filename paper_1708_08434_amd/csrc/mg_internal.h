@@ -101,6 +101,8 @@ struct DevTables {
 
 }  // namespace mg
 
+struct mg_nn;
+
 struct mg_tree {
     // ---- host tables (canonical order) ----
     int64_t n = 0;
@@ -161,6 +163,10 @@ struct mg_tree {
     // 0 = levels 1 and 2 step by step, otherwise one launch (k_bottom)
     int32_t sched[2][mg::kMaxLevel + 2];
     int32_t fusion = MG_FUSE_ALL;  // mg_set_fusion flags
+    // ---- network of MG_LEARNED solves (mg_nn_bind; caller-owned) ----
+    mg_nn *nn = nullptr;
+    void *nn_ws = nullptr;
+    int64_t nn_ws_bytes = 0;
     mg_tree() {
         for (auto &row : sched)
             for (auto &v : row) v = 3;

@@ -22,7 +22,8 @@ MG_IDX_ORDER, MG_IDX_LEVEL, MG_IDX_IJK, MG_IDX_TREE, MG_IDX_PARENT, MG_IDX_CHILD
     MG_IDX_CFQ = range(8)
 MG_FIELD_PHI, MG_FIELD_RHS, MG_FIELD_OLD, MG_FIELD_BCVAL, MG_FIELD_E32, MG_FIELD_R32, \
     MG_FIELD_OLD32 = range(7)
-MG_FP64, MG_MIXED = 0, 1
+MG_FP64, MG_MIXED, MG_LEARNED = 0, 1, 2
+MG_DTYPE_F64, MG_DTYPE_F32 = 0, 1
 MG_OP_SMOOTH, MG_OP_FAS_DOWN, MG_OP_PROLONG, MG_OP_COARSE, MG_OP_RESTRICT_ALL, MG_OP_VCYCLE = \
     range(1, 7)
 MG_OP_F32 = 0x100
@@ -40,7 +41,7 @@ EXPORTS = ["mg_tree_create", "mg_tree_destroy", "mg_tree_info", "mg_tree_bind", 
            "mg_residual", "mg_tree_residuals", "mg_step", "mg_timing_enable", "mg_timing_read",
            "mg_autotune", "mg_set_schedule", "mg_stream_copy", "mg_efield", "mg_refine_scores",
            "mg_regrid_plan", "mg_transfer", "mg_fluid_workspace_bytes", "mg_fluid_bind",
-           "mg_fluid_stage", "mg_fluid_step", "mg_set_fusion", "mg_last_error"]
+           "mg_fluid_stage", "mg_fluid_step", "mg_set_fusion", "mg_field", "mg_last_error"]
 
 
 class mg_domain(ctypes.Structure):
@@ -67,13 +68,14 @@ class mg_solve_stats(ctypes.Structure):
     _fields_ = [("n_vcycles", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("rel_res", ctypes.c_double), ("l2", ctypes.c_double), ("linf", ctypes.c_double),
                 ("beff_l2", ctypes.c_double), ("rel_hist", ctypes.c_double * 64),
-                ("t_ms", ctypes.c_double)]
+                ("t_ms", ctypes.c_double), ("nn_accepted", ctypes.c_int32),
+                ("nn_fell_back", ctypes.c_int32)]
 
     def as_dict(self):
         n = self.n_vcycles
         return dict(n_vcycles=n, status=self.status, rel=self.rel_res, l2=self.l2,
                     linf=self.linf, beff=self.beff_l2, hist=np.array(self.rel_hist[:n + 1]),
-                    t_ms=self.t_ms)
+                    t_ms=self.t_ms, nn_accepted=self.nn_accepted, nn_fell_back=self.nn_fell_back)
 
 
 class mg_kernel_timing_t(ctypes.Structure):
@@ -104,6 +106,7 @@ def lib():
         L.mg_tree_index.argtypes = [P, I32, P]
         L.mg_field_set.argtypes = [P, I32, P]
         L.mg_field_get.argtypes = [P, I32, P]
+        L.mg_field.argtypes = [P, I32, I32, ctypes.POINTER(P), ctypes.POINTER(I64), P]
         L.mg_default_opts.argtypes = [ctypes.POINTER(mg_solve_opts)]
         L.mg_default_opts.restype = None
         L.mg_fmg_solve.argtypes = [P, ctypes.POINTER(mg_solve_opts), ctypes.POINTER(mg_solve_stats)]
@@ -189,6 +192,18 @@ def mg_field_set(h, which, dev_ptr):
 
 def mg_field_get(h, which, dev_ptr):
     check(lib().mg_field_get(h, which, ctypes.c_void_p(dev_ptr)))
+
+
+def mg_field(h, which, dtype, nlev=None):
+    """Borrowed device pointer to a field's own storage (colour-split cell
+    order), its element count and, if nlev is given, the first box of each
+    level (nlev + 1 entries)."""
+    ptr = ctypes.c_void_p()
+    n = ctypes.c_int64()
+    lo = (ctypes.c_int64 * (nlev + 1))() if nlev is not None else None
+    check(lib().mg_field(h, int(which), int(dtype), ctypes.byref(ptr), ctypes.byref(n),
+                         None if lo is None else ctypes.cast(lo, ctypes.c_void_p)))
+    return ptr.value, n.value, (list(lo) if lo is not None else None)
 
 
 def mg_default_opts():

@@ -16,7 +16,7 @@ MG_NN_PARAMS = 7809
 EXPORTS = ["mg_nn_state_bytes", "mg_nn_create", "mg_nn_destroy", "mg_nn_set_params",
            "mg_nn_get_params", "mg_nn_forward", "mg_nn_train_bytes", "mg_nn_gradient",
            "mg_nn_get_grad", "mg_nn_adam", "mg_learned_bytes", "mg_nn_inputs", "mg_nn_targets",
-           "mg_learned_step", "mg_learned_solve", "mg_nn_gradient_static"]
+           "mg_learned_step", "mg_learned_solve", "mg_nn_gradient_static", "mg_nn_bind"]
 MG_NN_STATIC_MAX_BOXES = 64
 
 
@@ -56,6 +56,7 @@ def lib():
         L.mg_nn_inputs.argtypes = [P, P, P]
         L.mg_nn_targets.argtypes = [P, P, P, P]
         L.mg_learned_step.argtypes = [P, P, P, I64, P]
+        L.mg_nn_bind.argtypes = [P, P, P, I64]
         L.mg_learned_solve.argtypes = [P, P, P, I64, ctypes.POINTER(M.mg_solve_opts),
                                        ctypes.POINTER(M.mg_solve_stats),
                                        ctypes.POINTER(mg_learned_stats)]
@@ -160,6 +161,12 @@ def mg_learned_solve(tree_h, nn_h, ws_ptr, ws_bytes, opts, raise_on_error=True):
     if raise_on_error:
         M.check(rc)
     return st, ls
+
+
+def mg_nn_bind(tree_h, nn_h, ws_ptr, ws_bytes):
+    """Attach a network and its learned-step workspace to a tree for
+    mg_fmg_solve(precision=MG_LEARNED) (nn_h None detaches)."""
+    M.check(lib().mg_nn_bind(tree_h, nn_h, ctypes.c_void_p(ws_ptr), int(ws_bytes)))
 
 
 # --------------------------------------------------------- convenience

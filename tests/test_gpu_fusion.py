@@ -109,3 +109,28 @@ def test_fusion_flags_are_checked():
     with pytest.raises(M.MGError) as e:
         M.mg_set_fusion(g.h, 1 << 20)
     assert e.value.code == M.MG_EINVAL
+
+
+@pytest.mark.timeout(300)
+def test_fusion_full_size_streamer_gives_the_same_bits():
+    """The benchmark streamer tree (10,825 boxes, 9,472 leaf boxes): long
+    enough that the persistent norm workgroups each walk several leaf boxes
+    and the fused prolongation runs on levels of thousands of boxes; FP64 and
+    mixed FMG solves with every flag against none."""
+    from workloads import c2
+    w = c2()
+    g = M.Tree.from_workload(w)
+    rhs = w.rhs(g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK))
+    say("fusion full size", g.n, "boxes", int(g.info.n_leaf_boxes), "leaf boxes")
+    out = {}
+    for flags in (0, M.MG_FUSE_ALL):
+        M.mg_set_fusion(g.h, flags)
+        g.set_field(M.MG_FIELD_RHS, rhs)
+        res = []
+        for prec in (M.MG_FP64, M.MG_MIXED):
+            st = g.fmg_solve(precision=prec)
+            res.append((st["n_vcycles"], tuple(st["hist"]), g.get_field(M.MG_FIELD_PHI)))
+        out[flags] = res
+    for (na, ha, pa), (nb, hb, pb) in zip(out[0], out[M.MG_FUSE_ALL]):
+        assert na == nb and ha == hb, (ha, hb)
+        assert np.array_equal(pa, pb), np.abs(pa - pb).max()

@@ -376,3 +376,36 @@ def test_trained_network_against_plain_solve():
     assert plain["rel"] <= 1e-8 and res["rel"] <= 1e-8
     assert diff <= 1e-6
     assert res["n_vcycles"] <= plain["n_vcycles"] + 1
+
+
+def test_learned_precision_through_fmg_solve():
+    """mg_fmg_solve(precision=MG_LEARNED) with a network attached by
+    mg_nn_bind runs the learned solve: the same bits and statistics as
+    mg_learned_solve (a random network: steps kept, then the fallback), and
+    nn_accepted / nn_fell_back in the solve statistics; without a network it
+    is refused, and mg_vcycle refuses the learned precision."""
+    say("MG_LEARNED through mg_fmg_solve")
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    net = NN.Net(rand_params(33, scale=0.5))
+    L = NN.Learned(g)
+    with pytest.raises(M.MGError) as e:
+        g.fmg_solve(precision=M.MG_LEARNED)
+    assert e.value.code == M.MG_ESTATE
+    ref = L.solve(net)
+    phi_ref = g.get_field(M.MG_FIELD_PHI)
+    NN.mg_nn_bind(g.h, net.h, L.ws.data_ptr(), L.ws.numel())
+    st = g.fmg_solve(precision=M.MG_LEARNED)
+    assert np.array_equal(g.get_field(M.MG_FIELD_PHI), phi_ref)
+    assert st["n_vcycles"] == ref["n_vcycles"] and np.array_equal(st["hist"], ref["hist"])
+    assert st["nn_accepted"] == ref["accepted"] and st["nn_fell_back"] == ref["fallback_cycle"]
+    say("  cycles", st["n_vcycles"], "accepted", st["nn_accepted"], "fell back at", st["nn_fell_back"])
+    with pytest.raises(M.MGError) as e:
+        g.vcycles(2, precision=M.MG_LEARNED)
+    assert e.value.code == M.MG_EINVAL
+    NN.mg_nn_bind(g.h, None, 0, 0)
+    with pytest.raises(M.MGError):
+        g.fmg_solve(precision=M.MG_LEARNED)
+    plain = g.fmg_solve()
+    assert plain["nn_accepted"] == 0 and plain["nn_fell_back"] == 0

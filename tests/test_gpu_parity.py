@@ -722,3 +722,55 @@ def test_bottom_kernel_forest_matches_the_oracle():
     err = np.linalg.norm((pg - po)[leaf]) / np.linalg.norm(po[leaf])
     say("bottom forest", sg["n_vcycles"], so["n_vcycles"], err)
     assert sg["n_vcycles"] == so["n_vcycles"] and err <= SOLVE_TOL
+
+
+def cs_order():
+    """Natural cell index (k*8 + j)*8 + i of each colour-split position."""
+    i, j, k = np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij")
+    cs = ((i + j + k) & 1) * 256 + (k * 8 + j) * 4 + (i >> 1)
+    nat = (k * 8 + j) * 8 + i
+    out = np.empty(512, dtype=np.int64)
+    out[cs.reshape(-1)] = nat.reshape(-1)
+    return out
+
+
+def test_borrowed_field_pointers():
+    """mg_field lends the fields' own storage: its contents are the
+    colour-split order of what mg_field_get copies out (FP64 and FP32), the
+    level offsets are the tree's, a write through the pointer (announced by
+    calling mg_field again) is what the next solve starts from, and a wrong
+    dtype is refused."""
+    import torch
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    g.fmg_solve(rel_tol=1e-6)
+    g.fmg_solve(precision=M.MG_MIXED, rel_tol=1e-6)
+    perm = cs_order()
+    for which, dtype, tdt in ((M.MG_FIELD_PHI, M.MG_DTYPE_F64, torch.float64),
+                              (M.MG_FIELD_RHS, M.MG_DTYPE_F64, torch.float64),
+                              (M.MG_FIELD_E32, M.MG_DTYPE_F32, torch.float32)):
+        ptr, n, lo = M.mg_field(g.h, which, dtype, g.nlev)
+        assert n == 512 * g.n
+        assert lo == [int(v) for v in g.info.level_start[:g.nlev + 1]]
+        raw = torch.empty(n, dtype=tdt, device="cuda")
+        M.mg_stream_copy(raw.data_ptr(), ptr, n * raw.element_size(), 0, g.stream.cuda_stream)
+        g.stream.synchronize()
+        nat = np.empty((g.n, 512))
+        nat[:, perm] = raw.cpu().numpy().astype(np.float64).reshape(g.n, 512)
+        assert np.array_equal(nat.reshape(g.n, 8, 8, 8), g.get_field(which)), which
+    with pytest.raises(M.MGError) as e:
+        M.mg_field(g.h, M.MG_FIELD_PHI, M.MG_DTYPE_F32)
+    assert e.value.code == M.MG_EINVAL
+    # write a converged potential through the pointer: warm V-cycles start from it
+    g.fmg_solve(rel_tol=1e-10)
+    conv = g.get_field(M.MG_FIELD_PHI, to_numpy=False)
+    g.fmg_solve(rel_tol=1e-2)
+    ptr, n, _ = M.mg_field(g.h, M.MG_FIELD_PHI, M.MG_DTYPE_F64)
+    src = torch.empty(n, dtype=torch.float64, device="cuda")
+    src[:] = conv.reshape(g.n, 512)[:, torch.from_numpy(perm).cuda()].reshape(-1)
+    torch.cuda.synchronize()
+    M.mg_stream_copy(ptr, src.data_ptr(), n * 8, 0, g.stream.cuda_stream)
+    M.mg_field(g.h, M.MG_FIELD_PHI, M.MG_DTYPE_F64)
+    st = g.vcycles(1)
+    assert st["hist"][0] <= 1e-10, st["hist"]
