@@ -290,6 +290,27 @@ def learned_leg(g, args, k_plain, value_plain):
     el = time.perf_counter() - t1
     phi = g.get_field(M.MG_FIELD_PHI)
     n_leaf = int(g.info.n_leaf_cells)
+    # the per-level placement: a learned step on each level's leaf boxes after
+    # that level's up-sweeps (its cycles launch kernel by kernel)
+    for _ in range(max(1, args.warmup)):
+        resl = L.solve(net, learned_placement=1)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    run_l = []
+    for _ in range(args.steps):
+        t_run = time.perf_counter()
+        resl = L.solve(net, learned_placement=1)
+        run_l.append(time.perf_counter() - t_run)
+    torch.cuda.synchronize()
+    el_l = time.perf_counter() - t2
+    phi_levels = g.get_field(M.MG_FIELD_PHI)
+    per_level = {"placement": "a learned step on each level's leaf boxes after its up-sweeps",
+                 "value": n_leaf * args.steps / el_l, "unit": "cells/s",
+                 "ms_per_step": 1e3 * el_l / args.steps, "runs": run_stats(run_l, n_leaf),
+                 "vcycles": resl["n_vcycles"], "accepted_cycles": resl["accepted"],
+                 "fallback_cycle": resl["fallback_cycle"], "learned_ms_per_step": resl["t_learned_ms"],
+                 "final_rel_res": resl["rel"], "hist": [float(v) for v in resl["hist"]],
+                 "vs_plain_fp64": (n_leaf * args.steps / el_l) / value_plain}
     # forward kernel on every leaf box of the benchmark tree, HIP events on
     # the stream it is launched on (torch's current stream)
     xin, _ = L.inputs()
@@ -306,8 +327,10 @@ def learned_leg(g, args, k_plain, value_plain):
     torch.cuda.synchronize()
     launch_s = e0.elapsed_time(e1) / 1e3 / reps
     tflops = NN_FLOP_PER_CELL * 512 * nbox / launch_s / 1e12
-    return phi, {"value": n_leaf * args.steps / el, "unit": "cells/s", "ms_per_step": 1e3 * el / args.steps,
-            "runs": run_stats(run_s, n_leaf),
+    return phi, phi_levels, {"placement": "a learned step after every V-cycle that does not stop the solve",
+            "value": n_leaf * args.steps / el, "unit": "cells/s", "ms_per_step": 1e3 * el / args.steps,
+            "runs": run_stats(run_s, n_leaf), "hist": [float(v) for v in res["hist"]],
+            "per_level": per_level,
             "vcycles": res["n_vcycles"], "vcycles_plain_fp64": k_plain,
             "accepted_steps": res["accepted"], "fallback_cycle": res["fallback_cycle"],
             "learned_ms_per_step": res["t_learned_ms"], "final_rel_res": res["rel"],
@@ -743,7 +766,7 @@ def main():
     learned = None
     if not args.no_learned:
         log("learned leg")
-        results["learned"], learned = learned_leg(g, args, k, value)
+        results["learned"], results["learned_per_level"], learned = learned_leg(g, args, k, value)
     copy = copy_bandwidth()
     mb = model_bytes(counts, n_leaf, k)
     # the level whose half-sweeps move the most bytes (the finest level of a
@@ -768,6 +791,7 @@ def main():
                    "fusion": M.MG_FUSE_ALL if args.fusion is None else args.fusion,
                    "gsrb_schedule": {"fp64": sched64, "fp32": sched32}},
         "runs": run_stats(run_s, n_leaf),
+        "hist": [float(v) for v in stats["hist"]],
         # solve level: the per-sweep byte model of the FMG solve (127 B per
         # stored cell per V(2,2) visit, FMG summed over the top levels, 16 B
         # per leaf cell per residual check) over the solve time
@@ -842,6 +866,9 @@ def main():
         for name, key in (("mixed", "mixed"), ("learned", "learned")):
             if key in out and name in acc:
                 out[key]["rel_l2_vs_oracle_reference"] = acc[name]["rel_l2_vs_reference"]
+        if "learned" in out and "learned_per_level" in acc:
+            out["learned"]["per_level"]["rel_l2_vs_oracle_reference"] = \
+                acc["learned_per_level"]["rel_l2_vs_reference"]
     if rank == 0:
         print(json.dumps(out), flush=True)
 

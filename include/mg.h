@@ -199,6 +199,11 @@ typedef struct {
                             NaN.  0 (default): a check before and after every
                             cycle.  Ignored elsewhere (mixed precision needs
                             each step's residual).                          */
+    int32_t learned_placement; /* MG_LEARNED / mg_learned_solve: 0 (default) a
+                            learned step after every V-cycle that does not
+                            stop the solve; 1 a learned step on each level's
+                            leaf boxes after that level's up-sweeps
+                            (include/mg_nn.h)                               */
 } mg_solve_opts;
 
 typedef struct {

@@ -148,6 +148,28 @@ int mg_learned_step(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes, double *s
  * plain V-cycles (fallback).  n_vcycles counts V-cycles; rel_hist[k] is the
  * relative residual after cycle k including its learned step.
  */
+/*
+ * Per-level placement (mg_solve_opts.learned_placement = 1): inside every
+ * V-cycle after the first, right after the up-sweeps of each level l >= 3
+ * with leaf boxes, a learned step on that level alone:
+ *   r    = b - L phi on the level's leaf boxes with the cycle's ghosts
+ *          (covered cells as the cycle left them);
+ *   x, c as above on those boxes (the same network);
+ *   q    = L0 c with c zero off those boxes (homogeneous boundary data,
+ *          zero coarse side at refinement boundaries);
+ *   s    = per tree <r, q> / <q, q> over the level's leaf cells, 0 when not
+ *          finite or not positive;  phi += s c.
+ * The first V-cycle is plain and gives the plain residual factor; while a
+ * cycle with the steps reduces the relative residual by at least that
+ * factor it counts as accepted, and the first that does not makes the
+ * remaining cycles plain (fallback; phi is kept).  These cycles launch
+ * kernel by kernel (each step reads its sums back to the host).
+ * mg_learned_level_step applies the step to one level of the current phi
+ * (steps: host [n_trees], may be NULL); MG_EINVAL for a level outside
+ * 3..n_levels.
+ */
+int mg_learned_level_step(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes, int level, double *steps);
+
 typedef struct {
     int32_t accepted;       /* learned steps kept */
     int32_t fallback_cycle; /* cycle at which the step was dropped, 0 if never */

@@ -283,6 +283,110 @@ def learned_solve(tree, params, tol=1e-8, max_cycles=50, n_down=2, n_up=2):
     return dict(rel=rel, n_vcycles=k, hist=np.array(hist), accepted=accepted, fallback=fallback)
 
 
+# ---------------------------------------------------------------------------
+# Per-level placement (a reading of the survey's "after the up-sweeps" for
+# each level; the paper has no learned component).  Inside a V-cycle, right
+# after the up-sweeps of a level l >= 3 that has leaf boxes:
+#   r   = b - L_l phi on the level-l boxes, with the ghosts of the cycle (no
+#         restriction of covered cells: the level's own cycle state);
+#   x   = network inputs of the level-l leaf boxes, built from r exactly as for
+#         the composite step (same-level leaf neighbours fill the ghost layer);
+#   c   = scale * network(x) on those boxes, zero elsewhere;
+#   q   = A0 c (the composite operator with homogeneous boundary data) on the
+#         level-l leaf boxes;
+#   s   = per tree, <r, q> / <q, q> over the tree's level-l leaf cells (the
+#         one-column least-squares step; 0 when <q, q> is 0 or not finite, or
+#         when s <= 0);
+#   phi += s c on those boxes.
+# The solve: the FMG pass, one plain V-cycle (its residual factor is the
+# plain factor), then V-cycles with the per-level steps while each such
+# cycle's factor does not exceed the plain one; the first that does makes
+# the rest plain (no restore: the cycle still lowered the residual).
+# ---------------------------------------------------------------------------
+
+def learned_step_level(tree, params, level, round_bf16=True):
+    """The per-level step on `level` of the tree's current cycle state.
+    Returns dict(s [ntree], c)."""
+    from . import PHI, RES, IDX_LEVEL, IDX_NBR, IDX_TREE, OP_RESIDUAL
+    phi = tree.get_field(PHI)
+    lv = tree.index(IDX_LEVEL)
+    tid = tree.index(IDX_TREE)
+    nbr = tree.index(IDX_NBR)
+    leaf = tree.leaf_mask()
+    on = leaf & (lv == level)
+    if not on.any():
+        return dict(s=np.zeros(tree.ntree), c=np.zeros_like(phi))
+    tree.step(OP_RESIDUAL, level)
+    r = np.where((lv == level)[:, None, None, None], tree.get_field(RES), 0.0)
+    X, scale = gather_inputs(r, lv, nbr, on, tree.length)
+    y, _ = forward(params, X, round_bf16)
+    c = np.zeros_like(phi)
+    c[on] = scale[:, None, None, None] * y
+    q = np.zeros_like(phi)
+    q[leaf] = tree.apply(c[leaf].ravel(), homog=True).reshape(-1, 8, 8, 8)
+    s = np.zeros(tree.ntree)
+    for tr in range(tree.ntree):
+        m = on & (tid == tr)
+        if not m.any():
+            continue
+        rq, qq = float(np.sum(r[m] * q[m])), float(np.sum(q[m] * q[m]))
+        if qq > 0 and np.isfinite(qq) and np.isfinite(rq) and rq / qq > 0:
+            s[tr] = rq / qq
+    new = phi.copy()
+    st = s[tid[on]]
+    upd = st != 0
+    ids = np.nonzero(on)[0][upd]
+    new[ids] += st[upd][:, None, None, None] * c[ids]
+    tree.set_field(PHI, new)  # also undoes the restriction the operator application made
+    return dict(s=s, c=c)
+
+
+def vcycle_levels(tree, params, top, n_down=2, n_up=2, low_step=3):
+    """One V-cycle with the per-level learned step after the up-sweeps of every
+    level >= low_step, from the single steps of the C oracle."""
+    from . import OP_SMOOTH, OP_FAS_DOWN, OP_PROLONG, OP_COARSE
+    for l in range(top, 1, -1):
+        tree.step(OP_SMOOTH, l, n_down)
+        tree.step(OP_FAS_DOWN, l)
+    tree.step(OP_COARSE, 1)
+    for l in range(2, top + 1):
+        tree.step(OP_PROLONG, l)
+        tree.step(OP_SMOOTH, l, n_up)
+        if l >= low_step:
+            learned_step_level(tree, params, l)
+
+
+def learned_solve_levels(tree, params, tol=1e-8, max_cycles=50, n_down=2, n_up=2):
+    """The per-level learned solve (see above).  Returns dict(rel, n_vcycles,
+    hist, accepted, fallback)."""
+    st = tree.fmg_solve(tol=1e300, max_cycles=0, n_down=n_down, n_up=n_up)
+    rel = st["rel"]
+    hist, plain, use, accepted, fallback, stall, k = [rel], None, True, 0, 0, 0, 0
+    while rel > tol:
+        k += 1
+        if k > max_cycles:
+            raise O_error("no convergence within max_cycles")
+        prev = rel
+        if k == 1 or not use:
+            rel = tree.vcycles(1, tol=0.0, n_down=n_down, n_up=n_up)["rel"]
+            if k == 1:
+                plain = rel / prev
+        else:
+            vcycle_levels(tree, params, tree.nlev, n_down, n_up)
+            rel = tree.residual()["rel"]
+            if rel / prev > plain:
+                use, fallback = False, k
+            else:
+                accepted += 1
+        hist.append(rel)
+        if not np.isfinite(rel):
+            raise O_error("non-finite residual")
+        stall = stall + 1 if rel >= prev else 0
+        if stall >= 3:
+            raise O_error("residual stagnates")
+    return dict(rel=rel, n_vcycles=k, hist=np.array(hist), accepted=accepted, fallback=fallback)
+
+
 def O_error(msg):
     from . import OracleError
     return OracleError(-5, msg)

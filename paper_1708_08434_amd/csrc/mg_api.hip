@@ -294,7 +294,10 @@ template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int n
     } else {
         coarse(t, F);
     }
-    for (int l = low; l <= top; l++) prolong_smooth(t, F, l, nu);
+    for (int l = low; l <= top; l++) {
+        prolong_smooth(t, F, l, nu);
+        if (sizeof(T) == 8 && t->level_hook && !t->hook_rc) t->hook_rc = t->level_hook(t, l, t->hook_ctx);
+    }
 }
 
 // FMG pass from the current (zero) field: FAS data top-down, root solve, then
@@ -571,7 +574,8 @@ int check_opts(const mg_solve_opts *o) {
     if (!o || (o->precision != MG_FP64 && o->precision != MG_MIXED && o->precision != MG_LEARNED) ||
         o->n_down < 0 ||
         o->n_up < 0 || o->max_cycles < 0 || o->max_cycles > 10000 || !(o->rel_tol >= 0) ||
-        (o->final_check_only != 0 && o->final_check_only != 1)) {
+        (o->final_check_only != 0 && o->final_check_only != 1) ||
+        (o->learned_placement != 0 && o->learned_placement != 1)) {
         set_error("invalid solver options");
         return MG_EINVAL;
     }
@@ -741,6 +745,130 @@ int learned_step_impl(mg_tree *t, mg_nn *nn, const LearnedWs &L, double *steps_h
     return rc;
 }
 
+// Per-level learned step on the leaf boxes of level l >= 3 (after the
+// level's up-sweeps inside an FP64 V-cycle, or on the current state): the
+// level's residual with the cycle's ghosts (covered cells as they are), the
+// network's correction c on those boxes, q = A0 c with homogeneous boundary
+// data (c is zero off the level's leaf boxes: refined same-level boxes hold
+// 0, and the level's refinement-boundary values are set to 0), and per tree
+// phi += s c with s = <r, q> / <q, q> (0 when not finite or not positive).
+// steps_host (may be NULL): [ntree] the steps.  Synchronises.
+int learned_level_step(mg_tree *t, mg_nn *nn, const LearnedWs &L, int l, double *steps_host) {
+    if (l < 3 || l > t->nlev) return MG_OK;
+    const int64_t q0 = t->fstart[l], nq = t->fstart[l + 1] - q0;
+    if (nq <= 0) return MG_OK;
+    Fields<double> F = f64(t);
+    Fields<float> E = f32(t);
+    hipStream_t s = stream_of(t);
+    const int32_t *list = t->d.leaf + q0;
+    ensure_cf(t, F, l);
+    launch_leaf_norms(F.g, F.phi, F.rhs, F.chat, list, nq, L.partial, E.rhs, s);  // r in FP32
+    launch_nn_gather(E.rhs, list, nq, t->d.nbr, t->d.ijk, t->d.isleaf, t->dom.len, L.x, L.scale, s);
+    launch_nn_forward(nn->prm, nn->pk, nq, nullptr, L.x, L.y, nullptr, nullptr, s);
+    launch_nn_scatter(L.y, L.scale, list, nq, t->d.ijk, -1, E.phi, s);
+    int64_t c0 = t->sstart[l], nc = t->sstart[l + 1] - c0;
+    launch_fill<float>(E.chat + c0 * 64, nc * 64, 0.0f, s);  // no correction on the coarse side
+    launch_leaf_apply<float>(E.g, E.phi, E.chat, list, nq, L.q, s);
+    dirty_all(E);
+    launch_nn_dots1(E.rhs, L.q, list, nq, t->d.ijk, t->dom.len, L.partial, s);
+    std::vector<double> part((size_t)2 * nq);
+    int rc = hip_check(hipMemcpyAsync(part.data(), L.partial, part.size() * sizeof(double),
+                                      hipMemcpyDeviceToHost, s), "level step sums readback");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "stream synchronize");
+    if (rc) return rc;
+    const int S = kStepStride, T = t->ntree;
+    std::vector<double> rq(T, 0.0), qq(T, 0.0), st((size_t)T * S, 0.0);
+    for (int64_t q = 0; q < nq; q++) {  // fixed order: leaf-list order
+        int tr = t->tid[t->leaf[q0 + q]];
+        rq[tr] += part[2 * q];
+        qq[tr] += part[2 * q + 1];
+    }
+    for (int tr = 0; tr < T; tr++) {
+        double v = qq[tr] > 0.0 ? rq[tr] / qq[tr] : 0.0;
+        st[(size_t)tr * S + l] = std::isfinite(v) && v > 0.0 ? v : 0.0;
+        if (steps_host) steps_host[tr] = st[(size_t)tr * S + l];
+    }
+    rc = hip_check(hipMemcpyAsync(L.steps, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice, s),
+                   "step upload");
+    if (rc) return rc;
+    launch_nn_update(F.phi, L.y, L.scale, list, nq, t->d.ijk, t->d.tid, L.steps, S, s);
+    dirty(F, l);
+    return hip_check(hipGetLastError(), "level step launch");
+}
+
+struct LevelHookCtx {
+    mg_nn *nn;
+    const LearnedWs *L;
+};
+int level_hook_fn(mg_tree *t, int l, void *ctx) {
+    auto *c = (LevelHookCtx *)ctx;
+    return learned_level_step(t, c->nn, *c->L, l, nullptr);
+}
+
+// The per-level learned solve (opts learned_placement = 1): the FMG pass, one
+// plain V-cycle (its residual factor is the plain factor), then V-cycles
+// with the per-level step after every level's up-sweeps, launched kernel by
+// kernel, while each such cycle's factor does not exceed the plain one; the
+// first that does makes the remaining cycles plain (phi is kept).
+int learned_solve_levels(mg_tree *t, mg_nn *nn, const LearnedWs &L, const mg_solve_opts *o, mg_solve_stats *s,
+                         mg_learned_stats *lst) {
+    const int T = t->ntree;
+    double t0 = now_ms();
+    int rc = run_seq(t, mg_tree::SEQ_FMG, o, 4 * T);
+    if (rc) return s->status = rc;
+    for (int tr = 0; tr < T; tr++) t->beff_tree[tr] = std::sqrt(t->host_result[2 * T + 2 * tr]);
+    if ((rc = record_check(t, s, 0))) return s->status = rc;
+    double plain = 0.0;
+    bool use = true;
+    int stall = 0;
+    LevelHookCtx ctx{nn, &L};
+    for (int k = 1; s->rel_res > o->rel_tol; k++) {
+        if (k > o->max_cycles) {
+            set_error("no convergence within max_cycles");
+            return s->status = MG_ENOCONV;
+        }
+        double prev = s->rel_res;
+        if (k == 1 || !use) {
+            if ((rc = run_seq(t, mg_tree::SEQ_VCHECK, o, 2 * T))) return s->status = rc;
+        } else {
+            double tl = now_ms();
+            dirty_all(f32(t));
+            t->level_hook = level_hook_fn;
+            t->hook_ctx = &ctx;
+            t->hook_rc = MG_OK;
+            run_body(t, mg_tree::SEQ_VCHECK, o->n_down, o->n_up);
+            t->level_hook = nullptr;
+            rc = t->hook_rc;
+            if (!rc) rc = read_results(t, 2 * T);
+            if (rc) return s->status = rc;
+            lst->t_learned_ms += now_ms() - tl;
+        }
+        s->n_vcycles = k;
+        if ((rc = record_check(t, s, k))) return s->status = rc;
+        if (k == 1) {
+            plain = prev > 0.0 ? s->rel_res / prev : 0.0;
+        } else if (use) {
+            if (s->rel_res / prev > plain) {
+                use = false;
+                lst->fallback_cycle = k;
+            } else {
+                lst->accepted++;
+            }
+        }
+        stall = s->rel_res >= prev ? stall + 1 : 0;
+        if (stall >= 3) {
+            set_error("residual stagnates");
+            return s->status = MG_ENOCONV;
+        }
+    }
+    restrict_all(t, f64(t));
+    rc = hip_check(hipGetLastError(), "kernel launch");
+    s->t_ms = now_ms() - t0;
+    s->nn_accepted = lst->accepted;
+    s->nn_fell_back = lst->fallback_cycle;
+    return s->status = rc;
+}
+
 // Network state in the caller's device memory.
 int64_t nn_state_layout(char *base, mg_nn *nn) {
     int64_t o = 0;
@@ -807,6 +935,7 @@ void mg_default_opts(mg_solve_opts *o) {
     o->rel_tol = 1e-8;
     o->graphs = 1;
     o->final_check_only = 0;
+    o->learned_placement = 0;
 }
 
 int mg_tree_create(mg_tree **out, const mg_domain *dom, int64_t n, const int32_t *level,
@@ -1946,6 +2075,22 @@ int mg_learned_step(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes, double *s
     return learned_step_impl(t, nn, L, steps);
 }
 
+int mg_learned_level_step(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes, int level, double *steps) {
+    int rc = require_bound(t);
+    if (rc || (rc = require_nn(nn)) || (rc = check_learned_ws(t, ws, ws_bytes))) return rc;
+    if (level < 3 || level > t->nlev) {
+        set_error("mg_learned_level_step: level outside 3..n_levels");
+        return MG_EINVAL;
+    }
+    LearnedWs L;
+    learned_layout(t, (char *)ws, &L);
+    if (steps)
+        for (int tr = 0; tr < t->ntree; tr++) steps[tr] = 0.0;
+    rc = learned_level_step(t, nn, L, level, steps);
+    if (!rc) rc = hip_check(hipStreamSynchronize(stream_of(t)), "stream synchronize");
+    return rc;
+}
+
 int mg_learned_solve(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes, const mg_solve_opts *o,
                      mg_solve_stats *st, mg_learned_stats *ls) {
     int rc = require_bound(t);
@@ -1963,6 +2108,7 @@ int mg_learned_solve(mg_tree *t, mg_nn *nn, void *ws, int64_t ws_bytes, const mg
     mg_learned_stats lloc;
     mg_learned_stats *lst = ls ? ls : &lloc;
     std::memset(lst, 0, sizeof *lst);
+    if (o->learned_placement == 1) return learned_solve_levels(t, nn, L, o, s, lst);
     double t0 = now_ms();
     const int T = t->ntree;
     Fields<double> F = f64(t);

@@ -163,6 +163,11 @@ struct mg_tree {
     // 0 = levels 1 and 2 step by step, otherwise one launch (k_bottom)
     int32_t sched[2][mg::kMaxLevel + 2];
     int32_t fusion = MG_FUSE_ALL;  // mg_set_fusion flags
+    // ---- hook after each level's up-sweeps in FP64 V-cycles (the per-level
+    //      learned step; only set while V-cycles launch kernel by kernel) ----
+    int (*level_hook)(mg_tree *, int level, void *ctx) = nullptr;
+    void *hook_ctx = nullptr;
+    int hook_rc = 0;
     // ---- network of MG_LEARNED solves (mg_nn_bind; caller-owned) ----
     mg_nn *nn = nullptr;
     void *nn_ws = nullptr;

@@ -52,6 +52,8 @@ void launch_nn_scatter(const float *y, const float *scale, const int32_t *leaf, 
                        const int32_t *ijk4, int mod3, float *e32, hipStream_t s);
 void launch_nn_dots(const float *r32, const float *q3, const int32_t *leaf, int64_t nleaf,
                     const int32_t *ijk4, double len, double *partial, hipStream_t s);
+void launch_nn_dots1(const float *r32, const float *q, const int32_t *list, int64_t n, const int32_t *ijk4,
+                     double len, double *partial, hipStream_t s);
 void launch_nn_update(double *phi, const float *y, const float *scale, const int32_t *leaf,
                       int64_t nleaf, const int32_t *ijk4, const int32_t *tid, const double *steps,
                       int stride, hipStream_t s);

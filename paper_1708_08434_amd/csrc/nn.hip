@@ -634,6 +634,33 @@ __global__ __launch_bounds__(256) void k_nn_dots(const float *__restrict__ r32,
     }
 }
 
+// Per listed box: the volume-weighted sums <r, q> and <q, q> of one column
+// (the per-level learned step).
+__global__ __launch_bounds__(256) void k_nn_dots1(const float *__restrict__ r32, const float *__restrict__ q,
+                                                  const int32_t *__restrict__ list,
+                                                  const int32_t *__restrict__ ijk4, double len,
+                                                  double *__restrict__ partial) {
+    __shared__ double S[4];
+    const int64_t p = blockIdx.x;
+    const int64_t b = list[p];
+    const int t = threadIdx.x;
+    const int l = ijk4[b * 4 + 3];
+    const double h = len / (8.0 * (double)(1 << (l - 1)));
+    double rq = 0.0, qq = 0.0;
+    for (int e = t; e < 512; e += 256) {
+        double r = r32[b * 512 + e], c = q[p * 512 + e];
+        rq += r * c;
+        qq += c * c;
+    }
+    const double vol = h * h * h;
+    double a = block_sum256(rq, S);
+    double c = block_sum256(qq, S);
+    if (t == 0) {
+        partial[2 * p] = a * vol;
+        partial[2 * p + 1] = c * vol;
+    }
+}
+
 // phi += steps[tree][level] * (scale * y) on the leaf boxes (boxes whose
 // step is 0 are left untouched, also where the correction is not finite).
 __global__ __launch_bounds__(256) void k_nn_update(double *__restrict__ phi,
@@ -751,6 +778,12 @@ void launch_nn_dots(const float *r32, const float *q3, const int32_t *leaf, int6
     if (nleaf <= 0) return;
     hipLaunchKernelGGL(k_nn_dots, dim3((unsigned)nleaf), dim3(256), 0, s, r32, q3, leaf, nleaf, ijk4, len,
                        partial);
+}
+
+void launch_nn_dots1(const float *r32, const float *q, const int32_t *list, int64_t n, const int32_t *ijk4,
+                     double len, double *partial, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_nn_dots1, dim3((unsigned)n), dim3(256), 0, s, r32, q, list, ijk4, len, partial);
 }
 
 void launch_nn_update(double *phi, const float *y, const float *scale, const int32_t *leaf,

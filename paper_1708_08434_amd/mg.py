@@ -61,7 +61,7 @@ class mg_solve_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("n_down", ctypes.c_int32),
                 ("n_up", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
                 ("rel_tol", ctypes.c_double), ("graphs", ctypes.c_int32),
-                ("final_check_only", ctypes.c_int32)]
+                ("final_check_only", ctypes.c_int32), ("learned_placement", ctypes.c_int32)]
 
 
 class mg_solve_stats(ctypes.Structure):

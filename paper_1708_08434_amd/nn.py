@@ -16,7 +16,8 @@ MG_NN_PARAMS = 7809
 EXPORTS = ["mg_nn_state_bytes", "mg_nn_create", "mg_nn_destroy", "mg_nn_set_params",
            "mg_nn_get_params", "mg_nn_forward", "mg_nn_train_bytes", "mg_nn_gradient",
            "mg_nn_get_grad", "mg_nn_adam", "mg_learned_bytes", "mg_nn_inputs", "mg_nn_targets",
-           "mg_learned_step", "mg_learned_solve", "mg_nn_gradient_static", "mg_nn_bind"]
+           "mg_learned_step", "mg_learned_solve", "mg_nn_gradient_static", "mg_nn_bind",
+           "mg_learned_level_step"]
 MG_NN_STATIC_MAX_BOXES = 64
 
 
@@ -57,6 +58,7 @@ def lib():
         L.mg_nn_targets.argtypes = [P, P, P, P]
         L.mg_learned_step.argtypes = [P, P, P, I64, P]
         L.mg_nn_bind.argtypes = [P, P, P, I64]
+        L.mg_learned_level_step.argtypes = [P, P, P, I64, ctypes.c_int32, P]
         L.mg_learned_solve.argtypes = [P, P, P, I64, ctypes.POINTER(M.mg_solve_opts),
                                        ctypes.POINTER(M.mg_solve_stats),
                                        ctypes.POINTER(mg_learned_stats)]
@@ -163,6 +165,15 @@ def mg_learned_solve(tree_h, nn_h, ws_ptr, ws_bytes, opts, raise_on_error=True):
     return st, ls
 
 
+def mg_learned_level_step(tree_h, nn_h, ws_ptr, ws_bytes, level, ntree):
+    """The per-level learned step on one level of the current phi; returns
+    the per-tree steps."""
+    st = np.zeros(ntree)
+    M.check(lib().mg_learned_level_step(tree_h, nn_h, ctypes.c_void_p(ws_ptr), int(ws_bytes), int(level),
+                                        st.ctypes.data_as(ctypes.c_void_p)))
+    return st
+
+
 def mg_nn_bind(tree_h, nn_h, ws_ptr, ws_bytes):
     """Attach a network and its learned-step workspace to a tree for
     mg_fmg_solve(precision=MG_LEARNED) (nn_h None detaches)."""
@@ -254,6 +265,10 @@ class Learned:
     def step(self, net):
         return mg_learned_step(self.tree.h, net.h, self.ws.data_ptr(), self.ws.numel(),
                                int(self.tree.info.n_trees), self.tree.nlev)
+
+    def level_step(self, net, level):
+        return mg_learned_level_step(self.tree.h, net.h, self.ws.data_ptr(), self.ws.numel(), level,
+                                     int(self.tree.info.n_trees))
 
     def solve(self, net, raise_on_error=True, **kw):
         st, ls = mg_learned_solve(self.tree.h, net.h, self.ws.data_ptr(), self.ws.numel(),

@@ -409,3 +409,67 @@ def test_learned_precision_through_fmg_solve():
         g.fmg_solve(precision=M.MG_LEARNED)
     plain = g.fmg_solve()
     assert plain["nn_accepted"] == 0 and plain["nn_fell_back"] == 0
+
+
+# ------------------------------------------------ per-level placement
+
+@pytest.mark.parametrize("level", [3, 4])
+def test_level_step_parity(level):
+    """The per-level step on one level of a cycle-like state (covered cells
+    not restricted) against the oracle's learned_step_level: the per-tree
+    step and the updated potential."""
+    say("level step parity, level", level)
+    g, o = tree_pair(amr_tree())
+    o.fmg_solve(tol=1e30)
+    o.vcycles(1, tol=0.0)
+    phi = o.get_field(O.PHI) + 0.01 * np.random.default_rng(5).standard_normal((o.n, 8, 8, 8))
+    p = rand_params(17, scale=0.5).astype(np.float64)
+    o.set_field(O.PHI, phi)
+    out = N.learned_step_level(o, p, level)
+    if out["s"][0] == 0.0:  # a correction against the residual gets no step: flip the output
+        W1, b1, W2, b2, W3, b3 = N.unpack(p)
+        p = N.pack(W1, b1, W2, b2, -W3, -b3)
+        o.set_field(O.PHI, phi)
+        out = N.learned_step_level(o, p, level)
+    g.set_field(M.MG_FIELD_PHI, phi)
+    steps = NN.Learned(g).level_step(NN.Net(p.astype(np.float32)), level)
+    say("   step gpu", steps, "oracle", out["s"])
+    assert out["s"][0] > 0
+    assert abs(steps[0] - out["s"][0]) <= STEP_REL * out["s"][0]
+    upd = o.get_field(O.PHI) - phi
+    assert np.abs(g.get_field(M.MG_FIELD_PHI) - o.get_field(O.PHI)).max() <= STEP_REL * np.abs(upd).max()
+    assert np.abs(upd).max() > 0
+
+
+def test_per_level_learned_solve_matches_oracle():
+    """Random weights, the per-level placement: the GPU solve and the oracle's
+    per-level solve (built from its single steps) take the same decisions and
+    converge to the same solution."""
+    say("per-level learned solve vs oracle")
+    g, o = tree_pair(amr_tree())
+    p = rand_params(16, scale=0.3)
+    res = NN.Learned(g).solve(NN.Net(p), learned_placement=1)
+    ref = N.learned_solve_levels(o, p.astype(np.float64))
+    say("   gpu", res["n_vcycles"], res["accepted"], res["fallback_cycle"], res["hist"],
+        "oracle", ref["n_vcycles"], ref["accepted"], ref["fallback"], ref["hist"])
+    assert res["rel"] <= 1e-8 and ref["rel"] <= 1e-8
+    assert abs(res["n_vcycles"] - ref["n_vcycles"]) <= 1
+    assert abs(res["accepted"] - ref["accepted"]) <= 1
+    leaf = o.leaf_mask()
+    a, b = g.get_field(M.MG_FIELD_PHI)[leaf], o.get_field(O.PHI)[leaf]
+    assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max()
+
+
+def test_per_level_zero_network_is_the_plain_solve():
+    """Zero weights: every per-level step is 0, so the per-level learned solve
+    is bit for bit the plain FP64 solve (its cycles launch kernel by kernel,
+    the plain solve's from recorded graphs: the same kernels)."""
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    plain = g.fmg_solve()
+    phi_plain = g.get_field(M.MG_FIELD_PHI)
+    res = NN.Learned(g).solve(NN.Net(np.zeros(N.N_PARAMS, dtype=np.float32)), learned_placement=1)
+    assert res["n_vcycles"] == plain["n_vcycles"]
+    assert np.array_equal(res["hist"], plain["hist"])
+    assert np.array_equal(g.get_field(M.MG_FIELD_PHI), phi_plain)

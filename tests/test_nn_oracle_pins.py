@@ -319,3 +319,83 @@ def test_learned_step_scale_invariance():
     assert np.allclose(outs[0]["X"], outs[1]["X"], rtol=1e-12, atol=1e-14)
     assert np.allclose(outs[0]["s"], outs[1]["s"], rtol=1e-9)
     assert np.allclose(outs[0]["c"] * 1024.0, outs[1]["c"], rtol=1e-12, atol=1e-300)
+
+
+# ----------------------------------------------------- per-level placement
+
+def _amr_state(seed):
+    """The AMR pin tree (levels 2-5, refinement boundaries, refined same-level
+    neighbours) with a random potential and right-hand side."""
+    from tests.test_oracle_pins import amr_tree
+    t = _tree(amr_tree())
+    rng = np.random.default_rng(seed)
+    t.set_field(O.RHS, rng.standard_normal((t.n, 8, 8, 8)) * 50.0)
+    t.set_field(O.PHI, rng.standard_normal((t.n, 8, 8, 8)))
+    return t
+
+
+@pytest.mark.parametrize("level", [3, 4, 5])
+def test_level_step_residual_orthogonal_to_its_column(level):
+    """After the per-level step the level's residual (recomputed by the C
+    oracle's residual step) equals r - s q, is orthogonal to q = A0 c over the
+    level's leaf cells (the one-column normal equation) and is smaller."""
+    t = _amr_state(40 + level)
+    lv, leaf = t.index(O.IDX_LEVEL), t.leaf_mask()
+    on = leaf & (lv == level)
+    assert on.any()
+    t.step(O.OP_RESIDUAL, level)
+    r = t.get_field(O.RES)
+    phi0 = t.get_field(O.PHI)
+    p = _rand_params(30, scale=0.5)
+    out = N.learned_step_level(t, p, level)
+    if out["s"][0] == 0.0:
+        # a correction against the residual gets no step; negating the last
+        # layer negates the network's output, so the same state gets one
+        W1, b1, W2, b2, W3, b3 = N.unpack(p)
+        p = N.pack(W1, b1, W2, b2, -W3, -b3)
+        t.set_field(O.PHI, phi0)
+        out = N.learned_step_level(t, p, level)
+    s = out["s"][0]
+    assert s > 0.0
+    t.step(O.OP_RESIDUAL, level)
+    r_new = t.get_field(O.RES)
+    # q from the composite operator on c alone (homogeneous), an independent path
+    saved = t.get_field(O.PHI)
+    q = np.zeros_like(phi0)
+    q[leaf] = t.apply(out["c"][leaf].ravel(), homog=True).reshape(-1, 8, 8, 8)
+    t.set_field(O.PHI, saved)
+    assert np.abs((r_new - (r - s * q))[on]).max() <= 1e-10 * np.abs(r[on]).max()
+    ip = np.sum(r_new[on] * q[on])
+    assert abs(ip) <= 1e-10 * np.sqrt(np.sum(q[on] ** 2) * np.sum(r[on] ** 2))
+    assert np.sum(r_new[on] ** 2) < np.sum(r[on] ** 2)
+    # only the level's leaf boxes moved
+    assert np.array_equal(saved[~on], phi0[~on])
+
+
+def test_level_step_equals_the_composite_step_on_a_restricted_state():
+    """With covered cells restricted, the level's residual is the composite
+    residual on its leaf boxes, so the per-level correction is the composite
+    step's correction on those boxes."""
+    t = _amr_state(50)
+    t.step(O.OP_RESTRICT_ALL)
+    phi = t.get_field(O.PHI)
+    p = _rand_params(31, scale=0.5)
+    comp = N.learned_step(t, p)
+    t.set_field(O.PHI, phi)
+    lv, leaf = t.index(O.IDX_LEVEL), t.leaf_mask()
+    for level in (3, 4, 5):
+        t.set_field(O.PHI, phi)
+        out = N.learned_step_level(t, p, level)
+        on = leaf & (lv == level)
+        assert np.allclose(out["c"][on], comp["c"][on], rtol=1e-10, atol=1e-12 * np.abs(comp["c"]).max())
+        assert np.all(out["c"][~on] == 0.0)
+
+
+def test_levels_vcycle_with_zero_network_is_the_plain_vcycle():
+    """The per-level V-cycle, built from the oracle's single steps, with a
+    zero network (zero correction, zero step) is bit for bit the oracle's
+    own V-cycle."""
+    a, b = _amr_state(60), _amr_state(60)
+    N.vcycle_levels(a, np.zeros(N.N_PARAMS), a.nlev)
+    b.step(O.OP_VCYCLE, b.nlev, 2)
+    assert np.array_equal(a.get_field(O.PHI), b.get_field(O.PHI))
