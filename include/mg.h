@@ -452,9 +452,13 @@ int mg_set_schedule(mg_tree *t, int precision, const int32_t *schedule);
  *     not a pass of its own: the first red and black half-sweeps after it form
  *     each prolonged value they read from the unprolonged field and the
  *     parent's correction, which saves reading and writing the level once.
+ *   MG_FUSE_BEFF: the norm of the residual of phi = 0 (the divisor of the
+ *     relative residual) comes from the FMG pass's top-down restriction,
+ *     which starts from phi = 0: it reads no phi and also sums the norms of
+ *     the leaf boxes, instead of a norm pass of its own.
  * MG_EINVAL on unknown flags.  Changing the flags drops recorded graphs.
  */
-enum { MG_FUSE_PROLONG = 1, MG_FUSE_ALL = 1 };
+enum { MG_FUSE_PROLONG = 1, MG_FUSE_BEFF = 2, MG_FUSE_ALL = 3 };
 int mg_set_fusion(mg_tree *t, int flags);
 
 /*

@@ -65,10 +65,13 @@ void launch_restrict_leaves(const Geo &g, T *phi, const int32_t *leaf, int64_t n
 template <typename T>
 void launch_cf_coarse(const Geo &g, const T *phi, T *chat, const int32_t *slots, int64_t s0,
                       int64_t ns, hipStream_t s);
+// partial != null: phi is zero everywhere (FMG start) and is not read; each
+// leaf box also writes its norm partials (as k_leaf_norms) at leafpos[b].
 template <typename T>
 void launch_resid_restrict(const Geo &g, T *phi, T *rhs, T *old, const T *chat, int64_t b0,
                            int64_t nb, const int32_t *leaf_prev, int64_t nleaf_prev, T inv_h2,
-                           hipStream_t s);
+                           hipStream_t s, const int32_t *leafpos = nullptr, double *partial = nullptr,
+                           double vol = 0.0);
 template <typename T>
 void launch_fas_rhs(const Geo &g, const T *phi, T *rhs, const T *chat, const int32_t *list,
                     int64_t nlist, T inv_h2, hipStream_t s);

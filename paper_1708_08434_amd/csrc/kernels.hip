@@ -46,6 +46,9 @@ __device__ __forceinline__ void tangential(int a, int &t1, int &t2) {
     t2 = a == 2 ? 1 : 2;
 }
 
+// max that carries NaN through (a non-finite residual must reach the test)
+__device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
+
 // Ghost values: Dirichlet face value gv reflected through the boundary cell,
 // and the refinement-boundary quadratic through the coarse value ch and the
 // first two interior fine cells.  Every kernel evaluates them through these
@@ -59,6 +62,12 @@ __device__ __forceinline__ double fmadd(double a, double b, double c) { return _
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <typename T> __device__ __forceinline__ T cf_ghost(T ch, T own, T inward) {
     return fmadd((T)kCfCoarse, ch, fmadd((T)kCfFine1, own, -((T)kCfFine2 * inward)));
+}
+// Residual b - (s - 6 own) / h^2 of a cell with neighbour sum s, with the
+// multiply-adds written out so that every kernel that forms a residual
+// (restriction, stopping test, bottom of the cycle) rounds it alike.
+template <typename T> __device__ __forceinline__ T resid_of(T b, T s, T own, T inv_h2) {
+    return fmadd(-fmadd((T)-6, own, s), inv_h2, b);
 }
 template <typename T>
 __device__ __forceinline__ T bc_value(const Geo &g, int64_t b, int d, int u, int v) {
@@ -653,13 +662,33 @@ __global__ __launch_bounds__(256) void k_cf_coarse(Geo g, const T *__restrict__ 
 // k_fas_rhs).  Extra blocks copy phi -> old on the listed leaf boxes of level
 // l-1 (those with a refined face or edge neighbour: the only leaf boxes whose
 // old values a prolongation reads).
+//
+// ZERO: phi is zero on every level (the top-down pass of an FMG solve from
+// phi = 0), so it is not read: the box is zero and its ghosts are those of
+// the zero field (the boundary data and the refinement-boundary values
+// c_hat of the zero field), which are the values the general path reads and
+// forms.  The residual of a leaf box is then the residual of phi = 0, and
+// the box also writes its volume-weighted sum of r^2 and max |r| at its leaf
+// position leafpos[b] of `partial`, with the arithmetic and the summation
+// order of k_leaf_norms (the norm the stopping test divides by).
 template <typename T>
+__device__ __forceinline__ T ghost_of_zero(const Geo &g, const T *__restrict__ chat, int64_t b, int d, int nb,
+                                           int slot, int u, int v) {
+    if (nb >= 0) return (T)0;
+    if (nb == -2) return g.bct[d] == 1 ? (T)0 : dirichlet_ghost<T>(bc_value<T>(g, b, d, u, v), (T)0);
+    return cf_ghost<T>(chat[(int64_t)slot * 64 + v * 8 + u], (T)0, (T)0);
+}
+
+template <typename T, bool ZERO>
 __global__ __launch_bounds__(256) void k_resid_restrict(Geo g, T *__restrict__ phi, T *__restrict__ rhs,
                                                         T *__restrict__ old, const T *__restrict__ chat,
                                                         int64_t b0, int64_t nbx,
                                                         const int32_t *__restrict__ leaf_prev,
-                                                        int64_t nleaf_prev, T inv_h2) {
+                                                        int64_t nleaf_prev, T inv_h2,
+                                                        const int32_t *__restrict__ leafpos,
+                                                        double *__restrict__ partial, double vol) {
     __shared__ T P[512], H[384], R[512];
+    __shared__ double S[4], M[4];
     int64_t blk = blockIdx.x;
     int t = threadIdx.x;
     int64_t nmain = xcd_grid(nbx);
@@ -667,8 +696,8 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Geo g, T *__restrict__ p
         int64_t q = blk - nmain;
         if (q >= nleaf_prev) return;
         int64_t p = leaf_prev[q];
-        old[p * 512 + t] = phi[p * 512 + t];
-        old[p * 512 + 256 + t] = phi[p * 512 + 256 + t];
+        old[p * 512 + t] = ZERO ? (T)0 : phi[p * 512 + t];
+        old[p * 512 + 256 + t] = ZERO ? (T)0 : phi[p * 512 + 256 + t];
         return;
     }
     int64_t lb = xcd_map(blk, nbx);
@@ -678,17 +707,52 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Geo g, T *__restrict__ p
     const int64_t p = g.parent[b];
     const int bi = g.ijk[b * 4] & 1, bj = g.ijk[b * 4 + 1] & 1, bk = g.ijk[b * 4 + 2] & 1;
     T r0 = rhs[b * 512 + t], r1 = rhs[b * 512 + 256 + t];
-    stage_full<T>(g, phi, chat, b, P, H);
+    if (ZERO) {
+        const FaceTab ft = face_tab(g, b);
+        P[t] = (T)0;
+        P[256 + t] = (T)0;
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            int e = t + 256 * r;
+            if (e < 384) {
+                int d = e >> 6, w = e & 63;
+                H[e] = ghost_of_zero<T>(g, chat, b, d, pick6(ft.nb, d), pick6(ft.slot, d), w & 7, w >> 3);
+            }
+        }
+    } else {
+        stage_full<T>(g, phi, chat, b, P, H);
+    }
     __syncthreads();
     int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
+    double ss = 0.0, mx = 0.0;
 #pragma unroll
     for (int c = 0; c < 2; c++) {
         int i = 2 * m + ((j + k + c) & 1);
         T own = P[c * 256 + t];
         T s = sum_full<T>(P, H, i, j, k);
-        R[c * 256 + t] = (c ? r1 : r0) - (s - (T)6 * own) * inv_h2;
+        T r = resid_of<T>(c ? r1 : r0, s, own, inv_h2);
+        R[c * 256 + t] = r;
+        if (ZERO) {
+            ss += (double)r * (double)r;
+            mx = nanmax(fabs((double)r), mx);
+        }
+    }
+    if (ZERO && leafpos[b] >= 0) {  // block-uniform
+        for (int off = 32; off > 0; off >>= 1) {
+            ss += __shfl_xor(ss, off);
+            mx = nanmax(__shfl_xor(mx, off), mx);
+        }
+        if ((t & 63) == 0) {
+            S[t >> 6] = ss;
+            M[t >> 6] = mx;
+        }
     }
     __syncthreads();
+    if (ZERO && t == 0 && leafpos[b] >= 0) {
+        int64_t q = leafpos[b];
+        partial[2 * q] = ((S[0] + S[1]) + (S[2] + S[3])) * vol;
+        partial[2 * q + 1] = nanmax(nanmax(M[0], M[1]), nanmax(M[2], M[3]));
+    }
     if (t < 64) {
         int pi = t & 3, pj = (t >> 2) & 3, pk = t >> 4;
         T sphi = 0, sres = 0;
@@ -1319,7 +1383,7 @@ __global__ __launch_bounds__(1024) void k_bottom(Geo g, T *__restrict__ phi, T *
             cs16_cell(p, I, J, K);
             T own = F2[p];
             T sum = bot_sum<T>(F2, GB, nm, I, J, K, own);
-            R2[p] = B2[p] - (sum - (T)6 * own) * inv_h2_2;
+            R2[p] = resid_of<T>(B2[p], sum, own, inv_h2_2);
         }
         __syncthreads();
         if (tid < 512) {
@@ -1496,7 +1560,6 @@ __global__ __launch_bounds__(64) void k_restrict_leaves(Geo g, T *__restrict__ p
     phi[p * 512 + cs_idx(ci, cj, ck)] = (T)0.125 * s;
 }
 
-__device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
 // Leaf residual norms: per listed box, sum of r^2 h^3 and max |r|.  When
 // r_out is set the residual is also stored, rounded to FP32 (right-hand side
@@ -1525,7 +1588,7 @@ __global__ __launch_bounds__(256) void k_leaf_norms(Geo g, const double *__restr
         int i = 2 * m + ((j + k + c) & 1);
         double own = P[c * 256 + t];
         double s = sum_full<double>(P, H, i, j, k);
-        double r = (c ? r1 : r0) - (s - 6.0 * own) * inv_h2;
+        double r = resid_of<double>(c ? r1 : r0, s, own, inv_h2);
         if (r_out) r_out[b * 512 + c * 256 + t] = (float)r;
         ss += r * r;
         mx = nanmax(fabs(r), mx);
@@ -1870,11 +1933,15 @@ void launch_cf_coarse(const Geo &g, const T *phi, T *chat, const int32_t *slots,
 template <typename T>
 void launch_resid_restrict(const Geo &g, T *phi, T *rhs, T *old, const T *chat, int64_t b0,
                            int64_t nb, const int32_t *leaf_prev, int64_t nleaf_prev, T inv_h2,
-                           hipStream_t s) {
+                           hipStream_t s, const int32_t *leafpos, double *partial, double vol) {
     if (nb + nleaf_prev <= 0) return;
     dim3 grid((unsigned)(xcd_grid(nb) + nleaf_prev));
-    hipLaunchKernelGGL(k_resid_restrict<T>, grid, dim3(256), 0, s, g, phi, rhs, old, chat, b0, nb,
-                       leaf_prev, nleaf_prev, inv_h2);
+    if (partial)
+        hipLaunchKernelGGL((k_resid_restrict<T, true>), grid, dim3(256), 0, s, g, phi, rhs, old, chat, b0, nb,
+                           leaf_prev, nleaf_prev, inv_h2, leafpos, partial, vol);
+    else
+        hipLaunchKernelGGL((k_resid_restrict<T, false>), grid, dim3(256), 0, s, g, phi, rhs, old, chat, b0, nb,
+                           leaf_prev, nleaf_prev, inv_h2, leafpos, partial, vol);
 }
 template <typename T>
 void launch_fas_rhs(const Geo &g, const T *phi, T *rhs, const T *chat, const int32_t *list,
@@ -1996,7 +2063,8 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
     template void launch_cf_coarse<T>(const Geo &, const T *, T *, const int32_t *, int64_t,     \
                                       int64_t, hipStream_t);                                     \
     template void launch_resid_restrict<T>(const Geo &, T *, T *, T *, const T *, int64_t,       \
-                                           int64_t, const int32_t *, int64_t, T, hipStream_t);   \
+                                           int64_t, const int32_t *, int64_t, T, hipStream_t,    \
+                                           const int32_t *, double *, double);                   \
     template void launch_fas_rhs<T>(const Geo &, const T *, T *, const T *, const int32_t *,     \
                                     int64_t, T, hipStream_t);                                    \
     template void launch_prolong_cf<T>(const Geo &, T *, const T *, int64_t, int64_t, T *,       \

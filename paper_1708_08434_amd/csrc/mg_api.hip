@@ -180,12 +180,17 @@ template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsw
 // defer_rhs: leave the coarse right-hand side L phi_c + r_c of the refined
 // level-(l-1) boxes to the first fused sweep of level l-1 (smooth with
 // fas_first), which forms it from the same values.
-template <typename T> void fas_down(mg_tree *t, const Fields<T> &F, int l, bool defer_rhs = false) {
+// zero_norms (FP64, phi = 0 everywhere): the residual kernel skips reading
+// phi and leaves the norm partials of the residual of phi = 0 of the level's
+// leaf boxes in the partial buffer (at their leaf positions).
+template <typename T> void fas_down(mg_tree *t, const Fields<T> &F, int l, bool defer_rhs = false,
+                                    bool zero_norms = false) {
     ensure_cf(t, F, l);
     double h = hlev(t, l);
     launch_resid_restrict<T>(F.g, F.phi, F.rhs, F.old, F.chat, lbeg(t, l), lcount(t, l),
                              t->d.oldcp + t->ostart[l - 1], t->ostart[l] - t->ostart[l - 1],
-                             (T)(1.0 / (h * h)), stream_of(t));
+                             (T)(1.0 / (h * h)), stream_of(t), t->d.leafpos,
+                             zero_norms ? t->d.partial : nullptr, h * h * h);
     dirty(F, l - 1);
     ensure_cf(t, F, l - 1);
     if (defer_rhs) return;
@@ -302,14 +307,26 @@ template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int n
 
 // FMG pass from the current (zero) field: FAS data top-down, root solve, then
 // for each finer level the prolonged correction and one V-cycle on top.
-template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int nu) {
+// beff_slot >= 0 (FP64, from phi = 0): the top-down pass also gives the
+// per-tree norms of the residual of phi = 0 (into result[beff_slot ..]), the
+// norms the stopping test divides by, without a pass of their own.
+template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int nu, int beff_slot = -1) {
     // the top-down FAS pass changes level l-1 only after the last use of
     // c_hat(l), and c_hat(l-1) reads level l-2, still untouched: every c_hat
     // it needs can be computed up front from the initial field
     ensure_cf_all(t, F);
     bool one = use_bottom<T>(t);
     int low = one ? 3 : 2;
-    for (int l = t->nlev; l >= low; l--) fas_down(t, F, l, one && l == low);
+    for (int l = t->nlev; l >= low; l--) fas_down(t, F, l, one && l == low, beff_slot >= 0);
+    if (beff_slot >= 0) {
+        // leaf boxes on levels below the top-down pass (those of a tree of one
+        // or two levels): the norm kernel, on the still zero field
+        int64_t q0 = t->fstart[1], q1 = t->fstart[std::min(low, t->nlev + 1)];
+        launch_leaf_norms(f64(t).g, t->d.phi, t->d.rhs, t->d.chat, t->d.leaf + q0, q1 - q0, t->d.partial + 2 * q0,
+                          nullptr, stream_of(t));
+        launch_reduce_trees(t->d.partial, t->d.leaf_tree, t->d.chunk, (int64_t)t->chunk.size() / 3, t->d.choff,
+                            t->ntree, t->d.part2, t->d.result + beff_slot, stream_of(t));
+    }
     if (one) {
         bottom(t, F, nd, nu, true, t->nlev >= low);  // fas_down(2), coarse, prolong(2), V-cycle(2)
     } else {
@@ -377,8 +394,12 @@ void run_body(mg_tree *t, int seq, int nd, int nu) {
     case mg_tree::SEQ_FMG:
         launch_fill<double>(F.phi, 512 * t->n, 0.0, stream_of(t));
         dirty_all(F);
-        norms_launch(t, 2 * t->ntree, nullptr);
-        fmg_pass(t, F, nd, nu);
+        if (t->fusion & MG_FUSE_BEFF) {
+            fmg_pass(t, F, nd, nu, 2 * t->ntree);
+        } else {
+            norms_launch(t, 2 * t->ntree, nullptr);
+            fmg_pass(t, F, nd, nu);
+        }
         restrict_for_check(t, F);
         norms_launch(t, 0, nullptr);
         break;
@@ -1052,6 +1073,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.leaf = (int32_t *)(base + t->off.leaf);
     d.cleaf = (int32_t *)(base + t->off.cleaf);
     d.oldcp = (int32_t *)(base + t->off.oldcp);
+    d.leafpos = (int32_t *)(base + t->off.leafpos);
     d.slots = (int32_t *)(base + t->off.slots);
     d.leaf_tree = (int32_t *)(base + t->off.leaf_tree);
     d.tree_off = (int32_t *)(base + t->off.tree_off);
@@ -1106,6 +1128,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     rc = rc ? rc : up(d.leaf, t->leaf.data(), t->leaf.size() * 4);
     rc = rc ? rc : up(d.cleaf, t->cleaf.data(), t->cleaf.size() * 4);
     rc = rc ? rc : up(d.oldcp, t->oldcp.data(), t->oldcp.size() * 4);
+    rc = rc ? rc : up(d.leafpos, t->leafpos.data(), t->leafpos.size() * 4);
     rc = rc ? rc : up(d.slots, t->slots.data(), t->slots.size() * 4);
     rc = rc ? rc : up(d.leaf_tree, t->leaf_tree.data(), t->leaf_tree.size() * 4);
     rc = rc ? rc : up(d.tree_off, t->tree_off.data(), t->tree_off.size() * 4);

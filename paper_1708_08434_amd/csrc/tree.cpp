@@ -366,6 +366,8 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
             (t->child[8 * b] >= 0 ? t->refined : t->leaf).push_back((int32_t)b);
     }
     t->nleaf = (int64_t)t->leaf.size();
+    t->leafpos.assign(n, -1);  // position in the leaf list, -1 for boxes with children
+    for (int64_t q = 0; q < t->nleaf; q++) t->leafpos[t->leaf[q]] = (int32_t)q;
     // per-level lists of the leaf boxes whose phi a down-leg copies into
     // phi_old.  The prolongation into level l+1 reads phi - phi_old of level l
     // only on the parents of level-(l+1) boxes and one cell layer around them,
@@ -458,6 +460,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.leaf = take(4 * t->nleaf);
     t->off.cleaf = take(4 * (int64_t)t->cleaf.size());
     t->off.oldcp = take(4 * (int64_t)t->oldcp.size());
+    t->off.leafpos = take(4 * n);
     t->off.slots = take(8 * t->nslot);
     t->off.slotx = take(32 * t->nslot);
     t->off.leaf_tree = take(4 * t->nleaf);
