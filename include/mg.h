@@ -456,9 +456,14 @@ int mg_set_schedule(mg_tree *t, int precision, const int32_t *schedule);
  *     relative residual) comes from the FMG pass's top-down restriction,
  *     which starts from phi = 0: it reads no phi and also sums the norms of
  *     the leaf boxes, instead of a norm pass of its own.
+ *   MG_FUSE_RESTRICT: before a stopping test, the restriction of the leaf
+ *     boxes' values onto their parents' cells (the covered cells that the
+ *     test's residual and c_hat read) is done by each level's last black
+ *     half-sweep of the cycle, on the levels whose sweep variant is a
+ *     one-box half-sweep, instead of by a pass of its own.
  * MG_EINVAL on unknown flags.  Changing the flags drops recorded graphs.
  */
-enum { MG_FUSE_PROLONG = 1, MG_FUSE_BEFF = 2, MG_FUSE_ALL = 3 };
+enum { MG_FUSE_PROLONG = 1, MG_FUSE_BEFF = 2, MG_FUSE_RESTRICT = 4, MG_FUSE_ALL = 7 };
 int mg_set_fusion(mg_tree *t, int flags);
 
 /*

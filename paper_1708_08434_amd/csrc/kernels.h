@@ -45,10 +45,13 @@ constexpr int kGsrbOctVariant = 8;    // 8, 9: octet half-sweeps
 constexpr int kGsrbPipeVariant = 10;  // 10..13: persistent prefetching half-sweeps
 constexpr int kGsrbDefault = 3;       // 2 cells per thread, XCD mapping
 // One colour in place; a fused variant, or an octet variant on a box count
-// that is not a multiple of 8, falls back to kGsrbDefault.
+// that is not a multiple of 8, falls back to kGsrbDefault.  rmask (black
+// colour, variants with gsrb_restricts): the boxes with rmask[b] != 0 also
+// restrict their swept values onto their parent cells.
 template <typename T>
 void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
-                 int colour, int variant, hipStream_t s);
+                 int colour, int variant, hipStream_t s, const int32_t *rmask = nullptr);
+constexpr bool gsrb_restricts(int variant) { return variant >= 0 && variant < kGsrbHalfVariants; }
 // One full sweep (red, then black) from src into dst (no aliasing).
 template <typename T>
 // fas = 1: also complete the FAS right-hand side L src + restricted
@@ -113,6 +116,10 @@ void launch_bottom(const Geo &g, T *phi, T *rhs, T *old, const double *eig, int6
 void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const double *chat,
                        const int32_t *leaf, int64_t nleaf, double *partial, float *r_out,
                        hipStream_t s);
+// The same norms over the leaf boxes among [b0, b0+nb), into partial at
+// their leaf positions leafpos[b] (-1: not a leaf, skipped).
+void launch_box_norms(const Geo &g, const double *phi, const double *rhs, const double *chat, int64_t b0,
+                      int64_t nb, const int32_t *leafpos, double *partial, float *r_out, hipStream_t s);
 template <typename T>
 void launch_leaf_apply(const Geo &g, const T *x, const T *chat, const int32_t *leaf, int64_t nleaf,
                        T *out, hipStream_t s);

@@ -209,14 +209,20 @@ template <> struct VecN<float, 1> { using type = float; };
 template <> struct VecN<float, 2> { using type = float2; };
 template <> struct VecN<float, 4> { using type = float4; };
 
-template <int C, typename T, int CPT>
+// RST (black colour only): boxes with rmask[b] != 0 also set their parent
+// cells to the mean of the 8 children under each, from the swept values (the
+// arithmetic of k_restrict_leaves), when this is the box's last sweep of the
+// cycle.
+template <int C, typename T, int CPT, bool RST = false>
 __global__ __launch_bounds__(256 / CPT) void k_gsrb(Geo g, T *__restrict__ phi,
                                                     const T *__restrict__ rhs,
                                                     const T *__restrict__ chat, int64_t b0,
-                                                    int64_t nbx, T h2, int xcd) {
+                                                    int64_t nbx, T h2, int xcd,
+                                                    const int32_t *__restrict__ rmask = nullptr) {
     using V = typename VecN<T, CPT>::type;
     constexpr int NT = 256 / CPT;
-    __shared__ T S[256], H[192];
+    __shared__ T SB[RST ? 512 : 256], H[192];
+    T *S = SB;
     int64_t lb = xcd ? xcd_map(blockIdx.x, nbx) : (int64_t)blockIdx.x;
     if (lb >= nbx) return;
     int64_t b = b0 + lb;
@@ -247,6 +253,25 @@ __global__ __launch_bounds__(256 / CPT) void k_gsrb(Geo g, T *__restrict__ phi,
         out[w] = (s - h2 * bb[w]) * (T)kSixth;
     }
     reinterpret_cast<V *>(phi + b * 512 + C * 256)[t] = res;
+    if (RST && rmask[b]) {  // block-uniform
+        // SB: colour 0 (the staged other colour) then colour 1 (this sweep's)
+        reinterpret_cast<V *>(SB + 256)[t] = res;
+        __syncthreads();
+        for (int e = t; e < 64; e += NT) {
+            int pi = e & 3, pj = (e >> 2) & 3, pk = e >> 4;
+            T sum = 0;
+#pragma unroll
+            for (int dk = 0; dk < 2; dk++)
+#pragma unroll
+                for (int dj = 0; dj < 2; dj++)
+#pragma unroll
+                    for (int di = 0; di < 2; di++) sum += SB[cs_idx(2 * pi + di, 2 * pj + dj, 2 * pk + dk)];
+            int64_t p = g.parent[b];
+            int ci = 4 * (g.ijk[b * 4] & 1) + pi, cj = 4 * (g.ijk[b * 4 + 1] & 1) + pj,
+                ck = 4 * (g.ijk[b * 4 + 2] & 1) + pk;
+            phi[p * 512 + cs_idx(ci, cj, ck)] = (T)0.125 * sum;
+        }
+    }
 }
 
 // Workgroup barrier that orders LDS only: global loads issued before it stay
@@ -733,7 +758,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Geo g, T *__restrict__ p
         T r = resid_of<T>(c ? r1 : r0, s, own, inv_h2);
         R[c * 256 + t] = r;
         if (ZERO) {
-            ss += (double)r * (double)r;
+            ss = fmadd((double)r, (double)r, ss);
             mx = nanmax(fabs((double)r), mx);
         }
     }
@@ -1590,7 +1615,7 @@ __global__ __launch_bounds__(256) void k_leaf_norms(Geo g, const double *__restr
         double s = sum_full<double>(P, H, i, j, k);
         double r = resid_of<double>(c ? r1 : r0, s, own, inv_h2);
         if (r_out) r_out[b * 512 + c * 256 + t] = (float)r;
-        ss += r * r;
+        ss = fmadd(r, r, ss);
         mx = nanmax(fabs(r), mx);
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -1605,6 +1630,83 @@ __global__ __launch_bounds__(256) void k_leaf_norms(Geo g, const double *__restr
     if (t == 0) {
         partial[2 * q] = ((S[0] + S[1]) + (S[2] + S[3])) * vol;
         partial[2 * q + 1] = nanmax(nanmax(M[0], M[1]), nanmax(M[2], M[3]));
+    }
+}
+
+// The norms of k_leaf_norms on the leaf boxes among [b0, b0+nb) (leafpos[b]
+// >= 0; the others exit at once), into partial at their leaf positions: the
+// box comes from the block index, so the loads wait on no list lookup, and
+// 128 threads per box with paired loads keep twice the boxes in flight.
+// Thread u holds cell positions 2u and 2u+1 of both colours; the per-box sum
+// follows k_leaf_norms' tree over the 256 positions (the shuffles over u
+// are its stages 32..2, the pair sum its stage 1), so the partials are the
+// same bits.
+__global__ __launch_bounds__(128) void k_box_norms(Geo g, const double *__restrict__ phi,
+                                                   const double *__restrict__ rhs,
+                                                   const double *__restrict__ chat, int64_t b0, int64_t nb,
+                                                   const int32_t *__restrict__ leafpos,
+                                                   double *__restrict__ partial, float *__restrict__ r_out) {
+    __shared__ double P[512], H[384], S[4], M[4];
+    int64_t lb = xcd_map(blockIdx.x, nb);
+    if (lb >= nb) return;
+    const int64_t b = b0 + lb;
+    const int32_t q = leafpos[b];
+    if (q < 0) return;
+    const int u = threadIdx.x;
+    const double2 p0 = reinterpret_cast<const double2 *>(phi + b * 512)[u];
+    const double2 p1 = reinterpret_cast<const double2 *>(phi + b * 512 + 256)[u];
+    const double2 r0 = reinterpret_cast<const double2 *>(rhs + b * 512)[u];
+    const double2 r1 = reinterpret_cast<const double2 *>(rhs + b * 512 + 256)[u];
+    const FaceTab ft = face_tab(g, b);
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        int e = u + 128 * r, d = e >> 6, w = e & 63;
+        H[e] = ghost_at<double>(g, phi, chat, b, d, pick6(ft.nb, d), pick6(ft.slot, d), w & 7, w >> 3);
+    }
+    reinterpret_cast<double2 *>(P)[u] = p0;
+    reinterpret_cast<double2 *>(P)[128 + u] = p1;
+    __syncthreads();
+    const int l = g.ijk[b * 4 + 3];
+    const double h = g.len / (8.0 * (double)(1 << (l - 1)));
+    const double inv_h2 = 1.0 / (h * h), vol = h * h * h;
+    double ss[2], mx[2], rr[2][2];
+#pragma unroll
+    for (int sl = 0; sl < 2; sl++) {
+        const int t = 2 * u + sl;
+        const int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
+        ss[sl] = 0.0;
+        mx[sl] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            const int i = 2 * m + ((j + k + c) & 1);
+            const double rc = c ? (sl ? r1.y : r1.x) : (sl ? r0.y : r0.x);
+            double r = resid_of<double>(rc, sum_full<double>(P, H, i, j, k), P[c * 256 + t], inv_h2);
+            rr[c][sl] = r;
+            ss[sl] = fmadd(r, r, ss[sl]);
+            mx[sl] = nanmax(fabs(r), mx[sl]);
+        }
+    }
+    if (r_out) {
+        reinterpret_cast<float2 *>(r_out + b * 512)[u] = make_float2((float)rr[0][0], (float)rr[0][1]);
+        reinterpret_cast<float2 *>(r_out + b * 512 + 256)[u] = make_float2((float)rr[1][0], (float)rr[1][1]);
+    }
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+#pragma unroll
+        for (int sl = 0; sl < 2; sl++) {
+            ss[sl] += __shfl_xor(ss[sl], off);
+            mx[sl] = nanmax(__shfl_xor(mx[sl], off), mx[sl]);
+        }
+    }
+    const double st = ss[0] + ss[1], mt = nanmax(mx[1], mx[0]);
+    if ((u & 31) == 0) {
+        S[u >> 5] = st;
+        M[u >> 5] = mt;
+    }
+    __syncthreads();
+    if (u == 0) {
+        partial[2 * (int64_t)q] = ((S[0] + S[1]) + (S[2] + S[3])) * vol;
+        partial[2 * (int64_t)q + 1] = nanmax(nanmax(M[0], M[1]), nanmax(M[2], M[3]));
     }
 }
 
@@ -1867,12 +1969,17 @@ void launch_unpack(const T *cs, double *nat, int64_t nbox, hipStream_t s) {
 }
 template <typename T, int CPT>
 void launch_gsrb_cpt(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb,
-                     T h2, int colour, int xcd, hipStream_t s) {
+                     T h2, int colour, int xcd, hipStream_t s, const int32_t *rmask) {
     dim3 grid((unsigned)(xcd ? xcd_grid(nb) : nb)), block(256 / CPT);
     if (colour == 0)
-        hipLaunchKernelGGL((k_gsrb<0, T, CPT>), grid, block, 0, s, g, phi, rhs, chat, b0, nb, h2, xcd);
+        hipLaunchKernelGGL((k_gsrb<0, T, CPT>), grid, block, 0, s, g, phi, rhs, chat, b0, nb, h2, xcd,
+                           nullptr);
+    else if (rmask)
+        hipLaunchKernelGGL((k_gsrb<1, T, CPT, true>), grid, block, 0, s, g, phi, rhs, chat, b0, nb, h2, xcd,
+                           rmask);
     else
-        hipLaunchKernelGGL((k_gsrb<1, T, CPT>), grid, block, 0, s, g, phi, rhs, chat, b0, nb, h2, xcd);
+        hipLaunchKernelGGL((k_gsrb<1, T, CPT>), grid, block, 0, s, g, phi, rhs, chat, b0, nb, h2, xcd,
+                           nullptr);
 }
 
 template <typename T>
@@ -1891,8 +1998,10 @@ void launch_gsrb_sweep(const Geo &g, const T *src, T *dst, T *rhs, const T *chat
 
 template <typename T>
 void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
-                 int colour, int variant, hipStream_t s) {
+                 int colour, int variant, hipStream_t s, const int32_t *rmask) {
     if (nb <= 0) return;
+    if (rmask && (colour != 1 || !gsrb_restricts(variant)))
+        rmask = nullptr;  // callers check gsrb_restricts first
     if (variant >= kGsrbPipeVariant) {
         // persistent workgroups: at most 2048 (c = 5) or 4096 (c = 6)
         int64_t cap = variant >= kGsrbPipeVariant + 2 ? 4096 : 2048;
@@ -1918,9 +2027,9 @@ void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, 
     if (variant >= kGsrbHalfVariants) variant = kGsrbDefault;
     int xcd = variant & 1;
     switch (variant >> 1) {
-    case 0: launch_gsrb_cpt<T, 1>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s); break;
-    case 2: launch_gsrb_cpt<T, 4>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s); break;
-    default: launch_gsrb_cpt<T, 2>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s); break;
+    case 0: launch_gsrb_cpt<T, 1>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s, rmask); break;
+    case 2: launch_gsrb_cpt<T, 4>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s, rmask); break;
+    default: launch_gsrb_cpt<T, 2>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s, rmask); break;
     }
 }
 template <typename T>
@@ -2005,6 +2114,12 @@ void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const
     hipLaunchKernelGGL(k_leaf_norms, dim3((unsigned)xcd_grid(nleaf)), dim3(256), 0, s, g, phi, rhs,
                        chat, leaf, nleaf, partial, r_out);
 }
+void launch_box_norms(const Geo &g, const double *phi, const double *rhs, const double *chat, int64_t b0,
+                      int64_t nb, const int32_t *leafpos, double *partial, float *r_out, hipStream_t s) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_box_norms, dim3((unsigned)xcd_grid(nb)), dim3(128), 0, s, g, phi, rhs, chat, b0, nb,
+                       leafpos, partial, r_out);
+}
 template <typename T>
 void launch_leaf_apply(const Geo &g, const T *x, const T *chat, const int32_t *leaf, int64_t nleaf,
                        T *out, hipStream_t s) {
@@ -2056,7 +2171,7 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
     template void launch_pack<T>(const double *, T *, int64_t, hipStream_t);                     \
     template void launch_unpack<T>(const T *, double *, int64_t, hipStream_t);                   \
     template void launch_gsrb<T>(const Geo &, T *, const T *, const T *, int64_t, int64_t, T, int, \
-                                 int, hipStream_t);                                              \
+                                 int, hipStream_t, const int32_t *);                             \
     template void launch_gsrb_sweep<T>(const Geo &, const T *, T *, T *, const T *, int64_t,       \
                                        int64_t, T, int, hipStream_t, int, const int32_t *, T, T *); \
     template void launch_restrict_leaves<T>(const Geo &, T *, const int32_t *, int64_t, hipStream_t); \

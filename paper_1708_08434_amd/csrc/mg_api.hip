@@ -126,7 +126,10 @@ template <typename T> bool smooth_fuses_fas(const mg_tree *t, int l, int nsweep)
     int variant = t->sched[sizeof(T) == 4 ? 1 : 0][l];
     return nsweep >= 2 && l >= 2 && variant >= kGsrbFusedVariant && variant < kGsrbOctVariant;
 }
-template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsweep, bool fas_first = false) {
+// rmask: the last half-sweep (a one-box half-sweep variant, black) also
+// restricts the boxes of the mask onto their parents (rst_fuses).
+template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsweep, bool fas_first = false,
+                                  const int32_t *rmask = nullptr) {
     if (nsweep <= 0) return;
     ensure_cf(t, F, l);
     double h = hlev(t, l);
@@ -162,7 +165,7 @@ template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsw
     for (; it < nsweep; it++)  // half-sweeps (a fused schedule's odd last sweep: the default)
         for (int c = 0; c < 2; c++) {
             launch_gsrb<T>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l), h2, c, variant,
-                           stream_of(t));
+                           stream_of(t), c == 1 && it == nsweep - 1 ? rmask : nullptr);
             launches++;
         }
     if (e0) {
@@ -222,6 +225,21 @@ template <typename T> void restrict_all(mg_tree *t, const Fields<T> &F) {
     }
 }
 
+// With MG_FUSE_RESTRICT, does the last up-sweep of level l in a cycle of nu
+// up-sweeps (FP64, the finest level on top) also do level l's part of the
+// restriction before a stopping test?  Levels 1-2 of the one-launch bottom,
+// sweep variants without the restricting kernel, cycles whose up-sweeps are
+// all fused with the prolongation, and a per-level hook (it reads level l's
+// residual after the sweeps) leave it to restrict_for_check.
+bool rst_fuses(const mg_tree *t, int l, int nu) {
+    if (!(t->fusion & MG_FUSE_RESTRICT) || t->level_hook || l < 2 || l > t->nlev) return false;
+    if (t->bottom_ok && t->sched[0][1] != 0 && l < 3) return false;  // use_bottom<double>
+    int variant = t->sched[0][l];
+    if (!gsrb_restricts(variant)) return false;
+    int plain = (t->fusion & MG_FUSE_PROLONG) && nu >= 1 ? nu - 1 : nu;
+    return plain >= 1;
+}
+
 // Before a stopping test: parent cells <- the mean of their children, in one
 // launch over the leaf boxes of the list cleaf.  A residual or c_hat reads a
 // covered cell only next to a leaf cell of its own level, that is across the
@@ -229,8 +247,25 @@ template <typename T> void restrict_all(mg_tree *t, const Fields<T> &F) {
 // leaf box, and under 2:1 nesting such a cell has only leaf children; so the
 // test sees exactly the values of restrict_all.  The next cycle's down-leg
 // restricts every level before it reads it.
-template <typename T> void restrict_for_check(mg_tree *t, const Fields<T> &F) {
-    launch_restrict_leaves<T>(F.g, F.phi, t->d.cleaf, (int64_t)t->cleaf.size(), stream_of(t));
+// nu >= 0 (FP64, after a cycle of nu up-sweeps that ran with rst): the levels
+// whose last up-sweep restricted (rst_fuses) are skipped, the others go in
+// one launch per run of consecutive levels.
+template <typename T> void restrict_for_check(mg_tree *t, const Fields<T> &F, int nu = -1) {
+    if (nu < 0 || sizeof(T) != 8) {
+        launch_restrict_leaves<T>(F.g, F.phi, t->d.cleaf, (int64_t)t->cleaf.size(), stream_of(t));
+    } else {
+        for (int l = 2; l <= t->nlev;) {
+            if (rst_fuses(t, l, nu)) {
+                l++;
+                continue;
+            }
+            int l1 = l;
+            while (l1 + 1 <= t->nlev && !rst_fuses(t, l1 + 1, nu)) l1++;
+            launch_restrict_leaves<T>(F.g, F.phi, t->d.cleaf + t->cstart[l], t->cstart[l1 + 1] - t->cstart[l],
+                                      stream_of(t));
+            l = l1 + 1;
+        }
+    }
     for (int l = t->nlev; l >= 2; l--) dirty(F, l - 1);
 }
 
@@ -256,12 +291,13 @@ template <typename T> void bottom(mg_tree *t, const Fields<T> &F, int nd, int nu
 // (and a half-sweep schedule on the level) the first sweep forms the
 // prolonged values it reads on the fly and no prolongation pass runs; the
 // result is the same bits.
-template <typename T> void prolong_smooth(mg_tree *t, const Fields<T> &F, int l, int nsweep) {
+template <typename T> void prolong_smooth(mg_tree *t, const Fields<T> &F, int l, int nsweep,
+                                          const int32_t *rmask = nullptr) {
     int variant = t->sched[sizeof(T) == 4 ? 1 : 0][l];
     bool fused_sweeps = variant >= kGsrbFusedVariant && variant < kGsrbOctVariant;
     if (!(t->fusion & MG_FUSE_PROLONG) || nsweep < 1 || l < 2 || fused_sweeps) {
         prolong(t, F, l);
-        smooth(t, F, l, nsweep);
+        smooth(t, F, l, nsweep, false, rmask);
         return;
     }
     // the parents' corrections as padded blocks, with c_hat of level l (both
@@ -276,13 +312,16 @@ template <typename T> void prolong_smooth(mg_tree *t, const Fields<T> &F, int l,
         launch_gsrb_pro<T>(F.g, F.phi, F.rhs, pad, F.chat, lbeg(t, l), lcount(t, l), (T)(h * h), c,
                            stream_of(t));
     dirty(F, l);
-    smooth(t, F, l, nsweep - 1);
+    smooth(t, F, l, nsweep - 1, false, rmask);
 }
 
 // pro_top: the top level still needs the prolonged correction before its
 // first smoothing (the FMG pass's interpolation to a new finest level).
+// rst (FP64, top = finest level): the cycle ends in a stopping test, and the
+// levels' last up-sweeps do their part of its restriction (rst_fuses); then
+// call restrict_for_check(t, F, nu).
 template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int nd, int nu,
-                                  bool pro_top = false) {
+                                  bool pro_top = false, bool rst = false) {
     bool one = use_bottom<T>(t) && top >= 2;
     int low = one ? 3 : 2;
     bool deferred = false;
@@ -300,7 +339,8 @@ template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int n
         coarse(t, F);
     }
     for (int l = low; l <= top; l++) {
-        prolong_smooth(t, F, l, nu);
+        bool r = rst && sizeof(T) == 8 && top == t->nlev && rst_fuses(t, l, nu);
+        prolong_smooth(t, F, l, nu, r ? t->d.cmask : nullptr);
         if (sizeof(T) == 8 && t->level_hook && !t->hook_rc) t->hook_rc = t->level_hook(t, l, t->hook_ctx);
     }
 }
@@ -310,7 +350,8 @@ template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int n
 // beff_slot >= 0 (FP64, from phi = 0): the top-down pass also gives the
 // per-tree norms of the residual of phi = 0 (into result[beff_slot ..]), the
 // norms the stopping test divides by, without a pass of their own.
-template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int nu, int beff_slot = -1) {
+template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int nu, int beff_slot = -1,
+                                    bool rst = false) {
     // the top-down FAS pass changes level l-1 only after the last use of
     // c_hat(l), and c_hat(l-1) reads level l-2, still untouched: every c_hat
     // it needs can be computed up front from the initial field
@@ -321,9 +362,9 @@ template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int 
     if (beff_slot >= 0) {
         // leaf boxes on levels below the top-down pass (those of a tree of one
         // or two levels): the norm kernel, on the still zero field
-        int64_t q0 = t->fstart[1], q1 = t->fstart[std::min(low, t->nlev + 1)];
-        launch_leaf_norms(f64(t).g, t->d.phi, t->d.rhs, t->d.chat, t->d.leaf + q0, q1 - q0, t->d.partial + 2 * q0,
-                          nullptr, stream_of(t));
+        int top = std::min(low - 1, t->nlev);
+        launch_box_norms(f64(t).g, t->d.phi, t->d.rhs, t->d.chat, lbeg(t, 1), t->lstart[top] - lbeg(t, 1),
+                         t->d.leafpos, t->d.partial, nullptr, stream_of(t));
         launch_reduce_trees(t->d.partial, t->d.leaf_tree, t->d.chunk, (int64_t)t->chunk.size() / 3, t->d.choff,
                             t->ntree, t->d.part2, t->d.result + beff_slot, stream_of(t));
     }
@@ -332,7 +373,7 @@ template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int 
     } else {
         coarse(t, F);
     }
-    for (int l = low; l <= t->nlev; l++) vcycle(t, F, l, nd, nu, true);
+    for (int l = low; l <= t->nlev; l++) vcycle(t, F, l, nd, nu, true, rst && l == t->nlev);
 }
 
 // Per-tree leaf residual norms of the FP64 solution into result[slot + 2t],
@@ -341,7 +382,7 @@ template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int 
 void norms_launch(mg_tree *t, int slot, float *r32) {
     Fields<double> F = f64(t);
     ensure_cf_all(t, F);
-    launch_leaf_norms(F.g, F.phi, F.rhs, F.chat, t->d.leaf, t->nleaf, t->d.partial, r32, stream_of(t));
+    launch_box_norms(F.g, F.phi, F.rhs, F.chat, 0, t->n, t->d.leafpos, t->d.partial, r32, stream_of(t));
     launch_reduce_trees(t->d.partial, t->d.leaf_tree, t->d.chunk, (int64_t)t->chunk.size() / 3, t->d.choff,
                         t->ntree, t->d.part2, t->d.result + slot, stream_of(t));
 }
@@ -395,25 +436,25 @@ void run_body(mg_tree *t, int seq, int nd, int nu) {
         launch_fill<double>(F.phi, 512 * t->n, 0.0, stream_of(t));
         dirty_all(F);
         if (t->fusion & MG_FUSE_BEFF) {
-            fmg_pass(t, F, nd, nu, 2 * t->ntree);
+            fmg_pass(t, F, nd, nu, 2 * t->ntree, true);
         } else {
             norms_launch(t, 2 * t->ntree, nullptr);
-            fmg_pass(t, F, nd, nu);
+            fmg_pass(t, F, nd, nu, -1, true);
         }
-        restrict_for_check(t, F);
+        restrict_for_check(t, F, nu);
         norms_launch(t, 0, nullptr);
         break;
     case mg_tree::SEQ_VCHECK:
-        vcycle(t, F, t->nlev, nd, nu);
-        restrict_for_check(t, F);
+        vcycle(t, F, t->nlev, nd, nu, false, true);
+        restrict_for_check(t, F, nu);
         norms_launch(t, 0, nullptr);
         break;
     case mg_tree::SEQ_V:
         // a check without its norms: the next cycle starts from the state a
         // check leaves (covered cells read by c_hat restricted, every
         // level's c_hat computed from them), so phi is the same bits
-        vcycle(t, F, t->nlev, nd, nu);
-        restrict_for_check(t, F);
+        vcycle(t, F, t->nlev, nd, nu, false, true);
+        restrict_for_check(t, F, nu);
         ensure_cf_all(t, F);
         break;
     case mg_tree::SEQ_MIX_START:
@@ -1074,6 +1115,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.cleaf = (int32_t *)(base + t->off.cleaf);
     d.oldcp = (int32_t *)(base + t->off.oldcp);
     d.leafpos = (int32_t *)(base + t->off.leafpos);
+    d.cmask = (int32_t *)(base + t->off.cmask);
     d.slots = (int32_t *)(base + t->off.slots);
     d.leaf_tree = (int32_t *)(base + t->off.leaf_tree);
     d.tree_off = (int32_t *)(base + t->off.tree_off);
@@ -1129,6 +1171,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     rc = rc ? rc : up(d.cleaf, t->cleaf.data(), t->cleaf.size() * 4);
     rc = rc ? rc : up(d.oldcp, t->oldcp.data(), t->oldcp.size() * 4);
     rc = rc ? rc : up(d.leafpos, t->leafpos.data(), t->leafpos.size() * 4);
+    rc = rc ? rc : up(d.cmask, t->cmask.data(), t->cmask.size() * 4);
     rc = rc ? rc : up(d.slots, t->slots.data(), t->slots.size() * 4);
     rc = rc ? rc : up(d.leaf_tree, t->leaf_tree.data(), t->leaf_tree.size() * 4);
     rc = rc ? rc : up(d.tree_off, t->tree_off.data(), t->tree_off.size() * 4);

@@ -73,6 +73,7 @@ struct DevTables {
     int32_t *cleaf = nullptr;    // leaf boxes whose parent cells a stopping test reads
     int32_t *oldcp = nullptr;    // per level: leaf boxes whose phi_old a prolongation reads
     int32_t *leafpos = nullptr;  // [n] position in the leaf list, -1 for boxes with children
+    int32_t *cmask = nullptr;    // [n] 1 for the boxes of cleaf
     int32_t *slots = nullptr;    // [nslot][2] (box, face)
     int32_t *leaf_tree = nullptr;  // leaf-list positions grouped by tree (ascending within a tree)
     int32_t *tree_off = nullptr;   // [ntree+1] offsets into leaf_tree
@@ -115,8 +116,10 @@ struct mg_tree {
     std::vector<int32_t> cleaf;                         // leaf boxes restricted before a stopping test
     std::vector<int32_t> oldcp;                         // per level: leaf boxes copied into phi_old
     std::vector<int32_t> leafpos;                       // [n] leaf-list position, -1 if refined
+    std::vector<int32_t> cmask;                         // [n] 1 for the boxes of cleaf
     int64_t ostart[mg::kMaxLevel + 2] = {0};            // oldcp of level l: [ostart[l], ostart[l+1])
     int64_t rstart[mg::kMaxLevel + 2] = {0}, fstart[mg::kMaxLevel + 2] = {0};
+    int64_t cstart[mg::kMaxLevel + 2] = {0};           // per-level offsets into cleaf
     std::vector<int32_t> slots;                         // (box, face) per slot
     mg::RawArray<int32_t> n27;                          // [n][27] same-level box at ijk + o, -1, -2
     std::vector<int32_t> root2;                         // first level-2 box per tree, or -1
@@ -128,7 +131,7 @@ struct mg_tree {
     mg_domain dom{};
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
-    struct { int64_t nbr, cfslot, cfq, xt, pnb, n27, slotx, ijk, parent, refined, leaf, cleaf, oldcp, leafpos, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
+    struct { int64_t nbr, cfslot, cfq, xt, pnb, n27, slotx, ijk, parent, refined, leaf, cleaf, oldcp, leafpos, cmask, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
              phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, swp, fas, dpad, total; } off{};
     // ---- fluid model (mg_fluid_bind): caller's second workspace ----
     void *fws = nullptr;

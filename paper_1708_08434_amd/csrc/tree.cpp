@@ -398,6 +398,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     // where the parent's neighbour there is a leaf box (a refined box has
     // all 8 children and no refinement-boundary face)
     t->cleaf.clear();
+    t->cmask.assign(n, 0);
     for (int64_t q = 0; q < t->nleaf; q++) {
         int64_t b = t->leaf[q];
         if (t->lev[b] < 2) continue;
@@ -406,9 +407,17 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
             int32_t nb = t->nbr[6 * p + 2 * a + (t->ijk[3 * b + a] & 1)];
             if (nb >= 0 && t->child[8 * (int64_t)nb] < 0) {
                 t->cleaf.push_back((int32_t)b);
+                t->cmask[b] = 1;
                 break;
             }
         }
+    }
+    // the list follows the leaf list's level order: level l's entries are
+    // [cstart[l], cstart[l+1])
+    for (int l = 0; l <= kMaxLevel + 1; l++) {
+        int64_t c = 0;
+        while (c < (int64_t)t->cleaf.size() && t->lev[t->cleaf[c]] < l) c++;
+        t->cstart[l] = c;
     }
     // leaf-list positions grouped by tree, ascending inside each tree (the
     // order of the per-tree norm reduction)
@@ -461,6 +470,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.cleaf = take(4 * (int64_t)t->cleaf.size());
     t->off.oldcp = take(4 * (int64_t)t->oldcp.size());
     t->off.leafpos = take(4 * n);
+    t->off.cmask = take(4 * n);
     t->off.slots = take(8 * t->nslot);
     t->off.slotx = take(32 * t->nslot);
     t->off.leaf_tree = take(4 * t->nleaf);

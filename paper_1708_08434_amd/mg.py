@@ -29,7 +29,8 @@ MG_OP_SMOOTH, MG_OP_FAS_DOWN, MG_OP_PROLONG, MG_OP_COARSE, MG_OP_RESTRICT_ALL, M
 MG_OP_F32 = 0x100
 MG_FUSE_PROLONG = 1
 MG_FUSE_BEFF = 2
-MG_FUSE_ALL = 3
+MG_FUSE_RESTRICT = 4
+MG_FUSE_ALL = 7
 MG_GSRB_VARIANTS = 14  # launch variants: 6, 7 fused sweeps, 8, 9 octets, 10-13 persistent
 MG_GSRB_FUSED = (6, 7)
 MG_GSRB_OCTET = (8, 9)
