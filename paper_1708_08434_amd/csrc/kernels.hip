@@ -47,6 +47,41 @@ __device__ __forceinline__ void tangential(int a, int &t1, int &t2) {
 }
 
 // max that carries NaN through (a non-finite residual must reach the test)
+// Loads of data that a launch reads exactly once (right-hand sides) carry
+// the non-temporal hint, so that they do not displace from L2 the cells that
+// neighbouring workgroups re-read as ghosts.
+#ifndef MG_STREAM_RHS
+#define MG_STREAM_RHS 1
+#endif
+template <typename T> struct StreamLd {
+    static __device__ __forceinline__ T ld(const T *p) {
+#if MG_STREAM_RHS
+        return __builtin_nontemporal_load(p);
+#else
+        return *p;
+#endif
+    }
+};
+template <typename E, typename V, int N> struct StreamVec {
+    typedef E native __attribute__((ext_vector_type(N)));
+    static __device__ __forceinline__ V ld(const V *p) {
+#if MG_STREAM_RHS
+        native v = __builtin_nontemporal_load(reinterpret_cast<const native *>(p));
+        V r;
+#pragma unroll
+        for (int i = 0; i < N; i++) reinterpret_cast<E *>(&r)[i] = v[i];
+        return r;
+#else
+        return *p;
+#endif
+    }
+};
+template <> struct StreamLd<double2> : StreamVec<double, double2, 2> {};
+template <> struct StreamLd<double4> : StreamVec<double, double4, 4> {};
+template <> struct StreamLd<float2> : StreamVec<float, float2, 2> {};
+template <> struct StreamLd<float4> : StreamVec<float, float4, 4> {};
+template <typename T> __device__ __forceinline__ T ld_stream(const T *p) { return StreamLd<T>::ld(p); }
+
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
 // Ghost values: Dirichlet face value gv reflected through the boundary cell,
@@ -229,7 +264,7 @@ __global__ __launch_bounds__(256 / CPT) void k_gsrb(Geo g, T *__restrict__ phi,
     int t = threadIdx.x;
     const FaceTab ft = face_tab(g, b);
     V o = reinterpret_cast<const V *>(phi + b * 512 + (1 - C) * 256)[t];
-    V bv = reinterpret_cast<const V *>(rhs + b * 512 + C * 256)[t];
+    V bv = ld_stream(reinterpret_cast<const V *>(rhs + b * 512 + C * 256) + t);
 #pragma unroll
     for (int e = t; e < 192; e += NT) gsrb_ghost<T>(g, ft, phi, chat, b, C, e, H);
     reinterpret_cast<V *>(S)[t] = o;
@@ -313,7 +348,7 @@ __global__ __launch_bounds__(128) void k_gsrb_pipe(Geo g, T *__restrict__ phi, c
     int64_t b = b0 + base;
     FaceTab ft = face_tab(g, b);
     V o = reinterpret_cast<const V *>(phi + b * 512 + (1 - C) * 256)[t];
-    V bv = reinterpret_cast<const V *>(rhs + b * 512 + C * 256)[t];
+    V bv = ld_stream(reinterpret_cast<const V *>(rhs + b * 512 + C * 256) + t);
     T g0 = gsrb_ghost_val<T>(g, ft, phi, chat, b, C, t);
     T g1 = t < 64 ? gsrb_ghost_val<T>(g, ft, phi, chat, b, C, t + 128) : (T)0;
     int64_t nxt = base + step;
@@ -327,7 +362,7 @@ __global__ __launch_bounds__(128) void k_gsrb_pipe(Geo g, T *__restrict__ phi, c
         FaceTab ftnn = ftn;
         if (more) {
             on = reinterpret_cast<const V *>(phi + bn * 512 + (1 - C) * 256)[t];
-            bvn = reinterpret_cast<const V *>(rhs + bn * 512 + C * 256)[t];
+            bvn = ld_stream(reinterpret_cast<const V *>(rhs + bn * 512 + C * 256) + t);
             g0n = gsrb_ghost_val<T>(g, ftn, phi, chat, bn, C, t);
             if (t < 64) g1n = gsrb_ghost_val<T>(g, ftn, phi, chat, bn, C, t + 128);
             if (nxt + step < end) ftnn = face_tab(g, bn + step);
@@ -390,7 +425,7 @@ __global__ __launch_bounds__(512) void k_gsrb_oct(Geo g, T *__restrict__ phi, co
     int ox = 8 * (o & 1), oy = 8 * ((o >> 1) & 1), oz = 8 * (o >> 2);
     // other colour of row (j, k) of box o: 4 values, I/2 = ox/2 + m
     V4 so = reinterpret_cast<const V4 *>(phi + bx * 512 + (1 - C) * 256)[rw];
-    V4 bv = reinterpret_cast<const V4 *>(rhs + bx * 512 + C * 256)[rw];
+    V4 bv = ld_stream(reinterpret_cast<const V4 *>(rhs + bx * 512 + C * 256) + rw);
     // ghosts of the outer surface: entry e = d*128 + v*8 + u/2 over the
     // 16 x 16 face (u along t1, v along t2), cells of colour C
     for (int e = t; e < 768; e += 512) {
@@ -731,7 +766,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Geo g, T *__restrict__ p
     // indices of the parent cells, loaded with the data (not after the barriers)
     const int64_t p = g.parent[b];
     const int bi = g.ijk[b * 4] & 1, bj = g.ijk[b * 4 + 1] & 1, bk = g.ijk[b * 4 + 2] & 1;
-    T r0 = rhs[b * 512 + t], r1 = rhs[b * 512 + 256 + t];
+    T r0 = ld_stream(rhs + b * 512 + t), r1 = ld_stream(rhs + b * 512 + 256 + t);
     if (ZERO) {
         const FaceTab ft = face_tab(g, b);
         P[t] = (T)0;
@@ -1024,7 +1059,7 @@ __global__ __launch_bounds__(128) void k_gsrb_pro_red(Geo g, T *__restrict__ phi
     const int t = threadIdx.x;
     const FaceTab ft = face_tab(g, b);
     V blk = reinterpret_cast<const V *>(phi + b * 512 + 256)[t];
-    V bv = reinterpret_cast<const V *>(rhs + b * 512)[t];
+    V bv = ld_stream(reinterpret_cast<const V *>(rhs + b * 512) + t);
     const T *pk = pad + (lb >> 3) * 1000 + pad_corner(lb);
     T dv0 = pk[pad_off(t)];
     T dv1 = t + 128 < 216 ? pk[pad_off(t + 128)] : (T)0;
@@ -1132,7 +1167,7 @@ __global__ __launch_bounds__(128) void k_gsrb_pro_black(Geo g, T *__restrict__ p
 #pragma unroll
     for (int d = 0; d < 6; d++) bnd = bnd || ft.nb[d] < 0;
     V o = reinterpret_cast<const V *>(phi + b * 512)[t];
-    V bv = reinterpret_cast<const V *>(rhs + b * 512 + 256)[t];
+    V bv = ld_stream(reinterpret_cast<const V *>(rhs + b * 512 + 256) + t);
     T raw[2], in_new[2], ch[2];
 #pragma unroll
     for (int r = 0; r < 2; r++) {
@@ -1655,8 +1690,8 @@ __global__ __launch_bounds__(128) void k_box_norms(Geo g, const double *__restri
     const int u = threadIdx.x;
     const double2 p0 = reinterpret_cast<const double2 *>(phi + b * 512)[u];
     const double2 p1 = reinterpret_cast<const double2 *>(phi + b * 512 + 256)[u];
-    const double2 r0 = reinterpret_cast<const double2 *>(rhs + b * 512)[u];
-    const double2 r1 = reinterpret_cast<const double2 *>(rhs + b * 512 + 256)[u];
+    const double2 r0 = ld_stream(reinterpret_cast<const double2 *>(rhs + b * 512) + u);
+    const double2 r1 = ld_stream(reinterpret_cast<const double2 *>(rhs + b * 512 + 256) + u);
     const FaceTab ft = face_tab(g, b);
 #pragma unroll
     for (int r = 0; r < 3; r++) {
