@@ -461,9 +461,13 @@ int mg_set_schedule(mg_tree *t, int precision, const int32_t *schedule);
  *     test's residual and c_hat read) is done by each level's last black
  *     half-sweep of the cycle, on the levels whose sweep variant is a
  *     one-box half-sweep, instead of by a pass of its own.
+ *   MG_FUSE_IR: in the mixed-precision solve, the FP64 update phi += e and
+ *     that restriction are done by the FP32 correction cycle's last black
+ *     half-sweep of each level (from the lowest level of the run up to the
+ *     finest whose sweep variant has it), instead of by passes of their own.
  * MG_EINVAL on unknown flags.  Changing the flags drops recorded graphs.
  */
-enum { MG_FUSE_PROLONG = 1, MG_FUSE_BEFF = 2, MG_FUSE_RESTRICT = 4, MG_FUSE_ALL = 7 };
+enum { MG_FUSE_PROLONG = 1, MG_FUSE_BEFF = 2, MG_FUSE_RESTRICT = 4, MG_FUSE_IR = 8, MG_FUSE_ALL = 15 };
 int mg_set_fusion(mg_tree *t, int flags);
 
 /*

@@ -45,13 +45,20 @@ constexpr int kGsrbOctVariant = 8;    // 8, 9: octet half-sweeps
 constexpr int kGsrbPipeVariant = 10;  // 10..13: persistent prefetching half-sweeps
 constexpr int kGsrbDefault = 3;       // 2 cells per thread, XCD mapping
 // One colour in place; a fused variant, or an octet variant on a box count
-// that is not a multiple of 8, falls back to kGsrbDefault.  rmask (black
-// colour, variants with gsrb_restricts): the boxes with rmask[b] != 0 also
-// restrict their swept values onto their parent cells.
+// that is not a multiple of 8, falls back to kGsrbDefault.  Black colour
+// only: with phi64 (FP32, variants with gsrb_updates) every box also adds its
+// new correction to phi64 (phi64 += (double) e on all its cells) and the
+// boxes with rmask[b] != 0 (rmask may be null) restrict the updated phi64
+// onto their parents' cells; without phi64, rmask (variants with
+// gsrb_restricts) makes those boxes restrict their swept values.
 template <typename T>
 void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
-                 int colour, int variant, hipStream_t s, const int32_t *rmask = nullptr);
+                 int colour, int variant, hipStream_t s, const int32_t *rmask = nullptr,
+                 double *phi64 = nullptr);
 constexpr bool gsrb_restricts(int variant) { return variant >= 0 && variant < kGsrbHalfVariants; }
+constexpr bool gsrb_updates(int variant) {
+    return gsrb_restricts(variant) || (variant >= kGsrbOctVariant && variant < kGsrbPipeVariant);
+}
 // One full sweep (red, then black) from src into dst (no aliasing).
 template <typename T>
 // fas = 1: also complete the FAS right-hand side L src + restricted

@@ -244,19 +244,69 @@ template <> struct VecN<float, 1> { using type = float; };
 template <> struct VecN<float, 2> { using type = float2; };
 template <> struct VecN<float, 4> { using type = float4; };
 
-// RST (black colour only): boxes with rmask[b] != 0 also set their parent
-// cells to the mean of the 8 children under each, from the swept values (the
-// arithmetic of k_restrict_leaves), when this is the box's last sweep of the
-// cycle.
-template <int C, typename T, int CPT, bool RST = false>
+// Restriction of a box's 512 values (colour-split, in LDS) onto its parent's
+// cells: the mean of the 8 children under each, k_restrict_leaves' order.
+template <typename T>
+__device__ __forceinline__ void restrict_box(const Geo &g, const T *U, int64_t b, T *__restrict__ dst, int e) {
+    int pi = e & 3, pj = (e >> 2) & 3, pk = e >> 4;
+    T sum = 0;
+#pragma unroll
+    for (int dk = 0; dk < 2; dk++)
+#pragma unroll
+        for (int dj = 0; dj < 2; dj++)
+#pragma unroll
+            for (int di = 0; di < 2; di++) sum += U[cs_idx(2 * pi + di, 2 * pj + dj, 2 * pk + dk)];
+    int64_t p = g.parent[b];
+    int ci = 4 * (g.ijk[b * 4] & 1) + pi, cj = 4 * (g.ijk[b * 4 + 1] & 1) + pj, ck = 4 * (g.ijk[b * 4 + 2] & 1) + pk;
+    dst[p * 512 + cs_idx(ci, cj, ck)] = (T)0.125 * sum;
+}
+
+// phi64 += (double) e on N cells of each colour at colour-half position q0
+// (k_ir_update's arithmetic); the updated values are also left in U
+// (colour-split) when U is set.
+template <typename T, int N>
+__device__ __forceinline__ void ir_add(double *__restrict__ phi64, int64_t b, int C, int q0, const T *eC,
+                                       const T *eO, double *U) {
+    using D = typename VecN<double, N>::type;
+    D *pc = reinterpret_cast<D *>(phi64 + b * 512 + C * 256 + q0);
+    D *po = reinterpret_cast<D *>(phi64 + b * 512 + (1 - C) * 256 + q0);
+    D vc = *pc, vo = *po;
+    double *xc = reinterpret_cast<double *>(&vc), *xo = reinterpret_cast<double *>(&vo);
+#pragma unroll
+    for (int w = 0; w < N; w++) {
+        xc[w] += (double)eC[w];
+        xo[w] += (double)eO[w];
+    }
+    *pc = vc;
+    *po = vo;
+    if (U) {
+#pragma unroll
+        for (int w = 0; w < N; w++) {
+            U[C * 256 + q0 + w] = xc[w];
+            U[(1 - C) * 256 + q0 + w] = xo[w];
+        }
+    }
+}
+
+// Modes of the black half-sweep when it is a box's last sweep of the cycle
+// before a stopping test:
+//  kSweepRestrict: boxes with rmask[b] != 0 also set their parent cells to
+//    the mean of the 8 children under each, from the swept values.
+//  kSweepIrUpdate (FP32 correction cycle): phi64 += e on all 512 cells of
+//    the box (the refinement update), and boxes with rmask set restrict the
+//    updated phi64 onto their parents (rmask may be null).
+constexpr int kSweepPlain = 0, kSweepRestrict = 1, kSweepIrUpdate = 2;
+template <int C, typename T, int CPT, int MODE = kSweepPlain>
 __global__ __launch_bounds__(256 / CPT) void k_gsrb(Geo g, T *__restrict__ phi,
                                                     const T *__restrict__ rhs,
                                                     const T *__restrict__ chat, int64_t b0,
                                                     int64_t nbx, T h2, int xcd,
-                                                    const int32_t *__restrict__ rmask = nullptr) {
+                                                    const int32_t *__restrict__ rmask = nullptr,
+                                                    double *__restrict__ phi64 = nullptr) {
     using V = typename VecN<T, CPT>::type;
     constexpr int NT = 256 / CPT;
-    __shared__ T SB[RST ? 512 : 256], H[192];
+    __shared__ T SB[MODE == kSweepRestrict ? 512 : 256], H[192];
+    __shared__ double U[MODE == kSweepIrUpdate ? 512 : 1];
     T *S = SB;
     int64_t lb = xcd ? xcd_map(blockIdx.x, nbx) : (int64_t)blockIdx.x;
     if (lb >= nbx) return;
@@ -288,23 +338,18 @@ __global__ __launch_bounds__(256 / CPT) void k_gsrb(Geo g, T *__restrict__ phi,
         out[w] = (s - h2 * bb[w]) * (T)kSixth;
     }
     reinterpret_cast<V *>(phi + b * 512 + C * 256)[t] = res;
-    if (RST && rmask[b]) {  // block-uniform
+    if (MODE == kSweepRestrict && rmask[b]) {  // block-uniform
         // SB: colour 0 (the staged other colour) then colour 1 (this sweep's)
         reinterpret_cast<V *>(SB + 256)[t] = res;
         __syncthreads();
-        for (int e = t; e < 64; e += NT) {
-            int pi = e & 3, pj = (e >> 2) & 3, pk = e >> 4;
-            T sum = 0;
-#pragma unroll
-            for (int dk = 0; dk < 2; dk++)
-#pragma unroll
-                for (int dj = 0; dj < 2; dj++)
-#pragma unroll
-                    for (int di = 0; di < 2; di++) sum += SB[cs_idx(2 * pi + di, 2 * pj + dj, 2 * pk + dk)];
-            int64_t p = g.parent[b];
-            int ci = 4 * (g.ijk[b * 4] & 1) + pi, cj = 4 * (g.ijk[b * 4 + 1] & 1) + pj,
-                ck = 4 * (g.ijk[b * 4 + 2] & 1) + pk;
-            phi[p * 512 + cs_idx(ci, cj, ck)] = (T)0.125 * sum;
+        for (int e = t; e < 64; e += NT) restrict_box<T>(g, SB, b, phi, e);
+    }
+    if (MODE == kSweepIrUpdate) {
+        const bool r = rmask && rmask[b];  // block-uniform
+        ir_add<T, CPT>(phi64, b, C, CPT * t, out, reinterpret_cast<const T *>(&o), r ? U : nullptr);
+        if (r) {
+            __syncthreads();
+            for (int e = t; e < 64; e += NT) restrict_box<double>(g, U, b, phi64, e);
         }
     }
 }
@@ -409,13 +454,16 @@ __global__ __launch_bounds__(128) void k_gsrb_pipe(Geo g, T *__restrict__ phi, c
 // cells of this colour) needs ghosts: half the ghost traffic per cell of the
 // one-box launches.  S holds the other colour of the 16^3 grid (colour-split
 // rows: (K*16 + J)*8 + I/2); thread t owns one box row (4 cells) of colour C,
-// read and written as one vector.  Same arithmetic per cell as k_gsrb.
-template <int C, typename T>
+// read and written as one vector.  Same arithmetic per cell as k_gsrb.  IR:
+// k_gsrb's kSweepIrUpdate mode (each box's 64 threads restrict it).
+template <int C, typename T, bool IR = false>
 __global__ __launch_bounds__(512) void k_gsrb_oct(Geo g, T *__restrict__ phi, const T *__restrict__ rhs,
                                                   const T *__restrict__ chat, int64_t b0, int64_t noct,
-                                                  T h2, int xcd) {
+                                                  T h2, int xcd, const int32_t *__restrict__ rmask = nullptr,
+                                                  double *__restrict__ phi64 = nullptr) {
     using V4 = typename VecN<T, 4>::type;
     __shared__ T S[2048], H[6 * 128];
+    __shared__ double U[IR ? 8 * 512 : 1];
     int64_t lo = xcd ? xcd_map(blockIdx.x, noct) : (int64_t)blockIdx.x;
     if (lo >= noct) return;
     int64_t ob = b0 + 8 * lo;
@@ -464,6 +512,13 @@ __global__ __launch_bounds__(512) void k_gsrb_oct(Geo g, T *__restrict__ phi, co
         out[m] = (s - h2 * bb[m]) * (T)kSixth;
     }
     reinterpret_cast<V4 *>(phi + bx * 512 + C * 256)[rw] = res;
+    if (IR) {
+        ir_add<T, 4>(phi64, bx, C, 4 * rw, out, reinterpret_cast<const T *>(&so), rmask ? U + o * 512 : nullptr);
+        if (rmask) {
+            __syncthreads();
+            if (rmask[bx]) restrict_box<double>(g, U + o * 512, bx, phi64, rw);
+        }
+    }
 }
 
 // One full red-black sweep (red half, then black half) of boxes [b0, b0+nbx)
@@ -2004,17 +2059,20 @@ void launch_unpack(const T *cs, double *nat, int64_t nbox, hipStream_t s) {
 }
 template <typename T, int CPT>
 void launch_gsrb_cpt(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb,
-                     T h2, int colour, int xcd, hipStream_t s, const int32_t *rmask) {
+                     T h2, int colour, int xcd, hipStream_t s, const int32_t *rmask, double *phi64) {
     dim3 grid((unsigned)(xcd ? xcd_grid(nb) : nb)), block(256 / CPT);
     if (colour == 0)
         hipLaunchKernelGGL((k_gsrb<0, T, CPT>), grid, block, 0, s, g, phi, rhs, chat, b0, nb, h2, xcd,
-                           nullptr);
+                           nullptr, nullptr);
+    else if (phi64)
+        hipLaunchKernelGGL((k_gsrb<1, T, CPT, kSweepIrUpdate>), grid, block, 0, s, g, phi, rhs, chat, b0, nb,
+                           h2, xcd, rmask, phi64);
     else if (rmask)
-        hipLaunchKernelGGL((k_gsrb<1, T, CPT, true>), grid, block, 0, s, g, phi, rhs, chat, b0, nb, h2, xcd,
-                           rmask);
+        hipLaunchKernelGGL((k_gsrb<1, T, CPT, kSweepRestrict>), grid, block, 0, s, g, phi, rhs, chat, b0, nb,
+                           h2, xcd, rmask, nullptr);
     else
         hipLaunchKernelGGL((k_gsrb<1, T, CPT>), grid, block, 0, s, g, phi, rhs, chat, b0, nb, h2, xcd,
-                           nullptr);
+                           nullptr, nullptr);
 }
 
 template <typename T>
@@ -2033,10 +2091,13 @@ void launch_gsrb_sweep(const Geo &g, const T *src, T *dst, T *rhs, const T *chat
 
 template <typename T>
 void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, int64_t nb, T h2,
-                 int colour, int variant, hipStream_t s, const int32_t *rmask) {
+                 int colour, int variant, hipStream_t s, const int32_t *rmask, double *phi64) {
     if (nb <= 0) return;
-    if (rmask && (colour != 1 || !gsrb_restricts(variant)))
-        rmask = nullptr;  // callers check gsrb_restricts first
+    if (colour != 1 || (phi64 ? !gsrb_updates(variant) : !gsrb_restricts(variant))) {
+        rmask = nullptr;  // callers check gsrb_restricts / gsrb_updates first
+        phi64 = nullptr;
+    }
+    if (sizeof(T) != 4) phi64 = nullptr;
     if (variant >= kGsrbPipeVariant) {
         // persistent workgroups: at most 2048 (c = 5) or 4096 (c = 6)
         int64_t cap = variant >= kGsrbPipeVariant + 2 ? 4096 : 2048;
@@ -2054,17 +2115,22 @@ void launch_gsrb(const Geo &g, T *phi, const T *rhs, const T *chat, int64_t b0, 
         int xcd = variant & 1;
         dim3 grid((unsigned)(xcd ? xcd_grid(noct) : noct));
         if (colour == 0)
-            hipLaunchKernelGGL((k_gsrb_oct<0, T>), grid, dim3(512), 0, s, g, phi, rhs, chat, b0, noct, h2, xcd);
+            hipLaunchKernelGGL((k_gsrb_oct<0, T>), grid, dim3(512), 0, s, g, phi, rhs, chat, b0, noct, h2, xcd,
+                               nullptr, nullptr);
+        else if (phi64)
+            hipLaunchKernelGGL((k_gsrb_oct<1, T, true>), grid, dim3(512), 0, s, g, phi, rhs, chat, b0, noct, h2,
+                               xcd, rmask, phi64);
         else
-            hipLaunchKernelGGL((k_gsrb_oct<1, T>), grid, dim3(512), 0, s, g, phi, rhs, chat, b0, noct, h2, xcd);
+            hipLaunchKernelGGL((k_gsrb_oct<1, T>), grid, dim3(512), 0, s, g, phi, rhs, chat, b0, noct, h2, xcd,
+                               nullptr, nullptr);
         return;
     }
     if (variant >= kGsrbHalfVariants) variant = kGsrbDefault;
     int xcd = variant & 1;
     switch (variant >> 1) {
-    case 0: launch_gsrb_cpt<T, 1>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s, rmask); break;
-    case 2: launch_gsrb_cpt<T, 4>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s, rmask); break;
-    default: launch_gsrb_cpt<T, 2>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s, rmask); break;
+    case 0: launch_gsrb_cpt<T, 1>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s, rmask, phi64); break;
+    case 2: launch_gsrb_cpt<T, 4>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s, rmask, phi64); break;
+    default: launch_gsrb_cpt<T, 2>(g, phi, rhs, chat, b0, nb, h2, colour, xcd, s, rmask, phi64); break;
     }
 }
 template <typename T>
@@ -2206,7 +2272,7 @@ void launch_reduce_trees(const double *partial, const int32_t *leaf_tree, const 
     template void launch_pack<T>(const double *, T *, int64_t, hipStream_t);                     \
     template void launch_unpack<T>(const T *, double *, int64_t, hipStream_t);                   \
     template void launch_gsrb<T>(const Geo &, T *, const T *, const T *, int64_t, int64_t, T, int, \
-                                 int, hipStream_t, const int32_t *);                             \
+                                 int, hipStream_t, const int32_t *, double *);                   \
     template void launch_gsrb_sweep<T>(const Geo &, const T *, T *, T *, const T *, int64_t,       \
                                        int64_t, T, int, hipStream_t, int, const int32_t *, T, T *); \
     template void launch_restrict_leaves<T>(const Geo &, T *, const int32_t *, int64_t, hipStream_t); \

@@ -126,10 +126,11 @@ template <typename T> bool smooth_fuses_fas(const mg_tree *t, int l, int nsweep)
     int variant = t->sched[sizeof(T) == 4 ? 1 : 0][l];
     return nsweep >= 2 && l >= 2 && variant >= kGsrbFusedVariant && variant < kGsrbOctVariant;
 }
-// rmask: the last half-sweep (a one-box half-sweep variant, black) also
-// restricts the boxes of the mask onto their parents (rst_fuses).
+// rmask / phi64: the last half-sweep (black) also restricts the boxes of the
+// mask onto their parents (rst_fuses), or with phi64 (FP32) adds the
+// correction to phi64 and restricts the updated values (ir_fuses).
 template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsweep, bool fas_first = false,
-                                  const int32_t *rmask = nullptr) {
+                                  const int32_t *rmask = nullptr, double *phi64 = nullptr) {
     if (nsweep <= 0) return;
     ensure_cf(t, F, l);
     double h = hlev(t, l);
@@ -164,8 +165,9 @@ template <typename T> void smooth(mg_tree *t, const Fields<T> &F, int l, int nsw
     }
     for (; it < nsweep; it++)  // half-sweeps (a fused schedule's odd last sweep: the default)
         for (int c = 0; c < 2; c++) {
+            bool last = c == 1 && it == nsweep - 1;
             launch_gsrb<T>(F.g, F.phi, F.rhs, F.chat, lbeg(t, l), lcount(t, l), h2, c, variant,
-                           stream_of(t), c == 1 && it == nsweep - 1 ? rmask : nullptr);
+                           stream_of(t), last ? rmask : nullptr, last ? phi64 : nullptr);
             launches++;
         }
     if (e0) {
@@ -240,6 +242,27 @@ bool rst_fuses(const mg_tree *t, int l, int nu) {
     return plain >= 1;
 }
 
+// With MG_FUSE_IR, does the last up-sweep of level l in an FP32 correction
+// cycle of nu up-sweeps also add the level's correction to the FP64 field
+// (and restrict it)?  Same exclusions as rst_fuses, with the FP32 schedule
+// and the variants that have the update.
+bool ir_fuses(const mg_tree *t, int l, int nu) {
+    if (!(t->fusion & MG_FUSE_IR) || l < 2 || l > t->nlev) return false;
+    if (t->bottom_ok && t->sched[1][1] != 0 && l < 3) return false;  // use_bottom<float>
+    int variant = t->sched[1][l];
+    if (!gsrb_updates(variant)) return false;
+    int plain = (t->fusion & MG_FUSE_PROLONG) && nu >= 1 ? nu - 1 : nu;
+    return plain >= 1;
+}
+// The lowest level of the run of levels up to the finest whose last up-sweep
+// does the update (t->nlev + 1: none).  Level ir_low's own restriction stays
+// after the cycle: its parents are updated only then.
+int ir_low(const mg_tree *t, int nu) {
+    int l = t->nlev;
+    while (l >= 2 && ir_fuses(t, l, nu)) l--;
+    return l + 1;
+}
+
 // Before a stopping test: parent cells <- the mean of their children, in one
 // launch over the leaf boxes of the list cleaf.  A residual or c_hat reads a
 // covered cell only next to a leaf cell of its own level, that is across the
@@ -292,12 +315,12 @@ template <typename T> void bottom(mg_tree *t, const Fields<T> &F, int nd, int nu
 // prolonged values it reads on the fly and no prolongation pass runs; the
 // result is the same bits.
 template <typename T> void prolong_smooth(mg_tree *t, const Fields<T> &F, int l, int nsweep,
-                                          const int32_t *rmask = nullptr) {
+                                          const int32_t *rmask = nullptr, double *phi64 = nullptr) {
     int variant = t->sched[sizeof(T) == 4 ? 1 : 0][l];
     bool fused_sweeps = variant >= kGsrbFusedVariant && variant < kGsrbOctVariant;
     if (!(t->fusion & MG_FUSE_PROLONG) || nsweep < 1 || l < 2 || fused_sweeps) {
         prolong(t, F, l);
-        smooth(t, F, l, nsweep, false, rmask);
+        smooth(t, F, l, nsweep, false, rmask, phi64);
         return;
     }
     // the parents' corrections as padded blocks, with c_hat of level l (both
@@ -312,16 +335,18 @@ template <typename T> void prolong_smooth(mg_tree *t, const Fields<T> &F, int l,
         launch_gsrb_pro<T>(F.g, F.phi, F.rhs, pad, F.chat, lbeg(t, l), lcount(t, l), (T)(h * h), c,
                            stream_of(t));
     dirty(F, l);
-    smooth(t, F, l, nsweep - 1, false, rmask);
+    smooth(t, F, l, nsweep - 1, false, rmask, phi64);
 }
 
 // pro_top: the top level still needs the prolonged correction before its
 // first smoothing (the FMG pass's interpolation to a new finest level).
 // rst (FP64, top = finest level): the cycle ends in a stopping test, and the
 // levels' last up-sweeps do their part of its restriction (rst_fuses); then
-// call restrict_for_check(t, F, nu).
+// call restrict_for_check(t, F, nu).  ir (FP32 correction cycle, top =
+// finest level): the last up-sweeps of the levels from ir_low up also add
+// the correction to the FP64 field and restrict it; then call ir_finish.
 template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int nd, int nu,
-                                  bool pro_top = false, bool rst = false) {
+                                  bool pro_top = false, bool rst = false, bool ir = false) {
     bool one = use_bottom<T>(t) && top >= 2;
     int low = one ? 3 : 2;
     bool deferred = false;
@@ -338,9 +363,13 @@ template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int n
     } else {
         coarse(t, F);
     }
+    int lf = ir && sizeof(T) == 4 && top == t->nlev ? ir_low(t, nu) : t->nlev + 1;
     for (int l = low; l <= top; l++) {
         bool r = rst && sizeof(T) == 8 && top == t->nlev && rst_fuses(t, l, nu);
-        prolong_smooth(t, F, l, nu, r ? t->d.cmask : nullptr);
+        if (l >= lf)
+            prolong_smooth(t, F, l, nu, l > lf ? t->d.cmask : nullptr, t->d.phi);
+        else
+            prolong_smooth(t, F, l, nu, r ? t->d.cmask : nullptr);
         if (sizeof(T) == 8 && t->level_hook && !t->hook_rc) t->hook_rc = t->level_hook(t, l, t->hook_ctx);
     }
 }
@@ -351,7 +380,7 @@ template <typename T> void vcycle(mg_tree *t, const Fields<T> &F, int top, int n
 // per-tree norms of the residual of phi = 0 (into result[beff_slot ..]), the
 // norms the stopping test divides by, without a pass of their own.
 template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int nu, int beff_slot = -1,
-                                    bool rst = false) {
+                                    bool rst = false, bool ir = false) {
     // the top-down FAS pass changes level l-1 only after the last use of
     // c_hat(l), and c_hat(l-1) reads level l-2, still untouched: every c_hat
     // it needs can be computed up front from the initial field
@@ -373,7 +402,25 @@ template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int 
     } else {
         coarse(t, F);
     }
-    for (int l = low; l <= t->nlev; l++) vcycle(t, F, l, nd, nu, true, rst && l == t->nlev);
+    for (int l = low; l <= t->nlev; l++) vcycle(t, F, l, nd, nu, true, rst && l == t->nlev, ir && l == t->nlev);
+}
+
+// After an FP32 correction cycle run with ir: the update phi += e of the
+// levels below ir_low (one launch over their boxes), then the restriction of
+// the leaf boxes of levels 2 .. ir_low (their parents are updated now).
+// Without ir: the update of every box, then restrict_for_check.
+void ir_finish(mg_tree *t, int nu, bool ir) {
+    Fields<double> F = f64(t);
+    int lf = ir ? ir_low(t, nu) : t->nlev + 1;
+    if (lf > t->nlev) {
+        launch_ir_update(F.phi, f32(t).phi, 512 * t->n, stream_of(t));
+        restrict_for_check(t, F);
+        return;
+    }
+    launch_ir_update(F.phi, f32(t).phi, 512 * t->lstart[lf - 1], stream_of(t));
+    launch_restrict_leaves<double>(F.g, F.phi, t->d.cleaf + t->cstart[2], t->cstart[lf + 1] - t->cstart[2],
+                                   stream_of(t));
+    for (int l = t->nlev; l >= 2; l--) dirty(F, l - 1);
 }
 
 // Per-tree leaf residual norms of the FP64 solution into result[slot + 2t],
@@ -464,15 +511,17 @@ void run_body(mg_tree *t, int seq, int nd, int nu) {
         break;
     case mg_tree::SEQ_MIX_FMG:
     case mg_tree::SEQ_MIX_V:
+    {
         launch_fill<float>(E.phi, 512 * t->n, 0.0f, stream_of(t));
         dirty_all(E);
-        if (seq == mg_tree::SEQ_MIX_FMG) fmg_pass(t, E, nd, nu);
-        else vcycle(t, E, t->nlev, nd, nu);
-        launch_ir_update(F.phi, E.phi, 512 * t->n, stream_of(t));
+        bool ir = t->fusion & MG_FUSE_IR;
+        if (seq == mg_tree::SEQ_MIX_FMG) fmg_pass(t, E, nd, nu, -1, false, ir);
+        else vcycle(t, E, t->nlev, nd, nu, false, false, ir);
         dirty_all(F);
-        restrict_for_check(t, F);
+        ir_finish(t, nu, ir);
         norms_launch(t, 0, E.rhs);
         break;
+    }
     }
 }
 

@@ -30,7 +30,8 @@ MG_OP_F32 = 0x100
 MG_FUSE_PROLONG = 1
 MG_FUSE_BEFF = 2
 MG_FUSE_RESTRICT = 4
-MG_FUSE_ALL = 7
+MG_FUSE_IR = 8
+MG_FUSE_ALL = 15
 MG_GSRB_VARIANTS = 14  # launch variants: 6, 7 fused sweeps, 8, 9 octets, 10-13 persistent
 MG_GSRB_FUSED = (6, 7)
 MG_GSRB_OCTET = (8, 9)
