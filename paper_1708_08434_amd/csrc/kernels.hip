@@ -795,24 +795,32 @@ __device__ __forceinline__ T ghost_of_zero(const Geo &g, const T *__restrict__ c
 }
 
 template <typename T, bool ZERO>
-__global__ __launch_bounds__(256) void k_resid_restrict(Geo g, T *__restrict__ phi, T *__restrict__ rhs,
+__global__ __launch_bounds__(128) void k_resid_restrict(Geo g, T *__restrict__ phi, T *__restrict__ rhs,
                                                         T *__restrict__ old, const T *__restrict__ chat,
                                                         int64_t b0, int64_t nbx,
                                                         const int32_t *__restrict__ leaf_prev,
                                                         int64_t nleaf_prev, T inv_h2,
                                                         const int32_t *__restrict__ leafpos,
                                                         double *__restrict__ partial, double vol) {
+    // 128 threads per box: thread u holds cell positions 2u and 2u+1 of both
+    // colours (paired loads); the ZERO norm partials follow k_box_norms' tree
+    using V = typename VecN<T, 2>::type;
     __shared__ T P[512], H[384], R[512];
     __shared__ double S[4], M[4];
     int64_t blk = blockIdx.x;
-    int t = threadIdx.x;
+    const int u = threadIdx.x;
     int64_t nmain = xcd_grid(nbx);
     if (blk >= nmain) {
         int64_t q = blk - nmain;
         if (q >= nleaf_prev) return;
         int64_t p = leaf_prev[q];
-        old[p * 512 + t] = ZERO ? (T)0 : phi[p * 512 + t];
-        old[p * 512 + 256 + t] = ZERO ? (T)0 : phi[p * 512 + 256 + t];
+        V *dst = reinterpret_cast<V *>(old + p * 512);
+        const V *src = reinterpret_cast<const V *>(phi + p * 512);
+        V z;
+        z.x = (T)0;
+        z.y = (T)0;
+        dst[u] = ZERO ? z : src[u];
+        dst[128 + u] = ZERO ? z : src[128 + u];
         return;
     }
     int64_t lb = xcd_map(blk, nbx);
@@ -821,55 +829,71 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Geo g, T *__restrict__ p
     // indices of the parent cells, loaded with the data (not after the barriers)
     const int64_t p = g.parent[b];
     const int bi = g.ijk[b * 4] & 1, bj = g.ijk[b * 4 + 1] & 1, bk = g.ijk[b * 4 + 2] & 1;
-    T r0 = ld_stream(rhs + b * 512 + t), r1 = ld_stream(rhs + b * 512 + 256 + t);
+    const V r0 = ld_stream(reinterpret_cast<const V *>(rhs + b * 512) + u);
+    const V r1 = ld_stream(reinterpret_cast<const V *>(rhs + b * 512 + 256) + u);
+    const FaceTab ft = face_tab(g, b);
     if (ZERO) {
-        const FaceTab ft = face_tab(g, b);
-        P[t] = (T)0;
-        P[256 + t] = (T)0;
+        V z;
+        z.x = (T)0;
+        z.y = (T)0;
+        reinterpret_cast<V *>(P)[u] = z;
+        reinterpret_cast<V *>(P)[128 + u] = z;
 #pragma unroll
-        for (int r = 0; r < 2; r++) {
-            int e = t + 256 * r;
-            if (e < 384) {
-                int d = e >> 6, w = e & 63;
-                H[e] = ghost_of_zero<T>(g, chat, b, d, pick6(ft.nb, d), pick6(ft.slot, d), w & 7, w >> 3);
-            }
+        for (int r = 0; r < 3; r++) {
+            int e = u + 128 * r, d = e >> 6, w = e & 63;
+            H[e] = ghost_of_zero<T>(g, chat, b, d, pick6(ft.nb, d), pick6(ft.slot, d), w & 7, w >> 3);
         }
     } else {
-        stage_full<T>(g, phi, chat, b, P, H);
+        const V p0 = reinterpret_cast<const V *>(phi + b * 512)[u];
+        const V p1 = reinterpret_cast<const V *>(phi + b * 512 + 256)[u];
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            int e = u + 128 * r, d = e >> 6, w = e & 63;
+            H[e] = ghost_at<T>(g, phi, chat, b, d, pick6(ft.nb, d), pick6(ft.slot, d), w & 7, w >> 3);
+        }
+        reinterpret_cast<V *>(P)[u] = p0;
+        reinterpret_cast<V *>(P)[128 + u] = p1;
     }
     __syncthreads();
-    int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
-    double ss = 0.0, mx = 0.0;
+    double ss[2] = {0.0, 0.0}, mx[2] = {0.0, 0.0};
 #pragma unroll
-    for (int c = 0; c < 2; c++) {
-        int i = 2 * m + ((j + k + c) & 1);
-        T own = P[c * 256 + t];
-        T s = sum_full<T>(P, H, i, j, k);
-        T r = resid_of<T>(c ? r1 : r0, s, own, inv_h2);
-        R[c * 256 + t] = r;
-        if (ZERO) {
-            ss = fmadd((double)r, (double)r, ss);
-            mx = nanmax(fabs((double)r), mx);
+    for (int sl = 0; sl < 2; sl++) {
+        const int t = 2 * u + sl;
+        const int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            int i = 2 * m + ((j + k + c) & 1);
+            T rc = c ? (sl ? r1.y : r1.x) : (sl ? r0.y : r0.x);
+            T r = resid_of<T>(rc, sum_full<T>(P, H, i, j, k), P[c * 256 + t], inv_h2);
+            R[c * 256 + t] = r;
+            if (ZERO) {
+                ss[sl] = fmadd((double)r, (double)r, ss[sl]);
+                mx[sl] = nanmax(fabs((double)r), mx[sl]);
+            }
         }
     }
     if (ZERO && leafpos[b] >= 0) {  // block-uniform
-        for (int off = 32; off > 0; off >>= 1) {
-            ss += __shfl_xor(ss, off);
-            mx = nanmax(__shfl_xor(mx, off), mx);
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) {
+#pragma unroll
+            for (int sl = 0; sl < 2; sl++) {
+                ss[sl] += __shfl_xor(ss[sl], off);
+                mx[sl] = nanmax(__shfl_xor(mx[sl], off), mx[sl]);
+            }
         }
-        if ((t & 63) == 0) {
-            S[t >> 6] = ss;
-            M[t >> 6] = mx;
+        if ((u & 31) == 0) {
+            S[u >> 5] = ss[0] + ss[1];
+            M[u >> 5] = nanmax(mx[1], mx[0]);
         }
     }
     __syncthreads();
-    if (ZERO && t == 0 && leafpos[b] >= 0) {
+    if (ZERO && u == 0 && leafpos[b] >= 0) {
         int64_t q = leafpos[b];
         partial[2 * q] = ((S[0] + S[1]) + (S[2] + S[3])) * vol;
         partial[2 * q + 1] = nanmax(nanmax(M[0], M[1]), nanmax(M[2], M[3]));
     }
-    if (t < 64) {
-        int pi = t & 3, pj = (t >> 2) & 3, pk = t >> 4;
+    if (u < 64) {
+        int pi = u & 3, pj = (u >> 2) & 3, pk = u >> 4;
         T sphi = 0, sres = 0;
 #pragma unroll
         for (int dk = 0; dk < 2; dk++)
@@ -2147,10 +2171,10 @@ void launch_resid_restrict(const Geo &g, T *phi, T *rhs, T *old, const T *chat, 
     if (nb + nleaf_prev <= 0) return;
     dim3 grid((unsigned)(xcd_grid(nb) + nleaf_prev));
     if (partial)
-        hipLaunchKernelGGL((k_resid_restrict<T, true>), grid, dim3(256), 0, s, g, phi, rhs, old, chat, b0, nb,
+        hipLaunchKernelGGL((k_resid_restrict<T, true>), grid, dim3(128), 0, s, g, phi, rhs, old, chat, b0, nb,
                            leaf_prev, nleaf_prev, inv_h2, leafpos, partial, vol);
     else
-        hipLaunchKernelGGL((k_resid_restrict<T, false>), grid, dim3(256), 0, s, g, phi, rhs, old, chat, b0, nb,
+        hipLaunchKernelGGL((k_resid_restrict<T, false>), grid, dim3(128), 0, s, g, phi, rhs, old, chat, b0, nb,
                            leaf_prev, nleaf_prev, inv_h2, leafpos, partial, vol);
 }
 template <typename T>
