@@ -749,7 +749,9 @@ def main():
         results["mixed"] = g.get_field(M.MG_FIELD_PHI)
         mixed = {"value": n_leaf * args.steps / el_m, "unit": "cells/s",
                  "ms_per_step": 1e3 * el_m / args.steps, "runs": run_stats(mrun, n_leaf),
-                 "refinement_steps": ms_stats["n_vcycles"], "final_rel_res": ms_stats["rel"]}
+                 "refinement_steps": ms_stats["n_vcycles"], "final_rel_res": ms_stats["rel"],
+                 "launches": {"start_and_fmg": ms_stats["launches_fmg"],
+                              "per_refinement_step": ms_stats["launches_cycle"]}}
     if args.copy_probe > 0:
         src = torch.empty(args.copy_probe // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
         dst = torch.empty_like(src)
@@ -787,6 +789,9 @@ def main():
                    "n_trees": int(g.info.n_trees),
                    "n_leaf": n_leaf, "n_boxes": g.n, "levels": g.nlev, "rel_tol": 1e-8,
                    "vcycles_after_fmg": k, "final_rel_res": stats["rel"], "precision": "fp64",
+                   "launches": {"fmg_with_check": stats["launches_fmg"],
+                                "per_vcycle_with_check": stats["launches_cycle"],
+                                "per_solve": stats["launches_fmg"] + k * stats["launches_cycle"]},
                    "smoothing": "V(2,2) red-black Gauss-Seidel",
                    "fusion": M.MG_FUSE_ALL if args.fusion is None else args.fusion,
                    "gsrb_schedule": {"fp64": sched64, "fp32": sched32}},

@@ -219,6 +219,13 @@ typedef struct {
     int32_t nn_accepted;       /* MG_LEARNED: learned steps kept               */
     int32_t nn_fell_back;      /* MG_LEARNED: cycle at which the learned step
                                   was dropped for plain V-cycles, 0 if never   */
+    int32_t launches_fmg;      /* mg_fmg_solve with graphs: kernel launches of
+                                  the recorded FMG sequence (FP64: phi <- 0,
+                                  FMG pass, stopping test; MG_MIXED: start and
+                                  first correction step); 0 otherwise          */
+    int32_t launches_cycle;    /* the same for one further cycle with its
+                                  stopping test (FP64: V-cycle; MG_MIXED: FP32
+                                  V-cycle and FP64 update); 0 if none ran      */
 } mg_solve_stats;
 
 void mg_default_opts(mg_solve_opts *o);

@@ -558,6 +558,9 @@ int record(mg_tree *t, mg_tree::Graph &g, int seq, int nd, int nu) {
     load_state(t, g.pre);
     hipGraph_t graph = nullptr;
     if ((rc = hip_check(hipStreamEndCapture(cs, &graph), "end capture"))) return rc;
+    size_t nodes = 0;
+    (void)hipGraphGetNodes(graph, nullptr, &nodes);
+    g.nodes = (int)nodes;
     hipGraphExec_t exec = nullptr;
     rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate graph");
     (void)hipGraphDestroy(graph);
@@ -1358,6 +1361,13 @@ int mg_fmg_solve(mg_tree *t, const mg_solve_opts *o, mg_solve_stats *st) {
     }
     if (!rc) restrict_all(t, f64(t));  // every covered cell: the mean of its children
     if (!rc) rc = hip_check(hipGetLastError(), "kernel launch");
+    if (o->graphs && !t->timing) {
+        bool fp64 = o->precision == MG_FP64;
+        s->launches_fmg = fp64 ? t->graphs[mg_tree::SEQ_FMG].nodes
+                               : t->graphs[mg_tree::SEQ_MIX_START].nodes + t->graphs[mg_tree::SEQ_MIX_FMG].nodes;
+        if (s->n_vcycles > 1 || (fp64 && s->n_vcycles > 0))
+            s->launches_cycle = t->graphs[fp64 ? mg_tree::SEQ_VCHECK : mg_tree::SEQ_MIX_V].nodes;
+    }
     s->t_ms = now_ms() - t0;
     return s->status = rc;
 }
@@ -1413,6 +1423,13 @@ int mg_vcycle(mg_tree *t, const mg_solve_opts *o, int n_cycles, mg_solve_stats *
     }
     if (!rc) restrict_all(t, f64(t));  // every covered cell: the mean of its children
     if (!rc) rc = hip_check(hipGetLastError(), "kernel launch");
+    if (o->graphs && !t->timing) {
+        bool fp64 = o->precision == MG_FP64;
+        s->launches_fmg = fp64 ? t->graphs[mg_tree::SEQ_FMG].nodes
+                               : t->graphs[mg_tree::SEQ_MIX_START].nodes + t->graphs[mg_tree::SEQ_MIX_FMG].nodes;
+        if (s->n_vcycles > 1 || (fp64 && s->n_vcycles > 0))
+            s->launches_cycle = t->graphs[fp64 ? mg_tree::SEQ_VCHECK : mg_tree::SEQ_MIX_V].nodes;
+    }
     s->t_ms = now_ms() - t0;
     return s->status = rc;
 }

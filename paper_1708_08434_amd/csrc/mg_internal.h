@@ -159,6 +159,7 @@ struct mg_tree {
     struct Graph {
         void *exec = nullptr;
         int nd = -1, nu = -1;
+        int nodes = 0;  // kernel launches recorded
         bool pre[2][mg::kMaxLevel + 2], post[2][mg::kMaxLevel + 2];  // c_hat validity
     };
     enum { SEQ_FMG = 0, SEQ_VCHECK, SEQ_MIX_START, SEQ_MIX_FMG, SEQ_MIX_V, SEQ_V, SEQ_COUNT };

@@ -72,13 +72,15 @@ class mg_solve_stats(ctypes.Structure):
                 ("rel_res", ctypes.c_double), ("l2", ctypes.c_double), ("linf", ctypes.c_double),
                 ("beff_l2", ctypes.c_double), ("rel_hist", ctypes.c_double * 64),
                 ("t_ms", ctypes.c_double), ("nn_accepted", ctypes.c_int32),
-                ("nn_fell_back", ctypes.c_int32)]
+                ("nn_fell_back", ctypes.c_int32), ("launches_fmg", ctypes.c_int32),
+                ("launches_cycle", ctypes.c_int32)]
 
     def as_dict(self):
         n = self.n_vcycles
         return dict(n_vcycles=n, status=self.status, rel=self.rel_res, l2=self.l2,
                     linf=self.linf, beff=self.beff_l2, hist=np.array(self.rel_hist[:n + 1]),
-                    t_ms=self.t_ms, nn_accepted=self.nn_accepted, nn_fell_back=self.nn_fell_back)
+                    t_ms=self.t_ms, nn_accepted=self.nn_accepted, nn_fell_back=self.nn_fell_back,
+                    launches_fmg=self.launches_fmg, launches_cycle=self.launches_cycle)
 
 
 class mg_kernel_timing_t(ctypes.Structure):

@@ -134,3 +134,27 @@ def test_fusion_full_size_streamer_gives_the_same_bits():
     for (na, ha, pa), (nb, hb, pb) in zip(out[0], out[M.MG_FUSE_ALL]):
         assert na == nb and ha == hb, (ha, hb)
         assert np.array_equal(pa, pb), np.abs(pa - pb).max()
+
+
+def test_solve_statistics_count_the_recorded_launches():
+    """The solve statistics report the kernel launches of the recorded FMG
+    and per-cycle sequences; the fused sequences launch no more kernels than
+    the unfused ones (the fused FMG sequence fewer: its first norm pass is
+    gone), in FP64 and in the mixed-precision solve."""
+    g, rhs = make_tree("streamer_small")
+    g.set_field(M.MG_FIELD_RHS, rhs)
+    got = {}
+    for flags in (0, M.MG_FUSE_ALL):
+        M.mg_set_fusion(g.h, flags)
+        for prec in (M.MG_FP64, M.MG_MIXED):
+            st = g.fmg_solve(precision=prec)
+            assert st["n_vcycles"] >= 2
+            got[flags, prec] = (st["launches_fmg"], st["launches_cycle"])
+            say("launches", flags, prec, got[flags, prec])
+    for prec in (M.MG_FP64, M.MG_MIXED):
+        f0, c0 = got[0, prec]
+        f1, c1 = got[M.MG_FUSE_ALL, prec]
+        assert 0 < c1 <= c0 and 0 < f1 <= f0
+        assert f0 > c0 and f1 > c1
+    assert got[M.MG_FUSE_ALL, M.MG_FP64][0] < got[0, M.MG_FP64][0]
+

@@ -347,11 +347,15 @@ def test_learned_step_on_a_root_only_tree():
 
 # ------------------------------------------------------------ A/B
 
-def test_trained_network_against_plain_solve():
-    """What the trained network gains: train on held-out seeded streamer
+def test_trained_network_solve_stays_within_one_cycle_of_plain():
+    """A trained network in a solve: train on held-out seeded streamer
     trees, then solve an unseen streamer problem with and without the
     learned step.  Both must reach the tolerance and the same discrete
-    solution; the cycle counts and times are reported, whatever they are."""
+    solution, and the learned solve's acceptance test and fallback must keep
+    it within one V-cycle of the plain solve (a step that does not lower the
+    residual enough is rejected and the solve continues with plain cycles).
+    This bounds the cost of a useless network; it does not claim a gain (the
+    A/B on the benchmark trees shows none, and the design notes record it)."""
     from workloads import forest, streamer_small
     tw = forest(n_trees=4, refinements=3, base=3, lo_cells=5e4, hi_cells=3e5)
     tt = M.Tree.from_workload(tw)
