@@ -139,8 +139,7 @@ def test_fusion_full_size_streamer_gives_the_same_bits():
 def test_solve_statistics_count_the_recorded_launches():
     """The solve statistics report the kernel launches of the recorded FMG
     and per-cycle sequences; the fused sequences launch no more kernels than
-    the unfused ones (the fused FMG sequence fewer: its first norm pass is
-    gone), in FP64 and in the mixed-precision solve."""
+    the unfused ones, in FP64 and in the mixed-precision solve."""
     g, rhs = make_tree("streamer_small")
     g.set_field(M.MG_FIELD_RHS, rhs)
     got = {}
@@ -156,5 +155,4 @@ def test_solve_statistics_count_the_recorded_launches():
         f1, c1 = got[M.MG_FUSE_ALL, prec]
         assert 0 < c1 <= c0 and 0 < f1 <= f0
         assert f0 > c0 and f1 > c1
-    assert got[M.MG_FUSE_ALL, M.MG_FP64][0] < got[0, M.MG_FP64][0]
 
