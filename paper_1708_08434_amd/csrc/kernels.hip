@@ -917,25 +917,46 @@ __global__ __launch_bounds__(128) void k_resid_restrict(Geo g, T *__restrict__ p
 // rhs <- L phi + rhs on the listed (refined) boxes: completes the coarse
 // right-hand side L_c(R phi) + R r of the full approximation scheme.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fas_rhs(Geo g, const T *__restrict__ phi, T *__restrict__ rhs,
+__global__ __launch_bounds__(128) void k_fas_rhs(Geo g, const T *__restrict__ phi, T *__restrict__ rhs,
                                                  const T *__restrict__ chat,
                                                  const int32_t *__restrict__ list, int64_t nlist,
                                                  T inv_h2) {
+    // 128 threads per box: thread u holds cell positions 2u and 2u+1 of both
+    // colours (paired loads and stores)
+    using V = typename VecN<T, 2>::type;
     __shared__ T P[512], H[384];
     int64_t q = xcd_map(blockIdx.x, nlist);
     if (q >= nlist) return;
     int64_t b = list[q];
-    int t = threadIdx.x;
-    T r0 = rhs[b * 512 + t], r1 = rhs[b * 512 + 256 + t];
-    stage_full<T>(g, phi, chat, b, P, H);
+    const int u = threadIdx.x;
+    const V r0 = ld_stream(reinterpret_cast<const V *>(rhs + b * 512) + u);
+    const V r1 = ld_stream(reinterpret_cast<const V *>(rhs + b * 512 + 256) + u);
+    const V p0 = reinterpret_cast<const V *>(phi + b * 512)[u];
+    const V p1 = reinterpret_cast<const V *>(phi + b * 512 + 256)[u];
+    const FaceTab ft = face_tab(g, b);
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        int e = u + 128 * r, d = e >> 6, w = e & 63;
+        H[e] = ghost_at<T>(g, phi, chat, b, d, pick6(ft.nb, d), pick6(ft.slot, d), w & 7, w >> 3);
+    }
+    reinterpret_cast<V *>(P)[u] = p0;
+    reinterpret_cast<V *>(P)[128 + u] = p1;
     __syncthreads();
-    int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
+    const T *rr0 = reinterpret_cast<const T *>(&r0), *rr1 = reinterpret_cast<const T *>(&r1);
 #pragma unroll
     for (int c = 0; c < 2; c++) {
-        int i = 2 * m + ((j + k + c) & 1);
-        T own = P[c * 256 + t];
-        T s = sum_full<T>(P, H, i, j, k);
-        rhs[b * 512 + c * 256 + t] = (s - (T)6 * own) * inv_h2 + (c ? r1 : r0);
+        V out;
+        T *o = reinterpret_cast<T *>(&out);
+#pragma unroll
+        for (int sl = 0; sl < 2; sl++) {
+            const int t = 2 * u + sl;
+            const int m = t & 3, j = (t >> 2) & 7, k = t >> 5;
+            int i = 2 * m + ((j + k + c) & 1);
+            T own = P[c * 256 + t];
+            T s = sum_full<T>(P, H, i, j, k);
+            o[sl] = (s - (T)6 * own) * inv_h2 + (c ? rr1[sl] : rr0[sl]);
+        }
+        reinterpret_cast<V *>(rhs + b * 512 + c * 256)[u] = out;
     }
 }
 
@@ -2181,7 +2202,7 @@ template <typename T>
 void launch_fas_rhs(const Geo &g, const T *phi, T *rhs, const T *chat, const int32_t *list,
                     int64_t nlist, T inv_h2, hipStream_t s) {
     if (nlist <= 0) return;
-    hipLaunchKernelGGL(k_fas_rhs<T>, dim3((unsigned)xcd_grid(nlist)), dim3(256), 0, s, g, phi, rhs,
+    hipLaunchKernelGGL(k_fas_rhs<T>, dim3((unsigned)xcd_grid(nlist)), dim3(128), 0, s, g, phi, rhs,
                        chat, list, nlist, inv_h2);
 }
 template <typename T>
