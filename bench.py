@@ -128,6 +128,42 @@ def traffic_probe(w, reps=8):
           flush=True)
 
 
+def solve_traffic_probe(w, schedule=None, fusion=None):
+    """Launches to count the HBM traffic of one FP64 FMG solve under
+    rocprofv3 --pmc: a warm-up solve (graphs recorded), then a 1 KiB
+    copy-kernel launch of 1 block, one FP64 solve, a 1 KiB copy of 2 blocks
+    (the markers that bracket the solve's dispatches), then the 2 GiB copy
+    kernel whose counters calibrate FETCH_SIZE and WRITE_SIZE."""
+    import torch
+    from paper_1708_08434_amd import mg as M
+    g = M.Tree.from_workload(w, device="cuda:0")
+    if fusion is not None:
+        M.mg_set_fusion(g.h, fusion)
+    if schedule:
+        parts = parse_schedule(schedule, g.nlev, M.MG_GSRB_VARIANTS)
+        M.mg_set_schedule(g.h, M.MG_FP64, parts[0])
+    g.set_rhs_from(w)
+    st = g.fmg_solve()
+    mark = torch.zeros(2, 1024 // 8, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    M.mg_stream_copy(mark[1].data_ptr(), mark[0].data_ptr(), 1024, 1, g.stream.cuda_stream)
+    st = g.fmg_solve()
+    M.mg_stream_copy(mark[1].data_ptr(), mark[0].data_ptr(), 1024, 2, g.stream.cuda_stream)
+    torch.cuda.synchronize()
+    nbytes = 2 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    M.mg_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, 0, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    ls = list(g.info.level_start[:g.nlev + 1])
+    counts = [ls[i + 1] - ls[i] for i in range(g.nlev)]
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read() + open(DRIVER_SRC, "rb").read()).hexdigest()
+    print(json.dumps({"solve_traffic_probe": {
+        "workload": w.name, "vcycles_after_fmg": st["n_vcycles"], "copy_bytes": nbytes,
+        "model_bytes": model_bytes(counts, int(g.info.n_leaf_cells), st["n_vcycles"]),
+        "source_sha256": sha}}), flush=True)
+
+
 def cpu_model():
     """The host CPU's model name from /proc/cpuinfo (None if unreadable)."""
     try:
@@ -651,6 +687,8 @@ def main():
                     help="time steps of the fluid leg (paper setup, SI units); 0 skips it")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only the launches that rocprofv3 --pmc counts for the traffic summary")
+    ap.add_argument("--solve-traffic-probe", action="store_true",
+                    help="only the launches that rocprofv3 --pmc counts for the traffic of one FP64 solve")
     ap.add_argument("--schedule", default=None,
                     help="fixed Gauss-Seidel launch variant per level instead of the autotuner: "
                          "FP64 list, optionally '/' and the FP32 list, e.g. 3,7,7,1,7,7,1,11/3,1,7,1,7,7,1,9 "
@@ -681,6 +719,9 @@ def main():
     w = gen[args.workload]()
     if args.traffic_probe:
         traffic_probe(w)
+        return
+    if args.solve_traffic_probe:
+        solve_traffic_probe(w, args.schedule, args.fusion)
         return
     g = M.Tree.from_workload(w, device="cuda:0")
     if args.fusion is not None:
