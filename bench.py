@@ -659,6 +659,7 @@ def solve_traffic(workload):
 
 
 WORKLOAD_TEXT = {
+    "uniform": " uniform 64^3 grid (levels 1-4 of 8^3 boxes, no refinement)",
     "streamer": " static streamer octree (base 64^3 + 4 refinement levels)",
     "forest": " forest of 128 uneven streamer trees (base 32^3 + <=5 levels)",
     "branched": " branched streamer octree (base 64^3 + 6 refinement levels)",
@@ -696,8 +697,9 @@ def main():
     ap.add_argument("--fusion", type=int, default=None,
                     help="mg_set_fusion flags for the solves (default: all fused sequences)")
     ap.add_argument("--workload", default="two_streamers",
-                    choices=["streamer", "forest", "branched", "two_streamers", "paper_setup"],
-                    help="two_streamers: base 64^3 + 7 levels, 1.2e8 cells (default); streamer: "
+                    choices=["uniform", "streamer", "forest", "branched", "two_streamers", "paper_setup"],
+                    help="two_streamers: base 64^3 + 7 levels, 1.2e8 cells (default); uniform: 64^3 "
+                         "cells, no refinement; streamer: "
                          "base 64^3 + 4 levels, 4.8e6 cells; forest: 128 uneven trees, 7.1e7 "
                          "cells; branched: base 64^3 + 6 levels, 2.9e7 cells; paper_setup: the "
                          "streamer tree in the paper's SI setup (40 mm, 80 kV, Neumann sides)")
@@ -710,11 +712,11 @@ def main():
     import numpy as np
     import torch
     from paper_1708_08434_amd import mg as M
-    from workloads import c2, c3, c5, forest, paper_setup
+    from workloads import c1, c2, c3, c5, forest, paper_setup
 
     from paper_1708_08434_amd import autotune
 
-    gen = {"streamer": c2, "forest": forest, "branched": c3, "two_streamers": c5,
+    gen = {"uniform": c1, "streamer": c2, "forest": forest, "branched": c3, "two_streamers": c5,
            "paper_setup": paper_setup}
     w = gen[args.workload]()
     if args.traffic_probe:
