@@ -469,7 +469,7 @@ def regrid_leg(w, args, sched64):
     level).  Then the head
     moves down 2.5e-4 (10 um of the paper's 40 mm domain, a quarter of a
     finest cell) per field solve, each field solve runs two warm-started
-    V-cycles, and every 4th solve is preceded by a timed regrid step: GPU
+    V-cycles, and every 2nd solve is preceded by a timed regrid step: GPU
     refinement scores, the host plan, the new tree (create + bind, with the
     benchmark tree's autotuned schedule) and the transfer of phi
     (mg_transfer).  The charge of each mesh is generated on the host and is
@@ -477,7 +477,7 @@ def regrid_leg(w, args, sched64):
     import torch
     from paper_1708_08434_amd import mg as M
     from workloads import c2_head_sequence
-    dz, every, z0, deref = 2.5e-4, 4, 0.62, 0.125
+    dz, every, z0, deref = 2.5e-4, 2, 0.62, 0.125
 
     def tree(lv, ij, tr):
         t = M.Tree(lv, ij, tr, w.lo, w.length, w.bc_type, w.bc_val, device="cuda:0")
@@ -678,8 +678,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction leg")
     ap.add_argument("--train-steps", type=int, default=300, help="Adam steps of the learned leg")
-    ap.add_argument("--regrid-steps", type=int, default=8,
-                    help="field solves of the regrid leg (a regrid every 4th); 0 skips it")
+    ap.add_argument("--regrid-steps", type=int, default=16,
+                    help="field solves of the regrid leg (a regrid every 2nd); 0 skips it")
     ap.add_argument("--ts-steps", type=int, default=8,
                     help="time steps (2 warm-started field solves each) of the time-stepping leg; "
                          "0 skips it")

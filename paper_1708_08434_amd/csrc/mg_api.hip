@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <unordered_map>
 #include <new>
 #include <string>
@@ -1076,6 +1077,45 @@ int mg_tree_create(mg_tree **out, const mg_domain *dom, int64_t n, const int32_t
     return MG_OK;
 }
 
+// Capture streams and pinned result buffers outlive the trees that used
+// them: a mesh adaptation creates and destroys a tree per step, and creating
+// a stream or a pinned buffer costs more than the new tree's table upload.
+// A destroyed tree hands them back (its bound stream has been synchronised,
+// and a capture stream never executes work); the next bind takes them.
+std::mutex g_spare_mu;
+std::vector<std::pair<int, void *>> g_spare_streams;    // (device, stream)
+std::vector<std::pair<size_t, double *>> g_spare_pinned;  // (capacity, buffer)
+
+int take_capture_stream(int device, void **out) {
+    {
+        std::lock_guard<std::mutex> lk(g_spare_mu);
+        for (size_t i = 0; i < g_spare_streams.size(); i++)
+            if (g_spare_streams[i].first == device) {
+                *out = g_spare_streams[i].second;
+                g_spare_streams.erase(g_spare_streams.begin() + i);
+                return MG_OK;
+            }
+    }
+    hipStream_t cs = nullptr;
+    int rc = hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+    *out = (void *)cs;
+    return rc;
+}
+int take_pinned(size_t bytes, double **out, size_t *cap) {
+    {
+        std::lock_guard<std::mutex> lk(g_spare_mu);
+        for (size_t i = 0; i < g_spare_pinned.size(); i++)
+            if (g_spare_pinned[i].first >= bytes) {
+                *cap = g_spare_pinned[i].first;
+                *out = g_spare_pinned[i].second;
+                g_spare_pinned.erase(g_spare_pinned.begin() + i);
+                return MG_OK;
+            }
+    }
+    *cap = std::max<size_t>(bytes, 4096);
+    return hip_check(hipHostMalloc((void **)out, *cap), "pinned host buffer");
+}
+
 int mg_tree_destroy(mg_tree *t) {
     if (!t) return MG_OK;
     // work enqueued without a host wait (mg_vcycle without statistics,
@@ -1083,13 +1123,16 @@ int mg_tree_destroy(mg_tree *t) {
     // the graphs and the pinned buffer released below
     if (t->stream) (void)hipStreamSynchronize((hipStream_t)t->stream);
     for (auto &g : t->graphs) drop_graph(g);
-    if (t->host_result) (void)hipHostFree(t->host_result);
+    {
+        std::lock_guard<std::mutex> lk(g_spare_mu);
+        if (t->host_result) g_spare_pinned.push_back({t->host_result_bytes, t->host_result});
+        if (t->cap_stream) g_spare_streams.push_back({t->cap_device, t->cap_stream});
+    }
     for (auto &p : t->probes) {
         t->ev_pool.push_back(p.e0);
         t->ev_pool.push_back(p.e1);
     }
     for (void *e : t->ev_pool) (void)hipEventDestroy((hipEvent_t)e);
-    if (t->cap_stream) (void)hipStreamDestroy((hipStream_t)t->cap_stream);
     delete t;
     return MG_OK;
 }
@@ -1145,11 +1188,17 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     t->ws = ws;
     t->stream = stream;
     t->cur_stream = stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (t->cap_stream && t->cap_device != dev) {  // rebound on another device
+        std::lock_guard<std::mutex> lk(g_spare_mu);
+        g_spare_streams.push_back({t->cap_device, t->cap_stream});
+        t->cap_stream = nullptr;
+    }
     if (!t->cap_stream) {
-        hipStream_t cs = nullptr;
-        int rc = hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+        int rc = take_capture_stream(dev, &t->cap_stream);
         if (rc) return rc;
-        t->cap_stream = (void *)cs;
+        t->cap_device = dev;
     }
     char *base = (char *)ws;
     DevTables &d = t->d;
@@ -1193,8 +1242,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.fas = (void *)(base + t->off.fas);
     d.dpad = (void *)(base + t->off.dpad);
     if (!t->host_result) {
-        int rc = hip_check(hipHostMalloc((void **)&t->host_result, 4 * t->ntree * sizeof(double)),
-                           "pinned host buffer");
+        int rc = take_pinned(4 * t->ntree * sizeof(double), &t->host_result, &t->host_result_bytes);
         if (rc) return rc;
     }
     std::vector<int32_t> ijk4((size_t)4 * t->n), isleaf((size_t)t->n);
@@ -1703,21 +1751,26 @@ int mg_transfer(mg_tree *from, mg_tree *to) {
         set_error("mg_transfer: the trees cover different domains");
         return MG_EINVAL;
     }
+    // the canonical order of both trees: (level, tree, Morton index), so one
+    // merge pass over the two box arrays pairs the boxes
     auto key = [](const mg_tree *t, int64_t b) {
-        return ((uint64_t)t->tid[b] << 48) | ((uint64_t)t->lev[b] << 42) | ((uint64_t)t->ijk[3 * b] << 28) |
-               ((uint64_t)t->ijk[3 * b + 1] << 14) | (uint64_t)t->ijk[3 * b + 2];
+        return ((uint64_t)t->lev[b] << 58) | ((uint64_t)t->tid[b] << 42) |
+               morton(t->ijk[3 * b], t->ijk[3 * b + 1], t->ijk[3 * b + 2]);
     };
     // new box -> old box with the same level and position (or -1); the boxes
     // without one, grouped by level, are interpolated from their parents
     std::vector<int32_t> src((size_t)to->n), list;
     std::vector<int64_t> lstart(to->nlev + 2, 0);
     try {
-        std::unordered_map<uint64_t, int32_t> old;
-        old.reserve((size_t)from->n * 2);
-        for (int64_t b = 0; b < from->n; b++) old.emplace(key(from, b), (int32_t)b);
+        int64_t a = 0;
+        uint64_t ka = from->n ? key(from, 0) : ~0ull;
         for (int64_t b = 0; b < to->n; b++) {
-            auto it = old.find(key(to, b));
-            src[b] = it == old.end() ? -1 : it->second;
+            uint64_t kb = key(to, b);
+            while (a < from->n && ka < kb) {
+                a++;
+                ka = a < from->n ? key(from, a) : ~0ull;
+            }
+            src[b] = a < from->n && ka == kb ? (int32_t)a : -1;
             if (src[b] < 0 && to->lev[b] == 1) {
                 set_error("mg_transfer: a tree of the new forest has no counterpart in the old one");
                 return MG_EINVAL;

@@ -143,10 +143,12 @@ struct mg_tree {
     void *stream = nullptr;      // caller's stream: every replay and direct launch goes here
     void *cur_stream = nullptr;  // stream the launchers use (the capture stream while capturing)
     void *cap_stream = nullptr;  // private stream used only to record graphs
+    int cap_device = -1;         // device of cap_stream
     mg::DevTables d;
     bool cf_valid[mg::kMaxLevel + 2] = {false};    // c_hat of the FP64 field current per level
     bool cf_valid32[mg::kMaxLevel + 2] = {false};  // same for the FP32 correction field
     double *host_result = nullptr;  // pinned host buffer for norms, [4*ntree]
+    size_t host_result_bytes = 0;    // its capacity
     std::vector<double> beff_tree, rel_tree;  // per tree: norm of the residual of phi = 0, last rel
     // ---- optional event timing of the half-sweep kernel ----
     // A probe is a pair of events around the consecutive half-sweeps of one
