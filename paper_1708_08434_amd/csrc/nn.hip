@@ -43,6 +43,9 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
+// The same rounding (nearest even) by the hardware conversion; a NaN stays a
+// NaN (its payload may differ from f2bf's).  Two values per instruction.
+__device__ __forceinline__ uint16_t f2bf_hw(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ float round_bf(float f) { return bf2f(f2bf(f)); }
 // max(z, 0) that propagates NaN (a non-finite weight must reach the output)
@@ -105,25 +108,17 @@ __global__ __launch_bounds__(256) void k_nn_pack(const float *__restrict__ prm, 
 // each thread prefetches its part of the next box's input during the current
 // box.  Tiles are 16 consecutive cells (two x-rows of 8), one MFMA row each.
 //
-// Layer 2 reads one 16-byte LDS fragment per lane for a pair of (dj, dk)
-// kernel rows (lanes of K groups 0-1 the first row, 2-3 the second) at the
-// centre column di = 1; the di = 0 and di = 2 operands are the same
-// fragment moved one lane down or up inside each 16-lane DPP row, zero
-// across the ends of the 8-cell x-rows (where the zero padding of the "same"
-// convolution lies).  The zeroing is applied to the moving values before
-// the move, and the moved values feed the MFMA directly: a select placed
-// after the move gave wrong values on gfx950.  5 loads and 15 MFMAs per
-// tile cover the 27 taps.
-// DPP row shifts inside rows of 16 lanes (0 where the source lane is outside
-// the row): control 0x111 (row_shr:1) hands lane l the value of lane l-1,
-// 0x101 (row_shl:1) the value of lane l+1 (checked on gfx950).
-__device__ __forceinline__ uint32_t dpp_from_prev(uint32_t v) {  // lane l gets lane l-1
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);
-}
-__device__ __forceinline__ uint32_t dpp_from_next(uint32_t v) {  // lane l gets lane l+1
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x101, 0xf, 0xf, true);
-}
-
+// Layer 2 reads, per lane and pair of (dj, dk) kernel rows (lanes of K
+// groups 0-1 the first row, 2-3 the second), three 16-byte LDS fragments:
+// the centre column di = 1 and the cells one to either side (di = 0, 2);
+// A1's zero padding supplies the "same" convolution's zeros at the ends of
+// the x-rows.  15 loads and 15 MFMAs per tile cover the 27 taps.  (Moving
+// the centre fragment across lanes with DPP row shifts instead saves LDS
+// loads but costs 16 vector instructions per pair for the shifts and the
+// row-end masks, and the kernel was bound by those.)  A1's rows and the
+// layer-3 partial sums are padded so that the 16 lanes of an MFMA column
+// group address different LDS banks.  Activations are rounded to BF16
+// (nearest even) by the hardware conversion.
 constexpr int kFwdThreads = 256;  // 4 waves; 3 workgroups per CU
 
 template <bool SAVE>
@@ -134,8 +129,17 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3, 
                                                         uint16_t *__restrict__ a1o,
                                                         uint16_t *__restrict__ a2o) {
     __shared__ __attribute__((aligned(16))) uint16_t xs[1008];
-    // A1 [1000][16] BF16 (32000 bytes), later one half of Q, [16][512] FP32 (32768 bytes)
-    __shared__ __attribute__((aligned(16))) uint4 R[2048];
+    // A1 [1000][16] BF16 (32000 bytes), later one half of Q, [16][kQs] FP32
+    // (rows padded from 512 to kQs floats: the 16 lanes that store one MFMA
+    // result column each write a different row, which then start in
+    // different LDS banks)
+    constexpr int kQs = 516;
+    // A1 layout (u16 units): padded cell (x, y, z) at z*kA1z + y*kA1y + x*16,
+    // each y-row 10 cells + 16 bytes, so that the two x-rows of a 16-cell
+    // tile start in different LDS banks
+    constexpr int kA1y = 168, kA1z = 10 * kA1y, kA1 = 10 * kA1z;
+    constexpr int kR = (16 * kQs > kA1 / 2 ? 16 * kQs : kA1 / 2) / 4;
+    __shared__ __attribute__((aligned(16))) uint4 R[kR];
     __shared__ __attribute__((aligned(16))) uint16_t A2[512 * 16];
     uint16_t *A1 = reinterpret_cast<uint16_t *>(R);
     float *Q = reinterpret_cast<float *>(R);
@@ -159,6 +163,19 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3, 
         int tp = 8 * g + qq;
         off1[qq] = tp < 27 ? tap_off(tp) : -1;
     }
+    // layer 3: which of the 27 taps of this thread's two output cells lie
+    // inside the box (the same for every box)
+    uint32_t inside[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int c = t + 256 * h, ci = c & 7, cj = (c >> 3) & 7, ck = c >> 6;
+        uint32_t msk = 0;
+        for (int tp = 0; tp < 27; tp++) {
+            int ii = ci + tp % 3 - 1, jj = cj + (tp / 3) % 3 - 1, kk = ck + tp / 9 - 1;
+            if ((unsigned)ii < 8u && (unsigned)jj < 8u && (unsigned)kk < 8u) msk |= 1u << tp;
+        }
+        inside[h] = msk;
+    }
     int64_t q = blockIdx.x;
     float xn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (q < nbox) {
@@ -170,10 +187,10 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3, 
     for (; q < nbox; q += gridDim.x) {
         __syncthreads();  // the previous box is done with every LDS buffer
         // zero A1 (its padding must be 0; Q of the previous box overwrote it)
-        for (int e = t; e < 2000; e += kFwdThreads) R[e] = make_uint4(0, 0, 0, 0);
+        for (int e = t; e < kA1 / 8; e += kFwdThreads) R[e] = make_uint4(0, 0, 0, 0);
 #pragma unroll
         for (int h = 0; h < 4; h++)
-            if (t + 256 * h < 1000) xs[t + 256 * h] = f2bf(xn[h]);
+            if (t + 256 * h < 1000) xs[t + 256 * h] = f2bf_hw(xn[h]);
         const int64_t qn = q + gridDim.x;
         if (qn < nbox) {
             const float *xb = x + (idx ? (int64_t)idx[qn] : qn) * 1000;
@@ -200,43 +217,34 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3, 
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 int c = 16 * m + 4 * g + r, pi = c & 7, pj = (c >> 3) & 7, pk3 = c >> 6;
-                uint16_t v = f2bf(relu(D[r] + bias1));
-                A1[(((pk3 + 1) * 10 + pj + 1) * 10 + pi + 1) * 16 + o] = v;
+                uint16_t v = f2bf_hw(relu(D[r] + bias1));
+                A1[(pk3 + 1) * kA1z + (pj + 1) * kA1y + (pi + 1) * 16 + o] = v;
                 if (SAVE) a1o[(q * 16 + o) * 512 + c] = v;
             }
         }
         __syncthreads();
-        // ---- layer 2: 9 kernel rows in 5 pairs, 3 x-shifts each
+        // ---- layer 2: 9 kernel rows in 5 pairs, 3 x-shifts each; the
+        // x-shifted operands are loaded from the zero-padded A1 one cell to
+        // either side (the padding supplies the "same" convolution's zeros)
         {
-            // zero the values that must not cross an x-row end before they
-            // move: di = 0 takes lane l-1 (its i = 7 lanes masked), di = 2
-            // takes lane l+1 (its i = 0 lanes masked); lanes 0 and 15 of a
-            // DPP row receive 0 from the move itself
-            const uint32_t keep_l = (row & 7) == 7 ? 0u : ~0u, keep_r = (row & 7) == 0 ? 0u : ~0u;
 #pragma unroll 1
             for (int mm = 0; mm < 8; mm++) {
                 const int m = w + 4 * mm;
                 int cell = 16 * m + row, i = cell & 7, j = (cell >> 3) & 7, k = cell >> 6;
-                const int base = (k * 10 + j) * 10 + i + 1;  // centre column di = 1
+                const int base = k * kA1z + j * kA1y + (i + 1) * 16;  // centre column di = 1
                 f32x4 acc = zero;
 #pragma unroll
                 for (int p = 0; p < 5; p++) {
                     const int ra = 2 * p, rb = 2 * p + 1;  // kernel row = dk*3 + dj
-                    const int offa = (ra / 3) * 100 + (ra % 3) * 10;
-                    const int offb = rb < 9 ? (rb / 3) * 100 + (rb % 3) * 10 : 0;
-                    uint4 F = make_uint4(0, 0, 0, 0);  // the tenth kernel row does not exist
-                    if (g < 2 || rb < 9)
-                        F = *reinterpret_cast<const uint4 *>(A1 + (base + (g < 2 ? offa : offb)) * 16 +
-                                                             8 * (g & 1));
-                    uint4 L, Rr;
-                    L.x = dpp_from_prev(F.x & keep_l);
-                    L.y = dpp_from_prev(F.y & keep_l);
-                    L.z = dpp_from_prev(F.z & keep_l);
-                    L.w = dpp_from_prev(F.w & keep_l);
-                    Rr.x = dpp_from_next(F.x & keep_r);
-                    Rr.y = dpp_from_next(F.y & keep_r);
-                    Rr.z = dpp_from_next(F.z & keep_r);
-                    Rr.w = dpp_from_next(F.w & keep_r);
+                    const int offa = (ra / 3) * kA1z + (ra % 3) * kA1y;
+                    const int offb = rb < 9 ? (rb / 3) * kA1z + (rb % 3) * kA1y : 0;
+                    uint4 F = make_uint4(0, 0, 0, 0), L = F, Rr = F;  // the tenth kernel row does not exist
+                    if (g < 2 || rb < 9) {
+                        const uint16_t *src = A1 + base + (g < 2 ? offa : offb) + 8 * (g & 1);
+                        L = *reinterpret_cast<const uint4 *>(src - 16);
+                        F = *reinterpret_cast<const uint4 *>(src);
+                        Rr = *reinterpret_cast<const uint4 *>(src + 16);
+                    }
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, L), B2[3 * p + 0],
                                                                   acc, 0, 0, 0);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, F), B2[3 * p + 1],
@@ -247,7 +255,7 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3, 
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     int c = 16 * m + 4 * g + r;
-                    uint16_t v = f2bf(relu(acc[r] + bias2));
+                    uint16_t v = f2bf_hw(relu(acc[r] + bias2));
                     A2[c * 16 + o] = v;
                     if (SAVE) a2o[(q * 16 + o) * 512 + c] = v;
                 }
@@ -262,20 +270,17 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3, 
             int cell = 16 * m + row;
             s16x4 A = *reinterpret_cast<const s16x4 *>(A2 + cell * 16 + 4 * g);
             f32x4 D = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B3[0], zero, 0, 0, 0);
-            *reinterpret_cast<f32x4 *>(Q + o * 512 + 16 * m + 4 * g) = D;
+            *reinterpret_cast<f32x4 *>(Q + o * kQs + 16 * m + 4 * g) = D;
         }
         __syncthreads();
         float s[2];
 #pragma unroll
         for (int h = 0; h < 2; h++) {
-            const int c = t + 256 * h, ci = c & 7, cj = (c >> 3) & 7, ck = c >> 6;
+            const int c = t + 256 * h;
             s[h] = b3;
 #pragma unroll
-            for (int tp = 0; tp < 16; tp++) {
-                int ii = ci + tp % 3 - 1, jj = cj + (tp / 3) % 3 - 1, kk = ck + tp / 9 - 1;
-                if ((unsigned)ii < 8u && (unsigned)jj < 8u && (unsigned)kk < 8u)
-                    s[h] += Q[tp * 512 + (kk * 8 + jj) * 8 + ii];
-            }
+            for (int tp = 0; tp < 16; tp++)
+                if ((inside[h] >> tp) & 1u) s[h] += Q[tp * kQs + c + (tp / 9 - 1) * 64 + ((tp / 3) % 3 - 1) * 8 + tp % 3 - 1];
         }
         __syncthreads();
 #pragma unroll 2
@@ -284,18 +289,16 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3, 
             int cell = 16 * m + row;
             s16x4 A = *reinterpret_cast<const s16x4 *>(A2 + cell * 16 + 4 * g);
             f32x4 D = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B3[1], zero, 0, 0, 0);
-            if (o < 11) *reinterpret_cast<f32x4 *>(Q + o * 512 + 16 * m + 4 * g) = D;
+            if (o < 11) *reinterpret_cast<f32x4 *>(Q + o * kQs + 16 * m + 4 * g) = D;
         }
         __syncthreads();
 #pragma unroll
         for (int h = 0; h < 2; h++) {
-            const int c = t + 256 * h, ci = c & 7, cj = (c >> 3) & 7, ck = c >> 6;
+            const int c = t + 256 * h;
 #pragma unroll
-            for (int tp = 16; tp < 27; tp++) {
-                int ii = ci + tp % 3 - 1, jj = cj + (tp / 3) % 3 - 1, kk = ck + tp / 9 - 1;
-                if ((unsigned)ii < 8u && (unsigned)jj < 8u && (unsigned)kk < 8u)
-                    s[h] += Q[(tp - 16) * 512 + (kk * 8 + jj) * 8 + ii];
-            }
+            for (int tp = 16; tp < 27; tp++)
+                if ((inside[h] >> tp) & 1u)
+                    s[h] += Q[(tp - 16) * kQs + c + (tp / 9 - 1) * 64 + ((tp / 3) % 3 - 1) * 8 + tp % 3 - 1];
             y[q * 512 + c] = s[h];
         }
     }
