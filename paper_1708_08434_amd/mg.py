@@ -67,6 +67,9 @@ class mg_solve_opts(ctypes.Structure):
                 ("final_check_only", ctypes.c_int32), ("learned_placement", ctypes.c_int32)]
 
 
+_WS_ROUND = 64 << 20  # workspace allocations are rounded up to this
+
+
 class mg_solve_stats(ctypes.Structure):
     _fields_ = [("n_vcycles", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("rel_res", ctypes.c_double), ("l2", ctypes.c_double), ("linf", ctypes.c_double),
@@ -379,7 +382,14 @@ class Tree:
             import torch
             self.device = torch.device(device)
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-            self.ws = torch.empty(int(self.info.workspace_bytes), dtype=torch.uint8, device=self.device)
+            # rounded up (64 MiB for large trees): trees of a mesh adaptation
+            # differ by a few boxes, and equal sizes let torch's caching
+            # allocator hand a freed workspace to the next tree instead of
+            # making a new allocation
+            need = int(self.info.workspace_bytes)
+            r = _WS_ROUND if need >= 4 * _WS_ROUND else 2 << 20
+            nbytes = -(-need // r) * r
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             mg_tree_bind(self.h, self.ws.data_ptr(), self.ws.numel(), self.stream.cuda_stream)
 
     @classmethod
