@@ -9,7 +9,7 @@
 namespace mg {
 
 constexpr int kNnParams = 7809;   // 16*27 + 16 + 16*16*27 + 16 + 16*27 + 1
-constexpr int kNnPacked = 8704;   // BF16 MFMA operand fragments of the weights
+constexpr int kNnPacked = 10240;  // BF16 MFMA operand fragments of the weights
 constexpr int kNnFwdBlocks = 768; // persistent forward workgroups (3 per CU)
 constexpr int kNnWgradBlocks = 512;
 

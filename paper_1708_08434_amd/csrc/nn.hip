@@ -35,7 +35,7 @@ typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kW1 = 0, kB1 = 432, kW2 = 448, kB2 = 7360, kW3 = 7376, kB3 = 7808;
-constexpr int kP1 = 0, kP2 = 512, kP3 = 8192;  // offsets in the packed fragments
+constexpr int kP1 = 0, kP2 = 512, kP3 = 512 + 18 * 512;  // offsets in the packed fragments
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -84,11 +84,13 @@ __global__ __launch_bounds__(256) void k_nn_pack(const float *__restrict__ prm, 
             int lane = e >> 3, q = e & 7, o = lane & 15, g = lane >> 4, t = 8 * g + q;
             if (t < 27) v = prm[kW1 + o * 27 + t];
         } else if (e < kP3) {
-            // fragment f = 3 p + di: K groups 0-1 kernel row 2p, groups 2-3 row 2p+1
+            // fragment f = (2 dk + type) 3 + di: type 0 has kernel rows dj = 0
+            // in K groups 0-1 and dj = 1 in groups 2-3, type 1 dj = 2 in
+            // groups 0-1 and zeros in 2-3
             int e2 = e - kP2, f = e2 >> 9, r = e2 & 511, lane = r >> 3, q = r & 7;
-            int p = f / 3, di = f % 3, o = lane & 15, g = lane >> 4, ch = 8 * (g & 1) + q;
-            int krow = g < 2 ? 2 * p : 2 * p + 1;
-            if (krow < 9) v = prm[kW2 + (o * 16 + ch) * 27 + krow * 3 + di];
+            int dk = f / 6, type = (f / 3) & 1, di = f % 3, o = lane & 15, g = lane >> 4, ch = 8 * (g & 1) + q;
+            int dj = type == 0 ? (g < 2 ? 0 : 1) : (g < 2 ? 2 : -1);
+            if (dj >= 0) v = prm[kW2 + (o * 16 + ch) * 27 + (dk * 3 + dj) * 3 + di];
         } else {
             int e3 = e - kP3, nt = e3 >> 8, r = e3 & 255, lane = r >> 2, q = r & 3;
             int n = lane & 15, g = lane >> 4, tap = 16 * nt + n, ch = 4 * g + q;
@@ -108,17 +110,19 @@ __global__ __launch_bounds__(256) void k_nn_pack(const float *__restrict__ prm, 
 // each thread prefetches its part of the next box's input during the current
 // box.  Tiles are 16 consecutive cells (two x-rows of 8), one MFMA row each.
 //
-// Layer 2 reads, per lane and pair of (dj, dk) kernel rows (lanes of K
-// groups 0-1 the first row, 2-3 the second), three 16-byte LDS fragments:
-// the centre column di = 1 and the cells one to either side (di = 0, 2);
-// A1's zero padding supplies the "same" convolution's zeros at the ends of
-// the x-rows.  15 loads and 15 MFMAs per tile cover the 27 taps.  (Moving
-// the centre fragment across lanes with DPP row shifts instead saves LDS
-// loads but costs 16 vector instructions per pair for the shifts and the
-// row-end masks, and the kernel was bound by those.)  A1's rows and the
-// layer-3 partial sums are padded so that the 16 lanes of an MFMA column
-// group address different LDS banks.  Activations are rounded to BF16
-// (nearest even) by the hardware conversion.
+// Layer 2 pairs the kernel rows within one z offset dk (dj = 0 with 1, and
+// dj = 2 alone: 18 MFMAs per 16-cell tile, 27 taps in 32-wide K groups) so
+// that a loaded input slice serves the three output slices it reaches: each
+// wave walks the z-slices of its y-rows and loads every input fragment once
+// (6 per slice), instead of once per output tile (15 per tile).  The
+// x-shifted operands are loaded from A1 one cell to either side; its zero
+// padding supplies the "same" convolution's zeros at the ends of the x-rows
+// (moving one fragment across lanes with DPP row shifts instead costs 16
+// vector instructions per pair for the shifts and row-end masks, which
+// bounded an earlier version).  A1's rows and the layer-3 partial sums are
+// padded so that the 16 lanes of an MFMA column group address different
+// LDS banks.  Activations are rounded to BF16 (nearest even) by the
+// hardware conversion.
 constexpr int kFwdThreads = 256;  // 4 waves; 3 workgroups per CU
 
 template <bool SAVE>
@@ -149,9 +153,9 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3, 
 
     // ---- weights, once per workgroup
     const bf16x8 B1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(pk + kP1 + lane * 8));
-    bf16x8 B2[15];
+    bf16x8 B2[18];
 #pragma unroll
-    for (int f = 0; f < 15; f++)
+    for (int f = 0; f < 18; f++)
         B2[f] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(pk + kP2 + (f * 64 + lane) * 8));
     s16x4 B3[2];
 #pragma unroll
@@ -217,51 +221,66 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3, 
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 int c = 16 * m + 4 * g + r, pi = c & 7, pj = (c >> 3) & 7, pk3 = c >> 6;
-                uint16_t v = f2bf_hw(relu(D[r] + bias1));
-                A1[(pk3 + 1) * kA1z + (pj + 1) * kA1y + (pi + 1) * 16 + o] = v;
-                if (SAVE) a1o[(q * 16 + o) * 512 + c] = v;
+                A1[(pk3 + 1) * kA1z + (pj + 1) * kA1y + (pi + 1) * 16 + o] = f2bf_hw(relu(D[r] + bias1));
             }
         }
         __syncthreads();
-        // ---- layer 2: 9 kernel rows in 5 pairs, 3 x-shifts each; the
-        // x-shifted operands are loaded from the zero-padded A1 one cell to
-        // either side (the padding supplies the "same" convolution's zeros)
+        if (SAVE)  // a1 for training, [box][channel][cell]
+            for (int e = t; e < 8192; e += kFwdThreads) {
+                int ch = e >> 9, c = e & 511;
+                a1o[(q * 16 + ch) * 512 + c] =
+                    A1[((c >> 6) + 1) * kA1z + (((c >> 3) & 7) + 1) * kA1y + ((c & 7) + 1) * 16 + ch];
+            }
+        // ---- layer 2, blocked along z: wave w owns the output tiles of
+        // y-rows (2w, 2w+1) at every z.  Each padded input slice zs is loaded
+        // once (per x-shift di: the kernel rows dj = 0 | 1 in K groups 0-1 |
+        // 2-3, and dj = 2 | nothing) and feeds the three output slices
+        // k = zs - dk it reaches; an output slice is complete after its
+        // input slice k + 2.  The x-shifted operands come from the
+        // zero-padded A1 one cell to either side.
         {
-#pragma unroll 1
-            for (int mm = 0; mm < 8; mm++) {
-                const int m = w + 4 * mm;
-                int cell = 16 * m + row, i = cell & 7, j = (cell >> 3) & 7, k = cell >> 6;
-                const int base = k * kA1z + j * kA1y + (i + 1) * 16;  // centre column di = 1
-                f32x4 acc = zero;
+            const int i = row & 7, jj = 2 * w + (row >> 3);
+            const int colA = (g < 2 ? 0 : 1) * kA1y, colB = 2 * kA1y;  // kernel row dj of each K group
+            f32x4 acc[3] = {zero, zero, zero};
 #pragma unroll
-                for (int p = 0; p < 5; p++) {
-                    const int ra = 2 * p, rb = 2 * p + 1;  // kernel row = dk*3 + dj
-                    const int offa = (ra / 3) * kA1z + (ra % 3) * kA1y;
-                    const int offb = rb < 9 ? (rb / 3) * kA1z + (rb % 3) * kA1y : 0;
-                    uint4 F = make_uint4(0, 0, 0, 0), L = F, Rr = F;  // the tenth kernel row does not exist
-                    if (g < 2 || rb < 9) {
-                        const uint16_t *src = A1 + base + (g < 2 ? offa : offb) + 8 * (g & 1);
-                        L = *reinterpret_cast<const uint4 *>(src - 16);
-                        F = *reinterpret_cast<const uint4 *>(src);
-                        Rr = *reinterpret_cast<const uint4 *>(src + 16);
-                    }
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, L), B2[3 * p + 0],
-                                                                  acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, F), B2[3 * p + 1],
-                                                                  acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Rr), B2[3 * p + 2],
-                                                                  acc, 0, 0, 0);
+            for (int zs = 0; zs < 10; zs++) {
+                const uint16_t *src = A1 + zs * kA1z + jj * kA1y + i * 16 + 8 * (g & 1);
+                uint4 FA[3], FB[3];
+#pragma unroll
+                for (int di = 0; di < 3; di++) {
+                    FA[di] = *reinterpret_cast<const uint4 *>(src + colA + di * 16);
+                    FB[di] = g < 2 ? *reinterpret_cast<const uint4 *>(src + colB + di * 16) : make_uint4(0, 0, 0, 0);
                 }
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    int c = 16 * m + 4 * g + r;
-                    uint16_t v = f2bf_hw(relu(acc[r] + bias2));
-                    A2[c * 16 + o] = v;
-                    if (SAVE) a2o[(q * 16 + o) * 512 + c] = v;
+                for (int dk = 0; dk < 3; dk++) {
+                    const int k = zs - dk;
+                    if (k < 0 || k > 7) continue;
+#pragma unroll
+                    for (int di = 0; di < 3; di++) {
+                        acc[k % 3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf16x8, FA[di]), B2[(dk * 2 + 0) * 3 + di], acc[k % 3], 0, 0, 0);
+                        acc[k % 3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf16x8, FB[di]), B2[(dk * 2 + 1) * 3 + di], acc[k % 3], 0, 0, 0);
+                    }
+                }
+                const int kd = zs - 2;  // the output slice completed by this input slice
+                if (kd >= 0) {
+                    const int m = 4 * kd + w;
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        int c = 16 * m + 4 * g + r;
+                        A2[c * 16 + o] = f2bf_hw(relu(acc[kd % 3][r] + bias2));
+                    }
+                    acc[kd % 3] = zero;
                 }
             }
         }
         __syncthreads();  // A1 is dead; its space holds Q from here on
+        if (SAVE)  // a2 for training, [box][channel][cell]
+            for (int e = t; e < 8192; e += kFwdThreads) {
+                int ch = e >> 9, c = e & 511;
+                a2o[(q * 16 + ch) * 512 + c] = A2[c * 16 + ch];
+            }
         // ---- layer 3: Q[tap][cell] = sum_c W3[c][tap] a2[c][cell], taps
         // 0-15 now and 16-26 after the first half of the sum
 #pragma unroll 2
