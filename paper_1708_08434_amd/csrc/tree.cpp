@@ -8,6 +8,7 @@
 // pass plus a sort (section 2.1.2 notes that geometric multigrid needs almost
 // no extra work when the mesh changes).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <atomic>
@@ -226,34 +227,51 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     n27.reset((size_t)27 * n);
     for (int64_t b = lbegin(1); b < lend(1); b++)
         for (int o = 0; o < 27; o++) n27[27 * b + o] = o == 13 ? (int32_t)b : -2;
+    // For a box whose coordinates have parities par (bit a: coordinate a
+    // odd) and a direction oi, the containing level-(l-1) box's direction
+    // from the parent and the octant of the neighbour position in it depend
+    // on par and oi only: tabulated once.
+    struct Up27 {
+        uint8_t up, oct;
+    };
+    static const auto up_tab = [] {
+        std::array<std::array<Up27, 27>, 8> tab{};
+        for (int par = 0; par < 8; par++)
+            for (int oi = 0; oi < 27; oi++) {
+                int o[3] = {oi % 3 - 1, (oi / 3) % 3 - 1, oi / 9 - 1}, up = 0, oct = 0, mul = 1;
+                for (int a = 0; a < 3; a++) {
+                    int s = ((par >> a) & 1) + o[a];  // position relative to the parent's first child, -1..2
+                    up += mul * ((s + 2) / 2);        // -1, 0, +1 parent directions -> 0, 1, 2
+                    oct |= (s & 1) << a;
+                    mul *= 3;
+                }
+                tab[par][oi] = Up27{(uint8_t)up, (uint8_t)oct};
+            }
+        return tab;
+    }();
     for (int l = 2; l <= t->nlev; l++) {
         int32_t lim = 1 << (l - 1);
         // fills the 27 entries of box b; returns the first direction that
         // violates nesting, or -1
         auto fill27 = [&](int64_t b) {
-            int32_t p = t->parent[b];
+            const int32_t *P27 = &n27[27 * (int64_t)t->parent[b]];
             const int32_t *B = &t->ijk[3 * b];
-            for (int oz = -1; oz <= 1; oz++)
-                for (int oy = -1; oy <= 1; oy++)
-                    for (int ox = -1; ox <= 1; ox++) {
-                        int o[3] = {ox, oy, oz}, pos[3], up[3];
-                        bool inside = true;
-                        for (int a = 0; a < 3; a++) {
-                            pos[a] = B[a] + o[a];
-                            inside = inside && pos[a] >= 0 && pos[a] < lim;
-                            // offset of the containing level-(l-1) box from the parent
-                            up[a] = ((B[a] & 1) + o[a] + 2) / 2 - 1;
-                        }
-                        int oi = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
-                        if (!inside) {
-                            n27[27 * b + oi] = -2;
-                            continue;
-                        }
-                        int32_t cont = n27[27 * (int64_t)p + (up[0] + 1) + 3 * (up[1] + 1) + 9 * (up[2] + 1)];
-                        if (cont < 0) return oi;
-                        int oct = (pos[0] & 1) + 2 * (pos[1] & 1) + 4 * (pos[2] & 1);
-                        n27[27 * b + oi] = t->child[8 * (int64_t)cont + oct];  // -1: coarser leaf
-                    }
+            const auto &tab = up_tab[(B[0] & 1) | ((B[1] & 1) << 1) | ((B[2] & 1) << 2)];
+            // directions along each axis that leave the domain
+            const bool lo[3] = {B[0] == 0, B[1] == 0, B[2] == 0};
+            const bool hi[3] = {B[0] == lim - 1, B[1] == lim - 1, B[2] == lim - 1};
+            int32_t *out = &n27[27 * b];
+            for (int oi = 0; oi < 27; oi++) {
+                int ox = oi % 3, oy = (oi / 3) % 3, oz = oi / 9;
+                if ((ox == 0 && lo[0]) || (ox == 2 && hi[0]) || (oy == 0 && lo[1]) || (oy == 2 && hi[1]) ||
+                    (oz == 0 && lo[2]) || (oz == 2 && hi[2])) {
+                    out[oi] = -2;
+                    continue;
+                }
+                int32_t cont = P27[tab[oi].up];
+                if (cont < 0) return oi;
+                out[oi] = t->child[8 * (int64_t)cont + tab[oi].oct];  // -1: coarser leaf
+            }
             return -1;
         };
         FirstBad bad;
@@ -378,13 +396,13 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     for (int l = 1; l <= kMaxLevel + 1; l++) {
         t->ostart[l] = (int64_t)t->oldcp.size();
         if (l > t->nlev) continue;
+        // the 6 face and 12 edge directions of the 27-neighbourhood
+        static const int fe[18] = {1, 3, 4, 5, 7, 9, 10, 11, 12, 14, 15, 16, 17, 19, 21, 22, 23, 25};
         for (int64_t q = t->fstart[l]; q < (int64_t)t->leaf.size() && t->lev[t->leaf[q]] == l; q++) {
             int64_t b = t->leaf[q];
-            for (int o = 0; o < 27; o++) {
-                int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-                int m = (ox != 0) + (oy != 0) + (oz != 0);
-                if (m == 0 || m == 3) continue;
-                int32_t nb = n27[27 * b + o];
+            const int32_t *N27 = &n27[27 * b];
+            for (int e = 0; e < 18; e++) {
+                int32_t nb = N27[fe[e]];
                 if (nb >= 0 && t->child[8 * (int64_t)nb] >= 0) {
                     t->oldcp.push_back((int32_t)b);
                     break;
