@@ -363,8 +363,8 @@ int mg_fluid_stage(mg_tree *t, const double *e_face, const double *e_norm, doubl
 int mg_fluid_step(mg_tree *t, double *ne, double *ni, double dt, int32_t n_vcycles, double *dt_next);
 
 /* Relative residual, L2 and max norms of the current phi on the leaf cells,
- * as the stopping test of mg_fmg_solve takes them (the survey's reading of
- * the residual norm, which the paper does not give): covered cells first
+ * as the stopping test of mg_fmg_solve takes them (a reading of the
+ * residual norm, which the paper does not give): covered cells first
  * reset to the mean of their children; r = b - L phi with the ghosts of the
  * solver; l2 = sqrt(sum r^2 h^3) over leaf cells (volume-weighted); linf =
  * max |r|; rel = l2 divided by the l2 of the residual of phi = 0 (boundary

@@ -284,8 +284,8 @@ def learned_solve(tree, params, tol=1e-8, max_cycles=50, n_down=2, n_up=2):
 
 
 # ---------------------------------------------------------------------------
-# Per-level placement (a reading of the survey's "after the up-sweeps" for
-# each level; the paper has no learned component).  Inside a V-cycle, right
+# Per-level placement (a learned step after the up-sweeps of each level;
+# the paper has no learned component, so this is a reading).  Inside a V-cycle, right
 # after the up-sweeps of a level l >= 3 that has leaf boxes:
 #   r   = b - L_l phi on the level-l boxes, with the ghosts of the cycle (no
 #         restriction of covered cells: the level's own cycle state);
