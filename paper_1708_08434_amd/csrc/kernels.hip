@@ -1775,12 +1775,17 @@ __global__ __launch_bounds__(256) void k_leaf_norms(Geo g, const double *__restr
 // Thread u holds cell positions 2u and 2u+1 of both colours; the per-box sum
 // follows k_leaf_norms' tree over the 256 positions (the shuffles over u
 // are its stages 32..2, the pair sum its stage 1), so the partials are the
-// same bits.
+// same bits.  With h = len 2^-(l+2), 1/h^2 and h^3 are the power-of-two
+// scalings ilen2 2^(2(l+2)) and len3 2^(-3(l+2)) of ilen2 = 1/len^2 and
+// len3 = len^3 (the same bits as dividing, in the normal range), so the
+// kernel holds no divide.  OUT: the FP32 residual is also stored.
+template <bool OUT>
 __global__ __launch_bounds__(128) void k_box_norms(Geo g, const double *__restrict__ phi,
                                                    const double *__restrict__ rhs,
                                                    const double *__restrict__ chat, int64_t b0, int64_t nb,
                                                    const int32_t *__restrict__ leafpos,
-                                                   double *__restrict__ partial, float *__restrict__ r_out) {
+                                                   double *__restrict__ partial, float *__restrict__ r_out,
+                                                   double ilen2, double len3) {
     __shared__ double P[512], H[384], S[4], M[4];
     int64_t lb = xcd_map(blockIdx.x, nb);
     if (lb >= nb) return;
@@ -1802,8 +1807,7 @@ __global__ __launch_bounds__(128) void k_box_norms(Geo g, const double *__restri
     reinterpret_cast<double2 *>(P)[128 + u] = p1;
     __syncthreads();
     const int l = g.ijk[b * 4 + 3];
-    const double h = g.len / (8.0 * (double)(1 << (l - 1)));
-    const double inv_h2 = 1.0 / (h * h), vol = h * h * h;
+    const double inv_h2 = ldexp(ilen2, 2 * (l + 2)), vol = ldexp(len3, -3 * (l + 2));
     double ss[2], mx[2], rr[2][2];
 #pragma unroll
     for (int sl = 0; sl < 2; sl++) {
@@ -1821,7 +1825,7 @@ __global__ __launch_bounds__(128) void k_box_norms(Geo g, const double *__restri
             mx[sl] = nanmax(fabs(r), mx[sl]);
         }
     }
-    if (r_out) {
+    if (OUT) {
         reinterpret_cast<float2 *>(r_out + b * 512)[u] = make_float2((float)rr[0][0], (float)rr[0][1]);
         reinterpret_cast<float2 *>(r_out + b * 512 + 256)[u] = make_float2((float)rr[1][0], (float)rr[1][1]);
     }
@@ -2263,8 +2267,13 @@ void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const
 void launch_box_norms(const Geo &g, const double *phi, const double *rhs, const double *chat, int64_t b0,
                       int64_t nb, const int32_t *leafpos, double *partial, float *r_out, hipStream_t s) {
     if (nb <= 0) return;
-    hipLaunchKernelGGL(k_box_norms, dim3((unsigned)xcd_grid(nb)), dim3(128), 0, s, g, phi, rhs, chat, b0, nb,
-                       leafpos, partial, r_out);
+    const double ilen2 = 1.0 / (g.len * g.len), len3 = g.len * g.len * g.len;
+    if (r_out)
+        hipLaunchKernelGGL(k_box_norms<true>, dim3((unsigned)xcd_grid(nb)), dim3(128), 0, s, g, phi, rhs, chat,
+                           b0, nb, leafpos, partial, r_out, ilen2, len3);
+    else
+        hipLaunchKernelGGL(k_box_norms<false>, dim3((unsigned)xcd_grid(nb)), dim3(128), 0, s, g, phi, rhs, chat,
+                           b0, nb, leafpos, partial, r_out, ilen2, len3);
 }
 template <typename T>
 void launch_leaf_apply(const Geo &g, const T *x, const T *chat, const int32_t *leaf, int64_t nleaf,

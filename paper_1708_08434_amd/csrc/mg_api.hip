@@ -1085,6 +1085,10 @@ int mg_tree_create(mg_tree **out, const mg_domain *dom, int64_t n, const int32_t
 std::mutex g_spare_mu;
 std::vector<std::pair<int, void *>> g_spare_streams;    // (device, stream)
 std::vector<std::pair<size_t, double *>> g_spare_pinned;  // (capacity, buffer)
+// The pinned staging buffer of the table upload (the largest one used so
+// far; a bind holds it until its upload has completed).
+char *g_stage = nullptr;
+size_t g_stage_cap = 0;
 
 int take_capture_stream(int device, void **out) {
     {
@@ -1114,6 +1118,34 @@ int take_pinned(size_t bytes, double **out, size_t *cap) {
     }
     *cap = std::max<size_t>(bytes, 4096);
     return hip_check(hipHostMalloc((void **)out, *cap), "pinned host buffer");
+}
+
+int take_stage(size_t bytes, char **out, size_t *cap) {
+    {
+        std::lock_guard<std::mutex> lk(g_spare_mu);
+        if (g_stage && g_stage_cap >= bytes) {
+            *out = g_stage;
+            *cap = g_stage_cap;
+            g_stage = nullptr;
+            g_stage_cap = 0;
+            return MG_OK;
+        }
+    }
+    *cap = std::max<size_t>(bytes, 1 << 20);
+    return hip_check(hipHostMalloc((void **)out, *cap), "pinned staging buffer");
+}
+// Keeps the larger of the returned buffer and the pooled one.
+void give_stage(char *p, size_t cap) {
+    char *drop = p;
+    {
+        std::lock_guard<std::mutex> lk(g_spare_mu);
+        if (!g_stage || g_stage_cap < cap) {
+            drop = g_stage;
+            g_stage = p;
+            g_stage_cap = cap;
+        }
+    }
+    if (drop) (void)hipHostFree(drop);
 }
 
 int mg_tree_destroy(mg_tree *t) {
@@ -1245,43 +1277,52 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
         int rc = take_pinned(4 * t->ntree * sizeof(double), &t->host_result, &t->host_result_bytes);
         if (rc) return rc;
     }
-    std::vector<int32_t> ijk4((size_t)4 * t->n), isleaf((size_t)t->n);
-    for (int64_t b = 0; b < t->n; b++) isleaf[b] = t->child[8 * b] < 0 ? 1 : 0;
+    // The tables fill [0, off.phi) of the workspace: staged at their
+    // workspace offsets in one pinned buffer and uploaded by one copy (the
+    // gaps and the device-only part2 carry whatever the buffer holds).
+    const size_t tab_bytes = (size_t)t->off.phi;
+    char *stage = nullptr;
+    size_t stage_cap = 0;
+    int rc = take_stage(tab_bytes, &stage, &stage_cap);
+    if (rc) return rc;
+    auto put = [&](int64_t off, const void *src, size_t nbytes) {
+        if (nbytes) std::memcpy(stage + off, src, nbytes);
+    };
+    put(t->off.nbr, t->nbr.data(), t->nbr.size() * 4);
+    put(t->off.cfslot, t->cfslot.data(), t->cfslot.size() * 4);
+    put(t->off.cfq, t->cfq.data(), t->cfq.size() * 4);
+    put(t->off.xt, t->xt.data(), t->xt.size() * 4);
+    put(t->off.pnb, t->pnb.data(), t->pnb.size() * 4);
+    put(t->off.n27, t->n27.data(), t->n27.size() * 4);
+    put(t->off.slotx, t->slotx.data(), t->slotx.size() * 4);
+    put(t->off.parent, t->parent.data(), t->parent.size() * 4);
+    put(t->off.refined, t->refined.data(), t->refined.size() * 4);
+    put(t->off.leaf, t->leaf.data(), t->leaf.size() * 4);
+    put(t->off.cleaf, t->cleaf.data(), t->cleaf.size() * 4);
+    put(t->off.oldcp, t->oldcp.data(), t->oldcp.size() * 4);
+    put(t->off.leafpos, t->leafpos.data(), t->leafpos.size() * 4);
+    put(t->off.cmask, t->cmask.data(), t->cmask.size() * 4);
+    put(t->off.slots, t->slots.data(), t->slots.size() * 4);
+    put(t->off.leaf_tree, t->leaf_tree.data(), t->leaf_tree.size() * 4);
+    put(t->off.tree_off, t->tree_off.data(), t->tree_off.size() * 4);
+    put(t->off.chunk, t->chunk.data(), t->chunk.size() * 4);
+    put(t->off.choff, t->choff.data(), t->choff.size() * 4);
+    put(t->off.tid, t->tid.data(), t->tid.size() * 4);
+    put(t->off.root2, t->root2.data(), t->root2.size() * 4);
+    put(t->off.eig, t->eig, sizeof t->eig);
+    int32_t *ijk4 = (int32_t *)(stage + t->off.ijk), *isleaf = (int32_t *)(stage + t->off.isleaf);
     for (int64_t b = 0; b < t->n; b++) {
         for (int a = 0; a < 3; a++) ijk4[4 * b + a] = t->ijk[3 * b + a];
         ijk4[4 * b + 3] = t->lev[b];
+        isleaf[b] = t->child[8 * b] < 0 ? 1 : 0;
     }
     hipStream_t s = stream_of(t);
-    auto up = [&](void *dst, const void *src, size_t n) {
-        return n ? hip_check(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s), "table upload")
-                 : MG_OK;
-    };
-    int rc = MG_OK;
-    rc = rc ? rc : up(d.nbr, t->nbr.data(), t->nbr.size() * 4);
-    rc = rc ? rc : up(d.cfslot, t->cfslot.data(), t->cfslot.size() * 4);
-    rc = rc ? rc : up(d.cfq, t->cfq.data(), t->cfq.size() * 4);
-    rc = rc ? rc : up(d.xt, t->xt.data(), t->xt.size() * 4);
-    rc = rc ? rc : up(d.pnb, t->pnb.data(), t->pnb.size() * 4);
-    rc = rc ? rc : up(d.n27, t->n27.data(), t->n27.size() * 4);
-    rc = rc ? rc : up(d.slotx, t->slotx.data(), t->slotx.size() * 4);
-    rc = rc ? rc : up(d.ijk, ijk4.data(), ijk4.size() * 4);
-    rc = rc ? rc : up(d.parent, t->parent.data(), t->parent.size() * 4);
-    rc = rc ? rc : up(d.refined, t->refined.data(), t->refined.size() * 4);
-    rc = rc ? rc : up(d.leaf, t->leaf.data(), t->leaf.size() * 4);
-    rc = rc ? rc : up(d.cleaf, t->cleaf.data(), t->cleaf.size() * 4);
-    rc = rc ? rc : up(d.oldcp, t->oldcp.data(), t->oldcp.size() * 4);
-    rc = rc ? rc : up(d.leafpos, t->leafpos.data(), t->leafpos.size() * 4);
-    rc = rc ? rc : up(d.cmask, t->cmask.data(), t->cmask.size() * 4);
-    rc = rc ? rc : up(d.slots, t->slots.data(), t->slots.size() * 4);
-    rc = rc ? rc : up(d.leaf_tree, t->leaf_tree.data(), t->leaf_tree.size() * 4);
-    rc = rc ? rc : up(d.tree_off, t->tree_off.data(), t->tree_off.size() * 4);
-    rc = rc ? rc : up(d.chunk, t->chunk.data(), t->chunk.size() * 4);
-    rc = rc ? rc : up(d.choff, t->choff.data(), t->choff.size() * 4);
-    rc = rc ? rc : up(d.isleaf, isleaf.data(), isleaf.size() * 4);
-    rc = rc ? rc : up(d.tid, t->tid.data(), t->tid.size() * 4);
-    rc = rc ? rc : up(d.root2, t->root2.data(), t->root2.size() * 4);
-    rc = rc ? rc : up(d.eig, t->eig, sizeof t->eig);
-    if (rc) return rc;
+    rc = hip_check(hipMemcpyAsync(ws, stage, tab_bytes, hipMemcpyHostToDevice, s), "table upload");
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        give_stage(stage, stage_cap);
+        return rc;
+    }
     launch_fill<double>(d.phi, 512 * t->n, 0.0, s);
     launch_fill<double>(d.rhs, 512 * t->n, 0.0, s);
     launch_fill<double>(d.old, 512 * t->n, 0.0, s);
@@ -1291,8 +1332,10 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     if (d.bcval) launch_fill<double>(d.bcval, 6 * 64 * t->n, 0.0, s);
     dirty_all(f64(t));
     dirty_all(f32(t));
-    // the host vectors used as upload sources are freed on return
-    return hip_check(hipStreamSynchronize(s), "bind");
+    // the staging buffer goes back to the pool once the upload has run
+    rc = hip_check(hipStreamSynchronize(s), "bind");
+    give_stage(stage, stage_cap);
+    return rc;
 }
 
 int mg_field_set(mg_tree *t, int which, const double *dev) {

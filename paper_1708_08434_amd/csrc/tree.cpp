@@ -274,11 +274,43 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
             }
             return -1;
         };
+        // The 8 children of the k-th refined box P of level l-1 are the boxes
+        // 8k .. 8k+7 of level l in octant order, and a child's parities are
+        // its octant.  So the entries of fill27 for all eight follow from one
+        // value per direction u of P's 27-neighbourhood: the first child of
+        // the level-(l-1) box there (children are consecutive in octant
+        // order, so child oct is first + oct), -1 for a leaf, -2 outside the
+        // domain (a level-l position is outside exactly when its level-(l-1)
+        // position is), -3 in the domain but not covered down to level l-1
+        // (a nesting violation).
+        auto fill_octet = [&](int64_t c0) {
+            const int32_t *P27 = &n27[27 * (int64_t)t->parent[c0]];
+            int32_t first[27];
+            for (int u = 0; u < 27; u++) {
+                int32_t cont = P27[u];
+                first[u] = cont == -2 ? -2 : cont < 0 ? -3 : t->child[8 * (int64_t)cont];
+            }
+            for (int o = 0; o < 8; o++) {
+                const auto &tab = up_tab[o];
+                int32_t *outp = &n27[27 * (c0 + o)];
+                bool bad_o = false;
+                for (int oi = 0; oi < 27; oi++) {
+                    int32_t f = first[tab[oi].up];
+                    outp[oi] = f >= 0 ? f + tab[oi].oct : f;
+                    bad_o = bad_o || f == -3;
+                }
+                if (bad_o) return c0 + o;
+            }
+            return (int64_t)-1;
+        };
         FirstBad bad;
         int64_t l0 = lbegin(l);
         parallel_for(lend(l) - l0, [&](int64_t lo, int64_t hi) {
-            for (int64_t b = l0 + lo; b < l0 + hi; b++)
-                if (fill27(b) >= 0) bad.add(b);
+            // octets whose first box lies in [lo, hi)
+            for (int64_t q = (lo + 7) / 8; q < (hi + 7) / 8; q++) {
+                int64_t bb = fill_octet(l0 + 8 * q);
+                if (bb >= 0) bad.add(bb);
+            }
         });
         if (bad.v >= 0) {
             int64_t bb = bad.v;
