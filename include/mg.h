@@ -101,8 +101,12 @@ int mg_tree_info(const mg_tree *t, mg_tree_info_t *info);
  * mg_tree_bind - attach a caller-owned device workspace and a stream.
  *   ws      device pointer, 256-byte aligned, >= info.workspace_bytes
  *   stream  hipStream_t (as void*), e.g. torch.cuda.current_stream()
- * Uploads the index tables into the workspace (asynchronously on stream) and
- * zeroes the fields.  The workspace must stay valid until rebind or destroy.
+ * Uploads the index tables into the workspace with one copy from a pinned
+ * host staging buffer, zeroes the fields, and waits for both on the stream
+ * before returning.  The staging buffer (the tables' size, a few hundred
+ * bytes per box) is pooled: the library keeps the largest one it has used
+ * until the process ends.  The workspace must stay valid until rebind or
+ * destroy.
  */
 int mg_tree_bind(mg_tree *t, void *ws, int64_t ws_bytes, void *stream);
 
@@ -305,6 +309,24 @@ int mg_efield(mg_tree *t, double *e_face, double *e_norm);
 int mg_refine_scores(mg_tree *t, double *scores);
 int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, double h_deref,
                    int max_level, int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree, int64_t *n_out);
+/*
+ * The criterion of step 2 tests, per leaf box, one value: the largest score
+ * over its cells and the cells of its same-level leaf neighbours within 3
+ * cells (the 3-cell buffer of section 2.5).  mg_refine_near forms it on the
+ * GPU from step 1's device scores:
+ *   near[b] = max over o in the 27-neighbourhood of scores[N*27 + 26 - o]
+ *   for the same-level leaf neighbour N = b + o (b's own scores[b*27 + 13]
+ *   where there is none or it is refined), 0 for a refined box.
+ *   scores, near: device, n*27 and n doubles.  Asynchronous, on the bound
+ *   stream; the maximum is taken in the order of mg_regrid_plan's, so near
+ *   is the same bits as the value the host plan forms.
+ * mg_regrid_plan_near is mg_regrid_plan from a host copy of near (n doubles
+ * instead of n*27): the same box list.  Errors as mg_regrid_plan.
+ */
+int mg_refine_near(mg_tree *t, const double *scores, double *near);
+int mg_regrid_plan_near(const mg_tree *t, const double *near, double c3, double deref, double h_deref,
+                        int max_level, int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree,
+                        int64_t *n_out);
 int mg_transfer(mg_tree *from, mg_tree *to);
 
 /*

@@ -135,6 +135,10 @@ void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s)
 // and the transfer of phi to a new tree (copy of boxes present in both, then
 // level by level the interpolation of new boxes from their parents).
 void launch_refine_scores(const Geo &g, const double *rhs, int64_t n, double *scores, hipStream_t s);
+// near[b] (leaf boxes): the largest score over b's cells and the cells of its
+// same-level leaf neighbours within 3 cells; 0 for refined boxes
+void launch_refine_near(const int32_t *n27, const int32_t *isleaf, const double *scores, int64_t n, double *near,
+                        hipStream_t s);
 void launch_transfer_copy(const double *from, double *to, const int32_t *src, int64_t n, hipStream_t s);
 void launch_transfer_interp(const Geo &g, double *phi, const double *chat, const int32_t *list, int64_t nlist,
                             hipStream_t s);

@@ -1960,6 +1960,34 @@ __global__ __launch_bounds__(256) void k_refine_scores(Geo g, const double *__re
     if (t < 27) scores[b * 27 + t] = fmax(fmax(W[0][t], W[1][t]), fmax(W[2][t], W[3][t]));
 }
 
+// The refinement criterion with its 3-cell buffer (section 2.5) reduced to
+// one value per box: for a leaf box b, near[b] = the largest score over b's
+// cells and the cells of its same-level leaf neighbours within 3 cells of
+// it (region 26 - o of neighbour b + o; a missing or refined neighbour
+// contributes b's own whole-box score r = 13); 0 for a refined box.  The
+// maximum is taken as (m < x) ? x : m in the order o = 0..26, the host
+// planner's arithmetic, so the two give the same bits.
+__global__ __launch_bounds__(256) void k_refine_near(const int32_t *__restrict__ n27,
+                                                     const int32_t *__restrict__ isleaf,
+                                                     const double *__restrict__ sc, int64_t n,
+                                                     double *__restrict__ near) {
+    int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= n) return;
+    if (!isleaf[b]) {
+        near[b] = 0.0;
+        return;
+    }
+    const int32_t *nb = n27 + 27 * b;
+    double m = sc[27 * b + 13];
+    for (int o = 0; o < 27; o++) {
+        int32_t N = nb[o];
+        bool use = N >= 0 && isleaf[N];
+        double x = sc[use ? 27 * (int64_t)N + (26 - o) : 27 * b + 13];
+        m = (m < x) ? x : m;
+    }
+    near[b] = m;
+}
+
 // Transfer of phi to a new tree.  Copy: new box b takes the old box src[b]
 // (same level and position) when src[b] >= 0.
 __global__ __launch_bounds__(256) void k_transfer_copy(const double *__restrict__ from, double *__restrict__ to,
@@ -2288,6 +2316,12 @@ void launch_efield(const Geo &g, const double *phi, const double *chat, int64_t 
                    double *e_norm, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_efield, dim3((unsigned)xcd_grid(n)), dim3(256), 0, s, g, phi, chat, n, e_face, e_norm);
+}
+void launch_refine_near(const int32_t *n27, const int32_t *isleaf, const double *scores, int64_t n, double *near,
+                        hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_refine_near, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n27, isleaf, scores, n,
+                       near);
 }
 void launch_refine_scores(const Geo &g, const double *rhs, int64_t n, double *scores, hipStream_t s) {
     if (n <= 0) return;

@@ -1550,30 +1550,64 @@ int mg_refine_scores(mg_tree *t, double *scores) {
     return hip_check(hipGetLastError(), "refine scores launch");
 }
 
-int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, double h_deref,
-                   int max_level, int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree, int64_t *n_out) {
-    if (!t || !scores || !n_out || !(c3 > 0) || !(deref >= 0) || !(h_deref > 0) || max_level < 1 ||
+int mg_refine_near(mg_tree *t, const double *scores, double *near) {
+    int rc = require_bound(t);
+    if (rc) return rc;
+    if (!scores || !near) {
+        set_error("mg_refine_near: null argument");
+        return MG_EINVAL;
+    }
+    launch_refine_near(t->d.n27, t->d.isleaf, scores, t->n, near, stream_of(t));
+    return hip_check(hipGetLastError(), "refine near launch");
+}
+
+// mg_regrid_plan and mg_regrid_plan_near: the same plan, from the 27 region
+// scores of every box or from their per-box reduction (near != 0).
+static int plan_common(const mg_tree *t, const double *scores, const double *near, double c3, double deref,
+                       double h_deref, int max_level, int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree,
+                       int64_t *n_out, const char *name) {
+    if (!t || !(scores || near) || !n_out || !(c3 > 0) || !(deref >= 0) || !(h_deref > 0) || max_level < 1 ||
         max_level > kMaxLevel ||
         cap < 0 || (cap > 0 && (!level || !ijk || !tree))) {
-        set_error("mg_regrid_plan: invalid arguments");
+        set_error(std::string(name) + ": invalid arguments");
         return MG_EINVAL;
     }
     std::vector<int32_t> lv, ij, tr;
     try {
-        regrid_plan(t, scores, c3, deref, h_deref, max_level, lv, ij, tr);
+        if (near)
+            regrid_plan_near(t, near, c3, deref, h_deref, max_level, lv, ij, tr);
+        else
+            regrid_plan(t, scores, c3, deref, h_deref, max_level, lv, ij, tr);
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed");
         return MG_ENOMEM;
     }
     *n_out = (int64_t)lv.size();
     if ((int64_t)lv.size() > cap) {
-        set_error("mg_regrid_plan: output capacity too small (n_out holds the size needed)");
+        set_error(std::string(name) + ": output capacity too small (n_out holds the size needed)");
         return MG_ENOMEM;
     }
     std::copy(lv.begin(), lv.end(), level);
     std::copy(ij.begin(), ij.end(), ijk);
     std::copy(tr.begin(), tr.end(), tree);
     return MG_OK;
+}
+
+int mg_regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, double h_deref,
+                   int max_level, int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree, int64_t *n_out) {
+    return plan_common(t, scores, nullptr, c3, deref, h_deref, max_level, cap, level, ijk, tree, n_out,
+                       "mg_regrid_plan");
+}
+
+int mg_regrid_plan_near(const mg_tree *t, const double *near, double c3, double deref, double h_deref,
+                        int max_level, int64_t cap, int32_t *level, int32_t *ijk, int32_t *tree,
+                        int64_t *n_out) {
+    if (!near) {
+        set_error("mg_regrid_plan_near: null near");
+        return MG_EINVAL;
+    }
+    return plan_common(t, nullptr, near, c3, deref, h_deref, max_level, cap, level, ijk, tree, n_out,
+                       "mg_regrid_plan_near");
 }
 
 // ------------------------------------------------------------ fluid model

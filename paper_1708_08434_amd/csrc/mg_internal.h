@@ -194,9 +194,15 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
 uint64_t morton(int32_t i, int32_t j, int32_t k);
 
 // One regrid step (regrid.cpp): the new box list from per-box refinement
-// scores; see mg_regrid_plan in mg.h.
+// scores; see mg_regrid_plan in mg.h.  regrid_near reduces the 27 scores of
+// each leaf box and its neighbours to the one value the criterion tests
+// (the host twin of k_refine_near), and regrid_plan_near plans from those.
 int regrid_plan(const mg_tree *t, const double *scores, double c3, double deref, double h_deref,
                 int max_level,
                 std::vector<int32_t> &level, std::vector<int32_t> &ijk, std::vector<int32_t> &tree);
+void regrid_near(const mg_tree *t, const double *scores, double *near);
+int regrid_plan_near(const mg_tree *t, const double *near, double c3, double deref, double h_deref,
+                     int max_level, std::vector<int32_t> &level, std::vector<int32_t> &ijk,
+                     std::vector<int32_t> &tree);
 void root_eigen(const int32_t bc_type[6], double *eig);
 }

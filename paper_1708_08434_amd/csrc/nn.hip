@@ -11,9 +11,11 @@
 // Forward: a box's activations stay in LDS (one box at a time per workgroup).
 //  * layer 1 is an implicit GEMM [16 cells x 32 taps (27 used)] x [32 x 16
 //    channels]: one 16x16x32 BF16 MFMA per 16-cell tile;
-//  * layer 2 is an implicit GEMM with K = 27 taps x 16 channels, taken as 15
-//    16x16x32 MFMAs per tile (two kernel rows of 16 channels per
-//    instruction); activations are stored [padded cell][channel];
+//  * layer 2 is an implicit GEMM with K = 27 taps x 16 channels, taken as 18
+//    16x16x32 MFMAs per tile (the kernel rows of one z offset paired, 16
+//    channels each, per instruction) and blocked along z, so that each
+//    loaded input slice serves the three output slices it reaches;
+//    activations are stored [padded cell][channel];
 //  * layer 3 first forms Q[tap][cell] = sum_c W3[c][tap] a2[c][cell] with
 //    16x16x16 MFMAs (N = taps), then y[cell] = b3 + sum_tap Q[tap][cell+tap-1],
 //    which turns the 16->1 convolution into a dense GEMM plus a 27-term sum.

@@ -32,41 +32,58 @@ uint64_t key(int64_t tree, int l, int64_t i, int64_t j, int64_t k) {
     return ((uint64_t)l << 58) | ((uint64_t)tree << 42) | morton((int32_t)i, (int32_t)j, (int32_t)k);
 }
 
-// every third bit of m, from bit s, packed
+// The coordinate bits of m from bit s (bits s, s+3, ..., s+39), packed: the
+// inverse of morton()'s spread, with the level and tree bits masked off.
 int32_t compact3(uint64_t m, int s) {
-    int32_t v = 0;
-    for (int b = 0; b < 14; b++) v |= (int32_t)((m >> (3 * b + s)) & 1) << b;
-    return v;
+    uint64_t v = (m >> s) & 0x0000009249249249ULL;
+    v = (v | (v >> 2)) & 0x10c30c30c30c30c3ULL;
+    v = (v | (v >> 4)) & 0x100f00f00f00f00fULL;
+    v = (v | (v >> 8)) & 0x001f0000ff0000ffULL;
+    v = (v | (v >> 16)) & 0x001f00000000ffffULL;
+    v = (v | (v >> 32)) & 0x00000000001fffffULL;
+    return (int32_t)v;
 }
 
 }  // namespace
 
-int regrid_plan(const mg_tree *t, const double *sc, double c3, double deref, double h_deref, int max_level,
-                std::vector<int32_t> &level, std::vector<int32_t> &ijk, std::vector<int32_t> &tree) {
+void regrid_near(const mg_tree *t, const double *sc, double *near) {
     const int64_t n = t->n;
-    std::vector<char> leaf(n), refine(n, 0), drop(n, 0);
-    parallel_for(n, [&](int64_t lo, int64_t hi) {
-        for (int64_t b = lo; b < hi; b++) leaf[b] = t->child[8 * b] < 0;
-    });
     // near[b] (leaves): the largest score over the cells of b and the cells
     // of same-level leaf neighbours within 3 cells of b; scores[b][r] is the
     // largest |b| h^2 over the cells of b in region r = (sx+1) + 3 (sy+1) +
     // 9 (sz+1) (s_a = -1: cells 0..2 along a, +1: cells 5..7, 0: all), and
     // the cells of neighbour b + o within 3 cells of b form its region -o,
     // i.e. 26 - o.  Scores are >= 0, so a missing neighbour reads b's own.
-    std::vector<double> near(n, 0.0);
     parallel_for(n, [&](int64_t lo, int64_t hi) {
         for (int64_t b = lo; b < hi; b++) {
-            if (!leaf[b]) continue;
+            near[b] = 0.0;
+            if (t->child[8 * b] >= 0) continue;
             const int32_t *nb = &t->n27[27 * b];
             double m = sc[27 * b + 13];
             for (int o = 0; o < 27; o++) {
                 int64_t N = nb[o];
-                bool use = N >= 0 && leaf[N >= 0 ? N : b];
+                bool use = N >= 0 && t->child[8 * (N >= 0 ? N : b)] < 0;
                 m = std::max(m, sc[use ? 27 * N + (26 - o) : 27 * b + 13]);
             }
             near[b] = m;
         }
+    });
+}
+
+int regrid_plan(const mg_tree *t, const double *sc, double c3, double deref, double h_deref, int max_level,
+                std::vector<int32_t> &level, std::vector<int32_t> &ijk, std::vector<int32_t> &tree) {
+    std::vector<double> near(t->n);
+    regrid_near(t, sc, near.data());
+    return regrid_plan_near(t, near.data(), c3, deref, h_deref, max_level, level, ijk, tree);
+}
+
+int regrid_plan_near(const mg_tree *t, const double *near, double c3, double deref, double h_deref,
+                     int max_level, std::vector<int32_t> &level, std::vector<int32_t> &ijk,
+                     std::vector<int32_t> &tree) {
+    const int64_t n = t->n;
+    std::vector<char> leaf(n), refine(n, 0), drop(n, 0);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t b = lo; b < hi; b++) leaf[b] = t->child[8 * b] < 0;
     });
     parallel_for(n, [&](int64_t lo, int64_t hi) {
         for (int64_t b = lo; b < hi; b++)

@@ -43,8 +43,9 @@ EXPORTS = ["mg_tree_create", "mg_tree_destroy", "mg_tree_info", "mg_tree_bind", 
            "mg_field_set", "mg_field_get", "mg_default_opts", "mg_fmg_solve", "mg_vcycle",
            "mg_residual", "mg_tree_residuals", "mg_step", "mg_timing_enable", "mg_timing_read",
            "mg_autotune", "mg_set_schedule", "mg_stream_copy", "mg_efield", "mg_refine_scores",
-           "mg_regrid_plan", "mg_transfer", "mg_fluid_workspace_bytes", "mg_fluid_bind",
-           "mg_fluid_stage", "mg_fluid_step", "mg_set_fusion", "mg_field", "mg_last_error"]
+           "mg_refine_near", "mg_regrid_plan", "mg_regrid_plan_near", "mg_transfer",
+           "mg_fluid_workspace_bytes", "mg_fluid_bind", "mg_fluid_stage", "mg_fluid_step", "mg_set_fusion",
+           "mg_field", "mg_last_error"]
 
 
 class mg_domain(ctypes.Structure):
@@ -125,6 +126,9 @@ def lib():
         L.mg_refine_scores.argtypes = [P, P]
         L.mg_regrid_plan.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I32, I64,
                                       P, P, P, P]
+        L.mg_refine_near.argtypes = [P, P, P]
+        L.mg_regrid_plan_near.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I32, I64,
+                                           P, P, P, P]
         L.mg_transfer.argtypes = [P, P]
         L.mg_fluid_workspace_bytes.argtypes = [P, I32]
         L.mg_fluid_workspace_bytes.restype = I64
@@ -253,9 +257,22 @@ def mg_refine_scores(h, scores_ptr):
     check(lib().mg_refine_scores(h, ctypes.c_void_p(scores_ptr)))
 
 
+def mg_refine_near(h, scores_ptr, near_ptr):
+    check(lib().mg_refine_near(h, ctypes.c_void_p(scores_ptr), ctypes.c_void_p(near_ptr)))
+
+
 def mg_regrid_plan(h, scores, c3, deref, max_level, h_deref=float("inf")):
     """New box list (level, ijk, tree) from host scores [n][27]."""
-    sc = np.ascontiguousarray(scores, dtype=np.float64)
+    return _plan(lib().mg_regrid_plan, h, scores, c3, deref, max_level, h_deref)
+
+
+def mg_regrid_plan_near(h, near, c3, deref, max_level, h_deref=float("inf")):
+    """The same box list from host per-box values near [n] (mg_refine_near)."""
+    return _plan(lib().mg_regrid_plan_near, h, near, c3, deref, max_level, h_deref)
+
+
+def _plan(fn, h, values, c3, deref, max_level, h_deref):
+    sc = np.ascontiguousarray(values, dtype=np.float64)
     need = ctypes.c_int64()
     args = (float(c3), float(deref), float(h_deref), int(max_level))
     n = 2 * len(sc) + 4096                   # enough unless the step refines most boxes
@@ -263,7 +280,7 @@ def mg_regrid_plan(h, scores, c3, deref, max_level, h_deref=float("inf")):
         lv = np.zeros(n, dtype=np.int32)
         ij = np.zeros((n, 3), dtype=np.int32)
         tr = np.zeros(n, dtype=np.int32)
-        rc = lib().mg_regrid_plan(h, _p(sc), *args, n, _p(lv), _p(ij), _p(tr), ctypes.byref(need))
+        rc = fn(h, _p(sc), *args, n, _p(lv), _p(ij), _p(tr), ctypes.byref(need))
         if rc == MG_ENOMEM and need.value > n:
             n = need.value
             continue
@@ -379,18 +396,23 @@ class Tree:
         self.length = float(length)
         self.ws = None
         if bind:
-            import torch
-            self.device = torch.device(device)
-            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-            # rounded up (64 MiB for large trees): trees of a mesh adaptation
-            # differ by a few boxes, and equal sizes let torch's caching
-            # allocator hand a freed workspace to the next tree instead of
-            # making a new allocation
-            need = int(self.info.workspace_bytes)
-            r = _WS_ROUND if need >= 4 * _WS_ROUND else 2 << 20
-            nbytes = -(-need // r) * r
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            mg_tree_bind(self.h, self.ws.data_ptr(), self.ws.numel(), self.stream.cuda_stream)
+            self.bind(device, stream)
+
+    def bind(self, device="cuda", stream=None):
+        """Allocate the device workspace with torch and attach it
+        (mg_tree_bind: table upload and zeroed fields, waited for)."""
+        import torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # rounded up (64 MiB for large trees): trees of a mesh adaptation
+        # differ by a few boxes, and equal sizes let torch's caching
+        # allocator hand a freed workspace to the next tree instead of
+        # making a new allocation
+        need = int(self.info.workspace_bytes)
+        r = _WS_ROUND if need >= 4 * _WS_ROUND else 2 << 20
+        nbytes = -(-need // r) * r
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        mg_tree_bind(self.h, self.ws.data_ptr(), self.ws.numel(), self.stream.cuda_stream)
 
     @classmethod
     def from_workload(cls, w, **kw):
@@ -459,6 +481,18 @@ class Tree:
         mg_refine_scores(self.h, out.data_ptr())
         self.stream.synchronize()
         return out.cpu().numpy()
+
+    def refine_near(self):
+        """[n] per-box values of the refinement criterion with its 3-cell
+        buffer (mg_refine_scores, then mg_refine_near on the GPU), as a numpy
+        array: the input of mg_regrid_plan_near."""
+        import torch
+        sc = torch.empty((self.n, 27), dtype=torch.float64, device=self.device)
+        near = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        mg_refine_scores(self.h, sc.data_ptr())
+        mg_refine_near(self.h, sc.data_ptr(), near.data_ptr())
+        self.stream.synchronize()
+        return near.cpu().numpy()
 
     def efield(self, to_numpy=True):
         """Face components [n][3][9][8][8] and cell-centre strength [n][8][8][8]

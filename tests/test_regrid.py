@@ -12,8 +12,11 @@ CPU (no GPU):
 * the oracle's transfer: exact for linear potentials across refinement,
   derefinement and nesting refinement; the identity on an unchanged tree; and
   a new box checked cell by cell against the stencil evaluated by hand.
-GPU: the scores against numpy, the transfer against the oracle, and a whole
-regrid step (plan, transfer, warm V-cycles) against the oracle."""
+* the plan from the per-box values of the criterion (mg_regrid_plan_near)
+  against the same rules and against the plan from the 27 scores.
+GPU: the scores against numpy, the per-box values against the rule applied
+to those scores, the transfer against the oracle, and a whole regrid step
+(plan, transfer, warm V-cycles) against the oracle."""
 import itertools
 
 import numpy as np
@@ -148,6 +151,52 @@ def test_plan_matches_the_rules_on_random_scores(seed, h_deref):
     O.OracleTree(lv, ij, tr)
 
 
+def near_of(level, ijk, tree, scores):
+    """Per box, the value the criterion tests (written from the rule): for a
+    leaf, the largest score over its cells and the cells of its same-level
+    leaf neighbours within 3 cells of it; 0 for a refined box."""
+    keys = [(int(t), int(l), int(c[0]), int(c[1]), int(c[2])) for l, c, t in zip(level, ijk, tree)]
+    idx = {k: q for q, k in enumerate(keys)}
+    out = np.zeros(len(keys))
+    for q, k in enumerate(keys):
+        if children(k)[0] in idx:
+            continue
+        t, l, i, j, kk = k
+        lim = 1 << (l - 1)
+        v = [scores[q][13]]
+        for o in OFFS:
+            p = (i + o[0], j + o[1], kk + o[2])
+            n = (t, l) + p
+            if min(p) >= 0 and max(p) < lim and n in idx and children(n)[0] not in idx:
+                v.append(scores[idx[n]][reg(tuple(-x for x in o))])
+        out[q] = max(v)
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_plan_from_near_values_matches_the_rules(seed):
+    """mg_regrid_plan_near on the per-box values of the criterion gives the
+    reference rules' plan, and the same list as mg_regrid_plan on the 27
+    scores."""
+    bl = forest_boxes()
+    rng = np.random.default_rng(seed)
+    sc = rng.lognormal(0.0, 1.5, (bl.n, 27)) * 10.0 ** rng.uniform(-4, 0, (bl.n, 1))
+    sc[:, 13] = np.maximum(sc[:, 13], sc.max(axis=1))
+    c3 = float(np.quantile(sc[:, 13], 0.98))
+    near = near_of(bl.level, bl.ijk, bl.tree, sc)
+    h = M.mg_tree_create(M.make_domain(), bl.level, bl.ijk, bl.tree)
+    try:
+        order = M.mg_tree_index(h, M.MG_IDX_ORDER, bl.n).reshape(-1)
+        a = M.mg_regrid_plan_near(h, near[order], c3, 0.3, 6)
+        b = M.mg_regrid_plan(h, sc[order], c3, 0.3, 6)
+    finally:
+        M.mg_tree_destroy(h)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    got = {(int(t), int(l), *map(int, c)) for l, c, t in zip(a[0], a[1], a[2])}
+    assert got == ref_plan(bl.level, bl.ijk, bl.tree, sc, c3, 0.3, 6)
+
+
 def test_plan_refines_around_a_charge_and_derefines_behind_it():
     """Structured case: a uniform level-3 tree whose finest boxes near x = 0.2
     are refined; the charge is now at x = 0.8.  Boxes near the charge get
@@ -229,6 +278,30 @@ def test_gpu_scores_match_numpy():
     want = numpy_scores(lv, ij, g.get_field(M.MG_FIELD_RHS))
     print("scores", g.n, "boxes, max", want.max(), flush=True)
     assert np.array_equal(sc, want)
+
+
+@pytest.mark.gpu
+def test_gpu_near_values_match_the_host_rule():
+    """mg_refine_near on the GPU against the rule's per-box values computed
+    here from the GPU's own scores (the same bits), and the plans from the
+    two paths (identical lists)."""
+    w = streamer_small()
+    g = M.Tree.from_workload(w)
+    g.set_rhs_from(w)
+    sc = g.refine_scores()
+    near = g.refine_near()
+    lv, ij, tr = g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK), g.index(M.MG_IDX_TREE)
+    want = near_of(lv, ij, tr, sc)
+    print("near", g.n, "boxes, max", want.max(), flush=True)
+    assert np.array_equal(near, want)
+    c3 = 0.1 * float(want.max())
+    a = M.mg_regrid_plan_near(g.h, near, c3, 0.125, g.nlev + 1)
+    b = M.mg_regrid_plan(g.h, sc, c3, 0.125, g.nlev + 1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    new = {(int(t), int(l), *map(int, c)) for l, c, t in zip(a[0], a[1], a[2])}
+    old = {(int(t), int(l), *map(int, c)) for l, c, t in zip(lv, ij, tr)}
+    assert new != old                            # the step changes the tree
 
 
 @pytest.mark.gpu
