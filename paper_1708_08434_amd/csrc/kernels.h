@@ -12,7 +12,6 @@ struct Geo {
     const int32_t *cfslot;  // [n][6]
     const int32_t *cfq;     // [n][6]
     const int32_t *xt;      // [n][6][4][2] faces of the face neighbours
-    const int32_t *pnb;     // [n][6] the parent's face neighbours
     const int32_t *n27;     // [n][27] same-level box at ijk + o, o in {-1,0,1}^3 (x fastest);
                             // -1 covered only by a coarser leaf, -2 outside the domain
     const int32_t *slotx;   // [nslot][8] Q, base t1, base t2, Q's neighbours -t1 +t1 -t2 +t2
@@ -135,6 +134,8 @@ void launch_ir_update(double *phi, const float *e, int64_t count, hipStream_t s)
 // and the transfer of phi to a new tree (copy of boxes present in both, then
 // level by level the interpolation of new boxes from their parents).
 void launch_refine_scores(const Geo &g, const double *rhs, int64_t n, double *scores, hipStream_t s);
+// xt[b][d][4][2] from the face tables nbr and cfslot ([n][6], on the device)
+void launch_face_xt(const int32_t *nbr, const int32_t *cfslot, int64_t n, int32_t *xt, hipStream_t s);
 // near[b] (leaf boxes): the largest score over b's cells and the cells of its
 // same-level leaf neighbours within 3 cells; 0 for refined boxes
 void launch_refine_near(const int32_t *n27, const int32_t *isleaf, const double *scores, int64_t n, double *near,

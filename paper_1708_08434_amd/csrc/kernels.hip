@@ -1000,7 +1000,7 @@ __global__ __launch_bounds__(256) void k_prolong_cf(Geo g, T *__restrict__ phi, 
                 del = phi[q] - old[q];
             } else {
                 int face = 2 * oax + (C[oax] > 7 ? 1 : 0);
-                int N = g.pnb[b * 6 + face];  // = nbr[p][face]
+                int N = g.nbr[p * 6 + face];  // the parent's face neighbour
                 if (N >= 0) {
                     C[oax] = C[oax] > 7 ? 0 : 7;
                     int64_t q = (int64_t)N * 512 + cs_idx3(C);
@@ -1920,6 +1920,33 @@ __global__ __launch_bounds__(256) void k_efield(Geo g, const double *__restrict_
     }
 }
 
+// Faces of the face neighbours, formed from the uploaded face tables: for
+// box b, face d with a same-level neighbour N, and the 4 faces of N across
+// the two axes tangential to d (-t1, +t1, -t2, +t2), the pair (nbr[N][d'],
+// cfslot[N][d']) (the fused Gauss-Seidel sweep recomputes N's face layer
+// and needs N's ghosts); all -2 where face d has no same-level neighbour.
+// One thread per (box, face).
+__global__ __launch_bounds__(256) void k_face_xt(const int32_t *__restrict__ nbr, const int32_t *__restrict__ cfslot,
+                                                 int64_t n, int32_t *__restrict__ xt) {
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= 6 * n) return;
+    const int d = (int)(e % 6);
+    const int32_t N = nbr[e];
+    int32_t *out = xt + e * 8;
+    if (N < 0) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) out[q] = -2;
+        return;
+    }
+    const int a = d >> 1, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+    const int tf[4] = {2 * t1, 2 * t1 + 1, 2 * t2, 2 * t2 + 1};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        out[2 * q] = nbr[6 * (int64_t)N + tf[q]];
+        out[2 * q + 1] = cfslot[6 * (int64_t)N + tf[q]];
+    }
+}
+
 // Refinement scores (section 2.5, the space-charge criterion |b| h^2 > c3):
 // for box b, scores[b*27 + r] = the largest |b| h^2 over its cells in region
 // r = (sx+1) + 3 (sy+1) + 9 (sz+1), where along each axis s = -1 takes cells
@@ -2316,6 +2343,10 @@ void launch_efield(const Geo &g, const double *phi, const double *chat, int64_t 
                    double *e_norm, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_efield, dim3((unsigned)xcd_grid(n)), dim3(256), 0, s, g, phi, chat, n, e_face, e_norm);
+}
+void launch_face_xt(const int32_t *nbr, const int32_t *cfslot, int64_t n, int32_t *xt, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_face_xt, dim3((unsigned)((6 * n + 255) / 256)), dim3(256), 0, s, nbr, cfslot, n, xt);
 }
 void launch_refine_near(const int32_t *n27, const int32_t *isleaf, const double *scores, int64_t n, double *near,
                         hipStream_t s) {

@@ -52,7 +52,6 @@ Geo geo(const mg_tree *t, bool homogeneous) {
     g.cfslot = t->d.cfslot;
     g.cfq = t->d.cfq;
     g.xt = t->d.xt;
-    g.pnb = t->d.pnb;
     g.n27 = t->d.n27;
     g.slotx = t->d.slotx;
     g.ijk = t->d.ijk;
@@ -1238,7 +1237,6 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     d.cfslot = (int32_t *)(base + t->off.cfslot);
     d.cfq = (int32_t *)(base + t->off.cfq);
     d.xt = (int32_t *)(base + t->off.xt);
-    d.pnb = (int32_t *)(base + t->off.pnb);
     d.n27 = (int32_t *)(base + t->off.n27);
     d.slotx = (int32_t *)(base + t->off.slotx);
     d.ijk = (int32_t *)(base + t->off.ijk);
@@ -1277,10 +1275,11 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
         int rc = take_pinned(4 * t->ntree * sizeof(double), &t->host_result, &t->host_result_bytes);
         if (rc) return rc;
     }
-    // The tables fill [0, off.phi) of the workspace: staged at their
-    // workspace offsets in one pinned buffer and uploaded by one copy (the
-    // gaps and the device-only part2 carry whatever the buffer holds).
-    const size_t tab_bytes = (size_t)t->off.phi;
+    // The host-built tables fill [0, off.xt) of the workspace: staged at
+    // their workspace offsets in one pinned buffer and uploaded by one copy
+    // (the gaps and the device-only part2 carry whatever the buffer holds);
+    // xt, the last table, is formed on the GPU right after.
+    const size_t tab_bytes = (size_t)t->off.xt;
     char *stage = nullptr;
     size_t stage_cap = 0;
     int rc = take_stage(tab_bytes, &stage, &stage_cap);
@@ -1291,8 +1290,6 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     put(t->off.nbr, t->nbr.data(), t->nbr.size() * 4);
     put(t->off.cfslot, t->cfslot.data(), t->cfslot.size() * 4);
     put(t->off.cfq, t->cfq.data(), t->cfq.size() * 4);
-    put(t->off.xt, t->xt.data(), t->xt.size() * 4);
-    put(t->off.pnb, t->pnb.data(), t->pnb.size() * 4);
     put(t->off.n27, t->n27.data(), t->n27.size() * 4);
     put(t->off.slotx, t->slotx.data(), t->slotx.size() * 4);
     put(t->off.parent, t->parent.data(), t->parent.size() * 4);
@@ -1323,6 +1320,7 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
         give_stage(stage, stage_cap);
         return rc;
     }
+    launch_face_xt(d.nbr, d.cfslot, t->n, d.xt, s);  // a gather of the uploaded face tables
     launch_fill<double>(d.phi, 512 * t->n, 0.0, s);
     launch_fill<double>(d.rhs, 512 * t->n, 0.0, s);
     launch_fill<double>(d.old, 512 * t->n, 0.0, s);

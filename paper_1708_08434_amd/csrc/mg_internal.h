@@ -63,7 +63,6 @@ struct DevTables {
     int32_t *cfslot = nullptr;   // [n][6]  slot of a refinement-boundary face, or -1
     int32_t *cfq = nullptr;      // [n][6]  coarser box across a refinement-boundary face
     int32_t *xt = nullptr;       // [n][6][4][2] faces of the face neighbours (fused sweep)
-    int32_t *pnb = nullptr;      // [n][6] the parent's face neighbours
     int32_t *n27 = nullptr;      // [n][27] same-level box at ijk + o (-1 coarser, -2 outside)
     int32_t *slotx = nullptr;    // [nslot][8] coarse-side indices of a slot's c_hat
     int32_t *ijk = nullptr;      // [n][4]  i, j, k, level
@@ -109,8 +108,8 @@ struct mg_tree {
     // ---- host tables (canonical order) ----
     int64_t n = 0;
     int nlev = 0, ntree = 0;
-    std::vector<int32_t> order, lev, ijk, tid, parent, child, nbr, cfq, cfslot, pnb, slotx;
-    mg::RawArray<int32_t> xt;                           // [n][6][4][2] (see tree.cpp)
+    std::vector<int32_t> order, lev, ijk, tid, parent, child, nbr, cfq, cfslot, slotx;
+    // (xt, the faces of the face neighbours, is formed on the GPU at bind)
     int64_t lstart[mg::kMaxLevel + 2] = {0};
     std::vector<int32_t> refined, leaf;                 // box ids grouped by level
     std::vector<int32_t> cleaf;                         // leaf boxes restricted before a stopping test
@@ -131,7 +130,7 @@ struct mg_tree {
     mg_domain dom{};
     double eig[3 * 64 + 3 * 8] = {0};
     // ---- workspace layout (byte offsets) ----
-    struct { int64_t nbr, cfslot, cfq, xt, pnb, n27, slotx, ijk, parent, refined, leaf, cleaf, oldcp, leafpos, cmask, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
+    struct { int64_t nbr, cfslot, cfq, xt, n27, slotx, ijk, parent, refined, leaf, cleaf, oldcp, leafpos, cmask, slots, leaf_tree, tree_off, chunk, choff, part2, isleaf, tid, root2, eig,
              phi, rhs, old, chat, bcval, partial, result, e32, r32, old32, chat32, swp, fas, dpad, total; } off{};
     // ---- fluid model (mg_fluid_bind): caller's second workspace ----
     void *fws = nullptr;

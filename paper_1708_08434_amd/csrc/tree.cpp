@@ -376,35 +376,6 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
         x[6] = t->nbr[6 * (int64_t)Q + 2 * t2 + 1];
     }
     });
-    // the parent's face neighbours of every box (prolongation stages the
-    // parent's correction one cell beyond its octant)
-    t->pnb.assign((size_t)6 * n, -2);
-    parallel_for(n, [&](int64_t lo, int64_t hi) {
-        for (int64_t b = lo; b < hi; b++)
-            if (t->parent[b] >= 0)
-                for (int f = 0; f < 6; f++) t->pnb[6 * b + f] = t->nbr[6 * (int64_t)t->parent[b] + f];
-    });
-    // faces of the face neighbours: for box b, face d with a same-level
-    // neighbour N, and the 4 faces of N across the two axes tangential to d
-    // (-t1, +t1, -t2, +t2), the pair (nbr[N][d'], cfslot[N][d']); the fused
-    // Gauss-Seidel sweep recomputes N's face layer and needs N's ghosts.
-    t->xt.reset((size_t)6 * 4 * 2 * n);
-    parallel_for(n, [&](int64_t lo, int64_t hi) {
-    for (int64_t b = lo; b < hi; b++)
-        for (int d = 0; d < 6; d++) {
-            int32_t N = t->nbr[6 * b + d];
-            if (N < 0) {
-                for (int q = 0; q < 8; q++) t->xt[(6 * b + d) * 8 + q] = -2;
-                continue;
-            }
-            int a = d >> 1, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
-            const int tf[4] = {2 * t1, 2 * t1 + 1, 2 * t2, 2 * t2 + 1};
-            for (int q = 0; q < 4; q++) {
-                t->xt[((6 * b + d) * 4 + q) * 2] = t->nbr[6 * (int64_t)N + tf[q]];
-                t->xt[((6 * b + d) * 4 + q) * 2 + 1] = t->cfslot[6 * (int64_t)N + tf[q]];
-            }
-        }
-    });
     // per-level lists of refined and leaf boxes
     t->refined.clear();
     t->leaf.clear();
@@ -510,8 +481,6 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.nbr = take(24 * n);
     t->off.cfslot = take(24 * n);
     t->off.cfq = take(24 * n);
-    t->off.xt = take(192 * n);
-    t->off.pnb = take(24 * n);
     t->off.n27 = take(108 * n);
     t->off.ijk = take(16 * n);
     t->off.parent = take(4 * n);
@@ -532,6 +501,7 @@ int build_tree(mg_tree *t, const mg_domain *dom, int64_t n, const int32_t *level
     t->off.tid = take(4 * n);
     t->off.root2 = take(4 * (int64_t)ntree);
     t->off.eig = take(8 * (3 * 64 + 3 * 8));
+    t->off.xt = take(192 * n);  // last of the tables: formed on the GPU, not uploaded
     t->off.phi = take(8 * kCells * n);
     t->off.rhs = take(8 * kCells * n);
     t->off.old = take(8 * kCells * n);
