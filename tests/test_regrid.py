@@ -197,6 +197,39 @@ def test_plan_from_near_values_matches_the_rules(seed):
     assert got == ref_plan(bl.level, bl.ijk, bl.tree, sc, c3, 0.3, 6)
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_plan_on_the_deepest_level_matches_the_rules(seed):
+    """A tree refined at its far corner down to level 15, so that box
+    coordinates reach 2^14 - 1 and every bit of the planner's packed keys is
+    used; both planner entry points against the rules, with refinement
+    capped at level 15."""
+    corner = [(l, (1 << (l - 1)) - 1, (1 << (l - 1)) - 1, (1 << (l - 1)) - 1) for l in range(1, 15)]
+    bl = refine_boxes_explicit(1, corner, max_level=15)
+    assert int(bl.level.max()) == 15 and int(bl.ijk.max()) == (1 << 14) - 1
+    rng = np.random.default_rng(seed)
+    sc = rng.lognormal(0.0, 1.5, (bl.n, 27)) * 10.0 ** rng.uniform(-4, 0, (bl.n, 1))
+    sc[:, 13] = np.maximum(sc[:, 13], sc.max(axis=1))
+    c3 = float(np.quantile(sc[:, 13], 0.8))
+    near = near_of(bl.level, bl.ijk, bl.tree, sc)
+    h = M.mg_tree_create(M.make_domain(), bl.level, bl.ijk, bl.tree)
+    try:
+        order = M.mg_tree_index(h, M.MG_IDX_ORDER, bl.n).reshape(-1)
+        a = M.mg_regrid_plan(h, sc[order], c3, 0.3, 15)
+        b = M.mg_regrid_plan_near(h, near[order], c3, 0.3, 15)
+    finally:
+        M.mg_tree_destroy(h)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    got = {(int(t), int(l), *map(int, c)) for l, c, t in zip(a[0], a[1], a[2])}
+    want = ref_plan(bl.level, bl.ijk, bl.tree, sc, c3, 0.3, 15)
+    old = {(int(t), int(l), *map(int, c)) for l, c, t in zip(bl.level, bl.ijk, bl.tree)}
+    assert got == want, (len(got ^ want), sorted(got ^ want)[:5])
+    assert got != old
+    assert max(k[1] for k in got) == 15 and max(max(k[2:]) for k in got) == (1 << 14) - 1
+    h2 = M.mg_tree_create(M.make_domain(), *a)
+    M.mg_tree_destroy(h2)
+
+
 def test_plan_refines_around_a_charge_and_derefines_behind_it():
     """Structured case: a uniform level-3 tree whose finest boxes near x = 0.2
     are refined; the charge is now at x = 0.8.  Boxes near the charge get
