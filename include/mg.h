@@ -106,7 +106,8 @@ int mg_tree_info(const mg_tree *t, mg_tree_info_t *info);
  * before returning.  The staging buffer (the tables' size, a few hundred
  * bytes per box) is pooled: the library keeps the largest one it has used
  * until the process ends.  The workspace must stay valid until rebind or
- * destroy.
+ * destroy.  On an error the tree is left unbound (MG_ESTATE from the calls
+ * that need a workspace until a bind succeeds).
  */
 int mg_tree_bind(mg_tree *t, void *ws, int64_t ws_bytes, void *stream);
 

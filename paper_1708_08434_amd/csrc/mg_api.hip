@@ -1206,6 +1206,8 @@ int mg_tree_index(const mg_tree *t, int what, int32_t *out) {
     return MG_OK;
 }
 
+static int bind_tables(mg_tree *t, void *ws, void *stream);
+
 int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
     if (!t || !ws) {
         set_error("null argument");
@@ -1215,6 +1217,12 @@ int mg_tree_bind(mg_tree *t, void *ws, int64_t bytes, void *stream) {
         set_error("workspace too small or not 256-byte aligned");
         return MG_ENOMEM;
     }
+    int rc = bind_tables(t, ws, stream);
+    if (rc) t->ws = nullptr;  // a failed bind leaves the tree unbound, not half uploaded
+    return rc;
+}
+
+static int bind_tables(mg_tree *t, void *ws, void *stream) {
     for (auto &g : t->graphs) drop_graph(g);
     t->ws = ws;
     t->stream = stream;

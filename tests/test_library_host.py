@@ -168,6 +168,31 @@ def test_workspace_size_is_reported():
     assert g.info.n_leaf_cells == w.n_leaf
 
 
+def _no_gpu():
+    import torch
+    return torch.cuda.device_count() == 0
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="needs a machine without a GPU: the bind must fail in the runtime")
+def test_a_failed_bind_leaves_the_tree_unbound():
+    """Without a device, mg_tree_bind fails in the HIP runtime (MG_EHIP); the
+    tree must then count as unbound, so the next call that needs a
+    workspace is refused (MG_ESTATE) instead of running on tables that were
+    never uploaded."""
+    b = uniform_boxes(2)
+    h = M.mg_tree_create(M.make_domain(), b.level, b.ijk, b.tree)
+    try:
+        nbytes = int(M.mg_tree_info(h).workspace_bytes)
+        with pytest.raises(M.MGError) as e:
+            M.mg_tree_bind(h, 1 << 20, nbytes, 0)
+        assert e.value.code == M.MG_EHIP
+        with pytest.raises(M.MGError) as e:
+            M.mg_field_set(h, M.MG_FIELD_RHS, 1 << 20)
+        assert e.value.code == M.MG_ESTATE
+    finally:
+        M.mg_tree_destroy(h)
+
+
 def test_schedule_entries_are_validated():
     """mg_set_schedule takes one entry per level in 0..MG_GSRB_VARIANTS-1
     (host state only, no GPU); mg_autotune needs a bound workspace."""
