@@ -314,13 +314,20 @@ def test_gpu_scores_match_numpy():
 
 
 @pytest.mark.gpu
-def test_gpu_near_values_match_the_host_rule():
+@pytest.mark.parametrize("case", ["streamer_small", "forest"])
+def test_gpu_near_values_match_the_host_rule(case):
     """mg_refine_near on the GPU against the rule's per-box values computed
     here from the GPU's own scores (the same bits), and the plans from the
-    two paths (identical lists)."""
-    w = streamer_small()
-    g = M.Tree.from_workload(w)
-    g.set_rhs_from(w)
+    two paths (identical lists); on the small streamer tree and on a forest
+    of two trees with a seeded random charge."""
+    if case == "streamer_small":
+        w = streamer_small()
+        g = M.Tree.from_workload(w)
+        g.set_rhs_from(w)
+    else:
+        bl = forest_boxes()
+        g = M.Tree(bl.level, bl.ijk, bl.tree, bc_type=(0,) * 6)
+        g.set_field(M.MG_FIELD_RHS, np.random.default_rng(5).lognormal(0.0, 2.0, (g.n, 8, 8, 8)))
     sc = g.refine_scores()
     near = g.refine_near()
     lv, ij, tr = g.index(M.MG_IDX_LEVEL), g.index(M.MG_IDX_IJK), g.index(M.MG_IDX_TREE)
