@@ -122,10 +122,10 @@ void launch_bottom(const Geo &g, T *phi, T *rhs, T *old, const double *eig, int6
 void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const double *chat,
                        const int32_t *leaf, int64_t nleaf, double *partial, float *r_out,
                        hipStream_t s);
-// The same norms over the leaf boxes among [b0, b0+nb), into partial at
-// their leaf positions leafpos[b] (-1: not a leaf, skipped).
-void launch_box_norms(const Geo &g, const double *phi, const double *rhs, const double *chat, int64_t b0,
-                      int64_t nb, const int32_t *leafpos, double *partial, float *r_out, hipStream_t s);
+// The same norms over the leaf boxes leaf[q0 .. q0+nq) of the level-grouped
+// leaf list, into partial at their positions q (XCD shares of the list).
+void launch_box_norms(const Geo &g, const double *phi, const double *rhs, const double *chat, const int32_t *leaf,
+                      int64_t q0, int64_t nq, double *partial, float *r_out, hipStream_t s);
 template <typename T>
 void launch_leaf_apply(const Geo &g, const T *x, const T *chat, const int32_t *leaf, int64_t nleaf,
                        T *out, hipStream_t s);

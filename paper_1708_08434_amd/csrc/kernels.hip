@@ -1768,9 +1768,11 @@ __global__ __launch_bounds__(256) void k_leaf_norms(Geo g, const double *__restr
     }
 }
 
-// The norms of k_leaf_norms on the leaf boxes among [b0, b0+nb) (leafpos[b]
-// >= 0; the others exit at once), into partial at their leaf positions: the
-// box comes from the block index, so the loads wait on no list lookup, and
+// The norms of k_leaf_norms on the leaf boxes leaf[q0 .. q0+nq), into
+// partial at their leaf positions q.  Each XCD takes a contiguous share of
+// the leaf list (XCD-aware mapping of q): over the box range instead, the
+// refined boxes, which exit at once, crowd the first shares (on the
+// two-streamer tree the busiest XCD had 14% more leaf boxes than the mean).
 // 128 threads per box with paired loads keep twice the boxes in flight.
 // Thread u holds cell positions 2u and 2u+1 of both colours; the per-box sum
 // follows k_leaf_norms' tree over the 256 positions (the shuffles over u
@@ -1782,16 +1784,15 @@ __global__ __launch_bounds__(256) void k_leaf_norms(Geo g, const double *__restr
 template <bool OUT>
 __global__ __launch_bounds__(128) void k_box_norms(Geo g, const double *__restrict__ phi,
                                                    const double *__restrict__ rhs,
-                                                   const double *__restrict__ chat, int64_t b0, int64_t nb,
-                                                   const int32_t *__restrict__ leafpos,
+                                                   const double *__restrict__ chat,
+                                                   const int32_t *__restrict__ leaf, int64_t q0, int64_t nq,
                                                    double *__restrict__ partial, float *__restrict__ r_out,
                                                    double ilen2, double len3) {
     __shared__ double P[512], H[384], S[4], M[4];
-    int64_t lb = xcd_map(blockIdx.x, nb);
-    if (lb >= nb) return;
-    const int64_t b = b0 + lb;
-    const int32_t q = leafpos[b];
-    if (q < 0) return;
+    int64_t lq = xcd_map(blockIdx.x, nq);
+    if (lq >= nq) return;
+    const int64_t q = q0 + lq;
+    const int64_t b = leaf[q];
     const int u = threadIdx.x;
     const double2 p0 = reinterpret_cast<const double2 *>(phi + b * 512)[u];
     const double2 p1 = reinterpret_cast<const double2 *>(phi + b * 512 + 256)[u];
@@ -1844,8 +1845,8 @@ __global__ __launch_bounds__(128) void k_box_norms(Geo g, const double *__restri
     }
     __syncthreads();
     if (u == 0) {
-        partial[2 * (int64_t)q] = ((S[0] + S[1]) + (S[2] + S[3])) * vol;
-        partial[2 * (int64_t)q + 1] = nanmax(nanmax(M[0], M[1]), nanmax(M[2], M[3]));
+        partial[2 * q] = ((S[0] + S[1]) + (S[2] + S[3])) * vol;
+        partial[2 * q + 1] = nanmax(nanmax(M[0], M[1]), nanmax(M[2], M[3]));
     }
 }
 
@@ -2319,16 +2320,16 @@ void launch_leaf_norms(const Geo &g, const double *phi, const double *rhs, const
     hipLaunchKernelGGL(k_leaf_norms, dim3((unsigned)xcd_grid(nleaf)), dim3(256), 0, s, g, phi, rhs,
                        chat, leaf, nleaf, partial, r_out);
 }
-void launch_box_norms(const Geo &g, const double *phi, const double *rhs, const double *chat, int64_t b0,
-                      int64_t nb, const int32_t *leafpos, double *partial, float *r_out, hipStream_t s) {
-    if (nb <= 0) return;
+void launch_box_norms(const Geo &g, const double *phi, const double *rhs, const double *chat, const int32_t *leaf,
+                      int64_t q0, int64_t nq, double *partial, float *r_out, hipStream_t s) {
+    if (nq <= 0) return;
     const double ilen2 = 1.0 / (g.len * g.len), len3 = g.len * g.len * g.len;
     if (r_out)
-        hipLaunchKernelGGL(k_box_norms<true>, dim3((unsigned)xcd_grid(nb)), dim3(128), 0, s, g, phi, rhs, chat,
-                           b0, nb, leafpos, partial, r_out, ilen2, len3);
+        hipLaunchKernelGGL(k_box_norms<true>, dim3((unsigned)xcd_grid(nq)), dim3(128), 0, s, g, phi, rhs, chat,
+                           leaf, q0, nq, partial, r_out, ilen2, len3);
     else
-        hipLaunchKernelGGL(k_box_norms<false>, dim3((unsigned)xcd_grid(nb)), dim3(128), 0, s, g, phi, rhs, chat,
-                           b0, nb, leafpos, partial, r_out, ilen2, len3);
+        hipLaunchKernelGGL(k_box_norms<false>, dim3((unsigned)xcd_grid(nq)), dim3(128), 0, s, g, phi, rhs, chat,
+                           leaf, q0, nq, partial, r_out, ilen2, len3);
 }
 template <typename T>
 void launch_leaf_apply(const Geo &g, const T *x, const T *chat, const int32_t *leaf, int64_t nleaf,

@@ -392,8 +392,8 @@ template <typename T> void fmg_pass(mg_tree *t, const Fields<T> &F, int nd, int 
         // leaf boxes on levels below the top-down pass (those of a tree of one
         // or two levels): the norm kernel, on the still zero field
         int top = std::min(low - 1, t->nlev);
-        launch_box_norms(f64(t).g, t->d.phi, t->d.rhs, t->d.chat, lbeg(t, 1), t->lstart[top] - lbeg(t, 1),
-                         t->d.leafpos, t->d.partial, nullptr, stream_of(t));
+        launch_box_norms(f64(t).g, t->d.phi, t->d.rhs, t->d.chat, t->d.leaf, 0, t->fstart[top + 1],
+                         t->d.partial, nullptr, stream_of(t));
         launch_reduce_trees(t->d.partial, t->d.leaf_tree, t->d.chunk, (int64_t)t->chunk.size() / 3, t->d.choff,
                             t->ntree, t->d.part2, t->d.result + beff_slot, stream_of(t));
     }
@@ -429,7 +429,7 @@ void ir_finish(mg_tree *t, int nu, bool ir) {
 void norms_launch(mg_tree *t, int slot, float *r32) {
     Fields<double> F = f64(t);
     ensure_cf_all(t, F);
-    launch_box_norms(F.g, F.phi, F.rhs, F.chat, 0, t->n, t->d.leafpos, t->d.partial, r32, stream_of(t));
+    launch_box_norms(F.g, F.phi, F.rhs, F.chat, t->d.leaf, 0, t->nleaf, t->d.partial, r32, stream_of(t));
     launch_reduce_trees(t->d.partial, t->d.leaf_tree, t->d.chunk, (int64_t)t->chunk.size() / 3, t->d.choff,
                         t->ntree, t->d.part2, t->d.result + slot, stream_of(t));
 }
